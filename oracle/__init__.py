@@ -1,0 +1,216 @@
+"""FP64 CPU oracle (ctypes binding of ``sta_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this package.  The GPU library
+never loads it, and it shares no code with the GPU library.
+
+Every function mirrors a definition of the static-timing hot path (see the
+header of ``sta_oracle.c`` for the paper sections each one follows).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+_P32 = ctypes.POINTER(ctypes.c_int32)
+_P64 = ctypes.POINTER(ctypes.c_int64)
+_PF = ctypes.POINTER(ctypes.c_float)
+_PD = ctypes.POINTER(ctypes.c_double)
+_P8 = ctypes.POINTER(ctypes.c_int8)
+
+
+class _ODesign(ctypes.Structure):
+    _fields_ = [
+        ("n_pins", ctypes.c_int32), ("n_cells", ctypes.c_int32), ("n_nets", ctypes.c_int32),
+        ("n_pi", ctypes.c_int32), ("n_po", ctypes.c_int32),
+        ("pin_kind", _P32),
+        ("cell_type", _P32), ("cell_in_ptr", _P32), ("cell_in_pin", _P32), ("cell_out_pin", _P32),
+        ("net_driver", _P32), ("net_sink_ptr", _P32), ("net_sink_pin", _P32),
+        ("net_node_ptr", _P64),
+        ("parent", _P32),
+        ("res_kohm", _PF), ("cap_ff", _PF),
+        ("sink_node", _P32),
+        ("n_types", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("n_inputs", _P32), ("sense", _P32),
+        ("pin_cap_ff", _PF), ("slew_axis", _PF), ("load_axis", _PF), ("tables", _PF),
+        ("po_cap_ff", ctypes.c_float),
+        ("pi_at", _PF), ("pi_slew", _PF), ("po_rat", _PF),
+        ("dangling_rat", ctypes.c_float * 4),
+        ("dangling_policy", ctypes.c_int32),
+    ]
+
+
+class _OResult(ctypes.Structure):
+    _fields_ = [
+        ("level", _P32), ("level_order", _P32),
+        ("L_net", _PD),
+        ("d_sink", _PD), ("q_sink", _PD),
+        ("at", _PD), ("slew", _PD), ("rat", _PD), ("slack", _PD),
+        ("crit", _P8),
+        ("ep_pin", _P32),
+        ("ep_slack", _PD),
+        ("ep_order", _P32),
+        ("wns", ctypes.c_double * 2), ("tns", ctypes.c_double * 2),
+        ("n_ep", ctypes.c_int32), ("n_levels", ctypes.c_int32),
+    ]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        lib = ctypes.CDLL(LIB_PATH)
+        lib.orc_levelize.restype = ctypes.c_int
+        lib.orc_levelize.argtypes = [ctypes.POINTER(_ODesign), _P32, _P32, _P32]
+        lib.orc_rc.restype = None
+        lib.orc_rc.argtypes = [ctypes.POINTER(_ODesign), _PD, _PD, _PD, _PD]
+        lib.orc_rc_tree.restype = None
+        lib.orc_rc_tree.argtypes = [ctypes.c_int64, _P32, _PD, _PD, _PD, _PD, _PD, _PD]
+        lib.orc_nldm.restype = ctypes.c_double
+        lib.orc_nldm.argtypes = [ctypes.c_int32, ctypes.c_int32, _PF, _PF, _PF,
+                                 ctypes.c_double, ctypes.c_double]
+        lib.orc_sta.restype = ctypes.c_int
+        lib.orc_sta.argtypes = [ctypes.POINTER(_ODesign), _PD, ctypes.POINTER(_OResult)]
+        _lib = lib
+    return _lib
+
+
+def _ptr(a, typ):
+    return a.ctypes.data_as(typ)
+
+
+class _Keep:
+    """Holds the contiguous arrays a ctypes struct points into."""
+
+    def __init__(self):
+        self.arrays = []
+
+    def __call__(self, a, dtype, typ):
+        a = np.ascontiguousarray(a, dtype=dtype)
+        self.arrays.append(a)
+        return _ptr(a, typ)
+
+
+def _odesign(d, keep: _Keep) -> _ODesign:
+    i32 = lambda a: keep(a, np.int32, _P32)  # noqa: E731
+    f32 = lambda a: keep(a, np.float32, _PF)  # noqa: E731
+    od = _ODesign()
+    od.n_pins, od.n_cells, od.n_nets = d.n_pins, d.n_cells, d.n_nets
+    od.n_pi, od.n_po = d.n_pi, d.n_po
+    od.pin_kind = i32(d.pin_kind)
+    od.cell_type, od.cell_in_ptr = i32(d.cell_type), i32(d.cell_in_ptr)
+    od.cell_in_pin, od.cell_out_pin = i32(d.cell_in_pin), i32(d.cell_out_pin)
+    od.net_driver, od.net_sink_ptr, od.net_sink_pin = (i32(d.net_driver), i32(d.net_sink_ptr),
+                                                       i32(d.net_sink_pin))
+    od.net_node_ptr = keep(d.net_node_ptr, np.int64, _P64)
+    od.parent = i32(d.parent)
+    od.res_kohm, od.cap_ff = f32(d.res_kohm), f32(d.cap_ff)
+    od.sink_node = i32(d.sink_node)
+    od.n_types, od.nx, od.ny = d.n_types, d.nx, d.ny
+    od.n_inputs, od.sense = i32(d.n_inputs), i32(d.sense)
+    od.pin_cap_ff, od.slew_axis = f32(d.pin_cap_ff), f32(d.slew_axis)
+    od.load_axis, od.tables = f32(d.load_axis), f32(d.tables)
+    od.po_cap_ff = float(d.po_cap_ff)
+    od.pi_at, od.pi_slew, od.po_rat = f32(d.pi_at), f32(d.pi_slew), f32(d.po_rat)
+    for v in range(4):
+        od.dangling_rat[v] = float(d.dangling_rat[v])
+    od.dangling_policy = int(d.dangling_policy)
+    return od
+
+
+def levelize(d):
+    """Pin levels and the (level, pin id) order; raises on a cycle."""
+    lib, keep = _load(), _Keep()
+    od = _odesign(d, keep)
+    level = np.zeros(d.n_pins, np.int32)
+    order = np.zeros(d.n_pins, np.int32)
+    nl = ctypes.c_int32(0)
+    if lib.orc_levelize(ctypes.byref(od), _ptr(level, _P32), _ptr(order, _P32), ctypes.byref(nl)):
+        raise ValueError("combinational cycle")
+    return level, order, int(nl.value)
+
+
+def rc(d, wire_cap=None):
+    """Per net load, per sink Elmore delay d and impulse spread q (caller orders)."""
+    lib, keep = _load(), _Keep()
+    od = _odesign(d, keep)
+    L = np.zeros(d.n_nets, np.float64)
+    dd = np.zeros(d.n_sinks, np.float64)
+    q = np.zeros(d.n_sinks, np.float64)
+    wc = None if wire_cap is None else keep(wire_cap, np.float64, _PD)
+    lib.orc_rc(ctypes.byref(od), wc, _ptr(L, _PD), _ptr(dd, _PD), _ptr(q, _PD))
+    return L, dd, q
+
+
+def rc_tree(parent, R, Chat):
+    """Elmore recursions on one tree: (load, d, ld, m2) per node."""
+    lib = _load()
+    parent = np.ascontiguousarray(parent, np.int32)
+    R = np.ascontiguousarray(R, np.float64)
+    Chat = np.ascontiguousarray(Chat, np.float64)
+    m = len(parent)
+    outs = [np.zeros(m, np.float64) for _ in range(4)]
+    lib.orc_rc_tree(m, _ptr(parent, _P32), _ptr(R, _PD), _ptr(Chat, _PD),
+                    *[_ptr(o, _PD) for o in outs])
+    return tuple(outs)
+
+
+def nldm(xa, ya, table, X, Y):
+    """Bilinear NLDM value with boundary-segment extrapolation."""
+    lib = _load()
+    xa = np.ascontiguousarray(xa, np.float32)
+    ya = np.ascontiguousarray(ya, np.float32)
+    table = np.ascontiguousarray(table, np.float32)
+    return lib.orc_nldm(len(xa), len(ya), _ptr(xa, _PF), _ptr(ya, _PF), _ptr(table, _PF),
+                        float(X), float(Y))
+
+
+def sta(d, wire_cap=None):
+    """Full analysis: levels, RC, AT/slew, RAT, slack, crit, endpoints, WNS/TNS."""
+    lib, keep = _load(), _Keep()
+    od = _odesign(d, keep)
+    NP = d.n_pins
+    r = {
+        "level": np.zeros(NP, np.int32), "level_order": np.zeros(NP, np.int32),
+        "L_net": np.zeros(d.n_nets, np.float64),
+        "d_sink": np.zeros(max(1, d.n_sinks), np.float64),
+        "q_sink": np.zeros(max(1, d.n_sinks), np.float64),
+        "at": np.zeros((NP, 4), np.float64), "slew": np.zeros((NP, 4), np.float64),
+        "rat": np.zeros((NP, 4), np.float64), "slack": np.zeros((NP, 4), np.float64),
+        "crit": np.zeros((NP, 4), np.int8),
+        "ep_pin": np.zeros(NP, np.int32),
+        "ep_slack": np.zeros((NP, 2), np.float64),
+        "ep_order": np.zeros(2 * NP, np.int32),
+    }
+    res = _OResult()
+    res.level, res.level_order = _ptr(r["level"], _P32), _ptr(r["level_order"], _P32)
+    res.L_net = _ptr(r["L_net"], _PD)
+    res.d_sink, res.q_sink = _ptr(r["d_sink"], _PD), _ptr(r["q_sink"], _PD)
+    res.at, res.slew = _ptr(r["at"], _PD), _ptr(r["slew"], _PD)
+    res.rat, res.slack = _ptr(r["rat"], _PD), _ptr(r["slack"], _PD)
+    res.crit = _ptr(r["crit"], _P8)
+    res.ep_pin, res.ep_slack = _ptr(r["ep_pin"], _P32), _ptr(r["ep_slack"], _PD)
+    res.ep_order = _ptr(r["ep_order"], _P32)
+    wc = None if wire_cap is None else keep(wire_cap, np.float64, _PD)
+    if lib.orc_sta(ctypes.byref(od), wc, ctypes.byref(res)):
+        raise ValueError("combinational cycle")
+    ne = res.n_ep
+    r["n_ep"] = ne
+    r["n_levels"] = res.n_levels
+    r["ep_pin"] = r["ep_pin"][:ne].copy()
+    r["ep_slack"] = r["ep_slack"][:ne].copy()
+    r["ep_order"] = r["ep_order"][:2 * ne].reshape(2, ne).copy()
+    r["d_sink"] = r["d_sink"][:d.n_sinks]
+    r["q_sink"] = r["q_sink"][:d.n_sinks]
+    r["wns"] = np.array([res.wns[0], res.wns[1]])
+    r["tns"] = np.array([res.tns[0], res.tns[1]])
+    return r
