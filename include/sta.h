@@ -1,0 +1,223 @@
+/*
+ * sta.h - C ABI of the MI355X static-timing hot path (libsta.so).
+ *
+ * What it computes (HeteroSTA, arXiv 2511.11660): graph-based static timing
+ * analysis on a flattened netlist.  Per net, Elmore delay and slew on the RC
+ * tree (§III "Delay models", "Parasitics (RC) inputs"); per cell arc, NLDM
+ * delay and output slew by bilinear table lookup (§IV-A, Table I); levelized
+ * forward propagation of arrival time and slew and backward propagation of
+ * required time, giving per-pin slack, endpoint slack, WNS and TNS (§I, §III
+ * "Report options").  The interface follows the paper's flattened,
+ * zero-translation API (§II last paragraph, §III "Heterogeneous netlist
+ * database"): the netlist arrives as net and cell CSR arrays, parasitics as a
+ * flattened RC CSR, and every input and output array may live in host or
+ * device memory (§III "Parasitics (RC) inputs", "Report options").
+ *
+ * Conventions
+ *   - Views: index v = 2*el + rf, el 0 early / 1 late, rf 0 rise / 1 fall.
+ *     Arrays documented as [n][4] hold the four views of item n contiguously.
+ *   - Units: time ps, capacitance fF, resistance kOhm (kOhm x fF = ps).
+ *   - Pins carry caller ids 0..n_pins-1.  PIs are ranked by ascending pin id
+ *     (index into pi_at / pi_slew), POs likewise (index into po_rat).
+ *     Endpoints are the PO pins plus, when dangling_policy is 1, every cell
+ *     output without fanout; endpoint e is the e-th endpoint in ascending pin
+ *     id.
+ *   - sta_mem STA_HOST / STA_DEVICE tells where a pointer lives.  Device
+ *     pointers are HIP device addresses on the context's device.
+ *   - Every function returns a status; no exception crosses the ABI.  On an
+ *     error the thread-local sta_last_error() string says what was wrong.
+ *   - A context is used by one host thread at a time.  Work is enqueued on the
+ *     HIP stream passed in (NULL = the default stream); calls that return data
+ *     to host memory synchronize that stream.
+ */
+#ifndef STA_H
+#define STA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sta_ctx sta_ctx; /* opaque */
+
+typedef enum {
+  STA_OK = 0,
+  STA_E_ARG = 1,         /* malformed input (bounds, kinds, CSR, NaN, ...) */
+  STA_E_CYCLE = 2,       /* the timing graph has a combinational cycle */
+  STA_E_OOM = 3,         /* device or host allocation failed */
+  STA_E_DEVICE = 4,      /* a HIP call or kernel failed */
+  STA_E_STATE = 5,       /* call not valid in the context's current state */
+  STA_E_UNSUPPORTED = 6  /* valid input outside what this build supports */
+} sta_status;
+
+typedef enum { STA_HOST = 0, STA_DEVICE = 1 } sta_mem;
+
+typedef enum { STA_PIN_PI = 0, STA_PIN_CELL_IN = 1, STA_PIN_CELL_OUT = 2, STA_PIN_PO = 3 } sta_pin_kind;
+
+/* Flattened netlist (§III "Heterogeneous netlist database": net and cell CSR
+ * arrays taken directly from a flow, no pin remapping).  Every PI and cell
+ * output pin drives exactly one net (which may have no sinks); every cell
+ * input and PO pin is a sink of exactly one net.  Cells have one output and
+ * at least one input; the order of a cell's inputs is its fanin position. */
+typedef struct {
+  int32_t n_pins, n_cells, n_nets, n_pi, n_po;
+  const int32_t *pin_kind;     /* [n_pins] sta_pin_kind */
+  const int32_t *cell_type;    /* [n_cells] library type */
+  const int32_t *cell_in_ptr;  /* [n_cells+1] CSR offsets into cell_in_pin */
+  const int32_t *cell_in_pin;  /* [cell_in_ptr[n_cells]] input pins per cell */
+  const int32_t *cell_out_pin; /* [n_cells] */
+  const int32_t *net_driver;   /* [n_nets] driving pin */
+  const int32_t *net_sink_ptr; /* [n_nets+1] CSR offsets into net_sink_pin */
+  const int32_t *net_sink_pin; /* [net_sink_ptr[n_nets]] sink pins per net */
+  sta_mem mem;
+} sta_graph_desc;
+
+/* Flattened RC CSR (§III "Parasitics (RC) inputs").  Net n owns nodes
+ * [net_node_ptr[n], net_node_ptr[n+1]); node 0 of a net is its root at the
+ * driver.  parent is net-local with parent[root] = -1 and parent[k] < k.
+ * res_kohm[k] is the resistance of the segment parent->k; cap_ff[k] the ground
+ * cap at node k.  sink_node[s] is the net-local node of sink s, aligned with
+ * sta_graph_desc.net_sink_pin.  The receiving pin's input cap (library pin cap
+ * or po_cap_ff) is added at its node. */
+typedef struct {
+  int64_t n_nodes;
+  const int64_t *net_node_ptr; /* [n_nets+1] */
+  const int32_t *parent;       /* [n_nodes] */
+  const float *res_kohm;       /* [n_nodes] */
+  const float *cap_ff;         /* [n_nodes] */
+  const int32_t *sink_node;    /* [n_sinks] */
+  sta_mem mem;
+} sta_rc_desc;
+
+/* Liberty-style NLDM library (§IV-A, Table I uses NLDM).  Per type: tables
+ * [4][nx][ny] = cell_rise, cell_fall, rise_transition, fall_transition indexed
+ * by (input slew, output load); axes strictly increasing.  sense: 0 positive
+ * unate, 1 negative unate, 2 non-unate; all arcs of a type share its tables.
+ * Always host memory. */
+typedef struct {
+  int32_t n_types, nx, ny;     /* n_types <= 64, 2 <= nx, ny <= 8 */
+  const int32_t *n_inputs;     /* [n_types] */
+  const int32_t *sense;        /* [n_types] */
+  const float *pin_cap_ff;     /* [n_types] input pin cap */
+  const float *slew_axis;      /* [n_types][nx] ps */
+  const float *load_axis;      /* [n_types][ny] fF */
+  const float *tables;         /* [n_types][4][nx][ny] ps */
+  float po_cap_ff;             /* load of a PO pin */
+} sta_lib_desc;
+
+/* Boundary constraints; always host memory. */
+typedef struct {
+  const float *pi_at;          /* [n_pi][4] */
+  const float *pi_slew;        /* [n_pi][4] */
+  const float *po_rat;         /* [n_po][4] */
+  float dangling_rat[4];       /* RAT of dangling cell outputs when they are endpoints */
+} sta_constraints;
+
+/* Schedules for the level sweeps. */
+typedef enum {
+  STA_SCHED_PERSISTENT = 0,    /* one launch per sweep, device-side level counters */
+  STA_SCHED_PER_LEVEL = 1      /* one launch per level */
+} sta_sched;
+
+typedef struct {
+  int32_t mode;                /* 0 hard max/min (only mode in this build) */
+  float gamma_ps;              /* smoothing temperature (mode 1) */
+  int32_t dangling_policy;     /* 0: zero-fanout cell outputs unconstrained; 1: endpoints */
+  int32_t sched;               /* sta_sched */
+  int32_t big_net_nodes;       /* nets with more RC nodes go to the wide RC kernel; 0 = 255 */
+  int32_t sort_endpoints;      /* 1: sta_update_timing also orders endpoints by slack */
+  int32_t profile;             /* 1: record per-kernel HIP event times in sta_update_timing */
+  int32_t device;              /* HIP device ordinal; -1 = current device */
+} sta_options;
+
+typedef struct {
+  int32_t n_pins, n_cells, n_nets, n_pi, n_po, n_sinks;
+  int64_t n_nodes;
+  int32_t n_levels;            /* pin levels (max pin level + 1) */
+  int32_t n_cell_levels;       /* max cell level (cells at 1..n_cell_levels) */
+  int32_t n_endpoints;
+  int32_t n_big_nets;          /* nets routed to the wide RC kernel */
+  int32_t n_chunks;            /* sweep work items */
+  int32_t device;
+} sta_info;
+
+/* Fills *opt with the defaults (hard mode, persistent schedule, sorting on). */
+void sta_options_default(sta_options *opt);
+
+/* Validates the inputs on the host, levelizes the timing graph on the device
+ * (longest-path levels; a cycle gives STA_E_CYCLE) and builds the device
+ * layout.  All input arrays are read during the call only (device arrays are
+ * copied); the context owns every buffer it allocates.  opts may be NULL for
+ * the defaults.  *out is set only on STA_OK. */
+sta_status sta_create(const sta_graph_desc *graph, const sta_rc_desc *rc, const sta_lib_desc *lib,
+                      const sta_constraints *cons, const sta_options *opts, sta_ctx **out);
+
+/* Releases the context and its device memory.  NULL is a no-op. */
+void sta_destroy(sta_ctx *ctx);
+
+/* Replaces every RC node's ground cap (caller node order, [n_nodes] fF), the
+ * quantity an optimization loop changes between timing updates (§IV-C, IV-D
+ * flows call the timer inside their loop).  The values are copied (permuted
+ * into the device layout) on `stream`; the caller's buffer may be reused once
+ * the stream has passed this point.  Values must be finite and >= 0 (checked
+ * on the host for STA_HOST input only). */
+sta_status sta_set_wire_caps(sta_ctx *ctx, const float *cap_ff, sta_mem mem, void *stream);
+
+/* One full timing update on `stream`, asynchronous: RC pass (Elmore delay,
+ * impulse spread, net load), forward AT/slew sweep with NLDM lookups, backward
+ * RAT sweep with slacks, endpoint WNS/TNS (FP64, fixed reduction order) and,
+ * if enabled, the endpoint order.  Device faults surface as STA_E_DEVICE at
+ * the next synchronizing call. */
+sta_status sta_update_timing(sta_ctx *ctx, void *stream);
+
+/* Slack report (§III "Report options": pin slacks, WNS/TNS).  Any pointer may
+ * be NULL to skip it.  pin_slack [n_pins][4] (late RAT-AT, early AT-RAT, +inf
+ * when unconstrained); ep_slack [n_endpoints][2] (min over rise/fall, per
+ * early/late); ep_order [2][n_endpoints] endpoint indices by ascending (slack,
+ * pin id), per early/late (requires sort_endpoints); wns[2], tns[2] per
+ * early/late with WNS = min(0, min slack) and TNS = sum of min(0, slack)
+ * (Table IV prints both as 0 for a clean design).  Array outputs go to `dst`
+ * memory; wns/tns are always host doubles.  Synchronizes `stream` when any
+ * output is host memory. */
+sta_status sta_report_slack(sta_ctx *ctx, float *pin_slack, float *ep_slack, int32_t *ep_order,
+                            double *wns, double *tns, sta_mem dst, void *stream);
+
+/* Per-pin timing in caller pin order, each [n_pins][4] or NULL: arrival,
+ * slew, required time, and the critical fanin of each cell output view
+ * (2 * fanin position + input transition, ties to the lower value; -1 for
+ * pins that are not cell outputs). */
+sta_status sta_report_timing(sta_ctx *ctx, float *at, float *slew, float *rat, int8_t *crit,
+                             sta_mem dst, void *stream);
+
+/* Pin levels [n_pins] and the pins in ascending (level, pin id) [n_pins]. */
+sta_status sta_report_levels(sta_ctx *ctx, int32_t *pin_level, int32_t *level_order, sta_mem dst,
+                             void *stream);
+
+/* RC pass results (§III "Delay models"): net_load [n_nets] in caller net order,
+ * sink_delay and sink_spread [n_sinks] in caller sink order (Elmore delay and
+ * impulse-response spread q; sink slew = sqrt(driver slew^2 + q)). */
+sta_status sta_report_rc(sta_ctx *ctx, float *net_load, float *sink_delay, float *sink_spread,
+                         sta_mem dst, void *stream);
+
+/* Endpoint pins [n_endpoints] in endpoint-index order (ascending pin id). */
+sta_status sta_report_endpoints(sta_ctx *ctx, int32_t *ep_pin, sta_mem dst, void *stream);
+
+/* Sizes and schedule facts of a context. */
+sta_status sta_get_info(const sta_ctx *ctx, sta_info *info);
+
+/* Per-kernel durations (ms) of the last sta_update_timing when profiling is on:
+ * ms[0] RC small nets, ms[1] RC big nets, ms[2] forward sweep, ms[3] backward
+ * sweep, ms[4] endpoint reduction, ms[5] endpoint sort.  *n receives the count
+ * (6); ms needs room for 6.  Synchronizes the last update's stream. */
+sta_status sta_get_phase_times(sta_ctx *ctx, float *ms, int32_t *n);
+
+/* Name of a status code; message of the calling thread's last error. */
+const char *sta_status_string(sta_status s);
+const char *sta_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STA_H */

@@ -214,3 +214,70 @@ def sta(d, wire_cap=None):
     r["wns"] = np.array([res.wns[0], res.wns[1]])
     r["tns"] = np.array([res.tns[0], res.tns[1]])
     return r
+
+
+# ------------------------------------------------------------ smooth form
+
+class _OSmooth(ctypes.Structure):
+    _fields_ = [
+        ("at", _PD), ("slew", _PD), ("L_net", _PD), ("d_sink", _PD), ("q_sink", _PD),
+        ("ep_pin", _P32), ("ep_s", _PD),
+        ("tns", ctypes.c_double), ("wns", ctypes.c_double),
+        ("n_ep", ctypes.c_int32), ("sig", ctypes.c_uint64),
+    ]
+
+
+def _smooth_struct(d):
+    NP = d.n_pins
+    r = {"at": np.zeros((NP, 4)), "slew": np.zeros((NP, 4)), "L_net": np.zeros(d.n_nets),
+         "d_sink": np.zeros(max(1, d.n_sinks)), "q_sink": np.zeros(max(1, d.n_sinks)),
+         "ep_pin": np.zeros(NP, np.int32), "ep_s": np.zeros(NP)}
+    o = _OSmooth()
+    for k in ("at", "slew", "L_net", "d_sink", "q_sink", "ep_s"):
+        setattr(o, k, _ptr(r[k], _PD))
+    o.ep_pin = _ptr(r["ep_pin"], _P32)
+    return r, o
+
+
+def _smooth_finish(r, o):
+    ne = o.n_ep
+    r["n_ep"] = ne
+    r["ep_pin"] = r["ep_pin"][:ne].copy()
+    r["ep_s"] = r["ep_s"][:ne].copy()
+    r["tns"], r["wns"], r["sig"] = o.tns, o.wns, o.sig
+    return r
+
+
+def smooth_sta(d, gamma, wire_cap=None):
+    """Smooth forward: late AT merges by log-sum-exp (temperature gamma), smooth
+    late endpoint slack, TNS_g and WNS_g."""
+    lib, keep = _load(), _Keep()
+    lib.orc_smooth_sta.restype = ctypes.c_int
+    lib.orc_smooth_sta.argtypes = [ctypes.POINTER(_ODesign), _PD, ctypes.c_double, ctypes.POINTER(_OSmooth)]
+    od = _odesign(d, keep)
+    r, o = _smooth_struct(d)
+    wc = None if wire_cap is None else keep(wire_cap, np.float64, _PD)
+    if lib.orc_smooth_sta(ctypes.byref(od), wc, float(gamma), ctypes.byref(o)):
+        raise ValueError("combinational cycle")
+    return _smooth_finish(r, o)
+
+
+def smooth_adjoint(d, gamma, g_tns=1.0, g_wns=0.0, wire_cap=None):
+    """Gradient of g_tns*TNS_g + g_wns*WNS_g: per RC node cap (caller node
+    order), per pin NLDM load (cell outputs), per arc and late view delay."""
+    lib, keep = _load(), _Keep()
+    lib.orc_smooth_adjoint.restype = ctypes.c_int
+    lib.orc_smooth_adjoint.argtypes = [ctypes.POINTER(_ODesign), _PD, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_double, _PD, _PD, _PD, ctypes.POINTER(_OSmooth)]
+    od = _odesign(d, keep)
+    r, o = _smooth_struct(d)
+    gc = np.zeros(int(d.n_nodes))
+    gl = np.zeros(d.n_pins)
+    ga = np.zeros((int(d.cell_in_ptr[-1]), 4))
+    wc = None if wire_cap is None else keep(wire_cap, np.float64, _PD)
+    if lib.orc_smooth_adjoint(ctypes.byref(od), wc, float(gamma), float(g_tns), float(g_wns),
+                              _ptr(gc, _PD), _ptr(gl, _PD), _ptr(ga, _PD), ctypes.byref(o)):
+        raise ValueError("combinational cycle")
+    r = _smooth_finish(r, o)
+    r["grad_wire_cap"], r["grad_pin_load"], r["grad_arc_delay"] = gc, gl, ga
+    return r

@@ -417,3 +417,335 @@ int orc_sta(const orc_design *D, const double *wire_cap, orc_result *out) {
   roles_free(&R);
   return 0;
 }
+
+/* ================================================================ smooth form
+ *
+ * Differentiable variant (not in the paper; it serves gradient-based
+ * optimization loops of the kind §IV-C and §IV-D drive, where per-pin slacks
+ * are fed back).  Late arrival merges use the log-sum-exp smooth maximum
+ *     LSE_g(x) = m + g log sum exp((x_i - m) / g),  m = max x,
+ * the late endpoint slack is the smooth minimum over rise/fall of RAT - AT,
+ *     s = -LSE_g(AT_R - RAT_R, AT_F - RAT_F),
+ * and the objective terms are
+ *     TNS_g = sum_ep -g log(1 + exp(-s/g))            (smooth min(0, s))
+ *     WNS_g = -g log(1 + sum_ep exp(-s/g))            (smooth min(0, min s)).
+ * Early views and all slew merges stay hard.  The adjoint is reverse mode
+ * through these definitions, the bilinear lookups and the RC moments. */
+
+typedef struct {
+  double *at, *slew;   /* [n_pins][4] */
+  double *L_net;       /* [n_nets] */
+  double *d_sink, *q_sink; /* [n_sinks] */
+  int32_t *ep_pin;     /* [n_ep] (capacity n_pins) */
+  double *ep_s;        /* [n_ep] smooth late slack */
+  double tns, wns;
+  int32_t n_ep;
+  uint64_t sig;        /* hash of every discrete choice (table segments, slew winners) */
+} orc_smooth_result;
+
+static double lse2(double a, double b, double g) {
+  double m = a > b ? a : b;
+  return m + g * log(exp((a - m) / g) + exp((b - m) / g));
+}
+
+/* log(1 + exp(x)) without overflow */
+static double softplus(double x) { return x > 0 ? x + log1p(exp(-x)) : log1p(exp(x)); }
+
+static uint64_t mix(uint64_t h, uint64_t v) {
+  h ^= v + 0x9E3779B97F4A7C15ull + (h << 6) + (h >> 2);
+  return h;
+}
+
+/* Bilinear value and its partials in X and Y on the segment the lookup picks. */
+static double nldm_d(int32_t nx, int32_t ny, const float *xa, const float *ya, const float *T, double X,
+                     double Y, double *dX, double *dY, int32_t *seg) {
+  int32_t i = 0, j = 0;
+  for (int32_t m = 1; m <= nx - 2; m++)
+    if ((double)xa[m] <= X) i = m;
+  for (int32_t m = 1; m <= ny - 2; m++)
+    if ((double)ya[m] <= Y) j = m;
+  double hx = (double)xa[i + 1] - xa[i], hy = (double)ya[j + 1] - ya[j];
+  double t = (X - xa[i]) / hx, u = (Y - ya[j]) / hy;
+  double T00 = T[i * ny + j], T10 = T[(i + 1) * ny + j], T01 = T[i * ny + j + 1], T11 = T[(i + 1) * ny + j + 1];
+  if (dX) *dX = ((1 - u) * (T10 - T00) + u * (T11 - T01)) / hx;
+  if (dY) *dY = ((1 - t) * (T01 - T00) + t * (T11 - T10)) / hy;
+  if (seg) *seg = i * 16 + j;
+  return (1 - t) * (1 - u) * T00 + t * (1 - u) * T10 + (1 - t) * u * T01 + t * u * T11;
+}
+
+static const float *tab_of(const orc_design *D, int32_t type, int k) {
+  return D->tables + ((size_t)type * 4 + (size_t)k) * D->nx * D->ny;
+}
+
+/* Smooth forward; returns 1 on a cycle.  level_order must come from
+ * orc_levelize. */
+static int smooth_forward(const orc_design *D, const roles_t *R, const int32_t *order, const double *wire_cap,
+                          double gamma, orc_smooth_result *out) {
+  int32_t NP = D->n_pins;
+  double *at = out->at, *sl = out->slew;
+  uint64_t sig = 1469598103934665603ull;
+  orc_rc(D, wire_cap, out->L_net, out->d_sink, out->q_sink);
+  for (int32_t o = 0; o < NP; o++) {
+    int32_t p = order[o];
+    int32_t kind = D->pin_kind[p];
+    if (kind == PI_) {
+      for (int v = 0; v < 4; v++) {
+        at[p * 4 + v] = D->pi_at[R->rank[p] * 4 + v];
+        sl[p * 4 + v] = D->pi_slew[R->rank[p] * 4 + v];
+      }
+    } else if (kind == CIN_ || kind == PO_) {
+      int32_t s = R->sink_idx[p];
+      int32_t drv = D->net_driver[R->sink_net[s]];
+      for (int v = 0; v < 4; v++) {
+        at[p * 4 + v] = at[drv * 4 + v] + out->d_sink[s];
+        sl[p * 4 + v] = sqrt(sl[drv * 4 + v] * sl[drv * 4 + v] + out->q_sink[s]);
+      }
+    } else {
+      int32_t c = R->cell_of[p], type = D->cell_type[c], sense = D->sense[type];
+      double load = out->L_net[R->drv_net[p]];
+      const float *xa = D->slew_axis + (size_t)type * D->nx, *ya = D->load_axis + (size_t)type * D->ny;
+      for (int el = 0; el < 2; el++)
+        for (int r_o = 0; r_o < 2; r_o++) {
+          double best_sl = el ? -INFINITY : INFINITY, hard = el ? -INFINITY : INFINITY;
+          int win = -1;
+          /* candidate values */
+          double z[16];
+          int nz = 0;
+          for (int32_t k = D->cell_in_ptr[c]; k < D->cell_in_ptr[c + 1]; k++) {
+            int32_t in = D->cell_in_pin[k];
+            for (int r_i = 0; r_i < 2; r_i++) {
+              if (!arc_maps(sense, r_i, r_o)) continue;
+              double x = sl[in * 4 + el * 2 + r_i];
+              int32_t seg;
+              double dl = nldm_d(D->nx, D->ny, xa, ya, tab_of(D, type, r_o), x, load, NULL, NULL, &seg);
+              double cs = nldm_d(D->nx, D->ny, xa, ya, tab_of(D, type, 2 + r_o), x, load, NULL, NULL, NULL);
+              if (el) sig = mix(sig, (uint64_t)seg);
+              z[nz++] = at[in * 4 + el * 2 + r_i] + dl;
+              if (el ? z[nz - 1] > hard : z[nz - 1] < hard) hard = z[nz - 1];
+              if (el ? cs > best_sl : cs < best_sl) {
+                best_sl = cs;
+                win = (k - D->cell_in_ptr[c]) * 2 + r_i;
+              }
+            }
+          }
+          if (el) {
+            double acc = 0.0;
+            for (int i = 0; i < nz; i++) acc += exp((z[i] - hard) / gamma);
+            at[p * 4 + el * 2 + r_o] = hard + gamma * log(acc);
+            sig = mix(sig, (uint64_t)win);
+          } else {
+            at[p * 4 + el * 2 + r_o] = hard;
+          }
+          sl[p * 4 + el * 2 + r_o] = best_sl;
+        }
+    }
+  }
+  /* endpoints and the smooth objective */
+  int32_t ne = 0;
+  for (int32_t p = 0; p < NP; p++)
+    if (is_endpoint(D, R, p)) out->ep_pin[ne++] = p;
+  out->n_ep = ne;
+  double tns = 0.0, mx = 0.0;
+  for (int32_t e = 0; e < ne; e++) {
+    int32_t p = out->ep_pin[e];
+    double rr, rf;
+    if (D->pin_kind[p] == PO_) {
+      rr = D->po_rat[R->rank[p] * 4 + 2];
+      rf = D->po_rat[R->rank[p] * 4 + 3];
+    } else {
+      rr = D->dangling_rat[2];
+      rf = D->dangling_rat[3];
+    }
+    double s = -lse2(at[p * 4 + 2] - rr, at[p * 4 + 3] - rf, gamma);
+    out->ep_s[e] = s;
+    tns += -gamma * softplus(-s / gamma);
+    if (-s / gamma > mx) mx = -s / gamma;
+  }
+  double acc = exp(-mx);
+  for (int32_t e = 0; e < ne; e++) acc += exp(-out->ep_s[e] / gamma - mx);
+  out->tns = tns;
+  out->wns = -gamma * (mx + log(acc));
+  out->sig = sig;
+  return 0;
+}
+
+int orc_smooth_sta(const orc_design *D, const double *wire_cap, double gamma, orc_smooth_result *out) {
+  int32_t NP = D->n_pins, nl;
+  int32_t *level = malloc(sizeof(int32_t) * (size_t)NP), *order = malloc(sizeof(int32_t) * (size_t)NP);
+  int cyc = orc_levelize(D, level, order, &nl);
+  if (!cyc) {
+    roles_t R;
+    roles_build(D, &R);
+    smooth_forward(D, &R, order, wire_cap, gamma, out);
+    roles_free(&R);
+  }
+  free(level);
+  free(order);
+  return cyc;
+}
+
+/* Gradient of J = g_tns TNS_g + g_wns WNS_g with respect to every RC node's
+ * ground cap (caller node order), every cell output's NLDM load (the partial
+ * through the lookups only, per pin) and every cell arc's additive delay per
+ * late output view (arcs in cell_in_pin order, [n_arcs][4], early views 0).
+ * Reverse mode over the smooth forward, in reverse level order. */
+int orc_smooth_adjoint(const orc_design *D, const double *wire_cap, double gamma, double g_tns, double g_wns,
+                       double *grad_cap, double *grad_load, double *grad_arc, orc_smooth_result *fwd) {
+  int32_t NP = D->n_pins, nl;
+  int32_t NS = D->net_sink_ptr[D->n_nets];
+  int32_t *level = malloc(sizeof(int32_t) * (size_t)NP), *order = malloc(sizeof(int32_t) * (size_t)NP);
+  if (orc_levelize(D, level, order, &nl)) {
+    free(level);
+    free(order);
+    return 1;
+  }
+  roles_t R;
+  roles_build(D, &R);
+  smooth_forward(D, &R, order, wire_cap, gamma, fwd);
+  const double *at = fwd->at, *sl = fwd->slew;
+  double *gA = calloc((size_t)NP * 2, sizeof(double)), *gS = calloc((size_t)NP * 2, sizeof(double));
+  double *gL = calloc((size_t)D->n_nets, sizeof(double));
+  double *gd = calloc((size_t)(NS > 0 ? NS : 1), sizeof(double)), *gq = calloc((size_t)(NS > 0 ? NS : 1), sizeof(double));
+  int32_t n_arcs = D->cell_in_ptr[D->n_cells];
+  memset(grad_arc, 0, sizeof(double) * (size_t)n_arcs * 4);
+  memset(grad_load, 0, sizeof(double) * (size_t)NP);
+
+  /* seeds at the endpoints */
+  double mx = 0.0;
+  for (int32_t e = 0; e < fwd->n_ep; e++)
+    if (-fwd->ep_s[e] / gamma > mx) mx = -fwd->ep_s[e] / gamma;
+  double den = exp(-mx);
+  for (int32_t e = 0; e < fwd->n_ep; e++) den += exp(-fwd->ep_s[e] / gamma - mx);
+  for (int32_t e = 0; e < fwd->n_ep; e++) {
+    int32_t p = fwd->ep_pin[e];
+    double s = fwd->ep_s[e];
+    double sig_t = 1.0 / (1.0 + exp(s / gamma));               /* d TNS_g / d s */
+    double sig_w = exp(-s / gamma - mx) / den;                  /* d WNS_g / d s */
+    double gs = g_tns * sig_t + g_wns * sig_w;
+    double rr, rf;
+    if (D->pin_kind[p] == PO_) {
+      rr = D->po_rat[R.rank[p] * 4 + 2];
+      rf = D->po_rat[R.rank[p] * 4 + 3];
+    } else {
+      rr = D->dangling_rat[2];
+      rf = D->dangling_rat[3];
+    }
+    /* s = -LSE(a_R, a_F), a = AT - RAT: ds/dAT_rf = -softmax_rf */
+    double aR = at[p * 4 + 2] - rr, aF = at[p * 4 + 3] - rf, l = lse2(aR, aF, gamma);
+    gA[p * 2 + 0] += -gs * exp((aR - l) / gamma);
+    gA[p * 2 + 1] += -gs * exp((aF - l) / gamma);
+  }
+
+  /* reverse sweep over late views */
+  for (int32_t o = NP - 1; o >= 0; o--) {
+    int32_t p = order[o];
+    int32_t kind = D->pin_kind[p];
+    if (kind == CIN_ || kind == PO_) {
+      int32_t s = R.sink_idx[p];
+      int32_t drv = D->net_driver[R.sink_net[s]];
+      for (int rf = 0; rf < 2; rf++) {
+        double sp = sl[p * 4 + 2 + rf], sd = sl[drv * 4 + 2 + rf];
+        gA[drv * 2 + rf] += gA[p * 2 + rf];
+        gd[s] += gA[p * 2 + rf];
+        gS[drv * 2 + rf] += gS[p * 2 + rf] * sd / sp;
+        gq[s] += gS[p * 2 + rf] / (2.0 * sp);
+      }
+    } else if (kind == COUT_) {
+      int32_t c = R.cell_of[p], type = D->cell_type[c], sense = D->sense[type];
+      int32_t net = R.drv_net[p];
+      double load = fwd->L_net[net];
+      const float *xa = D->slew_axis + (size_t)type * D->nx, *ya = D->load_axis + (size_t)type * D->ny;
+      for (int r_o = 0; r_o < 2; r_o++) {
+        double gat = gA[p * 2 + r_o], gsl = gS[p * 2 + r_o];
+        double best_sl = -INFINITY;
+        int32_t win_in = -1, win_ri = -1;
+        double win_dx = 0.0, win_dy = 0.0;
+        for (int32_t k = D->cell_in_ptr[c]; k < D->cell_in_ptr[c + 1]; k++) {
+          int32_t in = D->cell_in_pin[k];
+          for (int r_i = 0; r_i < 2; r_i++) {
+            if (!arc_maps(sense, r_i, r_o)) continue;
+            double x = sl[in * 4 + 2 + r_i], ddx, ddy, sdx, sdy;
+            double dl = nldm_d(D->nx, D->ny, xa, ya, tab_of(D, type, r_o), x, load, &ddx, &ddy, NULL);
+            double cs = nldm_d(D->nx, D->ny, xa, ya, tab_of(D, type, 2 + r_o), x, load, &sdx, &sdy, NULL);
+            double w = exp((at[in * 4 + 2 + r_i] + dl - at[p * 4 + 2 + r_o]) / gamma); /* softmax weight */
+            gA[in * 2 + r_i] += w * gat;
+            gS[in * 2 + r_i] += w * gat * ddx;
+            gL[net] += w * gat * ddy;
+            grad_arc[(size_t)k * 4 + 2 + r_o] += w * gat;
+            if (cs > best_sl) {
+              best_sl = cs;
+              win_in = in;
+              win_ri = r_i;
+              win_dx = sdx;
+              win_dy = sdy;
+            }
+          }
+        }
+        gS[win_in * 2 + win_ri] += gsl * win_dx;
+        gL[net] += gsl * win_dy;
+      }
+      grad_load[p] = gL[net];
+    }
+  }
+
+  /* RC adjoint per net: J depends on the node caps through L_net (every node),
+   * d_s and q_s = 2 m2 - d^2.  With R_kj the shared path resistance:
+   *   dd_v/dC_k = R_vk,   dm2_v/dC_k = R_vk d_k + sum_j C^_j R_vj R_jk,
+   * so, with gd_v = dJ/dd_v - 2 d_v dJ/dq_v and gm_v = 2 dJ/dq_v at sink nodes,
+   *   dJ/dC_k = gL + sum_{a on path(k)} R_a Gd(a) + d_k H_k + sum_{a on path(k)} R_a K(a)
+   *   Gd(a) = subtree sum of gd, H_j = sum_{a on path(j)} R_a Gm(a),
+   *   Gm(a) = subtree sum of gm, K(a) = subtree sum of C^ H. */
+  double *pc = malloc(sizeof(double) * (size_t)(NS > 0 ? NS : 1));
+  sink_pincaps(D, &R, pc);
+  int64_t maxm = 1;
+  for (int32_t n = 0; n < D->n_nets; n++) {
+    int64_t m = D->net_node_ptr[n + 1] - D->net_node_ptr[n];
+    if (m > maxm) maxm = m;
+  }
+  double *Rv = malloc(sizeof(double) * maxm), *Ch = malloc(sizeof(double) * maxm);
+  double *load = malloc(sizeof(double) * maxm), *dd = malloc(sizeof(double) * maxm);
+  double *ld = malloc(sizeof(double) * maxm), *m2 = malloc(sizeof(double) * maxm);
+  double *Gd = malloc(sizeof(double) * maxm), *Gm = malloc(sizeof(double) * maxm);
+  double *H = malloc(sizeof(double) * maxm), *K = malloc(sizeof(double) * maxm);
+  double *PA = malloc(sizeof(double) * maxm), *PB = malloc(sizeof(double) * maxm);
+  for (int32_t n = 0; n < D->n_nets; n++) {
+    int64_t base = D->net_node_ptr[n], m = D->net_node_ptr[n + 1] - base;
+    const int32_t *par = D->parent + base;
+    for (int64_t k = 0; k < m; k++) {
+      Rv[k] = (double)D->res_kohm[base + k];
+      Ch[k] = wire_cap ? wire_cap[base + k] : (double)D->cap_ff[base + k];
+      Gd[k] = Gm[k] = 0.0;
+    }
+    for (int32_t s = D->net_sink_ptr[n]; s < D->net_sink_ptr[n + 1]; s++) Ch[D->sink_node[s]] += pc[s];
+    orc_rc_tree(m, par, Rv, Ch, load, dd, ld, m2);
+    for (int32_t s = D->net_sink_ptr[n]; s < D->net_sink_ptr[n + 1]; s++) {
+      int32_t k = D->sink_node[s];
+      double qraw = 2.0 * m2[k] - dd[k] * dd[k];
+      double gqs = qraw > 0.0 ? gq[s] : 0.0;
+      Gd[k] += gd[s] - 2.0 * dd[k] * gqs;
+      Gm[k] += 2.0 * gqs;
+    }
+    for (int64_t k = m - 1; k >= 1; k--) {
+      Gd[par[k]] += Gd[k];
+      Gm[par[k]] += Gm[k];
+    }
+    H[0] = 0.0;
+    PA[0] = 0.0;
+    for (int64_t k = 1; k < m; k++) {
+      H[k] = H[par[k]] + Rv[k] * Gm[k];
+      PA[k] = PA[par[k]] + Rv[k] * Gd[k];
+    }
+    for (int64_t k = 0; k < m; k++) K[k] = Ch[k] * H[k];
+    for (int64_t k = m - 1; k >= 1; k--) K[par[k]] += K[k];
+    PB[0] = 0.0;
+    for (int64_t k = 1; k < m; k++) PB[k] = PB[par[k]] + Rv[k] * K[k];
+    for (int64_t k = 0; k < m; k++) grad_cap[base + k] = gL[n] + PA[k] + dd[k] * H[k] + PB[k];
+  }
+  free(Rv); free(Ch); free(load); free(dd); free(ld); free(m2); free(Gd); free(Gm); free(H); free(K);
+  free(PA); free(PB); free(pc);
+  free(gA); free(gS); free(gL); free(gd); free(gq);
+  roles_free(&R);
+  free(level);
+  free(order);
+  return 0;
+}

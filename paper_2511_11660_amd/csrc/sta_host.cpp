@@ -1,0 +1,998 @@
+// Host runtime behind include/sta.h: input validation, device levelization
+// driver, level-sorted device layout, update sequencing and reports.
+//
+// Inputs follow the paper's flattened interface (§III "Heterogeneous netlist
+// database", "Parasitics (RC) inputs"); outputs may go to host or device memory
+// (§III "Report options").  Validation is pure host code and runs before the
+// first HIP call, so malformed inputs are rejected without a device.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/sta.h"
+#include "sta_internal.h"
+
+using namespace sta;
+
+namespace {
+
+thread_local std::string g_err;
+
+sta_status fail(sta_status s, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+sta_status hip_fail(hipError_t e, const char *what) {
+  return fail(e == hipErrorOutOfMemory ? STA_E_OOM : STA_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr)                                   \
+  do {                                                  \
+    hipError_t e_ = (expr);                             \
+    if (e_ != hipSuccess) return hip_fail(e_, #expr);   \
+  } while (0)
+
+#define STA_TRY(expr)              \
+  do {                             \
+    sta_status s_ = (expr);        \
+    if (s_ != STA_OK) return s_;   \
+  } while (0)
+
+// Owned device allocation.
+struct DevMem {
+  void *p = nullptr;
+  DevMem() = default;
+  DevMem(const DevMem &) = delete;
+  DevMem &operator=(const DevMem &) = delete;
+  ~DevMem() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+// Host view of one input array: the caller's host memory or a host copy of
+// caller device memory.
+template <class T>
+struct HostArr {
+  const T *p = nullptr;
+  std::vector<T> own;
+  sta_status load(const T *src, size_t n, sta_mem mem, const char *name) {
+    if (n == 0) {
+      p = nullptr;
+      return STA_OK;
+    }
+    if (!src) return fail(STA_E_ARG, "%s is NULL", name);
+    if (mem == STA_HOST) {
+      p = src;
+      return STA_OK;
+    }
+    own.resize(n);
+    hipError_t e = hipMemcpy(own.data(), src, n * sizeof(T), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, name);
+    p = own.data();
+    return STA_OK;
+  }
+  const T &operator[](size_t i) const { return p[i]; }
+};
+
+bool finite(float v) { return std::isfinite(v); }
+
+}  // namespace
+
+struct sta_ctx {
+  int device = 0;
+  sta_options opt{};
+  int n_pins = 0, n_cells = 0, n_nets = 0, n_pi = 0, n_po = 0, n_sinks = 0, n_drv = 0, n_ep = 0;
+  int n_cell_levels = 0, n_levels = 0, n_chunks = 0, n_big = 0, n_rc_chunks = 0;
+  int64_t n_nodes = 0;
+  int n_cu = 0, sweep_grid = 1;
+  std::vector<std::unique_ptr<DevMem>> mem;
+  DevDesign D{};
+  float *rc_cap = nullptr;
+  int32_t *pin_loc = nullptr, *net_slot = nullptr, *sink_slot = nullptr, *node_src = nullptr;
+  int32_t *ep_pin = nullptr, *pin_level = nullptr, *level_order = nullptr;
+  int2 *rc_chunks = nullptr;
+  BigNet *big = nullptr;
+  int32_t *big_end = nullptr;
+  float *big_pc = nullptr;
+  double *big_scratch = nullptr;
+  double *partials = nullptr, *out = nullptr;
+  uint32_t *keys = nullptr, *keys_out = nullptr;
+  int32_t *vals = nullptr, *order = nullptr;
+  void *sort_temp = nullptr;
+  size_t sort_bytes = 0;
+  std::vector<int> level_chunk_begin;  // [n_cell_levels+2]
+  hipEvent_t ev[8]{};
+  bool events = false, timed = false;
+  hipStream_t last_stream = nullptr;
+
+  template <class T>
+  sta_status alloc(T **out_p, size_t n) {
+    auto m = std::make_unique<DevMem>();
+    if (n == 0) n = 1;
+    hipError_t e = hipMalloc(&m->p, n * sizeof(T));
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+    *out_p = static_cast<T *>(m->p);
+    mem.push_back(std::move(m));
+    return STA_OK;
+  }
+  template <class T>
+  sta_status upload(T **out_p, const std::vector<T> &h) {
+    STA_TRY(alloc(out_p, h.size()));
+    if (!h.empty()) HIP_TRY(hipMemcpy(*out_p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+    return STA_OK;
+  }
+  ~sta_ctx() {
+    if (events)
+      for (auto &e : ev) (void)hipEventDestroy(e);
+  }
+};
+
+extern "C" {
+
+void sta_options_default(sta_options *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof *o);
+  o->mode = 0;
+  o->gamma_ps = 5.0f;
+  o->dangling_policy = 0;
+  o->sched = STA_SCHED_PERSISTENT;
+  o->big_net_nodes = 0;
+  o->sort_endpoints = 1;
+  o->profile = 0;
+  o->device = -1;
+}
+
+const char *sta_status_string(sta_status s) {
+  switch (s) {
+    case STA_OK: return "STA_OK";
+    case STA_E_ARG: return "STA_E_ARG";
+    case STA_E_CYCLE: return "STA_E_CYCLE";
+    case STA_E_OOM: return "STA_E_OOM";
+    case STA_E_DEVICE: return "STA_E_DEVICE";
+    case STA_E_STATE: return "STA_E_STATE";
+    case STA_E_UNSUPPORTED: return "STA_E_UNSUPPORTED";
+  }
+  return "STA_E_UNKNOWN";
+}
+
+const char *sta_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"
+
+namespace {
+
+// All host-side input arrays of sta_create.
+struct Inputs {
+  const sta_graph_desc *g;
+  const sta_rc_desc *rc;
+  const sta_lib_desc *lib;
+  const sta_constraints *cons;
+  HostArr<int32_t> pin_kind, cell_type, cell_in_ptr, cell_in_pin, cell_out_pin;
+  HostArr<int32_t> net_driver, net_sink_ptr, net_sink_pin;
+  HostArr<int64_t> net_node_ptr;
+  HostArr<int32_t> parent, sink_node;
+  HostArr<float> res, cap;
+  // derived pin maps
+  std::vector<int32_t> cell_of_pin, net_of_drv, sink_idx_of_pin, drv_of_sink_pin, rank;
+};
+
+sta_status load_graph(Inputs &I) {
+  const sta_graph_desc &g = *I.g;
+  if (g.n_pins < 1 || g.n_cells < 0 || g.n_nets < 1 || g.n_pi < 1 || g.n_po < 0)
+    return fail(STA_E_ARG, "bad graph sizes (pins %d cells %d nets %d pi %d po %d)", g.n_pins, g.n_cells,
+                g.n_nets, g.n_pi, g.n_po);
+  if (g.mem != STA_HOST && g.mem != STA_DEVICE) return fail(STA_E_ARG, "graph.mem invalid");
+  STA_TRY(I.pin_kind.load(g.pin_kind, g.n_pins, g.mem, "pin_kind"));
+  STA_TRY(I.cell_in_ptr.load(g.cell_in_ptr, (size_t)g.n_cells + 1, g.mem, "cell_in_ptr"));
+  STA_TRY(I.net_sink_ptr.load(g.net_sink_ptr, (size_t)g.n_nets + 1, g.mem, "net_sink_ptr"));
+  if (I.cell_in_ptr[0] != 0 || I.net_sink_ptr[0] != 0) return fail(STA_E_ARG, "CSR offsets must start at 0");
+  const int32_t n_cin = I.cell_in_ptr[g.n_cells], n_sink = I.net_sink_ptr[g.n_nets];
+  if (n_cin < 0 || n_sink < 0) return fail(STA_E_ARG, "negative CSR size");
+  STA_TRY(I.cell_type.load(g.cell_type, g.n_cells, g.mem, "cell_type"));
+  STA_TRY(I.cell_in_pin.load(g.cell_in_pin, n_cin, g.mem, "cell_in_pin"));
+  STA_TRY(I.cell_out_pin.load(g.cell_out_pin, g.n_cells, g.mem, "cell_out_pin"));
+  STA_TRY(I.net_driver.load(g.net_driver, g.n_nets, g.mem, "net_driver"));
+  STA_TRY(I.net_sink_pin.load(g.net_sink_pin, n_sink, g.mem, "net_sink_pin"));
+  return STA_OK;
+}
+
+sta_status validate_graph(Inputs &I) {
+  const sta_graph_desc &g = *I.g;
+  const sta_lib_desc &lib = *I.lib;
+  const int NP = g.n_pins;
+  int cnt[4] = {0, 0, 0, 0};
+  I.rank.assign(NP, -1);
+  for (int p = 0; p < NP; ++p) {
+    const int k = I.pin_kind[p];
+    if (k < 0 || k > 3) return fail(STA_E_ARG, "pin %d has kind %d", p, k);
+    if (k == STA_PIN_PI || k == STA_PIN_PO) I.rank[p] = cnt[k];
+    cnt[k]++;
+  }
+  if (cnt[STA_PIN_PI] != g.n_pi || cnt[STA_PIN_PO] != g.n_po || cnt[STA_PIN_CELL_OUT] != g.n_cells)
+    return fail(STA_E_ARG, "pin kind counts (PI %d, PO %d, cell out %d) disagree with n_pi/n_po/n_cells",
+                cnt[0], cnt[3], cnt[2]);
+  if (g.n_nets != g.n_pi + g.n_cells)
+    return fail(STA_E_ARG, "every PI and cell output drives one net: n_nets must be %d", g.n_pi + g.n_cells);
+  if (I.cell_in_ptr[g.n_cells] != cnt[STA_PIN_CELL_IN])
+    return fail(STA_E_ARG, "cell_in_ptr covers %d pins, design has %d cell inputs", I.cell_in_ptr[g.n_cells],
+                cnt[1]);
+  if (I.net_sink_ptr[g.n_nets] != cnt[STA_PIN_CELL_IN] + cnt[STA_PIN_PO])
+    return fail(STA_E_ARG, "net_sink_ptr covers %d sinks, design has %d", I.net_sink_ptr[g.n_nets],
+                cnt[1] + cnt[3]);
+  I.cell_of_pin.assign(NP, -1);
+  for (int c = 0; c < g.n_cells; ++c) {
+    const int a = I.cell_in_ptr[c], b = I.cell_in_ptr[c + 1];
+    if (b <= a) return fail(STA_E_ARG, "cell %d has no inputs or decreasing cell_in_ptr", c);
+    const int t = I.cell_type[c];
+    if (t < 0 || t >= lib.n_types) return fail(STA_E_ARG, "cell %d has type %d", c, t);
+    if (lib.n_inputs[t] != b - a)
+      return fail(STA_E_ARG, "cell %d has %d inputs, its type %d has %d", c, b - a, t, lib.n_inputs[t]);
+    for (int k = a; k < b; ++k) {
+      const int p = I.cell_in_pin[k];
+      if (p < 0 || p >= NP || I.pin_kind[p] != STA_PIN_CELL_IN)
+        return fail(STA_E_ARG, "cell %d input %d is pin %d, not a cell input pin", c, k - a, p);
+      if (I.cell_of_pin[p] >= 0) return fail(STA_E_ARG, "pin %d is an input of two cells", p);
+      I.cell_of_pin[p] = c;
+    }
+    const int o = I.cell_out_pin[c];
+    if (o < 0 || o >= NP || I.pin_kind[o] != STA_PIN_CELL_OUT)
+      return fail(STA_E_ARG, "cell %d output is pin %d, not a cell output pin", c, o);
+    if (I.cell_of_pin[o] >= 0) return fail(STA_E_ARG, "pin %d is the output of two cells", o);
+    I.cell_of_pin[o] = c;
+  }
+  I.net_of_drv.assign(NP, -1);
+  I.sink_idx_of_pin.assign(NP, -1);
+  I.drv_of_sink_pin.assign(NP, -1);
+  for (int n = 0; n < g.n_nets; ++n) {
+    const int d = I.net_driver[n];
+    if (d < 0 || d >= NP || (I.pin_kind[d] != STA_PIN_PI && I.pin_kind[d] != STA_PIN_CELL_OUT))
+      return fail(STA_E_ARG, "net %d driver %d is not a PI or cell output", n, d);
+    if (I.net_of_drv[d] >= 0) return fail(STA_E_ARG, "pin %d drives two nets", d);
+    I.net_of_drv[d] = n;
+    const int a = I.net_sink_ptr[n], b = I.net_sink_ptr[n + 1];
+    if (b < a) return fail(STA_E_ARG, "net_sink_ptr decreases at net %d", n);
+    for (int s = a; s < b; ++s) {
+      const int p = I.net_sink_pin[s];
+      if (p < 0 || p >= NP || (I.pin_kind[p] != STA_PIN_CELL_IN && I.pin_kind[p] != STA_PIN_PO))
+        return fail(STA_E_ARG, "net %d sink %d is pin %d, not a cell input or PO", n, s - a, p);
+      if (I.sink_idx_of_pin[p] >= 0) return fail(STA_E_ARG, "pin %d is a sink of two nets", p);
+      I.sink_idx_of_pin[p] = s;
+      I.drv_of_sink_pin[p] = d;
+    }
+  }
+  return STA_OK;
+}
+
+sta_status load_validate_rc(Inputs &I) {
+  const sta_rc_desc &rc = *I.rc;
+  const sta_graph_desc &g = *I.g;
+  if (rc.mem != STA_HOST && rc.mem != STA_DEVICE) return fail(STA_E_ARG, "rc.mem invalid");
+  if (rc.n_nodes < g.n_nets || rc.n_nodes >= (int64_t)INT32_MAX)
+    return fail(STA_E_ARG, "rc.n_nodes %lld out of range", (long long)rc.n_nodes);
+  const size_t NN = (size_t)rc.n_nodes;
+  STA_TRY(I.net_node_ptr.load(rc.net_node_ptr, (size_t)g.n_nets + 1, rc.mem, "net_node_ptr"));
+  STA_TRY(I.parent.load(rc.parent, NN, rc.mem, "parent"));
+  STA_TRY(I.res.load(rc.res_kohm, NN, rc.mem, "res_kohm"));
+  STA_TRY(I.cap.load(rc.cap_ff, NN, rc.mem, "cap_ff"));
+  STA_TRY(I.sink_node.load(rc.sink_node, (size_t)I.net_sink_ptr[g.n_nets], rc.mem, "sink_node"));
+  if (I.net_node_ptr[0] != 0 || I.net_node_ptr[g.n_nets] != rc.n_nodes)
+    return fail(STA_E_ARG, "net_node_ptr must run from 0 to n_nodes");
+  for (int n = 0; n < g.n_nets; ++n) {
+    const int64_t a = I.net_node_ptr[n], b = I.net_node_ptr[n + 1];
+    if (b <= a) return fail(STA_E_ARG, "net %d has no RC node (root required)", n);
+    if (I.parent[a] != -1) return fail(STA_E_ARG, "net %d: root parent must be -1", n);
+    for (int64_t k = a + 1; k < b; ++k) {
+      const int64_t pk = I.parent[k];
+      if (pk < 0 || pk >= k - a) return fail(STA_E_ARG, "net %d node %lld: parent %lld not < child", n,
+                                            (long long)(k - a), (long long)pk);
+    }
+    for (int s = I.net_sink_ptr[n]; s < I.net_sink_ptr[n + 1]; ++s) {
+      const int64_t k = I.sink_node[s];
+      if (k < 0 || k >= b - a) return fail(STA_E_ARG, "sink %d: node %lld outside its net", s, (long long)k);
+    }
+  }
+  for (size_t k = 0; k < NN; ++k) {
+    if (!finite(I.res[k]) || I.res[k] < 0.0f) return fail(STA_E_ARG, "res_kohm[%zu] invalid", k);
+    if (!finite(I.cap[k]) || I.cap[k] < 0.0f) return fail(STA_E_ARG, "cap_ff[%zu] invalid", k);
+  }
+  return STA_OK;
+}
+
+sta_status validate_lib(const sta_lib_desc &L) {
+  if (L.n_types < 1 || L.n_types > kMaxTypes) return fail(STA_E_UNSUPPORTED, "n_types %d not in [1, %d]", L.n_types, kMaxTypes);
+  if (L.nx < 2 || L.ny < 2 || L.nx > kMaxAxis || L.ny > kMaxAxis)
+    return fail(STA_E_UNSUPPORTED, "table size %dx%d not in [2,8]x[2,8]", L.nx, L.ny);
+  if (!L.n_inputs || !L.sense || !L.pin_cap_ff || !L.slew_axis || !L.load_axis || !L.tables)
+    return fail(STA_E_ARG, "library array is NULL");
+  if (!finite(L.po_cap_ff) || L.po_cap_ff < 0.0f) return fail(STA_E_ARG, "po_cap_ff invalid");
+  for (int t = 0; t < L.n_types; ++t) {
+    if (L.n_inputs[t] < 1) return fail(STA_E_ARG, "type %d has %d inputs", t, L.n_inputs[t]);
+    if (L.sense[t] < 0 || L.sense[t] > 2) return fail(STA_E_ARG, "type %d sense %d", t, L.sense[t]);
+    if (!finite(L.pin_cap_ff[t]) || L.pin_cap_ff[t] < 0.0f) return fail(STA_E_ARG, "type %d pin cap", t);
+    for (int i = 0; i < L.nx; ++i) {
+      const float v = L.slew_axis[t * L.nx + i];
+      if (!finite(v) || (i > 0 && !(v > L.slew_axis[t * L.nx + i - 1])))
+        return fail(STA_E_ARG, "type %d slew axis not strictly increasing", t);
+    }
+    for (int j = 0; j < L.ny; ++j) {
+      const float v = L.load_axis[t * L.ny + j];
+      if (!finite(v) || (j > 0 && !(v > L.load_axis[t * L.ny + j - 1])))
+        return fail(STA_E_ARG, "type %d load axis not strictly increasing", t);
+    }
+    for (int k = 0; k < 4 * L.nx * L.ny; ++k)
+      if (!finite(L.tables[(size_t)t * 4 * L.nx * L.ny + k])) return fail(STA_E_ARG, "type %d table value", t);
+  }
+  return STA_OK;
+}
+
+sta_status validate_cons(const sta_constraints &C, const sta_graph_desc &g) {
+  if (!C.pi_at || !C.pi_slew || (g.n_po > 0 && !C.po_rat)) return fail(STA_E_ARG, "constraint array is NULL");
+  for (int i = 0; i < g.n_pi * 4; ++i) {
+    if (!finite(C.pi_at[i])) return fail(STA_E_ARG, "pi_at[%d] not finite", i);
+    if (!finite(C.pi_slew[i]) || C.pi_slew[i] < 0.0f) return fail(STA_E_ARG, "pi_slew[%d] invalid", i);
+  }
+  for (int i = 0; i < g.n_po * 4; ++i)
+    if (!finite(C.po_rat[i])) return fail(STA_E_ARG, "po_rat[%d] not finite", i);
+  for (int v = 0; v < 4; ++v)
+    if (!finite(C.dangling_rat[v])) return fail(STA_E_ARG, "dangling_rat not finite");
+  return STA_OK;
+}
+
+// DFS preorder of one tree (children visited in increasing index); returns
+// new_of_old.
+std::vector<int32_t> preorder(const int32_t *par, int m) {
+  std::vector<int32_t> cnt(m + 1, 0), kids(m > 0 ? m - 1 : 0), pos(m + 1, 0);
+  for (int k = 1; k < m; ++k) cnt[par[k] + 1]++;
+  for (int k = 0; k < m; ++k) cnt[k + 1] += cnt[k];
+  for (int k = 0; k < m; ++k) pos[k] = cnt[k];
+  for (int k = 1; k < m; ++k) kids[pos[par[k]]++] = k;
+  std::vector<int32_t> newof(m), stack;
+  stack.reserve(m);
+  stack.push_back(0);
+  int next = 0;
+  while (!stack.empty()) {
+    const int u = stack.back();
+    stack.pop_back();
+    newof[u] = next++;
+    for (int i = cnt[u + 1] - 1; i >= cnt[u]; --i) stack.push_back(kids[i]);
+  }
+  return newof;
+}
+
+}  // namespace
+
+// Levelize on the device; fills cell_level (host) and the context's pin levels
+// and level order.
+static sta_status levelize(sta_ctx *C, const Inputs &I, std::vector<int32_t> &cell_level) {
+  const sta_graph_desc &g = *I.g;
+  const int NP = g.n_pins, NC = g.n_cells;
+  std::vector<int32_t> cell_nin(NC), cell_of_in(NP, -1), pis;
+  for (int c = 0; c < NC; ++c) cell_nin[c] = I.cell_in_ptr[c + 1] - I.cell_in_ptr[c];
+  for (int p = 0; p < NP; ++p) {
+    if (I.pin_kind[p] == STA_PIN_CELL_IN) cell_of_in[p] = I.cell_of_pin[p];
+    if (I.pin_kind[p] == STA_PIN_PI) pis.push_back(p);
+  }
+  std::vector<int32_t> h_kind(I.pin_kind.p, I.pin_kind.p + NP);
+  std::vector<int32_t> h_nsp(I.net_sink_ptr.p, I.net_sink_ptr.p + g.n_nets + 1);
+  std::vector<int32_t> h_nsn(I.net_sink_pin.p, I.net_sink_pin.p + h_nsp.back());
+  std::vector<int32_t> h_cout(I.cell_out_pin.p, I.cell_out_pin.p + NC);
+  sta_ctx tmp;  // scratch allocations released on return
+  int32_t *d_kind, *d_net_of_drv, *d_nsp, *d_nsn, *d_cell_of_in, *d_cout, *d_nin, *d_cell_of_pin, *d_drv_of_sink;
+  int32_t *d_pending, *d_cell_level, *d_fa, *d_fb, *d_keys, *d_keys_out, *d_vals;
+  uint32_t *d_cnt;
+  STA_TRY(tmp.upload(&d_kind, h_kind));
+  STA_TRY(tmp.upload(&d_net_of_drv, I.net_of_drv));
+  STA_TRY(tmp.upload(&d_nsp, h_nsp));
+  STA_TRY(tmp.upload(&d_nsn, h_nsn));
+  STA_TRY(tmp.upload(&d_cell_of_in, cell_of_in));
+  STA_TRY(tmp.upload(&d_cout, h_cout));
+  STA_TRY(tmp.upload(&d_nin, cell_nin));
+  STA_TRY(tmp.upload(&d_cell_of_pin, I.cell_of_pin));
+  STA_TRY(tmp.upload(&d_drv_of_sink, I.drv_of_sink_pin));
+  STA_TRY(tmp.alloc(&d_pending, NC));
+  STA_TRY(tmp.alloc(&d_cell_level, NC));
+  STA_TRY(tmp.alloc(&d_fa, std::max(NP, 1)));
+  STA_TRY(tmp.alloc(&d_fb, std::max(NP, 1)));
+  STA_TRY(tmp.alloc(&d_cnt, 1));
+  HIP_TRY(hipMemcpy(d_fa, pis.data(), pis.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  HIP_TRY(launch_level_init(d_pending, d_cell_level, d_nin, NC, nullptr));
+  int n_front = (int)pis.size(), lvl = 0;
+  while (n_front > 0) {
+    HIP_TRY(hipMemset(d_cnt, 0, sizeof(uint32_t)));
+    HIP_TRY(launch_level_step(d_fa, n_front, lvl, d_net_of_drv, d_nsp, d_nsn, d_cell_of_in, d_cout, d_pending,
+                              d_cell_level, d_fb, d_cnt, nullptr));
+    uint32_t nn = 0;
+    HIP_TRY(hipMemcpy(&nn, d_cnt, sizeof nn, hipMemcpyDeviceToHost));
+    std::swap(d_fa, d_fb);
+    n_front = (int)nn;
+    ++lvl;
+  }
+  cell_level.resize(NC);
+  if (NC > 0)
+    HIP_TRY(hipMemcpy(cell_level.data(), d_cell_level, NC * sizeof(int32_t), hipMemcpyDeviceToHost));
+  for (int c = 0; c < NC; ++c)
+    if (cell_level[c] < 0) return fail(STA_E_CYCLE, "combinational cycle through cell %d", c);
+  // pin levels and the (level, pin id) order, on the device
+  STA_TRY(C->alloc(&C->pin_level, NP));
+  STA_TRY(C->alloc(&C->level_order, NP));
+  HIP_TRY(launch_pin_levels(d_kind, d_cell_of_pin, d_cell_level, d_drv_of_sink, C->pin_level, NP, nullptr));
+  STA_TRY(tmp.alloc(&d_vals, NP));
+  STA_TRY(tmp.alloc(&d_keys_out, NP));
+  HIP_TRY(launch_iota(d_vals, NP, nullptr));
+  int maxc = 0;
+  for (int c = 0; c < NC; ++c) maxc = std::max(maxc, cell_level[c]);
+  const int max_pin_level = 2 * maxc + 1;
+  int bits = 1;
+  while ((1 << bits) <= max_pin_level) ++bits;
+  const size_t tb = level_sort_temp_bytes(NP);
+  void *d_temp;
+  STA_TRY(tmp.alloc(reinterpret_cast<unsigned char **>(&d_temp), tb));
+  d_keys = C->pin_level;
+  HIP_TRY(sort_levels(d_temp, tb, d_keys, d_keys_out, d_vals, C->level_order, NP, bits, nullptr));
+  HIP_TRY(hipDeviceSynchronize());
+  std::vector<int32_t> pl(NP);
+  HIP_TRY(hipMemcpy(pl.data(), C->pin_level, NP * sizeof(int32_t), hipMemcpyDeviceToHost));
+  C->n_levels = 1 + *std::max_element(pl.begin(), pl.end());
+  C->n_cell_levels = maxc;
+  return STA_OK;
+}
+
+static sta_status build_layout(sta_ctx *C, const Inputs &I, const std::vector<int32_t> &cell_level) {
+  const sta_graph_desc &g = *I.g;
+  const sta_lib_desc &lib = *I.lib;
+  const sta_constraints &cons = *I.cons;
+  const int NP = g.n_pins, NC = g.n_cells, NPI = g.n_pi;
+  const int L = C->n_cell_levels;
+  int big_thr = C->opt.big_net_nodes > 0 ? C->opt.big_net_nodes : kSmallNetMaxNodes;
+  if (big_thr > kSmallNetMaxNodes) big_thr = kSmallNetMaxNodes;
+
+  // driver slots: PIs by pin id, then cells by (level, output pin id)
+  std::vector<int32_t> drv_pin;
+  drv_pin.reserve(NPI + NC);
+  std::vector<int32_t> lvl_ptr(L + 2, 0);
+  for (int p = 0; p < NP; ++p)
+    if (I.pin_kind[p] == STA_PIN_PI) drv_pin.push_back(p);
+  lvl_ptr[1] = NPI;
+  {
+    std::vector<int32_t> cnt(L + 2, 0);
+    for (int c = 0; c < NC; ++c) cnt[cell_level[c]]++;
+    for (int l = 1; l <= L; ++l) lvl_ptr[l + 1] = lvl_ptr[l] + cnt[l];
+    std::vector<int32_t> fill(lvl_ptr.begin(), lvl_ptr.end());
+    drv_pin.resize(NPI + NC);
+    for (int p = 0; p < NP; ++p)
+      if (I.pin_kind[p] == STA_PIN_CELL_OUT) drv_pin[fill[cell_level[I.cell_of_pin[p]]]++] = p;
+  }
+  const int ND = NPI + NC;
+  C->n_drv = ND;
+  std::vector<int32_t> slot_of_pin(NP, -1);
+  for (int x = 0; x < ND; ++x) slot_of_pin[drv_pin[x]] = x;
+
+  // endpoints: POs, plus dangling cell outputs under dangling_policy 1
+  std::vector<int32_t> ep_of_pin(NP, -1), ep_pin;
+  std::vector<float4> ep_rat;
+  for (int p = 0; p < NP; ++p) {
+    const int k = I.pin_kind[p];
+    bool is_ep = k == STA_PIN_PO;
+    if (k == STA_PIN_CELL_OUT && C->opt.dangling_policy) {
+      const int n = I.net_of_drv[p];
+      is_ep = I.net_sink_ptr[n + 1] == I.net_sink_ptr[n];
+    }
+    if (!is_ep) continue;
+    ep_of_pin[p] = (int)ep_pin.size();
+    ep_pin.push_back(p);
+    if (k == STA_PIN_PO) {
+      const float *r = cons.po_rat + 4 * (size_t)I.rank[p];
+      ep_rat.push_back(make_float4(r[0], r[1], r[2], r[3]));
+    } else {
+      ep_rat.push_back(make_float4(cons.dangling_rat[0], cons.dangling_rat[1], cons.dangling_rat[2],
+                                   cons.dangling_rat[3]));
+    }
+  }
+  C->n_ep = (int)ep_pin.size();
+
+  // nets in slot order, sinks net-major, RC nodes net-major
+  std::vector<int32_t> sink_ptr(ND + 1, 0), rc_ptr(ND + 1, 0), net_slot(g.n_nets);
+  for (int x = 0; x < ND; ++x) {
+    const int n = I.net_of_drv[drv_pin[x]];
+    net_slot[n] = x;
+    sink_ptr[x + 1] = sink_ptr[x] + (I.net_sink_ptr[n + 1] - I.net_sink_ptr[n]);
+    const int64_t m = I.net_node_ptr[n + 1] - I.net_node_ptr[n];
+    if ((int64_t)rc_ptr[x] + m >= INT32_MAX) return fail(STA_E_UNSUPPORTED, "too many RC nodes");
+    rc_ptr[x + 1] = rc_ptr[x] + (int32_t)m;
+  }
+  const int NS = sink_ptr[ND];
+  const int64_t NN = rc_ptr[ND];
+  C->n_sinks = NS;
+  C->n_nodes = NN;
+  std::vector<int32_t> sink_drv(NS), sink_cons(NS), sink_node(NS), sink_slot(NS), pin_loc(NP);
+  std::vector<float> sink_pincap(NS), rc_res(NN), rc_cap(NN);
+  std::vector<int32_t> rc_parent(NN), node_src(NN), big_x, big_end;
+  std::vector<float> big_pc;
+  std::vector<BigNet> big;
+  int64_t big_scr = 0;
+  for (int x = 0; x < ND; ++x) {
+    const int n = I.net_of_drv[drv_pin[x]];
+    const int64_t cb = I.net_node_ptr[n];
+    const int m = rc_ptr[x + 1] - rc_ptr[x];
+    const int base = rc_ptr[x];
+    const bool is_big = m > big_thr;
+    std::vector<int32_t> newof;
+    if (is_big) {
+      newof = preorder(I.parent.p + cb, m);
+      big_x.push_back(x);
+      BigNet bn;
+      bn.x = x;
+      bn.m = m;
+      bn.aux = (int64_t)big_end.size();
+      bn.scr = big_scr;
+      big.push_back(bn);
+      big_scr += 4 * ((int64_t)m + 1);
+    }
+    for (int k = 0; k < m; ++k) {
+      const int nk = is_big ? newof[k] : k;
+      const int pk = I.parent[cb + k];
+      rc_parent[base + nk] = pk < 0 ? -1 : (is_big ? newof[pk] : pk);
+      rc_res[base + nk] = I.res[cb + k];
+      rc_cap[base + nk] = I.cap[cb + k];
+      node_src[base + nk] = (int32_t)(cb + k);
+    }
+    if (is_big) {
+      // subtree end of each node in preorder, and the receiving pin caps per node
+      std::vector<int32_t> size(m, 1);
+      for (int k = m - 1; k >= 1; --k) size[rc_parent[base + k]] += size[k];
+      std::vector<double> pcd(m, 0.0);
+      for (int sc = I.net_sink_ptr[n]; sc < I.net_sink_ptr[n + 1]; ++sc) {
+        const int p = I.net_sink_pin[sc];
+        pcd[newof[I.sink_node[sc]]] +=
+            I.pin_kind[p] == STA_PIN_PO ? lib.po_cap_ff : lib.pin_cap_ff[I.cell_type[I.cell_of_pin[p]]];
+      }
+      for (int k = 0; k < m; ++k) {
+        big_end.push_back(k + size[k]);
+        big_pc.push_back((float)pcd[k]);
+      }
+    }
+    int s = sink_ptr[x];
+    for (int sc = I.net_sink_ptr[n]; sc < I.net_sink_ptr[n + 1]; ++sc, ++s) {
+      const int p = I.net_sink_pin[sc];
+      sink_slot[sc] = s;
+      sink_drv[s] = x;
+      const int k = I.sink_node[sc];
+      sink_node[s] = is_big ? newof[k] : k;
+      if (I.pin_kind[p] == STA_PIN_PO) {
+        sink_pincap[s] = lib.po_cap_ff;
+        sink_cons[s] = -1 - ep_of_pin[p];
+      } else {
+        const int c = I.cell_of_pin[p];
+        sink_pincap[s] = lib.pin_cap_ff[I.cell_type[c]];
+        sink_cons[s] = slot_of_pin[I.cell_out_pin[c]];
+      }
+      pin_loc[p] = -1 - s;
+    }
+    pin_loc[drv_pin[x]] = x;
+  }
+  C->n_big = (int)big_x.size();
+
+  // per driver slot: cell type, fanin (sink slots of the inputs), endpoint
+  std::vector<int32_t> cell_type(ND, -1), fanin_ptr(ND + 1, 0), fanin_sink, drv_ep(ND, -1);
+  fanin_sink.reserve(I.cell_in_ptr[NC]);
+  for (int x = 0; x < ND; ++x) {
+    const int p = drv_pin[x];
+    drv_ep[x] = ep_of_pin[p];
+    if (x >= NPI) {
+      const int c = I.cell_of_pin[p];
+      cell_type[x] = I.cell_type[c];
+      for (int k = I.cell_in_ptr[c]; k < I.cell_in_ptr[c + 1]; ++k)
+        fanin_sink.push_back(sink_slot[I.sink_idx_of_pin[I.cell_in_pin[k]]]);
+    }
+    fanin_ptr[x + 1] = (int32_t)fanin_sink.size();
+  }
+  std::vector<float4> pi_at(NPI), pi_slew(NPI);
+  for (int x = 0; x < NPI; ++x) {
+    const int r = I.rank[drv_pin[x]];
+    const float *a = cons.pi_at + 4 * (size_t)r, *s = cons.pi_slew + 4 * (size_t)r;
+    pi_at[x] = make_float4(a[0], a[1], a[2], a[3]);
+    pi_slew[x] = make_float4(s[0], s[1], s[2], s[3]);
+  }
+
+  // sweep chunks: 64 consecutive slots of one level
+  std::vector<int32_t> chunk_start, chunk_level, level_nchunks(L + 1, 0);
+  C->level_chunk_begin.assign(L + 2, 0);
+  for (int l = 0; l <= L; ++l) {
+    C->level_chunk_begin[l] = (int)chunk_level.size();
+    for (int x = lvl_ptr[l]; x < lvl_ptr[l + 1]; x += kChunk) {
+      chunk_start.push_back(x);
+      chunk_level.push_back(l);
+      level_nchunks[l]++;
+    }
+  }
+  C->level_chunk_begin[L + 1] = (int)chunk_level.size();
+  chunk_start.push_back(ND);
+  C->n_chunks = (int)chunk_level.size();
+
+  // RC chunks: runs of small nets, <= kRcBlock nets and <= kRcChunkNodes nodes
+  std::vector<int2> rc_chunks;
+  {
+    int cx0 = -1, nodes = 0;
+    auto flush = [&](int xend) {
+      if (cx0 >= 0 && xend > cx0) rc_chunks.push_back(make_int2(cx0, xend));
+      cx0 = -1;
+      nodes = 0;
+    };
+    size_t bi = 0;
+    for (int x = 0; x < ND; ++x) {
+      const int m = rc_ptr[x + 1] - rc_ptr[x];
+      if (bi < big_x.size() && big_x[bi] == x) {
+        flush(x);
+        ++bi;
+        continue;
+      }
+      if (cx0 >= 0 && (x - cx0 >= kRcBlock || nodes + m > kRcChunkNodes)) flush(x);
+      if (cx0 < 0) cx0 = x;
+      nodes += m;
+    }
+    flush(ND);
+  }
+  C->n_rc_chunks = (int)rc_chunks.size();
+
+  // packed library
+  const TabLayout lay{lib.nx, lib.ny};
+  const int ts = lay.stride();
+  std::vector<float> tab((size_t)lib.n_types * ts);
+  for (int t = 0; t < lib.n_types; ++t) {
+    float *o = tab.data() + (size_t)t * ts;
+    const float *xa = lib.slew_axis + t * lib.nx, *ya = lib.load_axis + t * lib.ny;
+    for (int i = 0; i < lib.nx; ++i) o[lay.xa() + i] = xa[i];
+    for (int j = 0; j < lib.ny; ++j) o[lay.ya() + j] = ya[j];
+    for (int i = 0; i + 1 < lib.nx; ++i) o[lay.rdx() + i] = 1.0f / (xa[i + 1] - xa[i]);
+    for (int j = 0; j + 1 < lib.ny; ++j) o[lay.rdy() + j] = 1.0f / (ya[j + 1] - ya[j]);
+    std::memcpy(o + lay.tab(0), lib.tables + (size_t)t * 4 * lib.nx * lib.ny, sizeof(float) * 4 * lib.nx * lib.ny);
+  }
+  std::vector<int32_t> sense(lib.sense, lib.sense + lib.n_types);
+
+  // upload
+  DevDesign &D = C->D;
+  D.n_drv = ND;
+  D.n_pi = NPI;
+  D.n_sinks = NS;
+  D.n_ep = C->n_ep;
+  D.n_cell_levels = L;
+  D.n_types = lib.n_types;
+  D.nx = lib.nx;
+  D.ny = lib.ny;
+  D.tstride = ts;
+  D.n_chunks = C->n_chunks;
+  int32_t *p32;
+  float *pf;
+  float4 *p4;
+  STA_TRY(C->upload(&p32, sink_ptr)); D.sink_ptr = p32;
+  STA_TRY(C->upload(&p32, rc_ptr)); D.rc_ptr = p32;
+  STA_TRY(C->upload(&p32, fanin_ptr)); D.fanin_ptr = p32;
+  STA_TRY(C->upload(&p32, fanin_sink)); D.fanin_sink = p32;
+  STA_TRY(C->upload(&p32, cell_type)); D.cell_type = p32;
+  STA_TRY(C->upload(&p32, drv_ep)); D.drv_ep = p32;
+  STA_TRY(C->upload(&p4, pi_at)); D.pi_at = p4;
+  STA_TRY(C->upload(&p4, pi_slew)); D.pi_slew = p4;
+  STA_TRY(C->upload(&p32, sink_drv)); D.sink_drv = p32;
+  STA_TRY(C->upload(&p32, sink_cons)); D.sink_cons = p32;
+  STA_TRY(C->upload(&p32, sink_node)); D.sink_node = p32;
+  STA_TRY(C->upload(&pf, sink_pincap)); D.sink_pincap = pf;
+  STA_TRY(C->upload(&p32, rc_parent)); D.rc_parent = p32;
+  STA_TRY(C->upload(&pf, rc_res)); D.rc_res = pf;
+  STA_TRY(C->upload(&C->rc_cap, rc_cap)); D.rc_cap = C->rc_cap;
+  STA_TRY(C->upload(&p4, ep_rat)); D.ep_rat = p4;
+  STA_TRY(C->upload(&pf, tab)); D.tables = pf;
+  STA_TRY(C->upload(&p32, sense)); D.sense = p32;
+  STA_TRY(C->upload(&p32, chunk_start)); D.chunk_start = p32;
+  STA_TRY(C->upload(&p32, chunk_level)); D.chunk_level = p32;
+  STA_TRY(C->upload(&p32, level_nchunks)); D.level_nchunks = p32;
+  STA_TRY(C->alloc(&D.L_net, ND));
+  STA_TRY(C->alloc(&D.dq, NS));
+  STA_TRY(C->alloc(&D.drv_state, ND));
+  STA_TRY(C->alloc(&D.sink_state, NS));
+  STA_TRY(C->alloc(&D.drv_crit, ND));
+  STA_TRY(C->alloc(&D.drv_rat, ND));
+  STA_TRY(C->alloc(&D.sink_rat, NS));
+  STA_TRY(C->alloc(&D.drv_slack, ND));
+  STA_TRY(C->alloc(&D.sink_slack, NS));
+  STA_TRY(C->alloc(&D.ep_slack, C->n_ep));
+  const int n_ctr = kCtrLevels + 2 * (L + 1);
+  STA_TRY(C->alloc(&D.counters, n_ctr));
+  HIP_TRY(hipMemset(D.counters, 0, n_ctr * sizeof(uint32_t)));
+
+  STA_TRY(C->upload(&C->pin_loc, pin_loc));
+  STA_TRY(C->upload(&C->net_slot, net_slot));
+  STA_TRY(C->upload(&C->sink_slot, sink_slot));
+  STA_TRY(C->upload(&C->node_src, node_src));
+  STA_TRY(C->upload(&C->ep_pin, ep_pin));
+  STA_TRY(C->upload(&C->rc_chunks, rc_chunks));
+  STA_TRY(C->upload(&C->big, big));
+  STA_TRY(C->upload(&C->big_end, big_end));
+  STA_TRY(C->upload(&C->big_pc, big_pc));
+  STA_TRY(C->alloc(&C->big_scratch, (size_t)std::max<int64_t>(big_scr, 1)));
+  STA_TRY(C->alloc(&C->partials, 4 * kReduceBlocks));
+  STA_TRY(C->alloc(&C->out, 4));
+  HIP_TRY(hipMemset(C->out, 0, 4 * sizeof(double)));
+  const int ne = std::max(C->n_ep, 1);
+  STA_TRY(C->alloc(&C->keys, 2 * (size_t)ne));
+  STA_TRY(C->alloc(&C->keys_out, 2 * (size_t)ne));
+  STA_TRY(C->alloc(&C->vals, ne));
+  STA_TRY(C->alloc(&C->order, 2 * (size_t)ne));
+  C->sort_bytes = sort_temp_bytes(ne);
+  unsigned char *st;
+  STA_TRY(C->alloc(&st, C->sort_bytes));
+  C->sort_temp = st;
+
+  // persistent grid: every resident block slot on the device
+  const size_t lds = sweep_lds_bytes(D);
+  if (lds > 160 * 1024) return fail(STA_E_UNSUPPORTED, "library too large for LDS (%zu bytes)", lds);
+  C->sweep_grid = sweep_blocks_per_cu(lds) * C->n_cu;
+  if (C->sweep_grid < 1) C->sweep_grid = 1;
+  return STA_OK;
+}
+
+extern "C" sta_status sta_create(const sta_graph_desc *graph, const sta_rc_desc *rc, const sta_lib_desc *lib,
+                                 const sta_constraints *cons, const sta_options *opts, sta_ctx **out) {
+  if (!graph || !rc || !lib || !cons || !out) return fail(STA_E_ARG, "NULL descriptor");
+  sta_options o;
+  sta_options_default(&o);
+  if (opts) o = *opts;
+  if (o.mode != 0) return fail(STA_E_UNSUPPORTED, "only mode 0 (hard max/min) is built");
+  if (o.sched != STA_SCHED_PERSISTENT && o.sched != STA_SCHED_PER_LEVEL) return fail(STA_E_ARG, "bad sched");
+  if (o.big_net_nodes < 0) return fail(STA_E_ARG, "big_net_nodes < 0");
+  if (o.dangling_policy != 0 && o.dangling_policy != 1) return fail(STA_E_ARG, "bad dangling_policy");
+  STA_TRY(validate_lib(*lib));
+  Inputs I;
+  I.g = graph;
+  I.rc = rc;
+  I.lib = lib;
+  I.cons = cons;
+  // device memory inputs need the device before validation
+  const bool dev_in = graph->mem == STA_DEVICE || rc->mem == STA_DEVICE;
+  auto C = std::make_unique<sta_ctx>();
+  C->opt = o;
+  auto init_device = [&]() -> sta_status {
+    int ndev = 0;
+    HIP_TRY(hipGetDeviceCount(&ndev));
+    if (ndev < 1) return fail(STA_E_DEVICE, "no HIP device");
+    if (o.device >= 0) {
+      if (o.device >= ndev) return fail(STA_E_ARG, "device %d of %d", o.device, ndev);
+      HIP_TRY(hipSetDevice(o.device));
+    }
+    HIP_TRY(hipGetDevice(&C->device));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, C->device));
+    C->n_cu = prop.multiProcessorCount;
+    return STA_OK;
+  };
+  if (dev_in) STA_TRY(init_device());
+  STA_TRY(load_graph(I));
+  STA_TRY(validate_graph(I));
+  STA_TRY(load_validate_rc(I));
+  STA_TRY(validate_cons(*cons, *graph));
+  if (!dev_in) STA_TRY(init_device());
+  C->n_pins = graph->n_pins;
+  C->n_cells = graph->n_cells;
+  C->n_nets = graph->n_nets;
+  C->n_pi = graph->n_pi;
+  C->n_po = graph->n_po;
+  std::vector<int32_t> cell_level;
+  STA_TRY(levelize(C.get(), I, cell_level));
+  STA_TRY(build_layout(C.get(), I, cell_level));
+  for (auto &e : C->ev) HIP_TRY(hipEventCreate(&e));
+  C->events = true;
+  HIP_TRY(hipDeviceSynchronize());
+  *out = C.release();
+  return STA_OK;
+}
+
+extern "C" void sta_destroy(sta_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  delete ctx;
+}
+
+extern "C" sta_status sta_set_wire_caps(sta_ctx *C, const float *cap_ff, sta_mem mem, void *stream) {
+  if (!C) return fail(STA_E_STATE, "NULL context");
+  if (!cap_ff) return fail(STA_E_ARG, "cap_ff is NULL");
+  HIP_TRY(hipSetDevice(C->device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (mem == STA_HOST) {
+    for (int64_t k = 0; k < C->n_nodes; ++k)
+      if (!finite(cap_ff[k]) || cap_ff[k] < 0.0f) return fail(STA_E_ARG, "cap_ff[%lld] invalid", (long long)k);
+    float *tmp;
+    sta_ctx scratch;
+    STA_TRY(scratch.alloc(&tmp, C->n_nodes));
+    HIP_TRY(hipMemcpyAsync(tmp, cap_ff, C->n_nodes * sizeof(float), hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_permute_caps(tmp, C->node_src, C->rc_cap, C->n_nodes, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  } else if (mem == STA_DEVICE) {
+    HIP_TRY(launch_permute_caps(cap_ff, C->node_src, C->rc_cap, C->n_nodes, s));
+  } else {
+    return fail(STA_E_ARG, "bad mem");
+  }
+  return STA_OK;
+}
+
+extern "C" sta_status sta_update_timing(sta_ctx *C, void *stream) {
+  if (!C) return fail(STA_E_STATE, "NULL context");
+  HIP_TRY(hipSetDevice(C->device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool prof = C->opt.profile != 0;
+  const DevDesign &D = C->D;
+  if (prof) HIP_TRY(hipEventRecord(C->ev[0], s));
+  HIP_TRY(launch_rc(D, C->rc_chunks, C->n_rc_chunks, C->big, C->n_big, C->big_end, C->big_pc, C->big_scratch, s));
+  if (prof) HIP_TRY(hipEventRecord(C->ev[1], s));
+  if (prof) HIP_TRY(hipEventRecord(C->ev[2], s));
+  if (C->opt.sched == STA_SCHED_PERSISTENT) {
+    HIP_TRY(launch_forward(D, C->sweep_grid, s));
+  } else {
+    for (int l = 0; l <= C->n_cell_levels; ++l)
+      HIP_TRY(launch_forward_level(D, C->level_chunk_begin[l], C->level_chunk_begin[l + 1], s));
+  }
+  if (prof) HIP_TRY(hipEventRecord(C->ev[3], s));
+  if (C->opt.sched == STA_SCHED_PERSISTENT) {
+    HIP_TRY(launch_backward(D, C->sweep_grid, s));
+  } else {
+    for (int l = C->n_cell_levels; l >= 0; --l)
+      HIP_TRY(launch_backward_level(D, C->level_chunk_begin[l], C->level_chunk_begin[l + 1], s));
+  }
+  if (prof) HIP_TRY(hipEventRecord(C->ev[4], s));
+  const bool sort = C->opt.sort_endpoints && C->n_ep > 0;
+  HIP_TRY(launch_reduce(D, C->partials, C->out, sort ? C->keys : nullptr, sort ? C->vals : nullptr, s));
+  if (prof) HIP_TRY(hipEventRecord(C->ev[5], s));
+  if (sort) {
+    for (int el = 0; el < 2; ++el)
+      HIP_TRY(sort_endpoints(C->sort_temp, C->sort_bytes, C->keys + (size_t)el * C->n_ep,
+                             C->keys_out + (size_t)el * C->n_ep, C->vals, C->order + (size_t)el * C->n_ep,
+                             C->n_ep, s));
+  }
+  if (prof) HIP_TRY(hipEventRecord(C->ev[6], s));
+  C->timed = prof;
+  C->last_stream = s;
+  return STA_OK;
+}
+
+extern "C" sta_status sta_get_phase_times(sta_ctx *C, float *ms, int32_t *n) {
+  if (!C || !ms || !n) return fail(STA_E_ARG, "NULL argument");
+  if (!C->timed) return fail(STA_E_STATE, "no profiled update (set options.profile = 1)");
+  HIP_TRY(hipSetDevice(C->device));
+  HIP_TRY(hipEventSynchronize(C->ev[6]));
+  for (int i = 0; i < 6; ++i) HIP_TRY(hipEventElapsedTime(&ms[i], C->ev[i], C->ev[i + 1]));
+  *n = 6;
+  return STA_OK;
+}
+
+// Copies n bytes of device data to dst (host or device).
+static sta_status deliver(void *dst, const void *src, size_t bytes, sta_mem m, hipStream_t s) {
+  if (!dst || bytes == 0) return STA_OK;
+  HIP_TRY(hipMemcpyAsync(dst, src, bytes, m == STA_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, s));
+  return STA_OK;
+}
+
+extern "C" sta_status sta_report_timing(sta_ctx *C, float *at, float *slew, float *rat, int8_t *crit,
+                                        sta_mem dst, void *stream) {
+  if (!C) return fail(STA_E_STATE, "NULL context");
+  if (dst != STA_HOST && dst != STA_DEVICE) return fail(STA_E_ARG, "bad dst");
+  HIP_TRY(hipSetDevice(C->device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t n4 = (size_t)C->n_pins * sizeof(float4);
+  if (dst == STA_DEVICE) {
+    HIP_TRY(launch_report_pins(C->D, C->pin_loc, C->n_pins, reinterpret_cast<float4 *>(at),
+                               reinterpret_cast<float4 *>(slew), reinterpret_cast<float4 *>(rat),
+                               reinterpret_cast<uint32_t *>(crit), nullptr, s));
+    return STA_OK;
+  }
+  sta_ctx tmp;
+  float4 *a = nullptr, *sl = nullptr, *r = nullptr;
+  uint32_t *cr = nullptr;
+  if (at) STA_TRY(tmp.alloc(&a, C->n_pins));
+  if (slew) STA_TRY(tmp.alloc(&sl, C->n_pins));
+  if (rat) STA_TRY(tmp.alloc(&r, C->n_pins));
+  if (crit) STA_TRY(tmp.alloc(&cr, C->n_pins));
+  HIP_TRY(launch_report_pins(C->D, C->pin_loc, C->n_pins, a, sl, r, cr, nullptr, s));
+  STA_TRY(deliver(at, a, n4, STA_HOST, s));
+  STA_TRY(deliver(slew, sl, n4, STA_HOST, s));
+  STA_TRY(deliver(rat, r, n4, STA_HOST, s));
+  STA_TRY(deliver(crit, cr, (size_t)C->n_pins * 4, STA_HOST, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return STA_OK;
+}
+
+extern "C" sta_status sta_report_slack(sta_ctx *C, float *pin_slack, float *ep_slack, int32_t *ep_order,
+                                       double *wns, double *tns, sta_mem dst, void *stream) {
+  if (!C) return fail(STA_E_STATE, "NULL context");
+  if (dst != STA_HOST && dst != STA_DEVICE) return fail(STA_E_ARG, "bad dst");
+  if (ep_order && !C->opt.sort_endpoints) return fail(STA_E_STATE, "endpoint sorting is disabled");
+  HIP_TRY(hipSetDevice(C->device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  sta_ctx tmp;
+  if (pin_slack) {
+    float4 *ps = reinterpret_cast<float4 *>(pin_slack);
+    if (dst == STA_HOST) STA_TRY(tmp.alloc(&ps, C->n_pins));
+    HIP_TRY(launch_report_pins(C->D, C->pin_loc, C->n_pins, nullptr, nullptr, nullptr, nullptr, ps, s));
+    if (dst == STA_HOST) STA_TRY(deliver(pin_slack, ps, (size_t)C->n_pins * sizeof(float4), STA_HOST, s));
+  }
+  STA_TRY(deliver(ep_slack, C->D.ep_slack, (size_t)C->n_ep * sizeof(float2), dst, s));
+  STA_TRY(deliver(ep_order, C->order, (size_t)C->n_ep * 2 * sizeof(int32_t), dst, s));
+  double h[4] = {0, 0, 0, 0};
+  if (wns || tns) HIP_TRY(hipMemcpyAsync(h, C->out, sizeof h, hipMemcpyDeviceToHost, s));
+  if (dst == STA_HOST || wns || tns) HIP_TRY(hipStreamSynchronize(s));
+  if (wns) { wns[0] = h[0]; wns[1] = h[1]; }
+  if (tns) { tns[0] = h[2]; tns[1] = h[3]; }
+  return STA_OK;
+}
+
+extern "C" sta_status sta_report_levels(sta_ctx *C, int32_t *pin_level, int32_t *level_order, sta_mem dst,
+                                        void *stream) {
+  if (!C) return fail(STA_E_STATE, "NULL context");
+  HIP_TRY(hipSetDevice(C->device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  STA_TRY(deliver(pin_level, C->pin_level, (size_t)C->n_pins * 4, dst, s));
+  STA_TRY(deliver(level_order, C->level_order, (size_t)C->n_pins * 4, dst, s));
+  if (dst == STA_HOST) HIP_TRY(hipStreamSynchronize(s));
+  return STA_OK;
+}
+
+extern "C" sta_status sta_report_rc(sta_ctx *C, float *net_load, float *sink_delay, float *sink_spread,
+                                    sta_mem dst, void *stream) {
+  if (!C) return fail(STA_E_STATE, "NULL context");
+  HIP_TRY(hipSetDevice(C->device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (dst == STA_DEVICE) {
+    HIP_TRY(launch_report_rc(C->D, C->net_slot, C->n_nets, C->sink_slot, C->n_sinks, net_load, sink_delay,
+                             sink_spread, s));
+    return STA_OK;
+  }
+  sta_ctx tmp;
+  float *l = nullptr, *d = nullptr, *q = nullptr;
+  if (net_load) STA_TRY(tmp.alloc(&l, C->n_nets));
+  if (sink_delay) STA_TRY(tmp.alloc(&d, C->n_sinks));
+  if (sink_spread) STA_TRY(tmp.alloc(&q, C->n_sinks));
+  HIP_TRY(launch_report_rc(C->D, C->net_slot, C->n_nets, C->sink_slot, C->n_sinks, l, d, q, s));
+  STA_TRY(deliver(net_load, l, (size_t)C->n_nets * 4, STA_HOST, s));
+  STA_TRY(deliver(sink_delay, d, (size_t)C->n_sinks * 4, STA_HOST, s));
+  STA_TRY(deliver(sink_spread, q, (size_t)C->n_sinks * 4, STA_HOST, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return STA_OK;
+}
+
+extern "C" sta_status sta_report_endpoints(sta_ctx *C, int32_t *ep_pin, sta_mem dst, void *stream) {
+  if (!C) return fail(STA_E_STATE, "NULL context");
+  HIP_TRY(hipSetDevice(C->device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  STA_TRY(deliver(ep_pin, C->ep_pin, (size_t)C->n_ep * 4, dst, s));
+  if (dst == STA_HOST) HIP_TRY(hipStreamSynchronize(s));
+  return STA_OK;
+}
+
+extern "C" sta_status sta_get_info(const sta_ctx *C, sta_info *info) {
+  if (!C || !info) return fail(STA_E_ARG, "NULL argument");
+  info->n_pins = C->n_pins;
+  info->n_cells = C->n_cells;
+  info->n_nets = C->n_nets;
+  info->n_pi = C->n_pi;
+  info->n_po = C->n_po;
+  info->n_sinks = C->n_sinks;
+  info->n_nodes = C->n_nodes;
+  info->n_levels = C->n_levels;
+  info->n_cell_levels = C->n_cell_levels;
+  info->n_endpoints = C->n_ep;
+  info->n_big_nets = C->n_big;
+  info->n_chunks = C->n_chunks;
+  info->device = C->device;
+  return STA_OK;
+}

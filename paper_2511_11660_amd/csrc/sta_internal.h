@@ -1,0 +1,155 @@
+// Device layout shared by the host runtime (sta_host.cpp) and the kernels
+// (sta_kernels.hip).  Everything is level-sorted once at create time:
+//
+//   driver slots  [0, n_drv): the PIs (ascending pin id), then the cells in
+//                 ascending (cell level, output pin id).  Slot x drives net x.
+//                 Level l occupies [lvl_ptr[l], lvl_ptr[l+1]); level 0 = PIs.
+//   sink slots    [0, n_sinks): net-major, sinks of net x in
+//                 [sink_ptr[x], sink_ptr[x+1]) in the caller's sink order.
+//   RC nodes      net-major in driver-slot order; node order inside a net is
+//                 the caller's (small nets) or DFS preorder (big nets).
+//
+// Pin state is an AoS record of the four views: at[4] then slew[4] (32 B), so a
+// fanin gather is one 32-byte access.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace sta {
+
+constexpr int kWave = 64;
+constexpr int kMaxTypes = 64;
+constexpr int kMaxAxis = 8;
+constexpr int kSweepBlock = 256;            // 4 waves, each wave owns one chunk at a time
+constexpr int kChunk = kWave;               // driver slots per sweep chunk
+constexpr int kRcBlock = 256;               // one small net per thread
+constexpr int kRcChunkNodes = 2048;         // RC nodes staged in LDS per block
+constexpr int kSmallNetMaxNodes = 255;      // parents fit in a byte
+constexpr int kReduceBlocks = 128;
+
+struct alignas(32) PinState {
+  float4 at;
+  float4 slew;
+};
+
+// counters[] layout
+constexpr int kCtrFwdTicket = 0;
+constexpr int kCtrBwdTicket = 1;
+constexpr int kCtrReduce = 2;
+constexpr int kCtrLevels = 4;  // fwd_done[L+1] then bwd_done[L+1]
+
+struct DevDesign {
+  int32_t n_drv, n_pi, n_sinks, n_ep, n_cell_levels;
+  int32_t n_types, nx, ny, tstride;
+  int32_t n_chunks;
+
+  // driver slots
+  const int32_t *sink_ptr;    // [n_drv+1]
+  const int32_t *rc_ptr;      // [n_drv+1]
+  const int32_t *fanin_ptr;   // [n_drv+1] (empty for PIs)
+  const int32_t *fanin_sink;  // sink slot of each cell input, fanin order
+  const int32_t *cell_type;   // [n_drv] (-1 for PIs)
+  const int32_t *drv_ep;      // [n_drv] endpoint index of a dangling endpoint, else -1
+  const float4 *pi_at;        // [n_pi]
+  const float4 *pi_slew;      // [n_pi]
+
+  // sink slots
+  const int32_t *sink_drv;    // [n_sinks] driver slot
+  const int32_t *sink_cons;   // [n_sinks] consumer driver slot, or -1 - endpoint
+  const int32_t *sink_node;   // [n_sinks] net-local RC node
+  const float *sink_pincap;   // [n_sinks]
+
+  // RC nodes
+  const int32_t *rc_parent;   // net-local, -1 at the root
+  const float *rc_res;
+  const float *rc_cap;
+
+  // endpoints
+  const float4 *ep_rat;       // [n_ep]
+
+  // library, packed per type: xa[nx] ya[ny] rdx[nx-1] rdy[ny-1] T[4][nx][ny]
+  const float *tables;
+  const int32_t *sense;
+
+  // state written by the update
+  float *L_net;               // [n_drv]
+  float2 *dq;                 // [n_sinks] (Elmore delay, spread)
+  PinState *drv_state;        // [n_drv]
+  PinState *sink_state;       // [n_sinks]
+  uint32_t *drv_crit;         // [n_drv] four int8 critical-fanin codes
+  float4 *drv_rat, *sink_rat;
+  float4 *drv_slack, *sink_slack;
+  float2 *ep_slack;           // [n_ep] (early, late)
+
+  // sweep schedule
+  const int32_t *chunk_start;   // [n_chunks+1] driver-slot ranges
+  const int32_t *chunk_level;   // [n_chunks]
+  const int32_t *level_nchunks; // [n_cell_levels+1]
+  uint32_t *counters;
+};
+
+// A wide RC net (more nodes than one lane handles), nodes in DFS preorder.
+struct BigNet {
+  int32_t x, m;       // driver slot, node count
+  int64_t aux;        // offset into big_end / big_pc (one entry per node)
+  int64_t scr;        // offset into the FP64 scratch (4 * (m + 1) doubles)
+};
+
+// Packed-table offsets for one type.
+struct TabLayout {
+  int nx, ny;
+  __host__ __device__ int xa() const { return 0; }
+  __host__ __device__ int ya() const { return nx; }
+  __host__ __device__ int rdx() const { return nx + ny; }
+  __host__ __device__ int rdy() const { return nx + ny + nx - 1; }
+  __host__ __device__ int tab(int k) const { return 2 * nx + 2 * ny - 2 + k * nx * ny; }
+  __host__ __device__ int stride() const { return 2 * nx + 2 * ny - 2 + 4 * nx * ny; }
+};
+
+// Launch wrappers (sta_kernels.hip).  All return hipError_t of the launch.
+hipError_t launch_rc(const DevDesign &D, const int2 *chunks, int n_chunks, const BigNet *big, int n_big,
+                     const int32_t *big_end, const float *big_pc, double *scratch, hipStream_t s);
+hipError_t launch_forward(const DevDesign &D, int persistent_grid, hipStream_t s);
+hipError_t launch_forward_level(const DevDesign &D, int c0, int c1, hipStream_t s);
+hipError_t launch_backward(const DevDesign &D, int persistent_grid, hipStream_t s);
+hipError_t launch_backward_level(const DevDesign &D, int c0, int c1, hipStream_t s);
+hipError_t launch_reset_counters(uint32_t *counters, int n, hipStream_t s);
+hipError_t launch_reduce(const DevDesign &D, double *partials, double *out, uint32_t *keys,
+                         int32_t *vals, hipStream_t s);
+hipError_t sort_endpoints(void *temp, size_t temp_bytes, const uint32_t *keys_in,
+                          uint32_t *keys_out, const int32_t *vals_in, int32_t *vals_out, int n,
+                          hipStream_t s);
+size_t sort_temp_bytes(int n);
+int sweep_blocks_per_cu(size_t lds_bytes);
+size_t sweep_lds_bytes(const DevDesign &D);
+
+// levelization
+hipError_t launch_level_init(int32_t *pending, int32_t *cell_level, const int32_t *cell_nin,
+                             int n_cells, hipStream_t s);
+hipError_t launch_level_step(const int32_t *frontier, int n_front, int lvl,
+                             const int32_t *net_of_drv_pin, const int32_t *net_sink_ptr,
+                             const int32_t *net_sink_pin, const int32_t *cell_of_in_pin,
+                             const int32_t *cell_out_pin, int32_t *pending, int32_t *cell_level,
+                             int32_t *next, uint32_t *next_count, hipStream_t s);
+hipError_t launch_pin_levels(const int32_t *pin_kind, const int32_t *cell_of_pin,
+                             const int32_t *cell_level, const int32_t *drv_of_sink_pin,
+                             int32_t *pin_level, int n_pins, hipStream_t s);
+hipError_t sort_levels(void *temp, size_t temp_bytes, const int32_t *keys_in, int32_t *keys_out,
+                       const int32_t *vals_in, int32_t *vals_out, int n, int key_bits,
+                       hipStream_t s);
+size_t level_sort_temp_bytes(int n);
+hipError_t launch_iota(int32_t *a, int n, hipStream_t s);
+
+// reports and inputs
+hipError_t launch_report_pins(const DevDesign &D, const int32_t *pin_loc, int n_pins, float4 *at,
+                              float4 *slew, float4 *rat, uint32_t *crit, float4 *slack,
+                              hipStream_t s);
+hipError_t launch_report_rc(const DevDesign &D, const int32_t *net_slot, int n_nets,
+                            const int32_t *sink_slot, int n_sinks, float *net_load,
+                            float *sink_delay, float *sink_spread, hipStream_t s);
+hipError_t launch_permute_caps(const float *src, const int32_t *node_src, float *dst, int64_t n,
+                               hipStream_t s);
+
+}  // namespace sta

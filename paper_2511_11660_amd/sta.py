@@ -1,0 +1,320 @@
+"""ctypes binding of ``libsta.so`` (declared in ``include/sta.h``).
+
+The module-level functions carry the C names and only marshal arguments:
+every step of the timing path runs in the library's HIP kernels.  Host
+arrays are numpy; device arrays are anything exposing ``data_ptr()`` (torch
+tensors on ``cuda``), and streams are raw HIP stream handles (an int) or a
+torch stream.  ``STA`` is a small owner of one context built from a
+``synth.Design``-shaped object.
+
+There is no CPU fallback: if ``libsta.so`` is missing or fails to load, every
+entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsta.so")
+
+STA_OK, STA_E_ARG, STA_E_CYCLE, STA_E_OOM, STA_E_DEVICE, STA_E_STATE, STA_E_UNSUPPORTED = range(7)
+STA_HOST, STA_DEVICE = 0, 1
+STA_SCHED_PERSISTENT, STA_SCHED_PER_LEVEL = 0, 1
+
+_P32 = ctypes.POINTER(ctypes.c_int32)
+_P64 = ctypes.POINTER(ctypes.c_int64)
+_PF = ctypes.POINTER(ctypes.c_float)
+_PD = ctypes.POINTER(ctypes.c_double)
+_VP = ctypes.c_void_p
+
+
+class sta_graph_desc(ctypes.Structure):
+    _fields_ = [("n_pins", ctypes.c_int32), ("n_cells", ctypes.c_int32), ("n_nets", ctypes.c_int32),
+                ("n_pi", ctypes.c_int32), ("n_po", ctypes.c_int32),
+                ("pin_kind", _VP), ("cell_type", _VP), ("cell_in_ptr", _VP), ("cell_in_pin", _VP),
+                ("cell_out_pin", _VP), ("net_driver", _VP), ("net_sink_ptr", _VP),
+                ("net_sink_pin", _VP), ("mem", ctypes.c_int)]
+
+
+class sta_rc_desc(ctypes.Structure):
+    _fields_ = [("n_nodes", ctypes.c_int64), ("net_node_ptr", _VP), ("parent", _VP),
+                ("res_kohm", _VP), ("cap_ff", _VP), ("sink_node", _VP), ("mem", ctypes.c_int)]
+
+
+class sta_lib_desc(ctypes.Structure):
+    _fields_ = [("n_types", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("n_inputs", _VP), ("sense", _VP), ("pin_cap_ff", _VP), ("slew_axis", _VP),
+                ("load_axis", _VP), ("tables", _VP), ("po_cap_ff", ctypes.c_float)]
+
+
+class sta_constraints(ctypes.Structure):
+    _fields_ = [("pi_at", _VP), ("pi_slew", _VP), ("po_rat", _VP),
+                ("dangling_rat", ctypes.c_float * 4)]
+
+
+class sta_options(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("gamma_ps", ctypes.c_float),
+                ("dangling_policy", ctypes.c_int32), ("sched", ctypes.c_int32),
+                ("big_net_nodes", ctypes.c_int32), ("sort_endpoints", ctypes.c_int32),
+                ("profile", ctypes.c_int32), ("device", ctypes.c_int32)]
+
+
+class sta_info(ctypes.Structure):
+    _fields_ = [("n_pins", ctypes.c_int32), ("n_cells", ctypes.c_int32), ("n_nets", ctypes.c_int32),
+                ("n_pi", ctypes.c_int32), ("n_po", ctypes.c_int32), ("n_sinks", ctypes.c_int32),
+                ("n_nodes", ctypes.c_int64), ("n_levels", ctypes.c_int32),
+                ("n_cell_levels", ctypes.c_int32), ("n_endpoints", ctypes.c_int32),
+                ("n_big_nets", ctypes.c_int32), ("n_chunks", ctypes.c_int32),
+                ("device", ctypes.c_int32)]
+
+
+# (name, restype, argtypes) of every exported function
+_SIGS = [
+    ("sta_options_default", None, [ctypes.POINTER(sta_options)]),
+    ("sta_create", ctypes.c_int, [ctypes.POINTER(sta_graph_desc), ctypes.POINTER(sta_rc_desc),
+                                  ctypes.POINTER(sta_lib_desc), ctypes.POINTER(sta_constraints),
+                                  ctypes.POINTER(sta_options), ctypes.POINTER(_VP)]),
+    ("sta_destroy", None, [_VP]),
+    ("sta_set_wire_caps", ctypes.c_int, [_VP, _VP, ctypes.c_int, _VP]),
+    ("sta_update_timing", ctypes.c_int, [_VP, _VP]),
+    ("sta_report_slack", ctypes.c_int, [_VP, _VP, _VP, _VP, _PD, _PD, ctypes.c_int, _VP]),
+    ("sta_report_timing", ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, ctypes.c_int, _VP]),
+    ("sta_report_levels", ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int, _VP]),
+    ("sta_report_rc", ctypes.c_int, [_VP, _VP, _VP, _VP, ctypes.c_int, _VP]),
+    ("sta_report_endpoints", ctypes.c_int, [_VP, _VP, ctypes.c_int, _VP]),
+    ("sta_get_info", ctypes.c_int, [_VP, ctypes.POINTER(sta_info)]),
+    ("sta_get_phase_times", ctypes.c_int, [_VP, _PF, _P32]),
+    ("sta_status_string", ctypes.c_char_p, [ctypes.c_int]),
+    ("sta_last_error", ctypes.c_char_p, []),
+]
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Loads libsta.so (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, res, args in _SIGS:
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = lib
+    return _lib
+
+
+class StaError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        self.status = status
+        super().__init__(f"{sta_status_string(status)}: {msg}")
+
+
+def sta_status_string(s: int) -> str:
+    return load().sta_status_string(s).decode()
+
+
+def sta_last_error() -> str:
+    return load().sta_last_error().decode()
+
+
+def _check(status: int) -> None:
+    if status != STA_OK:
+        raise StaError(status, sta_last_error())
+
+
+def _addr(a) -> int | None:
+    """Address of a numpy array / torch tensor / int, or None."""
+    if a is None:
+        return None
+    if isinstance(a, int):
+        return a
+    if hasattr(a, "data_ptr"):
+        return a.data_ptr()
+    if isinstance(a, np.ndarray):
+        if not a.flags["C_CONTIGUOUS"]:
+            raise ValueError("array must be C-contiguous")
+        return a.ctypes.data
+    raise TypeError(f"cannot take the address of {type(a)}")
+
+
+def _stream(s) -> int | None:
+    if s is None:
+        return None
+    if isinstance(s, int):
+        return s
+    return s.cuda_stream  # torch.cuda.Stream
+
+
+def sta_options_default() -> sta_options:
+    o = sta_options()
+    load().sta_options_default(ctypes.byref(o))
+    return o
+
+
+def sta_create(graph: sta_graph_desc, rc: sta_rc_desc, lib: sta_lib_desc, cons: sta_constraints,
+               opts: sta_options | None = None) -> int:
+    ctx = _VP()
+    _check(load().sta_create(ctypes.byref(graph), ctypes.byref(rc), ctypes.byref(lib),
+                             ctypes.byref(cons), ctypes.byref(opts) if opts is not None else None,
+                             ctypes.byref(ctx)))
+    return ctx.value
+
+
+def sta_destroy(ctx: int) -> None:
+    load().sta_destroy(ctx)
+
+
+def sta_set_wire_caps(ctx: int, cap_ff, mem: int, stream=None) -> None:
+    _check(load().sta_set_wire_caps(ctx, _addr(cap_ff), mem, _stream(stream)))
+
+
+def sta_update_timing(ctx: int, stream=None) -> None:
+    _check(load().sta_update_timing(ctx, _stream(stream)))
+
+
+def sta_report_slack(ctx: int, pin_slack=None, ep_slack=None, ep_order=None, dst: int = STA_HOST,
+                     stream=None):
+    wns = (ctypes.c_double * 2)()
+    tns = (ctypes.c_double * 2)()
+    _check(load().sta_report_slack(ctx, _addr(pin_slack), _addr(ep_slack), _addr(ep_order),
+                                   ctypes.cast(wns, _PD), ctypes.cast(tns, _PD), dst, _stream(stream)))
+    return np.array(list(wns)), np.array(list(tns))
+
+
+def sta_report_timing(ctx: int, at=None, slew=None, rat=None, crit=None, dst: int = STA_HOST,
+                      stream=None) -> None:
+    _check(load().sta_report_timing(ctx, _addr(at), _addr(slew), _addr(rat), _addr(crit), dst,
+                                    _stream(stream)))
+
+
+def sta_report_levels(ctx: int, pin_level=None, level_order=None, dst: int = STA_HOST,
+                      stream=None) -> None:
+    _check(load().sta_report_levels(ctx, _addr(pin_level), _addr(level_order), dst, _stream(stream)))
+
+
+def sta_report_rc(ctx: int, net_load=None, sink_delay=None, sink_spread=None, dst: int = STA_HOST,
+                  stream=None) -> None:
+    _check(load().sta_report_rc(ctx, _addr(net_load), _addr(sink_delay), _addr(sink_spread), dst,
+                                _stream(stream)))
+
+
+def sta_report_endpoints(ctx: int, ep_pin=None, dst: int = STA_HOST, stream=None) -> None:
+    _check(load().sta_report_endpoints(ctx, _addr(ep_pin), dst, _stream(stream)))
+
+
+def sta_get_info(ctx: int) -> sta_info:
+    info = sta_info()
+    _check(load().sta_get_info(ctx, ctypes.byref(info)))
+    return info
+
+
+def sta_get_phase_times(ctx: int) -> np.ndarray:
+    ms = (ctypes.c_float * 8)()
+    n = ctypes.c_int32(0)
+    _check(load().sta_get_phase_times(ctx, ctypes.cast(ms, _PF), ctypes.byref(n)))
+    return np.array(list(ms)[: n.value], dtype=np.float64)
+
+
+PHASES = ("rc_small", "rc_big", "forward", "backward", "reduce", "sort")
+
+
+# ------------------------------------------------------------------ owner
+
+def descriptors(d, keep: list):
+    """Host-memory descriptors for a synth.Design-shaped object.  Arrays that
+    the descriptors point to are appended to `keep` (the caller holds them)."""
+
+    def a(x, dt):
+        x = np.ascontiguousarray(x, dtype=dt)
+        keep.append(x)
+        return x.ctypes.data
+
+    g = sta_graph_desc(d.n_pins, d.n_cells, d.n_nets, d.n_pi, d.n_po,
+                       a(d.pin_kind, np.int32), a(d.cell_type, np.int32), a(d.cell_in_ptr, np.int32),
+                       a(d.cell_in_pin, np.int32), a(d.cell_out_pin, np.int32),
+                       a(d.net_driver, np.int32), a(d.net_sink_ptr, np.int32),
+                       a(d.net_sink_pin, np.int32), STA_HOST)
+    rc = sta_rc_desc(int(d.n_nodes), a(d.net_node_ptr, np.int64), a(d.parent, np.int32),
+                     a(d.res_kohm, np.float32), a(d.cap_ff, np.float32), a(d.sink_node, np.int32),
+                     STA_HOST)
+    lib = sta_lib_desc(d.n_types, d.nx, d.ny, a(d.n_inputs, np.int32), a(d.sense, np.int32),
+                       a(d.pin_cap_ff, np.float32), a(d.slew_axis, np.float32),
+                       a(d.load_axis, np.float32), a(d.tables, np.float32), float(d.po_cap_ff))
+    cons = sta_constraints(a(d.pi_at, np.float32), a(d.pi_slew, np.float32), a(d.po_rat, np.float32),
+                           (ctypes.c_float * 4)(*[float(v) for v in d.dangling_rat]))
+    return g, rc, lib, cons
+
+
+class STA:
+    """One timing context on the current HIP device."""
+
+    def __init__(self, design, **opts):
+        o = sta_options_default()
+        o.dangling_policy = int(design.dangling_policy)
+        for k, v in opts.items():
+            setattr(o, k, v)
+        keep: list = []
+        g, rc, lib, cons = descriptors(design, keep)
+        self.ctx = sta_create(g, rc, lib, cons, o)
+        self.info = sta_get_info(self.ctx)
+        self.opts = o
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            sta_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def update(self, stream=None):
+        sta_update_timing(self.ctx, stream)
+
+    def set_wire_caps(self, cap, stream=None):
+        mem = STA_DEVICE if hasattr(cap, "data_ptr") else STA_HOST
+        sta_set_wire_caps(self.ctx, cap, mem, stream)
+
+    def timing(self):
+        n = self.info.n_pins
+        at, slew, rat = (np.zeros((n, 4), np.float32) for _ in range(3))
+        crit = np.zeros((n, 4), np.int8)
+        sta_report_timing(self.ctx, at, slew, rat, crit)
+        return {"at": at, "slew": slew, "rat": rat, "crit": crit}
+
+    def slack(self):
+        n, ne = self.info.n_pins, self.info.n_endpoints
+        ps = np.zeros((n, 4), np.float32)
+        es = np.zeros((max(ne, 1), 2), np.float32)
+        eo = np.zeros((2, max(ne, 1)), np.int32)
+        wns, tns = sta_report_slack(self.ctx, ps, es, eo if self.opts.sort_endpoints else None)
+        return {"slack": ps, "ep_slack": es[:ne], "ep_order": eo[:, :ne], "wns": wns, "tns": tns}
+
+    def levels(self):
+        n = self.info.n_pins
+        lv, lo = np.zeros(n, np.int32), np.zeros(n, np.int32)
+        sta_report_levels(self.ctx, lv, lo)
+        return lv, lo
+
+    def rc(self):
+        L = np.zeros(self.info.n_nets, np.float32)
+        d = np.zeros(max(1, self.info.n_sinks), np.float32)
+        q = np.zeros(max(1, self.info.n_sinks), np.float32)
+        sta_report_rc(self.ctx, L, d, q)
+        return L, d[: self.info.n_sinks], q[: self.info.n_sinks]
+
+    def endpoints(self):
+        e = np.zeros(max(1, self.info.n_endpoints), np.int32)
+        sta_report_endpoints(self.ctx, e)
+        return e[: self.info.n_endpoints]
+
+    def phase_times(self):
+        return sta_get_phase_times(self.ctx)

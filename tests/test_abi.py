@@ -1,0 +1,144 @@
+"""C ABI checks that need no GPU: the library loads, exports every function
+include/sta.h declares, and rejects malformed inputs during host validation
+(before any device call) with the documented status codes."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from designs import CIN, COUT, PI, PO, make_design, planar_table, single_segment_net
+from paper_2511_11660_amd import sta as S
+from paper_2511_11660_amd import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _has_gpu():
+    try:
+        import torch
+        return torch.cuda.device_count() > 0
+    except Exception:
+        return False
+
+
+def test_exports_every_declared_function():
+    hdr = open(os.path.join(ROOT, "include", "sta.h")).read()
+    declared = set(re.findall(r"\b(sta_[a-z_]+)\s*\(", hdr))
+    assert "sta_create" in declared and "sta_update_timing" in declared
+    lib = ctypes.CDLL(S.LIB_PATH)
+    missing = [f for f in sorted(declared) if not hasattr(lib, f)]
+    assert not missing, missing
+    bound = {name for name, _, _ in S._SIGS}
+    assert declared <= bound, declared - bound
+
+
+def test_status_strings_and_defaults():
+    assert S.sta_status_string(S.STA_E_CYCLE) == "STA_E_CYCLE"
+    o = S.sta_options_default()
+    assert o.mode == 0 and o.sort_endpoints == 1 and o.device == -1 and o.gamma_ps == 5.0
+
+
+def _tiny():
+    return synth.generate(synth.tiny_config())
+
+
+def _create(d, **opts):
+    keep = []
+    g, rc, lib, cons = S.descriptors(d, keep)
+    o = S.sta_options_default()
+    for k, v in opts.items():
+        setattr(o, k, v)
+    return S.sta_create(g, rc, lib, cons, o)
+
+
+def _expect(d, status, **opts):
+    with pytest.raises(S.StaError) as e:
+        _create(d, **opts)
+    assert e.value.status == status, str(e.value)
+    return str(e.value)
+
+
+def test_rejects_bad_pin_kind():
+    d = _tiny()
+    d.pin_kind[5] = 7
+    assert "kind" in _expect(d, S.STA_E_ARG)
+
+
+def test_rejects_parent_not_less_than_child():
+    d = _tiny()
+    k = int(d.net_node_ptr[3]) + 2
+    d.parent[k] = 5
+    assert "parent" in _expect(d, S.STA_E_ARG)
+
+
+def test_rejects_sink_node_outside_net():
+    d = _tiny()
+    d.sink_node[0] = 10_000
+    _expect(d, S.STA_E_ARG)
+
+
+def test_rejects_nan_and_negative_caps():
+    d = _tiny()
+    d.cap_ff[17] = np.nan
+    _expect(d, S.STA_E_ARG)
+    d = _tiny()
+    d.res_kohm[17] = -1.0
+    _expect(d, S.STA_E_ARG)
+
+
+def test_rejects_non_increasing_axis():
+    d = _tiny()
+    d.slew_axis[2, 3] = d.slew_axis[2, 2]
+    assert "axis" in _expect(d, S.STA_E_ARG)
+
+
+def test_rejects_pin_on_two_nets():
+    d = _tiny()
+    d.net_sink_pin[1] = d.net_sink_pin[0]
+    _expect(d, S.STA_E_ARG)
+
+
+def test_rejects_wrong_input_count_for_type():
+    d = _tiny()
+    d.n_inputs[:] = 3
+    assert "inputs" in _expect(d, S.STA_E_ARG)
+
+
+def test_rejects_unsupported_mode_and_sizes():
+    d = _tiny()
+    _expect(d, S.STA_E_UNSUPPORTED, mode=1)
+    _expect(d, S.STA_E_ARG, sched=7)
+    d2 = _tiny()
+    d2.nx = 9
+    _expect(d2, S.STA_E_UNSUPPORTED)
+
+
+def test_rejects_nan_constraint():
+    d = _tiny()
+    d.po_rat[0, 2] = np.inf
+    _expect(d, S.STA_E_ARG)
+
+
+def test_rejects_cell_without_inputs():
+    kinds = [PI, COUT, CIN, COUT]
+    cells = [(0, [], 1), (0, [2], 3)]
+    nets = [single_segment_net(0, [2], 0.01, 1.0), single_segment_net(1, [], 0, 0),
+            single_segment_net(3, [], 0, 0)]
+    t = np.stack([np.stack([planar_table(5, 0.1, 1.0)] * 4)])
+    d = make_design(kinds, cells, nets, n_inputs=[1], sense=[0], pin_cap=[1.0], tables=t)
+    _expect(d, S.STA_E_ARG)
+
+
+@pytest.mark.skipif(_has_gpu(), reason="checks the no-device error path")
+def test_valid_design_without_device_reports_device_error():
+    d = _tiny()
+    msg = _expect(d, S.STA_E_DEVICE)
+    assert msg
+
+
+def test_null_context_calls_are_state_errors():
+    with pytest.raises(S.StaError) as e:
+        S.sta_update_timing(0)
+    assert e.value.status == S.STA_E_STATE

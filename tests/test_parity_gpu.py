@@ -1,0 +1,147 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle, element
+by element, on seeded synthetic designs (tiny, mid-size, 1M pins) and on the
+10M-pin design the benchmark times, plus hand-built and edge-case designs."""
+import numpy as np
+import pytest
+
+import oracle
+from designs import CIN, COUT, PI, PO, make_design, planar_table, single_segment_net
+from paper_2511_11660_amd import synth
+from paper_2511_11660_amd.sta import STA, STA_SCHED_PER_LEVEL, STA_SCHED_PERSISTENT
+from parity import compare_full, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(d, **opts):
+    print(f"[parity] design pins={d.n_pins} cells={d.n_cells} opts={opts}", flush=True)
+    s = STA(d, **opts)
+    s.update()
+    out = run_gpu(s)
+    s.close()
+    return out
+
+
+@pytest.mark.parametrize("sched", [STA_SCHED_PERSISTENT, STA_SCHED_PER_LEVEL])
+def test_tiny(sched):
+    d = synth.generate(synth.tiny_config())
+    r = oracle.sta(d)
+    stats = compare_full(d, r, _run(d, sched=sched))
+    print(stats)
+
+
+def test_tiny_shuffled_ids_and_big_net_path():
+    """Permuted pin, cell and net ids; every net with more than 8 RC nodes goes
+    through the wide-net RC kernel (preorder layout)."""
+    d = synth.generate(synth.tiny_config(seed=7, shuffle=1))
+    r = oracle.sta(d)
+    compare_full(d, r, _run(d, big_net_nodes=8))
+
+
+def test_tiny_dangling_endpoints():
+    d = synth.generate(synth.tiny_config(seed=9, dangling_policy=1, rat_early_ps=40.0))
+    r = oracle.sta(d)
+    compare_full(d, r, _run(d))
+
+
+def test_worked_chain_design():
+    import test_oracle_pins as pins
+    d, *_ = pins._chain_design()
+    r = oracle.sta(d)
+    compare_full(d, r, _run(d))
+
+
+def test_high_fanout_nets():
+    """Nets of a few hundred to a thousand sinks driven by PIs / level-1 cells
+    (the RC trees exceed the LDS-staged limit)."""
+    cfg = synth.mid_config(seed=21, n_cells=20_000, n_levels=25, n_hf=6, hf_min=200, hf_max=1000)
+    d = synth.generate(cfg)
+    assert np.diff(d.net_node_ptr).max() > 255
+    r = oracle.sta(d)
+    compare_full(d, r, _run(d))
+
+
+@pytest.mark.parametrize("sched", [STA_SCHED_PERSISTENT, STA_SCHED_PER_LEVEL])
+def test_mid(sched):
+    d = synth.generate(synth.mid_config(n_cells=60_000, n_levels=40, seed=12))
+    r = oracle.sta(d)
+    compare_full(d, r, _run(d, sched=sched))
+
+
+def test_1m_pins():
+    d = synth.generate(synth.mid_config())
+    r = oracle.sta(d)
+    stats = compare_full(d, r, _run(d))
+    print(stats)
+
+
+def test_determinism_and_repeat():
+    d = synth.generate(synth.mid_config(n_cells=30_000, n_levels=30, seed=13))
+    s = STA(d)
+    s.update()
+    a = run_gpu(s)
+    s.update()
+    s.update()
+    b = run_gpu(s)
+    s.close()
+    for k in ("at", "slew", "rat", "crit"):
+        np.testing.assert_array_equal(a["timing"][k], b["timing"][k])
+    np.testing.assert_array_equal(a["slack"]["slack"], b["slack"]["slack"])
+    np.testing.assert_array_equal(a["slack"]["tns"], b["slack"]["tns"])
+    np.testing.assert_array_equal(a["slack"]["ep_order"], b["slack"]["ep_order"])
+
+
+def test_set_wire_caps_host_and_device():
+    import torch
+    d = synth.generate(synth.tiny_config(seed=3))
+    rng = np.random.default_rng(0)
+    caps = (d.cap_ff * rng.uniform(0.5, 2.0, d.cap_ff.shape)).astype(np.float32)
+    r = oracle.sta(d, wire_cap=caps.astype(np.float64))
+    s = STA(d)
+    s.set_wire_caps(caps)
+    s.update()
+    compare_full(d, r, run_gpu(s))
+    caps2 = (d.cap_ff * rng.uniform(0.5, 2.0, d.cap_ff.shape)).astype(np.float32)
+    r2 = oracle.sta(d, wire_cap=caps2.astype(np.float64))
+    s.set_wire_caps(torch.from_numpy(caps2).cuda())
+    torch.cuda.synchronize()
+    s.update()
+    compare_full(d, r2, run_gpu(s))
+    s.close()
+
+
+def test_device_outputs_match_host_outputs():
+    import torch
+    from paper_2511_11660_amd import sta as S
+    d = synth.generate(synth.tiny_config(seed=4))
+    s = STA(d)
+    s.update()
+    h = s.timing()
+    at = torch.empty((d.n_pins, 4), dtype=torch.float32, device="cuda")
+    crit = torch.empty((d.n_pins, 4), dtype=torch.int8, device="cuda")
+    S.sta_report_timing(s.ctx, at=at, crit=crit, dst=S.STA_DEVICE)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(at.cpu().numpy(), h["at"])
+    np.testing.assert_array_equal(crit.cpu().numpy(), h["crit"])
+    s.close()
+
+
+def test_single_cell_and_pi_to_po():
+    """Degenerate designs: one cell; a PI wired straight to a PO; a dangling PI."""
+    kinds = [PI, PI, PI, CIN, COUT, PO, PO]
+    cells = [(0, [3], 4)]
+    nets = [single_segment_net(0, [3], 0.01, 1.0), single_segment_net(1, [6], 0.02, 0.5),
+            single_segment_net(2, [], 0.0, 0.0), single_segment_net(4, [5], 0.03, 2.0)]
+    tables = np.stack([np.stack([planar_table(7, 0.1, 1.3)] * 2 + [planar_table(3, 0.05, 2.0)] * 2)])
+    d = make_design(kinds, cells, nets, n_inputs=[1], sense=[2], pin_cap=[1.0], tables=tables)
+    r = oracle.sta(d)
+    compare_full(d, r, _run(d))
+
+
+@pytest.mark.slow
+def test_10m_pins_full():
+    """The benchmark's 10M-pin design at full size, persistent schedule."""
+    d = synth.generate(synth.large_config())
+    r = oracle.sta(d)
+    stats = compare_full(d, r, _run(d))
+    print(stats)
