@@ -67,6 +67,25 @@ def cpu_baseline(design, n_pins: int) -> dict:
                       f"{dt:.2f} s"}
 
 
+def copy_calibration(mib: int, reps: int) -> int:
+    """A plain device copy of known size, so HBM counters (FETCH_SIZE,
+    WRITE_SIZE) can be scaled: each launch reads and writes mib MiB."""
+    import torch
+    n = mib * 1024 * 1024 // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    print(json.dumps({"copy_mib": mib, "ms": ms, "GBps_read_plus_write": 2 * mib * 1048576 / (ms * 1e-3) / 1e9}))
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,7 +94,11 @@ def main() -> int:
     ap.add_argument("--workload", default="10M", choices=["10M", "1M", "tiny"])
     ap.add_argument("--sched", type=int, default=0, help="0 persistent, 1 one launch per level")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
+                    help="only run a device-to-device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
+    if args.copy_calib:
+        return copy_calibration(args.copy_calib, args.steps)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is a design note "
                                    "only (see DESIGN.md)", "n_gpus": args.gpus}))

@@ -117,12 +117,14 @@ typedef struct {
 /* Schedules for the level sweeps. */
 typedef enum {
   STA_SCHED_PERSISTENT = 0,    /* one launch per sweep, device-side level counters */
-  STA_SCHED_PER_LEVEL = 1      /* one launch per level */
+  STA_SCHED_PER_LEVEL = 1,     /* one launch per level */
+  STA_SCHED_GRAPH = 2          /* one launch per level, captured once in a HIP graph and replayed
+                                  (in-graph phases are not timed separately) */
 } sta_sched;
 
 typedef struct {
-  int32_t mode;                /* 0 hard max/min (only mode in this build) */
-  float gamma_ps;              /* smoothing temperature (mode 1) */
+  int32_t mode;                /* 0 hard max/min; 1 smooth late arrival merges (differentiable) */
+  float gamma_ps;              /* smoothing temperature of mode 1 (> 0), e.g. 5 ps */
   int32_t dangling_policy;     /* 0: zero-fanout cell outputs unconstrained; 1: endpoints */
   int32_t sched;               /* sta_sched */
   int32_t big_net_nodes;       /* nets with more RC nodes go to the wide RC kernel; 0 = 255 */
@@ -206,11 +208,38 @@ sta_status sta_report_endpoints(sta_ctx *ctx, int32_t *ep_pin, sta_mem dst, void
 /* Sizes and schedule facts of a context. */
 sta_status sta_get_info(const sta_ctx *ctx, sta_info *info);
 
-/* Per-kernel durations (ms) of the last sta_update_timing when profiling is on:
- * ms[0] RC small nets, ms[1] RC big nets, ms[2] forward sweep, ms[3] backward
- * sweep, ms[4] endpoint reduction, ms[5] endpoint sort.  *n receives the count
- * (6); ms needs room for 6.  Synchronizes the last update's stream. */
+/* Per-kernel durations (ms) when profiling is on: ms[0] RC pass, ms[1] unused
+ * (0), ms[2] forward sweep, ms[3] backward sweep, ms[4] endpoint reduction,
+ * ms[5] endpoint sort of the last sta_update_timing; ms[6] adjoint sweep and
+ * ms[7] RC adjoint of the last sta_backward (0 if none).  *n receives the count
+ * (8); ms needs room for 8.  Synchronizes the streams of those calls. */
 sta_status sta_get_phase_times(sta_ctx *ctx, float *ms, int32_t *n);
+
+/* Smooth mode (options.mode = 1).  Not in the paper: a differentiable form for
+ * gradient-driven optimization loops of the kind §IV-C (timing-driven
+ * placement, which consumes back-propagated pin slacks) and §IV-D run.  Late
+ * arrival merges become log-sum-exp with temperature g = gamma_ps; the late
+ * endpoint slack is s = -LSE_g(AT - RAT over rise/fall); the update reports
+ * (through sta_report_slack) tns[1] = TNS_g = sum -g log(1 + e^{-s/g}) and
+ * wns[1] = WNS_g = -g log(1 + sum e^{-s/g}), with the early views hard.  In
+ * this mode the update runs no required-time sweep (pin RAT/slack reports
+ * return STA_E_STATE).
+ *
+ * sta_backward computes, after sta_update_timing on the same context, the
+ * gradient of J = g_tns TNS_g + g_wns WNS_g with respect to:
+ *   grad_wire_cap  [n_nodes]    every RC node's ground cap, caller node order
+ *                               (through the RC moments and the driver's load);
+ *   grad_pin_load  [n_pins]     each cell output's NLDM load (partial through
+ *                               the lookups only; 0 on other pins);
+ *   grad_arc_delay [n_arcs][4]  each cell arc's additive delay per output view
+ *                               (arcs in cell_in_pin order; early views 0).
+ * Any output may be NULL; outputs go to `dst` memory.  Activations are not
+ * stored beyond the per-pin arrival/slew the update keeps anyway: the reverse
+ * sweep recomputes delays, softmax weights and table partials from them.
+ * Gradients are accumulated in a fixed order (bitwise reproducible).
+ * STA_E_STATE if the context is not in mode 1 or was never updated. */
+sta_status sta_backward(sta_ctx *ctx, float g_tns, float g_wns, float *grad_wire_cap, float *grad_pin_load,
+                        float *grad_arc_delay, sta_mem dst, void *stream);
 
 /* Name of a status code; message of the calling thread's last error. */
 const char *sta_status_string(sta_status s);

@@ -42,9 +42,25 @@ def _run(cmd: list[str]) -> None:
 
 
 def build_sta() -> str:
+    """Compiles the kernels and host runtime, then links the shared object
+    without a hard dependency on one HIP runtime copy: the process supplies it
+    (the binding preloads the runtime the process already uses, so torch and
+    this library share one HIP/HSA runtime, its streams and allocations)."""
     srcs = [os.path.join(CSRC, "sta_kernels.hip"), os.path.join(CSRC, "sta_host.cpp")]
+    objs = []
+    bdir = os.path.join(CSRC, "_build")
+    os.makedirs(bdir, exist_ok=True)
+    compile_flags = [f for f in HIP_FLAGS if f != "-shared"]
+    for src in srcs:
+        obj = os.path.join(bdir, os.path.basename(src) + ".o")
+        _run([_hipcc(), *compile_flags, "-I", os.path.join(ROOT, "include"), "-x", "hip", "-c", src,
+              "-o", obj])
+        objs.append(obj)
     tmp = LIBSTA + ".tmp"
-    _run([_hipcc(), *HIP_FLAGS, "-I", os.path.join(ROOT, "include"), "-x", "hip", *srcs, "-o", tmp])
+    clangxx = "/opt/rocm/llvm/bin/clang++"
+    if not os.path.exists(clangxx):
+        clangxx = shutil.which("clang++") or "g++"
+    _run([clangxx, "-shared", "-fPIC", "-o", tmp, *objs, "-Wl,--no-undefined-version"])
     os.replace(tmp, LIBSTA)
     return LIBSTA
 

@@ -105,16 +105,26 @@ struct sta_ctx {
   int32_t *ep_pin = nullptr, *pin_level = nullptr, *level_order = nullptr;
   int2 *rc_chunks = nullptr;
   BigNet *big = nullptr;
-  int32_t *big_end = nullptr;
+  int32_t *big_end = nullptr, *big_nsp = nullptr, *big_nsl = nullptr, *big_egp = nullptr, *big_egl = nullptr;
+  WideNets wide{};
+  hipStream_t side = nullptr;          // wide-net RC kernels run here, overlapping the small nets
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   float *big_pc = nullptr;
   double *big_scratch = nullptr;
+  int32_t *arc_src = nullptr;
+  int n_fanin = 0;
+  bool updated = false;
   double *partials = nullptr, *out = nullptr;
   uint32_t *keys = nullptr, *keys_out = nullptr;
   int32_t *vals = nullptr, *order = nullptr;
   void *sort_temp = nullptr;
   size_t sort_bytes = 0;
   std::vector<int> level_chunk_begin;  // [n_cell_levels+2]
-  hipEvent_t ev[8]{};
+  hipEvent_t ev[10]{};  // 0..6 update phases, 7..9 adjoint phases
+  hipStream_t cap_stream = nullptr;   // graph schedule: capture stream
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  bool bwd_timed = false;
   bool events = false, timed = false;
   hipStream_t last_stream = nullptr;
 
@@ -137,6 +147,12 @@ struct sta_ctx {
   ~sta_ctx() {
     if (events)
       for (auto &e : ev) (void)hipEventDestroy(e);
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (side) (void)hipStreamDestroy(side);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
   }
 };
 
@@ -519,7 +535,7 @@ static sta_status build_layout(sta_ctx *C, const Inputs &I, const std::vector<in
   C->n_nodes = NN;
   std::vector<int32_t> sink_drv(NS), sink_cons(NS), sink_node(NS), sink_slot(NS), pin_loc(NP);
   std::vector<float> sink_pincap(NS), rc_res(NN), rc_cap(NN);
-  std::vector<int32_t> rc_parent(NN), node_src(NN), big_x, big_end;
+  std::vector<int32_t> rc_parent(NN), node_src(NN), big_x, big_end, big_nsp, big_nsl, big_egp, big_egl;
   std::vector<float> big_pc;
   std::vector<BigNet> big;
   int64_t big_scr = 0;
@@ -538,8 +554,10 @@ static sta_status build_layout(sta_ctx *C, const Inputs &I, const std::vector<in
       bn.m = m;
       bn.aux = (int64_t)big_end.size();
       bn.scr = big_scr;
+      bn.nsp = (int64_t)big_nsp.size();
+      bn.egp = (int64_t)big_egp.size();
       big.push_back(bn);
-      big_scr += 4 * ((int64_t)m + 1);
+      big_scr += kBigScratch * ((int64_t)m + 1);
     }
     for (int k = 0; k < m; ++k) {
       const int nk = is_big ? newof[k] : k;
@@ -563,6 +581,27 @@ static sta_status build_layout(sta_ctx *C, const Inputs &I, const std::vector<in
         big_end.push_back(k + size[k]);
         big_pc.push_back((float)pcd[k]);
       }
+      // Euler end-groups: for p in [0, m], the nodes a with end_a = p, found by
+      // walking up from p - 1 (a chain), kept deepest first
+      // (offsets local to the net; its list starts at its node offset aux,
+      // since every node belongs to exactly one group)
+      const int32_t *endv = big_end.data() + (big_end.size() - m);
+      const size_t gbase = big_egl.size();
+      big_egp.push_back(0);  // group p spans [egp[p], egp[p+1]); group 0 is empty
+      big_egp.push_back(0);
+      for (int p = 1; p <= m; ++p) {
+        for (int a = p - 1; a >= 0 && endv[a] == p; a = rc_parent[base + a]) big_egl.push_back(a);
+        big_egp.push_back((int32_t)(big_egl.size() - gbase));
+      }
+      // sinks of each node (local sink index, sink order) for the adjoint seeds
+      std::vector<int32_t> cnt(m + 1, 0);
+      const int ns = I.net_sink_ptr[n + 1] - I.net_sink_ptr[n];
+      for (int j = 0; j < ns; ++j) cnt[newof[I.sink_node[I.net_sink_ptr[n] + j]] + 1]++;
+      for (int k = 0; k < m; ++k) cnt[k + 1] += cnt[k];
+      const int32_t lbase = (int32_t)big_nsl.size();
+      for (int k = 0; k <= m; ++k) big_nsp.push_back(lbase + cnt[k]);
+      big_nsl.resize(big_nsl.size() + ns);
+      for (int j = 0; j < ns; ++j) big_nsl[lbase + cnt[newof[I.sink_node[I.net_sink_ptr[n] + j]]]++] = j;
     }
     int s = sink_ptr[x];
     for (int sc = I.net_sink_ptr[n]; sc < I.net_sink_ptr[n + 1]; ++sc, ++s) {
@@ -586,19 +625,25 @@ static sta_status build_layout(sta_ctx *C, const Inputs &I, const std::vector<in
   C->n_big = (int)big_x.size();
 
   // per driver slot: cell type, fanin (sink slots of the inputs), endpoint
-  std::vector<int32_t> cell_type(ND, -1), fanin_ptr(ND + 1, 0), fanin_sink, drv_ep(ND, -1);
+  std::vector<int32_t> cell_type(ND, -1), fanin_ptr(ND + 1, 0), fanin_sink, drv_ep(ND, -1), arc_src;
   fanin_sink.reserve(I.cell_in_ptr[NC]);
+  arc_src.reserve(I.cell_in_ptr[NC]);
   for (int x = 0; x < ND; ++x) {
     const int p = drv_pin[x];
     drv_ep[x] = ep_of_pin[p];
     if (x >= NPI) {
       const int c = I.cell_of_pin[p];
       cell_type[x] = I.cell_type[c];
-      for (int k = I.cell_in_ptr[c]; k < I.cell_in_ptr[c + 1]; ++k)
+      for (int k = I.cell_in_ptr[c]; k < I.cell_in_ptr[c + 1]; ++k) {
         fanin_sink.push_back(sink_slot[I.sink_idx_of_pin[I.cell_in_pin[k]]]);
+        arc_src.push_back(k);
+      }
     }
     fanin_ptr[x + 1] = (int32_t)fanin_sink.size();
   }
+  std::vector<int32_t> ep_loc(ep_pin.size());
+  for (size_t e = 0; e < ep_pin.size(); ++e) ep_loc[e] = pin_loc[ep_pin[e]];
+  C->n_fanin = (int)fanin_sink.size();
   std::vector<float4> pi_at(NPI), pi_slew(NPI);
   for (int x = 0; x < NPI; ++x) {
     const int r = I.rank[drv_pin[x]];
@@ -721,10 +766,26 @@ static sta_status build_layout(sta_ctx *C, const Inputs &I, const std::vector<in
   STA_TRY(C->upload(&C->big, big));
   STA_TRY(C->upload(&C->big_end, big_end));
   STA_TRY(C->upload(&C->big_pc, big_pc));
+  STA_TRY(C->upload(&C->big_nsp, big_nsp));
+  STA_TRY(C->upload(&C->big_nsl, big_nsl));
+  if (big_egl.size() != big_end.size()) return fail(STA_E_DEVICE, "internal: Euler group size mismatch");
+  STA_TRY(C->upload(&C->big_egp, big_egp));
+  STA_TRY(C->upload(&C->big_egl, big_egl));
+  STA_TRY(C->upload(&C->arc_src, arc_src));
+  STA_TRY(C->upload(&p32, ep_loc)); D.ep_loc = p32;
+  D.gamma = C->opt.mode == 1 ? C->opt.gamma_ps : 0.0f;
+  if (C->opt.mode == 1) {
+    STA_TRY(C->alloc(&D.g_sink, NS));
+    STA_TRY(C->alloc(&D.g_dq, NS));
+    STA_TRY(C->alloc(&D.g_load, ND));
+    STA_TRY(C->alloc(&D.g_arc, std::max(C->n_fanin, 1)));
+    STA_TRY(C->alloc(&D.g_cap, NN));
+  }
   STA_TRY(C->alloc(&C->big_scratch, (size_t)std::max<int64_t>(big_scr, 1)));
-  STA_TRY(C->alloc(&C->partials, 4 * kReduceBlocks));
-  STA_TRY(C->alloc(&C->out, 4));
-  HIP_TRY(hipMemset(C->out, 0, 4 * sizeof(double)));
+  STA_TRY(C->alloc(&C->partials, 8 * kReduceBlocks));
+  STA_TRY(C->alloc(&C->out, 8));
+  HIP_TRY(hipMemset(C->out, 0, 8 * sizeof(double)));
+  D.norm = C->out + 4;
   const int ne = std::max(C->n_ep, 1);
   STA_TRY(C->alloc(&C->keys, 2 * (size_t)ne));
   STA_TRY(C->alloc(&C->keys_out, 2 * (size_t)ne));
@@ -735,11 +796,31 @@ static sta_status build_layout(sta_ctx *C, const Inputs &I, const std::vector<in
   STA_TRY(C->alloc(&st, C->sort_bytes));
   C->sort_temp = st;
 
+  C->wide.big = C->big;
+  C->wide.n_big = C->n_big;
+  C->wide.end = C->big_end;
+  C->wide.nsp = C->big_nsp;
+  C->wide.nsl = C->big_nsl;
+  C->wide.egp = C->big_egp;
+  C->wide.egl = C->big_egl;
+  C->wide.pc = C->big_pc;
+  C->wide.scratch = C->big_scratch;
+  HIP_TRY(hipStreamCreateWithFlags(&C->side, hipStreamNonBlocking));
+  HIP_TRY(hipEventCreateWithFlags(&C->ev_fork, hipEventDisableTiming));
+  HIP_TRY(hipEventCreateWithFlags(&C->ev_join, hipEventDisableTiming));
+
   // persistent grid: every resident block slot on the device
   const size_t lds = sweep_lds_bytes(D);
   if (lds > 160 * 1024) return fail(STA_E_UNSUPPORTED, "library too large for LDS (%zu bytes)", lds);
   C->sweep_grid = sweep_blocks_per_cu(lds) * C->n_cu;
   if (C->sweep_grid < 1) C->sweep_grid = 1;
+  return STA_OK;
+}
+
+// Copies n bytes of device data to dst (host or device).
+static sta_status deliver(void *dst, const void *src, size_t bytes, sta_mem m, hipStream_t s) {
+  if (!dst || bytes == 0) return STA_OK;
+  HIP_TRY(hipMemcpyAsync(dst, src, bytes, m == STA_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, s));
   return STA_OK;
 }
 
@@ -749,8 +830,11 @@ extern "C" sta_status sta_create(const sta_graph_desc *graph, const sta_rc_desc 
   sta_options o;
   sta_options_default(&o);
   if (opts) o = *opts;
-  if (o.mode != 0) return fail(STA_E_UNSUPPORTED, "only mode 0 (hard max/min) is built");
-  if (o.sched != STA_SCHED_PERSISTENT && o.sched != STA_SCHED_PER_LEVEL) return fail(STA_E_ARG, "bad sched");
+  if (o.mode != 0 && o.mode != 1) return fail(STA_E_ARG, "mode must be 0 (hard) or 1 (smooth)");
+  if (o.mode == 1 && !(o.gamma_ps > 0.0f && std::isfinite(o.gamma_ps)))
+    return fail(STA_E_ARG, "smooth mode needs a finite gamma_ps > 0");
+  if (o.sched != STA_SCHED_PERSISTENT && o.sched != STA_SCHED_PER_LEVEL && o.sched != STA_SCHED_GRAPH)
+    return fail(STA_E_ARG, "bad sched");
   if (o.big_net_nodes < 0) return fail(STA_E_ARG, "big_net_nodes < 0");
   if (o.dangling_policy != 0 && o.dangling_policy != 1) return fail(STA_E_ARG, "bad dangling_policy");
   STA_TRY(validate_lib(*lib));
@@ -827,33 +911,92 @@ extern "C" sta_status sta_set_wire_caps(sta_ctx *C, const float *cap_ff, sta_mem
   return STA_OK;
 }
 
-extern "C" sta_status sta_update_timing(sta_ctx *C, void *stream) {
-  if (!C) return fail(STA_E_STATE, "NULL context");
-  HIP_TRY(hipSetDevice(C->device));
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  const bool prof = C->opt.profile != 0;
+// RC pass (or its adjoint): wide nets on the side stream, forked from and
+// joined back into s around the small-net kernel, so the two overlap.
+static sta_status enqueue_rc(sta_ctx *C, hipStream_t s, bool adjoint) {
   const DevDesign &D = C->D;
+  if (C->n_big > 0) {
+    HIP_TRY(hipEventRecord(C->ev_fork, s));
+    HIP_TRY(hipStreamWaitEvent(C->side, C->ev_fork, 0));
+    HIP_TRY(adjoint ? launch_rc_adjoint_wide(D, C->wide, C->side) : launch_rc_wide(D, C->wide, C->side));
+    HIP_TRY(hipEventRecord(C->ev_join, C->side));
+  }
+  HIP_TRY(adjoint ? launch_rc_adjoint(D, C->rc_chunks, C->n_rc_chunks, s) : launch_rc(D, C->rc_chunks, C->n_rc_chunks, s));
+  if (C->n_big > 0) HIP_TRY(hipStreamWaitEvent(s, C->ev_join, 0));
+  return STA_OK;
+}
+
+// Enqueues RC, both sweeps and the reduction on s (the body of one update,
+// without the endpoint sort).  With prof, events separate the phases.
+static sta_status enqueue_update(sta_ctx *C, hipStream_t s, bool prof) {
+  const DevDesign &D = C->D;
+  const bool smooth = C->opt.mode == 1;
+  const bool per_level = C->opt.sched != STA_SCHED_PERSISTENT;
+  const bool sort = C->opt.sort_endpoints && C->n_ep > 0;
   if (prof) HIP_TRY(hipEventRecord(C->ev[0], s));
-  HIP_TRY(launch_rc(D, C->rc_chunks, C->n_rc_chunks, C->big, C->n_big, C->big_end, C->big_pc, C->big_scratch, s));
+  STA_TRY(enqueue_rc(C, s, false));
   if (prof) HIP_TRY(hipEventRecord(C->ev[1], s));
   if (prof) HIP_TRY(hipEventRecord(C->ev[2], s));
-  if (C->opt.sched == STA_SCHED_PERSISTENT) {
+  if (!per_level) {
     HIP_TRY(launch_forward(D, C->sweep_grid, s));
   } else {
     for (int l = 0; l <= C->n_cell_levels; ++l)
       HIP_TRY(launch_forward_level(D, C->level_chunk_begin[l], C->level_chunk_begin[l + 1], s));
   }
   if (prof) HIP_TRY(hipEventRecord(C->ev[3], s));
-  if (C->opt.sched == STA_SCHED_PERSISTENT) {
-    HIP_TRY(launch_backward(D, C->sweep_grid, s));
-  } else {
-    for (int l = C->n_cell_levels; l >= 0; --l)
-      HIP_TRY(launch_backward_level(D, C->level_chunk_begin[l], C->level_chunk_begin[l + 1], s));
+  if (!smooth) {  // the smooth objective needs arrivals only; it skips the RAT sweep
+    if (!per_level) {
+      HIP_TRY(launch_backward(D, C->sweep_grid, s));
+    } else {
+      for (int l = C->n_cell_levels; l >= 0; --l)
+        HIP_TRY(launch_backward_level(D, C->level_chunk_begin[l], C->level_chunk_begin[l + 1], s));
+    }
   }
   if (prof) HIP_TRY(hipEventRecord(C->ev[4], s));
-  const bool sort = C->opt.sort_endpoints && C->n_ep > 0;
-  HIP_TRY(launch_reduce(D, C->partials, C->out, sort ? C->keys : nullptr, sort ? C->vals : nullptr, s));
+  if (smooth)
+    HIP_TRY(launch_reduce_smooth(D, C->partials, C->out, sort ? C->keys : nullptr, sort ? C->vals : nullptr, s));
+  else
+    HIP_TRY(launch_reduce(D, C->partials, C->out, sort ? C->keys : nullptr, sort ? C->vals : nullptr, s));
   if (prof) HIP_TRY(hipEventRecord(C->ev[5], s));
+  return STA_OK;
+}
+
+// Graph schedule: the per-level launch sequence of one update is captured once
+// and replayed; it holds kernel nodes only (counters are cleared by a kernel,
+// never by a memset node).
+static sta_status ensure_graph(sta_ctx *C) {
+  if (C->graph_exec) return STA_OK;
+  if (!C->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&C->cap_stream, hipStreamNonBlocking));
+  HIP_TRY(hipStreamBeginCapture(C->cap_stream, hipStreamCaptureModeThreadLocal));
+  sta_status st = enqueue_update(C, C->cap_stream, false);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(C->cap_stream, &g);
+  if (st != STA_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+  C->graph = g;
+  HIP_TRY(hipGraphInstantiate(&C->graph_exec, g, nullptr, nullptr, 0));
+  return STA_OK;
+}
+
+extern "C" sta_status sta_update_timing(sta_ctx *C, void *stream) {
+  if (!C) return fail(STA_E_STATE, "NULL context");
+  HIP_TRY(hipSetDevice(C->device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool prof = C->opt.profile != 0;
+  const bool sort = C->opt.sort_endpoints && C->n_ep > 0;
+  if (C->opt.sched == STA_SCHED_GRAPH) {
+    STA_TRY(ensure_graph(C));
+    if (prof) {
+      for (int i = 0; i < 5; ++i) HIP_TRY(hipEventRecord(C->ev[i], s));  // phases not separable in a graph
+    }
+    HIP_TRY(hipGraphLaunch(C->graph_exec, s));
+    if (prof) HIP_TRY(hipEventRecord(C->ev[5], s));
+  } else {
+    STA_TRY(enqueue_update(C, s, prof));
+  }
   if (sort) {
     for (int el = 0; el < 2; ++el)
       HIP_TRY(sort_endpoints(C->sort_temp, C->sort_bytes, C->keys + (size_t)el * C->n_ep,
@@ -863,6 +1006,51 @@ extern "C" sta_status sta_update_timing(sta_ctx *C, void *stream) {
   if (prof) HIP_TRY(hipEventRecord(C->ev[6], s));
   C->timed = prof;
   C->last_stream = s;
+  C->updated = true;
+  return STA_OK;
+}
+
+extern "C" sta_status sta_backward(sta_ctx *C, float g_tns, float g_wns, float *grad_wire_cap,
+                                   float *grad_pin_load, float *grad_arc_delay, sta_mem dst, void *stream) {
+  if (!C) return fail(STA_E_STATE, "NULL context");
+  if (C->opt.mode != 1) return fail(STA_E_STATE, "sta_backward needs a context created with mode 1 (smooth)");
+  if (!C->updated) return fail(STA_E_STATE, "sta_backward before sta_update_timing");
+  if (!std::isfinite(g_tns) || !std::isfinite(g_wns)) return fail(STA_E_ARG, "non-finite seed");
+  if (dst != STA_HOST && dst != STA_DEVICE) return fail(STA_E_ARG, "bad dst");
+  HIP_TRY(hipSetDevice(C->device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool prof = C->opt.profile != 0;
+  const DevDesign &D = C->D;
+  if (prof) HIP_TRY(hipEventRecord(C->ev[7], s));
+  HIP_TRY(launch_reset_counters(D.counters, kCtrLevels + 2 * (C->n_cell_levels + 1), s));
+  if (C->opt.sched == STA_SCHED_PERSISTENT) {
+    HIP_TRY(launch_adjoint(D, g_tns, g_wns, C->sweep_grid, s));
+  } else {
+    for (int l = C->n_cell_levels; l >= 0; --l)
+      HIP_TRY(launch_adjoint_level(D, g_tns, g_wns, C->level_chunk_begin[l], C->level_chunk_begin[l + 1], s));
+  }
+  if (prof) HIP_TRY(hipEventRecord(C->ev[8], s));
+  STA_TRY(enqueue_rc(C, s, true));
+  if (prof) HIP_TRY(hipEventRecord(C->ev[9], s));
+  C->bwd_timed = prof;
+  if (!grad_wire_cap && !grad_pin_load && !grad_arc_delay) return STA_OK;
+  if (dst == STA_DEVICE) {
+    HIP_TRY(launch_scatter_grads(D, C->node_src, C->n_nodes, grad_wire_cap, C->pin_loc, C->n_pins, grad_pin_load,
+                                 C->arc_src, C->n_fanin, reinterpret_cast<float4 *>(grad_arc_delay), s));
+    return STA_OK;
+  }
+  sta_ctx tmp;
+  float *gc = nullptr, *gl = nullptr;
+  float4 *ga = nullptr;
+  if (grad_wire_cap) STA_TRY(tmp.alloc(&gc, (size_t)C->n_nodes));
+  if (grad_pin_load) STA_TRY(tmp.alloc(&gl, C->n_pins));
+  if (grad_arc_delay) STA_TRY(tmp.alloc(&ga, std::max(C->n_fanin, 1)));
+  HIP_TRY(launch_scatter_grads(D, C->node_src, C->n_nodes, gc, C->pin_loc, C->n_pins, gl, C->arc_src, C->n_fanin,
+                               ga, s));
+  STA_TRY(deliver(grad_wire_cap, gc, (size_t)C->n_nodes * 4, STA_HOST, s));
+  STA_TRY(deliver(grad_pin_load, gl, (size_t)C->n_pins * 4, STA_HOST, s));
+  STA_TRY(deliver(grad_arc_delay, ga, (size_t)C->n_fanin * 16, STA_HOST, s));
+  HIP_TRY(hipStreamSynchronize(s));
   return STA_OK;
 }
 
@@ -872,14 +1060,13 @@ extern "C" sta_status sta_get_phase_times(sta_ctx *C, float *ms, int32_t *n) {
   HIP_TRY(hipSetDevice(C->device));
   HIP_TRY(hipEventSynchronize(C->ev[6]));
   for (int i = 0; i < 6; ++i) HIP_TRY(hipEventElapsedTime(&ms[i], C->ev[i], C->ev[i + 1]));
-  *n = 6;
-  return STA_OK;
-}
-
-// Copies n bytes of device data to dst (host or device).
-static sta_status deliver(void *dst, const void *src, size_t bytes, sta_mem m, hipStream_t s) {
-  if (!dst || bytes == 0) return STA_OK;
-  HIP_TRY(hipMemcpyAsync(dst, src, bytes, m == STA_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, s));
+  ms[6] = ms[7] = 0.0f;
+  if (C->bwd_timed) {
+    HIP_TRY(hipEventSynchronize(C->ev[9]));
+    HIP_TRY(hipEventElapsedTime(&ms[6], C->ev[7], C->ev[8]));
+    HIP_TRY(hipEventElapsedTime(&ms[7], C->ev[8], C->ev[9]));
+  }
+  *n = 8;
   return STA_OK;
 }
 
@@ -887,6 +1074,7 @@ extern "C" sta_status sta_report_timing(sta_ctx *C, float *at, float *slew, floa
                                         sta_mem dst, void *stream) {
   if (!C) return fail(STA_E_STATE, "NULL context");
   if (dst != STA_HOST && dst != STA_DEVICE) return fail(STA_E_ARG, "bad dst");
+  if (rat && C->opt.mode == 1) return fail(STA_E_STATE, "smooth mode computes no required times");
   HIP_TRY(hipSetDevice(C->device));
   hipStream_t s = static_cast<hipStream_t>(stream);
   const size_t n4 = (size_t)C->n_pins * sizeof(float4);
@@ -917,6 +1105,7 @@ extern "C" sta_status sta_report_slack(sta_ctx *C, float *pin_slack, float *ep_s
   if (!C) return fail(STA_E_STATE, "NULL context");
   if (dst != STA_HOST && dst != STA_DEVICE) return fail(STA_E_ARG, "bad dst");
   if (ep_order && !C->opt.sort_endpoints) return fail(STA_E_STATE, "endpoint sorting is disabled");
+  if (pin_slack && C->opt.mode == 1) return fail(STA_E_STATE, "smooth mode computes no pin slacks");
   HIP_TRY(hipSetDevice(C->device));
   hipStream_t s = static_cast<hipStream_t>(stream);
   sta_ctx tmp;

@@ -83,6 +83,17 @@ struct DevDesign {
   float4 *drv_slack, *sink_slack;
   float2 *ep_slack;           // [n_ep] (early, late)
 
+  // smooth (differentiable) mode: gamma > 0 turns late arrival merges into
+  // log-sum-exp; the adjoint writes the g_* arrays
+  float gamma;
+  const int32_t *ep_loc;        // [n_ep] endpoint pin: driver slot (>= 0) or -1 - sink slot
+  float4 *g_sink;               // [n_sinks] dJ/d(late AT R, F), dJ/d(late slew R, F)
+  float2 *g_dq;                 // [n_sinks] dJ/d(Elmore delay), dJ/d(spread q)
+  float *g_load;                // [n_drv] dJ/d(NLDM load) of each cell output
+  float2 *g_arc;                // [n_fanin] dJ/d(arc delay), late rise / fall output view
+  float *g_cap;                 // [n_nodes] dJ/d(node cap), layout order
+  double *norm;                 // [2] WNS_g normalisation (max shift M, denominator)
+
   // sweep schedule
   const int32_t *chunk_start;   // [n_chunks+1] driver-slot ranges
   const int32_t *chunk_level;   // [n_chunks]
@@ -94,8 +105,13 @@ struct DevDesign {
 struct BigNet {
   int32_t x, m;       // driver slot, node count
   int64_t aux;        // offset into big_end / big_pc (one entry per node)
-  int64_t scr;        // offset into the FP64 scratch (4 * (m + 1) doubles)
+  int64_t scr;        // offset into the FP64 scratch (kBigScratch * (m + 1) doubles)
+  int64_t nsp;        // offset into big_nsp (m + 1 entries: sinks of each node, CSR)
+  int64_t egp;        // offset into big_egp (m + 2 entries): nodes whose subtree ends at p,
+                      // listed in big_egl (aux-indexed, m entries) deepest first
 };
+constexpr int kWideBlock = 1024;            // threads per wide-net block
+constexpr int kBigScratch = 8;
 
 // Packed-table offsets for one type.
 struct TabLayout {
@@ -109,13 +125,33 @@ struct TabLayout {
 };
 
 // Launch wrappers (sta_kernels.hip).  All return hipError_t of the launch.
-hipError_t launch_rc(const DevDesign &D, const int2 *chunks, int n_chunks, const BigNet *big, int n_big,
-                     const int32_t *big_end, const float *big_pc, double *scratch, hipStream_t s);
+// Wide-net arrays handed to the RC kernels.
+struct WideNets {
+  const BigNet *big;
+  int n_big;
+  const int32_t *end, *nsp, *nsl, *egp, *egl;
+  const float *pc;
+  double *scratch;
+};
+
+hipError_t launch_rc(const DevDesign &D, const int2 *chunks, int n_chunks, hipStream_t s);
+hipError_t launch_rc_wide(const DevDesign &D, const WideNets &W, hipStream_t s);
+hipError_t launch_rc_adjoint_wide(const DevDesign &D, const WideNets &W, hipStream_t s);
 hipError_t launch_forward(const DevDesign &D, int persistent_grid, hipStream_t s);
 hipError_t launch_forward_level(const DevDesign &D, int c0, int c1, hipStream_t s);
 hipError_t launch_backward(const DevDesign &D, int persistent_grid, hipStream_t s);
 hipError_t launch_backward_level(const DevDesign &D, int c0, int c1, hipStream_t s);
 hipError_t launch_reset_counters(uint32_t *counters, int n, hipStream_t s);
+hipError_t launch_reduce_smooth(const DevDesign &D, double *partials, double *out, uint32_t *keys,
+                                int32_t *vals, hipStream_t s);
+hipError_t launch_adjoint(const DevDesign &D, float g_tns, float g_wns, int persistent_grid,
+                          hipStream_t s);
+hipError_t launch_adjoint_level(const DevDesign &D, float g_tns, float g_wns, int c0, int c1,
+                                hipStream_t s);
+hipError_t launch_rc_adjoint(const DevDesign &D, const int2 *chunks, int n_chunks, hipStream_t s);
+hipError_t launch_scatter_grads(const DevDesign &D, const int32_t *node_src, int64_t n_nodes,
+                                float *grad_cap, const int32_t *pin_loc, int n_pins, float *grad_load,
+                                const int32_t *arc_src, int n_arcs, float4 *grad_arc, hipStream_t s);
 hipError_t launch_reduce(const DevDesign &D, double *partials, double *out, uint32_t *keys,
                          int32_t *vals, hipStream_t s);
 hipError_t sort_endpoints(void *temp, size_t temp_bytes, const uint32_t *keys_in,

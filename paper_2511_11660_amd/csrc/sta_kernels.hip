@@ -70,6 +70,19 @@ __device__ __forceinline__ float bilerp(const float *T, int ny, AxisPos px, Axis
   return a + py.t * (b - a);
 }
 
+// Bilinear value and its partials in X and Y on the chosen segment.
+__device__ __forceinline__ float bilerp_d(const float *T, int ny, AxisPos px, AxisPos py, float rdx, float rdy,
+                                          float &dX, float &dY) {
+  const float *r0 = T + px.i * ny + py.i;
+  const float *r1 = r0 + ny;
+  const float e0 = r1[0] - r0[0], e1 = r1[1] - r0[1];
+  const float a = r0[0] + px.t * e0;
+  const float b = r0[1] + px.t * e1;
+  dX = (e0 + py.t * (e1 - e0)) * rdx;
+  dY = (b - a) * rdy;
+  return a + py.t * (b - a);
+}
+
 __device__ __forceinline__ float4 slack4(float4 at, float4 rat) {
   return make_float4(at.x - rat.x, at.y - rat.y, rat.z - at.z, rat.w - at.w);
 }
@@ -115,6 +128,10 @@ __device__ __forceinline__ void cell_forward(const DevDesign &D, const LdsLib &l
   float at[4] = {kInf, kInf, -kInf, -kInf};
   float sl[4] = {kInf, kInf, -kInf, -kInf};
   int cr[4] = {-1, -1, -1, -1};
+  // smooth mode: running log-sum-exp of the late candidates, sum of
+  // exp((z - max) / gamma) kept against the running max at[2 + ro]
+  const float g = D.gamma;
+  float lse[2] = {0.0f, 0.0f};
   const int f0 = D.fanin_ptr[x], f1 = D.fanin_ptr[x + 1];
   for (int f = f0; f < f1; ++f) {
     const PinState in = D.sink_state[D.fanin_sink[f]];
@@ -135,13 +152,20 @@ __device__ __forceinline__ void cell_forward(const DevDesign &D, const LdsLib &l
           const float os = bilerp(tb + lay.tab(2 + ro), D.ny, px, py);
           const float cand = ia[vi] + dl;
           if (el ? cand > at[vo] : cand < at[vo]) {
+            if (el && g > 0.0f) lse[ro] = lse[ro] * expf((at[vo] - cand) / g) + 1.0f;
             at[vo] = cand;
             cr[vo] = k2 + ri;
+          } else if (el && g > 0.0f) {
+            lse[ro] += expf((cand - at[vo]) / g);
           }
           sl[vo] = el ? fmaxf(sl[vo], os) : fminf(sl[vo], os);
         }
       }
     }
+  }
+  if (g > 0.0f) {
+    at[2] += g * logf(lse[0]);
+    at[3] += g * logf(lse[1]);
   }
   out.at = make_float4(at[0], at[1], at[2], at[3]);
   out.slew = make_float4(sl[0], sl[1], sl[2], sl[3]);
@@ -416,26 +440,27 @@ __device__ void block_scan(const double *in, double *out, int n, bool exclusive,
   __syncthreads();
 }
 
-// Y[p] = X[p] - sum of X[a] over the nodes a whose subtree ends at p.
-__device__ void euler_terms(const double *X, double *Y, const int32_t *par, const int32_t *end, int m) {
+// Y[p] = X[p] - sum of X[a] over the nodes a whose subtree ends at p (the
+// group of p, precomputed as a CSR in a fixed order, so the loads are
+// independent).
+__device__ void euler_terms(const double *X, double *Y, const int32_t *egp, const int32_t *egl, int m) {
   for (int p = threadIdx.x; p < m; p += blockDim.x) {
     double e = 0.0;
-    for (int a = p - 1; a >= 0 && end[a] == p; a = par[a]) e += X[a];
+    for (int i = egp[p]; i < egp[p + 1]; ++i) e += X[egl[i]];
     Y[p] = X[p] - e;
   }
   __syncthreads();
 }
 
-__device__ void rc_wide_net(const DevDesign &D, const BigNet &B, const int32_t *big_end, const float *big_pc,
-                            double *scratch, double *s_w) {
+__device__ void rc_wide_net(const DevDesign &D, const BigNet &B, const WideNets &W, double *s_w) {
   const int x = B.x, m = B.m;
   const int k0 = D.rc_ptr[x];
-  const int32_t *par = D.rc_parent + k0;
   const float *R = D.rc_res + k0;
   const float *Cw = D.rc_cap + k0;
-  const int32_t *end = big_end + B.aux;
-  const float *pc = big_pc + B.aux;
-  double *A = scratch + B.scr, *P = A + (m + 1), *X = P + (m + 1), *Y = X + (m + 1);
+  const int32_t *end = W.end + B.aux;
+  const float *pc = W.pc + B.aux;
+  const int32_t *egp = W.egp + B.egp, *egl = W.egl + B.aux;
+  double *A = W.scratch + B.scr, *P = A + (m + 1), *X = P + (m + 1), *Y = X + (m + 1);
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int k = tid; k < m; k += nt) A[k] = (double)Cw[k] + (double)pc[k];  // C^
   __syncthreads();
@@ -443,14 +468,14 @@ __device__ void rc_wide_net(const DevDesign &D, const BigNet &B, const int32_t *
   const double total = P[m];
   for (int k = tid; k < m; k += nt) X[k] = k ? (double)R[k] * (P[end[k]] - P[k]) : 0.0;  // R load
   __syncthreads();
-  euler_terms(X, Y, par, end, m);
+  euler_terms(X, Y, egp, egl, m);
   block_scan(Y, Y, m, false, s_w);                                         // Y: d
   for (int k = tid; k < m; k += nt) X[k] = A[k] * Y[k];                    // C^ d
   __syncthreads();
   block_scan(X, P, m, true, s_w);                                          // P: prefix of C^ d
   for (int k = tid; k < m; k += nt) X[k] = k ? (double)R[k] * (P[end[k]] - P[k]) : 0.0;  // R ld
   __syncthreads();
-  euler_terms(X, A, par, end, m);
+  euler_terms(X, A, egp, egl, m);
   block_scan(A, A, m, false, s_w);                                         // A: m2
   if (tid == 0) D.L_net[x] = (float)total;
   for (int s = D.sink_ptr[x] + tid; s < D.sink_ptr[x + 1]; s += nt) {
@@ -460,27 +485,25 @@ __device__ void rc_wide_net(const DevDesign &D, const BigNet &B, const int32_t *
   }
 }
 
-// One launch for the whole RC pass: blocks [0, n_big) each take a wide net
-// (dispatched first, so they overlap the small-net blocks), the rest take a
-// chunk of <= 256 small nets (<= kRcChunkNodes nodes): coalesced staging of
-// parent/R/C into LDS, one net per thread, coalesced sink output.  Block 0 also
-// clears the sweep counters for the launches that follow.
+// Wide nets: one 1024-thread block per net (launched on a side stream so it
+// overlaps the small-net kernel).
+__global__ __launch_bounds__(kWideBlock) void k_rc_wide(DevDesign D, WideNets W) {
+  __shared__ double s_w[kWideBlock / kWave + 1];
+  rc_wide_net(D, W.big[blockIdx.x], W, s_w);
+}
+
+// Small nets: one block per chunk of <= 256 nets (<= kRcChunkNodes nodes):
+// coalesced staging of parent/R/C into LDS, one net per thread, coalesced sink
+// output.  Block 0 also clears the sweep counters for the launches that follow.
 __global__ __launch_bounds__(kRcBlock) void k_rc(DevDesign D, const int2 *chunks, int n_chunks,
-                                                 const BigNet *big, int n_big, const int32_t *big_end,
-                                                 const float *big_pc, double *scratch, uint32_t *counters,
-                                                 int n_counters) {
+                                                 uint32_t *counters, int n_counters) {
   __shared__ uint8_t s_par[kRcChunkNodes];
   __shared__ float s_R[kRcChunkNodes], s_C[kRcChunkNodes], s_A[kRcChunkNodes], s_B[kRcChunkNodes];
   __shared__ int s_base[kRcBlock + 1];
-  __shared__ double s_w[kRcBlock / kWave + 1];
   const int tid = threadIdx.x;
   if (blockIdx.x == 0)
     for (int i = tid; i < n_counters; i += kRcBlock) counters[i] = 0u;
-  if ((int)blockIdx.x < n_big) {
-    rc_wide_net(D, big[blockIdx.x], big_end, big_pc, scratch, s_w);
-    return;
-  }
-  const int ci = blockIdx.x - n_big;
+  const int ci = blockIdx.x;
   if (ci >= n_chunks) return;
   const int2 ch = chunks[ci];
   const int x0 = ch.x, x1 = ch.y;
@@ -560,6 +583,393 @@ __global__ __launch_bounds__(256) void k_reduce(DevDesign D, double *partials, d
       out[0] = W0; out[1] = W1; out[2] = T0; out[3] = T1;
       D.counters[kCtrReduce] = 0u;
     }
+  }
+}
+
+// ------------------------------------------------------ smooth reduction
+
+// Smooth mode: per endpoint the early slack stays hard (min over rise/fall of
+// AT - RAT) and the late slack is the smooth minimum s = -LSE_g(AT - RAT over
+// rise/fall).  Reduces, in FP64 with a fixed partition and tree:
+//   out[0] = early WNS, out[1] = WNS_g = -g log(1 + sum e^{-s/g}),
+//   out[2] = early TNS, out[3] = TNS_g = sum -g log(1 + e^{-s/g}),
+//   out[4], out[5] = max shift M and denominator e^{-M} + sum e^{-s/g - M}.
+// The max-shifted sum is combined as (M, S) pairs so it never overflows.
+__global__ __launch_bounds__(256) void k_reduce_smooth(DevDesign D, double *partials, double *out,
+                                                      uint32_t *keys, int32_t *vals) {
+  __shared__ double sh[5][256];
+  const int n = D.n_ep;
+  const double g = D.gamma;
+  const int per = (n + kReduceBlocks - 1) / kReduceBlocks;
+  const int b0 = blockIdx.x * per, b1 = min(n, b0 + per);
+  double w0 = 0.0, t0 = 0.0, tg = 0.0, M = 0.0, S = 0.0;
+  for (int e = b0 + (int)threadIdx.x; e < b1; e += 256) {
+    const int loc = D.ep_loc[e];
+    const float4 at = loc >= 0 ? D.drv_state[loc].at : D.sink_state[-1 - loc].at;
+    const float4 R = D.ep_rat[e];
+    const float se = fminf(at.x - R.x, at.y - R.y);
+    const float aR = at.z - R.z, aF = at.w - R.w;
+    const float mx = fmaxf(aR, aF);
+    const float sl = -(mx + D.gamma * logf(expf((aR - mx) / D.gamma) + expf((aF - mx) / D.gamma)));
+    D.ep_slack[e] = make_float2(se, sl);
+    w0 = fmin(w0, (double)se);
+    if (se < 0.0f) t0 += (double)se;
+    const double z = -(double)sl / g;
+    tg += -g * (z > 0.0 ? z + log1p(exp(-z)) : log1p(exp(z)));
+    if (z > M) {
+      S = S * exp(M - z) + 1.0;
+      M = z;
+    } else {
+      S += exp(z - M);
+    }
+    if (keys) {
+      keys[e] = f2ukey(se);
+      keys[n + e] = f2ukey(sl);
+      vals[e] = e;
+    }
+  }
+  const int tid = threadIdx.x;
+  sh[0][tid] = w0; sh[1][tid] = t0; sh[2][tid] = tg; sh[3][tid] = M; sh[4][tid] = S;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (tid < o) {
+      sh[0][tid] = fmin(sh[0][tid], sh[0][tid + o]);
+      sh[1][tid] += sh[1][tid + o];
+      sh[2][tid] += sh[2][tid + o];
+      const double Ma = sh[3][tid], Mb = sh[3][tid + o], Mm = fmax(Ma, Mb);
+      sh[4][tid] = sh[4][tid] * exp(Ma - Mm) + sh[4][tid + o] * exp(Mb - Mm);
+      sh[3][tid] = Mm;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    for (int k = 0; k < 5; ++k) partials[blockIdx.x * 5 + k] = sh[k][0];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const uint32_t prev =
+        __hip_atomic_fetch_add(D.counters + kCtrReduce, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (prev == (uint32_t)(kReduceBlocks - 1)) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      double W0 = 0.0, T0 = 0.0, TG = 0.0, MM = 0.0, SS = 0.0;
+      for (int b = 0; b < kReduceBlocks; ++b) {
+        W0 = fmin(W0, partials[b * 5 + 0]);
+        T0 += partials[b * 5 + 1];
+        TG += partials[b * 5 + 2];
+        const double Mb = partials[b * 5 + 3], Mm = fmax(MM, Mb);
+        SS = SS * exp(MM - Mm) + partials[b * 5 + 4] * exp(Mb - Mm);
+        MM = Mm;
+      }
+      const double den = exp(-MM) + SS;
+      out[0] = W0;
+      out[1] = -g * (MM + log(den));
+      out[2] = T0;
+      out[3] = TG;
+      out[4] = MM;
+      out[5] = den;
+      D.counters[kCtrReduce] = 0u;
+    }
+  }
+}
+
+// ------------------------------------------------------------- adjoint
+
+// d J / d(late AT rise, fall) at an endpoint with smooth late slack s, for
+// J = g_tns TNS_g + g_wns WNS_g:  dJ/ds = g_tns / (1 + e^{s/g}) + g_wns e^{-s/g - M} / den,
+// ds/dAT_rf = -softmax_rf(AT - RAT).
+__device__ __forceinline__ float2 endpoint_seed(const DevDesign &D, float g_tns, float g_wns, int e, float4 at) {
+  const float g = D.gamma;
+  const float4 R = D.ep_rat[e];
+  const float s = D.ep_slack[e].y;
+  const float gs = g_tns / (1.0f + expf(s / g)) +
+                   g_wns * (float)(exp(-(double)s / g - D.norm[0]) / D.norm[1]);
+  return make_float2(-gs * expf((at.z - R.z + s) / g), -gs * expf((at.w - R.w + s) / g));
+}
+
+// Reverse mode through one cell output's late merges: softmax weights of the
+// log-sum-exp arrival merge, the slew merge's subgradient to its winner, and
+// the NLDM partials.  Every input sink has this cell as its only consumer, so
+// its gradient is written here, once; nothing is accumulated atomically.
+__device__ void cell_adjoint(const DevDesign &D, const LdsLib &lib, int x, const PinState &me, float gA0,
+                             float gA1, float gS0, float gS1) {
+  const int t = D.cell_type[x];
+  const int sense = lib.sense[t];
+  const float L = D.L_net[x];
+  const TabLayout lay{D.nx, D.ny};
+  const float *tb = lib.tab + t * D.tstride;
+  const AxisPos py = axis_find(tb + lay.ya(), tb + lay.rdy(), D.ny, L);
+  const float rdy = tb[lay.rdy() + py.i];
+  const float g = D.gamma;
+  const float ato[2] = {me.at.z, me.at.w};
+  const float gA[2] = {gA0, gA1}, gS[2] = {gS0, gS1};
+  const int f0 = D.fanin_ptr[x], f1 = D.fanin_ptr[x + 1];
+  // slew winners (same scan order and tie rule as the forward merge)
+  float best[2] = {-kInf, -kInf};
+  int win[2] = {-1, -1};
+  for (int f = f0; f < f1; ++f) {
+    const PinState in = D.sink_state[D.fanin_sink[f]];
+    const float is[2] = {in.slew.z, in.slew.w};
+#pragma unroll
+    for (int ri = 0; ri < 2; ++ri) {
+      const AxisPos px = axis_find(tb + lay.xa(), tb + lay.rdx(), D.nx, is[ri]);
+#pragma unroll
+      for (int ro = 0; ro < 2; ++ro) {
+        if (!arc_maps(sense, ri, ro)) continue;
+        const float cs = bilerp(tb + lay.tab(2 + ro), D.ny, px, py);
+        if (cs > best[ro]) {
+          best[ro] = cs;
+          win[ro] = (f - f0) * 2 + ri;
+        }
+      }
+    }
+  }
+  float gL = 0.0f;
+  for (int f = f0; f < f1; ++f) {
+    const int sidx = D.fanin_sink[f];
+    const PinState in = D.sink_state[sidx];
+    const float ia[2] = {in.at.z, in.at.w};
+    const float is[2] = {in.slew.z, in.slew.w};
+    float giA[2] = {0.0f, 0.0f}, giS[2] = {0.0f, 0.0f}, ga[2] = {0.0f, 0.0f};
+#pragma unroll
+    for (int ri = 0; ri < 2; ++ri) {
+      const AxisPos px = axis_find(tb + lay.xa(), tb + lay.rdx(), D.nx, is[ri]);
+      const float rdx = tb[lay.rdx() + px.i];
+#pragma unroll
+      for (int ro = 0; ro < 2; ++ro) {
+        if (!arc_maps(sense, ri, ro)) continue;
+        float dX, dY;
+        const float dl = bilerp_d(tb + lay.tab(ro), D.ny, px, py, rdx, rdy, dX, dY);
+        const float w = expf((ia[ri] + dl - ato[ro]) / g);
+        const float wa = w * gA[ro];
+        giA[ri] += wa;
+        giS[ri] += wa * dX;
+        gL += wa * dY;
+        ga[ro] += wa;
+        if (win[ro] == (f - f0) * 2 + ri) {
+          float sX, sY;
+          (void)bilerp_d(tb + lay.tab(2 + ro), D.ny, px, py, rdx, rdy, sX, sY);
+          giS[ri] += gS[ro] * sX;
+          gL += gS[ro] * sY;
+        }
+      }
+    }
+    D.g_sink[sidx] = make_float4(giA[0], giA[1], giS[0], giS[1]);
+    D.g_arc[f] = make_float2(ga[0], ga[1]);
+  }
+  D.g_load[x] = gL;
+}
+
+// One chunk of the reverse sweep: each lane owns a driver, sums its sinks'
+// gradients in sink order (d slew_s / d slew_drv = slew_drv / slew_s), records
+// dJ/dd and dJ/dq per sink for the RC adjoint, and then pushes through its own
+// cell to the cell's input sinks.
+__device__ void adj_chunk(const DevDesign &D, const LdsLib &lib, float g_tns, float g_wns, int c) {
+  const int x = D.chunk_start[c] + lane_id();
+  if (x >= D.chunk_start[c + 1]) return;
+  const PinState me = D.drv_state[x];
+  float gA0 = 0.0f, gA1 = 0.0f, gS0 = 0.0f, gS1 = 0.0f;
+  const int e = D.drv_ep[x];
+  if (e >= 0) {
+    const float2 sd = endpoint_seed(D, g_tns, g_wns, e, me.at);
+    gA0 = sd.x;
+    gA1 = sd.y;
+  }
+  for (int s = D.sink_ptr[x]; s < D.sink_ptr[x + 1]; ++s) {
+    const PinState ss = D.sink_state[s];
+    const int cons = D.sink_cons[s];
+    float4 gs;
+    if (cons < 0) {
+      const float2 sd = endpoint_seed(D, g_tns, g_wns, -1 - cons, ss.at);
+      gs = make_float4(sd.x, sd.y, 0.0f, 0.0f);
+    } else {
+      gs = D.g_sink[s];
+    }
+    gA0 += gs.x;
+    gA1 += gs.y;
+    gS0 += gs.z * (me.slew.z / ss.slew.z);
+    gS1 += gs.w * (me.slew.w / ss.slew.w);
+    D.g_dq[s] = make_float2(gs.x + gs.y, gs.z / (2.0f * ss.slew.z) + gs.w / (2.0f * ss.slew.w));
+  }
+  if (x >= D.n_pi) {
+    cell_adjoint(D, lib, x, me, gA0, gA1, gS0, gS1);
+  } else {
+    D.g_load[x] = 0.0f;
+  }
+}
+
+__global__ __launch_bounds__(kSweepBlock) void k_adjoint(DevDesign D, float g_tns, float g_wns, int c0, int c1,
+                                                        int persistent) {
+  extern __shared__ __align__(32) unsigned char smem[];
+  const LdsLib lib = load_lib(D, smem);
+  __syncthreads();
+  if (persistent) {
+    uint32_t *done = D.counters + kCtrLevels;  // reuses the forward counters (reset by the RC adjoint)
+    for (;;) {
+      const int t = take_ticket(D.counters + kCtrFwdTicket);
+      if (t >= D.n_chunks) break;
+      const int c = D.n_chunks - 1 - t;
+      const int lvl = D.chunk_level[c];
+      if (lvl < D.n_cell_levels) wait_count(done + lvl + 1, (uint32_t)D.level_nchunks[lvl + 1]);
+      adj_chunk(D, lib, g_tns, g_wns, c);
+      signal_done(done + lvl);
+    }
+  } else {
+    const int c = c0 + blockIdx.x * (kSweepBlock / kWave) + threadIdx.x / kWave;
+    if (c < c1) adj_chunk(D, lib, g_tns, g_wns, c);
+  }
+}
+
+// ------------------------------------------------------------ RC adjoint
+//
+// dJ/dC_k for every node k of a net, from dJ/dL (the driver's NLDM load), and
+// per sink v dJ/dd_v and dJ/dq_v with q = 2 m2 - d^2.  With R_kj the resistance
+// shared by the root->k and root->j paths, dd_v/dC_k = R_vk and
+// dm2_v/dC_k = R_vk d_k + sum_j C^_j R_vj R_jk, so with the sink-node seeds
+// gd_v = dJ/dd_v - 2 d_v dJ/dq_v and gm_v = 2 dJ/dq_v:
+//   dJ/dC_k = dJ/dL + PA_k + d_k H_k + PB_k,
+//   PA_k = path sum of R Gd, H_k = path sum of R Gm, PB_k = path sum of R K,
+//   Gd, Gm = subtree sums of gd, gm, K = subtree sum of C^ H.
+// (dJ/dq is dropped where the clamp q = max(0, .) is active.)
+
+__device__ void rc_adjoint_wide(const DevDesign &D, const BigNet &B, const WideNets &W, double *s_w) {
+  const int x = B.x, m = B.m;
+  const int k0 = D.rc_ptr[x];
+  const float *R = D.rc_res + k0;
+  const float *Cw = D.rc_cap + k0;
+  const int32_t *end = W.end + B.aux;
+  const float *pc = W.pc + B.aux;
+  const int32_t *nsp = W.nsp + B.nsp;
+  const int32_t *big_nsl = W.nsl;
+  const int32_t *egp = W.egp + B.egp, *egl = W.egl + B.aux;
+  const int s0 = D.sink_ptr[x];
+  const int st = m + 1;
+  double *A = W.scratch + B.scr, *P = A + st, *X = P + st, *Y = X + st, *Z = Y + st;
+  double *G1 = Z + st, *G2 = G1 + st, *T = G2 + st;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  // forward moments: Y = d, Z = m2
+  for (int k = tid; k < m; k += nt) A[k] = (double)Cw[k] + (double)pc[k];
+  __syncthreads();
+  block_scan(A, P, m, true, s_w);
+  for (int k = tid; k < m; k += nt) X[k] = k ? (double)R[k] * (P[end[k]] - P[k]) : 0.0;
+  __syncthreads();
+  euler_terms(X, Y, egp, egl, m);
+  block_scan(Y, Y, m, false, s_w);
+  for (int k = tid; k < m; k += nt) X[k] = A[k] * Y[k];
+  __syncthreads();
+  block_scan(X, P, m, true, s_w);
+  for (int k = tid; k < m; k += nt) X[k] = k ? (double)R[k] * (P[end[k]] - P[k]) : 0.0;
+  __syncthreads();
+  euler_terms(X, Z, egp, egl, m);
+  block_scan(Z, Z, m, false, s_w);
+  // sink-node seeds, sinks of a node in sink order
+  for (int k = tid; k < m; k += nt) {
+    double gd = 0.0, gm = 0.0;
+    for (int i = nsp[k]; i < nsp[k + 1]; ++i) {
+      const float2 g = D.g_dq[s0 + big_nsl[i]];
+      const double gq = (2.0 * Z[k] - Y[k] * Y[k]) > 0.0 ? (double)g.y : 0.0;
+      gd += (double)g.x - 2.0 * Y[k] * gq;
+      gm += 2.0 * gq;
+    }
+    G1[k] = gd;
+    G2[k] = gm;
+  }
+  __syncthreads();
+  block_scan(G1, P, m, true, s_w);                         // Gd = subtree sums
+  for (int k = tid; k < m; k += nt) G1[k] = P[end[k]] - P[k];
+  __syncthreads();
+  block_scan(G2, P, m, true, s_w);                         // Gm
+  for (int k = tid; k < m; k += nt) X[k] = k ? (double)R[k] * (P[end[k]] - P[k]) : 0.0;
+  __syncthreads();
+  euler_terms(X, T, egp, egl, m);                          // H = path sum of R Gm
+  block_scan(T, T, m, false, s_w);
+  for (int k = tid; k < m; k += nt) X[k] = k ? (double)R[k] * G1[k] : 0.0;
+  __syncthreads();
+  euler_terms(X, G1, egp, egl, m);                         // PA = path sum of R Gd
+  block_scan(G1, G1, m, false, s_w);
+  for (int k = tid; k < m; k += nt) X[k] = A[k] * T[k];
+  __syncthreads();
+  block_scan(X, P, m, true, s_w);                          // K = subtree sum of C^ H
+  for (int k = tid; k < m; k += nt) X[k] = k ? (double)R[k] * (P[end[k]] - P[k]) : 0.0;
+  __syncthreads();
+  euler_terms(X, G2, egp, egl, m);                         // PB = path sum of R K
+  block_scan(G2, G2, m, false, s_w);
+  const double gL = (double)D.g_load[x];
+  for (int k = tid; k < m; k += nt) D.g_cap[k0 + k] = (float)(gL + G1[k] + Y[k] * T[k] + G2[k]);
+}
+
+// Same block layout as k_rc.  Small nets: one lane per net in LDS, the forward
+// recursions recomputed, then the two subtree/path rounds.  Block 0 clears the
+// sweep counters (the next update and the next adjoint start from zero).
+__global__ __launch_bounds__(kWideBlock) void k_rc_adjoint_wide(DevDesign D, WideNets W) {
+  __shared__ double s_w[kWideBlock / kWave + 1];
+  rc_adjoint_wide(D, W.big[blockIdx.x], W, s_w);
+}
+
+__global__ __launch_bounds__(kRcBlock) void k_rc_adjoint(DevDesign D, const int2 *chunks, int n_chunks) {
+  __shared__ uint8_t s_par[kRcChunkNodes];
+  __shared__ float s_R[kRcChunkNodes], s_C[kRcChunkNodes], s_A[kRcChunkNodes], s_B[kRcChunkNodes];
+  __shared__ float s_E[kRcChunkNodes], s_F[kRcChunkNodes];
+  __shared__ int s_base[kRcBlock + 1];
+  const int tid = threadIdx.x;
+  const int ci = blockIdx.x;
+  if (ci >= n_chunks) return;
+  const int2 ch = chunks[ci];
+  const int x0 = ch.x, x1 = ch.y;
+  const int k0 = D.rc_ptr[x0], nk = D.rc_ptr[x1] - k0;
+  for (int i = tid; i < nk; i += kRcBlock) {
+    s_par[i] = (uint8_t)D.rc_parent[k0 + i];
+    s_R[i] = D.rc_res[k0 + i];
+    s_C[i] = D.rc_cap[k0 + i];
+  }
+  for (int i = tid; i <= x1 - x0; i += kRcBlock) s_base[i] = D.rc_ptr[x0 + i] - k0;
+  __syncthreads();
+  const int x = x0 + tid;
+  if (x < x1) {
+    const int b = s_base[tid], m = s_base[tid + 1] - b;
+    const uint8_t *par = s_par;
+    float *A = s_A, *B = s_B, *C = s_C, *E = s_E, *F = s_F, *R = s_R;
+    for (int s = D.sink_ptr[x]; s < D.sink_ptr[x + 1]; ++s) C[b + D.sink_node[s]] += D.sink_pincap[s];
+    (void)rc_tree_lds(par, R, C, A, B, b, m);  // A = m2, B = d
+    for (int k = 0; k < m; ++k) E[b + k] = F[b + k] = 0.0f;
+    for (int s = D.sink_ptr[x]; s < D.sink_ptr[x + 1]; ++s) {
+      const int k = b + D.sink_node[s];
+      const float2 g = D.g_dq[s];
+      const float gq = (2.0f * A[k] - B[k] * B[k]) > 0.0f ? g.y : 0.0f;
+      E[k] += g.x - 2.0f * B[k] * gq;
+      F[k] += 2.0f * gq;
+    }
+    for (int k = m - 1; k >= 1; --k) {  // Gd, Gm
+      E[b + par[b + k]] += E[b + k];
+      F[b + par[b + k]] += F[b + k];
+    }
+    A[b] = 0.0f;  // H
+    for (int k = 1; k < m; ++k) A[b + k] = A[b + par[b + k]] + R[b + k] * F[b + k];
+    E[b] = 0.0f;  // PA, in place (parents first)
+    for (int k = 1; k < m; ++k) E[b + k] = E[b + par[b + k]] + R[b + k] * E[b + k];
+    for (int k = 0; k < m; ++k) F[b + k] = C[b + k] * A[b + k];  // K
+    for (int k = m - 1; k >= 1; --k) F[b + par[b + k]] += F[b + k];
+    F[b] = 0.0f;  // PB
+    for (int k = 1; k < m; ++k) F[b + k] = F[b + par[b + k]] + R[b + k] * F[b + k];
+    const float gL = D.g_load[x];
+    for (int k = 0; k < m; ++k) C[b + k] = gL + E[b + k] + B[b + k] * A[b + k] + F[b + k];
+  }
+  __syncthreads();
+  for (int i = tid; i < nk; i += kRcBlock) D.g_cap[k0 + i] = s_C[i];
+}
+
+// Gradients back to caller order: node caps by the node permutation, NLDM
+// loads per cell-output pin (0 elsewhere), arc delays per caller arc (early
+// views 0).
+__global__ void k_scatter_grads(DevDesign D, const int32_t *node_src, int64_t n_nodes, float *grad_cap,
+                                const int32_t *pin_loc, int n_pins, float *grad_load, const int32_t *arc_src,
+                                int n_arcs, float4 *grad_arc) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (grad_cap && i < n_nodes) grad_cap[node_src[i]] = D.g_cap[i];
+  if (grad_load && i < n_pins) {
+    const int loc = pin_loc[i];
+    grad_load[i] = (loc >= D.n_pi) ? D.g_load[loc] : 0.0f;
+  }
+  if (grad_arc && i < n_arcs) {
+    const float2 g = D.g_arc[i];
+    grad_arc[arc_src[i]] = make_float4(0.0f, 0.0f, g.x, g.y);
   }
 }
 
@@ -689,13 +1099,22 @@ int sweep_blocks_per_cu(size_t lds_bytes) {
   return n < 1 ? 1 : n;
 }
 
-hipError_t launch_rc(const DevDesign &D, const int2 *chunks, int n_chunks, const BigNet *big, int n_big,
-                     const int32_t *big_end, const float *big_pc, double *scratch, hipStream_t s) {
+hipError_t launch_rc(const DevDesign &D, const int2 *chunks, int n_chunks, hipStream_t s) {
   const int n_ctr = kCtrLevels + 2 * (D.n_cell_levels + 1);
-  int grid = n_big + n_chunks;
-  if (grid < 1) grid = 1;
-  hipLaunchKernelGGL(k_rc, dim3(grid), dim3(kRcBlock), 0, s, D, chunks, n_chunks, big, n_big, big_end, big_pc,
-                     scratch, D.counters, n_ctr);
+  hipLaunchKernelGGL(k_rc, dim3(n_chunks > 0 ? n_chunks : 1), dim3(kRcBlock), 0, s, D, chunks, n_chunks, D.counters,
+                     n_ctr);
+  return hipGetLastError();
+}
+
+hipError_t launch_rc_wide(const DevDesign &D, const WideNets &W, hipStream_t s) {
+  if (W.n_big <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rc_wide, dim3(W.n_big), dim3(kWideBlock), 0, s, D, W);
+  return hipGetLastError();
+}
+
+hipError_t launch_rc_adjoint_wide(const DevDesign &D, const WideNets &W, hipStream_t s) {
+  if (W.n_big <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rc_adjoint_wide, dim3(W.n_big), dim3(kWideBlock), 0, s, D, W);
   return hipGetLastError();
 }
 
@@ -722,6 +1141,43 @@ hipError_t launch_backward_level(const DevDesign &D, int c0, int c1, hipStream_t
   const int per = kSweepBlock / kWave;
   hipLaunchKernelGGL(k_backward, dim3(blocks_for(c1 - c0, per)), dim3(kSweepBlock), sweep_lds_bytes(D), s,
                      D, c0, c1, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_smooth(const DevDesign &D, double *partials, double *out, uint32_t *keys, int32_t *vals,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_smooth, dim3(kReduceBlocks), dim3(256), 0, s, D, partials, out, keys, vals);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint(const DevDesign &D, float g_tns, float g_wns, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_adjoint, dim3(grid), dim3(kSweepBlock), sweep_lds_bytes(D), s, D, g_tns, g_wns, 0, 0, 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_level(const DevDesign &D, float g_tns, float g_wns, int c0, int c1, hipStream_t s) {
+  if (c1 <= c0) return hipSuccess;
+  const int per = kSweepBlock / kWave;
+  hipLaunchKernelGGL(k_adjoint, dim3(blocks_for(c1 - c0, per)), dim3(kSweepBlock), sweep_lds_bytes(D), s, D,
+                     g_tns, g_wns, c0, c1, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_rc_adjoint(const DevDesign &D, const int2 *chunks, int n_chunks, hipStream_t s) {
+  if (n_chunks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rc_adjoint, dim3(n_chunks), dim3(kRcBlock), 0, s, D, chunks, n_chunks);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_grads(const DevDesign &D, const int32_t *node_src, int64_t n_nodes, float *grad_cap,
+                                const int32_t *pin_loc, int n_pins, float *grad_load, const int32_t *arc_src,
+                                int n_arcs, float4 *grad_arc, hipStream_t s) {
+  int64_t n = n_nodes;
+  if (n_pins > n) n = n_pins;
+  if (n_arcs > n) n = n_arcs;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scatter_grads, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, D, node_src, n_nodes,
+                     grad_cap, pin_loc, n_pins, grad_load, arc_src, n_arcs, grad_arc);
   return hipGetLastError();
 }
 

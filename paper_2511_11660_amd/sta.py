@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libsta.so")
 
 STA_OK, STA_E_ARG, STA_E_CYCLE, STA_E_OOM, STA_E_DEVICE, STA_E_STATE, STA_E_UNSUPPORTED = range(7)
 STA_HOST, STA_DEVICE = 0, 1
-STA_SCHED_PERSISTENT, STA_SCHED_PER_LEVEL = 0, 1
+STA_SCHED_PERSISTENT, STA_SCHED_PER_LEVEL, STA_SCHED_GRAPH = 0, 1, 2
 
 _P32 = ctypes.POINTER(ctypes.c_int32)
 _P64 = ctypes.POINTER(ctypes.c_int64)
@@ -87,19 +87,40 @@ _SIGS = [
     ("sta_report_endpoints", ctypes.c_int, [_VP, _VP, ctypes.c_int, _VP]),
     ("sta_get_info", ctypes.c_int, [_VP, ctypes.POINTER(sta_info)]),
     ("sta_get_phase_times", ctypes.c_int, [_VP, _PF, _P32]),
+    ("sta_backward", ctypes.c_int, [_VP, ctypes.c_float, ctypes.c_float, _VP, _VP, _VP, ctypes.c_int, _VP]),
     ("sta_status_string", ctypes.c_char_p, [ctypes.c_int]),
     ("sta_last_error", ctypes.c_char_p, []),
 ]
 
 _lib = None
+_hip = None
+
+
+def hip_runtime_path() -> str:
+    """The HIP runtime this process uses: torch's bundled copy when torch is
+    importable (so device pointers, streams and the device state are shared
+    with torch), else the system ROCm runtime."""
+    try:
+        import torch
+        p = os.path.join(os.path.dirname(torch.__file__), "lib", "libamdhip64.so")
+        if os.path.exists(p):
+            return p
+    except ImportError:
+        pass
+    for p in ("/opt/rocm/lib/libamdhip64.so.7", "/opt/rocm/lib/libamdhip64.so"):
+        if os.path.exists(p):
+            return p
+    raise RuntimeError("no HIP runtime found")
 
 
 def load() -> ctypes.CDLL:
-    """Loads libsta.so (raises if it is not built)."""
-    global _lib
+    """Loads libsta.so (raises if it is not built).  The HIP runtime is loaded
+    first into the global symbol scope; libsta.so binds to it."""
+    global _lib, _hip
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        _hip = ctypes.CDLL(hip_runtime_path(), mode=ctypes.RTLD_GLOBAL)
         lib = ctypes.CDLL(LIB_PATH)
         for name, res, args in _SIGS:
             f = getattr(lib, name)
@@ -221,7 +242,13 @@ def sta_get_phase_times(ctx: int) -> np.ndarray:
     return np.array(list(ms)[: n.value], dtype=np.float64)
 
 
-PHASES = ("rc_small", "rc_big", "forward", "backward", "reduce", "sort")
+def sta_backward(ctx: int, g_tns: float, g_wns: float, grad_wire_cap=None, grad_pin_load=None,
+                 grad_arc_delay=None, dst: int = STA_HOST, stream=None) -> None:
+    _check(load().sta_backward(ctx, float(g_tns), float(g_wns), _addr(grad_wire_cap),
+                               _addr(grad_pin_load), _addr(grad_arc_delay), dst, _stream(stream)))
+
+
+PHASES = ("rc_small", "rc_big", "forward", "backward", "reduce", "sort", "adjoint_sweep", "adjoint_rc")
 
 
 # ------------------------------------------------------------------ owner
@@ -264,6 +291,7 @@ class STA:
         self.ctx = sta_create(g, rc, lib, cons, o)
         self.info = sta_get_info(self.ctx)
         self.opts = o
+        self._n_arcs = int(design.cell_in_ptr[-1])
 
     def close(self):
         if getattr(self, "ctx", None):
@@ -287,7 +315,7 @@ class STA:
         n = self.info.n_pins
         at, slew, rat = (np.zeros((n, 4), np.float32) for _ in range(3))
         crit = np.zeros((n, 4), np.int8)
-        sta_report_timing(self.ctx, at, slew, rat, crit)
+        sta_report_timing(self.ctx, at, slew, rat if self.opts.mode == 0 else None, crit)
         return {"at": at, "slew": slew, "rat": rat, "crit": crit}
 
     def slack(self):
@@ -295,7 +323,8 @@ class STA:
         ps = np.zeros((n, 4), np.float32)
         es = np.zeros((max(ne, 1), 2), np.float32)
         eo = np.zeros((2, max(ne, 1)), np.int32)
-        wns, tns = sta_report_slack(self.ctx, ps, es, eo if self.opts.sort_endpoints else None)
+        wns, tns = sta_report_slack(self.ctx, ps if self.opts.mode == 0 else None, es,
+                                    eo if self.opts.sort_endpoints else None)
         return {"slack": ps, "ep_slack": es[:ne], "ep_order": eo[:, :ne], "wns": wns, "tns": tns}
 
     def levels(self):
@@ -318,3 +347,54 @@ class STA:
 
     def phase_times(self):
         return sta_get_phase_times(self.ctx)
+
+    def backward(self, g_tns=1.0, g_wns=0.0):
+        """Host gradients of g_tns*TNS_g + g_wns*WNS_g (smooth mode)."""
+        gc = np.zeros(int(self.info.n_nodes), np.float32)
+        gl = np.zeros(self.info.n_pins, np.float32)
+        n_arcs = self._n_arcs
+        ga = np.zeros((max(n_arcs, 1), 4), np.float32)
+        sta_backward(self.ctx, g_tns, g_wns, gc, gl, ga)
+        return {"grad_wire_cap": gc, "grad_pin_load": gl, "grad_arc_delay": ga[:n_arcs]}
+
+
+def _smooth_function():
+    import torch
+
+    class SmoothTiming(torch.autograd.Function):
+        """(TNS_g, WNS_g) of the late views as a differentiable function of the RC
+        node caps (caller node order, a float32 cuda tensor).  forward: caps ->
+        sta_set_wire_caps + sta_update_timing on the current stream; backward:
+        sta_backward writes d/d(caps) straight into a torch-owned buffer."""
+
+        @staticmethod
+        def forward(ctx, caps, timer):
+            stream = torch.cuda.current_stream()
+            caps = caps.contiguous()
+            sta_set_wire_caps(timer.ctx, caps, STA_DEVICE, stream)
+            sta_update_timing(timer.ctx, stream)
+            wns, tns = sta_report_slack(timer.ctx, None, None, None, STA_HOST, stream)
+            ctx.timer = timer
+            ctx.n = caps.numel()
+            return torch.tensor([tns[1], wns[1]], dtype=torch.float64, device=caps.device)
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            g = grad_out.detach().cpu()
+            grad = torch.empty(ctx.n, dtype=torch.float32, device=grad_out.device)
+            sta_backward(ctx.timer.ctx, float(g[0]), float(g[1]), grad, None, None, STA_DEVICE,
+                         torch.cuda.current_stream())
+            return grad, None
+
+    return SmoothTiming
+
+
+_SMOOTH = None
+
+
+def smooth_timing(caps, timer):
+    """Differentiable (TNS_g, WNS_g) of a smooth-mode STA context wrt node caps."""
+    global _SMOOTH
+    if _SMOOTH is None:
+        _SMOOTH = _smooth_function()
+    return _SMOOTH.apply(caps, timer)

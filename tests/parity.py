@@ -1,9 +1,11 @@
 """Element-wise comparison of the HIP path against the FP64 oracle.
 
 Tolerance (FP32 GPU vs FP64 oracle): |g - o| <= max(1e-3 ps, 1e-5 S) where S
-is the magnitude the value is computed from.  Slew: S = |o|.  Arrival: the
-largest finite |AT| on the pin's fanin cone (for non-negative arrivals this is
-|AT| itself).  Required time is a chain of subtractions from the endpoint
+is the magnitude the value is computed from.  Arrival and slew: the largest
+finite |AT| (resp. |slew|) on the pin's fanin cone; for non-negative arrivals
+this is |AT| itself, and a slew extrapolated from a huge input slew (an
+unbuffered 9k-sink net gives 86 ns, 580x past the table) carries the FP32
+rounding of that input.  Required time is a chain of subtractions from the endpoint
 required times down to the pin, so S is the largest finite |RAT| on the pin's
 fanout cone: a RAT near zero derived from a 4500 ps endpoint carries FP32
 rounding of 4500 ps operands.  Slack: the larger of the two.  Scales are per
@@ -120,7 +122,8 @@ def _segmax(vals, members, starts, ends):
 
 
 def magnitude_scales(d, r):
-    """(fanin-cone max |AT|, fanout-cone max |RAT|) per pin and early/late."""
+    """(fanin-cone max |AT|, fanout-cone max |RAT|, fanin-cone max |slew|) per
+    pin and early/late."""
     NP = d.n_pins
     order, bounds = _levels(r)
     cin_out = np.full(NP, -1, np.int64)
@@ -134,15 +137,18 @@ def magnitude_scales(d, r):
     cell_of_out[d.cell_out_pin] = np.arange(d.n_cells)
     U = _absfin(r["at"])
     M = _absfin(r["rat"])
+    S = _absfin(r["slew"])
     nl = len(bounds) - 1
     for lv in range(nl):  # fanin cone, ascending levels
         pins = order[bounds[lv]:bounds[lv + 1]]
         sk = pins[drv_of_sink[pins] >= 0]
         U[sk] = np.maximum(U[sk], U[drv_of_sink[sk]])
+        S[sk] = np.maximum(S[sk], S[drv_of_sink[sk]])
         co = pins[cell_of_out[pins] >= 0]
         if len(co):
             c = cell_of_out[co]
             U[co] = np.maximum(U[co], _segmax(U, d.cell_in_pin, d.cell_in_ptr[c], d.cell_in_ptr[c + 1]))
+            S[co] = np.maximum(S[co], _segmax(S, d.cell_in_pin, d.cell_in_ptr[c], d.cell_in_ptr[c + 1]))
     for lv in range(nl - 1, -1, -1):  # fanout cone, descending levels
         pins = order[bounds[lv]:bounds[lv + 1]]
         ci = pins[cin_out[pins] >= 0]
@@ -154,7 +160,7 @@ def magnitude_scales(d, r):
             ne = b > a
             if ne.any():
                 M[dr[ne]] = np.maximum(M[dr[ne]], _segmax(M, d.net_sink_pin, a[ne], b[ne]))
-    return U, M
+    return U, M, S
 
 
 def _view_scale(S):
@@ -182,10 +188,10 @@ def compare_full(d, r, gpu, *, check_order=True):
     qerr = np.abs(q - r["q_sink"])
     assert (qerr <= qt).all(), f"sink spread outside tolerance at {np.argwhere(qerr > qt)[:5].ravel().tolist()}"
     t = gpu["timing"]
-    U, M = magnitude_scales(d, r)
+    U, M, S = magnitude_scales(d, r)
     Uv, Mv = _view_scale(U), _view_scale(M)
     stats["at"] = check_close("AT", t["at"], r["at"], Uv)
-    stats["slew"] = check_close("slew", t["slew"], r["slew"])
+    stats["slew"] = check_close("slew", t["slew"], r["slew"], _view_scale(S))
     stats["rat"] = check_close("RAT", t["rat"], r["rat"], Mv)
     s = gpu["slack"]
     scale = np.maximum(Uv, Mv)

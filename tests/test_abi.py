@@ -27,6 +27,7 @@ def test_exports_every_declared_function():
     hdr = open(os.path.join(ROOT, "include", "sta.h")).read()
     declared = set(re.findall(r"\b(sta_[a-z_]+)\s*\(", hdr))
     assert "sta_create" in declared and "sta_update_timing" in declared
+    S.load()  # brings in the process's HIP runtime first
     lib = ctypes.CDLL(S.LIB_PATH)
     missing = [f for f in sorted(declared) if not hasattr(lib, f)]
     assert not missing, missing
@@ -106,9 +107,11 @@ def test_rejects_wrong_input_count_for_type():
     assert "inputs" in _expect(d, S.STA_E_ARG)
 
 
-def test_rejects_unsupported_mode_and_sizes():
+def test_rejects_bad_mode_gamma_and_sizes():
     d = _tiny()
-    _expect(d, S.STA_E_UNSUPPORTED, mode=1)
+    _expect(d, S.STA_E_ARG, mode=5)
+    _expect(d, S.STA_E_ARG, mode=1, gamma_ps=0.0)
+    _expect(d, S.STA_E_ARG, mode=1, gamma_ps=float("nan"))
     _expect(d, S.STA_E_ARG, sched=7)
     d2 = _tiny()
     d2.nx = 9
@@ -141,4 +144,7 @@ def test_valid_design_without_device_reports_device_error():
 def test_null_context_calls_are_state_errors():
     with pytest.raises(S.StaError) as e:
         S.sta_update_timing(0)
+    assert e.value.status == S.STA_E_STATE
+    with pytest.raises(S.StaError) as e:
+        S.sta_backward(0, 1.0, 0.0)
     assert e.value.status == S.STA_E_STATE

@@ -1,0 +1,95 @@
+"""GPU parity of the differentiable (smooth) form: the smooth forward and the
+hand-written adjoint through the C ABI against the FP64 oracle's smooth
+forward and adjoint, plus the torch.autograd.Function wrapper."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2511_11660_amd import synth
+from paper_2511_11660_amd.sta import STA, STA_SCHED_PER_LEVEL, STA_SCHED_PERSISTENT
+
+pytestmark = pytest.mark.gpu
+GAMMA = 5.0
+
+
+def _close(name, g, o, rel, abs_):
+    g = np.asarray(g, np.float64)
+    o = np.asarray(o, np.float64)
+    err = np.abs(g - o)
+    tol = rel * np.abs(o) + abs_
+    bad = err > tol
+    assert not bad.any(), (f"{name}: {int(bad.sum())}/{g.size} outside; worst at "
+                           f"{int(np.argmax(err - tol))}: gpu {g.ravel()[np.argmax(err - tol)]} "
+                           f"oracle {o.ravel()[np.argmax(err - tol)]}")
+
+
+def _grad_scale(o):
+    """Absolute floor for a gradient array: FP32 accumulation over many terms."""
+    return 1e-5 * max(1.0, float(np.abs(o).max()))
+
+
+@pytest.mark.parametrize("sched", [STA_SCHED_PERSISTENT, STA_SCHED_PER_LEVEL])
+@pytest.mark.parametrize("cfg", ["tiny", "mid"])
+def test_smooth_forward_and_adjoint(cfg, sched):
+    d = synth.generate(synth.tiny_config(seed=8, dangling_policy=1) if cfg == "tiny" else
+                       synth.mid_config(n_cells=40_000, n_levels=30, seed=14))
+    print(f"[smooth] {cfg} pins={d.n_pins} sched={sched}", flush=True)
+    s = STA(d, mode=1, gamma_ps=GAMMA, sched=sched, big_net_nodes=40 if cfg == "tiny" else 0)
+    s.update()
+    t = s.timing()
+    sl = s.slack()
+    o = oracle.smooth_adjoint(d, GAMMA, 0.6, 0.4)
+    # smooth arrivals: same tolerance rule as the hard path (fanin-cone |AT|)
+    fin = np.isfinite(o["at"])
+    scale = np.maximum.accumulate(np.abs(np.where(fin, o["at"], 0)).max(1))  # loose per-pin floor
+    tol = np.maximum(1e-3, 1e-5 * np.abs(o["at"]).max())
+    assert np.abs(t["at"][fin] - o["at"][fin]).max() <= tol
+    assert sl["tns"][1] == pytest.approx(o["tns"], rel=1e-5, abs=1e-2)
+    assert sl["wns"][1] == pytest.approx(o["wns"], rel=1e-5, abs=1e-2)
+    g = s.backward(0.6, 0.4)
+    s.close()
+    for name in ("grad_wire_cap", "grad_pin_load", "grad_arc_delay"):
+        _close(name, g[name], o[name], 1e-3, _grad_scale(o[name]))
+
+
+def test_adjoint_is_deterministic():
+    d = synth.generate(synth.mid_config(n_cells=20_000, n_levels=25, seed=15))
+    s = STA(d, mode=1, gamma_ps=GAMMA)
+    s.update()
+    a = s.backward(1.0, 0.0)
+    s.update()
+    b = s.backward(1.0, 0.0)
+    s.close()
+    for k in a:
+        np.testing.assert_array_equal(a[k], b[k])
+
+
+def test_autograd_function_matches_oracle_gradient():
+    import torch
+    from paper_2511_11660_amd.sta import smooth_timing
+    d = synth.generate(synth.mid_config(n_cells=10_000, n_levels=20, seed=16))
+    s = STA(d, mode=1, gamma_ps=GAMMA)
+    caps = torch.from_numpy(d.cap_ff.copy()).cuda().requires_grad_(True)
+    out = smooth_timing(caps, s)
+    loss = 0.3 * out[0] + 0.7 * out[1]
+    loss.backward()
+    o = oracle.smooth_adjoint(d, GAMMA, 0.3, 0.7)
+    assert float(out[0]) == pytest.approx(o["tns"], rel=1e-5, abs=1e-2)
+    _close("autograd grad", caps.grad.cpu().numpy(), o["grad_wire_cap"], 1e-3, _grad_scale(o["grad_wire_cap"]))
+    s.close()
+
+
+@pytest.mark.slow
+def test_smooth_1m_pins_adjoint():
+    """The 1M-pin design (differentiable configuration): GPU adjoint against the
+    FP64 oracle adjoint on every node, pin and arc."""
+    d = synth.generate(synth.mid_config())
+    s = STA(d, mode=1, gamma_ps=GAMMA)
+    s.update()
+    sl = s.slack()
+    g = s.backward(1.0, 0.0)
+    s.close()
+    o = oracle.smooth_adjoint(d, GAMMA, 1.0, 0.0)
+    assert sl["tns"][1] == pytest.approx(o["tns"], rel=1e-5)
+    for name in ("grad_wire_cap", "grad_pin_load", "grad_arc_delay"):
+        _close(name, g[name], o[name], 1e-3, _grad_scale(o[name]))
