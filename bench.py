@@ -1,12 +1,16 @@
 """Timing-graph pins/s of one full static-timing update (RC pass, forward
 AT/slew sweep, backward RAT/slack sweep, WNS/TNS, endpoint order) on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--workload 10M|1M|tiny]
+    python bench.py [--steps K] [--warmup W] [--workload 10M|1M|tiny] [--sched auto|0|1|2]
 
 Prints ONE JSON line.  A step is one sta_update_timing over the whole design
 with every input resident in HBM.  `roofline` prices the dominant kernel's
 algorithmic bytes (each array element moved once per update) against 8 TB/s;
 `cpu_baseline` times the FP64 oracle single-threaded on the same design.
+Two side measurements ride along: `adjoint` (smooth-mode reverse pass time
+over smooth forward time on the 1M-pin design) and `batched` (256 uneven
+designs timed as one batch against the sum of the same designs timed one
+after another on one stream, each context tuned for itself).
 """
 from __future__ import annotations
 
@@ -67,6 +71,83 @@ def cpu_baseline(design, n_pins: int) -> dict:
                       f"{dt:.2f} s"}
 
 
+def _time_updates(ctxs, stream, steps):
+    """Mean ms of `steps` rounds of one update on each context in ctxs,
+    back to back on one stream."""
+    import torch
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(steps):
+        for c in ctxs:
+            c.update(stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / steps
+
+
+def adjoint_ratio(steps: int) -> dict:
+    """Smooth-mode update (LSE arrival merges, smooth TNS/WNS) and its reverse
+    pass (sta_backward into device gradient buffers) on the 1M-pin design."""
+    import torch
+    from paper_2511_11660_amd import synth
+    from paper_2511_11660_amd.sta import STA
+    d = synth.generate(synth.mid_config())
+    s = STA(d, mode=1, gamma_ps=5.0, sort_endpoints=0, device=0)
+    r = s.autotune(reps=3)
+    stream = torch.cuda.current_stream()
+    gc = torch.empty(int(d.n_nodes), dtype=torch.float32, device="cuda")
+    gl = torch.empty(d.n_pins, dtype=torch.float32, device="cuda")
+    ga = torch.empty((int(d.cell_in_ptr[-1]), 4), dtype=torch.float32, device="cuda")
+    from paper_2511_11660_amd.sta import STA_DEVICE, sta_backward
+    for _ in range(3):
+        s.update(stream)
+        sta_backward(s.ctx, 1.0, 0.0, gc, gl, ga, STA_DEVICE, stream)
+    t_fwd = _time_updates([s], stream, steps)
+    s.update(stream)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(steps):
+        sta_backward(s.ctx, 1.0, 0.0, gc, gl, ga, STA_DEVICE, stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t_bwd = ev0.elapsed_time(ev1) / steps
+    s.close()
+    return {"workload": "1M-pin synthetic design, smooth mode gamma 5 ps", "pins": d.n_pins,
+            "schedule": _SCHED_NAMES[r.sched], "forward_ms": t_fwd, "backward_ms": t_bwd,
+            "ratio": t_bwd / t_fwd}
+
+
+def batched_vs_per_design(steps: int, n_designs: int) -> dict:
+    import torch
+    from paper_2511_11660_amd import synth
+    from paper_2511_11660_amd.sta import STA
+    designs = [synth.generate(c) for c in synth.batch_configs(n_designs)]
+    pins = sum(d.n_pins for d in designs)
+    print(f"[bench] batch: {n_designs} designs, {pins} pins", file=sys.stderr, flush=True)
+    stream = torch.cuda.current_stream()
+    b = STA(designs, device=0)
+    rb = b.autotune(reps=3)
+    t_batch = _time_updates([b], stream, steps)
+    b.close()
+    singles = []
+    for d in designs:
+        s = STA(d, device=0)
+        s.autotune(reps=1)
+        singles.append(s)
+    t_seq = _time_updates(singles, stream, max(1, steps // 4))
+    for s in singles:
+        s.close()
+    return {"workload": f"{n_designs} uneven synthetic designs (1k-200k cells, 10-80 levels), shared library",
+            "designs": n_designs, "pins": pins, "schedule": _SCHED_NAMES[rb.sched],
+            "batched_ms": t_batch, "per_design_sum_ms": t_seq, "speedup": t_seq / t_batch,
+            "batched_pins_per_s": pins / (t_batch * 1e-3)}
+
+
+_SCHED_NAMES = {0: "persistent", 1: "per-level", 2: "graph"}
+
+
 def copy_calibration(mib: int, reps: int) -> int:
     """A plain device copy of known size, so HBM counters (FETCH_SIZE,
     WRITE_SIZE) can be scaled: each launch reads and writes mib MiB."""
@@ -92,8 +173,11 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="10M", choices=["10M", "1M", "tiny"])
-    ap.add_argument("--sched", type=int, default=0, help="0 persistent, 1 one launch per level")
+    ap.add_argument("--sched", default="auto",
+                    help="auto (tuned at setup), 0 persistent, 1 one launch per level, 2 HIP graph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-side", action="store_true", help="skip the adjoint and batched side measurements")
+    ap.add_argument("--batch-designs", type=int, default=256)
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -117,12 +201,18 @@ def main() -> int:
     t_gen = time.perf_counter() - t0
     print(f"[bench] generated {design.n_pins} pins in {t_gen:.1f}s", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    s = STA(design, sched=args.sched, profile=1, device=0)
+    s = STA(design, sched=0 if args.sched == "auto" else int(args.sched), device=0)
     t_create = time.perf_counter() - t0
     info = s.info
     print(f"[bench] created context in {t_create:.1f}s: {info.n_cell_levels} cell levels, "
           f"{info.n_endpoints} endpoints, {info.n_big_nets} big nets", file=sys.stderr, flush=True)
     stream = torch.cuda.current_stream()
+    tuned = None
+    if args.sched == "auto":
+        tuned = s.autotune(reps=5, stream=stream)
+        print(f"[bench] autotune: {_SCHED_NAMES[tuned.sched]} grid {tuned.sweep_blocks} "
+              f"({tuned.ms:.3f} ms, {tuned.n_tried} candidates)", file=sys.stderr, flush=True)
+    sched, s_blocks = s.opts.sched, s.opts.sweep_blocks
     for _ in range(args.warmup):
         s.update(stream)
     torch.cuda.synchronize()
@@ -138,14 +228,20 @@ def main() -> int:
     ms = ev0.elapsed_time(ev1) / args.steps
     print(f"[bench] {ms:.3f} ms per update", file=sys.stderr, flush=True)
 
-    # per-kernel durations: the library's HIP events on the same stream
-    phase = np.zeros(len(PHASES))
-    for _ in range(args.steps):
-        s.update(stream)
-        phase += s.phase_times()
-    phase /= args.steps
     wns_tns = s.slack()
     s.close()
+    # per-kernel durations: the library's HIP events on the same stream (a
+    # graph replay is not separable into phases, so its kernels are timed in
+    # the per-level launch sequence the graph holds)
+    prof = STA(design, sched=1 if sched == 2 else sched, sweep_blocks=s_blocks, profile=1, device=0)
+    for _ in range(args.warmup):
+        prof.update(stream)
+    phase = np.zeros(len(PHASES))
+    for _ in range(args.steps):
+        prof.update(stream)
+        phase += prof.phase_times()
+    phase /= args.steps
+    prof.close()
 
     n_arcs = int(design.cell_in_ptr[-1])
     ab = algorithmic_bytes(info, n_arcs)
@@ -170,7 +266,7 @@ def main() -> int:
         "config": {"workload": f"{args.workload}-pin synthetic STA design", "pins": info.n_pins,
                    "cells": info.n_cells, "nets": info.n_nets, "rc_nodes": int(info.n_nodes),
                    "cell_levels": info.n_cell_levels, "endpoints": info.n_endpoints,
-                   "views": 4, "schedule": "persistent" if args.sched == 0 else "per-level"},
+                   "views": 4, "schedule": _SCHED_NAMES[sched]},
         "hbm_frac_whole_update": ab["total"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "phase_ms": {k: float(v) for k, v in zip(PHASES, phase)},
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
@@ -179,6 +275,11 @@ def main() -> int:
         "wns_ps": [float(x) for x in wns_tns["wns"]],
         "tns_ps": [float(x) for x in wns_tns["tns"]],
     }
+    if not args.no_side:
+        print("[bench] adjoint ratio (1M-pin smooth)", file=sys.stderr, flush=True)
+        out["adjoint"] = adjoint_ratio(args.steps)
+        print("[bench] batched vs per-design", file=sys.stderr, flush=True)
+        out["batched"] = batched_vs_per_design(args.steps, args.batch_designs)
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(design, info.n_pins)

@@ -131,6 +131,8 @@ typedef struct {
   int32_t sort_endpoints;      /* 1: sta_update_timing also orders endpoints by slack */
   int32_t profile;             /* 1: record per-kernel HIP event times in sta_update_timing */
   int32_t device;              /* HIP device ordinal; -1 = current device */
+  int32_t sweep_blocks;        /* persistent sweep grid (blocks of 256 threads); 0 = every block slot
+                                  the device can hold resident (any value >= 1 is deadlock-free) */
 } sta_options;
 
 typedef struct {
@@ -240,6 +242,58 @@ sta_status sta_get_phase_times(sta_ctx *ctx, float *ms, int32_t *n);
  * STA_E_STATE if the context is not in mode 1 or was never updated. */
 sta_status sta_backward(sta_ctx *ctx, float g_tns, float g_wns, float *grad_wire_cap, float *grad_pin_load,
                         float *grad_arc_delay, sta_mem dst, void *stream);
+
+/* Batched form (not in the paper; the paper's flows time one design per call).
+ * Times n_designs independent designs that share one cell library (one
+ * technology) as a single timing graph: their netlists, RC trees and
+ * constraints are concatenated in design order (design d's pins, cells, nets,
+ * RC nodes, PIs and POs follow design d-1's), the union is levelized (design
+ * levels line up: level l of the union holds every design's level-l cells),
+ * and every sta_update_timing then runs each sweep over all designs at once
+ * (one persistent launch per sweep, or one HIP graph replay with
+ * STA_SCHED_GRAPH).  graphs, rcs and cons are arrays of n_designs
+ * descriptors, each validated as sta_create would (errors name the design);
+ * lib is the one shared library.  Per-pin results are bit-identical to timing
+ * each design alone.  The union must stay within the single-context limits
+ * (int32 pin, sink and node counts), else STA_E_UNSUPPORTED; batches time hard
+ * mode only (opts->mode must be 0, else STA_E_UNSUPPORTED).
+ *
+ * On a batched context the per-pin reports of sta_report_timing / _slack /
+ * _levels / _rc / _endpoints and sta_set_wire_caps use the concatenated
+ * orders; sta_report_slack's wns/tns aggregate the designs (min of WNS, sum of
+ * TNS in design order) and its ep_order holds, in each design's endpoint range,
+ * design-local endpoint indices by ascending (slack, pin id). */
+sta_status sta_batch_create(int32_t n_designs, const sta_graph_desc *graphs, const sta_rc_desc *rcs,
+                            const sta_lib_desc *lib, const sta_constraints *cons, const sta_options *opts,
+                            sta_ctx **out);
+
+/* Concatenation offsets of a batched context, host arrays of n_designs + 1
+ * entries each (any may be NULL): pin_off, ep_off (endpoint index ranges),
+ * node_off (RC node ranges).  *n_designs receives the design count (1 and the
+ * whole design for a context from sta_create). */
+sta_status sta_batch_offsets(const sta_ctx *ctx, int32_t *n_designs, int32_t *pin_off, int32_t *ep_off,
+                             int64_t *node_off);
+
+/* Per-design results of the last update, host doubles [n_designs][2] each
+ * (early, late), any may be NULL: WNS = min(0, min endpoint slack) and TNS =
+ * sum of min(0, slack) over the design's endpoints, reduced with the same
+ * partition and order as a single-design context (bit-identical to timing the
+ * design alone).  Synchronizes `stream`.  STA_E_STATE before an update. */
+sta_status sta_batch_report(sta_ctx *ctx, double *wns, double *tns, void *stream);
+
+/* Launch-configuration tuner.  Times `reps` updates (after one warm-up) on
+ * `stream` for each candidate schedule: the persistent sweeps at every grid
+ * size from 1 block per compute unit up to the occupancy limit, one launch per
+ * level, and the captured HIP graph; keeps the fastest in the context (later
+ * updates use it) and reports it.  Results of the tuning updates are those of
+ * a normal update.  Synchronizes `stream`. */
+typedef struct {
+  int32_t sched;               /* sta_sched chosen */
+  int32_t sweep_blocks;        /* persistent grid (blocks of 256 threads) */
+  float ms;                    /* mean update time of the choice */
+  int32_t n_tried;             /* candidates timed */
+} sta_tune_result;
+sta_status sta_autotune(sta_ctx *ctx, int32_t reps, sta_tune_result *best, void *stream);
 
 /* Name of a status code; message of the calling thread's last error. */
 const char *sta_status_string(sta_status s);

@@ -127,6 +127,16 @@ struct sta_ctx {
   bool bwd_timed = false;
   bool events = false, timed = false;
   hipStream_t last_stream = nullptr;
+  std::vector<int32_t> h_ep_pin;       // endpoint pins (host copy)
+  // batched contexts: concatenation offsets and per-design reduction buffers
+  int n_designs = 1;
+  bool batched = false;
+  std::vector<int32_t> pin_off, ep_off;
+  std::vector<int64_t> node_off;
+  int32_t *d_ep_off = nullptr;
+  double *b_partials = nullptr, *b_out = nullptr;
+  uint64_t *keys64 = nullptr, *keys64_out = nullptr;
+  int key_bits = 32;
 
   template <class T>
   sta_status alloc(T **out_p, size_t n) {
@@ -169,6 +179,7 @@ void sta_options_default(sta_options *o) {
   o->sort_endpoints = 1;
   o->profile = 0;
   o->device = -1;
+  o->sweep_blocks = 0;
 }
 
 const char *sta_status_string(sta_status s) {
@@ -203,6 +214,9 @@ struct Inputs {
   HostArr<float> res, cap;
   // derived pin maps
   std::vector<int32_t> cell_of_pin, net_of_drv, sink_idx_of_pin, drv_of_sink_pin, rank;
+  // batches: design pin offsets and each design's dangling-endpoint RAT [4]
+  const std::vector<int32_t> *pin_off = nullptr;
+  const std::vector<float> *dang = nullptr;
 };
 
 sta_status load_graph(Inputs &I) {
@@ -513,11 +527,16 @@ static sta_status build_layout(sta_ctx *C, const Inputs &I, const std::vector<in
       const float *r = cons.po_rat + 4 * (size_t)I.rank[p];
       ep_rat.push_back(make_float4(r[0], r[1], r[2], r[3]));
     } else {
-      ep_rat.push_back(make_float4(cons.dangling_rat[0], cons.dangling_rat[1], cons.dangling_rat[2],
-                                   cons.dangling_rat[3]));
+      const float *r = cons.dangling_rat;
+      if (I.dang) {
+        const size_t dsg = std::upper_bound(I.pin_off->begin(), I.pin_off->end(), p) - I.pin_off->begin() - 1;
+        r = I.dang->data() + 4 * dsg;
+      }
+      ep_rat.push_back(make_float4(r[0], r[1], r[2], r[3]));
     }
   }
   C->n_ep = (int)ep_pin.size();
+  C->h_ep_pin = ep_pin;
 
   // nets in slot order, sinks net-major, RC nodes net-major
   std::vector<int32_t> sink_ptr(ND + 1, 0), rc_ptr(ND + 1, 0), net_slot(g.n_nets);
@@ -695,7 +714,7 @@ static sta_status build_layout(sta_ctx *C, const Inputs &I, const std::vector<in
   // packed library
   const TabLayout lay{lib.nx, lib.ny};
   const int ts = lay.stride();
-  std::vector<float> tab((size_t)lib.n_types * ts);
+  std::vector<float> tab(((size_t)lib.n_types * ts + 3) & ~(size_t)3, 0.0f);  // padded for 16-byte staging loads
   for (int t = 0; t < lib.n_types; ++t) {
     float *o = tab.data() + (size_t)t * ts;
     const float *xa = lib.slew_axis + t * lib.nx, *ya = lib.load_axis + t * lib.ny;
@@ -814,6 +833,7 @@ static sta_status build_layout(sta_ctx *C, const Inputs &I, const std::vector<in
   if (lds > 160 * 1024) return fail(STA_E_UNSUPPORTED, "library too large for LDS (%zu bytes)", lds);
   C->sweep_grid = sweep_blocks_per_cu(lds) * C->n_cu;
   if (C->sweep_grid < 1) C->sweep_grid = 1;
+  if (C->opt.sweep_blocks > 0) C->sweep_grid = C->opt.sweep_blocks;
   return STA_OK;
 }
 
@@ -824,12 +844,7 @@ static sta_status deliver(void *dst, const void *src, size_t bytes, sta_mem m, h
   return STA_OK;
 }
 
-extern "C" sta_status sta_create(const sta_graph_desc *graph, const sta_rc_desc *rc, const sta_lib_desc *lib,
-                                 const sta_constraints *cons, const sta_options *opts, sta_ctx **out) {
-  if (!graph || !rc || !lib || !cons || !out) return fail(STA_E_ARG, "NULL descriptor");
-  sta_options o;
-  sta_options_default(&o);
-  if (opts) o = *opts;
+static sta_status check_options(const sta_options &o) {
   if (o.mode != 0 && o.mode != 1) return fail(STA_E_ARG, "mode must be 0 (hard) or 1 (smooth)");
   if (o.mode == 1 && !(o.gamma_ps > 0.0f && std::isfinite(o.gamma_ps)))
     return fail(STA_E_ARG, "smooth mode needs a finite gamma_ps > 0");
@@ -837,6 +852,48 @@ extern "C" sta_status sta_create(const sta_graph_desc *graph, const sta_rc_desc 
     return fail(STA_E_ARG, "bad sched");
   if (o.big_net_nodes < 0) return fail(STA_E_ARG, "big_net_nodes < 0");
   if (o.dangling_policy != 0 && o.dangling_policy != 1) return fail(STA_E_ARG, "bad dangling_policy");
+  if (o.sweep_blocks < 0) return fail(STA_E_ARG, "sweep_blocks < 0");
+  return STA_OK;
+}
+
+static sta_status init_device(sta_ctx *C) {
+  int ndev = 0;
+  HIP_TRY(hipGetDeviceCount(&ndev));
+  if (ndev < 1) return fail(STA_E_DEVICE, "no HIP device");
+  if (C->opt.device >= 0) {
+    if (C->opt.device >= ndev) return fail(STA_E_ARG, "device %d of %d", C->opt.device, ndev);
+    HIP_TRY(hipSetDevice(C->opt.device));
+  }
+  HIP_TRY(hipGetDevice(&C->device));
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, C->device));
+  C->n_cu = prop.multiProcessorCount;
+  return STA_OK;
+}
+
+// Levelizes the validated inputs and builds the device layout.
+static sta_status build_context(sta_ctx *C, const Inputs &I) {
+  const sta_graph_desc &g = *I.g;
+  C->n_pins = g.n_pins;
+  C->n_cells = g.n_cells;
+  C->n_nets = g.n_nets;
+  C->n_pi = g.n_pi;
+  C->n_po = g.n_po;
+  std::vector<int32_t> cell_level;
+  STA_TRY(levelize(C, I, cell_level));
+  STA_TRY(build_layout(C, I, cell_level));
+  for (auto &e : C->ev) HIP_TRY(hipEventCreate(&e));
+  C->events = true;
+  return STA_OK;
+}
+
+extern "C" sta_status sta_create(const sta_graph_desc *graph, const sta_rc_desc *rc, const sta_lib_desc *lib,
+                                 const sta_constraints *cons, const sta_options *opts, sta_ctx **out) {
+  if (!graph || !rc || !lib || !cons || !out) return fail(STA_E_ARG, "NULL descriptor");
+  sta_options o;
+  sta_options_default(&o);
+  if (opts) o = *opts;
+  STA_TRY(check_options(o));
   STA_TRY(validate_lib(*lib));
   Inputs I;
   I.g = graph;
@@ -847,38 +904,193 @@ extern "C" sta_status sta_create(const sta_graph_desc *graph, const sta_rc_desc 
   const bool dev_in = graph->mem == STA_DEVICE || rc->mem == STA_DEVICE;
   auto C = std::make_unique<sta_ctx>();
   C->opt = o;
-  auto init_device = [&]() -> sta_status {
-    int ndev = 0;
-    HIP_TRY(hipGetDeviceCount(&ndev));
-    if (ndev < 1) return fail(STA_E_DEVICE, "no HIP device");
-    if (o.device >= 0) {
-      if (o.device >= ndev) return fail(STA_E_ARG, "device %d of %d", o.device, ndev);
-      HIP_TRY(hipSetDevice(o.device));
-    }
-    HIP_TRY(hipGetDevice(&C->device));
-    hipDeviceProp_t prop;
-    HIP_TRY(hipGetDeviceProperties(&prop, C->device));
-    C->n_cu = prop.multiProcessorCount;
-    return STA_OK;
-  };
-  if (dev_in) STA_TRY(init_device());
+  if (dev_in) STA_TRY(init_device(C.get()));
   STA_TRY(load_graph(I));
   STA_TRY(validate_graph(I));
   STA_TRY(load_validate_rc(I));
   STA_TRY(validate_cons(*cons, *graph));
-  if (!dev_in) STA_TRY(init_device());
-  C->n_pins = graph->n_pins;
-  C->n_cells = graph->n_cells;
-  C->n_nets = graph->n_nets;
-  C->n_pi = graph->n_pi;
-  C->n_po = graph->n_po;
-  std::vector<int32_t> cell_level;
-  STA_TRY(levelize(C.get(), I, cell_level));
-  STA_TRY(build_layout(C.get(), I, cell_level));
-  for (auto &e : C->ev) HIP_TRY(hipEventCreate(&e));
-  C->events = true;
+  if (!dev_in) STA_TRY(init_device(C.get()));
+  STA_TRY(build_context(C.get(), I));
+  C->pin_off = {0, C->n_pins};
+  C->ep_off = {0, C->n_ep};
+  C->node_off = {0, C->n_nodes};
   HIP_TRY(hipDeviceSynchronize());
   *out = C.release();
+  return STA_OK;
+}
+
+// ------------------------------------------------------------ batches
+
+namespace {
+
+// Host arrays of a concatenated batch, in the caller layout of one design.
+struct Union {
+  std::vector<int32_t> pin_kind, cell_type, cell_in_ptr{0}, cell_in_pin, cell_out_pin;
+  std::vector<int32_t> net_driver, net_sink_ptr{0}, net_sink_pin, parent, sink_node;
+  std::vector<int64_t> net_node_ptr{0};
+  std::vector<float> res, cap, pi_at, pi_slew, po_rat, dang;
+  std::vector<int32_t> pin_off{0};
+  std::vector<int64_t> node_off{0};
+  int64_t n_pins = 0, n_cells = 0, n_nets = 0, n_pi = 0, n_po = 0;
+};
+
+template <class T>
+void append(std::vector<T> &dst, const T *src, size_t n, T add) {
+  const size_t b = dst.size();
+  dst.resize(b + n);
+  for (size_t i = 0; i < n; ++i) dst[b + i] = src[i] + add;
+}
+
+sta_status prefix_design(int d, sta_status st) {
+  g_err = "design " + std::to_string(d) + ": " + g_err;
+  return st;
+}
+
+}  // namespace
+
+extern "C" sta_status sta_batch_create(int32_t n_designs, const sta_graph_desc *graphs, const sta_rc_desc *rcs,
+                                       const sta_lib_desc *lib, const sta_constraints *cons,
+                                       const sta_options *opts, sta_ctx **out) {
+  if (!graphs || !rcs || !lib || !cons || !out) return fail(STA_E_ARG, "NULL descriptor");
+  if (n_designs < 1) return fail(STA_E_ARG, "n_designs %d < 1", n_designs);
+  sta_options o;
+  sta_options_default(&o);
+  if (opts) o = *opts;
+  STA_TRY(check_options(o));
+  if (o.mode != 0) return fail(STA_E_UNSUPPORTED, "batched contexts time hard mode (mode 0) only");
+  STA_TRY(validate_lib(*lib));
+  auto C = std::make_unique<sta_ctx>();
+  C->opt = o;
+  bool dev_in = false;
+  for (int d = 0; d < n_designs; ++d) dev_in |= graphs[d].mem == STA_DEVICE || rcs[d].mem == STA_DEVICE;
+  if (dev_in) STA_TRY(init_device(C.get()));
+
+  Union U;
+  for (int d = 0; d < n_designs; ++d) {
+    Inputs I;
+    I.g = &graphs[d];
+    I.rc = &rcs[d];
+    I.lib = lib;
+    I.cons = &cons[d];
+    sta_status st = load_graph(I);
+    if (st == STA_OK) st = validate_graph(I);
+    if (st == STA_OK) st = load_validate_rc(I);
+    if (st == STA_OK) st = validate_cons(cons[d], graphs[d]);
+    if (st != STA_OK) return prefix_design(d, st);
+    const sta_graph_desc &g = graphs[d];
+    const int32_t po = (int32_t)U.n_pins;
+    const int64_t no = U.node_off.back();
+    if (U.n_pins + g.n_pins >= INT32_MAX || no + I.rc->n_nodes >= INT32_MAX ||
+        (int64_t)U.net_sink_ptr.back() + I.net_sink_ptr[g.n_nets] >= INT32_MAX ||
+        (int64_t)U.cell_in_ptr.back() + I.cell_in_ptr[g.n_cells] >= INT32_MAX)
+      return fail(STA_E_UNSUPPORTED, "batch exceeds the int32 pin / sink / node limits at design %d", d);
+    append(U.pin_kind, I.pin_kind.p, g.n_pins, 0);
+    append(U.cell_type, I.cell_type.p, g.n_cells, 0);
+    append(U.cell_in_ptr, I.cell_in_ptr.p + 1, g.n_cells, U.cell_in_ptr.back());
+    append(U.cell_in_pin, I.cell_in_pin.p, I.cell_in_ptr[g.n_cells], po);
+    append(U.cell_out_pin, I.cell_out_pin.p, g.n_cells, po);
+    append(U.net_driver, I.net_driver.p, g.n_nets, po);
+    append(U.net_sink_ptr, I.net_sink_ptr.p + 1, g.n_nets, U.net_sink_ptr.back());
+    append(U.net_sink_pin, I.net_sink_pin.p, I.net_sink_ptr[g.n_nets], po);
+    append(U.net_node_ptr, I.net_node_ptr.p + 1, g.n_nets, no);
+    append(U.parent, I.parent.p, (size_t)I.rc->n_nodes, 0);
+    append(U.res, I.res.p, (size_t)I.rc->n_nodes, 0.0f);
+    append(U.cap, I.cap.p, (size_t)I.rc->n_nodes, 0.0f);
+    append(U.sink_node, I.sink_node.p, I.net_sink_ptr[g.n_nets], 0);
+    append(U.pi_at, cons[d].pi_at, 4 * (size_t)g.n_pi, 0.0f);
+    append(U.pi_slew, cons[d].pi_slew, 4 * (size_t)g.n_pi, 0.0f);
+    if (g.n_po > 0) append(U.po_rat, cons[d].po_rat, 4 * (size_t)g.n_po, 0.0f);
+    append(U.dang, cons[d].dangling_rat, 4, 0.0f);
+    U.n_pins += g.n_pins;
+    U.n_cells += g.n_cells;
+    U.n_nets += g.n_nets;
+    U.n_pi += g.n_pi;
+    U.n_po += g.n_po;
+    U.pin_off.push_back((int32_t)U.n_pins);
+    U.node_off.push_back(no + I.rc->n_nodes);
+  }
+  sta_graph_desc ug{};
+  ug.n_pins = (int32_t)U.n_pins;
+  ug.n_cells = (int32_t)U.n_cells;
+  ug.n_nets = (int32_t)U.n_nets;
+  ug.n_pi = (int32_t)U.n_pi;
+  ug.n_po = (int32_t)U.n_po;
+  ug.pin_kind = U.pin_kind.data();
+  ug.cell_type = U.cell_type.data();
+  ug.cell_in_ptr = U.cell_in_ptr.data();
+  ug.cell_in_pin = U.cell_in_pin.data();
+  ug.cell_out_pin = U.cell_out_pin.data();
+  ug.net_driver = U.net_driver.data();
+  ug.net_sink_ptr = U.net_sink_ptr.data();
+  ug.net_sink_pin = U.net_sink_pin.data();
+  ug.mem = STA_HOST;
+  sta_rc_desc ur{};
+  ur.n_nodes = U.node_off.back();
+  ur.net_node_ptr = U.net_node_ptr.data();
+  ur.parent = U.parent.data();
+  ur.res_kohm = U.res.data();
+  ur.cap_ff = U.cap.data();
+  ur.sink_node = U.sink_node.data();
+  ur.mem = STA_HOST;
+  sta_constraints uc = cons[0];
+  uc.pi_at = U.pi_at.data();
+  uc.pi_slew = U.pi_slew.data();
+  uc.po_rat = U.po_rat.empty() ? nullptr : U.po_rat.data();
+  Inputs I;
+  I.g = &ug;
+  I.rc = &ur;
+  I.lib = lib;
+  I.cons = &uc;
+  I.pin_off = &U.pin_off;
+  I.dang = &U.dang;
+  // every design passed validation; the union's derived maps are rebuilt here
+  STA_TRY(load_graph(I));
+  STA_TRY(validate_graph(I));
+  STA_TRY(load_validate_rc(I));
+  if (!dev_in) STA_TRY(init_device(C.get()));
+  STA_TRY(build_context(C.get(), I));
+
+  C->batched = true;
+  C->n_designs = n_designs;
+  C->pin_off = U.pin_off;
+  C->node_off = U.node_off;
+  C->ep_off.assign(1, 0);
+  {
+    size_t e = 0;
+    for (int d = 0; d < n_designs; ++d) {
+      while (e < C->h_ep_pin.size() && C->h_ep_pin[e] < U.pin_off[d + 1]) ++e;
+      C->ep_off.push_back((int32_t)e);
+    }
+  }
+  STA_TRY(C->upload(&C->d_ep_off, C->ep_off));
+  STA_TRY(C->alloc(&C->b_partials, (size_t)n_designs * kReduceBlocks * 4));
+  STA_TRY(C->alloc(&C->b_out, (size_t)n_designs * 4));
+  HIP_TRY(hipMemset(C->b_out, 0, (size_t)n_designs * 4 * sizeof(double)));
+  const int ne = std::max(C->n_ep, 1);
+  STA_TRY(C->alloc(&C->keys64, 2 * (size_t)ne));
+  STA_TRY(C->alloc(&C->keys64_out, 2 * (size_t)ne));
+  int bits = 0;
+  while ((1 << bits) < n_designs) ++bits;
+  C->key_bits = 32 + bits;
+  const size_t tb = sort_temp_bytes64(ne, C->key_bits);
+  if (tb > C->sort_bytes) {
+    unsigned char *st;
+    STA_TRY(C->alloc(&st, tb));
+    C->sort_temp = st;
+    C->sort_bytes = tb;
+  }
+  HIP_TRY(hipDeviceSynchronize());
+  *out = C.release();
+  return STA_OK;
+}
+
+extern "C" sta_status sta_batch_offsets(const sta_ctx *C, int32_t *n_designs, int32_t *pin_off, int32_t *ep_off,
+                                        int64_t *node_off) {
+  if (!C) return fail(STA_E_STATE, "NULL context");
+  if (n_designs) *n_designs = C->n_designs;
+  if (pin_off) std::copy(C->pin_off.begin(), C->pin_off.end(), pin_off);
+  if (ep_off) std::copy(C->ep_off.begin(), C->ep_off.end(), ep_off);
+  if (node_off) std::copy(C->node_off.begin(), C->node_off.end(), node_off);
   return STA_OK;
 }
 
@@ -955,6 +1167,9 @@ static sta_status enqueue_update(sta_ctx *C, hipStream_t s, bool prof) {
   if (prof) HIP_TRY(hipEventRecord(C->ev[4], s));
   if (smooth)
     HIP_TRY(launch_reduce_smooth(D, C->partials, C->out, sort ? C->keys : nullptr, sort ? C->vals : nullptr, s));
+  else if (C->batched)
+    HIP_TRY(launch_reduce_batch(D, C->d_ep_off, C->n_designs, C->b_partials, C->b_out,
+                                sort ? C->keys64 : nullptr, sort ? C->vals : nullptr, s));
   else
     HIP_TRY(launch_reduce(D, C->partials, C->out, sort ? C->keys : nullptr, sort ? C->vals : nullptr, s));
   if (prof) HIP_TRY(hipEventRecord(C->ev[5], s));
@@ -998,10 +1213,16 @@ extern "C" sta_status sta_update_timing(sta_ctx *C, void *stream) {
     STA_TRY(enqueue_update(C, s, prof));
   }
   if (sort) {
-    for (int el = 0; el < 2; ++el)
-      HIP_TRY(sort_endpoints(C->sort_temp, C->sort_bytes, C->keys + (size_t)el * C->n_ep,
-                             C->keys_out + (size_t)el * C->n_ep, C->vals, C->order + (size_t)el * C->n_ep,
-                             C->n_ep, s));
+    for (int el = 0; el < 2; ++el) {
+      if (C->batched)
+        HIP_TRY(sort_endpoints64(C->sort_temp, C->sort_bytes, C->keys64 + (size_t)el * C->n_ep,
+                                 C->keys64_out + (size_t)el * C->n_ep, C->vals,
+                                 C->order + (size_t)el * C->n_ep, C->n_ep, C->key_bits, s));
+      else
+        HIP_TRY(sort_endpoints(C->sort_temp, C->sort_bytes, C->keys + (size_t)el * C->n_ep,
+                               C->keys_out + (size_t)el * C->n_ep, C->vals, C->order + (size_t)el * C->n_ep,
+                               C->n_ep, s));
+    }
   }
   if (prof) HIP_TRY(hipEventRecord(C->ev[6], s));
   C->timed = prof;
@@ -1118,8 +1339,20 @@ extern "C" sta_status sta_report_slack(sta_ctx *C, float *pin_slack, float *ep_s
   STA_TRY(deliver(ep_slack, C->D.ep_slack, (size_t)C->n_ep * sizeof(float2), dst, s));
   STA_TRY(deliver(ep_order, C->order, (size_t)C->n_ep * 2 * sizeof(int32_t), dst, s));
   double h[4] = {0, 0, 0, 0};
-  if (wns || tns) HIP_TRY(hipMemcpyAsync(h, C->out, sizeof h, hipMemcpyDeviceToHost, s));
+  std::vector<double> hb;
+  if ((wns || tns) && C->batched) {
+    hb.resize((size_t)C->n_designs * 4);
+    HIP_TRY(hipMemcpyAsync(hb.data(), C->b_out, hb.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  } else if (wns || tns) {
+    HIP_TRY(hipMemcpyAsync(h, C->out, sizeof h, hipMemcpyDeviceToHost, s));
+  }
   if (dst == STA_HOST || wns || tns) HIP_TRY(hipStreamSynchronize(s));
+  for (int d = 0; d < (int)hb.size() / 4; ++d) {  // batch: min of WNS, sum of TNS in design order
+    h[0] = std::min(h[0], hb[4 * d + 0]);
+    h[1] = std::min(h[1], hb[4 * d + 1]);
+    h[2] += hb[4 * d + 2];
+    h[3] += hb[4 * d + 3];
+  }
   if (wns) { wns[0] = h[0]; wns[1] = h[1]; }
   if (tns) { tns[0] = h[2]; tns[1] = h[3]; }
   return STA_OK;
@@ -1183,5 +1416,79 @@ extern "C" sta_status sta_get_info(const sta_ctx *C, sta_info *info) {
   info->n_big_nets = C->n_big;
   info->n_chunks = C->n_chunks;
   info->device = C->device;
+  return STA_OK;
+}
+
+extern "C" sta_status sta_batch_report(sta_ctx *C, double *wns, double *tns, void *stream) {
+  if (!C) return fail(STA_E_STATE, "NULL context");
+  if (!C->updated) return fail(STA_E_STATE, "sta_batch_report before sta_update_timing");
+  HIP_TRY(hipSetDevice(C->device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::vector<double> h((size_t)C->n_designs * 4);
+  HIP_TRY(hipMemcpyAsync(h.data(), C->batched ? C->b_out : C->out, h.size() * sizeof(double),
+                         hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  for (int d = 0; d < C->n_designs; ++d) {
+    if (wns) { wns[2 * d] = h[4 * d + 0]; wns[2 * d + 1] = h[4 * d + 1]; }
+    if (tns) { tns[2 * d] = h[4 * d + 2]; tns[2 * d + 1] = h[4 * d + 3]; }
+  }
+  return STA_OK;
+}
+
+extern "C" sta_status sta_autotune(sta_ctx *C, int32_t reps, sta_tune_result *best, void *stream) {
+  if (!C) return fail(STA_E_STATE, "NULL context");
+  if (reps < 1) return fail(STA_E_ARG, "reps %d < 1", reps);
+  HIP_TRY(hipSetDevice(C->device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  struct Cand { int sched, grid; };
+  std::vector<Cand> cands;
+  const int max_per_cu = std::max(1, sweep_blocks_per_cu(sweep_lds_bytes(C->D)));
+  const int max_grid = max_per_cu * C->n_cu;
+  for (int k = 1; k <= max_per_cu; ++k) cands.push_back({STA_SCHED_PERSISTENT, k * C->n_cu});
+  cands.push_back({STA_SCHED_PER_LEVEL, max_grid});
+  cands.push_back({STA_SCHED_GRAPH, max_grid});
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  const sta_options saved = C->opt;
+  C->opt.profile = 0;
+  sta_tune_result r{saved.sched, C->sweep_grid, 0.0f, 0};
+  float best_ms = INFINITY;
+  sta_status st = STA_OK;
+  for (const Cand &c : cands) {
+    C->opt.sched = c.sched;
+    C->sweep_grid = c.grid;
+    st = sta_update_timing(C, s);  // warm-up (builds the graph once)
+    if (st != STA_OK) break;
+    hipError_t e = hipEventRecord(e0, s);
+    for (int i = 0; i < reps && st == STA_OK && e == hipSuccess; ++i) st = sta_update_timing(C, s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) {
+      st = hip_fail(e, "autotune timing");
+      break;
+    }
+    if (st != STA_OK) break;
+    ms /= (float)reps;
+    r.n_tried++;
+    if (ms < best_ms) {
+      best_ms = ms;
+      r.sched = c.sched;
+      r.sweep_blocks = c.grid;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  C->opt = saved;
+  if (st != STA_OK) {
+    C->sweep_grid = max_grid;
+    return st;
+  }
+  C->opt.sched = r.sched;
+  C->sweep_grid = r.sweep_blocks;
+  r.ms = best_ms;
+  if (best) *best = r;
   return STA_OK;
 }

@@ -158,6 +158,13 @@ hipError_t sort_endpoints(void *temp, size_t temp_bytes, const uint32_t *keys_in
                           uint32_t *keys_out, const int32_t *vals_in, int32_t *vals_out, int n,
                           hipStream_t s);
 size_t sort_temp_bytes(int n);
+// batches: per-design reductions (out[d][4] = early WNS, late WNS, early TNS,
+// late TNS) and the design-major endpoint sort on 64-bit keys
+hipError_t launch_reduce_batch(const DevDesign &D, const int32_t *ep_off, int n_designs, double *partials,
+                               double *out, uint64_t *keys, int32_t *vals, hipStream_t s);
+size_t sort_temp_bytes64(int n, int end_bit);
+hipError_t sort_endpoints64(void *temp, size_t temp_bytes, const uint64_t *keys_in, uint64_t *keys_out,
+                            const int32_t *vals_in, int32_t *vals_out, int n, int end_bit, hipStream_t s);
 int sweep_blocks_per_cu(size_t lds_bytes);
 size_t sweep_lds_bytes(const DevDesign &D);
 

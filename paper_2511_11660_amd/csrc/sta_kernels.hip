@@ -91,23 +91,89 @@ __device__ __forceinline__ float2 ep_slack2(float4 at, float4 rat) {
   return make_float2(fminf(at.x - rat.x, at.y - rat.y), fminf(rat.z - at.z, rat.w - at.w));
 }
 
+// Accesses to values that one wave writes and another wave of the same
+// persistent sweep reads.  kCoh selects agent-scope relaxed atomic loads and
+// stores (coherent across the XCDs' separate L2 caches on their own, emitted
+// with the device-scope cache bit), so the sweep's completion counters need no
+// L2 write-back or invalidate: a producer waits for its own coherent stores to
+// complete before bumping a counter, and a consumer issues its coherent loads
+// only after it has read the counter.  Without kCoh (one launch per level) the
+// kernel boundary orders everything and plain vector accesses are used.
+template <bool kCoh>
+__device__ __forceinline__ float4 ld4(const float4 *p) {
+  if constexpr (kCoh) {
+    const uint64_t *q = reinterpret_cast<const uint64_t *>(p);
+    const uint64_t a = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t b = __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return make_float4(__uint_as_float((uint32_t)a), __uint_as_float((uint32_t)(a >> 32)),
+                       __uint_as_float((uint32_t)b), __uint_as_float((uint32_t)(b >> 32)));
+  } else {
+    return *p;
+  }
+}
+
+template <bool kCoh>
+__device__ __forceinline__ void st4(float4 *p, float4 v) {
+  if constexpr (kCoh) {
+    uint64_t *q = reinterpret_cast<uint64_t *>(p);
+    __hip_atomic_store(q, (uint64_t)__float_as_uint(v.x) | ((uint64_t)__float_as_uint(v.y) << 32),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(q + 1, (uint64_t)__float_as_uint(v.z) | ((uint64_t)__float_as_uint(v.w) << 32),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  } else {
+    *p = v;
+  }
+}
+
+template <bool kCoh>
+__device__ __forceinline__ PinState ld_state(const PinState *p) {
+  PinState s;
+  s.at = ld4<kCoh>(&p->at);
+  s.slew = ld4<kCoh>(&p->slew);
+  return s;
+}
+
+template <bool kCoh>
+__device__ __forceinline__ void st_state(PinState *p, const PinState &v) {
+  st4<kCoh>(&p->at, v.at);
+  st4<kCoh>(&p->slew, v.slew);
+}
+
 // LDS image of the library: packed tables then the sense codes.
 struct LdsLib {
   const float *tab;
   const int *sense;
 };
 
+// The packed tables are padded to a multiple of 4 floats; every thread issues
+// all of its 16-byte loads before its LDS stores, so staging costs about one
+// memory round trip rather than one per 256 floats.
 __device__ LdsLib load_lib(const DevDesign &D, unsigned char *smem) {
   float *tab = reinterpret_cast<float *>(smem);
-  const int ntab = D.n_types * D.tstride;
-  for (int i = threadIdx.x; i < ntab; i += blockDim.x) tab[i] = D.tables[i];
-  int *sense = reinterpret_cast<int *>(tab + ntab);
+  const int n4 = (D.n_types * D.tstride + 3) >> 2;
+  const float4 *src = reinterpret_cast<const float4 *>(D.tables);
+  float4 *dst = reinterpret_cast<float4 *>(tab);
+  constexpr int kU = 8;
+  for (int b = 0; b < n4; b += kU * (int)blockDim.x) {
+    float4 v[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int i = b + u * (int)blockDim.x + (int)threadIdx.x;
+      if (i < n4) v[u] = src[i];
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int i = b + u * (int)blockDim.x + (int)threadIdx.x;
+      if (i < n4) dst[i] = v[u];
+    }
+  }
+  int *sense = reinterpret_cast<int *>(tab + 4 * n4);
   for (int i = threadIdx.x; i < D.n_types; i += blockDim.x) sense[i] = D.sense[i];
   return {tab, sense};
 }
 
 __host__ __device__ inline size_t lib_lds_bytes(int n_types, int tstride) {
-  size_t b = (size_t)n_types * tstride * 4 + (size_t)n_types * 4;
+  size_t b = (((size_t)n_types * tstride + 3) & ~(size_t)3) * 4 + (size_t)n_types * 4;
   return (b + 31) & ~(size_t)31;
 }
 
@@ -117,6 +183,7 @@ __host__ __device__ inline size_t lib_lds_bytes(int n_types, int tstride) {
 // (late max, early min), slew merged the same way independent of the AT
 // winner; the critical code is 2*fanin + input transition of the AT winner,
 // ties kept by the earlier candidate.
+template <bool kCoh>
 __device__ __forceinline__ void cell_forward(const DevDesign &D, const LdsLib &lib, int x,
                                              PinState &out, uint32_t &crit) {
   const int t = D.cell_type[x];
@@ -134,7 +201,7 @@ __device__ __forceinline__ void cell_forward(const DevDesign &D, const LdsLib &l
   float lse[2] = {0.0f, 0.0f};
   const int f0 = D.fanin_ptr[x], f1 = D.fanin_ptr[x + 1];
   for (int f = f0; f < f1; ++f) {
-    const PinState in = D.sink_state[D.fanin_sink[f]];
+    const PinState in = ld_state<kCoh>(D.sink_state + D.fanin_sink[f]);
     const float ia[4] = {in.at.x, in.at.y, in.at.z, in.at.w};
     const float is[4] = {in.slew.x, in.slew.y, in.slew.z, in.slew.w};
     const int k2 = (f - f0) * 2;
@@ -175,6 +242,7 @@ __device__ __forceinline__ void cell_forward(const DevDesign &D, const LdsLib &l
 
 // One chunk: the 64 drivers, then every sink of their nets
 // (AT_s = AT_drv + d, slew_s = sqrt(slew_drv^2 + q)).
+template <bool kCoh>
 __device__ void fwd_chunk(const DevDesign &D, const LdsLib &lib, PinState *wst, int c) {
   const int lane = lane_id();
   const int x0 = D.chunk_start[c], x1 = D.chunk_start[c + 1];
@@ -186,7 +254,7 @@ __device__ void fwd_chunk(const DevDesign &D, const LdsLib &lib, PinState *wst, 
       st.at = D.pi_at[x];
       st.slew = D.pi_slew[x];
     } else {
-      cell_forward(D, lib, x, st, crit);
+      cell_forward<kCoh>(D, lib, x, st, crit);
     }
     D.drv_state[x] = st;
     D.drv_crit[x] = crit;
@@ -201,7 +269,7 @@ __device__ void fwd_chunk(const DevDesign &D, const LdsLib &lib, PinState *wst, 
     o.at = make_float4(ds.at.x + w.x, ds.at.y + w.x, ds.at.z + w.x, ds.at.w + w.x);
     o.slew = make_float4(sqrtf(ds.slew.x * ds.slew.x + w.y), sqrtf(ds.slew.y * ds.slew.y + w.y),
                          sqrtf(ds.slew.z * ds.slew.z + w.y), sqrtf(ds.slew.w * ds.slew.w + w.y));
-    D.sink_state[s] = o;
+    st_state<kCoh>(D.sink_state + s, o);
   }
   wave_sync();
 }
@@ -219,7 +287,9 @@ __device__ __forceinline__ void wait_count(uint32_t *ctr, uint32_t target) {
     if (__builtin_amdgcn_readfirstlane(v) >= target) break;
     __builtin_amdgcn_s_sleep(1);
   }
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  // the loop exit waits on the counter load; keep the compiler from hoisting
+  // the coherent data loads that follow above it
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
 __device__ __forceinline__ int take_ticket(uint32_t *ctr) {
@@ -227,30 +297,34 @@ __device__ __forceinline__ int take_ticket(uint32_t *ctr) {
   return (int)__builtin_amdgcn_readfirstlane(old);
 }
 
+// Every coherent store of this wave has completed (vmcnt 0) before the counter
+// moves, so a consumer that sees the count reads the new values.
 __device__ __forceinline__ void signal_done(uint32_t *ctr) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);
   __hip_atomic_fetch_add(ctr, lane_id() == 0 ? 1u : 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__global__ __launch_bounds__(kSweepBlock) void k_forward(DevDesign D, int c0, int c1, int persistent) {
+template <bool kPersistent>
+__global__ __launch_bounds__(kSweepBlock) void k_forward(DevDesign D, int c0, int c1) {
   extern __shared__ __align__(32) unsigned char smem[];
   const LdsLib lib = load_lib(D, smem);
   PinState *wst = reinterpret_cast<PinState *>(smem + lib_lds_bytes(D.n_types, D.tstride)) +
                   (threadIdx.x / kWave) * kWave;
   __syncthreads();
-  if (persistent) {
+  if constexpr (kPersistent) {
     uint32_t *done = D.counters + kCtrLevels;
     for (;;) {
       const int c = take_ticket(D.counters + kCtrFwdTicket);
       if (c >= D.n_chunks) break;
       const int lvl = D.chunk_level[c];
       if (lvl > 0) wait_count(done + lvl - 1, (uint32_t)D.level_nchunks[lvl - 1]);
-      fwd_chunk(D, lib, wst, c);
+      fwd_chunk<true>(D, lib, wst, c);
       signal_done(done + lvl);
     }
   } else {
     const int c = c0 + blockIdx.x * (kSweepBlock / kWave) + threadIdx.x / kWave;
-    if (c < c1) fwd_chunk(D, lib, wst, c);
+    if (c < c1) fwd_chunk<false>(D, lib, wst, c);
   }
 }
 
@@ -260,6 +334,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_forward(DevDesign D, int c0, in
 // consumer cell's output RAT minus the recomputed arc delay, min for late and
 // max for early over the output transitions the input reaches) or from its
 // endpoint constraint; the drivers merge RAT_s - d over their sinks.
+template <bool kCoh>
 __device__ void bwd_chunk(const DevDesign &D, const LdsLib &lib, int *wacc, int c) {
   const int lane = lane_id();
   const int x0 = D.chunk_start[c], x1 = D.chunk_start[c + 1];
@@ -288,7 +363,7 @@ __device__ void bwd_chunk(const DevDesign &D, const LdsLib &lib, int *wacc, int 
       const int t = D.cell_type[cons];
       const int sense = lib.sense[t];
       const float L = D.L_net[cons];
-      const float4 Ro4 = D.drv_rat[cons];
+      const float4 Ro4 = ld4<kCoh>(D.drv_rat + cons);
       const float Ro[4] = {Ro4.x, Ro4.y, Ro4.z, Ro4.w};
       const float is[4] = {ss.slew.x, ss.slew.y, ss.slew.z, ss.slew.w};
       const float *tb = lib.tab + t * D.tstride;
@@ -326,7 +401,7 @@ __device__ void bwd_chunk(const DevDesign &D, const LdsLib &lib, int *wacc, int 
     const float4 R = make_float4(key2f(wacc[lane * 4 + 0]), key2f(wacc[lane * 4 + 1]),
                                  key2f(wacc[lane * 4 + 2]), key2f(wacc[lane * 4 + 3]));
     const float4 A = D.drv_state[x].at;
-    D.drv_rat[x] = R;
+    st4<kCoh>(D.drv_rat + x, R);
     D.drv_slack[x] = slack4(A, R);
     const int e = D.drv_ep[x];
     if (e >= 0) D.ep_slack[e] = ep_slack2(A, R);
@@ -334,13 +409,14 @@ __device__ void bwd_chunk(const DevDesign &D, const LdsLib &lib, int *wacc, int 
   wave_sync();
 }
 
-__global__ __launch_bounds__(kSweepBlock) void k_backward(DevDesign D, int c0, int c1, int persistent) {
+template <bool kPersistent>
+__global__ __launch_bounds__(kSweepBlock) void k_backward(DevDesign D, int c0, int c1) {
   extern __shared__ __align__(32) unsigned char smem[];
   const LdsLib lib = load_lib(D, smem);
   int *wacc = reinterpret_cast<int *>(smem + lib_lds_bytes(D.n_types, D.tstride)) +
               (threadIdx.x / kWave) * kWave * 4;
   __syncthreads();
-  if (persistent) {
+  if constexpr (kPersistent) {
     uint32_t *done = D.counters + kCtrLevels + D.n_cell_levels + 1;
     for (;;) {
       const int t = take_ticket(D.counters + kCtrBwdTicket);
@@ -348,12 +424,12 @@ __global__ __launch_bounds__(kSweepBlock) void k_backward(DevDesign D, int c0, i
       const int c = D.n_chunks - 1 - t;
       const int lvl = D.chunk_level[c];
       if (lvl < D.n_cell_levels) wait_count(done + lvl + 1, (uint32_t)D.level_nchunks[lvl + 1]);
-      bwd_chunk(D, lib, wacc, c);
+      bwd_chunk<true>(D, lib, wacc, c);
       signal_done(done + lvl);
     }
   } else {
     const int c = c0 + blockIdx.x * (kSweepBlock / kWave) + threadIdx.x / kWave;
-    if (c < c1) bwd_chunk(D, lib, wacc, c);
+    if (c < c1) bwd_chunk<false>(D, lib, wacc, c);
   }
 }
 
@@ -586,6 +662,65 @@ __global__ __launch_bounds__(256) void k_reduce(DevDesign D, double *partials, d
   }
 }
 
+// ------------------------------------------------------ batched reduction
+
+// Per-design WNS/TNS of a batch.  Block (b, d) reduces slice b of design d's
+// endpoints [ep_off[d], ep_off[d+1]) with the partition, per-thread order and
+// tree of k_reduce, and k_reduce_batch_final folds the slices in the same
+// order, so each design's figures are bit-identical to timing it alone.
+// Sort keys carry the design in their high 32 bits (design-major order);
+// values are design-local endpoint indices.
+__global__ __launch_bounds__(256) void k_reduce_batch(DevDesign D, const int32_t *ep_off, double *partials,
+                                                     uint64_t *keys, int32_t *vals) {
+  __shared__ double sh[4][256];
+  const int dsg = blockIdx.y;
+  const int e0 = ep_off[dsg];
+  const int n = ep_off[dsg + 1] - e0;
+  const int per = (n + kReduceBlocks - 1) / kReduceBlocks;
+  const int b0 = blockIdx.x * per, b1 = min(n, b0 + per);
+  double w0 = 0.0, w1 = 0.0, t0 = 0.0, t1 = 0.0;
+  for (int e = b0 + (int)threadIdx.x; e < b1; e += 256) {
+    const float2 s = D.ep_slack[e0 + e];
+    w0 = fmin(w0, (double)s.x);
+    w1 = fmin(w1, (double)s.y);
+    if (s.x < 0.0f) t0 += (double)s.x;
+    if (s.y < 0.0f) t1 += (double)s.y;
+    if (keys) {
+      keys[e0 + e] = ((uint64_t)dsg << 32) | f2ukey(s.x);
+      keys[D.n_ep + e0 + e] = ((uint64_t)dsg << 32) | f2ukey(s.y);
+      vals[e0 + e] = e;
+    }
+  }
+  const int tid = threadIdx.x;
+  sh[0][tid] = w0; sh[1][tid] = w1; sh[2][tid] = t0; sh[3][tid] = t1;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (tid < o) {
+      sh[0][tid] = fmin(sh[0][tid], sh[0][tid + o]);
+      sh[1][tid] = fmin(sh[1][tid], sh[1][tid + o]);
+      sh[2][tid] = sh[2][tid] + sh[2][tid + o];
+      sh[3][tid] = sh[3][tid] + sh[3][tid + o];
+    }
+    __syncthreads();
+  }
+  if (tid == 0)
+    for (int k = 0; k < 4; ++k) partials[((size_t)dsg * kReduceBlocks + blockIdx.x) * 4 + k] = sh[k][0];
+}
+
+__global__ void k_reduce_batch_final(const double *partials, double *out, int n_designs) {
+  const int dsg = blockIdx.x * blockDim.x + threadIdx.x;
+  if (dsg >= n_designs) return;
+  const double *p = partials + (size_t)dsg * kReduceBlocks * 4;
+  double W0 = 0.0, W1 = 0.0, T0 = 0.0, T1 = 0.0;
+  for (int b = 0; b < kReduceBlocks; ++b) {
+    W0 = fmin(W0, p[b * 4 + 0]);
+    W1 = fmin(W1, p[b * 4 + 1]);
+    T0 += p[b * 4 + 2];
+    T1 += p[b * 4 + 3];
+  }
+  out[dsg * 4 + 0] = W0; out[dsg * 4 + 1] = W1; out[dsg * 4 + 2] = T0; out[dsg * 4 + 3] = T1;
+}
+
 // ------------------------------------------------------ smooth reduction
 
 // Smooth mode: per endpoint the early slack stays hard (min over rise/fall of
@@ -688,6 +823,7 @@ __device__ __forceinline__ float2 endpoint_seed(const DevDesign &D, float g_tns,
 // log-sum-exp arrival merge, the slew merge's subgradient to its winner, and
 // the NLDM partials.  Every input sink has this cell as its only consumer, so
 // its gradient is written here, once; nothing is accumulated atomically.
+template <bool kCoh>
 __device__ void cell_adjoint(const DevDesign &D, const LdsLib &lib, int x, const PinState &me, float gA0,
                              float gA1, float gS0, float gS1) {
   const int t = D.cell_type[x];
@@ -751,7 +887,7 @@ __device__ void cell_adjoint(const DevDesign &D, const LdsLib &lib, int x, const
         }
       }
     }
-    D.g_sink[sidx] = make_float4(giA[0], giA[1], giS[0], giS[1]);
+    st4<kCoh>(D.g_sink + sidx, make_float4(giA[0], giA[1], giS[0], giS[1]));
     D.g_arc[f] = make_float2(ga[0], ga[1]);
   }
   D.g_load[x] = gL;
@@ -761,6 +897,7 @@ __device__ void cell_adjoint(const DevDesign &D, const LdsLib &lib, int x, const
 // gradients in sink order (d slew_s / d slew_drv = slew_drv / slew_s), records
 // dJ/dd and dJ/dq per sink for the RC adjoint, and then pushes through its own
 // cell to the cell's input sinks.
+template <bool kCoh>
 __device__ void adj_chunk(const DevDesign &D, const LdsLib &lib, float g_tns, float g_wns, int c) {
   const int x = D.chunk_start[c] + lane_id();
   if (x >= D.chunk_start[c + 1]) return;
@@ -780,7 +917,7 @@ __device__ void adj_chunk(const DevDesign &D, const LdsLib &lib, float g_tns, fl
       const float2 sd = endpoint_seed(D, g_tns, g_wns, -1 - cons, ss.at);
       gs = make_float4(sd.x, sd.y, 0.0f, 0.0f);
     } else {
-      gs = D.g_sink[s];
+      gs = ld4<kCoh>(D.g_sink + s);
     }
     gA0 += gs.x;
     gA1 += gs.y;
@@ -789,18 +926,18 @@ __device__ void adj_chunk(const DevDesign &D, const LdsLib &lib, float g_tns, fl
     D.g_dq[s] = make_float2(gs.x + gs.y, gs.z / (2.0f * ss.slew.z) + gs.w / (2.0f * ss.slew.w));
   }
   if (x >= D.n_pi) {
-    cell_adjoint(D, lib, x, me, gA0, gA1, gS0, gS1);
+    cell_adjoint<kCoh>(D, lib, x, me, gA0, gA1, gS0, gS1);
   } else {
     D.g_load[x] = 0.0f;
   }
 }
 
-__global__ __launch_bounds__(kSweepBlock) void k_adjoint(DevDesign D, float g_tns, float g_wns, int c0, int c1,
-                                                        int persistent) {
+template <bool kPersistent>
+__global__ __launch_bounds__(kSweepBlock) void k_adjoint(DevDesign D, float g_tns, float g_wns, int c0, int c1) {
   extern __shared__ __align__(32) unsigned char smem[];
   const LdsLib lib = load_lib(D, smem);
   __syncthreads();
-  if (persistent) {
+  if constexpr (kPersistent) {
     uint32_t *done = D.counters + kCtrLevels;  // reuses the forward counters (reset by the RC adjoint)
     for (;;) {
       const int t = take_ticket(D.counters + kCtrFwdTicket);
@@ -808,12 +945,12 @@ __global__ __launch_bounds__(kSweepBlock) void k_adjoint(DevDesign D, float g_tn
       const int c = D.n_chunks - 1 - t;
       const int lvl = D.chunk_level[c];
       if (lvl < D.n_cell_levels) wait_count(done + lvl + 1, (uint32_t)D.level_nchunks[lvl + 1]);
-      adj_chunk(D, lib, g_tns, g_wns, c);
+      adj_chunk<true>(D, lib, g_tns, g_wns, c);
       signal_done(done + lvl);
     }
   } else {
     const int c = c0 + blockIdx.x * (kSweepBlock / kWave) + threadIdx.x / kWave;
-    if (c < c1) adj_chunk(D, lib, g_tns, g_wns, c);
+    if (c < c1) adj_chunk<false>(D, lib, g_tns, g_wns, c);
   }
 }
 
@@ -1091,9 +1228,9 @@ size_t sweep_lds_bytes(const DevDesign &D) {
 
 int sweep_blocks_per_cu(size_t lds_bytes) {
   int nf = 0, nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nf, k_forward, kSweepBlock, lds_bytes) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nf, k_forward<true>, kSweepBlock, lds_bytes) != hipSuccess)
     return 1;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_backward, kSweepBlock, lds_bytes) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_backward<true>, kSweepBlock, lds_bytes) != hipSuccess)
     return 1;
   const int n = nf < nb ? nf : nb;
   return n < 1 ? 1 : n;
@@ -1119,28 +1256,28 @@ hipError_t launch_rc_adjoint_wide(const DevDesign &D, const WideNets &W, hipStre
 }
 
 hipError_t launch_forward(const DevDesign &D, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_forward, dim3(grid), dim3(kSweepBlock), sweep_lds_bytes(D), s, D, 0, 0, 1);
+  hipLaunchKernelGGL(k_forward<true>, dim3(grid), dim3(kSweepBlock), sweep_lds_bytes(D), s, D, 0, 0);
   return hipGetLastError();
 }
 
 hipError_t launch_forward_level(const DevDesign &D, int c0, int c1, hipStream_t s) {
   if (c1 <= c0) return hipSuccess;
   const int per = kSweepBlock / kWave;
-  hipLaunchKernelGGL(k_forward, dim3(blocks_for(c1 - c0, per)), dim3(kSweepBlock), sweep_lds_bytes(D), s,
-                     D, c0, c1, 0);
+  hipLaunchKernelGGL(k_forward<false>, dim3(blocks_for(c1 - c0, per)), dim3(kSweepBlock), sweep_lds_bytes(D), s,
+                     D, c0, c1);
   return hipGetLastError();
 }
 
 hipError_t launch_backward(const DevDesign &D, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_backward, dim3(grid), dim3(kSweepBlock), sweep_lds_bytes(D), s, D, 0, 0, 1);
+  hipLaunchKernelGGL(k_backward<true>, dim3(grid), dim3(kSweepBlock), sweep_lds_bytes(D), s, D, 0, 0);
   return hipGetLastError();
 }
 
 hipError_t launch_backward_level(const DevDesign &D, int c0, int c1, hipStream_t s) {
   if (c1 <= c0) return hipSuccess;
   const int per = kSweepBlock / kWave;
-  hipLaunchKernelGGL(k_backward, dim3(blocks_for(c1 - c0, per)), dim3(kSweepBlock), sweep_lds_bytes(D), s,
-                     D, c0, c1, 0);
+  hipLaunchKernelGGL(k_backward<false>, dim3(blocks_for(c1 - c0, per)), dim3(kSweepBlock), sweep_lds_bytes(D), s,
+                     D, c0, c1);
   return hipGetLastError();
 }
 
@@ -1151,15 +1288,15 @@ hipError_t launch_reduce_smooth(const DevDesign &D, double *partials, double *ou
 }
 
 hipError_t launch_adjoint(const DevDesign &D, float g_tns, float g_wns, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_adjoint, dim3(grid), dim3(kSweepBlock), sweep_lds_bytes(D), s, D, g_tns, g_wns, 0, 0, 1);
+  hipLaunchKernelGGL(k_adjoint<true>, dim3(grid), dim3(kSweepBlock), sweep_lds_bytes(D), s, D, g_tns, g_wns, 0, 0);
   return hipGetLastError();
 }
 
 hipError_t launch_adjoint_level(const DevDesign &D, float g_tns, float g_wns, int c0, int c1, hipStream_t s) {
   if (c1 <= c0) return hipSuccess;
   const int per = kSweepBlock / kWave;
-  hipLaunchKernelGGL(k_adjoint, dim3(blocks_for(c1 - c0, per)), dim3(kSweepBlock), sweep_lds_bytes(D), s, D,
-                     g_tns, g_wns, c0, c1, 0);
+  hipLaunchKernelGGL(k_adjoint<false>, dim3(blocks_for(c1 - c0, per)), dim3(kSweepBlock), sweep_lds_bytes(D), s, D,
+                     g_tns, g_wns, c0, c1);
   return hipGetLastError();
 }
 
@@ -1202,6 +1339,28 @@ size_t sort_temp_bytes(int n) {
 hipError_t sort_endpoints(void *temp, size_t temp_bytes, const uint32_t *keys_in, uint32_t *keys_out,
                           const int32_t *vals_in, int32_t *vals_out, int n, hipStream_t s) {
   return hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, keys_in, keys_out, vals_in, vals_out, n, 0, 32,
+                                            s);
+}
+
+hipError_t launch_reduce_batch(const DevDesign &D, const int32_t *ep_off, int n_designs, double *partials,
+                               double *out, uint64_t *keys, int32_t *vals, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_batch, dim3(kReduceBlocks, n_designs), dim3(256), 0, s, D, ep_off, partials, keys,
+                     vals);
+  hipLaunchKernelGGL(k_reduce_batch_final, dim3(blocks_for(n_designs, 256)), dim3(256), 0, s, partials, out,
+                     n_designs);
+  return hipGetLastError();
+}
+
+size_t sort_temp_bytes64(int n, int end_bit) {
+  size_t bytes = 0;
+  (void)hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (const uint64_t *)nullptr, (uint64_t *)nullptr,
+                                           (const int32_t *)nullptr, (int32_t *)nullptr, n, 0, end_bit);
+  return bytes;
+}
+
+hipError_t sort_endpoints64(void *temp, size_t temp_bytes, const uint64_t *keys_in, uint64_t *keys_out,
+                            const int32_t *vals_in, int32_t *vals_out, int n, int end_bit, hipStream_t s) {
+  return hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, keys_in, keys_out, vals_in, vals_out, n, 0, end_bit,
                                             s);
 }
 

@@ -59,7 +59,7 @@ class sta_options(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("gamma_ps", ctypes.c_float),
                 ("dangling_policy", ctypes.c_int32), ("sched", ctypes.c_int32),
                 ("big_net_nodes", ctypes.c_int32), ("sort_endpoints", ctypes.c_int32),
-                ("profile", ctypes.c_int32), ("device", ctypes.c_int32)]
+                ("profile", ctypes.c_int32), ("device", ctypes.c_int32), ("sweep_blocks", ctypes.c_int32)]
 
 
 class sta_info(ctypes.Structure):
@@ -69,6 +69,11 @@ class sta_info(ctypes.Structure):
                 ("n_cell_levels", ctypes.c_int32), ("n_endpoints", ctypes.c_int32),
                 ("n_big_nets", ctypes.c_int32), ("n_chunks", ctypes.c_int32),
                 ("device", ctypes.c_int32)]
+
+
+class sta_tune_result(ctypes.Structure):
+    _fields_ = [("sched", ctypes.c_int32), ("sweep_blocks", ctypes.c_int32), ("ms", ctypes.c_float),
+                ("n_tried", ctypes.c_int32)]
 
 
 # (name, restype, argtypes) of every exported function
@@ -88,6 +93,13 @@ _SIGS = [
     ("sta_get_info", ctypes.c_int, [_VP, ctypes.POINTER(sta_info)]),
     ("sta_get_phase_times", ctypes.c_int, [_VP, _PF, _P32]),
     ("sta_backward", ctypes.c_int, [_VP, ctypes.c_float, ctypes.c_float, _VP, _VP, _VP, ctypes.c_int, _VP]),
+    ("sta_batch_create", ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(sta_graph_desc),
+                                        ctypes.POINTER(sta_rc_desc), ctypes.POINTER(sta_lib_desc),
+                                        ctypes.POINTER(sta_constraints), ctypes.POINTER(sta_options),
+                                        ctypes.POINTER(_VP)]),
+    ("sta_batch_offsets", ctypes.c_int, [_VP, _P32, _P32, _P32, _P64]),
+    ("sta_batch_report", ctypes.c_int, [_VP, _PD, _PD, _VP]),
+    ("sta_autotune", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.POINTER(sta_tune_result), _VP]),
     ("sta_status_string", ctypes.c_char_p, [ctypes.c_int]),
     ("sta_last_error", ctypes.c_char_p, []),
 ]
@@ -248,6 +260,45 @@ def sta_backward(ctx: int, g_tns: float, g_wns: float, grad_wire_cap=None, grad_
                                _addr(grad_pin_load), _addr(grad_arc_delay), dst, _stream(stream)))
 
 
+def sta_batch_create(graphs, rcs, lib: sta_lib_desc, cons, opts: sta_options | None = None) -> int:
+    n = len(graphs)
+    if not (len(rcs) == len(cons) == n):
+        raise ValueError("graphs, rcs and cons must have one entry per design")
+    ga = (sta_graph_desc * n)(*graphs)
+    ra = (sta_rc_desc * n)(*rcs)
+    ca = (sta_constraints * n)(*cons)
+    ctx = _VP()
+    _check(load().sta_batch_create(n, ga, ra, ctypes.byref(lib), ca,
+                                   ctypes.byref(opts) if opts is not None else None, ctypes.byref(ctx)))
+    return ctx.value
+
+
+def sta_batch_offsets(ctx: int):
+    """(pin_off, ep_off, node_off) numpy arrays of n_designs + 1 entries."""
+    n = ctypes.c_int32(0)
+    _check(load().sta_batch_offsets(ctx, ctypes.byref(n), None, None, None))
+    pin = np.zeros(n.value + 1, np.int32)
+    ep = np.zeros(n.value + 1, np.int32)
+    node = np.zeros(n.value + 1, np.int64)
+    _check(load().sta_batch_offsets(ctx, ctypes.byref(n), pin.ctypes.data_as(_P32), ep.ctypes.data_as(_P32),
+                                    node.ctypes.data_as(_P64)))
+    return pin, ep, node
+
+
+def sta_batch_report(ctx: int, n_designs: int, stream=None):
+    """Per-design (wns, tns), each [n_designs][2] (early, late)."""
+    wns = np.zeros((n_designs, 2), np.float64)
+    tns = np.zeros((n_designs, 2), np.float64)
+    _check(load().sta_batch_report(ctx, wns.ctypes.data_as(_PD), tns.ctypes.data_as(_PD), _stream(stream)))
+    return wns, tns
+
+
+def sta_autotune(ctx: int, reps: int = 5, stream=None) -> sta_tune_result:
+    r = sta_tune_result()
+    _check(load().sta_autotune(ctx, int(reps), ctypes.byref(r), _stream(stream)))
+    return r
+
+
 PHASES = ("rc_small", "rc_big", "forward", "backward", "reduce", "sort", "adjoint_sweep", "adjoint_rc")
 
 
@@ -279,19 +330,28 @@ def descriptors(d, keep: list):
 
 
 class STA:
-    """One timing context on the current HIP device."""
+    """One timing context on the current HIP device: of one design, or of a
+    batch when given a list of designs that share one library."""
 
     def __init__(self, design, **opts):
+        batch = isinstance(design, (list, tuple))
+        designs = list(design) if batch else [design]
         o = sta_options_default()
-        o.dangling_policy = int(design.dangling_policy)
+        o.dangling_policy = int(designs[0].dangling_policy)
         for k, v in opts.items():
             setattr(o, k, v)
         keep: list = []
-        g, rc, lib, cons = descriptors(design, keep)
-        self.ctx = sta_create(g, rc, lib, cons, o)
+        descs = [descriptors(d, keep) for d in designs]
+        if batch:
+            self.ctx = sta_batch_create([x[0] for x in descs], [x[1] for x in descs], descs[0][2],
+                                        [x[3] for x in descs], o)
+        else:
+            g, rc, lib, cons = descs[0]
+            self.ctx = sta_create(g, rc, lib, cons, o)
+        self.n_designs = len(designs)
         self.info = sta_get_info(self.ctx)
         self.opts = o
-        self._n_arcs = int(design.cell_in_ptr[-1])
+        self._n_arcs = int(sum(int(d.cell_in_ptr[-1]) for d in designs))
 
     def close(self):
         if getattr(self, "ctx", None):
@@ -344,6 +404,18 @@ class STA:
         e = np.zeros(max(1, self.info.n_endpoints), np.int32)
         sta_report_endpoints(self.ctx, e)
         return e[: self.info.n_endpoints]
+
+    def batch_offsets(self):
+        return sta_batch_offsets(self.ctx)
+
+    def batch_report(self):
+        return sta_batch_report(self.ctx, self.n_designs)
+
+    def autotune(self, reps=5, stream=None):
+        r = sta_autotune(self.ctx, reps, stream)
+        self.opts.sched = r.sched
+        self.opts.sweep_blocks = r.sweep_blocks
+        return r
 
     def phase_times(self):
         return sta_get_phase_times(self.ctx)

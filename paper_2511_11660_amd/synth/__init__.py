@@ -37,6 +37,7 @@ class _Cfg(ctypes.Structure):
         ("dangling_policy", ctypes.c_int32),
         ("shuffle", ctypes.c_int32),
         ("seed", ctypes.c_uint64),
+        ("lib_seed", ctypes.c_uint64),
     ]
 
 
@@ -106,6 +107,7 @@ class SynthConfig:
     dangling_policy: int = 0
     shuffle: int = 0
     seed: int = 1
+    lib_seed: int = 0  # library tables / pin caps from this seed; 0 = seed
 
 
 @dataclass
@@ -167,7 +169,7 @@ def generate(cfg: SynthConfig) -> Design:
     c = _Cfg(cfg.n_cells, cfg.n_levels, cfg.n_pi, cfg.n_po, cfg.fanout_mu, cfg.fanout_cap,
              cfg.n_types, cfg.n_heavy, cfg.heavy_frac, cfg.n_hf, cfg.hf_min, cfg.hf_max,
              cfg.rat_ps, cfg.rat_early_ps, cfg.pi_at_ps, cfg.pi_slew_ps, cfg.po_cap_ff, cfg.dangling_policy,
-             cfg.shuffle, cfg.seed)
+             cfg.shuffle, cfg.seed, cfg.lib_seed)
     p = lib.synth_generate(ctypes.byref(c))
     if not p:
         raise ValueError(f"synth_generate rejected config {cfg}")
@@ -256,7 +258,8 @@ def batch_configs(n_designs: int = 256, base_seed: int = 5_000_000,
                   min_cells: int = 1000, max_cells: int = 200_000) -> list[SynthConfig]:
     """Uneven batch: per design, cells log-uniform in [min_cells, max_cells] and
     levels uniform in 10..80, drawn from the design's own seed; otherwise the
-    1M-pin generator settings."""
+    1M-pin generator settings.  All designs of a batch share one cell library
+    (one technology), drawn from the first design's seed."""
     out = []
     for i in range(n_designs):
         seed = base_seed + i
@@ -264,7 +267,7 @@ def batch_configs(n_designs: int = 256, base_seed: int = 5_000_000,
         cells = int(round(math.exp(rng.uniform(math.log(min_cells), math.log(max_cells)))))
         levels = int(rng.integers(10, 81))
         levels = min(levels, cells)
-        out.append(mid_config(seed=seed, n_cells=cells, n_levels=levels))
+        out.append(mid_config(seed=seed, n_cells=cells, n_levels=levels, lib_seed=base_seed))
     return out
 
 

@@ -97,6 +97,7 @@ typedef struct {
   int32_t dangling_policy;
   int32_t shuffle;      /* permute pin ids, cell order and net order */
   uint64_t seed;
+  uint64_t lib_seed;    /* library stream seed; 0 = the design seed */
 } synth_cfg;
 
 typedef struct {
@@ -183,7 +184,7 @@ synth_design *synth_generate(const synth_cfg *cfg) {
   const int64_t NPI = cfg->n_pi, NPO = cfg->n_po;
   if (NC < 1 || L < 1 || NPI < 1 || NPO < 0 || cfg->n_types < 1 || NC < L) return NULL;
   sm64_t g_lvl = stream(cfg->seed, 1), g_top = stream(cfg->seed, 2), g_rc = stream(cfg->seed, 3);
-  sm64_t g_lib = stream(cfg->seed, 4), g_shuf = stream(cfg->seed, 5);
+  sm64_t g_lib = stream(cfg->lib_seed ? cfg->lib_seed : cfg->seed, 4), g_shuf = stream(cfg->seed, 5);
 
   /* 1. level sizes */
   int64_t *lvl_size = (int64_t *)calloc((size_t)L + 2, sizeof(int64_t));

@@ -148,3 +148,38 @@ def test_null_context_calls_are_state_errors():
     with pytest.raises(S.StaError) as e:
         S.sta_backward(0, 1.0, 0.0)
     assert e.value.status == S.STA_E_STATE
+
+
+def _batch(designs, **opts):
+    keep = []
+    descs = [S.descriptors(d, keep) for d in designs]
+    o = S.sta_options_default()
+    for k, v in opts.items():
+        setattr(o, k, v)
+    lib = descs[0][2] if descs else S.sta_lib_desc()
+    return S.sta_batch_create([x[0] for x in descs], [x[1] for x in descs], lib, [x[3] for x in descs], o)
+
+
+def test_batch_validation_names_the_design():
+    a, b = _tiny(), synth.generate(synth.tiny_config(seed=3))
+    b.pin_kind[4] = 9
+    with pytest.raises(S.StaError) as e:
+        _batch([a, b])
+    assert e.value.status == S.STA_E_ARG and "design 1:" in str(e.value), str(e.value)
+
+
+def test_batch_rejects_smooth_mode_and_empty_batch():
+    with pytest.raises(S.StaError) as e:
+        _batch([_tiny(), _tiny()], mode=1)
+    assert e.value.status == S.STA_E_UNSUPPORTED
+    with pytest.raises(S.StaError) as e:
+        _batch([])
+    assert e.value.status == S.STA_E_ARG
+
+
+def test_batch_null_context_calls_are_state_errors():
+    for call in (lambda: S.sta_batch_report(0, 1), lambda: S.sta_autotune(0, 2),
+                 lambda: S.sta_batch_offsets(0)):
+        with pytest.raises(S.StaError) as e:
+            call()
+        assert e.value.status == S.STA_E_STATE

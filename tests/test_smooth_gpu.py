@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 from paper_2511_11660_amd import synth
-from paper_2511_11660_amd.sta import STA, STA_SCHED_PER_LEVEL, STA_SCHED_PERSISTENT
+from paper_2511_11660_amd.sta import STA, STA_SCHED_GRAPH, STA_SCHED_PER_LEVEL, STA_SCHED_PERSISTENT
 
 pytestmark = pytest.mark.gpu
 GAMMA = 5.0
@@ -28,7 +28,7 @@ def _grad_scale(o):
     return 1e-5 * max(1.0, float(np.abs(o).max()))
 
 
-@pytest.mark.parametrize("sched", [STA_SCHED_PERSISTENT, STA_SCHED_PER_LEVEL])
+@pytest.mark.parametrize("sched", [STA_SCHED_PERSISTENT, STA_SCHED_PER_LEVEL, STA_SCHED_GRAPH])
 @pytest.mark.parametrize("cfg", ["tiny", "mid"])
 def test_smooth_forward_and_adjoint(cfg, sched):
     d = synth.generate(synth.tiny_config(seed=8, dangling_policy=1) if cfg == "tiny" else
