@@ -98,6 +98,8 @@ struct sta_ctx {
   int n_cell_levels = 0, n_levels = 0, n_chunks = 0, n_big = 0, n_rc_chunks = 0;
   int64_t n_nodes = 0;
   int n_cu = 0, sweep_grid = 1;
+  bool coop = false;                   // persistent sweeps use the cooperative level-major kernels
+  int coop_max = 0;                    // cooperative grid limit (blocks)
   std::vector<std::unique_ptr<DevMem>> mem;
   DevDesign D{};
   float *rc_cap = nullptr;
@@ -538,18 +540,48 @@ static sta_status build_layout(sta_ctx *C, const Inputs &I, const std::vector<in
   C->n_ep = (int)ep_pin.size();
   C->h_ep_pin = ep_pin;
 
-  // nets in slot order, sinks net-major, RC nodes net-major
-  std::vector<int32_t> sink_ptr(ND + 1, 0), rc_ptr(ND + 1, 0), net_slot(g.n_nets);
+  // nets in slot order, sinks net-major.  RC nodes net-major in "RC order":
+  // within each window of kRcSortWindow consecutive slots, small nets by
+  // ascending node count (ties by slot), so the 64 nets a wave walks in
+  // parallel have near-equal trees while a block's outputs stay within one
+  // window of slots; then the wide nets.  rc_ptr[x] is
+  // the first node of net x; rc_start / rc_order list the small nets by RC
+  // position.
+  std::vector<int32_t> sink_ptr(ND + 1, 0), rc_ptr(ND + 1, 0), net_slot(g.n_nets), rc_m(ND);
+  int64_t NN = 0;
   for (int x = 0; x < ND; ++x) {
     const int n = I.net_of_drv[drv_pin[x]];
     net_slot[n] = x;
     sink_ptr[x + 1] = sink_ptr[x] + (I.net_sink_ptr[n + 1] - I.net_sink_ptr[n]);
     const int64_t m = I.net_node_ptr[n + 1] - I.net_node_ptr[n];
-    if ((int64_t)rc_ptr[x] + m >= INT32_MAX) return fail(STA_E_UNSUPPORTED, "too many RC nodes");
-    rc_ptr[x + 1] = rc_ptr[x] + (int32_t)m;
+    NN += m;
+    if (NN >= INT32_MAX) return fail(STA_E_UNSUPPORTED, "too many RC nodes");
+    rc_m[x] = (int32_t)m;
+  }
+  std::vector<int32_t> rc_order, rc_start;
+  {
+    std::vector<int32_t> small, wide;
+    for (int x = 0; x < ND; ++x) (rc_m[x] > big_thr ? wide : small).push_back(x);
+    std::stable_sort(small.begin(), small.end(), [&](int a, int b) {
+      const int wa = a / kRcSortWindow, wb = b / kRcSortWindow;
+      return wa != wb ? wa < wb : rc_m[a] < rc_m[b];
+    });
+    int32_t pos = 0;
+    rc_start.reserve(small.size() + 1);
+    for (int x : small) {
+      rc_start.push_back(pos);
+      rc_ptr[x] = pos;
+      pos += rc_m[x];
+    }
+    rc_start.push_back(pos);
+    for (int x : wide) {
+      rc_ptr[x] = pos;
+      pos += rc_m[x];
+    }
+    rc_ptr[ND] = pos;
+    rc_order = std::move(small);
   }
   const int NS = sink_ptr[ND];
-  const int64_t NN = rc_ptr[ND];
   C->n_sinks = NS;
   C->n_nodes = NN;
   std::vector<int32_t> sink_drv(NS), sink_cons(NS), sink_node(NS), sink_slot(NS), pin_loc(NP);
@@ -561,7 +593,7 @@ static sta_status build_layout(sta_ctx *C, const Inputs &I, const std::vector<in
   for (int x = 0; x < ND; ++x) {
     const int n = I.net_of_drv[drv_pin[x]];
     const int64_t cb = I.net_node_ptr[n];
-    const int m = rc_ptr[x + 1] - rc_ptr[x];
+    const int m = rc_m[x];
     const int base = rc_ptr[x];
     const bool is_big = m > big_thr;
     std::vector<int32_t> newof;
@@ -685,29 +717,39 @@ static sta_status build_layout(sta_ctx *C, const Inputs &I, const std::vector<in
   C->level_chunk_begin[L + 1] = (int)chunk_level.size();
   chunk_start.push_back(ND);
   C->n_chunks = (int)chunk_level.size();
+  std::vector<int4> chunk_rec(C->n_chunks);
+  for (int c = 0; c < C->n_chunks; ++c)
+    chunk_rec[c] = make_int4(chunk_start[c], chunk_start[c + 1], sink_ptr[chunk_start[c]],
+                             sink_ptr[chunk_start[c + 1]]);
+  // inline fanin sink slots when every type has at most 4 inputs
+  int max_in = 0;
+  for (int t = 0; t < lib.n_types; ++t) max_in = std::max(max_in, (int)lib.n_inputs[t]);
+  std::vector<int4> fanin4;
+  if (max_in <= 4) {
+    fanin4.assign(ND, make_int4(-1, -1, -1, -1));
+    for (int x = NPI; x < ND; ++x) {
+      int v[4] = {-1, -1, -1, -1};
+      for (int f = fanin_ptr[x]; f < fanin_ptr[x + 1]; ++f) v[f - fanin_ptr[x]] = fanin_sink[f];
+      fanin4[x] = make_int4(v[0], v[1], v[2], v[3]);
+    }
+  }
+  std::vector<ConsRec> cons_rec(ND);
+  for (int x = 0; x < ND; ++x) {
+    cons_rec[x] = ConsRec{};
+    cons_rec[x].type = cell_type[x];
+  }
 
-  // RC chunks: runs of small nets, <= kRcBlock nets and <= kRcChunkNodes nodes
+  // RC chunks: runs of RC positions, <= kRcBlock nets and <= kRcChunkNodes nodes
   std::vector<int2> rc_chunks;
   {
-    int cx0 = -1, nodes = 0;
-    auto flush = [&](int xend) {
-      if (cx0 >= 0 && xend > cx0) rc_chunks.push_back(make_int2(cx0, xend));
-      cx0 = -1;
-      nodes = 0;
-    };
-    size_t bi = 0;
-    for (int x = 0; x < ND; ++x) {
-      const int m = rc_ptr[x + 1] - rc_ptr[x];
-      if (bi < big_x.size() && big_x[bi] == x) {
-        flush(x);
-        ++bi;
-        continue;
-      }
-      if (cx0 >= 0 && (x - cx0 >= kRcBlock || nodes + m > kRcChunkNodes)) flush(x);
-      if (cx0 < 0) cx0 = x;
-      nodes += m;
+    const int nsm = (int)rc_order.size();
+    int j0 = 0;
+    while (j0 < nsm) {
+      int j1 = j0;
+      while (j1 < nsm && j1 - j0 < kRcBlock && rc_start[j1 + 1] - rc_start[j0] <= kRcChunkNodes) ++j1;
+      rc_chunks.push_back(make_int2(j0, j1));
+      j0 = j1;
     }
-    flush(ND);
   }
   C->n_rc_chunks = (int)rc_chunks.size();
 
@@ -743,6 +785,8 @@ static sta_status build_layout(sta_ctx *C, const Inputs &I, const std::vector<in
   float4 *p4;
   STA_TRY(C->upload(&p32, sink_ptr)); D.sink_ptr = p32;
   STA_TRY(C->upload(&p32, rc_ptr)); D.rc_ptr = p32;
+  STA_TRY(C->upload(&p32, rc_order)); D.rc_order = p32;
+  STA_TRY(C->upload(&p32, rc_start)); D.rc_start = p32;
   STA_TRY(C->upload(&p32, fanin_ptr)); D.fanin_ptr = p32;
   STA_TRY(C->upload(&p32, fanin_sink)); D.fanin_sink = p32;
   STA_TRY(C->upload(&p32, cell_type)); D.cell_type = p32;
@@ -752,27 +796,59 @@ static sta_status build_layout(sta_ctx *C, const Inputs &I, const std::vector<in
   STA_TRY(C->upload(&p32, sink_drv)); D.sink_drv = p32;
   STA_TRY(C->upload(&p32, sink_cons)); D.sink_cons = p32;
   STA_TRY(C->upload(&p32, sink_node)); D.sink_node = p32;
-  STA_TRY(C->upload(&pf, sink_pincap)); D.sink_pincap = pf;
-  STA_TRY(C->upload(&p32, rc_parent)); D.rc_parent = p32;
+  {
+    // small-net parents as bytes, lumped pin caps per node, sink ranges per RC position
+    std::vector<uint8_t> par8(NN, 0);
+    std::vector<double> pcd(NN, 0.0);
+    std::vector<int2> rc_sinks(rc_order.size());
+    for (int x = 0; x < ND; ++x) {
+      const int base = rc_ptr[x];
+      for (int s = sink_ptr[x]; s < sink_ptr[x + 1]; ++s) pcd[base + sink_node[s]] += sink_pincap[s];
+      if (rc_m[x] > big_thr) continue;
+      for (int k = 1; k < rc_m[x]; ++k) par8[base + k] = (uint8_t)rc_parent[base + k];
+    }
+    for (size_t j = 0; j < rc_order.size(); ++j)
+      rc_sinks[j] = make_int2(sink_ptr[rc_order[j]], sink_ptr[rc_order[j] + 1]);
+    std::vector<float> pcf(pcd.begin(), pcd.end());
+    uint8_t *p8;
+    STA_TRY(C->upload(&p8, par8)); D.rc_par8 = p8;
+    STA_TRY(C->upload(&pf, pcf)); D.rc_pc = pf;
+    int2 *p2;
+    STA_TRY(C->upload(&p2, rc_sinks)); D.rc_sinks = p2;
+  }
   STA_TRY(C->upload(&pf, rc_res)); D.rc_res = pf;
   STA_TRY(C->upload(&C->rc_cap, rc_cap)); D.rc_cap = C->rc_cap;
   STA_TRY(C->upload(&p4, ep_rat)); D.ep_rat = p4;
   STA_TRY(C->upload(&pf, tab)); D.tables = pf;
   STA_TRY(C->upload(&p32, sense)); D.sense = p32;
   STA_TRY(C->upload(&p32, chunk_start)); D.chunk_start = p32;
+  {
+    int4 *p4i;
+    STA_TRY(C->upload(&p4i, chunk_rec)); D.chunk_rec = p4i;
+    D.fanin4 = nullptr;
+    if (!fanin4.empty()) {
+      STA_TRY(C->upload(&p4i, fanin4));
+      D.fanin4 = p4i;
+    }
+    ConsRec *pcr;
+    STA_TRY(C->upload(&pcr, cons_rec)); D.cons_rec = pcr;
+  }
   STA_TRY(C->upload(&p32, chunk_level)); D.chunk_level = p32;
   STA_TRY(C->upload(&p32, level_nchunks)); D.level_nchunks = p32;
+  {
+    std::vector<int32_t> lcb(C->level_chunk_begin.begin(), C->level_chunk_begin.end());
+    STA_TRY(C->upload(&p32, lcb)); D.level_cbeg = p32;
+  }
   STA_TRY(C->alloc(&D.L_net, ND));
   STA_TRY(C->alloc(&D.dq, NS));
   STA_TRY(C->alloc(&D.drv_state, ND));
   STA_TRY(C->alloc(&D.sink_state, NS));
   STA_TRY(C->alloc(&D.drv_crit, ND));
-  STA_TRY(C->alloc(&D.drv_rat, ND));
   STA_TRY(C->alloc(&D.sink_rat, NS));
   STA_TRY(C->alloc(&D.drv_slack, ND));
   STA_TRY(C->alloc(&D.sink_slack, NS));
   STA_TRY(C->alloc(&D.ep_slack, C->n_ep));
-  const int n_ctr = kCtrLevels + 2 * (L + 1);
+  const int n_ctr = n_counters(L);
   STA_TRY(C->alloc(&D.counters, n_ctr));
   HIP_TRY(hipMemset(D.counters, 0, n_ctr * sizeof(uint32_t)));
 
@@ -828,12 +904,21 @@ static sta_status build_layout(sta_ctx *C, const Inputs &I, const std::vector<in
   HIP_TRY(hipEventCreateWithFlags(&C->ev_fork, hipEventDisableTiming));
   HIP_TRY(hipEventCreateWithFlags(&C->ev_join, hipEventDisableTiming));
 
-  // persistent grid: every resident block slot on the device
+  // persistent grid: every resident block slot on the device.  The level-major
+  // cooperative kernels need every block resident, which the cooperative
+  // launch guarantees; without cooperative launch support, or for a requested
+  // grid beyond the resident limit, the ticket kernels (correct for any grid)
+  // are used.
   const size_t lds = sweep_lds_bytes(D);
   if (lds > 160 * 1024) return fail(STA_E_UNSUPPORTED, "library too large for LDS (%zu bytes)", lds);
   C->sweep_grid = sweep_blocks_per_cu(lds) * C->n_cu;
   if (C->sweep_grid < 1) C->sweep_grid = 1;
+  int coop_ok = 0;
+  HIP_TRY(hipDeviceGetAttribute(&coop_ok, hipDeviceAttributeCooperativeLaunch, C->device));
+  C->coop_max = coop_ok ? coop_blocks_per_cu(lds) * C->n_cu : 0;
+  if (C->coop_max > 0) C->sweep_grid = C->coop_max;
   if (C->opt.sweep_blocks > 0) C->sweep_grid = C->opt.sweep_blocks;
+  C->coop = C->sweep_grid <= C->coop_max;
   return STA_OK;
 }
 
@@ -1150,7 +1235,7 @@ static sta_status enqueue_update(sta_ctx *C, hipStream_t s, bool prof) {
   if (prof) HIP_TRY(hipEventRecord(C->ev[1], s));
   if (prof) HIP_TRY(hipEventRecord(C->ev[2], s));
   if (!per_level) {
-    HIP_TRY(launch_forward(D, C->sweep_grid, s));
+    HIP_TRY(launch_forward(D, C->sweep_grid, C->coop, s));
   } else {
     for (int l = 0; l <= C->n_cell_levels; ++l)
       HIP_TRY(launch_forward_level(D, C->level_chunk_begin[l], C->level_chunk_begin[l + 1], s));
@@ -1158,7 +1243,7 @@ static sta_status enqueue_update(sta_ctx *C, hipStream_t s, bool prof) {
   if (prof) HIP_TRY(hipEventRecord(C->ev[3], s));
   if (!smooth) {  // the smooth objective needs arrivals only; it skips the RAT sweep
     if (!per_level) {
-      HIP_TRY(launch_backward(D, C->sweep_grid, s));
+      HIP_TRY(launch_backward(D, C->sweep_grid, C->coop, s));
     } else {
       for (int l = C->n_cell_levels; l >= 0; --l)
         HIP_TRY(launch_backward_level(D, C->level_chunk_begin[l], C->level_chunk_begin[l + 1], s));
@@ -1243,9 +1328,9 @@ extern "C" sta_status sta_backward(sta_ctx *C, float g_tns, float g_wns, float *
   const bool prof = C->opt.profile != 0;
   const DevDesign &D = C->D;
   if (prof) HIP_TRY(hipEventRecord(C->ev[7], s));
-  HIP_TRY(launch_reset_counters(D.counters, kCtrLevels + 2 * (C->n_cell_levels + 1), s));
+  HIP_TRY(launch_reset_counters(D.counters, n_counters(C->n_cell_levels), s));
   if (C->opt.sched == STA_SCHED_PERSISTENT) {
-    HIP_TRY(launch_adjoint(D, g_tns, g_wns, C->sweep_grid, s));
+    HIP_TRY(launch_adjoint(D, g_tns, g_wns, C->sweep_grid, C->coop, s));
   } else {
     for (int l = C->n_cell_levels; l >= 0; --l)
       HIP_TRY(launch_adjoint_level(D, g_tns, g_wns, C->level_chunk_begin[l], C->level_chunk_begin[l + 1], s));
@@ -1442,7 +1527,8 @@ extern "C" sta_status sta_autotune(sta_ctx *C, int32_t reps, sta_tune_result *be
   hipStream_t s = static_cast<hipStream_t>(stream);
   struct Cand { int sched, grid; };
   std::vector<Cand> cands;
-  const int max_per_cu = std::max(1, sweep_blocks_per_cu(sweep_lds_bytes(C->D)));
+  const int max_per_cu = std::max(1, C->coop_max > 0 ? C->coop_max / std::max(1, C->n_cu)
+                                                    : sweep_blocks_per_cu(sweep_lds_bytes(C->D)));
   const int max_grid = max_per_cu * C->n_cu;
   for (int k = 1; k <= max_per_cu; ++k) cands.push_back({STA_SCHED_PERSISTENT, k * C->n_cu});
   cands.push_back({STA_SCHED_PER_LEVEL, max_grid});
@@ -1458,6 +1544,7 @@ extern "C" sta_status sta_autotune(sta_ctx *C, int32_t reps, sta_tune_result *be
   for (const Cand &c : cands) {
     C->opt.sched = c.sched;
     C->sweep_grid = c.grid;
+    C->coop = c.grid <= C->coop_max;
     st = sta_update_timing(C, s);  // warm-up (builds the graph once)
     if (st != STA_OK) break;
     hipError_t e = hipEventRecord(e0, s);
@@ -1484,10 +1571,12 @@ extern "C" sta_status sta_autotune(sta_ctx *C, int32_t reps, sta_tune_result *be
   C->opt = saved;
   if (st != STA_OK) {
     C->sweep_grid = max_grid;
+    C->coop = max_grid <= C->coop_max;
     return st;
   }
   C->opt.sched = r.sched;
   C->sweep_grid = r.sweep_blocks;
+  C->coop = r.sweep_blocks <= C->coop_max;
   r.ms = best_ms;
   if (best) *best = r;
   return STA_OK;

@@ -26,6 +26,7 @@ constexpr int kSweepBlock = 256;            // 4 waves, each wave owns one chunk
 constexpr int kChunk = kWave;               // driver slots per sweep chunk
 constexpr int kRcBlock = 256;               // one small net per thread
 constexpr int kRcChunkNodes = 2048;         // RC nodes staged in LDS per block
+constexpr int kRcSortWindow = 4096;         // slots within which small nets are ordered by size
 constexpr int kSmallNetMaxNodes = 255;      // parents fit in a byte
 constexpr int kReduceBlocks = 128;
 
@@ -38,7 +39,21 @@ struct alignas(32) PinState {
 constexpr int kCtrFwdTicket = 0;
 constexpr int kCtrBwdTicket = 1;
 constexpr int kCtrReduce = 2;
-constexpr int kCtrLevels = 4;  // fwd_done[L+1] then bwd_done[L+1]
+constexpr int kCtrLevels = 4;  // then per sweep (forward, backward) and level: kDoneGroups counters
+constexpr int kDoneGroups = 8;  // completion counters per level (block b bumps group b % 8)
+__host__ __device__ inline int n_counters(int n_cell_levels) {
+  return kCtrLevels + 2 * (n_cell_levels + 1) * kDoneGroups;
+}
+
+// What the backward sweep gathers about a consumer cell, in one 32-byte record:
+// its output RAT (written by the sweep), NLDM load (written by the RC pass) and
+// library type (fixed).
+struct __align__(32) ConsRec {
+  float4 rat;
+  float L;
+  int32_t type;
+  float pad0, pad1;
+};
 
 struct DevDesign {
   int32_t n_drv, n_pi, n_sinks, n_ep, n_cell_levels;
@@ -47,7 +62,9 @@ struct DevDesign {
 
   // driver slots
   const int32_t *sink_ptr;    // [n_drv+1]
-  const int32_t *rc_ptr;      // [n_drv+1]
+  const int32_t *rc_ptr;      // [n_drv] first RC node of each net (RC order, not monotone in slot)
+  const int32_t *rc_order;    // [small nets] slot at each RC position
+  const int32_t *rc_start;    // [small nets + 1] first node at each RC position (monotone)
   const int32_t *fanin_ptr;   // [n_drv+1] (empty for PIs)
   const int32_t *fanin_sink;  // sink slot of each cell input, fanin order
   const int32_t *cell_type;   // [n_drv] (-1 for PIs)
@@ -59,10 +76,11 @@ struct DevDesign {
   const int32_t *sink_drv;    // [n_sinks] driver slot
   const int32_t *sink_cons;   // [n_sinks] consumer driver slot, or -1 - endpoint
   const int32_t *sink_node;   // [n_sinks] net-local RC node
-  const float *sink_pincap;   // [n_sinks]
 
   // RC nodes
-  const int32_t *rc_parent;   // net-local, -1 at the root
+  const uint8_t *rc_par8;     // net-local parent of a small-net node (root: 0, unused); 0 on wide nets
+  const float *rc_pc;         // receiving pin caps lumped at each node (fixed), summed in sink order
+  const int2 *rc_sinks;       // [small nets] sink-slot range at each RC position
   const float *rc_res;
   const float *rc_cap;
 
@@ -79,7 +97,8 @@ struct DevDesign {
   PinState *drv_state;        // [n_drv]
   PinState *sink_state;       // [n_sinks]
   uint32_t *drv_crit;         // [n_drv] four int8 critical-fanin codes
-  float4 *drv_rat, *sink_rat;
+  ConsRec *cons_rec;          // [n_drv] RAT / load / type per driver slot
+  float4 *sink_rat;
   float4 *drv_slack, *sink_slack;
   float2 *ep_slack;           // [n_ep] (early, late)
 
@@ -96,8 +115,11 @@ struct DevDesign {
 
   // sweep schedule
   const int32_t *chunk_start;   // [n_chunks+1] driver-slot ranges
+  const int4 *chunk_rec;        // [n_chunks] (first slot, end slot, first sink, end sink)
+  const int4 *fanin4;           // [n_drv] input sink slots of each cell, -1 padded; NULL if a type has > 4 inputs
   const int32_t *chunk_level;   // [n_chunks]
   const int32_t *level_nchunks; // [n_cell_levels+1]
+  const int32_t *level_cbeg;    // [n_cell_levels+2] first chunk of each level
   uint32_t *counters;
 };
 
@@ -137,14 +159,16 @@ struct WideNets {
 hipError_t launch_rc(const DevDesign &D, const int2 *chunks, int n_chunks, hipStream_t s);
 hipError_t launch_rc_wide(const DevDesign &D, const WideNets &W, hipStream_t s);
 hipError_t launch_rc_adjoint_wide(const DevDesign &D, const WideNets &W, hipStream_t s);
-hipError_t launch_forward(const DevDesign &D, int persistent_grid, hipStream_t s);
+// Persistent sweeps: with coop, the level-major static schedule on a
+// cooperative (co-resident) grid; otherwise the ticket schedule.
+hipError_t launch_forward(const DevDesign &D, int persistent_grid, bool coop, hipStream_t s);
 hipError_t launch_forward_level(const DevDesign &D, int c0, int c1, hipStream_t s);
-hipError_t launch_backward(const DevDesign &D, int persistent_grid, hipStream_t s);
+hipError_t launch_backward(const DevDesign &D, int persistent_grid, bool coop, hipStream_t s);
 hipError_t launch_backward_level(const DevDesign &D, int c0, int c1, hipStream_t s);
 hipError_t launch_reset_counters(uint32_t *counters, int n, hipStream_t s);
 hipError_t launch_reduce_smooth(const DevDesign &D, double *partials, double *out, uint32_t *keys,
                                 int32_t *vals, hipStream_t s);
-hipError_t launch_adjoint(const DevDesign &D, float g_tns, float g_wns, int persistent_grid,
+hipError_t launch_adjoint(const DevDesign &D, float g_tns, float g_wns, int persistent_grid, bool coop,
                           hipStream_t s);
 hipError_t launch_adjoint_level(const DevDesign &D, float g_tns, float g_wns, int c0, int c1,
                                 hipStream_t s);
@@ -166,6 +190,7 @@ size_t sort_temp_bytes64(int n, int end_bit);
 hipError_t sort_endpoints64(void *temp, size_t temp_bytes, const uint64_t *keys_in, uint64_t *keys_out,
                             const int32_t *vals_in, int32_t *vals_out, int n, int end_bit, hipStream_t s);
 int sweep_blocks_per_cu(size_t lds_bytes);
+int coop_blocks_per_cu(size_t lds_bytes);
 size_t sweep_lds_bytes(const DevDesign &D);
 
 // levelization

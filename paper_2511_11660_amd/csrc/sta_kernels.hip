@@ -157,9 +157,9 @@ __device__ LdsLib load_lib(const DevDesign &D, unsigned char *smem) {
   for (int b = 0; b < n4; b += kU * (int)blockDim.x) {
     float4 v[kU];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const int i = b + u * (int)blockDim.x + (int)threadIdx.x;
-      if (i < n4) v[u] = src[i];
+    for (int u = 0; u < kU; ++u) {  // clamped, unpredicated: all loads in flight together
+      const int i = min(b + u * (int)blockDim.x + (int)threadIdx.x, n4 - 1);
+      v[u] = src[i];
     }
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
@@ -183,94 +183,153 @@ __host__ __device__ inline size_t lib_lds_bytes(int n_types, int tstride) {
 // (late max, early min), slew merged the same way independent of the AT
 // winner; the critical code is 2*fanin + input transition of the AT winner,
 // ties kept by the earlier candidate.
-template <bool kCoh>
-__device__ __forceinline__ void cell_forward(const DevDesign &D, const LdsLib &lib, int x,
-                                             PinState &out, uint32_t &crit) {
-  const int t = D.cell_type[x];
-  const int sense = lib.sense[t];
-  const float L = D.L_net[x];
+// Arrival/slew merge of one cell output over its fanin arcs: AT_in + delay
+// (late max, early min), slew merged the same way independent of the AT
+// winner; the critical code is 2*fanin + input transition of the AT winner,
+// ties kept by the earlier candidate.  In smooth mode (gamma > 0) the late
+// merges keep a running log-sum-exp: lse[ro] = sum exp((z - max) / gamma)
+// against the running max at[2 + ro].
+struct Merge {
+  float at[4], sl[4], lse[2];
+  int cr[4];
+};
+
+struct CellCtx {
+  int sense;
+  const float *tb;
+  AxisPos py;
+};
+
+__device__ __forceinline__ CellCtx cell_ctx(const DevDesign &D, const LdsLib &lib, int t, float L) {
   const TabLayout lay{D.nx, D.ny};
   const float *tb = lib.tab + t * D.tstride;
-  const AxisPos py = axis_find(tb + lay.ya(), tb + lay.rdy(), D.ny, L);
-  float at[4] = {kInf, kInf, -kInf, -kInf};
-  float sl[4] = {kInf, kInf, -kInf, -kInf};
-  int cr[4] = {-1, -1, -1, -1};
-  // smooth mode: running log-sum-exp of the late candidates, sum of
-  // exp((z - max) / gamma) kept against the running max at[2 + ro]
+  return {lib.sense[t], tb, axis_find(tb + lay.ya(), tb + lay.rdy(), D.ny, L)};
+}
+
+__device__ __forceinline__ void merge_init(Merge &m) {
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    m.at[v] = v < 2 ? kInf : -kInf;
+    m.sl[v] = v < 2 ? kInf : -kInf;
+    m.cr[v] = -1;
+  }
+  m.lse[0] = m.lse[1] = 0.0f;
+}
+
+__device__ __forceinline__ void merge_one(const DevDesign &D, const CellCtx &cc, const PinState &in, int pos,
+                                          Merge &m) {
+  const TabLayout lay{D.nx, D.ny};
   const float g = D.gamma;
-  float lse[2] = {0.0f, 0.0f};
-  const int f0 = D.fanin_ptr[x], f1 = D.fanin_ptr[x + 1];
-  for (int f = f0; f < f1; ++f) {
-    const PinState in = ld_state<kCoh>(D.sink_state + D.fanin_sink[f]);
-    const float ia[4] = {in.at.x, in.at.y, in.at.z, in.at.w};
-    const float is[4] = {in.slew.x, in.slew.y, in.slew.z, in.slew.w};
-    const int k2 = (f - f0) * 2;
+  const float ia[4] = {in.at.x, in.at.y, in.at.z, in.at.w};
+  const float is[4] = {in.slew.x, in.slew.y, in.slew.z, in.slew.w};
+  const int k2 = pos * 2;
 #pragma unroll
-    for (int el = 0; el < 2; ++el) {
+  for (int el = 0; el < 2; ++el) {
 #pragma unroll
-      for (int ri = 0; ri < 2; ++ri) {
-        const int vi = el * 2 + ri;
-        const AxisPos px = axis_find(tb + lay.xa(), tb + lay.rdx(), D.nx, is[vi]);
+    for (int ri = 0; ri < 2; ++ri) {
+      const int vi = el * 2 + ri;
+      const AxisPos px = axis_find(cc.tb + lay.xa(), cc.tb + lay.rdx(), D.nx, is[vi]);
 #pragma unroll
-        for (int ro = 0; ro < 2; ++ro) {
-          if (!arc_maps(sense, ri, ro)) continue;
-          const int vo = el * 2 + ro;
-          const float dl = bilerp(tb + lay.tab(ro), D.ny, px, py);
-          const float os = bilerp(tb + lay.tab(2 + ro), D.ny, px, py);
-          const float cand = ia[vi] + dl;
-          if (el ? cand > at[vo] : cand < at[vo]) {
-            if (el && g > 0.0f) lse[ro] = lse[ro] * expf((at[vo] - cand) / g) + 1.0f;
-            at[vo] = cand;
-            cr[vo] = k2 + ri;
-          } else if (el && g > 0.0f) {
-            lse[ro] += expf((cand - at[vo]) / g);
-          }
-          sl[vo] = el ? fmaxf(sl[vo], os) : fminf(sl[vo], os);
+      for (int ro = 0; ro < 2; ++ro) {
+        if (!arc_maps(cc.sense, ri, ro)) continue;
+        const int vo = el * 2 + ro;
+        const float dl = bilerp(cc.tb + lay.tab(ro), D.ny, px, cc.py);
+        const float os = bilerp(cc.tb + lay.tab(2 + ro), D.ny, px, cc.py);
+        const float cand = ia[vi] + dl;
+        if (el ? cand > m.at[vo] : cand < m.at[vo]) {
+          if (el && g > 0.0f) m.lse[ro] = m.lse[ro] * expf((m.at[vo] - cand) / g) + 1.0f;
+          m.at[vo] = cand;
+          m.cr[vo] = k2 + ri;
+        } else if (el && g > 0.0f) {
+          m.lse[ro] += expf((cand - m.at[vo]) / g);
         }
+        m.sl[vo] = el ? fmaxf(m.sl[vo], os) : fminf(m.sl[vo], os);
       }
     }
   }
+}
+
+__device__ __forceinline__ void merge_finish(const DevDesign &D, Merge &m, PinState &out, uint32_t &crit) {
+  const float g = D.gamma;
   if (g > 0.0f) {
-    at[2] += g * logf(lse[0]);
-    at[3] += g * logf(lse[1]);
+    m.at[2] += g * logf(m.lse[0]);
+    m.at[3] += g * logf(m.lse[1]);
   }
-  out.at = make_float4(at[0], at[1], at[2], at[3]);
-  out.slew = make_float4(sl[0], sl[1], sl[2], sl[3]);
-  crit = (uint32_t)(cr[0] & 0xff) | ((uint32_t)(cr[1] & 0xff) << 8) |
-         ((uint32_t)(cr[2] & 0xff) << 16) | ((uint32_t)(cr[3] & 0xff) << 24);
+  out.at = make_float4(m.at[0], m.at[1], m.at[2], m.at[3]);
+  out.slew = make_float4(m.sl[0], m.sl[1], m.sl[2], m.sl[3]);
+  crit = (uint32_t)(m.cr[0] & 0xff) | ((uint32_t)(m.cr[1] & 0xff) << 8) |
+         ((uint32_t)(m.cr[2] & 0xff) << 16) | ((uint32_t)(m.cr[3] & 0xff) << 24);
+}
+
+// Cells of a library with types of more than 4 inputs: fanins through the CSR.
+template <bool kCoh>
+__device__ void cell_forward_csr(const DevDesign &D, const LdsLib &lib, int x, PinState &out, uint32_t &crit) {
+  const int f0 = D.fanin_ptr[x], f1 = D.fanin_ptr[x + 1];
+  const CellCtx cc = cell_ctx(D, lib, D.cell_type[x], D.L_net[x]);
+  Merge m;
+  merge_init(m);
+  for (int f = f0; f < f1; ++f) merge_one(D, cc, ld_state<kCoh>(D.sink_state + D.fanin_sink[f]), f - f0, m);
+  merge_finish(D, m, out, crit);
 }
 
 // One chunk: the 64 drivers, then every sink of their nets
-// (AT_s = AT_drv + d, slew_s = sqrt(slew_drv^2 + q)).
+// (AT_s = AT_drv + d, slew_s = sqrt(slew_drv^2 + q)).  Every load that does
+// not depend on another is issued first (sink metadata of the first two sink
+// rounds, the drivers' type, load and inline fanin ids), then the input-state
+// gathers, then the arithmetic: about three memory round trips per chunk.
 template <bool kCoh>
 __device__ void fwd_chunk(const DevDesign &D, const LdsLib &lib, PinState *wst, int c) {
   const int lane = lane_id();
-  const int x0 = D.chunk_start[c], x1 = D.chunk_start[c + 1];
+  const int4 cr = D.chunk_rec[c];
+  const int x0 = __builtin_amdgcn_readfirstlane(cr.x), x1 = __builtin_amdgcn_readfirstlane(cr.y);
+  const int s0 = __builtin_amdgcn_readfirstlane(cr.z), s1 = __builtin_amdgcn_readfirstlane(cr.w);
+  const int smax = max(s1 - 1, 0);
+  const int sA = s0 + lane, sB = sA + kWave;
+  const int dA = D.sink_drv[min(sA, smax)], dB = D.sink_drv[min(sB, smax)];
+  const float2 wA = D.dq[min(sA, smax)], wB = D.dq[min(sB, smax)];
   const int x = x0 + lane;
-  if (x < x1) {
-    PinState st;
-    uint32_t crit = 0xffffffffu;
-    if (x < D.n_pi) {
-      st.at = D.pi_at[x];
-      st.slew = D.pi_slew[x];
-    } else {
-      cell_forward<kCoh>(D, lib, x, st, crit);
-    }
+  const bool live = x < x1;
+  const int xc = live ? x : x0;
+  PinState st;
+  uint32_t crit = 0xffffffffu;
+  if (x0 < D.n_pi) {  // level 0: primary inputs only
+    st.at = D.pi_at[xc];
+    st.slew = D.pi_slew[xc];
+  } else if (D.fanin4) {
+    const int t = D.cell_type[xc];
+    const float L = D.L_net[xc];
+    const int4 f4 = D.fanin4[xc];
+    const int fs[4] = {f4.x, f4.y, f4.z, f4.w};
+    PinState in[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) in[k] = ld_state<kCoh>(D.sink_state + max(fs[k], 0));
+    const CellCtx cc = cell_ctx(D, lib, t, L);
+    Merge m;
+    merge_init(m);
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (fs[k] >= 0) merge_one(D, cc, in[k], k, m);
+    merge_finish(D, m, st, crit);
+  } else {
+    cell_forward_csr<kCoh>(D, lib, xc, st, crit);
+  }
+  if (live) {
     D.drv_state[x] = st;
     D.drv_crit[x] = crit;
     wst[lane] = st;
   }
   wave_sync();
-  const int s0 = D.sink_ptr[x0], s1 = D.sink_ptr[x1];
-  for (int s = s0 + lane; s < s1; s += kWave) {
-    const PinState ds = wst[D.sink_drv[s] - x0];
-    const float2 w = D.dq[s];
+  auto emit = [&](int s, int drv, float2 w) {
+    const PinState ds = wst[drv - x0];
     PinState o;
     o.at = make_float4(ds.at.x + w.x, ds.at.y + w.x, ds.at.z + w.x, ds.at.w + w.x);
     o.slew = make_float4(sqrtf(ds.slew.x * ds.slew.x + w.y), sqrtf(ds.slew.y * ds.slew.y + w.y),
                          sqrtf(ds.slew.z * ds.slew.z + w.y), sqrtf(ds.slew.w * ds.slew.w + w.y));
     st_state<kCoh>(D.sink_state + s, o);
-  }
+  };
+  if (sA < s1) emit(sA, dA, wA);
+  if (sB < s1) emit(sB, dB, wB);
+  for (int s = sB + kWave; s < s1; s += kWave) emit(s, D.sink_drv[s], D.dq[s]);
   wave_sync();
 }
 
@@ -281,9 +340,22 @@ __device__ void fwd_chunk(const DevDesign &D, const LdsLib &lib, PinState *wst, 
 // iterate together.  (With `if (lane == 0) atomic` at both ends of the loop,
 // jump threading merged the two regions into a lane-0-only path and the
 // other lanes re-entered the loop without a ticket.)
-__device__ __forceinline__ void wait_count(uint32_t *ctr, uint32_t target) {
+// Completion counters of sweep sw (0 forward / adjoint, 1 backward) at level
+// l: kDoneGroups words whose sum is the number of the level's chunks done.
+__device__ __forceinline__ uint32_t *level_ctr(const DevDesign &D, int sw, int l) {
+  return D.counters + kCtrLevels + ((size_t)sw * (D.n_cell_levels + 1) + l) * kDoneGroups;
+}
+
+// Polls until the level's group counters sum to target.  Every lane loads one
+// of the group words (lane & 7) and the sum is formed across 8 lanes, so the
+// loop has no divergent branch.
+__device__ __forceinline__ void wait_level(uint32_t *ctr, uint32_t target) {
   for (;;) {
-    const uint32_t v = __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t v = __hip_atomic_load(ctr + (lane_id() & (kDoneGroups - 1)), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+    v += __shfl_xor(v, 1);
+    v += __shfl_xor(v, 2);
+    v += __shfl_xor(v, 4);
     if (__builtin_amdgcn_readfirstlane(v) >= target) break;
     __builtin_amdgcn_s_sleep(1);
   }
@@ -299,10 +371,46 @@ __device__ __forceinline__ int take_ticket(uint32_t *ctr) {
 
 // Every coherent store of this wave has completed (vmcnt 0) before the counter
 // moves, so a consumer that sees the count reads the new values.
-__device__ __forceinline__ void signal_done(uint32_t *ctr) {
+__device__ __forceinline__ void signal_add(uint32_t *ctr, uint32_t n) {
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
   __builtin_amdgcn_s_waitcnt(0);
-  __hip_atomic_fetch_add(ctr, lane_id() == 0 ? 1u : 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_fetch_add(ctr, lane_id() == 0 ? n : 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Level-major static schedule for a cooperative grid (every block resident):
+// of each level, in sweep order, wave w of W takes chunks c0 + w, c0 + w + W,
+// ...  A block with chunks in a level first waits until the previous level in
+// sweep order is complete (which implies all earlier ones: every level has
+// chunks, each processed after its own wait), runs them, waits for its waves'
+// stores, and bumps its group counter by their number; blocks without chunks
+// in a level skip it entirely.  No per-chunk atomics.
+template <bool kReverse, class Body>
+__device__ __forceinline__ void coop_levels(const DevDesign &D, int sw, Body body) {
+  constexpr int kWaves = kSweepBlock / kWave;
+  const int L = D.n_cell_levels;
+  const int W = (int)gridDim.x * kWaves;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int b0 = blockIdx.x * kWaves;
+  const int g = blockIdx.x & (kDoneGroups - 1);
+  int prev = -1;
+  for (int i = 0; i <= L; ++i) {
+    const int l = kReverse ? L - i : i;
+    const int c0 = D.level_cbeg[l], n = D.level_cbeg[l + 1] - c0;
+    int mine = 0;
+#pragma unroll
+    for (int k = 0; k < kWaves; ++k)
+      if (b0 + k < n) mine += (n - (b0 + k) + W - 1) / W;
+    if (mine > 0) {
+      if (prev >= 0 && wave == 0)
+        wait_level(level_ctr(D, sw, prev), (uint32_t)(D.level_cbeg[prev + 1] - D.level_cbeg[prev]));
+      __syncthreads();
+      for (int c = c0 + b0 + wave; c < c0 + n; c += W) body(c);
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      if (wave == 0) signal_add(level_ctr(D, sw, l) + g, (uint32_t)mine);
+    }
+    prev = l;
+  }
 }
 
 template <bool kPersistent>
@@ -313,14 +421,13 @@ __global__ __launch_bounds__(kSweepBlock) void k_forward(DevDesign D, int c0, in
                   (threadIdx.x / kWave) * kWave;
   __syncthreads();
   if constexpr (kPersistent) {
-    uint32_t *done = D.counters + kCtrLevels;
     for (;;) {
       const int c = take_ticket(D.counters + kCtrFwdTicket);
       if (c >= D.n_chunks) break;
       const int lvl = D.chunk_level[c];
-      if (lvl > 0) wait_count(done + lvl - 1, (uint32_t)D.level_nchunks[lvl - 1]);
+      if (lvl > 0) wait_level(level_ctr(D, 0, lvl - 1), (uint32_t)D.level_nchunks[lvl - 1]);
       fwd_chunk<true>(D, lib, wst, c);
-      signal_done(done + lvl);
+      signal_add(level_ctr(D, 0, lvl), 1u);
     }
   } else {
     const int c = c0 + blockIdx.x * (kSweepBlock / kWave) + threadIdx.x / kWave;
@@ -334,76 +441,94 @@ __global__ __launch_bounds__(kSweepBlock) void k_forward(DevDesign D, int c0, in
 // consumer cell's output RAT minus the recomputed arc delay, min for late and
 // max for early over the output transitions the input reaches) or from its
 // endpoint constraint; the drivers merge RAT_s - d over their sinks.
+// RAT of one sink: its endpoint constraint, or its consumer cell's output RAT
+// minus the recomputed arc delay (min for late, max for early over the output
+// transitions the input reaches).
+template <bool kCoh>
+__device__ __forceinline__ float4 sink_rat(const DevDesign &D, const LdsLib &lib, const PinState &ss, int cons) {
+  if (cons < 0) return D.ep_rat[-1 - cons];
+  const TabLayout lay{D.nx, D.ny};
+  // consumer's output RAT, load and type: one 32-byte record
+  const float4 Ro4 = ld4<kCoh>(&D.cons_rec[cons].rat);
+  const float2 Lt = *reinterpret_cast<const float2 *>(&D.cons_rec[cons].L);
+  const int t = __float_as_int(Lt.y);
+  const int sense = lib.sense[t];
+  const float Ro[4] = {Ro4.x, Ro4.y, Ro4.z, Ro4.w};
+  const float is[4] = {ss.slew.x, ss.slew.y, ss.slew.z, ss.slew.w};
+  const float *tb = lib.tab + t * D.tstride;
+  const AxisPos py = axis_find(tb + lay.ya(), tb + lay.rdy(), D.ny, Lt.x);
+  float r[4];
+#pragma unroll
+  for (int el = 0; el < 2; ++el) {
+#pragma unroll
+    for (int ri = 0; ri < 2; ++ri) {
+      const int vi = el * 2 + ri;
+      const AxisPos px = axis_find(tb + lay.xa(), tb + lay.rdx(), D.nx, is[vi]);
+      float best = el ? kInf : -kInf;
+#pragma unroll
+      for (int ro = 0; ro < 2; ++ro) {
+        if (!arc_maps(sense, ri, ro)) continue;
+        const float cand = Ro[el * 2 + ro] - bilerp(tb + lay.tab(ro), D.ny, px, py);
+        best = el ? fminf(best, cand) : fmaxf(best, cand);
+      }
+      r[vi] = best;
+    }
+  }
+  return make_float4(r[0], r[1], r[2], r[3]);
+}
+
+// One chunk: every sink of the 64 drivers gets its RAT (sink_rat) and slack;
+// the drivers merge RAT_s - d over their sinks through LDS integer atomics on
+// order-preserving keys, starting from the neutral element; a dangling
+// endpoint driver's own constraint joins the merge last (min/max are
+// order-independent, so the result is the same and bit-reproducible).  The
+// first sink round and the driver records are requested before any
+// dependent load.
 template <bool kCoh>
 __device__ void bwd_chunk(const DevDesign &D, const LdsLib &lib, int *wacc, int c) {
   const int lane = lane_id();
-  const int x0 = D.chunk_start[c], x1 = D.chunk_start[c + 1];
+  const int4 cr = D.chunk_rec[c];
+  const int x0 = __builtin_amdgcn_readfirstlane(cr.x), x1 = __builtin_amdgcn_readfirstlane(cr.y);
+  const int s0 = __builtin_amdgcn_readfirstlane(cr.z), s1 = __builtin_amdgcn_readfirstlane(cr.w);
+  const int smax = max(s1 - 1, 0);
+  const int sA = s0 + lane, sAc = min(sA, smax);
+  const PinState ssA = D.sink_state[sAc];
+  const int consA = D.sink_cons[sAc];
+  const float dA = D.dq[sAc].x;
+  const int drvA = D.sink_drv[sAc];
   const int x = x0 + lane;
-  if (x < x1) {
-    float4 init = make_float4(-kInf, -kInf, kInf, kInf);
-    const int e = D.drv_ep[x];
-    if (e >= 0) init = D.ep_rat[e];
-    wacc[lane * 4 + 0] = f2key(init.x);
-    wacc[lane * 4 + 1] = f2key(init.y);
-    wacc[lane * 4 + 2] = f2key(init.z);
-    wacc[lane * 4 + 3] = f2key(init.w);
-  }
+  const bool live = x < x1;
+  const int xc = live ? x : x0;
+  const int e = D.drv_ep[xc];
+  const float4 A = D.drv_state[xc].at;
+  wacc[lane * 4 + 0] = f2key(-kInf);
+  wacc[lane * 4 + 1] = f2key(-kInf);
+  wacc[lane * 4 + 2] = f2key(kInf);
+  wacc[lane * 4 + 3] = f2key(kInf);
   wave_sync();
-  const TabLayout lay{D.nx, D.ny};
-  const int s0 = D.sink_ptr[x0], s1 = D.sink_ptr[x1];
-  for (int s = s0 + lane; s < s1; s += kWave) {
-    const PinState ss = D.sink_state[s];
-    const int cons = D.sink_cons[s];
-    float4 R;
-    if (cons < 0) {
-      const int e = -1 - cons;
-      R = D.ep_rat[e];
-      D.ep_slack[e] = ep_slack2(ss.at, R);
-    } else {
-      const int t = D.cell_type[cons];
-      const int sense = lib.sense[t];
-      const float L = D.L_net[cons];
-      const float4 Ro4 = ld4<kCoh>(D.drv_rat + cons);
-      const float Ro[4] = {Ro4.x, Ro4.y, Ro4.z, Ro4.w};
-      const float is[4] = {ss.slew.x, ss.slew.y, ss.slew.z, ss.slew.w};
-      const float *tb = lib.tab + t * D.tstride;
-      const AxisPos py = axis_find(tb + lay.ya(), tb + lay.rdy(), D.ny, L);
-      float r[4];
-#pragma unroll
-      for (int el = 0; el < 2; ++el) {
-#pragma unroll
-        for (int ri = 0; ri < 2; ++ri) {
-          const int vi = el * 2 + ri;
-          const AxisPos px = axis_find(tb + lay.xa(), tb + lay.rdx(), D.nx, is[vi]);
-          float best = el ? kInf : -kInf;
-#pragma unroll
-          for (int ro = 0; ro < 2; ++ro) {
-            if (!arc_maps(sense, ri, ro)) continue;
-            const float cand = Ro[el * 2 + ro] - bilerp(tb + lay.tab(ro), D.ny, px, py);
-            best = el ? fminf(best, cand) : fmaxf(best, cand);
-          }
-          r[vi] = best;
-        }
-      }
-      R = make_float4(r[0], r[1], r[2], r[3]);
-    }
+  auto sink = [&](int s, const PinState &ss, int cons, float d, int drv) {
+    const float4 R = sink_rat<kCoh>(D, lib, ss, cons);
+    if (cons < 0) D.ep_slack[-1 - cons] = ep_slack2(ss.at, R);
     D.sink_rat[s] = R;
     D.sink_slack[s] = slack4(ss.at, R);
-    const float d = D.dq[s].x;
-    int *acc = wacc + (D.sink_drv[s] - x0) * 4;
+    int *acc = wacc + (drv - x0) * 4;
     atomicMax(acc + 0, f2key(R.x - d));
     atomicMax(acc + 1, f2key(R.y - d));
     atomicMin(acc + 2, f2key(R.z - d));
     atomicMin(acc + 3, f2key(R.w - d));
-  }
+  };
+  if (sA < s1) sink(sA, ssA, consA, dA, drvA);
+  for (int s = sA + kWave; s < s1; s += kWave) sink(s, D.sink_state[s], D.sink_cons[s], D.dq[s].x, D.sink_drv[s]);
   wave_sync();
-  if (x < x1) {
-    const float4 R = make_float4(key2f(wacc[lane * 4 + 0]), key2f(wacc[lane * 4 + 1]),
-                                 key2f(wacc[lane * 4 + 2]), key2f(wacc[lane * 4 + 3]));
-    const float4 A = D.drv_state[x].at;
-    st4<kCoh>(D.drv_rat + x, R);
+  if (live) {
+    float4 R = make_float4(key2f(wacc[lane * 4 + 0]), key2f(wacc[lane * 4 + 1]),
+                           key2f(wacc[lane * 4 + 2]), key2f(wacc[lane * 4 + 3]));
+    if (e >= 0) {
+      const float4 E = D.ep_rat[e];
+      R = make_float4(fmaxf(R.x, E.x), fmaxf(R.y, E.y), fminf(R.z, E.z), fminf(R.w, E.w));
+    }
+    st4<kCoh>(&D.cons_rec[x].rat, R);
     D.drv_slack[x] = slack4(A, R);
-    const int e = D.drv_ep[x];
     if (e >= 0) D.ep_slack[e] = ep_slack2(A, R);
   }
   wave_sync();
@@ -417,20 +542,39 @@ __global__ __launch_bounds__(kSweepBlock) void k_backward(DevDesign D, int c0, i
               (threadIdx.x / kWave) * kWave * 4;
   __syncthreads();
   if constexpr (kPersistent) {
-    uint32_t *done = D.counters + kCtrLevels + D.n_cell_levels + 1;
     for (;;) {
       const int t = take_ticket(D.counters + kCtrBwdTicket);
       if (t >= D.n_chunks) break;
       const int c = D.n_chunks - 1 - t;
       const int lvl = D.chunk_level[c];
-      if (lvl < D.n_cell_levels) wait_count(done + lvl + 1, (uint32_t)D.level_nchunks[lvl + 1]);
+      if (lvl < D.n_cell_levels) wait_level(level_ctr(D, 1, lvl + 1), (uint32_t)D.level_nchunks[lvl + 1]);
       bwd_chunk<true>(D, lib, wacc, c);
-      signal_done(done + lvl);
+      signal_add(level_ctr(D, 1, lvl), 1u);
     }
   } else {
     const int c = c0 + blockIdx.x * (kSweepBlock / kWave) + threadIdx.x / kWave;
     if (c < c1) bwd_chunk<false>(D, lib, wacc, c);
   }
+}
+
+// ------------------------------------------------ cooperative sweeps
+
+__global__ __launch_bounds__(kSweepBlock) void k_forward_coop(DevDesign D) {
+  extern __shared__ __align__(32) unsigned char smem[];
+  const LdsLib lib = load_lib(D, smem);
+  PinState *wst = reinterpret_cast<PinState *>(smem + lib_lds_bytes(D.n_types, D.tstride)) +
+                  (threadIdx.x / kWave) * kWave;
+  __syncthreads();
+  coop_levels<false>(D, 0, [&](int c) { fwd_chunk<true>(D, lib, wst, c); });
+}
+
+__global__ __launch_bounds__(kSweepBlock) void k_backward_coop(DevDesign D) {
+  extern __shared__ __align__(32) unsigned char smem[];
+  const LdsLib lib = load_lib(D, smem);
+  int *wacc = reinterpret_cast<int *>(smem + lib_lds_bytes(D.n_types, D.tstride)) +
+              (threadIdx.x / kWave) * kWave * 4;
+  __syncthreads();
+  coop_levels<true>(D, 1, [&](int c) { bwd_chunk<true>(D, lib, wacc, c); });
 }
 
 // ------------------------------------------------------------------ RC
@@ -553,7 +697,10 @@ __device__ void rc_wide_net(const DevDesign &D, const BigNet &B, const WideNets 
   __syncthreads();
   euler_terms(X, A, egp, egl, m);
   block_scan(A, A, m, false, s_w);                                         // A: m2
-  if (tid == 0) D.L_net[x] = (float)total;
+  if (tid == 0) {
+    D.L_net[x] = (float)total;
+    D.cons_rec[x].L = (float)total;
+  }
   for (int s = D.sink_ptr[x] + tid; s < D.sink_ptr[x + 1]; s += nt) {
     const int k = D.sink_node[s];
     const double d = Y[k];
@@ -568,9 +715,39 @@ __global__ __launch_bounds__(kWideBlock) void k_rc_wide(DevDesign D, WideNets W)
   rc_wide_net(D, W.big[blockIdx.x], W, s_w);
 }
 
-// Small nets: one block per chunk of <= 256 nets (<= kRcChunkNodes nodes):
-// coalesced staging of parent/R/C into LDS, one net per thread, coalesced sink
-// output.  Block 0 also clears the sweep counters for the launches that follow.
+// Stages nodes [k0, k0 + nk) of one RC chunk into LDS: parent, R and
+// C^ = C + lumped pin caps.  Each thread requests all of its (clamped,
+// unpredicated) loads before its first LDS store.
+__device__ __forceinline__ void stage_rc_nodes(const DevDesign &D, int k0, int nk, uint8_t *par, float *R,
+                                               float *C) {
+  constexpr int kPer = kRcChunkNodes / kRcBlock;
+  const int tid = threadIdx.x;
+  const int last = k0 + max(nk - 1, 0);
+  uint8_t p[kPer];
+  float r[kPer], c[kPer], pc[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int i = min(k0 + u * kRcBlock + tid, last);
+    p[u] = D.rc_par8[i];
+    r[u] = D.rc_res[i];
+    c[u] = D.rc_cap[i];
+    pc[u] = D.rc_pc[i];
+  }
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int i = u * kRcBlock + tid;
+    if (i < nk) {
+      par[i] = p[u];
+      R[i] = r[u];
+      C[i] = c[u] + pc[u];
+    }
+  }
+}
+
+// Small nets: one block per chunk of <= 256 nets (<= kRcChunkNodes nodes,
+// consecutive in RC order): coalesced staging of parent/R/C into LDS, one net
+// per thread, each thread writing its net's load and sink moments.  Block 0
+// also clears the sweep counters for the launches that follow.
 __global__ __launch_bounds__(kRcBlock) void k_rc(DevDesign D, const int2 *chunks, int n_chunks,
                                                  uint32_t *counters, int n_counters) {
   __shared__ uint8_t s_par[kRcChunkNodes];
@@ -582,27 +759,26 @@ __global__ __launch_bounds__(kRcBlock) void k_rc(DevDesign D, const int2 *chunks
   const int ci = blockIdx.x;
   if (ci >= n_chunks) return;
   const int2 ch = chunks[ci];
-  const int x0 = ch.x, x1 = ch.y;
-  const int k0 = D.rc_ptr[x0], nk = D.rc_ptr[x1] - k0;
-  for (int i = tid; i < nk; i += kRcBlock) {
-    s_par[i] = (uint8_t)D.rc_parent[k0 + i];
-    s_R[i] = D.rc_res[k0 + i];
-    s_C[i] = D.rc_cap[k0 + i];
-  }
-  for (int i = tid; i <= x1 - x0; i += kRcBlock) s_base[i] = D.rc_ptr[x0 + i] - k0;
+  const int j0 = ch.x, j1 = ch.y;
+  const int k0 = D.rc_start[j0], nk = D.rc_start[j1] - k0;
+  const int j = j0 + tid;
+  const int jc = j < j1 ? j : j0;
+  const int x = D.rc_order[jc];
+  const int2 sr = D.rc_sinks[jc];
+  stage_rc_nodes(D, k0, nk, s_par, s_R, s_C);
+  for (int i = tid; i <= j1 - j0; i += kRcBlock) s_base[i] = D.rc_start[j0 + i] - k0;
   __syncthreads();
-  const int x = x0 + tid;
-  if (x < x1) {
+  if (j < j1) {
     const int b = s_base[tid], m = s_base[tid + 1] - b;
-    for (int s = D.sink_ptr[x]; s < D.sink_ptr[x + 1]; ++s) s_C[b + D.sink_node[s]] += D.sink_pincap[s];
-    D.L_net[x] = rc_tree_lds(s_par, s_R, s_C, s_A, s_B, b, m);
-  }
-  __syncthreads();
-  const int s0 = D.sink_ptr[x0], s1 = D.sink_ptr[x1];
-  for (int s = s0 + tid; s < s1; s += kRcBlock) {
-    const int k = s_base[D.sink_drv[s] - x0] + D.sink_node[s];
-    const float d = s_B[k];
-    D.dq[s] = make_float2(d, fmaxf(0.0f, 2.0f * s_A[k] - d * d));
+    const int s0 = sr.x, s1 = sr.y;
+    const float L = rc_tree_lds(s_par, s_R, s_C, s_A, s_B, b, m);
+    D.L_net[x] = L;
+    D.cons_rec[x].L = L;
+    for (int s = s0; s < s1; ++s) {
+      const int k = b + D.sink_node[s];
+      const float d = s_B[k];
+      D.dq[s] = make_float2(d, fmaxf(0.0f, 2.0f * s_A[k] - d * d));
+    }
   }
 }
 
@@ -899,8 +1075,9 @@ __device__ void cell_adjoint(const DevDesign &D, const LdsLib &lib, int x, const
 // cell to the cell's input sinks.
 template <bool kCoh>
 __device__ void adj_chunk(const DevDesign &D, const LdsLib &lib, float g_tns, float g_wns, int c) {
-  const int x = D.chunk_start[c] + lane_id();
-  if (x >= D.chunk_start[c + 1]) return;
+  const int4 cr = D.chunk_rec[c];
+  const int x = cr.x + lane_id();
+  if (x >= cr.y) return;
   const PinState me = D.drv_state[x];
   float gA0 = 0.0f, gA1 = 0.0f, gS0 = 0.0f, gS1 = 0.0f;
   const int e = D.drv_ep[x];
@@ -938,20 +1115,27 @@ __global__ __launch_bounds__(kSweepBlock) void k_adjoint(DevDesign D, float g_tn
   const LdsLib lib = load_lib(D, smem);
   __syncthreads();
   if constexpr (kPersistent) {
-    uint32_t *done = D.counters + kCtrLevels;  // reuses the forward counters (reset by the RC adjoint)
+    // reuses the forward counters (cleared before the adjoint sweep)
     for (;;) {
       const int t = take_ticket(D.counters + kCtrFwdTicket);
       if (t >= D.n_chunks) break;
       const int c = D.n_chunks - 1 - t;
       const int lvl = D.chunk_level[c];
-      if (lvl < D.n_cell_levels) wait_count(done + lvl + 1, (uint32_t)D.level_nchunks[lvl + 1]);
+      if (lvl < D.n_cell_levels) wait_level(level_ctr(D, 0, lvl + 1), (uint32_t)D.level_nchunks[lvl + 1]);
       adj_chunk<true>(D, lib, g_tns, g_wns, c);
-      signal_done(done + lvl);
+      signal_add(level_ctr(D, 0, lvl), 1u);
     }
   } else {
     const int c = c0 + blockIdx.x * (kSweepBlock / kWave) + threadIdx.x / kWave;
     if (c < c1) adj_chunk<false>(D, lib, g_tns, g_wns, c);
   }
+}
+
+__global__ __launch_bounds__(kSweepBlock) void k_adjoint_coop(DevDesign D, float g_tns, float g_wns) {
+  extern __shared__ __align__(32) unsigned char smem[];
+  const LdsLib lib = load_lib(D, smem);
+  __syncthreads();
+  coop_levels<true>(D, 0, [&](int c) { adj_chunk<true>(D, lib, g_tns, g_wns, c); });
 }
 
 // ------------------------------------------------------------ RC adjoint
@@ -1049,24 +1233,22 @@ __global__ __launch_bounds__(kRcBlock) void k_rc_adjoint(DevDesign D, const int2
   const int ci = blockIdx.x;
   if (ci >= n_chunks) return;
   const int2 ch = chunks[ci];
-  const int x0 = ch.x, x1 = ch.y;
-  const int k0 = D.rc_ptr[x0], nk = D.rc_ptr[x1] - k0;
-  for (int i = tid; i < nk; i += kRcBlock) {
-    s_par[i] = (uint8_t)D.rc_parent[k0 + i];
-    s_R[i] = D.rc_res[k0 + i];
-    s_C[i] = D.rc_cap[k0 + i];
-  }
-  for (int i = tid; i <= x1 - x0; i += kRcBlock) s_base[i] = D.rc_ptr[x0 + i] - k0;
+  const int j0 = ch.x, j1 = ch.y;
+  const int k0 = D.rc_start[j0], nk = D.rc_start[j1] - k0;
+  const int j = j0 + tid;
+  const int jc = j < j1 ? j : j0;
+  const int x = D.rc_order[jc];
+  const int2 sr = D.rc_sinks[jc];
+  stage_rc_nodes(D, k0, nk, s_par, s_R, s_C);
+  for (int i = tid; i <= j1 - j0; i += kRcBlock) s_base[i] = D.rc_start[j0 + i] - k0;
   __syncthreads();
-  const int x = x0 + tid;
-  if (x < x1) {
+  if (j < j1) {
     const int b = s_base[tid], m = s_base[tid + 1] - b;
     const uint8_t *par = s_par;
     float *A = s_A, *B = s_B, *C = s_C, *E = s_E, *F = s_F, *R = s_R;
-    for (int s = D.sink_ptr[x]; s < D.sink_ptr[x + 1]; ++s) C[b + D.sink_node[s]] += D.sink_pincap[s];
     (void)rc_tree_lds(par, R, C, A, B, b, m);  // A = m2, B = d
     for (int k = 0; k < m; ++k) E[b + k] = F[b + k] = 0.0f;
-    for (int s = D.sink_ptr[x]; s < D.sink_ptr[x + 1]; ++s) {
+    for (int s = sr.x; s < sr.y; ++s) {
       const int k = b + D.sink_node[s];
       const float2 g = D.g_dq[s];
       const float gq = (2.0f * A[k] - B[k] * B[k]) > 0.0f ? g.y : 0.0f;
@@ -1183,7 +1365,7 @@ __global__ void k_report_pins(DevDesign D, const int32_t *pin_loc, int n_pins, f
       if (at) at[p] = st.at;
       if (slew) slew[p] = st.slew;
     }
-    if (rat) rat[p] = D.drv_rat[loc];
+    if (rat) rat[p] = D.cons_rec[loc].rat;
     if (crit) crit[p] = D.drv_crit[loc];
     if (slack) slack[p] = D.drv_slack[loc];
   } else {
@@ -1226,6 +1408,20 @@ size_t sweep_lds_bytes(const DevDesign &D) {
   return lib_lds_bytes(D.n_types, D.tstride) + per_wave * (kSweepBlock / kWave);
 }
 
+// Blocks per CU every cooperative sweep kernel can keep resident at once.
+int coop_blocks_per_cu(size_t lds_bytes) {
+  int n = 1 << 30;
+  const void *ks[] = {reinterpret_cast<const void *>(&k_forward_coop),
+                      reinterpret_cast<const void *>(&k_backward_coop),
+                      reinterpret_cast<const void *>(&k_adjoint_coop)};
+  for (const void *k : ks) {
+    int b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k, kSweepBlock, lds_bytes) != hipSuccess) return 0;
+    n = b < n ? b : n;
+  }
+  return n;
+}
+
 int sweep_blocks_per_cu(size_t lds_bytes) {
   int nf = 0, nb = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nf, k_forward<true>, kSweepBlock, lds_bytes) != hipSuccess)
@@ -1237,7 +1433,7 @@ int sweep_blocks_per_cu(size_t lds_bytes) {
 }
 
 hipError_t launch_rc(const DevDesign &D, const int2 *chunks, int n_chunks, hipStream_t s) {
-  const int n_ctr = kCtrLevels + 2 * (D.n_cell_levels + 1);
+  const int n_ctr = n_counters(D.n_cell_levels);
   hipLaunchKernelGGL(k_rc, dim3(n_chunks > 0 ? n_chunks : 1), dim3(kRcBlock), 0, s, D, chunks, n_chunks, D.counters,
                      n_ctr);
   return hipGetLastError();
@@ -1255,7 +1451,13 @@ hipError_t launch_rc_adjoint_wide(const DevDesign &D, const WideNets &W, hipStre
   return hipGetLastError();
 }
 
-hipError_t launch_forward(const DevDesign &D, int grid, hipStream_t s) {
+hipError_t launch_forward(const DevDesign &D, int grid, bool coop, hipStream_t s) {
+  if (coop) {
+    DevDesign a = D;
+    void *args[] = {&a};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_forward_coop), dim3(grid),
+                                      dim3(kSweepBlock), args, (unsigned)sweep_lds_bytes(D), s);
+  }
   hipLaunchKernelGGL(k_forward<true>, dim3(grid), dim3(kSweepBlock), sweep_lds_bytes(D), s, D, 0, 0);
   return hipGetLastError();
 }
@@ -1268,7 +1470,13 @@ hipError_t launch_forward_level(const DevDesign &D, int c0, int c1, hipStream_t 
   return hipGetLastError();
 }
 
-hipError_t launch_backward(const DevDesign &D, int grid, hipStream_t s) {
+hipError_t launch_backward(const DevDesign &D, int grid, bool coop, hipStream_t s) {
+  if (coop) {
+    DevDesign a = D;
+    void *args[] = {&a};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_backward_coop), dim3(grid),
+                                      dim3(kSweepBlock), args, (unsigned)sweep_lds_bytes(D), s);
+  }
   hipLaunchKernelGGL(k_backward<true>, dim3(grid), dim3(kSweepBlock), sweep_lds_bytes(D), s, D, 0, 0);
   return hipGetLastError();
 }
@@ -1287,7 +1495,14 @@ hipError_t launch_reduce_smooth(const DevDesign &D, double *partials, double *ou
   return hipGetLastError();
 }
 
-hipError_t launch_adjoint(const DevDesign &D, float g_tns, float g_wns, int grid, hipStream_t s) {
+hipError_t launch_adjoint(const DevDesign &D, float g_tns, float g_wns, int grid, bool coop, hipStream_t s) {
+  if (coop) {
+    DevDesign a = D;
+    float gt = g_tns, gw = g_wns;
+    void *args[] = {&a, &gt, &gw};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_adjoint_coop), dim3(grid),
+                                      dim3(kSweepBlock), args, (unsigned)sweep_lds_bytes(D), s);
+  }
   hipLaunchKernelGGL(k_adjoint<true>, dim3(grid), dim3(kSweepBlock), sweep_lds_bytes(D), s, D, g_tns, g_wns, 0, 0);
   return hipGetLastError();
 }

@@ -145,3 +145,53 @@ def test_10m_pins_full():
     r = oracle.sta(d)
     stats = compare_full(d, r, _run(d))
     print(stats)
+
+
+def _wide_cell_design(seed=11):
+    """Cells of 5 and 6 inputs (beyond the inline fanin record, so the sweeps
+    read fanins through the CSR), mixed with 1- and 2-input cells, over three
+    levels, every output net a multi-sink star."""
+    rng = np.random.default_rng(seed)
+    n_inputs = [1, 2, 5, 6]
+    kinds, cells, nets = [], [], []
+
+    def pin(kind):
+        kinds.append(kind)
+        return len(kinds) - 1
+
+    pis = [pin(PI) for _ in range(10)]
+    sinks_of = {p: [] for p in pis}
+    prev = list(pis)
+    for level in range(3):
+        outs = []
+        for _ in range(6):
+            t = int(rng.integers(0, 4))
+            srcs = rng.choice(prev + pis, size=n_inputs[t], replace=True)
+            ins = []
+            for src in srcs:
+                ci = pin(CIN)
+                sinks_of[int(src)].append(ci)
+                ins.append(ci)
+            o = pin(COUT)
+            sinks_of[o] = []
+            cells.append((t, ins, o))
+            outs.append(o)
+        prev = outs
+    for o in prev:
+        sinks_of[o].append(pin(PO))
+    for drv, sk in sinks_of.items():
+        nets.append(single_segment_net(drv, sk, float(rng.uniform(0.005, 0.05)), float(rng.uniform(0.2, 2.0))))
+    tables = np.stack([np.stack([planar_table(5 + 3 * t, 0.1, 1.0 + 0.2 * t, 0.001),
+                                 planar_table(6 + 2 * t, 0.12, 1.1, 0.002),
+                                 planar_table(3, 0.05 + 0.01 * t, 2.0),
+                                 planar_table(4, 0.06, 1.8 + 0.1 * t)]) for t in range(4)])
+    return make_design(kinds, cells, nets, n_inputs=n_inputs, sense=[1, 0, 2, 1], pin_cap=[1.0, 1.5, 0.8, 2.2],
+                       tables=tables, po_rat=40.0, rat_early=20.0)
+
+
+@pytest.mark.parametrize("sched", [STA_SCHED_PERSISTENT, STA_SCHED_PER_LEVEL])
+def test_cells_wider_than_inline_fanins(sched):
+    d = _wide_cell_design()
+    assert int(np.diff(d.cell_in_ptr).max()) > 4
+    r = oracle.sta(d)
+    compare_full(d, r, _run(d, sched=sched))
