@@ -16,7 +16,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/sta.h"
+#include "sta.h"
 #include "sta_internal.h"
 
 using namespace sta;
@@ -121,7 +121,8 @@ struct sta_ctx {
   int32_t *vals = nullptr, *order = nullptr;
   void *sort_temp = nullptr;
   size_t sort_bytes = 0;
-  std::vector<int> level_chunk_begin;  // [n_cell_levels+2]
+  std::vector<int4> ph_fwd, ph_bwd, ph_adj;  // sweep phases (kind, first item, count, level)
+  int n_pieces = 0;
   hipEvent_t ev[10]{};  // 0..6 update phases, 7..9 adjoint phases
   hipStream_t cap_stream = nullptr;   // graph schedule: capture stream
   hipGraph_t graph = nullptr;
@@ -703,24 +704,56 @@ static sta_status build_layout(sta_ctx *C, const Inputs &I, const std::vector<in
     pi_slew[x] = make_float4(s[0], s[1], s[2], s[3]);
   }
 
-  // sweep chunks: 64 consecutive slots of one level
-  std::vector<int32_t> chunk_start, chunk_level, level_nchunks(L + 1, 0);
-  C->level_chunk_begin.assign(L + 2, 0);
+  // sweep chunks: up to 64 consecutive slots of one level; a driver with more
+  // than kSplitSinks sinks gets a chunk of its own, which keeps the first
+  // kPieceSinks sinks, the rest going to pieces of kPieceSinks sinks.
+  // Phases: forward = per level its chunks, then its pieces; backward = per
+  // level (descending) its pieces, then its chunks; adjoint = chunks only.
+  std::vector<int4> chunk_rec, piece_rec;
+  std::vector<int2> chunk_pieces;
+  std::vector<int32_t> lvl_cbeg(L + 2, 0), lvl_pbeg(L + 2, 0);
   for (int l = 0; l <= L; ++l) {
-    C->level_chunk_begin[l] = (int)chunk_level.size();
-    for (int x = lvl_ptr[l]; x < lvl_ptr[l + 1]; x += kChunk) {
-      chunk_start.push_back(x);
-      chunk_level.push_back(l);
-      level_nchunks[l]++;
+    lvl_cbeg[l] = (int)chunk_rec.size();
+    lvl_pbeg[l] = (int)piece_rec.size();
+    int x = lvl_ptr[l];
+    while (x < lvl_ptr[l + 1]) {
+      const auto fanout = [&](int y) { return sink_ptr[y + 1] - sink_ptr[y]; };
+      if (fanout(x) > kSplitSinks) {
+        const int c = (int)chunk_rec.size();
+        const int s0 = sink_ptr[x], s1 = sink_ptr[x + 1];
+        chunk_rec.push_back(make_int4(x, x + 1, s0, s0 + kPieceSinks));
+        const int p0 = (int)piece_rec.size();
+        for (int a = s0 + kPieceSinks; a < s1; a += kPieceSinks)
+          piece_rec.push_back(make_int4(x, a, std::min(s1, a + kPieceSinks), c));
+        chunk_pieces.push_back(make_int2(p0, (int)piece_rec.size() - p0));
+        ++x;
+        continue;
+      }
+      int y = x;
+      while (y < lvl_ptr[l + 1] && y - x < kChunk && fanout(y) <= kSplitSinks) ++y;
+      chunk_rec.push_back(make_int4(x, y, sink_ptr[x], sink_ptr[y]));
+      chunk_pieces.push_back(make_int2(0, 0));
+      x = y;
     }
   }
-  C->level_chunk_begin[L + 1] = (int)chunk_level.size();
-  chunk_start.push_back(ND);
-  C->n_chunks = (int)chunk_level.size();
-  std::vector<int4> chunk_rec(C->n_chunks);
-  for (int c = 0; c < C->n_chunks; ++c)
-    chunk_rec[c] = make_int4(chunk_start[c], chunk_start[c + 1], sink_ptr[chunk_start[c]],
-                             sink_ptr[chunk_start[c + 1]]);
+  lvl_cbeg[L + 1] = (int)chunk_rec.size();
+  lvl_pbeg[L + 1] = (int)piece_rec.size();
+  C->n_chunks = (int)chunk_rec.size();
+  C->n_pieces = (int)piece_rec.size();
+  C->ph_fwd.clear();
+  C->ph_bwd.clear();
+  C->ph_adj.clear();
+  for (int l = 0; l <= L; ++l) {
+    C->ph_fwd.push_back(make_int4(kItemChunk, lvl_cbeg[l], lvl_cbeg[l + 1] - lvl_cbeg[l], l));
+    if (lvl_pbeg[l + 1] > lvl_pbeg[l])
+      C->ph_fwd.push_back(make_int4(kItemPiece, lvl_pbeg[l], lvl_pbeg[l + 1] - lvl_pbeg[l], l));
+  }
+  for (int l = L; l >= 0; --l) {
+    if (lvl_pbeg[l + 1] > lvl_pbeg[l])
+      C->ph_bwd.push_back(make_int4(kItemPiece, lvl_pbeg[l], lvl_pbeg[l + 1] - lvl_pbeg[l], l));
+    C->ph_bwd.push_back(make_int4(kItemChunk, lvl_cbeg[l], lvl_cbeg[l + 1] - lvl_cbeg[l], l));
+    C->ph_adj.push_back(make_int4(kItemChunk, lvl_cbeg[l], lvl_cbeg[l + 1] - lvl_cbeg[l], l));
+  }
   // inline fanin sink slots when every type has at most 4 inputs
   int max_in = 0;
   for (int t = 0; t < lib.n_types; ++t) max_in = std::max(max_in, (int)lib.n_inputs[t]);
@@ -821,7 +854,6 @@ static sta_status build_layout(sta_ctx *C, const Inputs &I, const std::vector<in
   STA_TRY(C->upload(&p4, ep_rat)); D.ep_rat = p4;
   STA_TRY(C->upload(&pf, tab)); D.tables = pf;
   STA_TRY(C->upload(&p32, sense)); D.sense = p32;
-  STA_TRY(C->upload(&p32, chunk_start)); D.chunk_start = p32;
   {
     int4 *p4i;
     STA_TRY(C->upload(&p4i, chunk_rec)); D.chunk_rec = p4i;
@@ -833,11 +865,20 @@ static sta_status build_layout(sta_ctx *C, const Inputs &I, const std::vector<in
     ConsRec *pcr;
     STA_TRY(C->upload(&pcr, cons_rec)); D.cons_rec = pcr;
   }
-  STA_TRY(C->upload(&p32, chunk_level)); D.chunk_level = p32;
-  STA_TRY(C->upload(&p32, level_nchunks)); D.level_nchunks = p32;
   {
-    std::vector<int32_t> lcb(C->level_chunk_begin.begin(), C->level_chunk_begin.end());
-    STA_TRY(C->upload(&p32, lcb)); D.level_cbeg = p32;
+    std::vector<int4> ph(C->ph_fwd);
+    ph.insert(ph.end(), C->ph_bwd.begin(), C->ph_bwd.end());
+    ph.insert(ph.end(), C->ph_adj.begin(), C->ph_adj.end());
+    int4 *p4i;
+    STA_TRY(C->upload(&p4i, ph)); D.phases = p4i;
+    D.n_ph_fwd = (int)C->ph_fwd.size();
+    D.n_ph_bwd = (int)C->ph_bwd.size();
+    D.n_ph_adj = (int)C->ph_adj.size();
+    if (piece_rec.empty()) piece_rec.push_back(make_int4(0, 0, 0, 0));  // never read
+    STA_TRY(C->upload(&p4i, piece_rec)); D.piece_rec = p4i;
+    int2 *p2i;
+    STA_TRY(C->upload(&p2i, chunk_pieces)); D.chunk_pieces = p2i;
+    STA_TRY(C->alloc(&D.piece_rat, std::max(C->n_pieces, 1)));
   }
   STA_TRY(C->alloc(&D.L_net, ND));
   STA_TRY(C->alloc(&D.dq, NS));
@@ -848,7 +889,7 @@ static sta_status build_layout(sta_ctx *C, const Inputs &I, const std::vector<in
   STA_TRY(C->alloc(&D.drv_slack, ND));
   STA_TRY(C->alloc(&D.sink_slack, NS));
   STA_TRY(C->alloc(&D.ep_slack, C->n_ep));
-  const int n_ctr = n_counters(L);
+  const int n_ctr = n_counters(D.n_ph_fwd + D.n_ph_bwd);
   STA_TRY(C->alloc(&D.counters, n_ctr));
   HIP_TRY(hipMemset(D.counters, 0, n_ctr * sizeof(uint32_t)));
 
@@ -1237,16 +1278,14 @@ static sta_status enqueue_update(sta_ctx *C, hipStream_t s, bool prof) {
   if (!per_level) {
     HIP_TRY(launch_forward(D, C->sweep_grid, C->coop, s));
   } else {
-    for (int l = 0; l <= C->n_cell_levels; ++l)
-      HIP_TRY(launch_forward_level(D, C->level_chunk_begin[l], C->level_chunk_begin[l + 1], s));
+    for (const int4 &ph : C->ph_fwd) HIP_TRY(launch_forward_phase(D, ph, s));
   }
   if (prof) HIP_TRY(hipEventRecord(C->ev[3], s));
   if (!smooth) {  // the smooth objective needs arrivals only; it skips the RAT sweep
     if (!per_level) {
       HIP_TRY(launch_backward(D, C->sweep_grid, C->coop, s));
     } else {
-      for (int l = C->n_cell_levels; l >= 0; --l)
-        HIP_TRY(launch_backward_level(D, C->level_chunk_begin[l], C->level_chunk_begin[l + 1], s));
+      for (const int4 &ph : C->ph_bwd) HIP_TRY(launch_backward_phase(D, ph, s));
     }
   }
   if (prof) HIP_TRY(hipEventRecord(C->ev[4], s));
@@ -1328,12 +1367,11 @@ extern "C" sta_status sta_backward(sta_ctx *C, float g_tns, float g_wns, float *
   const bool prof = C->opt.profile != 0;
   const DevDesign &D = C->D;
   if (prof) HIP_TRY(hipEventRecord(C->ev[7], s));
-  HIP_TRY(launch_reset_counters(D.counters, n_counters(C->n_cell_levels), s));
+  HIP_TRY(launch_reset_counters(D.counters, n_counters(D.n_ph_fwd + D.n_ph_bwd), s));
   if (C->opt.sched == STA_SCHED_PERSISTENT) {
     HIP_TRY(launch_adjoint(D, g_tns, g_wns, C->sweep_grid, C->coop, s));
   } else {
-    for (int l = C->n_cell_levels; l >= 0; --l)
-      HIP_TRY(launch_adjoint_level(D, g_tns, g_wns, C->level_chunk_begin[l], C->level_chunk_begin[l + 1], s));
+    for (const int4 &ph : C->ph_adj) HIP_TRY(launch_adjoint_phase(D, g_tns, g_wns, ph, s));
   }
   if (prof) HIP_TRY(hipEventRecord(C->ev[8], s));
   STA_TRY(enqueue_rc(C, s, true));

@@ -35,15 +35,19 @@ struct alignas(32) PinState {
   float4 slew;
 };
 
-// counters[] layout
-constexpr int kCtrFwdTicket = 0;
-constexpr int kCtrBwdTicket = 1;
+// counters[] layout: kCtrReduce, then kDoneGroups completion counters per
+// sweep phase (forward phases, then backward phases; the adjoint reuses the
+// forward ones), then one ticket counter per phase
 constexpr int kCtrReduce = 2;
-constexpr int kCtrLevels = 4;  // then per sweep (forward, backward) and level: kDoneGroups counters
-constexpr int kDoneGroups = 8;  // completion counters per level (block b bumps group b % 8)
-__host__ __device__ inline int n_counters(int n_cell_levels) {
-  return kCtrLevels + 2 * (n_cell_levels + 1) * kDoneGroups;
-}
+constexpr int kCtrPhases = 4;
+constexpr int kDoneGroups = 8;  // completion counters per phase (block b bumps group b % 8)
+__host__ __device__ inline int n_counters(int n_phases) { return kCtrPhases + n_phases * (kDoneGroups + 1); }
+
+// Sweep phases: int4 (kind, first item, item count, level); items are chunks
+// or sink pieces of high-fanout drivers.
+constexpr int kItemChunk = 0, kItemPiece = 1;
+constexpr int kSplitSinks = 1024;  // a driver with more sinks gets its own chunk and sink pieces
+constexpr int kPieceSinks = 512;   // sinks per piece (the chunk keeps the first piece)
 
 // What the backward sweep gathers about a consumer cell, in one 32-byte record:
 // its output RAT (written by the sweep), NLDM load (written by the RC pass) and
@@ -114,12 +118,13 @@ struct DevDesign {
   double *norm;                 // [2] WNS_g normalisation (max shift M, denominator)
 
   // sweep schedule
-  const int32_t *chunk_start;   // [n_chunks+1] driver-slot ranges
   const int4 *chunk_rec;        // [n_chunks] (first slot, end slot, first sink, end sink)
   const int4 *fanin4;           // [n_drv] input sink slots of each cell, -1 padded; NULL if a type has > 4 inputs
-  const int32_t *chunk_level;   // [n_chunks]
-  const int32_t *level_nchunks; // [n_cell_levels+1]
-  const int32_t *level_cbeg;    // [n_cell_levels+2] first chunk of each level
+  const int4 *phases;           // forward, then backward, then adjoint phase lists
+  int32_t n_ph_fwd, n_ph_bwd, n_ph_adj;
+  const int4 *piece_rec;        // [n_pieces] (driver slot, first sink, end sink, owner chunk)
+  const int2 *chunk_pieces;     // [n_chunks] (first piece, count) of a high-fanout driver's chunk
+  float4 *piece_rat;            // [n_pieces] each piece's merge of RAT_s - d
   uint32_t *counters;
 };
 
@@ -133,7 +138,7 @@ struct BigNet {
                       // listed in big_egl (aux-indexed, m entries) deepest first
 };
 constexpr int kWideBlock = 1024;            // threads per wide-net block
-constexpr int kBigScratch = 8;
+constexpr int kBigScratch = 9;
 
 // Packed-table offsets for one type.
 struct TabLayout {
@@ -162,16 +167,15 @@ hipError_t launch_rc_adjoint_wide(const DevDesign &D, const WideNets &W, hipStre
 // Persistent sweeps: with coop, the level-major static schedule on a
 // cooperative (co-resident) grid; otherwise the ticket schedule.
 hipError_t launch_forward(const DevDesign &D, int persistent_grid, bool coop, hipStream_t s);
-hipError_t launch_forward_level(const DevDesign &D, int c0, int c1, hipStream_t s);
+hipError_t launch_forward_phase(const DevDesign &D, int4 phase, hipStream_t s);
 hipError_t launch_backward(const DevDesign &D, int persistent_grid, bool coop, hipStream_t s);
-hipError_t launch_backward_level(const DevDesign &D, int c0, int c1, hipStream_t s);
+hipError_t launch_backward_phase(const DevDesign &D, int4 phase, hipStream_t s);
 hipError_t launch_reset_counters(uint32_t *counters, int n, hipStream_t s);
 hipError_t launch_reduce_smooth(const DevDesign &D, double *partials, double *out, uint32_t *keys,
                                 int32_t *vals, hipStream_t s);
 hipError_t launch_adjoint(const DevDesign &D, float g_tns, float g_wns, int persistent_grid, bool coop,
                           hipStream_t s);
-hipError_t launch_adjoint_level(const DevDesign &D, float g_tns, float g_wns, int c0, int c1,
-                                hipStream_t s);
+hipError_t launch_adjoint_phase(const DevDesign &D, float g_tns, float g_wns, int4 phase, hipStream_t s);
 hipError_t launch_rc_adjoint(const DevDesign &D, const int2 *chunks, int n_chunks, hipStream_t s);
 hipError_t launch_scatter_grads(const DevDesign &D, const int32_t *node_src, int64_t n_nodes,
                                 float *grad_cap, const int32_t *pin_loc, int n_pins, float *grad_load,

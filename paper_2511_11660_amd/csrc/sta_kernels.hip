@@ -179,10 +179,6 @@ __host__ __device__ inline size_t lib_lds_bytes(int n_types, int tstride) {
 
 // ------------------------------------------------------------ forward
 
-// Arrival/slew of one cell output: merge over fanin arcs of AT_in + delay
-// (late max, early min), slew merged the same way independent of the AT
-// winner; the critical code is 2*fanin + input transition of the AT winner,
-// ties kept by the earlier candidate.
 // Arrival/slew merge of one cell output over its fanin arcs: AT_in + delay
 // (late max, early min), slew merged the same way independent of the AT
 // winner; the critical code is 2*fanin + input transition of the AT winner,
@@ -273,37 +269,71 @@ __device__ void cell_forward_csr(const DevDesign &D, const LdsLib &lib, int x, P
 }
 
 // One chunk: the 64 drivers, then every sink of their nets
-// (AT_s = AT_drv + d, slew_s = sqrt(slew_drv^2 + q)).  Every load that does
-// not depend on another is issued first (sink metadata of the first two sink
-// rounds, the drivers' type, load and inline fanin ids), then the input-state
-// gathers, then the arithmetic: about three memory round trips per chunk.
-template <bool kCoh>
-__device__ void fwd_chunk(const DevDesign &D, const LdsLib &lib, PinState *wst, int c) {
+// (AT_s = AT_drv + d, slew_s = sqrt(slew_drv^2 + q)).  Split in two:
+// fwd_prefetch requests everything that does not depend on the sweep itself
+// (the chunk record, the sink metadata of the first two sink rounds, each
+// lane's cell type, load and inline fanin ids, or its PI constraint), so a
+// persistent wave can issue it before it waits for the previous level;
+// fwd_finish gathers the input sink states and does the arithmetic.
+struct FwdPre {
+  int x0, x1, s0, s1;
+  int dA, dB;
+  float2 wA, wB;
+  int t;
+  float L;
+  int4 f4;
+  float4 pat, psl;
+};
+
+__device__ __forceinline__ FwdPre fwd_prefetch(const DevDesign &D, int c) {
+  FwdPre p;
   const int lane = lane_id();
   const int4 cr = D.chunk_rec[c];
-  const int x0 = __builtin_amdgcn_readfirstlane(cr.x), x1 = __builtin_amdgcn_readfirstlane(cr.y);
-  const int s0 = __builtin_amdgcn_readfirstlane(cr.z), s1 = __builtin_amdgcn_readfirstlane(cr.w);
-  const int smax = max(s1 - 1, 0);
-  const int sA = s0 + lane, sB = sA + kWave;
-  const int dA = D.sink_drv[min(sA, smax)], dB = D.sink_drv[min(sB, smax)];
-  const float2 wA = D.dq[min(sA, smax)], wB = D.dq[min(sB, smax)];
+  p.x0 = __builtin_amdgcn_readfirstlane(cr.x);
+  p.x1 = __builtin_amdgcn_readfirstlane(cr.y);
+  p.s0 = __builtin_amdgcn_readfirstlane(cr.z);
+  p.s1 = __builtin_amdgcn_readfirstlane(cr.w);
+  const int smax = max(p.s1 - 1, 0);
+  const int sA = min(p.s0 + lane, smax), sB = min(p.s0 + lane + kWave, smax);
+  p.dA = D.sink_drv[sA];
+  p.dB = D.sink_drv[sB];
+  p.wA = D.dq[sA];
+  p.wB = D.dq[sB];
+  const int x = p.x0 + lane;
+  const int xc = x < p.x1 ? x : p.x0;
+  p.t = 0;
+  p.L = 0.0f;
+  p.f4 = make_int4(-1, -1, -1, -1);
+  p.pat = p.psl = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  if (p.x0 < D.n_pi) {  // level 0: primary inputs only
+    p.pat = D.pi_at[xc];
+    p.psl = D.pi_slew[xc];
+  } else if (D.fanin4) {
+    p.t = D.cell_type[xc];
+    p.L = D.L_net[xc];
+    p.f4 = D.fanin4[xc];
+  }
+  return p;
+}
+
+template <bool kCoh>
+__device__ void fwd_finish(const DevDesign &D, const LdsLib &lib, PinState *wst, const FwdPre &p) {
+  const int lane = lane_id();
+  const int x0 = p.x0, x1 = p.x1, s1 = p.s1;
+  const int sA = p.s0 + lane, sB = sA + kWave;
   const int x = x0 + lane;
   const bool live = x < x1;
-  const int xc = live ? x : x0;
   PinState st;
   uint32_t crit = 0xffffffffu;
-  if (x0 < D.n_pi) {  // level 0: primary inputs only
-    st.at = D.pi_at[xc];
-    st.slew = D.pi_slew[xc];
+  if (x0 < D.n_pi) {
+    st.at = p.pat;
+    st.slew = p.psl;
   } else if (D.fanin4) {
-    const int t = D.cell_type[xc];
-    const float L = D.L_net[xc];
-    const int4 f4 = D.fanin4[xc];
-    const int fs[4] = {f4.x, f4.y, f4.z, f4.w};
+    const int fs[4] = {p.f4.x, p.f4.y, p.f4.z, p.f4.w};
     PinState in[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) in[k] = ld_state<kCoh>(D.sink_state + max(fs[k], 0));
-    const CellCtx cc = cell_ctx(D, lib, t, L);
+    const CellCtx cc = cell_ctx(D, lib, p.t, p.L);
     Merge m;
     merge_init(m);
 #pragma unroll
@@ -311,10 +341,10 @@ __device__ void fwd_chunk(const DevDesign &D, const LdsLib &lib, PinState *wst, 
       if (fs[k] >= 0) merge_one(D, cc, in[k], k, m);
     merge_finish(D, m, st, crit);
   } else {
-    cell_forward_csr<kCoh>(D, lib, xc, st, crit);
+    cell_forward_csr<kCoh>(D, lib, live ? x : x0, st, crit);
   }
   if (live) {
-    D.drv_state[x] = st;
+    st_state<kCoh>(D.drv_state + x, st);  // sink pieces of this driver read it in the next phase
     D.drv_crit[x] = crit;
     wst[lane] = st;
   }
@@ -327,120 +357,53 @@ __device__ void fwd_chunk(const DevDesign &D, const LdsLib &lib, PinState *wst, 
                          sqrtf(ds.slew.z * ds.slew.z + w.y), sqrtf(ds.slew.w * ds.slew.w + w.y));
     st_state<kCoh>(D.sink_state + s, o);
   };
-  if (sA < s1) emit(sA, dA, wA);
-  if (sB < s1) emit(sB, dB, wB);
+  if (sA < s1) emit(sA, p.dA, p.wA);
+  if (sB < s1) emit(sB, p.dB, p.wB);
   for (int s = sB + kWave; s < s1; s += kWave) emit(s, D.sink_drv[s], D.dq[s]);
   wave_sync();
 }
 
-// The persistent loops contain no lane-divergent branch: every lane issues the
-// counter atomics (lane 0 adds 1, the others 0, which the compiler folds into
-// one wave-level atomic) and the ticket / polled count are broadcast with
-// readfirstlane, so every loop exit is a scalar branch and the 64 lanes always
-// iterate together.  (With `if (lane == 0) atomic` at both ends of the loop,
-// jump threading merged the two regions into a lane-0-only path and the
-// other lanes re-entered the loop without a ticket.)
-// Completion counters of sweep sw (0 forward / adjoint, 1 backward) at level
-// l: kDoneGroups words whose sum is the number of the level's chunks done.
-__device__ __forceinline__ uint32_t *level_ctr(const DevDesign &D, int sw, int l) {
-  return D.counters + kCtrLevels + ((size_t)sw * (D.n_cell_levels + 1) + l) * kDoneGroups;
+template <bool kCoh>
+__device__ __forceinline__ void fwd_chunk(const DevDesign &D, const LdsLib &lib, PinState *wst, int c) {
+  fwd_finish<kCoh>(D, lib, wst, fwd_prefetch(D, c));
 }
 
-// Polls until the level's group counters sum to target.  Every lane loads one
-// of the group words (lane & 7) and the sum is formed across 8 lanes, so the
-// loop has no divergent branch.
-__device__ __forceinline__ void wait_level(uint32_t *ctr, uint32_t target) {
-  for (;;) {
-    uint32_t v = __hip_atomic_load(ctr + (lane_id() & (kDoneGroups - 1)), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-    v += __shfl_xor(v, 1);
-    v += __shfl_xor(v, 2);
-    v += __shfl_xor(v, 4);
-    if (__builtin_amdgcn_readfirstlane(v) >= target) break;
-    __builtin_amdgcn_s_sleep(1);
-  }
-  // the loop exit waits on the counter load; keep the compiler from hoisting
-  // the coherent data loads that follow above it
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-}
-
-__device__ __forceinline__ int take_ticket(uint32_t *ctr) {
-  const uint32_t old = atomicAdd(ctr, lane_id() == 0 ? 1u : 0u);
-  return (int)__builtin_amdgcn_readfirstlane(old);
-}
-
-// Every coherent store of this wave has completed (vmcnt 0) before the counter
-// moves, so a consumer that sees the count reads the new values.
-__device__ __forceinline__ void signal_add(uint32_t *ctr, uint32_t n) {
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  __builtin_amdgcn_s_waitcnt(0);
-  __hip_atomic_fetch_add(ctr, lane_id() == 0 ? n : 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Level-major static schedule for a cooperative grid (every block resident):
-// of each level, in sweep order, wave w of W takes chunks c0 + w, c0 + w + W,
-// ...  A block with chunks in a level first waits until the previous level in
-// sweep order is complete (which implies all earlier ones: every level has
-// chunks, each processed after its own wait), runs them, waits for its waves'
-// stores, and bumps its group counter by their number; blocks without chunks
-// in a level skip it entirely.  No per-chunk atomics.
-template <bool kReverse, class Body>
-__device__ __forceinline__ void coop_levels(const DevDesign &D, int sw, Body body) {
-  constexpr int kWaves = kSweepBlock / kWave;
-  const int L = D.n_cell_levels;
-  const int W = (int)gridDim.x * kWaves;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  const int b0 = blockIdx.x * kWaves;
-  const int g = blockIdx.x & (kDoneGroups - 1);
-  int prev = -1;
-  for (int i = 0; i <= L; ++i) {
-    const int l = kReverse ? L - i : i;
-    const int c0 = D.level_cbeg[l], n = D.level_cbeg[l + 1] - c0;
-    int mine = 0;
-#pragma unroll
-    for (int k = 0; k < kWaves; ++k)
-      if (b0 + k < n) mine += (n - (b0 + k) + W - 1) / W;
-    if (mine > 0) {
-      if (prev >= 0 && wave == 0)
-        wait_level(level_ctr(D, sw, prev), (uint32_t)(D.level_cbeg[prev + 1] - D.level_cbeg[prev]));
-      __syncthreads();
-      for (int c = c0 + b0 + wave; c < c0 + n; c += W) body(c);
-      __builtin_amdgcn_s_waitcnt(0);
-      __syncthreads();
-      if (wave == 0) signal_add(level_ctr(D, sw, l) + g, (uint32_t)mine);
-    }
-    prev = l;
+// Sinks beyond a high-fanout driver's first piece ("pieces"): every lane
+// derives sink states from the one driver state.
+template <bool kCoh>
+__device__ void fwd_piece(const DevDesign &D, int j) {
+  const int4 pr = D.piece_rec[j];
+  const int x = __builtin_amdgcn_readfirstlane(pr.x);
+  const int sa = __builtin_amdgcn_readfirstlane(pr.y), sb = __builtin_amdgcn_readfirstlane(pr.z);
+  const PinState ds = ld_state<kCoh>(D.drv_state + x);
+  for (int s = sa + lane_id(); s < sb; s += kWave) {
+    const float2 w = D.dq[s];
+    PinState o;
+    o.at = make_float4(ds.at.x + w.x, ds.at.y + w.x, ds.at.z + w.x, ds.at.w + w.x);
+    o.slew = make_float4(sqrtf(ds.slew.x * ds.slew.x + w.y), sqrtf(ds.slew.y * ds.slew.y + w.y),
+                         sqrtf(ds.slew.z * ds.slew.z + w.y), sqrtf(ds.slew.w * ds.slew.w + w.y));
+    st_state<kCoh>(D.sink_state + s, o);
   }
 }
 
-template <bool kPersistent>
+// One launch per phase (chunks of one level, or the pieces of one level).
 __global__ __launch_bounds__(kSweepBlock) void k_forward(DevDesign D, int c0, int c1) {
   extern __shared__ __align__(32) unsigned char smem[];
   const LdsLib lib = load_lib(D, smem);
   PinState *wst = reinterpret_cast<PinState *>(smem + lib_lds_bytes(D.n_types, D.tstride)) +
                   (threadIdx.x / kWave) * kWave;
   __syncthreads();
-  if constexpr (kPersistent) {
-    for (;;) {
-      const int c = take_ticket(D.counters + kCtrFwdTicket);
-      if (c >= D.n_chunks) break;
-      const int lvl = D.chunk_level[c];
-      if (lvl > 0) wait_level(level_ctr(D, 0, lvl - 1), (uint32_t)D.level_nchunks[lvl - 1]);
-      fwd_chunk<true>(D, lib, wst, c);
-      signal_add(level_ctr(D, 0, lvl), 1u);
-    }
-  } else {
-    const int c = c0 + blockIdx.x * (kSweepBlock / kWave) + threadIdx.x / kWave;
-    if (c < c1) fwd_chunk<false>(D, lib, wst, c);
-  }
+  const int c = c0 + blockIdx.x * (kSweepBlock / kWave) + threadIdx.x / kWave;
+  if (c < c1) fwd_chunk<false>(D, lib, wst, c);
+}
+
+__global__ __launch_bounds__(kSweepBlock) void k_forward_pieces(DevDesign D, int j0, int j1) {
+  const int j = j0 + blockIdx.x * (kSweepBlock / kWave) + threadIdx.x / kWave;
+  if (j < j1) fwd_piece<false>(D, j);
 }
 
 // ------------------------------------------------------------ backward
 
-// One chunk: every sink of the 64 drivers gets RAT from its consumer (the
-// consumer cell's output RAT minus the recomputed arc delay, min for late and
-// max for early over the output transitions the input reaches) or from its
-// endpoint constraint; the drivers merge RAT_s - d over their sinks.
 // RAT of one sink: its endpoint constraint, or its consumer cell's output RAT
 // minus the recomputed arc delay (min for late, max for early over the output
 // transitions the input reaches).
@@ -481,26 +444,49 @@ __device__ __forceinline__ float4 sink_rat(const DevDesign &D, const LdsLib &lib
 // the drivers merge RAT_s - d over their sinks through LDS integer atomics on
 // order-preserving keys, starting from the neutral element; a dangling
 // endpoint driver's own constraint joins the merge last (min/max are
-// order-independent, so the result is the same and bit-reproducible).  The
-// first sink round and the driver records are requested before any
-// dependent load.
-template <bool kCoh>
-__device__ void bwd_chunk(const DevDesign &D, const LdsLib &lib, int *wacc, int c) {
+// order-independent, so the result is the same and bit-reproducible).
+// bwd_prefetch requests what the sweep does not produce (chunk record, first
+// sink round's state, consumer id and delay, the drivers' endpoint index and
+// arrival); bwd_finish does the consumer gathers and the arithmetic.
+struct BwdPre {
+  int x0, x1, s0, s1;
+  PinState ssA;
+  int consA, drvA, e;
+  float dA;
+  float4 A;
+  int2 pcs;  // sink pieces of a high-fanout driver (first, count)
+};
+
+__device__ __forceinline__ BwdPre bwd_prefetch(const DevDesign &D, int c) {
+  BwdPre p;
   const int lane = lane_id();
   const int4 cr = D.chunk_rec[c];
-  const int x0 = __builtin_amdgcn_readfirstlane(cr.x), x1 = __builtin_amdgcn_readfirstlane(cr.y);
-  const int s0 = __builtin_amdgcn_readfirstlane(cr.z), s1 = __builtin_amdgcn_readfirstlane(cr.w);
-  const int smax = max(s1 - 1, 0);
-  const int sA = s0 + lane, sAc = min(sA, smax);
-  const PinState ssA = D.sink_state[sAc];
-  const int consA = D.sink_cons[sAc];
-  const float dA = D.dq[sAc].x;
-  const int drvA = D.sink_drv[sAc];
+  p.x0 = __builtin_amdgcn_readfirstlane(cr.x);
+  p.x1 = __builtin_amdgcn_readfirstlane(cr.y);
+  p.s0 = __builtin_amdgcn_readfirstlane(cr.z);
+  p.s1 = __builtin_amdgcn_readfirstlane(cr.w);
+  const int smax = max(p.s1 - 1, 0);
+  const int sAc = min(p.s0 + lane, smax);
+  p.ssA = D.sink_state[sAc];
+  p.consA = D.sink_cons[sAc];
+  p.dA = D.dq[sAc].x;
+  p.drvA = D.sink_drv[sAc];
+  const int x = p.x0 + lane;
+  const int xc = x < p.x1 ? x : p.x0;
+  p.e = D.drv_ep[xc];
+  p.A = D.drv_state[xc].at;
+  const int2 pcs = D.chunk_pieces[c];
+  p.pcs = make_int2(__builtin_amdgcn_readfirstlane(pcs.x), __builtin_amdgcn_readfirstlane(pcs.y));
+  return p;
+}
+
+template <bool kCoh>
+__device__ void bwd_finish(const DevDesign &D, const LdsLib &lib, int *wacc, const BwdPre &p) {
+  const int lane = lane_id();
+  const int x0 = p.x0, x1 = p.x1, s1 = p.s1;
+  const int sA = p.s0 + lane;
   const int x = x0 + lane;
   const bool live = x < x1;
-  const int xc = live ? x : x0;
-  const int e = D.drv_ep[xc];
-  const float4 A = D.drv_state[xc].at;
   wacc[lane * 4 + 0] = f2key(-kInf);
   wacc[lane * 4 + 1] = f2key(-kInf);
   wacc[lane * 4 + 2] = f2key(kInf);
@@ -517,64 +503,284 @@ __device__ void bwd_chunk(const DevDesign &D, const LdsLib &lib, int *wacc, int 
     atomicMin(acc + 2, f2key(R.z - d));
     atomicMin(acc + 3, f2key(R.w - d));
   };
-  if (sA < s1) sink(sA, ssA, consA, dA, drvA);
+  if (sA < s1) sink(sA, p.ssA, p.consA, p.dA, p.drvA);
   for (int s = sA + kWave; s < s1; s += kWave) sink(s, D.sink_state[s], D.sink_cons[s], D.dq[s].x, D.sink_drv[s]);
   wave_sync();
   if (live) {
     float4 R = make_float4(key2f(wacc[lane * 4 + 0]), key2f(wacc[lane * 4 + 1]),
                            key2f(wacc[lane * 4 + 2]), key2f(wacc[lane * 4 + 3]));
-    if (e >= 0) {
-      const float4 E = D.ep_rat[e];
+    if (p.e >= 0) {
+      const float4 E = D.ep_rat[p.e];
+      R = make_float4(fmaxf(R.x, E.x), fmaxf(R.y, E.y), fminf(R.z, E.z), fminf(R.w, E.w));
+    }
+    for (int k = 0; k < p.pcs.y; ++k) {  // a high-fanout driver (alone in its chunk): its pieces' merges
+      const float4 E = ld4<kCoh>(D.piece_rat + p.pcs.x + k);
       R = make_float4(fmaxf(R.x, E.x), fmaxf(R.y, E.y), fminf(R.z, E.z), fminf(R.w, E.w));
     }
     st4<kCoh>(&D.cons_rec[x].rat, R);
-    D.drv_slack[x] = slack4(A, R);
-    if (e >= 0) D.ep_slack[e] = ep_slack2(A, R);
+    D.drv_slack[x] = slack4(p.A, R);
+    if (p.e >= 0) D.ep_slack[p.e] = ep_slack2(p.A, R);
   }
   wave_sync();
 }
 
-template <bool kPersistent>
+template <bool kCoh>
+__device__ __forceinline__ void bwd_chunk(const DevDesign &D, const LdsLib &lib, int *wacc, int c) {
+  bwd_finish<kCoh>(D, lib, wacc, bwd_prefetch(D, c));
+}
+
+// Sink RATs of one piece of a high-fanout driver's sinks; the piece's merge
+// of RAT_s - d (max early, min late) is reduced across the wave and left in
+// piece_rat for the driver's own chunk, which runs in the next phase.
+template <bool kCoh>
+__device__ void bwd_piece(const DevDesign &D, const LdsLib &lib, int j) {
+  const int4 pr = D.piece_rec[j];
+  const int sa = __builtin_amdgcn_readfirstlane(pr.y), sb = __builtin_amdgcn_readfirstlane(pr.z);
+  float4 acc = make_float4(-kInf, -kInf, kInf, kInf);
+  for (int s = sa + lane_id(); s < sb; s += kWave) {
+    const PinState ss = D.sink_state[s];
+    const int cons = D.sink_cons[s];
+    const float d = D.dq[s].x;
+    const float4 R = sink_rat<kCoh>(D, lib, ss, cons);
+    if (cons < 0) D.ep_slack[-1 - cons] = ep_slack2(ss.at, R);
+    D.sink_rat[s] = R;
+    D.sink_slack[s] = slack4(ss.at, R);
+    acc = make_float4(fmaxf(acc.x, R.x - d), fmaxf(acc.y, R.y - d), fminf(acc.z, R.z - d), fminf(acc.w, R.w - d));
+  }
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    acc.x = fmaxf(acc.x, __shfl_xor(acc.x, off));
+    acc.y = fmaxf(acc.y, __shfl_xor(acc.y, off));
+    acc.z = fminf(acc.z, __shfl_xor(acc.z, off));
+    acc.w = fminf(acc.w, __shfl_xor(acc.w, off));
+  }
+  if (lane_id() == 0) st4<kCoh>(D.piece_rat + j, acc);
+}
+
 __global__ __launch_bounds__(kSweepBlock) void k_backward(DevDesign D, int c0, int c1) {
   extern __shared__ __align__(32) unsigned char smem[];
   const LdsLib lib = load_lib(D, smem);
   int *wacc = reinterpret_cast<int *>(smem + lib_lds_bytes(D.n_types, D.tstride)) +
               (threadIdx.x / kWave) * kWave * 4;
   __syncthreads();
-  if constexpr (kPersistent) {
-    for (;;) {
-      const int t = take_ticket(D.counters + kCtrBwdTicket);
-      if (t >= D.n_chunks) break;
-      const int c = D.n_chunks - 1 - t;
-      const int lvl = D.chunk_level[c];
-      if (lvl < D.n_cell_levels) wait_level(level_ctr(D, 1, lvl + 1), (uint32_t)D.level_nchunks[lvl + 1]);
-      bwd_chunk<true>(D, lib, wacc, c);
-      signal_add(level_ctr(D, 1, lvl), 1u);
-    }
+  const int c = c0 + blockIdx.x * (kSweepBlock / kWave) + threadIdx.x / kWave;
+  if (c < c1) bwd_chunk<false>(D, lib, wacc, c);
+}
+
+__global__ __launch_bounds__(kSweepBlock) void k_backward_pieces(DevDesign D, int j0, int j1) {
+  extern __shared__ __align__(32) unsigned char smem[];
+  const LdsLib lib = load_lib(D, smem);
+  __syncthreads();
+  const int j = j0 + blockIdx.x * (kSweepBlock / kWave) + threadIdx.x / kWave;
+  if (j < j1) bwd_piece<false>(D, lib, j);
+}
+
+// ------------------------------------------------ persistent sweeps
+//
+// A sweep is a list of phases in order (`Phase`: the chunks of one level, or
+// the sink pieces of one level's high-fanout drivers); every input of a phase
+// comes from earlier phases, so a phase may start once the previous one is
+// complete (which, by induction, implies all earlier ones).  Each phase has
+// kDoneGroups completion counters whose sum counts its finished items.
+//
+// All loop control is wave-uniform: counter atomics are issued by every lane
+// (lane 0 adds the count, the others 0, which the compiler folds into one
+// wave-level atomic) and polled or ticketed values are broadcast with
+// readfirstlane, so every loop exit is a scalar branch.  (With
+// `if (lane == 0) atomic` at both ends of a loop, jump threading once merged
+// the two regions into a lane-0-only path and the other lanes re-entered the
+// loop without a ticket.)
+
+template <bool kCoh>
+__device__ void adj_chunk(const DevDesign &D, const LdsLib &lib, float g_tns, float g_wns, int c);
+
+constexpr int kSweepFwd = 0, kSweepBwd = 1, kSweepAdj = 2;
+
+__device__ __forceinline__ const int4 *sweep_phases(const DevDesign &D, int kind, int &n, int &ctr_base) {
+  if (kind == kSweepBwd) {
+    n = D.n_ph_bwd;
+    ctr_base = D.n_ph_fwd;
+    return D.phases + D.n_ph_fwd;
+  }
+  if (kind == kSweepAdj) {
+    n = D.n_ph_adj;
+    ctr_base = 0;  // the forward counters, cleared before the adjoint sweep
+    return D.phases + D.n_ph_fwd + D.n_ph_bwd;
+  }
+  n = D.n_ph_fwd;
+  ctr_base = 0;
+  return D.phases;
+}
+
+__device__ __forceinline__ uint32_t *done_ctr(const DevDesign &D, int k) {
+  return D.counters + kCtrPhases + (size_t)k * kDoneGroups;
+}
+
+__device__ __forceinline__ uint32_t *ticket_ctr(const DevDesign &D, int k) {
+  return D.counters + kCtrPhases + (size_t)(D.n_ph_fwd + D.n_ph_bwd) * kDoneGroups + k;
+}
+
+// Polls until the phase's group counters sum to target.  Every lane loads one
+// of the group words (lane & 7) and the sum is formed across 8 lanes.
+__device__ __forceinline__ void wait_done(uint32_t *ctr, uint32_t target) {
+  for (;;) {
+    uint32_t v = __hip_atomic_load(ctr + (lane_id() & (kDoneGroups - 1)), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+    v += __shfl_xor(v, 1);
+    v += __shfl_xor(v, 2);
+    v += __shfl_xor(v, 4);
+    if (__builtin_amdgcn_readfirstlane(v) >= target) break;
+    __builtin_amdgcn_s_sleep(1);
+  }
+  // the loop exit waits on the counter load; keep the compiler from hoisting
+  // the coherent data loads that follow above it
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+__device__ __forceinline__ int take_ticket(uint32_t *ctr) {
+  const uint32_t old = atomicAdd(ctr, lane_id() == 0 ? 1u : 0u);
+  return (int)__builtin_amdgcn_readfirstlane(old);
+}
+
+// Every coherent store of this wave has completed (vmcnt 0) before the counter
+// moves, so a consumer that sees the count reads the new values.
+__device__ __forceinline__ void signal_add(uint32_t *ctr, uint32_t n) {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);
+  __hip_atomic_fetch_add(ctr, lane_id() == 0 ? n : 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int kKind>
+struct SweepPre {
+  using type = int;
+};
+template <>
+struct SweepPre<kSweepFwd> {
+  using type = FwdPre;
+};
+template <>
+struct SweepPre<kSweepBwd> {
+  using type = BwdPre;
+};
+
+// What a chunk needs that the sweep does not produce, requested early.
+template <int kKind>
+__device__ __forceinline__ typename SweepPre<kKind>::type sweep_pre(const DevDesign &D, int c);
+template <>
+__device__ __forceinline__ FwdPre sweep_pre<kSweepFwd>(const DevDesign &D, int c) { return fwd_prefetch(D, c); }
+template <>
+__device__ __forceinline__ BwdPre sweep_pre<kSweepBwd>(const DevDesign &D, int c) { return bwd_prefetch(D, c); }
+template <>
+__device__ __forceinline__ int sweep_pre<kSweepAdj>(const DevDesign &, int c) { return c; }
+
+// (Dispatch is by template constant rather than lambdas: a lambda capturing
+// the by-value kernel argument D by reference forces D into scratch memory.)
+template <int kKind>
+__device__ __forceinline__ void sweep_chunk(const DevDesign &D, const LdsLib &lib, unsigned char *wsm, int wave,
+                                            float g_tns, float g_wns, const typename SweepPre<kKind>::type &p) {
+  if constexpr (kKind == kSweepFwd) {
+    fwd_finish<true>(D, lib, reinterpret_cast<PinState *>(wsm) + wave * kWave, p);
+  } else if constexpr (kKind == kSweepBwd) {
+    bwd_finish<true>(D, lib, reinterpret_cast<int *>(wsm) + wave * kWave * 4, p);
   } else {
-    const int c = c0 + blockIdx.x * (kSweepBlock / kWave) + threadIdx.x / kWave;
-    if (c < c1) bwd_chunk<false>(D, lib, wacc, c);
+    adj_chunk<true>(D, lib, g_tns, g_wns, p);
   }
 }
 
-// ------------------------------------------------ cooperative sweeps
-
-__global__ __launch_bounds__(kSweepBlock) void k_forward_coop(DevDesign D) {
-  extern __shared__ __align__(32) unsigned char smem[];
-  const LdsLib lib = load_lib(D, smem);
-  PinState *wst = reinterpret_cast<PinState *>(smem + lib_lds_bytes(D.n_types, D.tstride)) +
-                  (threadIdx.x / kWave) * kWave;
-  __syncthreads();
-  coop_levels<false>(D, 0, [&](int c) { fwd_chunk<true>(D, lib, wst, c); });
+template <int kKind>
+__device__ __forceinline__ void sweep_piece(const DevDesign &D, const LdsLib &lib, int j) {
+  if constexpr (kKind == kSweepFwd) fwd_piece<true>(D, j);
+  if constexpr (kKind == kSweepBwd) bwd_piece<true>(D, lib, j);
 }
 
-__global__ __launch_bounds__(kSweepBlock) void k_backward_coop(DevDesign D) {
+// Cooperative schedule (every block resident, guaranteed by the cooperative
+// launch): of each phase, wave w of W takes items first + w, first + w + W, ...
+// A block with items in a phase first waits until the previous phase is
+// complete (its first chunk's sweep-independent loads already in flight),
+// runs them, waits for its waves' stores, and adds their number to its group
+// counter; blocks without items in a phase skip it.  No per-item atomics.
+template <int kKind>
+__device__ __forceinline__ void sweep_coop(const DevDesign &D, const LdsLib &lib, unsigned char *wsm, float g_tns,
+                                           float g_wns) {
+  constexpr int kWaves = kSweepBlock / kWave;
+  int n_ph = 0, base = 0;
+  const int4 *ph = sweep_phases(D, kKind, n_ph, base);
+  const int W = (int)gridDim.x * kWaves;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int b0 = blockIdx.x * kWaves;
+  const int g = blockIdx.x & (kDoneGroups - 1);
+  int prev_n = -1;
+  for (int k = 0; k < n_ph; ++k) {
+    const int4 P = ph[k];
+    const int kind = __builtin_amdgcn_readfirstlane(P.x), first = __builtin_amdgcn_readfirstlane(P.y);
+    const int n = __builtin_amdgcn_readfirstlane(P.z);
+    int mine = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w)
+      if (b0 + w < n) mine += (n - (b0 + w) + W - 1) / W;
+    if (mine > 0) {
+      const int cf = first + b0 + wave;
+      const bool chunks = kind == kItemChunk;
+      auto p = sweep_pre<kKind>(D, chunks && cf < first + n ? cf : 0);
+      if (prev_n >= 0 && wave == 0) wait_done(done_ctr(D, base + k - 1), (uint32_t)prev_n);
+      __syncthreads();
+      for (int c = cf; c < first + n; c += W) {
+        if (chunks) {
+          if (c != cf) p = sweep_pre<kKind>(D, c);
+          sweep_chunk<kKind>(D, lib, wsm, wave, g_tns, g_wns, p);
+        } else {
+          sweep_piece<kKind>(D, lib, c);
+        }
+      }
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      if (wave == 0) signal_add(done_ctr(D, base + k) + g, (uint32_t)mine);
+    }
+    prev_n = n;
+  }
+}
+
+// Ticket schedule (any grid size): waves take the items of each phase from the
+// phase's ticket counter in order and move to the next phase when it is
+// exhausted; an item waits for the previous phase to complete.  Only running
+// waves hold tickets, so the items of every earlier phase are in the hands of
+// running waves and finish.
+template <int kKind>
+__device__ __forceinline__ void sweep_tickets(const DevDesign &D, const LdsLib &lib, unsigned char *wsm, float g_tns,
+                                              float g_wns) {
+  int n_ph = 0, base = 0;
+  const int4 *ph = sweep_phases(D, kKind, n_ph, base);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  int prev_n = -1;
+  for (int k = 0; k < n_ph; ++k) {
+    const int4 P = ph[k];
+    const int kind = __builtin_amdgcn_readfirstlane(P.x), first = __builtin_amdgcn_readfirstlane(P.y);
+    const int n = __builtin_amdgcn_readfirstlane(P.z);
+    for (;;) {
+      const int t = take_ticket(ticket_ctr(D, base + k));
+      if (t >= n) break;
+      if (prev_n >= 0) wait_done(done_ctr(D, base + k - 1), (uint32_t)prev_n);
+      if (kind == kItemChunk) {
+        sweep_chunk<kKind>(D, lib, wsm, wave, g_tns, g_wns, sweep_pre<kKind>(D, first + t));
+      } else {
+        sweep_piece<kKind>(D, lib, first + t);
+      }
+      signal_add(done_ctr(D, base + k), 1u);
+    }
+    prev_n = n;
+  }
+}
+
+template <int kKind, bool kCoop>
+__global__ __launch_bounds__(kSweepBlock) void k_sweep(DevDesign D, float g_tns, float g_wns) {
   extern __shared__ __align__(32) unsigned char smem[];
   const LdsLib lib = load_lib(D, smem);
-  int *wacc = reinterpret_cast<int *>(smem + lib_lds_bytes(D.n_types, D.tstride)) +
-              (threadIdx.x / kWave) * kWave * 4;
   __syncthreads();
-  coop_levels<true>(D, 1, [&](int c) { bwd_chunk<true>(D, lib, wacc, c); });
+  unsigned char *wsm = smem + lib_lds_bytes(D.n_types, D.tstride);
+  if constexpr (kCoop)
+    sweep_coop<kKind>(D, lib, wsm, g_tns, g_wns);
+  else
+    sweep_tickets<kKind>(D, lib, wsm, g_tns, g_wns);
 }
 
 // ------------------------------------------------------------------ RC
@@ -623,8 +829,10 @@ __device__ void block_scan(const double *in, double *out, int n, bool exclusive,
     double x[kScanPer];
     double run = 0.0;
 #pragma unroll
+    for (int j = 0; j < kScanPer; ++j) x[j] = in[min(i0 + j, n - 1)];  // all loads in flight
+#pragma unroll
     for (int j = 0; j < kScanPer; ++j) {
-      x[j] = (i0 + j < n) ? in[i0 + j] : 0.0;
+      if (i0 + j >= n) x[j] = 0.0;
       run += x[j];
     }
     double incl = run;
@@ -660,16 +868,45 @@ __device__ void block_scan(const double *in, double *out, int n, bool exclusive,
   __syncthreads();
 }
 
-// Y[p] = X[p] - sum of X[a] over the nodes a whose subtree ends at p (the
-// group of p, precomputed as a CSR in a fixed order, so the loads are
-// independent).
-__device__ void euler_terms(const double *X, double *Y, const int32_t *egp, const int32_t *egl, int m) {
-  for (int p = threadIdx.x; p < m; p += blockDim.x) {
-    double e = 0.0;
-    for (int i = egp[p]; i < egp[p + 1]; ++i) e += X[egl[i]];
-    Y[p] = X[p] - e;
+// out[k] = load(k) for k in [0, m): each thread requests kMapUnroll elements
+// (strided by the block) before storing any, so a pass costs a few memory round
+// trips per 8192 nodes instead of one per node.  The functors capture plain
+// pointers only.
+constexpr int kMapUnroll = 4;
+
+template <class Load, class Store>
+__device__ __forceinline__ void wide_map(int m, Load load, Store store) {
+  using V = decltype(load(0));
+  const int nt = blockDim.x;
+  for (int b = threadIdx.x; b < m; b += kMapUnroll * nt) {
+    V v[kMapUnroll];
+#pragma unroll
+    for (int u = 0; u < kMapUnroll; ++u) v[u] = load(min(b + u * nt, m - 1));
+#pragma unroll
+    for (int u = 0; u < kMapUnroll; ++u)
+      if (b + u * nt < m) store(b + u * nt, v[u]);
   }
   __syncthreads();
+}
+
+// Path sums from edge terms X (X[0] = 0): out[p] = sum over the ancestors-or-
+// self a of p of X[a] = inclusive prefix over q <= p of (X[q] - E[q]), with
+// E[q] = sum of X[a] over the nodes a whose subtree ends at q.  The nodes are
+// listed grouped by end position (egl, offsets egp), so E is a difference of an
+// FP64 exclusive prefix V over X[egl[i]].
+__device__ void wide_path_sum(const double *X, const int32_t *egp, const int32_t *egl, double *V, double *out,
+                              int m, double *s_w) {
+  wide_map(m, [=](int i) { return X[egl[i]]; }, [=](int i, double v) { V[i] = v; });
+  block_scan(V, V, m, true, s_w);
+  wide_map(m, [=](int p) { return X[p] - (V[egp[p + 1]] - V[egp[p]]); }, [=](int p, double v) { out[p] = v; });
+  block_scan(out, out, m, false, s_w);
+}
+
+// X[k] = R[k] (subtree sum of the values whose exclusive prefix is P) for k > 0;
+// X[0] = 0 (the root has no segment).
+__device__ __forceinline__ void wide_edge(const float *R, const double *P, const int32_t *end, double *X, int m) {
+  wide_map(m, [=](int k) { return k ? (double)R[k] * (P[end[k]] - P[k]) : 0.0; },
+           [=](int k, double v) { X[k] = v; });
 }
 
 __device__ void rc_wide_net(const DevDesign &D, const BigNet &B, const WideNets &W, double *s_w) {
@@ -680,32 +917,31 @@ __device__ void rc_wide_net(const DevDesign &D, const BigNet &B, const WideNets 
   const int32_t *end = W.end + B.aux;
   const float *pc = W.pc + B.aux;
   const int32_t *egp = W.egp + B.egp, *egl = W.egl + B.aux;
-  double *A = W.scratch + B.scr, *P = A + (m + 1), *X = P + (m + 1), *Y = X + (m + 1);
-  const int tid = threadIdx.x, nt = blockDim.x;
-  for (int k = tid; k < m; k += nt) A[k] = (double)Cw[k] + (double)pc[k];  // C^
-  __syncthreads();
+  const int st = m + 1;
+  double *A = W.scratch + B.scr, *P = A + st, *X = P + st, *Y = X + st, *V = Y + st;
+  wide_map(m, [=](int k) { return (double)Cw[k] + (double)pc[k]; }, [=](int k, double v) { A[k] = v; });  // C^
   block_scan(A, P, m, true, s_w);                                          // P: prefix of C^
   const double total = P[m];
-  for (int k = tid; k < m; k += nt) X[k] = k ? (double)R[k] * (P[end[k]] - P[k]) : 0.0;  // R load
-  __syncthreads();
-  euler_terms(X, Y, egp, egl, m);
-  block_scan(Y, Y, m, false, s_w);                                         // Y: d
-  for (int k = tid; k < m; k += nt) X[k] = A[k] * Y[k];                    // C^ d
-  __syncthreads();
+  wide_edge(R, P, end, X, m);                                              // R load
+  wide_path_sum(X, egp, egl, V, Y, m, s_w);                                // Y: d
+  wide_map(m, [=](int k) { return A[k] * Y[k]; }, [=](int k, double v) { X[k] = v; });  // C^ d
   block_scan(X, P, m, true, s_w);                                          // P: prefix of C^ d
-  for (int k = tid; k < m; k += nt) X[k] = k ? (double)R[k] * (P[end[k]] - P[k]) : 0.0;  // R ld
-  __syncthreads();
-  euler_terms(X, A, egp, egl, m);
-  block_scan(A, A, m, false, s_w);                                         // A: m2
-  if (tid == 0) {
+  wide_edge(R, P, end, X, m);                                              // R ld
+  wide_path_sum(X, egp, egl, V, A, m, s_w);                                // A: m2
+  if (threadIdx.x == 0) {
     D.L_net[x] = (float)total;
     D.cons_rec[x].L = (float)total;
   }
-  for (int s = D.sink_ptr[x] + tid; s < D.sink_ptr[x + 1]; s += nt) {
-    const int k = D.sink_node[s];
-    const double d = Y[k];
-    D.dq[s] = make_float2((float)d, (float)fmax(0.0, 2.0 * A[k] - d * d));
-  }
+  const int s0 = D.sink_ptr[x], ns = D.sink_ptr[x + 1] - s0;
+  const int32_t *snode = D.sink_node + s0;
+  float2 *dq = D.dq + s0;
+  wide_map(ns,
+           [=](int j) {
+             const int k = snode[j];
+             const double d = Y[k];
+             return make_float2((float)d, (float)fmax(0.0, 2.0 * A[k] - d * d));
+           },
+           [=](int j, float2 v) { dq[j] = v; });
 }
 
 // Wide nets: one 1024-thread block per net (launched on a side stream so it
@@ -1109,33 +1345,12 @@ __device__ void adj_chunk(const DevDesign &D, const LdsLib &lib, float g_tns, fl
   }
 }
 
-template <bool kPersistent>
 __global__ __launch_bounds__(kSweepBlock) void k_adjoint(DevDesign D, float g_tns, float g_wns, int c0, int c1) {
   extern __shared__ __align__(32) unsigned char smem[];
   const LdsLib lib = load_lib(D, smem);
   __syncthreads();
-  if constexpr (kPersistent) {
-    // reuses the forward counters (cleared before the adjoint sweep)
-    for (;;) {
-      const int t = take_ticket(D.counters + kCtrFwdTicket);
-      if (t >= D.n_chunks) break;
-      const int c = D.n_chunks - 1 - t;
-      const int lvl = D.chunk_level[c];
-      if (lvl < D.n_cell_levels) wait_level(level_ctr(D, 0, lvl + 1), (uint32_t)D.level_nchunks[lvl + 1]);
-      adj_chunk<true>(D, lib, g_tns, g_wns, c);
-      signal_add(level_ctr(D, 0, lvl), 1u);
-    }
-  } else {
-    const int c = c0 + blockIdx.x * (kSweepBlock / kWave) + threadIdx.x / kWave;
-    if (c < c1) adj_chunk<false>(D, lib, g_tns, g_wns, c);
-  }
-}
-
-__global__ __launch_bounds__(kSweepBlock) void k_adjoint_coop(DevDesign D, float g_tns, float g_wns) {
-  extern __shared__ __align__(32) unsigned char smem[];
-  const LdsLib lib = load_lib(D, smem);
-  __syncthreads();
-  coop_levels<true>(D, 0, [&](int c) { adj_chunk<true>(D, lib, g_tns, g_wns, c); });
+  const int c = c0 + blockIdx.x * (kSweepBlock / kWave) + threadIdx.x / kWave;
+  if (c < c1) adj_chunk<false>(D, lib, g_tns, g_wns, c);
 }
 
 // ------------------------------------------------------------ RC adjoint
@@ -1158,33 +1373,26 @@ __device__ void rc_adjoint_wide(const DevDesign &D, const BigNet &B, const WideN
   const int32_t *end = W.end + B.aux;
   const float *pc = W.pc + B.aux;
   const int32_t *nsp = W.nsp + B.nsp;
-  const int32_t *big_nsl = W.nsl;
+  const int32_t *nsl = W.nsl;
   const int32_t *egp = W.egp + B.egp, *egl = W.egl + B.aux;
-  const int s0 = D.sink_ptr[x];
+  const float2 *gdq = D.g_dq + D.sink_ptr[x];
   const int st = m + 1;
   double *A = W.scratch + B.scr, *P = A + st, *X = P + st, *Y = X + st, *Z = Y + st;
-  double *G1 = Z + st, *G2 = G1 + st, *T = G2 + st;
-  const int tid = threadIdx.x, nt = blockDim.x;
+  double *G1 = Z + st, *G2 = G1 + st, *T = G2 + st, *V = T + st;
   // forward moments: Y = d, Z = m2
-  for (int k = tid; k < m; k += nt) A[k] = (double)Cw[k] + (double)pc[k];
-  __syncthreads();
+  wide_map(m, [=](int k) { return (double)Cw[k] + (double)pc[k]; }, [=](int k, double v) { A[k] = v; });
   block_scan(A, P, m, true, s_w);
-  for (int k = tid; k < m; k += nt) X[k] = k ? (double)R[k] * (P[end[k]] - P[k]) : 0.0;
-  __syncthreads();
-  euler_terms(X, Y, egp, egl, m);
-  block_scan(Y, Y, m, false, s_w);
-  for (int k = tid; k < m; k += nt) X[k] = A[k] * Y[k];
-  __syncthreads();
+  wide_edge(R, P, end, X, m);
+  wide_path_sum(X, egp, egl, V, Y, m, s_w);
+  wide_map(m, [=](int k) { return A[k] * Y[k]; }, [=](int k, double v) { X[k] = v; });
   block_scan(X, P, m, true, s_w);
-  for (int k = tid; k < m; k += nt) X[k] = k ? (double)R[k] * (P[end[k]] - P[k]) : 0.0;
-  __syncthreads();
-  euler_terms(X, Z, egp, egl, m);
-  block_scan(Z, Z, m, false, s_w);
+  wide_edge(R, P, end, X, m);
+  wide_path_sum(X, egp, egl, V, Z, m, s_w);
   // sink-node seeds, sinks of a node in sink order
-  for (int k = tid; k < m; k += nt) {
+  for (int k = threadIdx.x; k < m; k += blockDim.x) {
     double gd = 0.0, gm = 0.0;
     for (int i = nsp[k]; i < nsp[k + 1]; ++i) {
-      const float2 g = D.g_dq[s0 + big_nsl[i]];
+      const float2 g = gdq[nsl[i]];
       const double gq = (2.0 * Z[k] - Y[k] * Y[k]) > 0.0 ? (double)g.y : 0.0;
       gd += (double)g.x - 2.0 * Y[k] * gq;
       gm += 2.0 * gq;
@@ -1193,27 +1401,21 @@ __device__ void rc_adjoint_wide(const DevDesign &D, const BigNet &B, const WideN
     G2[k] = gm;
   }
   __syncthreads();
-  block_scan(G1, P, m, true, s_w);                         // Gd = subtree sums
-  for (int k = tid; k < m; k += nt) G1[k] = P[end[k]] - P[k];
-  __syncthreads();
-  block_scan(G2, P, m, true, s_w);                         // Gm
-  for (int k = tid; k < m; k += nt) X[k] = k ? (double)R[k] * (P[end[k]] - P[k]) : 0.0;
-  __syncthreads();
-  euler_terms(X, T, egp, egl, m);                          // H = path sum of R Gm
-  block_scan(T, T, m, false, s_w);
-  for (int k = tid; k < m; k += nt) X[k] = k ? (double)R[k] * G1[k] : 0.0;
-  __syncthreads();
-  euler_terms(X, G1, egp, egl, m);                         // PA = path sum of R Gd
-  block_scan(G1, G1, m, false, s_w);
-  for (int k = tid; k < m; k += nt) X[k] = A[k] * T[k];
-  __syncthreads();
-  block_scan(X, P, m, true, s_w);                          // K = subtree sum of C^ H
-  for (int k = tid; k < m; k += nt) X[k] = k ? (double)R[k] * (P[end[k]] - P[k]) : 0.0;
-  __syncthreads();
-  euler_terms(X, G2, egp, egl, m);                         // PB = path sum of R K
-  block_scan(G2, G2, m, false, s_w);
+  block_scan(G1, P, m, true, s_w);                          // Gd = subtree sums
+  wide_map(m, [=](int k) { return P[end[k]] - P[k]; }, [=](int k, double v) { G1[k] = v; });
+  block_scan(G2, P, m, true, s_w);                          // Gm
+  wide_edge(R, P, end, X, m);
+  wide_path_sum(X, egp, egl, V, T, m, s_w);                 // H = path sum of R Gm
+  wide_map(m, [=](int k) { return k ? (double)R[k] * G1[k] : 0.0; }, [=](int k, double v) { X[k] = v; });
+  wide_path_sum(X, egp, egl, V, G1, m, s_w);                // PA = path sum of R Gd
+  wide_map(m, [=](int k) { return A[k] * T[k]; }, [=](int k, double v) { X[k] = v; });
+  block_scan(X, P, m, true, s_w);                           // K = subtree sum of C^ H
+  wide_edge(R, P, end, X, m);
+  wide_path_sum(X, egp, egl, V, G2, m, s_w);                // PB = path sum of R K
   const double gL = (double)D.g_load[x];
-  for (int k = tid; k < m; k += nt) D.g_cap[k0 + k] = (float)(gL + G1[k] + Y[k] * T[k] + G2[k]);
+  float *gcap = D.g_cap + k0;
+  wide_map(m, [=](int k) { return (float)(gL + G1[k] + Y[k] * T[k] + G2[k]); },
+           [=](int k, float v) { gcap[k] = v; });
 }
 
 // Same block layout as k_rc.  Small nets: one lane per net in LDS, the forward
@@ -1408,12 +1610,13 @@ size_t sweep_lds_bytes(const DevDesign &D) {
   return lib_lds_bytes(D.n_types, D.tstride) + per_wave * (kSweepBlock / kWave);
 }
 
-// Blocks per CU every cooperative sweep kernel can keep resident at once.
-int coop_blocks_per_cu(size_t lds_bytes) {
+// Blocks per CU every sweep kernel of the given schedule can keep resident.
+template <bool kCoop>
+static int sweep_occupancy(size_t lds_bytes) {
   int n = 1 << 30;
-  const void *ks[] = {reinterpret_cast<const void *>(&k_forward_coop),
-                      reinterpret_cast<const void *>(&k_backward_coop),
-                      reinterpret_cast<const void *>(&k_adjoint_coop)};
+  const void *ks[] = {reinterpret_cast<const void *>(&k_sweep<kSweepFwd, kCoop>),
+                      reinterpret_cast<const void *>(&k_sweep<kSweepBwd, kCoop>),
+                      reinterpret_cast<const void *>(&k_sweep<kSweepAdj, kCoop>)};
   for (const void *k : ks) {
     int b = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k, kSweepBlock, lds_bytes) != hipSuccess) return 0;
@@ -1422,18 +1625,28 @@ int coop_blocks_per_cu(size_t lds_bytes) {
   return n;
 }
 
+int coop_blocks_per_cu(size_t lds_bytes) { return sweep_occupancy<true>(lds_bytes); }
+
 int sweep_blocks_per_cu(size_t lds_bytes) {
-  int nf = 0, nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nf, k_forward<true>, kSweepBlock, lds_bytes) != hipSuccess)
-    return 1;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_backward<true>, kSweepBlock, lds_bytes) != hipSuccess)
-    return 1;
-  const int n = nf < nb ? nf : nb;
+  const int n = sweep_occupancy<false>(lds_bytes);
   return n < 1 ? 1 : n;
 }
 
+template <int kKind>
+static hipError_t launch_sweep(const DevDesign &D, float g_tns, float g_wns, int grid, bool coop, hipStream_t s) {
+  if (coop) {
+    DevDesign a = D;
+    float gt = g_tns, gw = g_wns;
+    void *args[] = {&a, &gt, &gw};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_sweep<kKind, true>), dim3(grid),
+                                      dim3(kSweepBlock), args, (unsigned)sweep_lds_bytes(D), s);
+  }
+  hipLaunchKernelGGL((k_sweep<kKind, false>), dim3(grid), dim3(kSweepBlock), sweep_lds_bytes(D), s, D, g_tns, g_wns);
+  return hipGetLastError();
+}
+
 hipError_t launch_rc(const DevDesign &D, const int2 *chunks, int n_chunks, hipStream_t s) {
-  const int n_ctr = n_counters(D.n_cell_levels);
+  const int n_ctr = n_counters(D.n_ph_fwd + D.n_ph_bwd);
   hipLaunchKernelGGL(k_rc, dim3(n_chunks > 0 ? n_chunks : 1), dim3(kRcBlock), 0, s, D, chunks, n_chunks, D.counters,
                      n_ctr);
   return hipGetLastError();
@@ -1452,40 +1665,33 @@ hipError_t launch_rc_adjoint_wide(const DevDesign &D, const WideNets &W, hipStre
 }
 
 hipError_t launch_forward(const DevDesign &D, int grid, bool coop, hipStream_t s) {
-  if (coop) {
-    DevDesign a = D;
-    void *args[] = {&a};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_forward_coop), dim3(grid),
-                                      dim3(kSweepBlock), args, (unsigned)sweep_lds_bytes(D), s);
-  }
-  hipLaunchKernelGGL(k_forward<true>, dim3(grid), dim3(kSweepBlock), sweep_lds_bytes(D), s, D, 0, 0);
-  return hipGetLastError();
+  return launch_sweep<kSweepFwd>(D, 0.0f, 0.0f, grid, coop, s);
 }
 
-hipError_t launch_forward_level(const DevDesign &D, int c0, int c1, hipStream_t s) {
-  if (c1 <= c0) return hipSuccess;
+hipError_t launch_forward_phase(const DevDesign &D, int4 ph, hipStream_t s) {
+  if (ph.z <= 0) return hipSuccess;
   const int per = kSweepBlock / kWave;
-  hipLaunchKernelGGL(k_forward<false>, dim3(blocks_for(c1 - c0, per)), dim3(kSweepBlock), sweep_lds_bytes(D), s,
-                     D, c0, c1);
+  if (ph.x == kItemPiece)
+    hipLaunchKernelGGL(k_forward_pieces, dim3(blocks_for(ph.z, per)), dim3(kSweepBlock), 0, s, D, ph.y, ph.y + ph.z);
+  else
+    hipLaunchKernelGGL(k_forward, dim3(blocks_for(ph.z, per)), dim3(kSweepBlock), sweep_lds_bytes(D), s, D, ph.y,
+                       ph.y + ph.z);
   return hipGetLastError();
 }
 
 hipError_t launch_backward(const DevDesign &D, int grid, bool coop, hipStream_t s) {
-  if (coop) {
-    DevDesign a = D;
-    void *args[] = {&a};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_backward_coop), dim3(grid),
-                                      dim3(kSweepBlock), args, (unsigned)sweep_lds_bytes(D), s);
-  }
-  hipLaunchKernelGGL(k_backward<true>, dim3(grid), dim3(kSweepBlock), sweep_lds_bytes(D), s, D, 0, 0);
-  return hipGetLastError();
+  return launch_sweep<kSweepBwd>(D, 0.0f, 0.0f, grid, coop, s);
 }
 
-hipError_t launch_backward_level(const DevDesign &D, int c0, int c1, hipStream_t s) {
-  if (c1 <= c0) return hipSuccess;
+hipError_t launch_backward_phase(const DevDesign &D, int4 ph, hipStream_t s) {
+  if (ph.z <= 0) return hipSuccess;
   const int per = kSweepBlock / kWave;
-  hipLaunchKernelGGL(k_backward<false>, dim3(blocks_for(c1 - c0, per)), dim3(kSweepBlock), sweep_lds_bytes(D), s,
-                     D, c0, c1);
+  if (ph.x == kItemPiece)
+    hipLaunchKernelGGL(k_backward_pieces, dim3(blocks_for(ph.z, per)), dim3(kSweepBlock), sweep_lds_bytes(D), s, D,
+                       ph.y, ph.y + ph.z);
+  else
+    hipLaunchKernelGGL(k_backward, dim3(blocks_for(ph.z, per)), dim3(kSweepBlock), sweep_lds_bytes(D), s, D, ph.y,
+                       ph.y + ph.z);
   return hipGetLastError();
 }
 
@@ -1496,22 +1702,14 @@ hipError_t launch_reduce_smooth(const DevDesign &D, double *partials, double *ou
 }
 
 hipError_t launch_adjoint(const DevDesign &D, float g_tns, float g_wns, int grid, bool coop, hipStream_t s) {
-  if (coop) {
-    DevDesign a = D;
-    float gt = g_tns, gw = g_wns;
-    void *args[] = {&a, &gt, &gw};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_adjoint_coop), dim3(grid),
-                                      dim3(kSweepBlock), args, (unsigned)sweep_lds_bytes(D), s);
-  }
-  hipLaunchKernelGGL(k_adjoint<true>, dim3(grid), dim3(kSweepBlock), sweep_lds_bytes(D), s, D, g_tns, g_wns, 0, 0);
-  return hipGetLastError();
+  return launch_sweep<kSweepAdj>(D, g_tns, g_wns, grid, coop, s);
 }
 
-hipError_t launch_adjoint_level(const DevDesign &D, float g_tns, float g_wns, int c0, int c1, hipStream_t s) {
-  if (c1 <= c0) return hipSuccess;
+hipError_t launch_adjoint_phase(const DevDesign &D, float g_tns, float g_wns, int4 ph, hipStream_t s) {
+  if (ph.z <= 0) return hipSuccess;
   const int per = kSweepBlock / kWave;
-  hipLaunchKernelGGL(k_adjoint<false>, dim3(blocks_for(c1 - c0, per)), dim3(kSweepBlock), sweep_lds_bytes(D), s, D,
-                     g_tns, g_wns, c0, c1);
+  hipLaunchKernelGGL(k_adjoint, dim3(blocks_for(ph.z, per)), dim3(kSweepBlock), sweep_lds_bytes(D), s, D, g_tns,
+                     g_wns, ph.y, ph.y + ph.z);
   return hipGetLastError();
 }
 

@@ -195,3 +195,15 @@ def test_cells_wider_than_inline_fanins(sched):
     assert int(np.diff(d.cell_in_ptr).max()) > 4
     r = oracle.sta(d)
     compare_full(d, r, _run(d, sched=sched))
+
+
+@pytest.mark.parametrize("sched", [STA_SCHED_PERSISTENT, STA_SCHED_PER_LEVEL, STA_SCHED_GRAPH])
+def test_split_high_fanout_drivers(sched):
+    """Drivers of 1.5k-5k sinks: each gets a chunk of its own and its sinks
+    beyond the first piece go to separate work items (forward sink states,
+    backward RAT merges folded into the driver)."""
+    cfg = synth.mid_config(seed=23, n_cells=20_000, n_levels=20, n_hf=4, hf_min=1500, hf_max=5000)
+    d = synth.generate(cfg)
+    assert np.diff(d.net_sink_ptr).max() > 1024
+    r = oracle.sta(d)
+    compare_full(d, r, _run(d, sched=sched))
