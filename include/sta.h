@@ -295,6 +295,40 @@ typedef struct {
 } sta_tune_result;
 sta_status sta_autotune(sta_ctx *ctx, int32_t reps, sta_tune_result *best, void *stream);
 
+/* Top-k timing path report (§III "Report options": top-k path reports
+ * controlled by k, a per-endpoint limit and a slack-less-than threshold, as
+ * flattened CSR path-pin arrays with slacks).  A path runs from a primary
+ * input to an endpoint over net arcs and cell arcs (transitions as each
+ * type's unateness allows); its arrival is the startpoint arrival plus the
+ * arc delays of the last sta_update_timing (net arc: the sink's Elmore delay;
+ * cell arc: the NLDM delay at the input's propagated slew and the output
+ * net's load, in the query's early or late view); late slack = endpoint RAT
+ * - arrival, early slack = arrival - endpoint RAT, per endpoint transition.
+ * The report holds, in ascending slack, the paths of smallest slack over all
+ * endpoints, at most per_endpoint of them per endpoint, only those with
+ * slack < slack_below, and at most k in all.  Exact (k-best enumeration by
+ * deviations from each pin's critical fanin).  Needs a hard-mode context with
+ * endpoint sorting on (else STA_E_STATE).
+ *
+ *   *n_paths            (host) number of paths reported, <= k
+ *   path_ptr [k+1]      CSR offsets into path_pin / path_rf
+ *   path_pin, path_rf   [k * n_levels] pins from startpoint to endpoint and
+ *                       each pin's transition (0 rise, 1 fall); a path has
+ *                       at most n_levels (sta_info) pins
+ *   path_slack [k]      slack of each path; path_endpoint [k] its endpoint index
+ * Any array may be NULL; arrays go to `dst` memory.  Allocates device scratch
+ * for the search (bounded by k, per_endpoint and the level count);
+ * synchronizes `stream`. */
+typedef struct {
+  int32_t k;                   /* most paths reported (>= 1) */
+  int32_t per_endpoint;        /* most paths per endpoint, 1..64 */
+  float slack_below;           /* report only slack < slack_below (+inf: no threshold) */
+  int32_t el;                  /* 0 early (hold) view, 1 late (setup) view */
+} sta_path_query;
+sta_status sta_report_paths(sta_ctx *ctx, const sta_path_query *q, int32_t *n_paths, int32_t *path_ptr,
+                            int32_t *path_pin, int8_t *path_rf, float *path_slack, int32_t *path_endpoint,
+                            sta_mem dst, void *stream);
+
 /* Name of a status code; message of the calling thread's last error. */
 const char *sta_status_string(sta_status s);
 const char *sta_last_error(void);

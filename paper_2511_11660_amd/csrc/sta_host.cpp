@@ -105,6 +105,8 @@ struct sta_ctx {
   float *rc_cap = nullptr;
   int32_t *pin_loc = nullptr, *net_slot = nullptr, *sink_slot = nullptr, *node_src = nullptr;
   int32_t *ep_pin = nullptr, *pin_level = nullptr, *level_order = nullptr;
+  int32_t *slot_drv_pin = nullptr, *slot_sink_pin = nullptr;  // slot -> caller pin (path reports)
+  int max_in = 1;                      // most inputs of any library type
   int2 *rc_chunks = nullptr;
   BigNet *big = nullptr;
   int32_t *big_end = nullptr, *big_nsp = nullptr, *big_nsl = nullptr, *big_egp = nullptr, *big_egl = nullptr;
@@ -585,7 +587,7 @@ static sta_status build_layout(sta_ctx *C, const Inputs &I, const std::vector<in
   const int NS = sink_ptr[ND];
   C->n_sinks = NS;
   C->n_nodes = NN;
-  std::vector<int32_t> sink_drv(NS), sink_cons(NS), sink_node(NS), sink_slot(NS), pin_loc(NP);
+  std::vector<int32_t> sink_drv(NS), sink_cons(NS), sink_node(NS), sink_slot(NS), pin_loc(NP), sink_pin_of_slot(NS);
   std::vector<float> sink_pincap(NS), rc_res(NN), rc_cap(NN);
   std::vector<int32_t> rc_parent(NN), node_src(NN), big_x, big_end, big_nsp, big_nsl, big_egp, big_egl;
   std::vector<float> big_pc;
@@ -659,6 +661,7 @@ static sta_status build_layout(sta_ctx *C, const Inputs &I, const std::vector<in
     for (int sc = I.net_sink_ptr[n]; sc < I.net_sink_ptr[n + 1]; ++sc, ++s) {
       const int p = I.net_sink_pin[sc];
       sink_slot[sc] = s;
+      sink_pin_of_slot[s] = p;
       sink_drv[s] = x;
       const int k = I.sink_node[sc];
       sink_node[s] = is_big ? newof[k] : k;
@@ -757,6 +760,7 @@ static sta_status build_layout(sta_ctx *C, const Inputs &I, const std::vector<in
   // inline fanin sink slots when every type has at most 4 inputs
   int max_in = 0;
   for (int t = 0; t < lib.n_types; ++t) max_in = std::max(max_in, (int)lib.n_inputs[t]);
+  C->max_in = std::max(max_in, 1);
   std::vector<int4> fanin4;
   if (max_in <= 4) {
     fanin4.assign(ND, make_int4(-1, -1, -1, -1));
@@ -898,6 +902,8 @@ static sta_status build_layout(sta_ctx *C, const Inputs &I, const std::vector<in
   STA_TRY(C->upload(&C->sink_slot, sink_slot));
   STA_TRY(C->upload(&C->node_src, node_src));
   STA_TRY(C->upload(&C->ep_pin, ep_pin));
+  STA_TRY(C->upload(&C->slot_drv_pin, drv_pin));
+  STA_TRY(C->upload(&C->slot_sink_pin, sink_pin_of_slot));
   STA_TRY(C->upload(&C->rc_chunks, rc_chunks));
   STA_TRY(C->upload(&C->big, big));
   STA_TRY(C->upload(&C->big_end, big_end));
@@ -1617,5 +1623,120 @@ extern "C" sta_status sta_autotune(sta_ctx *C, int32_t reps, sta_tune_result *be
   C->coop = r.sweep_blocks <= C->coop_max;
   r.ms = best_ms;
   if (best) *best = r;
+  return STA_OK;
+}
+
+extern "C" sta_status sta_report_paths(sta_ctx *C, const sta_path_query *q, int32_t *n_paths, int32_t *path_ptr,
+                                       int32_t *path_pin, int8_t *path_rf, float *path_slack, int32_t *path_endpoint,
+                                       sta_mem dst, void *stream) {
+  if (!C) return fail(STA_E_STATE, "NULL context");
+  if (!q || !n_paths) return fail(STA_E_ARG, "NULL query or n_paths");
+  if (q->k < 1 || q->per_endpoint < 1 || q->per_endpoint > 64 || (q->el != 0 && q->el != 1) ||
+      std::isnan(q->slack_below))
+    return fail(STA_E_ARG, "bad path query (k %d, per_endpoint %d, el %d)", q->k, q->per_endpoint, q->el);
+  if (dst != STA_HOST && dst != STA_DEVICE) return fail(STA_E_ARG, "bad dst");
+  if (C->opt.mode != 0) return fail(STA_E_STATE, "path reports need a hard-mode context");
+  if (!C->opt.sort_endpoints) return fail(STA_E_STATE, "path reports need endpoint sorting");
+  if (!C->updated) return fail(STA_E_STATE, "sta_report_paths before sta_update_timing");
+  HIP_TRY(hipSetDevice(C->device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  *n_paths = 0;
+  const int ne = C->n_ep, el = q->el, m = q->per_endpoint;
+  // endpoints that can hold a reported path: the first k in ascending endpoint
+  // slack (each holds a path of its own slack), and only those below the
+  // threshold (no path of an endpoint is better than its slack)
+  const int cand = std::min(q->k, ne);
+  std::vector<int32_t> ord(cand);
+  std::vector<float2> eps(ne);
+  if (cand > 0) {
+    HIP_TRY(hipMemcpyAsync(ord.data(), C->order + (size_t)el * ne, cand * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(eps.data(), C->D.ep_slack, ne * sizeof(float2), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  int n_sel = 0;
+  while (n_sel < cand) {
+    const float sl = el ? eps[ord[n_sel]].y : eps[ord[n_sel]].x;
+    if (!(sl < q->slack_below)) break;
+    ++n_sel;
+  }
+  if (n_sel == 0) {
+    const int32_t zero = 0;
+    if (path_ptr && dst == STA_HOST) path_ptr[0] = 0;
+    if (path_ptr && dst == STA_DEVICE) {
+      HIP_TRY(hipMemcpyAsync(path_ptr, &zero, sizeof zero, hipMemcpyHostToDevice, s));
+      HIP_TRY(hipStreamSynchronize(s));
+    }
+    return STA_OK;
+  }
+  const int lmax = C->n_levels;
+  // heap bound: every pop pushes at most 2 max_in - 1 items per cell output on
+  // its path, and a path has at most lmax / 2 + 1 cell outputs
+  const int cap = m * ((lmax / 2 + 1) * (2 * C->max_in - 1) + 2);
+  const double bytes = (double)n_sel * ((double)cap * 16 + (double)m * lmax * 4 + m * 8.0);
+  if (bytes > 16e9) return fail(STA_E_UNSUPPORTED, "path search needs %.1f GB of scratch", bytes / 1e9);
+  sta_ctx tmp;
+  PathArgs A{};
+  A.eps = C->order + (size_t)el * ne;
+  A.n_eps = n_sel;
+  A.el = el;
+  A.m = m;
+  A.lmax = lmax;
+  A.cap = cap;
+  A.thr = q->slack_below;
+  A.drv_pin = C->slot_drv_pin;
+  A.sink_pin = C->slot_sink_pin;
+  STA_TRY(tmp.alloc(&A.items, (size_t)n_sel * cap));
+  STA_TRY(tmp.alloc(&A.nodes, (size_t)n_sel * m * lmax));
+  STA_TRY(tmp.alloc(&A.plen, (size_t)n_sel * m));
+  STA_TRY(tmp.alloc(&A.pkey, (size_t)n_sel * m));
+  HIP_TRY(launch_paths_enum(C->D, A, s));
+  // global selection: ascending slack over every found path (ties in
+  // endpoint order, then path order)
+  const int nc = n_sel * m;
+  uint32_t *keys, *keys_out;
+  int32_t *vals, *vals_out;
+  STA_TRY(tmp.alloc(&keys, nc));
+  STA_TRY(tmp.alloc(&keys_out, nc));
+  STA_TRY(tmp.alloc(&vals, nc));
+  STA_TRY(tmp.alloc(&vals_out, nc));
+  HIP_TRY(launch_paths_keys(A, keys, vals, s));
+  size_t sb = sort_temp_bytes(nc);
+  unsigned char *stemp;
+  STA_TRY(tmp.alloc(&stemp, sb));
+  HIP_TRY(sort_endpoints(stemp, sb, keys, keys_out, vals, vals_out, nc, s));
+  const int top = std::min(q->k, nc);
+  std::vector<uint32_t> hk(top);
+  HIP_TRY(hipMemcpyAsync(hk.data(), keys_out, top * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  int n_out = 0;
+  while (n_out < top && hk[n_out] != 0xffffffffu) ++n_out;
+  int32_t *len, *ptr;
+  STA_TRY(tmp.alloc(&len, n_out + 1));
+  STA_TRY(tmp.alloc(&ptr, n_out + 1));
+  HIP_TRY(hipMemsetAsync(len, 0, (n_out + 1) * sizeof(int32_t), s));
+  HIP_TRY(launch_paths_lengths(A, vals_out, n_out, len, s));
+  size_t xb = 0;
+  HIP_TRY(exclusive_sum(nullptr, xb, len, ptr, n_out + 1, s));
+  unsigned char *xtemp;
+  STA_TRY(tmp.alloc(&xtemp, xb));
+  HIP_TRY(exclusive_sum(xtemp, xb, len, ptr, n_out + 1, s));
+  int32_t total = 0;
+  HIP_TRY(hipMemcpyAsync(&total, ptr + n_out, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  int32_t *pin = nullptr, *pe = nullptr;
+  int8_t *prf = nullptr;
+  float *psl = nullptr;
+  STA_TRY(tmp.alloc(&pin, std::max(total, 1)));
+  STA_TRY(tmp.alloc(&prf, std::max(total, 1)));
+  STA_TRY(tmp.alloc(&psl, std::max(n_out, 1)));
+  STA_TRY(tmp.alloc(&pe, std::max(n_out, 1)));
+  HIP_TRY(launch_paths_emit(C->D, A, vals_out, n_out, ptr, pin, prf, psl, pe, s));
+  STA_TRY(deliver(path_ptr, ptr, (size_t)(n_out + 1) * 4, dst, s));
+  STA_TRY(deliver(path_pin, pin, (size_t)total * 4, dst, s));
+  STA_TRY(deliver(path_rf, prf, (size_t)total, dst, s));
+  STA_TRY(deliver(path_slack, psl, (size_t)n_out * 4, dst, s));
+  STA_TRY(deliver(path_endpoint, pe, (size_t)n_out * 4, dst, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  *n_paths = n_out;
   return STA_OK;
 }

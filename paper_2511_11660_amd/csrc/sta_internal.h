@@ -214,6 +214,26 @@ hipError_t sort_levels(void *temp, size_t temp_bytes, const int32_t *keys_in, in
 size_t level_sort_temp_bytes(int n);
 hipError_t launch_iota(int32_t *a, int n, hipStream_t s);
 
+// top-k path report: per selected endpoint, a best-first search over
+// deviations from the critical fanins (one thread per endpoint)
+struct PathArgs {
+  const int32_t *eps;   // [n_eps] endpoint indices, ascending endpoint slack
+  int n_eps, el, m, lmax, cap;
+  float thr;
+  int4 *items;          // [n_eps * cap] heap items (key bits, sequence, parent << 24 | position, node)
+  int32_t *nodes;       // [n_eps * m * lmax] path nodes, endpoint first
+  int32_t *plen;        // [n_eps * m] path lengths (0: none)
+  float *pkey;          // [n_eps * m] path slacks
+  const int32_t *drv_pin, *sink_pin;  // slot -> caller pin
+};
+hipError_t launch_paths_enum(const DevDesign &D, const PathArgs &A, hipStream_t s);
+hipError_t launch_paths_keys(const PathArgs &A, uint32_t *keys, int32_t *vals, hipStream_t s);
+hipError_t launch_paths_emit(const DevDesign &D, const PathArgs &A, const int32_t *sel, int n_sel,
+                             const int32_t *ptr, int32_t *pin, int8_t *rf, float *slack, int32_t *ep,
+                             hipStream_t s);
+hipError_t launch_paths_lengths(const PathArgs &A, const int32_t *sel, int n_sel, int32_t *len, hipStream_t s);
+hipError_t exclusive_sum(void *temp, size_t &temp_bytes, const int32_t *in, int32_t *out, int n, hipStream_t s);
+
 // reports and inputs
 hipError_t launch_report_pins(const DevDesign &D, const int32_t *pin_loc, int n_pins, float4 *at,
                               float4 *slew, float4 *rat, uint32_t *crit, float4 *slack,

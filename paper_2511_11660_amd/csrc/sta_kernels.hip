@@ -387,14 +387,17 @@ __device__ void fwd_piece(const DevDesign &D, int j) {
 }
 
 // One launch per phase (chunks of one level, or the pieces of one level).
+// (The chunk's sweep-independent loads are requested before the library is
+// staged, so the two overlap.)
 __global__ __launch_bounds__(kSweepBlock) void k_forward(DevDesign D, int c0, int c1) {
   extern __shared__ __align__(32) unsigned char smem[];
+  const int c = c0 + blockIdx.x * (kSweepBlock / kWave) + threadIdx.x / kWave;
+  const FwdPre p = fwd_prefetch(D, c < c1 ? c : c0);
   const LdsLib lib = load_lib(D, smem);
   PinState *wst = reinterpret_cast<PinState *>(smem + lib_lds_bytes(D.n_types, D.tstride)) +
                   (threadIdx.x / kWave) * kWave;
   __syncthreads();
-  const int c = c0 + blockIdx.x * (kSweepBlock / kWave) + threadIdx.x / kWave;
-  if (c < c1) fwd_chunk<false>(D, lib, wst, c);
+  if (c < c1) fwd_finish<false>(D, lib, wst, p);
 }
 
 __global__ __launch_bounds__(kSweepBlock) void k_forward_pieces(DevDesign D, int j0, int j1) {
@@ -450,9 +453,9 @@ __device__ __forceinline__ float4 sink_rat(const DevDesign &D, const LdsLib &lib
 // arrival); bwd_finish does the consumer gathers and the arithmetic.
 struct BwdPre {
   int x0, x1, s0, s1;
-  PinState ssA;
-  int consA, drvA, e;
-  float dA;
+  PinState ssA, ssB;  // the first two sink rounds
+  int consA, drvA, consB, drvB, e;
+  float dA, dB;
   float4 A;
   int2 pcs;  // sink pieces of a high-fanout driver (first, count)
 };
@@ -466,11 +469,15 @@ __device__ __forceinline__ BwdPre bwd_prefetch(const DevDesign &D, int c) {
   p.s0 = __builtin_amdgcn_readfirstlane(cr.z);
   p.s1 = __builtin_amdgcn_readfirstlane(cr.w);
   const int smax = max(p.s1 - 1, 0);
-  const int sAc = min(p.s0 + lane, smax);
+  const int sAc = min(p.s0 + lane, smax), sBc = min(p.s0 + lane + kWave, smax);
   p.ssA = D.sink_state[sAc];
   p.consA = D.sink_cons[sAc];
   p.dA = D.dq[sAc].x;
   p.drvA = D.sink_drv[sAc];
+  p.ssB = D.sink_state[sBc];
+  p.consB = D.sink_cons[sBc];
+  p.dB = D.dq[sBc].x;
+  p.drvB = D.sink_drv[sBc];
   const int x = p.x0 + lane;
   const int xc = x < p.x1 ? x : p.x0;
   p.e = D.drv_ep[xc];
@@ -504,7 +511,8 @@ __device__ void bwd_finish(const DevDesign &D, const LdsLib &lib, int *wacc, con
     atomicMin(acc + 3, f2key(R.w - d));
   };
   if (sA < s1) sink(sA, p.ssA, p.consA, p.dA, p.drvA);
-  for (int s = sA + kWave; s < s1; s += kWave) sink(s, D.sink_state[s], D.sink_cons[s], D.dq[s].x, D.sink_drv[s]);
+  if (sA + kWave < s1) sink(sA + kWave, p.ssB, p.consB, p.dB, p.drvB);
+  for (int s = sA + 2 * kWave; s < s1; s += kWave) sink(s, D.sink_state[s], D.sink_cons[s], D.dq[s].x, D.sink_drv[s]);
   wave_sync();
   if (live) {
     float4 R = make_float4(key2f(wacc[lane * 4 + 0]), key2f(wacc[lane * 4 + 1]),
@@ -559,12 +567,13 @@ __device__ void bwd_piece(const DevDesign &D, const LdsLib &lib, int j) {
 
 __global__ __launch_bounds__(kSweepBlock) void k_backward(DevDesign D, int c0, int c1) {
   extern __shared__ __align__(32) unsigned char smem[];
+  const int c = c0 + blockIdx.x * (kSweepBlock / kWave) + threadIdx.x / kWave;
+  const BwdPre p = bwd_prefetch(D, c < c1 ? c : c0);
   const LdsLib lib = load_lib(D, smem);
   int *wacc = reinterpret_cast<int *>(smem + lib_lds_bytes(D.n_types, D.tstride)) +
               (threadIdx.x / kWave) * kWave * 4;
   __syncthreads();
-  const int c = c0 + blockIdx.x * (kSweepBlock / kWave) + threadIdx.x / kWave;
-  if (c < c1) bwd_chunk<false>(D, lib, wacc, c);
+  if (c < c1) bwd_finish<false>(D, lib, wacc, p);
 }
 
 __global__ __launch_bounds__(kSweepBlock) void k_backward_pieces(DevDesign D, int j0, int j1) {
@@ -1603,6 +1612,177 @@ inline int blocks_for(int64_t n, int b) { return (int)((n + b - 1) / b); }
 
 }  // namespace
 
+// ------------------------------------------------------------ path report
+//
+// A node is (slot code, transition): code = 2 * slot + rf, driver slots first
+// (0..n_drv-1), then sink slots (n_drv + sink).  Backward from a node: a sink's
+// only predecessor is its net's driver (deviation 0); a cell output's
+// predecessors are the (input, input transition) candidates of its merge, the
+// critical one (drv_crit) with deviation 0 and every other with deviation
+// AT_out - (AT_in + delay) (late) or (AT_in + delay) - AT_out (early), the delay
+// recomputed exactly as the forward merge computes it; a primary input has
+// none.  A path = critical completion with a sequence of sidetracks: popping
+// the heap item of smallest key yields one complete path (its critical
+// completion, slack = key), and pushes one item per sidetrack available along
+// that completion (key + deviation).  Every path comes out exactly once, in
+// ascending slack.
+
+__device__ __forceinline__ bool item_less(int4 a, int4 b) {
+  const float ka = __int_as_float(a.x), kb = __int_as_float(b.x);
+  return ka < kb || (ka == kb && a.y < b.y);
+}
+
+__device__ void heap_push(int4 *h, int &n, int4 it) {
+  int i = n++;
+  while (i > 0) {
+    const int p = (i - 1) >> 1;
+    if (!item_less(it, h[p])) break;
+    h[i] = h[p];
+    i = p;
+  }
+  h[i] = it;
+}
+
+__device__ int4 heap_pop(int4 *h, int &n) {
+  const int4 top = h[0];
+  const int4 last = h[--n];
+  int i = 0;
+  for (;;) {
+    int c = 2 * i + 1;
+    if (c >= n) break;
+    if (c + 1 < n && item_less(h[c + 1], h[c])) ++c;
+    if (!item_less(h[c], last)) break;
+    h[i] = h[c];
+    i = c;
+  }
+  if (n > 0) h[i] = last;
+  return top;
+}
+
+__device__ __forceinline__ float node_at(const DevDesign &D, int code, int el) {
+  const int slot = code >> 1, v = el * 2 + (code & 1);
+  const float4 a = slot < D.n_drv ? D.drv_state[slot].at : D.sink_state[slot - D.n_drv].at;
+  return v == 0 ? a.x : v == 1 ? a.y : v == 2 ? a.z : a.w;
+}
+
+__device__ __forceinline__ float node_slew(const DevDesign &D, int code, int el) {
+  const int slot = code >> 1, v = el * 2 + (code & 1);
+  const float4 a = slot < D.n_drv ? D.drv_state[slot].slew : D.sink_state[slot - D.n_drv].slew;
+  return v == 0 ? a.x : v == 1 ? a.y : v == 2 ? a.z : a.w;
+}
+
+__global__ __launch_bounds__(256) void k_paths_enum(DevDesign D, PathArgs A) {
+  extern __shared__ __align__(32) unsigned char smem[];
+  const LdsLib lib = load_lib(D, smem);
+  __syncthreads();
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= A.n_eps) return;
+  const int el = A.el, m = A.m, lmax = A.lmax;
+  int4 *h = A.items + (size_t)t * A.cap;
+  int32_t *nodes = A.nodes + (size_t)t * m * lmax;
+  int32_t *plen = A.plen + (size_t)t * m;
+  float *pkey = A.pkey + (size_t)t * m;
+  for (int j = 0; j < m; ++j) plen[j] = 0;
+  const int e = A.eps[t];
+  const int loc = D.ep_loc[e];
+  const int slot = loc >= 0 ? loc : D.n_drv + (-1 - loc);
+  const float4 R = D.ep_rat[e];
+  int n = 0, seq = 0;
+  for (int rf = 0; rf < 2; ++rf) {
+    const int v = el * 2 + rf;
+    const float rat = v == 0 ? R.x : v == 1 ? R.y : v == 2 ? R.z : R.w;
+    if (!(fabsf(rat) < kInf)) continue;
+    const int code = slot * 2 + rf;
+    const float a = node_at(D, code, el);
+    const float key = el ? rat - a : a - rat;
+    heap_push(h, n, make_int4(__float_as_int(key), seq++, -1, code));
+  }
+  const TabLayout lay{D.nx, D.ny};
+  for (int j = 0; j < m && n > 0; ++j) {
+    const int4 it = heap_pop(h, n);
+    const float key = __int_as_float(it.x);
+    if (!(key < A.thr)) break;
+    int32_t *path = nodes + (size_t)j * lmax;
+    int len = 0;
+    if (it.z >= 0) {  // prefix of the parent path up to the sidetrack
+      const int parent = it.z >> 24, pos = it.z & 0xffffff;
+      const int32_t *pp = nodes + (size_t)parent * lmax;
+      for (; len < pos; ++len) path[len] = pp[len];
+    }
+    int code = it.w;
+    for (;;) {
+      path[len++] = code;
+      const int sl = code >> 1, rf = code & 1;
+      if (sl >= D.n_drv) {  // sink: its driver, same transition
+        code = D.sink_drv[sl - D.n_drv] * 2 + rf;
+        continue;
+      }
+      if (sl < D.n_pi) break;  // startpoint
+      const int v = el * 2 + rf;
+      const int crit = (int)((D.drv_crit[sl] >> (8 * v)) & 0xffu);
+      const float at_out = node_at(D, code, el);
+      const CellCtx cc = cell_ctx(D, lib, D.cell_type[sl], D.L_net[sl]);
+      const int f0 = D.fanin_ptr[sl], nf = D.fanin_ptr[sl + 1] - f0;
+      int next = -1;
+      for (int k = 0; k < nf; ++k) {
+        const int in_slot = D.n_drv + D.fanin_sink[f0 + k];
+        for (int ri = 0; ri < 2; ++ri) {
+          if (!arc_maps(cc.sense, ri, rf)) continue;
+          const int in_code = in_slot * 2 + ri;
+          if (k * 2 + ri == crit) {
+            next = in_code;
+            continue;
+          }
+          const float x = node_slew(D, in_code, el);
+          const AxisPos px = axis_find(cc.tb + lay.xa(), cc.tb + lay.rdx(), D.nx, x);
+          const float dl = bilerp(cc.tb + lay.tab(rf), D.ny, px, cc.py);
+          const float cand = node_at(D, in_code, el) + dl;
+          const float dev = fmaxf(el ? at_out - cand : cand - at_out, 0.0f);
+          const float k2 = key + dev;
+          if (k2 < A.thr && n < A.cap) heap_push(h, n, make_int4(__float_as_int(k2), seq++, (j << 24) | len, in_code));
+        }
+      }
+      if (next < 0) break;  // (every cell output has a critical candidate)
+      code = next;
+    }
+    plen[j] = len;
+    pkey[j] = key;
+  }
+}
+
+// Sort keys of every found path (unfilled slots sort last).
+__global__ void k_paths_keys(PathArgs A, uint32_t *keys, int32_t *vals) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.n_eps * A.m) return;
+  keys[i] = A.plen[i] > 0 ? f2ukey(A.pkey[i]) : 0xffffffffu;
+  vals[i] = i;
+}
+
+__global__ void k_paths_lengths(PathArgs A, const int32_t *sel, int n_sel, int32_t *len) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_sel) len[i] = A.plen[sel[i]];
+}
+
+// One thread per reported path: pins from startpoint to endpoint.
+__global__ void k_paths_emit(DevDesign D, PathArgs A, const int32_t *sel, int n_sel, const int32_t *ptr,
+                             int32_t *pin, int8_t *rf, float *slack, int32_t *ep) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_sel) return;
+  const int c = sel[i];
+  const int t = c / A.m;
+  const int len = A.plen[c];
+  const int32_t *path = A.nodes + (size_t)c * A.lmax;
+  if (slack) slack[i] = A.pkey[c];
+  if (ep) ep[i] = A.eps[t];
+  const int o = ptr[i];
+  for (int q = 0; q < len; ++q) {
+    const int code = path[len - 1 - q];
+    const int sl = code >> 1;
+    if (pin) pin[o + q] = sl < D.n_drv ? A.drv_pin[sl] : A.sink_pin[sl - D.n_drv];
+    if (rf) rf[o + q] = (int8_t)(code & 1);
+  }
+}
+
 // ------------------------------------------------------------ wrappers
 
 size_t sweep_lds_bytes(const DevDesign &D) {
@@ -1844,6 +2024,40 @@ hipError_t launch_permute_caps(const float *src, const int32_t *node_src, float 
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_permute_caps, dim3(blocks_for(n, 256)), dim3(256), 0, s, src, node_src, dst, n);
   return hipGetLastError();
+}
+
+
+hipError_t launch_paths_enum(const DevDesign &D, const PathArgs &A, hipStream_t s) {
+  if (A.n_eps <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_paths_enum, dim3(blocks_for(A.n_eps, 256)), dim3(256), lib_lds_bytes(D.n_types, D.tstride),
+                     s, D, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_paths_keys(const PathArgs &A, uint32_t *keys, int32_t *vals, hipStream_t s) {
+  const int n = A.n_eps * A.m;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_paths_keys, dim3(blocks_for(n, 256)), dim3(256), 0, s, A, keys, vals);
+  return hipGetLastError();
+}
+
+hipError_t launch_paths_lengths(const PathArgs &A, const int32_t *sel, int n_sel, int32_t *len, hipStream_t s) {
+  if (n_sel <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_paths_lengths, dim3(blocks_for(n_sel, 256)), dim3(256), 0, s, A, sel, n_sel, len);
+  return hipGetLastError();
+}
+
+hipError_t launch_paths_emit(const DevDesign &D, const PathArgs &A, const int32_t *sel, int n_sel,
+                             const int32_t *ptr, int32_t *pin, int8_t *rf, float *slack, int32_t *ep,
+                             hipStream_t s) {
+  if (n_sel <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_paths_emit, dim3(blocks_for(n_sel, 256)), dim3(256), 0, s, D, A, sel, n_sel, ptr, pin, rf,
+                     slack, ep);
+  return hipGetLastError();
+}
+
+hipError_t exclusive_sum(void *temp, size_t &temp_bytes, const int32_t *in, int32_t *out, int n, hipStream_t s) {
+  return hipcub::DeviceScan::ExclusiveSum(temp, temp_bytes, in, out, n, s);
 }
 
 }  // namespace sta

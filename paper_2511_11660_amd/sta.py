@@ -76,6 +76,11 @@ class sta_tune_result(ctypes.Structure):
                 ("n_tried", ctypes.c_int32)]
 
 
+class sta_path_query(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("per_endpoint", ctypes.c_int32), ("slack_below", ctypes.c_float),
+                ("el", ctypes.c_int32)]
+
+
 # (name, restype, argtypes) of every exported function
 _SIGS = [
     ("sta_options_default", None, [ctypes.POINTER(sta_options)]),
@@ -100,6 +105,8 @@ _SIGS = [
     ("sta_batch_offsets", ctypes.c_int, [_VP, _P32, _P32, _P32, _P64]),
     ("sta_batch_report", ctypes.c_int, [_VP, _PD, _PD, _VP]),
     ("sta_autotune", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.POINTER(sta_tune_result), _VP]),
+    ("sta_report_paths", ctypes.c_int, [_VP, ctypes.POINTER(sta_path_query), _P32, _VP, _VP, _VP, _VP, _VP,
+                                        ctypes.c_int, _VP]),
     ("sta_status_string", ctypes.c_char_p, [ctypes.c_int]),
     ("sta_last_error", ctypes.c_char_p, []),
 ]
@@ -299,6 +306,29 @@ def sta_autotune(ctx: int, reps: int = 5, stream=None) -> sta_tune_result:
     return r
 
 
+def sta_report_paths(ctx: int, k: int, per_endpoint: int = 1, slack_below: float = float("inf"), el: int = 1,
+                     max_len: int = 0, stream=None):
+    """Top-k path report into host arrays; returns a list of dicts (slack,
+    endpoint index, pins and transitions from startpoint to endpoint)."""
+    q = sta_path_query(int(k), int(per_endpoint), float(slack_below), int(el))
+    if max_len <= 0:
+        max_len = sta_get_info(ctx).n_levels
+    n = ctypes.c_int32(0)
+    ptr = np.zeros(k + 1, np.int32)
+    pins = np.zeros(k * max_len, np.int32)
+    rf = np.zeros(k * max_len, np.int8)
+    slack = np.zeros(k, np.float32)
+    ep = np.zeros(k, np.int32)
+    _check(load().sta_report_paths(ctx, ctypes.byref(q), ctypes.byref(n), _addr(ptr), _addr(pins), _addr(rf),
+                                   _addr(slack), _addr(ep), STA_HOST, _stream(stream)))
+    out = []
+    for i in range(n.value):
+        a, b = ptr[i], ptr[i + 1]
+        out.append({"slack": float(slack[i]), "endpoint": int(ep[i]), "pins": pins[a:b].tolist(),
+                    "rf": rf[a:b].tolist()})
+    return out
+
+
 PHASES = ("rc_small", "rc_big", "forward", "backward", "reduce", "sort", "adjoint_sweep", "adjoint_rc")
 
 
@@ -404,6 +434,9 @@ class STA:
         e = np.zeros(max(1, self.info.n_endpoints), np.int32)
         sta_report_endpoints(self.ctx, e)
         return e[: self.info.n_endpoints]
+
+    def paths(self, k, per_endpoint=1, slack_below=float("inf"), el=1):
+        return sta_report_paths(self.ctx, k, per_endpoint, slack_below, el, self.info.n_levels)
 
     def batch_offsets(self):
         return sta_batch_offsets(self.ctx)
