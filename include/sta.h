@@ -175,6 +175,30 @@ sta_status sta_set_wire_caps(sta_ctx *ctx, const float *cap_ff, sta_mem mem, voi
  * the next synchronizing call. */
 sta_status sta_update_timing(sta_ctx *ctx, void *stream);
 
+/* Incremental timing update (§I: incremental GPU graph propagation is among
+ * the prior art the paper builds on, and its TAU 2015 designs come from an
+ * incremental-timing contest; §IV flows call the timer after small changes).
+ * Precondition: sta_update_timing has run on this context, and since the
+ * last update (full or incremental) the wire caps changed only on the nets
+ * listed.  Recomputes the RC pass of those nets, arrivals in their fan-out
+ * cone and RATs in the fan-in cone of what changed, stopping wherever a
+ * recomputed value is bitwise unchanged, then WNS/TNS and the endpoint order
+ * as a full update does.  Every output is then bitwise equal to what
+ * sta_update_timing would give.  A net whose caps changed but is not listed
+ * leaves stale results (not detected).
+ *
+ *   nets [n_nets]   caller net ids (duplicates allowed), in `mem` memory; a
+ *                   device list is copied to the host first (synchronizes
+ *                   `stream`); n_nets = 0 recomputes nothing but the reports
+ *
+ * Errors: STA_E_STATE (NULL context, or no full update yet), STA_E_ARG (bad
+ * list or id), STA_E_UNSUPPORTED (batched context).  Without cooperative
+ * launch support the call runs a full update.  Allocates device queues and
+ * pinned staging (about 4 bytes per driver, chunk and RC chunk) on first use;
+ * asynchronous on `stream` otherwise. */
+sta_status sta_update_timing_incremental(sta_ctx *ctx, const int32_t *nets, int32_t n_nets, sta_mem mem,
+                                         void *stream);
+
 /* Slack report (§III "Report options": pin slacks, WNS/TNS).  Any pointer may
  * be NULL to skip it.  pin_slack [n_pins][4] (late RAT-AT, early AT-RAT, +inf
  * when unconstrained); ep_slack [n_endpoints][2] (min over rise/fall, per

@@ -142,6 +142,24 @@ struct sta_ctx {
   double *b_partials = nullptr, *b_out = nullptr;
   uint64_t *keys64 = nullptr, *keys64_out = nullptr;
   int key_bits = 32;
+  // incremental update: host maps from the layout; device queues made on first use
+  std::vector<int32_t> h_net_slot;     // net -> driver slot
+  std::vector<int32_t> h_rc_pos;       // slot -> RC position of a small net, or -1 - wide-net index
+  std::vector<int32_t> h_rc_chunk;     // RC position -> RC chunk
+  std::vector<int2> h_rc_chunks;
+  std::vector<BigNet> h_big;
+  int32_t *inc_chunk_of = nullptr;     // [n_drv]
+  int2 *inc_chunk_ph = nullptr;        // [n_chunks]
+  bool inc_ready = false;
+  IncArgs inc{};
+  uint32_t *inc_buf = nullptr;         // flags, queue lengths, recomputed-net bytes (cleared per update)
+  int inc_words = 0, inc_grid = 0;
+  int32_t *inc_slots = nullptr;        // [n_drv] seeded driver slots
+  int2 *inc_rc = nullptr, *inc_blk = nullptr;  // RC chunks and wide-net blocks to recompute
+  int32_t *inc_host = nullptr;         // pinned staging of the three lists
+  hipEvent_t inc_ev = nullptr;         // staging reusable once this has passed
+  std::vector<int32_t> inc_ids, inc_rs;
+  std::vector<uint8_t> inc_seen_slot, inc_seen_rc;
 
   template <class T>
   sta_status alloc(T **out_p, size_t n) {
@@ -168,6 +186,8 @@ struct sta_ctx {
     if (side) (void)hipStreamDestroy(side);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
+    if (inc_ev) (void)hipEventDestroy(inc_ev);
+    if (inc_host) (void)hipHostFree(inc_host);
   }
 };
 
@@ -610,6 +630,12 @@ static sta_status build_layout(sta_ctx *C, const Inputs &I, const std::vector<in
       bn.scr = big_scr;
       bn.nsp = (int64_t)big_nsp.size();
       bn.egp = (int64_t)big_egp.size();
+      bn.nblk = (m + kWideSeg - 1) / kWideSeg;
+      // the blocks of one net wait for each other, so all of them must fit on
+      // the device at once (2 blocks of 1024 threads per compute unit)
+      if (bn.nblk > 2 * std::max(C->n_cu, 1))
+        return fail(STA_E_UNSUPPORTED, "RC net of %d nodes exceeds the wide-net limit", m);
+      bn.tot = big.empty() ? 0 : big.back().tot + big.back().nblk;
       big.push_back(bn);
       big_scr += kBigScratch * ((int64_t)m + 1);
     }
@@ -906,6 +932,46 @@ static sta_status build_layout(sta_ctx *C, const Inputs &I, const std::vector<in
   STA_TRY(C->upload(&C->slot_sink_pin, sink_pin_of_slot));
   STA_TRY(C->upload(&C->rc_chunks, rc_chunks));
   STA_TRY(C->upload(&C->big, big));
+  {
+    // incremental update: chunk and phases of every driver / chunk, and the
+    // host maps from a net to what recomputes it
+    std::vector<int32_t> chunk_of(ND, 0);
+    for (size_t c = 0; c < chunk_rec.size(); ++c)
+      for (int x = chunk_rec[c].x; x < chunk_rec[c].y; ++x) chunk_of[x] = (int32_t)c;
+    std::vector<int32_t> fph(L + 1, 0), bph(L + 1, 0);
+    for (size_t k = 0; k < C->ph_fwd.size(); ++k)
+      if (C->ph_fwd[k].x == kItemChunk) fph[C->ph_fwd[k].w] = (int32_t)k;
+    for (size_t k = 0; k < C->ph_bwd.size(); ++k)
+      if (C->ph_bwd[k].x == kItemChunk) bph[C->ph_bwd[k].w] = (int32_t)k;
+    std::vector<int2> chunk_ph(chunk_rec.size());
+    for (int l = 0; l <= L; ++l)
+      for (int c = lvl_cbeg[l]; c < lvl_cbeg[l + 1]; ++c) chunk_ph[c] = make_int2(fph[l], bph[l]);
+    STA_TRY(C->upload(&C->inc_chunk_of, chunk_of));
+    STA_TRY(C->upload(&C->inc_chunk_ph, chunk_ph));
+    C->h_net_slot = net_slot;
+    C->h_rc_pos.assign(ND, 0);
+    for (size_t j = 0; j < rc_order.size(); ++j) C->h_rc_pos[rc_order[j]] = (int32_t)j;
+    for (size_t i = 0; i < big.size(); ++i) C->h_rc_pos[big[i].x] = -1 - (int32_t)i;
+    C->h_rc_chunk.assign(rc_order.size(), 0);
+    for (size_t r = 0; r < rc_chunks.size(); ++r)
+      for (int j = rc_chunks[r].x; j < rc_chunks[r].y; ++j) C->h_rc_chunk[j] = (int32_t)r;
+    C->h_rc_chunks = rc_chunks;
+    C->h_big = big;
+  }
+  {
+    // one launched block per (wide net, segment); per-net barrier counters
+    std::vector<int2> blk;
+    for (size_t i = 0; i < big.size(); ++i)
+      for (int b = 0; b < big[i].nblk; ++b) blk.push_back(make_int2((int)i, b));
+    const int n_tot = big.empty() ? 1 : big.back().tot + big.back().nblk;
+    int2 *pb;
+    STA_TRY(C->upload(&pb, blk));
+    C->wide.blk = pb;
+    C->wide.n_blk = (int)blk.size();
+    STA_TRY(C->alloc(&C->wide.tot, n_tot));
+    STA_TRY(C->alloc(&C->wide.sync, std::max<size_t>(2 * big.size(), 1)));
+    HIP_TRY(hipMemset(C->wide.sync, 0, std::max<size_t>(2 * big.size(), 1) * sizeof(uint32_t)));
+  }
   STA_TRY(C->upload(&C->big_end, big_end));
   STA_TRY(C->upload(&C->big_pc, big_pc));
   STA_TRY(C->upload(&C->big_nsp, big_nsp));
@@ -1270,13 +1336,42 @@ static sta_status enqueue_rc(sta_ctx *C, hipStream_t s, bool adjoint) {
   return STA_OK;
 }
 
+// WNS / TNS (and the endpoint sort keys) from the endpoint slacks.
+static sta_status enqueue_reduce(sta_ctx *C, hipStream_t s) {
+  const DevDesign &D = C->D;
+  const bool sort = C->opt.sort_endpoints && C->n_ep > 0;
+  if (C->opt.mode == 1)
+    HIP_TRY(launch_reduce_smooth(D, C->partials, C->out, sort ? C->keys : nullptr, sort ? C->vals : nullptr, s));
+  else if (C->batched)
+    HIP_TRY(launch_reduce_batch(D, C->d_ep_off, C->n_designs, C->b_partials, C->b_out,
+                                sort ? C->keys64 : nullptr, sort ? C->vals : nullptr, s));
+  else
+    HIP_TRY(launch_reduce(D, C->partials, C->out, sort ? C->keys : nullptr, sort ? C->vals : nullptr, s));
+  return STA_OK;
+}
+
+// Endpoint order per early/late from the keys the reduction wrote.
+static sta_status enqueue_sort(sta_ctx *C, hipStream_t s) {
+  if (!C->opt.sort_endpoints || C->n_ep <= 0) return STA_OK;
+  for (int el = 0; el < 2; ++el) {
+    if (C->batched)
+      HIP_TRY(sort_endpoints64(C->sort_temp, C->sort_bytes, C->keys64 + (size_t)el * C->n_ep,
+                               C->keys64_out + (size_t)el * C->n_ep, C->vals, C->order + (size_t)el * C->n_ep,
+                               C->n_ep, C->key_bits, s));
+    else
+      HIP_TRY(sort_endpoints(C->sort_temp, C->sort_bytes, C->keys + (size_t)el * C->n_ep,
+                             C->keys_out + (size_t)el * C->n_ep, C->vals, C->order + (size_t)el * C->n_ep,
+                             C->n_ep, s));
+  }
+  return STA_OK;
+}
+
 // Enqueues RC, both sweeps and the reduction on s (the body of one update,
 // without the endpoint sort).  With prof, events separate the phases.
 static sta_status enqueue_update(sta_ctx *C, hipStream_t s, bool prof) {
   const DevDesign &D = C->D;
   const bool smooth = C->opt.mode == 1;
   const bool per_level = C->opt.sched != STA_SCHED_PERSISTENT;
-  const bool sort = C->opt.sort_endpoints && C->n_ep > 0;
   if (prof) HIP_TRY(hipEventRecord(C->ev[0], s));
   STA_TRY(enqueue_rc(C, s, false));
   if (prof) HIP_TRY(hipEventRecord(C->ev[1], s));
@@ -1295,13 +1390,7 @@ static sta_status enqueue_update(sta_ctx *C, hipStream_t s, bool prof) {
     }
   }
   if (prof) HIP_TRY(hipEventRecord(C->ev[4], s));
-  if (smooth)
-    HIP_TRY(launch_reduce_smooth(D, C->partials, C->out, sort ? C->keys : nullptr, sort ? C->vals : nullptr, s));
-  else if (C->batched)
-    HIP_TRY(launch_reduce_batch(D, C->d_ep_off, C->n_designs, C->b_partials, C->b_out,
-                                sort ? C->keys64 : nullptr, sort ? C->vals : nullptr, s));
-  else
-    HIP_TRY(launch_reduce(D, C->partials, C->out, sort ? C->keys : nullptr, sort ? C->vals : nullptr, s));
+  STA_TRY(enqueue_reduce(C, s));
   if (prof) HIP_TRY(hipEventRecord(C->ev[5], s));
   return STA_OK;
 }
@@ -1331,7 +1420,6 @@ extern "C" sta_status sta_update_timing(sta_ctx *C, void *stream) {
   HIP_TRY(hipSetDevice(C->device));
   hipStream_t s = static_cast<hipStream_t>(stream);
   const bool prof = C->opt.profile != 0;
-  const bool sort = C->opt.sort_endpoints && C->n_ep > 0;
   if (C->opt.sched == STA_SCHED_GRAPH) {
     STA_TRY(ensure_graph(C));
     if (prof) {
@@ -1342,22 +1430,123 @@ extern "C" sta_status sta_update_timing(sta_ctx *C, void *stream) {
   } else {
     STA_TRY(enqueue_update(C, s, prof));
   }
-  if (sort) {
-    for (int el = 0; el < 2; ++el) {
-      if (C->batched)
-        HIP_TRY(sort_endpoints64(C->sort_temp, C->sort_bytes, C->keys64 + (size_t)el * C->n_ep,
-                                 C->keys64_out + (size_t)el * C->n_ep, C->vals,
-                                 C->order + (size_t)el * C->n_ep, C->n_ep, C->key_bits, s));
-      else
-        HIP_TRY(sort_endpoints(C->sort_temp, C->sort_bytes, C->keys + (size_t)el * C->n_ep,
-                               C->keys_out + (size_t)el * C->n_ep, C->vals, C->order + (size_t)el * C->n_ep,
-                               C->n_ep, s));
-    }
-  }
+  STA_TRY(enqueue_sort(C, s));
   if (prof) HIP_TRY(hipEventRecord(C->ev[6], s));
   C->timed = prof;
   C->last_stream = s;
   C->updated = true;
+  return STA_OK;
+}
+
+// Device queues and staging of the incremental update, made on first use.
+static sta_status inc_prepare(sta_ctx *C) {
+  if (C->inc_ready) return STA_OK;
+  const int n_ph = (int)(C->ph_fwd.size() + C->ph_bwd.size());
+  const int64_t words = 2 * (int64_t)C->n_chunks + n_ph + ((int64_t)C->n_drv + 3) / 4;
+  if (words >= INT32_MAX) return fail(STA_E_UNSUPPORTED, "design too large for the incremental queues");
+  STA_TRY(C->alloc(&C->inc_buf, (size_t)words));
+  C->inc_words = (int)words;
+  IncArgs &I = C->inc;
+  I.flag = C->inc_buf;
+  I.cnt = I.flag + 2 * (size_t)C->n_chunks;
+  I.rcd = reinterpret_cast<uint8_t *>(I.cnt + n_ph);
+  STA_TRY(C->alloc(&I.wl_c, 2 * (size_t)C->n_chunks));
+  STA_TRY(C->alloc(&I.wl_p, 2 * (size_t)std::max(C->n_pieces, 1)));
+  I.chunk_of = C->inc_chunk_of;
+  I.chunk_ph = C->inc_chunk_ph;
+  I.n_chunks = C->n_chunks;
+  I.n_pieces = C->n_pieces;
+  STA_TRY(C->alloc(&C->inc_slots, (size_t)C->n_drv));
+  STA_TRY(C->alloc(&C->inc_rc, (size_t)std::max(C->n_rc_chunks, 1)));
+  STA_TRY(C->alloc(&C->inc_blk, (size_t)std::max(C->wide.n_blk, 1)));
+  const size_t stage = (size_t)C->n_drv + 2 * (size_t)C->n_rc_chunks + 2 * (size_t)C->wide.n_blk + 1;
+  HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&C->inc_host), stage * sizeof(int32_t), hipHostMallocDefault));
+  HIP_TRY(hipEventCreateWithFlags(&C->inc_ev, hipEventDisableTiming));
+  // one block per compute unit (fewer blocks make the per-phase wait
+  // cheaper; a small cone has little work per phase), within the
+  // cooperative limit; sweep_blocks overrides
+  const int per_cu = inc_blocks_per_cu(sweep_lds_bytes(C->D));
+  const int cap = per_cu * std::max(C->n_cu, 1);
+  C->inc_grid = C->opt.sweep_blocks > 0 ? std::min(C->opt.sweep_blocks, cap) : std::min(std::max(C->n_cu, 1), cap);
+  C->inc_seen_slot.assign(C->n_drv, 0);
+  C->inc_seen_rc.assign(C->n_rc_chunks, 0);
+  C->inc_ready = true;
+  return STA_OK;
+}
+
+extern "C" sta_status sta_update_timing_incremental(sta_ctx *C, const int32_t *nets, int32_t n_nets, sta_mem mem,
+                                                    void *stream) {
+  if (!C) return fail(STA_E_STATE, "NULL context");
+  if (n_nets < 0) return fail(STA_E_ARG, "n_nets < 0");
+  if (n_nets > 0 && !nets) return fail(STA_E_ARG, "nets is NULL");
+  if (mem != STA_HOST && mem != STA_DEVICE) return fail(STA_E_ARG, "bad mem");
+  if (C->batched) return fail(STA_E_UNSUPPORTED, "incremental update of a batched context");
+  if (!C->updated) return fail(STA_E_STATE, "incremental update before a full sta_update_timing");
+  HIP_TRY(hipSetDevice(C->device));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  std::vector<int32_t> &ids = C->inc_ids;
+  ids.resize((size_t)n_nets);
+  if (n_nets > 0) {
+    if (mem == STA_DEVICE) {
+      HIP_TRY(hipMemcpyAsync(ids.data(), nets, (size_t)n_nets * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+    } else {
+      std::memcpy(ids.data(), nets, (size_t)n_nets * sizeof(int32_t));
+    }
+  }
+  for (int32_t i = 0; i < n_nets; ++i)
+    if (ids[i] < 0 || ids[i] >= C->n_nets) return fail(STA_E_ARG, "nets[%d] = %d out of range", i, ids[i]);
+  if (!C->coop) return sta_update_timing(C, stream);  // no resident-grid launch: a full update, same result
+  STA_TRY(inc_prepare(C));
+  HIP_TRY(hipEventSynchronize(C->inc_ev));  // the staging buffer's previous uploads have been read
+  // distinct driver slots; the RC chunks and wide-net blocks that recompute them
+  int32_t *h_slots = C->inc_host;
+  int2 *h_rc = reinterpret_cast<int2 *>(h_slots + C->n_drv);
+  int2 *h_blk = h_rc + C->n_rc_chunks;
+  int ns = 0, nr = 0, nb = 0;
+  std::vector<int32_t> &rs = C->inc_rs;
+  rs.clear();
+  for (int32_t n : ids) {
+    const int x = C->h_net_slot[n];
+    if (C->inc_seen_slot[x]) continue;
+    C->inc_seen_slot[x] = 1;
+    h_slots[ns++] = x;
+    const int j = C->h_rc_pos[x];
+    if (j >= 0) {
+      const int r = C->h_rc_chunk[j];
+      if (!C->inc_seen_rc[r]) {
+        C->inc_seen_rc[r] = 1;
+        rs.push_back(r);
+        h_rc[nr++] = C->h_rc_chunks[r];
+      }
+    } else {
+      const int i = -1 - j;
+      for (int b = 0; b < C->h_big[i].nblk; ++b) h_blk[nb++] = make_int2(i, b);
+    }
+  }
+  for (int i = 0; i < ns; ++i) C->inc_seen_slot[h_slots[i]] = 0;
+  for (int32_t r : rs) C->inc_seen_rc[r] = 0;
+  const DevDesign &D = C->D;
+  HIP_TRY(launch_reset_counters(C->inc_buf, C->inc_words, s));
+  HIP_TRY(launch_reset_counters(D.counters, n_counters(D.n_ph_fwd + D.n_ph_bwd), s));
+  if (ns > 0) HIP_TRY(hipMemcpyAsync(C->inc_slots, h_slots, (size_t)ns * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  if (nr > 0) HIP_TRY(hipMemcpyAsync(C->inc_rc, h_rc, (size_t)nr * sizeof(int2), hipMemcpyHostToDevice, s));
+  if (nb > 0) HIP_TRY(hipMemcpyAsync(C->inc_blk, h_blk, (size_t)nb * sizeof(int2), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipEventRecord(C->inc_ev, s));
+  HIP_TRY(launch_inc_seed(D, C->inc, C->inc_slots, ns, s));
+  if (nr > 0) HIP_TRY(launch_rc(D, C->inc_rc, nr, s));
+  if (nb > 0) {
+    WideNets W = C->wide;
+    W.blk = C->inc_blk;
+    W.n_blk = nb;
+    HIP_TRY(launch_rc_wide(D, W, s));
+  }
+  HIP_TRY(launch_inc_forward(D, C->inc, C->inc_grid, s));
+  if (C->opt.mode != 1) HIP_TRY(launch_inc_backward(D, C->inc, C->inc_grid, s));
+  STA_TRY(enqueue_reduce(C, s));
+  STA_TRY(enqueue_sort(C, s));
+  C->timed = false;
+  C->last_stream = s;
   return STA_OK;
 }
 

@@ -136,8 +136,11 @@ struct BigNet {
   int64_t nsp;        // offset into big_nsp (m + 1 entries: sinks of each node, CSR)
   int64_t egp;        // offset into big_egp (m + 2 entries): nodes whose subtree ends at p,
                       // listed in big_egl (aux-indexed, m entries) deepest first
+  int32_t nblk;       // blocks sharing the net (segments of kWideSeg preorder nodes)
+  int32_t tot;        // offset into the per-block scan totals
 };
 constexpr int kWideBlock = 1024;            // threads per wide-net block
+constexpr int kWideSeg = 8192;              // preorder nodes per wide-net block
 constexpr int kBigScratch = 9;
 
 // Packed-table offsets for one type.
@@ -156,11 +159,30 @@ struct TabLayout {
 struct WideNets {
   const BigNet *big;
   int n_big;
+  const int2 *blk;       // [n_blk] (net, segment) of each launched block
+  int n_blk;
   const int32_t *end, *nsp, *nsl, *egp, *egl;
   const float *pc;
   double *scratch;
+  double *tot;           // per-block scan totals
+  uint32_t *sync;        // [2 n_big] barrier arrivals and departures per net
 };
 
+// incremental update: per-sweep queues of the chunks and pieces to recompute
+struct IncArgs {
+  uint32_t *flag;            // [2 n_chunks] queued for the forward / backward sweep
+  uint32_t *cnt;             // [n_ph_fwd + n_ph_bwd] queue length of each phase
+  int32_t *wl_c;             // [2 n_chunks] queued chunks, each phase's at its first chunk id
+  int32_t *wl_p;             // [2 n_pieces] queued pieces, likewise
+  const int32_t *chunk_of;   // [n_drv] chunk of each driver slot
+  const int2 *chunk_ph;      // [n_chunks] (forward phase, backward phase index) of each chunk
+  uint8_t *rcd;              // [n_drv] 1: the driver's net was recomputed
+  int n_chunks, n_pieces;
+};
+hipError_t launch_inc_seed(const DevDesign &D, const IncArgs &I, const int32_t *slots, int n, hipStream_t s);
+hipError_t launch_inc_forward(const DevDesign &D, const IncArgs &I, int grid, hipStream_t s);
+hipError_t launch_inc_backward(const DevDesign &D, const IncArgs &I, int grid, hipStream_t s);
+int inc_blocks_per_cu(size_t lds_bytes);
 hipError_t launch_rc(const DevDesign &D, const int2 *chunks, int n_chunks, hipStream_t s);
 hipError_t launch_rc_wide(const DevDesign &D, const WideNets &W, hipStream_t s);
 hipError_t launch_rc_adjoint_wide(const DevDesign &D, const WideNets &W, hipStream_t s);

@@ -387,17 +387,126 @@ __device__ void fwd_piece(const DevDesign &D, int j) {
 }
 
 // One launch per phase (chunks of one level, or the pieces of one level).
-// (The chunk's sweep-independent loads are requested before the library is
-// staged, so the two overlap.)
+// Per-level forward: one block per chunk, thread 4 d + v computing output
+// view v = (early/late, rise/fall) of driver d of the chunk, so each thread
+// merges only the candidates of one view (in the same fanin / input-transition
+// order as the per-cell merge, so the results are identical); then the block
+// writes the chunk's sinks.  Every sweep-independent load is requested before
+// the library is staged.
+__device__ __forceinline__ void merge_view(const DevDesign &D, const CellCtx &cc, int el, int ro, const float ia[2],
+                                           const float is[2], int pos, float &at, float &sl, int &cr, float &lse) {
+  const TabLayout lay{D.nx, D.ny};
+  const float g = D.gamma;
+#pragma unroll
+  for (int ri = 0; ri < 2; ++ri) {
+    if (!arc_maps(cc.sense, ri, ro)) continue;
+    const AxisPos px = axis_find(cc.tb + lay.xa(), cc.tb + lay.rdx(), D.nx, is[ri]);
+    const float dl = bilerp(cc.tb + lay.tab(ro), D.ny, px, cc.py);
+    const float os = bilerp(cc.tb + lay.tab(2 + ro), D.ny, px, cc.py);
+    const float cand = ia[ri] + dl;
+    if (el ? cand > at : cand < at) {
+      if (el && g > 0.0f) lse = lse * expf((at - cand) / g) + 1.0f;
+      at = cand;
+      cr = pos * 2 + ri;
+    } else if (el && g > 0.0f) {
+      lse += expf((cand - at) / g);
+    }
+    sl = el ? fmaxf(sl, os) : fminf(sl, os);
+  }
+}
+
 __global__ __launch_bounds__(kSweepBlock) void k_forward(DevDesign D, int c0, int c1) {
   extern __shared__ __align__(32) unsigned char smem[];
-  const int c = c0 + blockIdx.x * (kSweepBlock / kWave) + threadIdx.x / kWave;
-  const FwdPre p = fwd_prefetch(D, c < c1 ? c : c0);
+  static_assert(kSweepBlock == 4 * kChunk, "one thread per driver view");
+  const int c = c0 + blockIdx.x;
+  const int tid = threadIdx.x, dv = tid >> 2, v = tid & 3, el = v >> 1, ro = v & 1;
+  const int4 cr4 = D.chunk_rec[c];
+  const int x0 = __builtin_amdgcn_readfirstlane(cr4.x), x1 = __builtin_amdgcn_readfirstlane(cr4.y);
+  const int s0 = __builtin_amdgcn_readfirstlane(cr4.z), s1 = __builtin_amdgcn_readfirstlane(cr4.w);
+  const int smax = max(s1 - 1, 0);
+  const int sA = min(s0 + tid, smax);
+  const int dA = D.sink_drv[sA];
+  const float2 wA = D.dq[sA];
+  const int x = x0 + dv;
+  const bool live = x < x1;
+  const int xc = live ? x : x0;
+  const bool pis = x0 < D.n_pi;  // level 0: primary inputs only
+  const bool inl = !pis && D.fanin4;
+  int t = 0;
+  float L = 0.0f;
+  int4 f4 = make_int4(-1, -1, -1, -1);
+  float pa = 0.0f, ps = 0.0f;
+  if (pis) {
+    pa = reinterpret_cast<const float *>(D.pi_at + xc)[v];
+    ps = reinterpret_cast<const float *>(D.pi_slew + xc)[v];
+  } else {
+    t = D.cell_type[xc];
+    L = D.L_net[xc];
+    if (inl) f4 = D.fanin4[xc];
+  }
+  // input states of this view's early/late half: AT and slew of (el, rise/fall)
+  const int fs[4] = {f4.x, f4.y, f4.z, f4.w};
+  float2 iat[4], isl[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const float *st = reinterpret_cast<const float *>(D.sink_state + max(fs[k], 0));
+    iat[k] = *reinterpret_cast<const float2 *>(st + 2 * el);
+    isl[k] = *reinterpret_cast<const float2 *>(st + 4 + 2 * el);
+  }
   const LdsLib lib = load_lib(D, smem);
-  PinState *wst = reinterpret_cast<PinState *>(smem + lib_lds_bytes(D.n_types, D.tstride)) +
-                  (threadIdx.x / kWave) * kWave;
+  PinState *wst = reinterpret_cast<PinState *>(smem + lib_lds_bytes(D.n_types, D.tstride));
   __syncthreads();
-  if (c < c1) fwd_finish<false>(D, lib, wst, p);
+  float at_v, sl_v;
+  int cr_v = -1;
+  if (pis) {
+    at_v = pa;
+    sl_v = ps;
+  } else {
+    const CellCtx cc = cell_ctx(D, lib, t, L);
+    at_v = el ? -kInf : kInf;
+    sl_v = el ? -kInf : kInf;
+    float lse = 0.0f;
+    if (inl) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (fs[k] < 0) continue;
+        const float ia[2] = {iat[k].x, iat[k].y}, is[2] = {isl[k].x, isl[k].y};
+        merge_view(D, cc, el, ro, ia, is, k, at_v, sl_v, cr_v, lse);
+      }
+    } else {
+      const int f0 = D.fanin_ptr[xc], f1 = D.fanin_ptr[xc + 1];
+      for (int f = f0; f < f1; ++f) {
+        const float *st = reinterpret_cast<const float *>(D.sink_state + D.fanin_sink[f]);
+        const float ia[2] = {st[2 * el], st[2 * el + 1]}, is[2] = {st[4 + 2 * el], st[5 + 2 * el]};
+        merge_view(D, cc, el, ro, ia, is, f - f0, at_v, sl_v, cr_v, lse);
+      }
+    }
+    if (el && D.gamma > 0.0f) at_v += D.gamma * logf(lse);
+  }
+  // the four views of a driver sit in adjacent lanes: assemble the crit word
+  uint32_t cw = (uint32_t)(cr_v & 0xff) << (8 * v);
+  cw |= __shfl_xor(cw, 1);
+  cw |= __shfl_xor(cw, 2);
+  if (live) {
+    float *o = reinterpret_cast<float *>(D.drv_state + x);
+    o[v] = at_v;
+    o[4 + v] = sl_v;
+    if (v == 0) D.drv_crit[x] = pis ? 0xffffffffu : cw;
+    float *w = reinterpret_cast<float *>(wst + dv);
+    w[v] = at_v;
+    w[4 + v] = sl_v;
+  }
+  __syncthreads();
+  auto emit = [&](int s, int drv, float2 w) {
+    const PinState ds = wst[drv - x0];
+    PinState o;
+    o.at = make_float4(ds.at.x + w.x, ds.at.y + w.x, ds.at.z + w.x, ds.at.w + w.x);
+    o.slew = make_float4(sqrtf(ds.slew.x * ds.slew.x + w.y), sqrtf(ds.slew.y * ds.slew.y + w.y),
+                         sqrtf(ds.slew.z * ds.slew.z + w.y), sqrtf(ds.slew.w * ds.slew.w + w.y));
+    D.sink_state[s] = o;
+  };
+  if (s0 + tid < s1) emit(s0 + tid, dA, wA);
+  for (int s = s0 + tid + kSweepBlock; s < s1; s += kSweepBlock) emit(s, D.sink_drv[s], D.dq[s]);
 }
 
 __global__ __launch_bounds__(kSweepBlock) void k_forward_pieces(DevDesign D, int j0, int j1) {
@@ -565,15 +674,109 @@ __device__ void bwd_piece(const DevDesign &D, const LdsLib &lib, int j) {
   if (lane_id() == 0) st4<kCoh>(D.piece_rat + j, acc);
 }
 
+// Per-level backward: one block per chunk.  Threads 2 j + el take sink j of
+// the chunk's range (in rounds of 128 sinks) for its early or late half (two
+// views each), merging RAT_s - d into LDS keys; then thread 4 d + v finishes
+// view v of driver d (endpoint constraint, pieces, slacks).  Sweep-independent
+// loads are requested before the library is staged.
 __global__ __launch_bounds__(kSweepBlock) void k_backward(DevDesign D, int c0, int c1) {
   extern __shared__ __align__(32) unsigned char smem[];
-  const int c = c0 + blockIdx.x * (kSweepBlock / kWave) + threadIdx.x / kWave;
-  const BwdPre p = bwd_prefetch(D, c < c1 ? c : c0);
+  const int c = c0 + blockIdx.x;
+  const int tid = threadIdx.x, el = tid & 1, dv = tid >> 2, v = tid & 3;
+  const int4 cr4 = D.chunk_rec[c];
+  const int x0 = __builtin_amdgcn_readfirstlane(cr4.x), x1 = __builtin_amdgcn_readfirstlane(cr4.y);
+  const int s0 = __builtin_amdgcn_readfirstlane(cr4.z), s1 = __builtin_amdgcn_readfirstlane(cr4.w);
+  const int smax = max(s1 - 1, 0);
+  const int sA = s0 + (tid >> 1), sAc = min(sA, smax);
+  auto ld_half = [&](int s, float2 &at, float2 &sl) {
+    const float *st = reinterpret_cast<const float *>(D.sink_state + s);
+    at = *reinterpret_cast<const float2 *>(st + 2 * el);
+    sl = *reinterpret_cast<const float2 *>(st + 4 + 2 * el);
+  };
+  float2 atA, slA;
+  ld_half(sAc, atA, slA);
+  const int consA = D.sink_cons[sAc];
+  const float dA = D.dq[sAc].x;
+  const int drvA = D.sink_drv[sAc];
+  const int x = x0 + dv;
+  const bool live = x < x1;
+  const int xc = live ? x : x0;
+  const int e = D.drv_ep[xc];
+  const float Av = reinterpret_cast<const float *>(D.drv_state + xc)[v];
+  const int2 pcs = D.chunk_pieces[c];
   const LdsLib lib = load_lib(D, smem);
-  int *wacc = reinterpret_cast<int *>(smem + lib_lds_bytes(D.n_types, D.tstride)) +
-              (threadIdx.x / kWave) * kWave * 4;
+  int *wacc = reinterpret_cast<int *>(smem + lib_lds_bytes(D.n_types, D.tstride));
+  wacc[tid] = f2key((v >> 1) ? kInf : -kInf);
   __syncthreads();
-  if (c < c1) bwd_finish<false>(D, lib, wacc, p);
+  const TabLayout lay{D.nx, D.ny};
+  auto sink = [&](int s, float2 at, float2 sl, int cons, float d, int drv) {
+    float r[2];
+    if (cons < 0) {
+      const float *er = reinterpret_cast<const float *>(D.ep_rat + (-1 - cons));
+      r[0] = er[2 * el];
+      r[1] = er[2 * el + 1];
+    } else {
+      const float2 Ro = *reinterpret_cast<const float2 *>(reinterpret_cast<const float *>(&D.cons_rec[cons].rat) + 2 * el);
+      const float2 Lt = *reinterpret_cast<const float2 *>(&D.cons_rec[cons].L);
+      const int t = __float_as_int(Lt.y);
+      const int sense = lib.sense[t];
+      const float *tb = lib.tab + t * D.tstride;
+      const AxisPos py = axis_find(tb + lay.ya(), tb + lay.rdy(), D.ny, Lt.x);
+      const float ro_[2] = {Ro.x, Ro.y}, is[2] = {sl.x, sl.y};
+#pragma unroll
+      for (int ri = 0; ri < 2; ++ri) {
+        const AxisPos px = axis_find(tb + lay.xa(), tb + lay.rdx(), D.nx, is[ri]);
+        float best = el ? kInf : -kInf;
+#pragma unroll
+        for (int ro = 0; ro < 2; ++ro) {
+          if (!arc_maps(sense, ri, ro)) continue;
+          const float cand = ro_[ro] - bilerp(tb + lay.tab(ro), D.ny, px, py);
+          best = el ? fminf(best, cand) : fmaxf(best, cand);
+        }
+        r[ri] = best;
+      }
+    }
+    float *rat = reinterpret_cast<float *>(D.sink_rat + s);
+    float *slk = reinterpret_cast<float *>(D.sink_slack + s);
+    rat[2 * el] = r[0];
+    rat[2 * el + 1] = r[1];
+    const float sk0 = el ? r[0] - at.x : at.x - r[0], sk1 = el ? r[1] - at.y : at.y - r[1];
+    slk[2 * el] = sk0;
+    slk[2 * el + 1] = sk1;
+    if (cons < 0) reinterpret_cast<float *>(D.ep_slack + (-1 - cons))[el] = fminf(sk0, sk1);
+    int *acc = wacc + (drv - x0) * 4 + 2 * el;
+    if (el) {
+      atomicMin(acc + 0, f2key(r[0] - d));
+      atomicMin(acc + 1, f2key(r[1] - d));
+    } else {
+      atomicMax(acc + 0, f2key(r[0] - d));
+      atomicMax(acc + 1, f2key(r[1] - d));
+    }
+  };
+  if (sA < s1) sink(sA, atA, slA, consA, dA, drvA);
+  for (int sj = sA + kSweepBlock / 2; sj < s1; sj += kSweepBlock / 2) {
+    float2 at, sl;
+    ld_half(sj, at, sl);
+    sink(sj, at, sl, D.sink_cons[sj], D.dq[sj].x, D.sink_drv[sj]);
+  }
+  __syncthreads();
+  float R = key2f(wacc[tid]);
+  const bool late = (v >> 1) != 0;
+  if (live && e >= 0) {
+    const float E = reinterpret_cast<const float *>(D.ep_rat + e)[v];
+    R = late ? fminf(R, E) : fmaxf(R, E);
+  }
+  for (int k = 0; k < pcs.y; ++k) {  // a high-fanout driver (alone in its chunk): its pieces' merges
+    const float E = reinterpret_cast<const float *>(D.piece_rat + pcs.x + k)[v];
+    R = late ? fminf(R, E) : fmaxf(R, E);
+  }
+  const float sk = late ? R - Av : Av - R;
+  const float skm = fminf(sk, __shfl_xor(sk, 1));  // min over rise/fall of this half
+  if (live) {
+    reinterpret_cast<float *>(&D.cons_rec[x].rat)[v] = R;
+    reinterpret_cast<float *>(D.drv_slack + x)[v] = sk;
+    if (e >= 0 && (v & 1) == 0) reinterpret_cast<float *>(D.ep_slack + e)[v >> 1] = skm;
+  }
 }
 
 __global__ __launch_bounds__(kSweepBlock) void k_backward_pieces(DevDesign D, int j0, int j1) {
@@ -792,6 +995,288 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(DevDesign D, float g_tns,
     sweep_tickets<kKind>(D, lib, wsm, g_tns, g_wns);
 }
 
+// ------------------------------------------------- incremental update
+//
+// After the caps of a few nets change, only their fan-out cone needs new
+// arrivals and only the fan-in cone of what changed needs new RATs.  The
+// sweeps walk the same phases as a full update, but each phase processes only
+// the items queued for it: a chunk is queued for the forward sweep when a net
+// of its drivers was recomputed (seeded) or when a sink feeding one of its
+// drivers changed value; for the backward sweep when its forward pass changed
+// a driver state, or when a consumer of one of its sinks changed its RAT or
+// load.  "Changed" is a bitwise comparison with the stored value, so a queued
+// chunk whose result is unchanged stops the cone there.  Every queued chunk is
+// recomputed with the same code as a full update, so the result is bitwise
+// the full update's.  Queueing targets a strictly later phase (a consumer is
+// at a higher level, a fan-in driver at a lower one), so a phase's queue is
+// complete once the previous phases are, and all blocks read its length after
+// waiting for the last non-empty phase.
+
+__device__ __forceinline__ void st_coh_i32(int32_t *p, int32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int32_t ld_coh_i32(const int32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ bool same_bits(const PinState &a, const PinState &b) {
+  return __float_as_uint(a.at.x) == __float_as_uint(b.at.x) && __float_as_uint(a.at.y) == __float_as_uint(b.at.y) &&
+         __float_as_uint(a.at.z) == __float_as_uint(b.at.z) && __float_as_uint(a.at.w) == __float_as_uint(b.at.w) &&
+         __float_as_uint(a.slew.x) == __float_as_uint(b.slew.x) &&
+         __float_as_uint(a.slew.y) == __float_as_uint(b.slew.y) &&
+         __float_as_uint(a.slew.z) == __float_as_uint(b.slew.z) && __float_as_uint(a.slew.w) == __float_as_uint(b.slew.w);
+}
+
+__device__ __forceinline__ bool same_bits4(float4 a, float4 b) {
+  return __float_as_uint(a.x) == __float_as_uint(b.x) && __float_as_uint(a.y) == __float_as_uint(b.y) &&
+         __float_as_uint(a.z) == __float_as_uint(b.z) && __float_as_uint(a.w) == __float_as_uint(b.w);
+}
+
+// Queue chunk c for the forward sweep (once).
+__device__ __forceinline__ void inc_queue_fwd(const DevDesign &D, const IncArgs &I, int c) {
+  if (__hip_atomic_exchange(I.flag + c, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) return;
+  const int k = I.chunk_ph[c].x;
+  const uint32_t pos = __hip_atomic_fetch_add(I.cnt + k, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  st_coh_i32(I.wl_c + D.phases[k].y + pos, c);
+}
+
+// Queue chunk c, and the sink pieces of its driver if it has any, for the
+// backward sweep (once); a level's pieces run in the phase before its chunks.
+__device__ __forceinline__ void inc_queue_bwd(const DevDesign &D, const IncArgs &I, int c) {
+  if (__hip_atomic_exchange(I.flag + I.n_chunks + c, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) return;
+  const int k = D.n_ph_fwd + I.chunk_ph[c].y;
+  const uint32_t pos = __hip_atomic_fetch_add(I.cnt + k, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  st_coh_i32(I.wl_c + I.n_chunks + D.phases[k].y + pos, c);
+  const int2 pcs = D.chunk_pieces[c];
+  if (pcs.y > 0) {
+    const uint32_t p0 = __hip_atomic_fetch_add(I.cnt + k - 1, (uint32_t)pcs.y, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+    int32_t *wl = I.wl_p + I.n_pieces + D.phases[k - 1].y + p0;
+    for (int i = 0; i < pcs.y; ++i) st_coh_i32(wl + i, pcs.x + i);
+  }
+}
+
+// Forward of one queued chunk: the drivers as in a full update; a driver whose
+// state is unchanged and whose net was not recomputed keeps its sinks; changed
+// sinks queue their consumers' chunks.
+__device__ void inc_fwd_chunk(const DevDesign &D, const LdsLib &lib, PinState *wst, const IncArgs &I, int c) {
+  const FwdPre p = fwd_prefetch(D, c);
+  const int lane = lane_id();
+  const int x0 = p.x0, x1 = p.x1, s1 = p.s1;
+  const int x = x0 + lane;
+  const bool live = x < x1;
+  const int xc = live ? x : x0;
+  const PinState old = D.drv_state[xc];
+  const bool rcd = I.rcd[xc] != 0;
+  PinState st;
+  uint32_t crit = 0xffffffffu;
+  if (x0 < D.n_pi) {
+    st.at = p.pat;
+    st.slew = p.psl;
+  } else if (D.fanin4) {
+    const int fs[4] = {p.f4.x, p.f4.y, p.f4.z, p.f4.w};
+    PinState in[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) in[k] = ld_state<true>(D.sink_state + max(fs[k], 0));
+    const CellCtx cc = cell_ctx(D, lib, p.t, p.L);
+    Merge m;
+    merge_init(m);
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (fs[k] >= 0) merge_one(D, cc, in[k], k, m);
+    merge_finish(D, m, st, crit);
+  } else {
+    cell_forward_csr<true>(D, lib, xc, st, crit);
+  }
+  const bool moved = live && !same_bits(st, old);
+  if (live) {
+    if (moved) st_state<true>(D.drv_state + x, st);
+    D.drv_crit[x] = crit;
+    wst[lane] = st;
+  }
+  const uint64_t redo = __ballot(live && (moved || rcd));
+  wave_sync();
+  if (redo == 0) return;
+  if (lane == 0) {
+    inc_queue_bwd(D, I, c);
+    const int2 pcs = D.chunk_pieces[c];
+    if (pcs.y > 0) {  // a high-fanout driver: its remaining sinks in the pieces phase that follows
+      const int k = I.chunk_ph[c].x + 1;
+      const uint32_t p0 = __hip_atomic_fetch_add(I.cnt + k, (uint32_t)pcs.y, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+      int32_t *wl = I.wl_p + D.phases[k].y + p0;
+      for (int i = 0; i < pcs.y; ++i) st_coh_i32(wl + i, pcs.x + i);
+    }
+  }
+  for (int s = p.s0 + lane; s < s1; s += kWave) {
+    const int drv = D.sink_drv[s];
+    if (!((redo >> (drv - x0)) & 1)) continue;
+    const PinState ds = wst[drv - x0];
+    const float2 w = D.dq[s];
+    PinState o;
+    o.at = make_float4(ds.at.x + w.x, ds.at.y + w.x, ds.at.z + w.x, ds.at.w + w.x);
+    o.slew = make_float4(sqrtf(ds.slew.x * ds.slew.x + w.y), sqrtf(ds.slew.y * ds.slew.y + w.y),
+                         sqrtf(ds.slew.z * ds.slew.z + w.y), sqrtf(ds.slew.w * ds.slew.w + w.y));
+    if (same_bits(o, D.sink_state[s])) continue;
+    st_state<true>(D.sink_state + s, o);
+    const int cons = D.sink_cons[s];
+    if (cons >= 0) inc_queue_fwd(D, I, I.chunk_of[cons]);
+  }
+  wave_sync();
+}
+
+// Forward of one queued piece (its driver changed or its net was recomputed).
+__device__ void inc_fwd_piece(const DevDesign &D, const IncArgs &I, int j) {
+  const int4 pr = D.piece_rec[j];
+  const int x = __builtin_amdgcn_readfirstlane(pr.x);
+  const int sa = __builtin_amdgcn_readfirstlane(pr.y), sb = __builtin_amdgcn_readfirstlane(pr.z);
+  const PinState ds = ld_state<true>(D.drv_state + x);
+  for (int s = sa + lane_id(); s < sb; s += kWave) {
+    const float2 w = D.dq[s];
+    PinState o;
+    o.at = make_float4(ds.at.x + w.x, ds.at.y + w.x, ds.at.z + w.x, ds.at.w + w.x);
+    o.slew = make_float4(sqrtf(ds.slew.x * ds.slew.x + w.y), sqrtf(ds.slew.y * ds.slew.y + w.y),
+                         sqrtf(ds.slew.z * ds.slew.z + w.y), sqrtf(ds.slew.w * ds.slew.w + w.y));
+    if (same_bits(o, D.sink_state[s])) continue;
+    st_state<true>(D.sink_state + s, o);
+    const int cons = D.sink_cons[s];
+    if (cons >= 0) inc_queue_fwd(D, I, I.chunk_of[cons]);
+  }
+}
+
+// Backward of one queued chunk, as in a full update; a driver whose RAT
+// changed, or whose load changed (its net was recomputed, so the delays of
+// its cell's input arcs did), queues the chunks of its fan-in sinks.
+__device__ void inc_bwd_chunk(const DevDesign &D, const LdsLib &lib, int *wacc, const IncArgs &I, int c) {
+  const BwdPre p = bwd_prefetch(D, c);
+  const int lane = lane_id();
+  const int x0 = p.x0, x1 = p.x1, s1 = p.s1;
+  const int sA = p.s0 + lane;
+  const int x = x0 + lane;
+  const bool live = x < x1;
+  const int xc = live ? x : x0;
+  const float4 old = D.cons_rec[xc].rat;
+  const bool rcd = I.rcd[xc] != 0;
+  wacc[lane * 4 + 0] = f2key(-kInf);
+  wacc[lane * 4 + 1] = f2key(-kInf);
+  wacc[lane * 4 + 2] = f2key(kInf);
+  wacc[lane * 4 + 3] = f2key(kInf);
+  wave_sync();
+  auto sink = [&](int s, const PinState &ss, int cons, float d, int drv) {
+    const float4 R = sink_rat<true>(D, lib, ss, cons);
+    if (cons < 0) D.ep_slack[-1 - cons] = ep_slack2(ss.at, R);
+    D.sink_rat[s] = R;
+    D.sink_slack[s] = slack4(ss.at, R);
+    int *acc = wacc + (drv - x0) * 4;
+    atomicMax(acc + 0, f2key(R.x - d));
+    atomicMax(acc + 1, f2key(R.y - d));
+    atomicMin(acc + 2, f2key(R.z - d));
+    atomicMin(acc + 3, f2key(R.w - d));
+  };
+  if (sA < s1) sink(sA, p.ssA, p.consA, p.dA, p.drvA);
+  if (sA + kWave < s1) sink(sA + kWave, p.ssB, p.consB, p.dB, p.drvB);
+  for (int s = sA + 2 * kWave; s < s1; s += kWave) sink(s, D.sink_state[s], D.sink_cons[s], D.dq[s].x, D.sink_drv[s]);
+  wave_sync();
+  if (live) {
+    float4 R = make_float4(key2f(wacc[lane * 4 + 0]), key2f(wacc[lane * 4 + 1]),
+                           key2f(wacc[lane * 4 + 2]), key2f(wacc[lane * 4 + 3]));
+    if (p.e >= 0) {
+      const float4 E = D.ep_rat[p.e];
+      R = make_float4(fmaxf(R.x, E.x), fmaxf(R.y, E.y), fminf(R.z, E.z), fminf(R.w, E.w));
+    }
+    for (int k = 0; k < p.pcs.y; ++k) {
+      const float4 E = ld4<true>(D.piece_rat + p.pcs.x + k);
+      R = make_float4(fmaxf(R.x, E.x), fmaxf(R.y, E.y), fminf(R.z, E.z), fminf(R.w, E.w));
+    }
+    const bool moved = !same_bits4(R, old);
+    if (moved) st4<true>(&D.cons_rec[x].rat, R);
+    D.drv_slack[x] = slack4(p.A, R);
+    if (p.e >= 0) D.ep_slack[p.e] = ep_slack2(p.A, R);
+    if ((moved || rcd) && x >= D.n_pi) {
+      if (D.fanin4) {
+        const int4 f4 = D.fanin4[x];
+        const int fs[4] = {f4.x, f4.y, f4.z, f4.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          if (fs[k] >= 0) inc_queue_bwd(D, I, I.chunk_of[D.sink_drv[fs[k]]]);
+      } else {
+        for (int f = D.fanin_ptr[x]; f < D.fanin_ptr[x + 1]; ++f)
+          inc_queue_bwd(D, I, I.chunk_of[D.sink_drv[D.fanin_sink[f]]]);
+      }
+    }
+  }
+  wave_sync();
+}
+
+// One sweep over the queued items: wave w of W takes the items w, w + W, ...
+// of each non-empty phase.  Every block reads each phase's queue length after
+// the last non-empty phase has completed (all blocks are resident: cooperative
+// launch), so all blocks agree on it and every loop ends.
+template <int kKind>
+__global__ __launch_bounds__(kSweepBlock) void k_inc_sweep(DevDesign D, IncArgs I) {
+  extern __shared__ __align__(32) unsigned char smem[];
+  __shared__ uint32_t s_n[2];
+  constexpr int kWaves = kSweepBlock / kWave;
+  const LdsLib lib = load_lib(D, smem);
+  __syncthreads();
+  unsigned char *wsm = smem + lib_lds_bytes(D.n_types, D.tstride);
+  int n_ph = 0, base = 0;
+  const int4 *ph = sweep_phases(D, kKind, n_ph, base);
+  const int W = (int)gridDim.x * kWaves;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int b0 = blockIdx.x * kWaves;
+  const int g = blockIdx.x & (kDoneGroups - 1);
+  const int off_c = kKind == kSweepBwd ? I.n_chunks : 0, off_p = kKind == kSweepBwd ? I.n_pieces : 0;
+  int wait_k = -1;
+  uint32_t wait_n = 0;
+  for (int k = 0; k < n_ph; ++k) {
+    if (wave == 0) {
+      if (wait_k >= 0) wait_done(done_ctr(D, base + wait_k), wait_n);
+      const uint32_t n = __hip_atomic_load(I.cnt + base + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (lane_id() == 0) s_n[k & 1] = n;
+    }
+    __syncthreads();
+    const int n = (int)__builtin_amdgcn_readfirstlane(s_n[k & 1]);
+    wait_k = -1;  // the last non-empty phase has completed
+    if (n == 0) continue;
+    const int4 P = ph[k];
+    const int kind = __builtin_amdgcn_readfirstlane(P.x), first = __builtin_amdgcn_readfirstlane(P.y);
+    int mine = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w)
+      if (b0 + w < n) mine += (n - (b0 + w) + W - 1) / W;
+    for (int i = b0 + wave; i < n; i += W) {
+      if (kind == kItemChunk) {
+        const int c = __builtin_amdgcn_readfirstlane(ld_coh_i32(I.wl_c + off_c + first + i));
+        if constexpr (kKind == kSweepFwd)
+          inc_fwd_chunk(D, lib, reinterpret_cast<PinState *>(wsm) + wave * kWave, I, c);
+        else
+          inc_bwd_chunk(D, lib, reinterpret_cast<int *>(wsm) + wave * kWave * 4, I, c);
+      } else {
+        const int j = __builtin_amdgcn_readfirstlane(ld_coh_i32(I.wl_p + off_p + first + i));
+        if constexpr (kKind == kSweepFwd)
+          inc_fwd_piece(D, I, j);
+        else
+          bwd_piece<true>(D, lib, j);
+      }
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (wave == 0 && mine > 0) signal_add(done_ctr(D, base + k) + g, (uint32_t)mine);
+    wait_k = k;
+    wait_n = (uint32_t)n;
+  }
+}
+
+// Seeds an incremental update: the drivers of the recomputed nets.
+__global__ void k_inc_seed(DevDesign D, IncArgs I, const int32_t *slots, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int x = slots[i];
+  I.rcd[x] = 1;
+  inc_queue_fwd(D, I, I.chunk_of[x]);
+}
+
 // ------------------------------------------------------------------ RC
 
 // Elmore recursions on one tree held in LDS (nodes b..b+m-1, parent < child):
@@ -812,36 +1297,130 @@ __device__ __forceinline__ float rc_tree_lds(const uint8_t *par, const float *R,
   return load;
 }
 
-// ---- wide nets: block per net, FP64 scans over the DFS preorder ----------
+// ---- wide nets: FP64 scans over the DFS preorder ---------------------------
 //
 // In preorder the subtree of node k is the index range [k, end_k), so
 //   load_k = sum of C^ over [k, end_k)           = P[end_k] - P[k]   (P = exclusive scan of C^)
 //   ld_k   = sum of C^ d over [k, end_k)         (same with C^ d)
 // and a path sum over the ancestors-or-self of k (the a with a <= k < end_a) is
 //   sum_{p <= k} (w_p - E_p),   E_p = sum of w_a over the nodes a with end_a = p,
-// which gives d (w = R load) and m2 (w = R ld).  The nodes with end_a = p form a
-// chain upward from p - 1, so E_p is gathered by walking that chain (each node is
-// visited once overall) in a fixed order.  FP64 keeps the prefix differences
-// exact to far below FP32 resolution.
+// which gives d (w = R load) and m2 (w = R ld).  The nodes are listed grouped by
+// end position (egl, offsets egp), so E is a difference of an FP64 prefix over
+// that list.  FP64 keeps the prefix differences exact far below FP32
+// resolution.
+//
+// A net of m nodes is shared by ceil(m / kWideSeg) blocks of 1024 threads, block
+// b owning preorder segment [b kWideSeg, (b+1) kWideSeg).  Scans run as a
+// segment reduction, a barrier among the net's blocks, a carry summed over the
+// earlier segments in block order (deterministic), and the segment scan.
+// Values one block writes and another reads (the FP64 scratch arrays) go
+// through agent-scope relaxed 64-bit atomics, and a block waits for its stores
+// before it arrives at a barrier (the persistent-sweep protocol).  The blocks
+// of a net never wait on anything but each other, so every block of a net
+// eventually runs; the last block to leave resets the net's counters for the
+// next launch (stream-ordered after this one).
 
-// Block-wide scan of in[0, n) into out (may alias in): inclusive, or exclusive
-// with out[n] = total.  Tiles of kScanPer consecutive elements per thread.
+struct WideCtx {
+  int m, k0, k1, b, nblk;
+  uint32_t *arrive, *leave;
+  double *tot;
+  uint32_t passed;
+};
+
+__device__ __forceinline__ double ldc(const double *p) {
+  return __longlong_as_double(
+      __hip_atomic_load(reinterpret_cast<const long long *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+
+__device__ __forceinline__ void stc(double *p, double v) {
+  __hip_atomic_store(reinterpret_cast<long long *>(p), __double_as_longlong(v), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Barrier among the blocks of one net.
+__device__ void wide_sync(WideCtx &c) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  ++c.passed;
+  if (c.nblk > 1 && threadIdx.x < kWave) {
+    signal_add(c.arrive, 1u);
+    const uint32_t target = c.passed * (uint32_t)c.nblk;
+    for (;;) {
+      const uint32_t v = __hip_atomic_load(c.arrive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (__builtin_amdgcn_readfirstlane(v) >= target) break;
+      __builtin_amdgcn_s_sleep(1);
+    }
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  }
+  __syncthreads();
+}
+
+// out[k] = load(k) over the block's segment; each thread requests kMapUnroll
+// elements (strided by the block) before storing any.
+constexpr int kMapUnroll = 4;
+
+template <class Load, class Store>
+__device__ __forceinline__ void seg_map(int k0, int k1, Load load, Store store) {
+  using V = decltype(load(0));
+  const int nt = blockDim.x;
+  for (int b = k0 + (int)threadIdx.x; b < k1; b += kMapUnroll * nt) {
+    V v[kMapUnroll];
+#pragma unroll
+    for (int u = 0; u < kMapUnroll; ++u) v[u] = load(min(b + u * nt, k1 - 1));
+#pragma unroll
+    for (int u = 0; u < kMapUnroll; ++u)
+      if (b + u * nt < k1) store(b + u * nt, v[u]);
+  }
+  __syncthreads();
+}
+
+// Sum of in over [k0, k1) in a fixed order (per thread, then a fixed tree).
+__device__ double block_sum(const double *in, int k0, int k1, double *s_w) {
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave, nw = blockDim.x / kWave;
+  double acc = 0.0;
+  for (int b = k0 + tid; b < k1; b += kMapUnroll * blockDim.x) {
+    double v[kMapUnroll];
+#pragma unroll
+    for (int u = 0; u < kMapUnroll; ++u) v[u] = ldc(in + min(b + u * (int)blockDim.x, k1 - 1));
+#pragma unroll
+    for (int u = 0; u < kMapUnroll; ++u)
+      if (b + u * (int)blockDim.x < k1) acc += v[u];
+  }
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if (lane == 0) s_w[wid] = acc;
+  __syncthreads();
+  double t = 0.0;
+  for (int w = 0; w < nw; ++w) t += s_w[w];
+  __syncthreads();
+  return t;
+}
+
+// Scan of in[0, m) into out over the net's blocks: exclusive with out[m] =
+// total, or inclusive; in may alias out.  Ends with a barrier, so every block
+// may read any of out afterwards.
 constexpr int kScanPer = 8;
 
-__device__ void block_scan(const double *in, double *out, int n, bool exclusive, double *s_w) {
+__device__ void wide_scan(WideCtx &c, const double *in, double *out, bool exclusive, double *s_w) {
+  const double part = block_sum(in, c.k0, c.k1, s_w);
+  if (c.nblk > 1) {
+    if (threadIdx.x == 0) stc(c.tot + c.b, part);
+    wide_sync(c);
+  }
+  double carry = 0.0;
+  for (int q = 0; q < c.b; ++q) carry += ldc(c.tot + q);
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
   const int nw = blockDim.x / kWave;
   const int tile = blockDim.x * kScanPer;
-  double carry = 0.0;
-  for (int base = 0; base < n; base += tile) {
+  for (int base = c.k0; base < c.k1; base += tile) {
     const int i0 = base + tid * kScanPer;
     double x[kScanPer];
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j) x[j] = ldc(in + min(i0 + j, c.k1 - 1));
     double run = 0.0;
 #pragma unroll
-    for (int j = 0; j < kScanPer; ++j) x[j] = in[min(i0 + j, n - 1)];  // all loads in flight
-#pragma unroll
     for (int j = 0; j < kScanPer; ++j) {
-      if (i0 + j >= n) x[j] = 0.0;
+      if (i0 + j >= c.k1) x[j] = 0.0;
       run += x[j];
     }
     double incl = run;
@@ -867,58 +1446,63 @@ __device__ void block_scan(const double *in, double *out, int n, bool exclusive,
     double pre = carry + s_w[wid] + excl;
 #pragma unroll
     for (int j = 0; j < kScanPer; ++j) {
-      if (i0 + j < n) out[i0 + j] = exclusive ? pre : pre + x[j];
+      if (i0 + j < c.k1) stc(out + i0 + j, exclusive ? pre : pre + x[j]);
       pre += x[j];
     }
     carry += s_w[nw];
     __syncthreads();
   }
-  if (exclusive && threadIdx.x == 0) out[n] = carry;
-  __syncthreads();
+  if (exclusive && c.b == c.nblk - 1 && threadIdx.x == 0) stc(out + c.m, carry);
+  wide_sync(c);
 }
 
-// out[k] = load(k) for k in [0, m): each thread requests kMapUnroll elements
-// (strided by the block) before storing any, so a pass costs a few memory round
-// trips per 8192 nodes instead of one per node.  The functors capture plain
-// pointers only.
-constexpr int kMapUnroll = 4;
+// X[k] = R[k] (subtree sum of the values whose exclusive prefix is P) for k > 0,
+// X[0] = 0, over the block's segment; then a barrier.
+__device__ __forceinline__ void wide_edge(WideCtx &c, const float *R, const double *P, const int32_t *end,
+                                          double *X) {
+  seg_map(c.k0, c.k1, [=](int k) { return k ? (double)R[k] * (ldc(P + end[k]) - ldc(P + k)) : 0.0; },
+          [=](int k, double v) { stc(X + k, v); });
+  wide_sync(c);
+}
 
-template <class Load, class Store>
-__device__ __forceinline__ void wide_map(int m, Load load, Store store) {
-  using V = decltype(load(0));
-  const int nt = blockDim.x;
-  for (int b = threadIdx.x; b < m; b += kMapUnroll * nt) {
-    V v[kMapUnroll];
-#pragma unroll
-    for (int u = 0; u < kMapUnroll; ++u) v[u] = load(min(b + u * nt, m - 1));
-#pragma unroll
-    for (int u = 0; u < kMapUnroll; ++u)
-      if (b + u * nt < m) store(b + u * nt, v[u]);
+// Path sums from edge terms X (complete over the net; X[0] = 0):
+// out[p] = sum over the ancestors-or-self a of p of X[a].
+__device__ void wide_path_sum(WideCtx &c, const double *X, const int32_t *egp, const int32_t *egl, double *V,
+                              double *out, double *s_w) {
+  seg_map(c.k0, c.k1, [=](int i) { return ldc(X + egl[i]); }, [=](int i, double v) { stc(V + i, v); });
+  wide_scan(c, V, V, true, s_w);
+  seg_map(c.k0, c.k1, [=](int p) { return ldc(X + p) - (ldc(V + egp[p + 1]) - ldc(V + egp[p])); },
+          [=](int p, double v) { stc(out + p, v); });
+  wide_scan(c, out, out, false, s_w);
+}
+
+__device__ WideCtx wide_ctx(const BigNet &B, const WideNets &W, int seg, int net) {
+  WideCtx c;
+  c.m = B.m;
+  c.b = seg;
+  c.nblk = B.nblk;
+  c.k0 = seg * kWideSeg;
+  c.k1 = min(B.m, c.k0 + kWideSeg);
+  c.arrive = W.sync + 2 * net;
+  c.leave = W.sync + 2 * net + 1;
+  c.tot = W.tot + B.tot;
+  c.passed = 0;
+  return c;
+}
+
+// The last block of a net to finish resets the net's counters.
+__device__ void wide_leave(WideCtx &c) {
+  __syncthreads();
+  if (c.nblk > 1 && threadIdx.x < kWave) {
+    const uint32_t old = atomicAdd(c.leave, lane_id() == 0 ? 1u : 0u);
+    if (__builtin_amdgcn_readfirstlane(old) == (uint32_t)(c.nblk - 1) && lane_id() == 0) {
+      *c.arrive = 0u;
+      *c.leave = 0u;
+    }
   }
-  __syncthreads();
 }
 
-// Path sums from edge terms X (X[0] = 0): out[p] = sum over the ancestors-or-
-// self a of p of X[a] = inclusive prefix over q <= p of (X[q] - E[q]), with
-// E[q] = sum of X[a] over the nodes a whose subtree ends at q.  The nodes are
-// listed grouped by end position (egl, offsets egp), so E is a difference of an
-// FP64 exclusive prefix V over X[egl[i]].
-__device__ void wide_path_sum(const double *X, const int32_t *egp, const int32_t *egl, double *V, double *out,
-                              int m, double *s_w) {
-  wide_map(m, [=](int i) { return X[egl[i]]; }, [=](int i, double v) { V[i] = v; });
-  block_scan(V, V, m, true, s_w);
-  wide_map(m, [=](int p) { return X[p] - (V[egp[p + 1]] - V[egp[p]]); }, [=](int p, double v) { out[p] = v; });
-  block_scan(out, out, m, false, s_w);
-}
-
-// X[k] = R[k] (subtree sum of the values whose exclusive prefix is P) for k > 0;
-// X[0] = 0 (the root has no segment).
-__device__ __forceinline__ void wide_edge(const float *R, const double *P, const int32_t *end, double *X, int m) {
-  wide_map(m, [=](int k) { return k ? (double)R[k] * (P[end[k]] - P[k]) : 0.0; },
-           [=](int k, double v) { X[k] = v; });
-}
-
-__device__ void rc_wide_net(const DevDesign &D, const BigNet &B, const WideNets &W, double *s_w) {
+__device__ void rc_wide_net(const DevDesign &D, const BigNet &B, const WideNets &W, WideCtx &c, double *s_w) {
   const int x = B.x, m = B.m;
   const int k0 = D.rc_ptr[x];
   const float *R = D.rc_res + k0;
@@ -928,36 +1512,43 @@ __device__ void rc_wide_net(const DevDesign &D, const BigNet &B, const WideNets 
   const int32_t *egp = W.egp + B.egp, *egl = W.egl + B.aux;
   const int st = m + 1;
   double *A = W.scratch + B.scr, *P = A + st, *X = P + st, *Y = X + st, *V = Y + st;
-  wide_map(m, [=](int k) { return (double)Cw[k] + (double)pc[k]; }, [=](int k, double v) { A[k] = v; });  // C^
-  block_scan(A, P, m, true, s_w);                                          // P: prefix of C^
-  const double total = P[m];
-  wide_edge(R, P, end, X, m);                                              // R load
-  wide_path_sum(X, egp, egl, V, Y, m, s_w);                                // Y: d
-  wide_map(m, [=](int k) { return A[k] * Y[k]; }, [=](int k, double v) { X[k] = v; });  // C^ d
-  block_scan(X, P, m, true, s_w);                                          // P: prefix of C^ d
-  wide_edge(R, P, end, X, m);                                              // R ld
-  wide_path_sum(X, egp, egl, V, A, m, s_w);                                // A: m2
-  if (threadIdx.x == 0) {
+  seg_map(c.k0, c.k1, [=](int k) { return (double)Cw[k] + (double)pc[k]; }, [=](int k, double v) { stc(A + k, v); });
+  wide_scan(c, A, P, true, s_w);                                           // P: prefix of C^
+  const double total = ldc(P + m);
+  wide_edge(c, R, P, end, X);                                              // R load
+  wide_path_sum(c, X, egp, egl, V, Y, s_w);                                // Y: d
+  seg_map(c.k0, c.k1, [=](int k) { return ldc(A + k) * ldc(Y + k); }, [=](int k, double v) { stc(X + k, v); });
+  wide_scan(c, X, P, true, s_w);                                           // P: prefix of C^ d
+  wide_edge(c, R, P, end, X);                                              // R ld
+  wide_path_sum(c, X, egp, egl, V, A, s_w);                                // A: m2
+  if (c.b == 0 && threadIdx.x == 0) {
     D.L_net[x] = (float)total;
     D.cons_rec[x].L = (float)total;
   }
+  // the net's sinks, split evenly over its blocks
   const int s0 = D.sink_ptr[x], ns = D.sink_ptr[x + 1] - s0;
+  const int per = (ns + c.nblk - 1) / c.nblk;
+  const int j0 = min(ns, c.b * per), j1 = min(ns, j0 + per);
   const int32_t *snode = D.sink_node + s0;
   float2 *dq = D.dq + s0;
-  wide_map(ns,
-           [=](int j) {
-             const int k = snode[j];
-             const double d = Y[k];
-             return make_float2((float)d, (float)fmax(0.0, 2.0 * A[k] - d * d));
-           },
-           [=](int j, float2 v) { dq[j] = v; });
+  seg_map(j0, j1,
+          [=](int j) {
+            const int k = snode[j];
+            const double d = ldc(Y + k);
+            return make_float2((float)d, (float)fmax(0.0, 2.0 * ldc(A + k) - d * d));
+          },
+          [=](int j, float2 v) { dq[j] = v; });
+  wide_leave(c);
 }
 
-// Wide nets: one 1024-thread block per net (launched on a side stream so it
-// overlaps the small-net kernel).
+// Wide nets: blocks of 1024 threads, several per net (launched on a side
+// stream so they overlap the small-net kernel).
 __global__ __launch_bounds__(kWideBlock) void k_rc_wide(DevDesign D, WideNets W) {
   __shared__ double s_w[kWideBlock / kWave + 1];
-  rc_wide_net(D, W.big[blockIdx.x], W, s_w);
+  const int2 nb = W.blk[blockIdx.x];
+  const BigNet &B = W.big[nb.x];
+  WideCtx c = wide_ctx(B, W, nb.y, nb.x);
+  rc_wide_net(D, B, W, c, s_w);
 }
 
 // Stages nodes [k0, k0 + nk) of one RC chunk into LDS: parent, R and
@@ -1374,7 +1965,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_adjoint(DevDesign D, float g_tn
 //   Gd, Gm = subtree sums of gd, gm, K = subtree sum of C^ H.
 // (dJ/dq is dropped where the clamp q = max(0, .) is active.)
 
-__device__ void rc_adjoint_wide(const DevDesign &D, const BigNet &B, const WideNets &W, double *s_w) {
+__device__ void rc_adjoint_wide(const DevDesign &D, const BigNet &B, const WideNets &W, WideCtx &c, double *s_w) {
   const int x = B.x, m = B.m;
   const int k0 = D.rc_ptr[x];
   const float *R = D.rc_res + k0;
@@ -1389,42 +1980,46 @@ __device__ void rc_adjoint_wide(const DevDesign &D, const BigNet &B, const WideN
   double *A = W.scratch + B.scr, *P = A + st, *X = P + st, *Y = X + st, *Z = Y + st;
   double *G1 = Z + st, *G2 = G1 + st, *T = G2 + st, *V = T + st;
   // forward moments: Y = d, Z = m2
-  wide_map(m, [=](int k) { return (double)Cw[k] + (double)pc[k]; }, [=](int k, double v) { A[k] = v; });
-  block_scan(A, P, m, true, s_w);
-  wide_edge(R, P, end, X, m);
-  wide_path_sum(X, egp, egl, V, Y, m, s_w);
-  wide_map(m, [=](int k) { return A[k] * Y[k]; }, [=](int k, double v) { X[k] = v; });
-  block_scan(X, P, m, true, s_w);
-  wide_edge(R, P, end, X, m);
-  wide_path_sum(X, egp, egl, V, Z, m, s_w);
+  seg_map(c.k0, c.k1, [=](int k) { return (double)Cw[k] + (double)pc[k]; }, [=](int k, double v) { stc(A + k, v); });
+  wide_scan(c, A, P, true, s_w);
+  wide_edge(c, R, P, end, X);
+  wide_path_sum(c, X, egp, egl, V, Y, s_w);
+  seg_map(c.k0, c.k1, [=](int k) { return ldc(A + k) * ldc(Y + k); }, [=](int k, double v) { stc(X + k, v); });
+  wide_scan(c, X, P, true, s_w);
+  wide_edge(c, R, P, end, X);
+  wide_path_sum(c, X, egp, egl, V, Z, s_w);
   // sink-node seeds, sinks of a node in sink order
-  for (int k = threadIdx.x; k < m; k += blockDim.x) {
+  for (int k = c.k0 + threadIdx.x; k < c.k1; k += blockDim.x) {
     double gd = 0.0, gm = 0.0;
+    const double yk = ldc(Y + k), zk = ldc(Z + k);
     for (int i = nsp[k]; i < nsp[k + 1]; ++i) {
       const float2 g = gdq[nsl[i]];
-      const double gq = (2.0 * Z[k] - Y[k] * Y[k]) > 0.0 ? (double)g.y : 0.0;
-      gd += (double)g.x - 2.0 * Y[k] * gq;
+      const double gq = (2.0 * zk - yk * yk) > 0.0 ? (double)g.y : 0.0;
+      gd += (double)g.x - 2.0 * yk * gq;
       gm += 2.0 * gq;
     }
-    G1[k] = gd;
-    G2[k] = gm;
+    stc(G1 + k, gd);
+    stc(G2 + k, gm);
   }
   __syncthreads();
-  block_scan(G1, P, m, true, s_w);                          // Gd = subtree sums
-  wide_map(m, [=](int k) { return P[end[k]] - P[k]; }, [=](int k, double v) { G1[k] = v; });
-  block_scan(G2, P, m, true, s_w);                          // Gm
-  wide_edge(R, P, end, X, m);
-  wide_path_sum(X, egp, egl, V, T, m, s_w);                 // H = path sum of R Gm
-  wide_map(m, [=](int k) { return k ? (double)R[k] * G1[k] : 0.0; }, [=](int k, double v) { X[k] = v; });
-  wide_path_sum(X, egp, egl, V, G1, m, s_w);                // PA = path sum of R Gd
-  wide_map(m, [=](int k) { return A[k] * T[k]; }, [=](int k, double v) { X[k] = v; });
-  block_scan(X, P, m, true, s_w);                           // K = subtree sum of C^ H
-  wide_edge(R, P, end, X, m);
-  wide_path_sum(X, egp, egl, V, G2, m, s_w);                // PB = path sum of R K
+  wide_scan(c, G1, P, true, s_w);                           // Gd = subtree sums
+  seg_map(c.k0, c.k1, [=](int k) { return ldc(P + end[k]) - ldc(P + k); }, [=](int k, double v) { stc(G1 + k, v); });
+  wide_scan(c, G2, P, true, s_w);                           // Gm
+  wide_edge(c, R, P, end, X);
+  wide_path_sum(c, X, egp, egl, V, T, s_w);                 // H = path sum of R Gm
+  seg_map(c.k0, c.k1, [=](int k) { return k ? (double)R[k] * ldc(G1 + k) : 0.0; },
+          [=](int k, double v) { stc(X + k, v); });
+  wide_sync(c);
+  wide_path_sum(c, X, egp, egl, V, G1, s_w);                // PA = path sum of R Gd
+  seg_map(c.k0, c.k1, [=](int k) { return ldc(A + k) * ldc(T + k); }, [=](int k, double v) { stc(X + k, v); });
+  wide_scan(c, X, P, true, s_w);                            // K = subtree sum of C^ H
+  wide_edge(c, R, P, end, X);
+  wide_path_sum(c, X, egp, egl, V, G2, s_w);                // PB = path sum of R K
   const double gL = (double)D.g_load[x];
   float *gcap = D.g_cap + k0;
-  wide_map(m, [=](int k) { return (float)(gL + G1[k] + Y[k] * T[k] + G2[k]); },
-           [=](int k, float v) { gcap[k] = v; });
+  seg_map(c.k0, c.k1, [=](int k) { return (float)(gL + ldc(G1 + k) + ldc(Y + k) * ldc(T + k) + ldc(G2 + k)); },
+          [=](int k, float v) { gcap[k] = v; });
+  wide_leave(c);
 }
 
 // Same block layout as k_rc.  Small nets: one lane per net in LDS, the forward
@@ -1432,7 +2027,10 @@ __device__ void rc_adjoint_wide(const DevDesign &D, const BigNet &B, const WideN
 // sweep counters (the next update and the next adjoint start from zero).
 __global__ __launch_bounds__(kWideBlock) void k_rc_adjoint_wide(DevDesign D, WideNets W) {
   __shared__ double s_w[kWideBlock / kWave + 1];
-  rc_adjoint_wide(D, W.big[blockIdx.x], W, s_w);
+  const int2 nb = W.blk[blockIdx.x];
+  const BigNet &B = W.big[nb.x];
+  WideCtx c = wide_ctx(B, W, nb.y, nb.x);
+  rc_adjoint_wide(D, B, W, c, s_w);
 }
 
 __global__ __launch_bounds__(kRcBlock) void k_rc_adjoint(DevDesign D, const int2 *chunks, int n_chunks) {
@@ -1834,13 +2432,13 @@ hipError_t launch_rc(const DevDesign &D, const int2 *chunks, int n_chunks, hipSt
 
 hipError_t launch_rc_wide(const DevDesign &D, const WideNets &W, hipStream_t s) {
   if (W.n_big <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_rc_wide, dim3(W.n_big), dim3(kWideBlock), 0, s, D, W);
+  hipLaunchKernelGGL(k_rc_wide, dim3(W.n_blk), dim3(kWideBlock), 0, s, D, W);
   return hipGetLastError();
 }
 
 hipError_t launch_rc_adjoint_wide(const DevDesign &D, const WideNets &W, hipStream_t s) {
   if (W.n_big <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_rc_adjoint_wide, dim3(W.n_big), dim3(kWideBlock), 0, s, D, W);
+  hipLaunchKernelGGL(k_rc_adjoint_wide, dim3(W.n_blk), dim3(kWideBlock), 0, s, D, W);
   return hipGetLastError();
 }
 
@@ -1854,8 +2452,7 @@ hipError_t launch_forward_phase(const DevDesign &D, int4 ph, hipStream_t s) {
   if (ph.x == kItemPiece)
     hipLaunchKernelGGL(k_forward_pieces, dim3(blocks_for(ph.z, per)), dim3(kSweepBlock), 0, s, D, ph.y, ph.y + ph.z);
   else
-    hipLaunchKernelGGL(k_forward, dim3(blocks_for(ph.z, per)), dim3(kSweepBlock), sweep_lds_bytes(D), s, D, ph.y,
-                       ph.y + ph.z);
+    hipLaunchKernelGGL(k_forward, dim3(ph.z), dim3(kSweepBlock), sweep_lds_bytes(D), s, D, ph.y, ph.y + ph.z);
   return hipGetLastError();
 }
 
@@ -1870,8 +2467,7 @@ hipError_t launch_backward_phase(const DevDesign &D, int4 ph, hipStream_t s) {
     hipLaunchKernelGGL(k_backward_pieces, dim3(blocks_for(ph.z, per)), dim3(kSweepBlock), sweep_lds_bytes(D), s, D,
                        ph.y, ph.y + ph.z);
   else
-    hipLaunchKernelGGL(k_backward, dim3(blocks_for(ph.z, per)), dim3(kSweepBlock), sweep_lds_bytes(D), s, D, ph.y,
-                       ph.y + ph.z);
+    hipLaunchKernelGGL(k_backward, dim3(ph.z), dim3(kSweepBlock), sweep_lds_bytes(D), s, D, ph.y, ph.y + ph.z);
   return hipGetLastError();
 }
 
@@ -1908,6 +2504,41 @@ hipError_t launch_scatter_grads(const DevDesign &D, const int32_t *node_src, int
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_scatter_grads, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, D, node_src, n_nodes,
                      grad_cap, pin_loc, n_pins, grad_load, arc_src, n_arcs, grad_arc);
+  return hipGetLastError();
+}
+
+template <int kKind>
+static hipError_t launch_inc(const DevDesign &D, const IncArgs &I, int grid, hipStream_t s) {
+  DevDesign a = D;
+  IncArgs b = I;
+  void *args[] = {&a, &b};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_inc_sweep<kKind>), dim3(grid),
+                                    dim3(kSweepBlock), args, (unsigned)sweep_lds_bytes(D), s);
+}
+
+hipError_t launch_inc_forward(const DevDesign &D, const IncArgs &I, int grid, hipStream_t s) {
+  return launch_inc<kSweepFwd>(D, I, grid, s);
+}
+
+hipError_t launch_inc_backward(const DevDesign &D, const IncArgs &I, int grid, hipStream_t s) {
+  return launch_inc<kSweepBwd>(D, I, grid, s);
+}
+
+int inc_blocks_per_cu(size_t lds_bytes) {
+  int n = 1 << 30;
+  const void *ks[] = {reinterpret_cast<const void *>(&k_inc_sweep<kSweepFwd>),
+                      reinterpret_cast<const void *>(&k_inc_sweep<kSweepBwd>)};
+  for (const void *k : ks) {
+    int b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k, kSweepBlock, lds_bytes) != hipSuccess) return 0;
+    n = b < n ? b : n;
+  }
+  return n;
+}
+
+hipError_t launch_inc_seed(const DevDesign &D, const IncArgs &I, const int32_t *slots, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_inc_seed, dim3(blocks_for(n, 256)), dim3(256), 0, s, D, I, slots, n);
   return hipGetLastError();
 }
 

@@ -90,6 +90,7 @@ _SIGS = [
     ("sta_destroy", None, [_VP]),
     ("sta_set_wire_caps", ctypes.c_int, [_VP, _VP, ctypes.c_int, _VP]),
     ("sta_update_timing", ctypes.c_int, [_VP, _VP]),
+    ("sta_update_timing_incremental", ctypes.c_int, [_VP, _VP, ctypes.c_int32, ctypes.c_int, _VP]),
     ("sta_report_slack", ctypes.c_int, [_VP, _VP, _VP, _VP, _PD, _PD, ctypes.c_int, _VP]),
     ("sta_report_timing", ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, ctypes.c_int, _VP]),
     ("sta_report_levels", ctypes.c_int, [_VP, _VP, _VP, ctypes.c_int, _VP]),
@@ -216,6 +217,16 @@ def sta_set_wire_caps(ctx: int, cap_ff, mem: int, stream=None) -> None:
 
 def sta_update_timing(ctx: int, stream=None) -> None:
     _check(load().sta_update_timing(ctx, _stream(stream)))
+
+
+def sta_update_timing_incremental(ctx: int, nets, mem: int = STA_HOST, stream=None) -> None:
+    if nets is None:
+        _check(load().sta_update_timing_incremental(ctx, None, 0, mem, _stream(stream)))
+        return
+    if mem == STA_HOST:
+        nets = np.ascontiguousarray(nets, np.int32)
+    n = int(nets.shape[0]) if hasattr(nets, "shape") else len(nets)
+    _check(load().sta_update_timing_incremental(ctx, _addr(nets) if n else None, n, mem, _stream(stream)))
 
 
 def sta_report_slack(ctx: int, pin_slack=None, ep_slack=None, ep_order=None, dst: int = STA_HOST,
@@ -396,6 +407,11 @@ class STA:
 
     def update(self, stream=None):
         sta_update_timing(self.ctx, stream)
+
+    def update_incremental(self, nets, stream=None):
+        """Incremental update after the caps of `nets` (caller net ids) changed."""
+        mem = STA_DEVICE if hasattr(nets, "data_ptr") else STA_HOST
+        sta_update_timing_incremental(self.ctx, nets, mem, stream)
 
     def set_wire_caps(self, cap, stream=None):
         mem = STA_DEVICE if hasattr(cap, "data_ptr") else STA_HOST

@@ -148,6 +148,9 @@ def test_null_context_calls_are_state_errors():
     with pytest.raises(S.StaError) as e:
         S.sta_backward(0, 1.0, 0.0)
     assert e.value.status == S.STA_E_STATE
+    with pytest.raises(S.StaError) as e:
+        S.sta_update_timing_incremental(0, np.array([0], np.int32))
+    assert e.value.status == S.STA_E_STATE
 
 
 def _batch(designs, **opts):

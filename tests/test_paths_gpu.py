@@ -34,7 +34,7 @@ def _fp64_slack(g, r, path, el):
     return rat - acc if el == 1 else acc - rat
 
 
-def _compare(d, got, ref, r, el, thr):
+def _compare(d, got, ref, r, el, thr, k, m):
     tol = max(1e-3, 1e-5 * _scale(r))
     gs = np.array([p["slack"] for p in got])
     rs = np.array([p["slack"] for p in ref])
@@ -46,13 +46,18 @@ def _compare(d, got, ref, r, el, thr):
     n = min(len(gs), len(rs))
     assert np.all(np.abs(gs[:n] - rs[:n]) <= tol), np.abs(gs[:n] - rs[:n]).max()
     g = P._Graph(d, r)
+    # every oracle path of each endpoint near the reported slacks (a tie may
+    # hide behind the per-endpoint limit): a GPU path must be one of the
+    # oracle's paths of its endpoint within tolerance of its slack
+    wide = P.top_paths(d, 4 * k + 16, m + 4, thr + 2 * tol if np.isfinite(thr) else thr, el, r)
+    by_ep = {}
+    for p in wide:
+        by_ep.setdefault(p["endpoint"], []).append(p)
     for i in range(n):
         _connected(d, got[i])
         assert abs(_fp64_slack(g, r, got[i], el) - gs[i]) <= tol
-        isolated = (i == 0 or rs[i] - rs[i - 1] > 2 * tol) and (i == n - 1 or rs[i + 1] - rs[i] > 2 * tol)
-        if isolated:
-            assert got[i]["pins"] == ref[i]["pins"] and got[i]["rf"] == ref[i]["rf"], i
-            assert got[i]["endpoint"] == ref[i]["endpoint"]
+        cands = [p for p in by_ep.get(got[i]["endpoint"], []) if abs(p["slack"] - gs[i]) <= 2 * tol]
+        assert any(p["pins"] == got[i]["pins"] and p["rf"] == got[i]["rf"] for p in cands), i
 
 
 @pytest.mark.parametrize("sched", [STA_SCHED_PERSISTENT, STA_SCHED_PER_LEVEL])
@@ -66,7 +71,7 @@ def test_paths_small_dags(seed, sched):
         for k, m, thr in [(10, 1, np.inf), (25, 3, np.inf), (500, 64, np.inf), (40, 5, 5.0)]:
             got = s.paths(k, m, thr, el)
             ref = P.top_paths(d, k, m, thr, el, r)
-            _compare(d, got, ref, r, el, thr)
+            _compare(d, got, ref, r, el, thr, k, m)
     s.close()
 
 
@@ -78,7 +83,7 @@ def test_paths_tiny_design():
     for el, k, m, thr in [(1, 200, 4, np.inf), (1, 500, 1, 0.0), (0, 100, 8, np.inf)]:
         got = s.paths(k, m, thr, el)
         ref = P.top_paths(d, k, m, thr, el, r)
-        _compare(d, got, ref, r, el, thr)
+        _compare(d, got, ref, r, el, thr, k, m)
     s.close()
 
 
@@ -89,7 +94,7 @@ def test_paths_mid_design_violators():
     s.update()
     got = s.paths(300, 2, 0.0, 1)
     ref = P.top_paths(d, 300, 2, 0.0, 1, r)
-    _compare(d, got, ref, r, 1, 0.0)
+    _compare(d, got, ref, r, 1, 0.0, 300, 2)
     s.close()
 
 
