@@ -48,27 +48,34 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str, workload: str):
-    """HBM bytes per launch from committed rocprofv3 FETCH_SIZE/WRITE_SIZE
-    counters, if they were taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+def measured_traffic(sweep: str, workload: str):
+    """HBM bytes of one sweep per update (summed over its launches) from the
+    committed rocprofv3 FETCH_SIZE/WRITE_SIZE counters, scaled by the same
+    counters on a plain device copy; None unless they were taken on the
+    current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{sweep}_{workload}.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         t = json.load(fh)
     if t.get("kernel_source_hash") != kernel_source_hash():
         return None
-    return t.get("bytes_per_launch")
+    return t.get("bytes_per_update")
 
 
-def cpu_baseline(design, n_pins: int) -> dict:
+def cpu_baseline(design, n_pins: int, runs: int = 3) -> dict:
+    """The FP64 oracle (plain C, one thread) on the whole design, median of
+    `runs` full updates."""
     import oracle
-    t0 = time.perf_counter()
-    oracle.sta(design)
-    dt = time.perf_counter() - t0
+    ts = []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        oracle.sta(design)
+        ts.append(time.perf_counter() - t0)
+    dt = sorted(ts)[len(ts) // 2]
     return {"value": n_pins / dt, "unit": "pins/s", "cores": 1, "kind": "oracle",
-            "sample": f"one full FP64 update of the same design ({n_pins} pins), single thread, "
-                      f"{dt:.2f} s"}
+            "sample": f"{runs} full FP64 updates of the same design ({n_pins} pins), single thread, "
+                      f"median {dt:.2f} s"}
 
 
 def _time_updates(ctxs, stream, steps):
