@@ -7,10 +7,11 @@ Prints ONE JSON line.  A step is one sta_update_timing over the whole design
 with every input resident in HBM.  `roofline` prices the dominant kernel's
 algorithmic bytes (each array element moved once per update) against 8 TB/s;
 `cpu_baseline` times the FP64 oracle single-threaded on the same design.
-Two side measurements ride along: `adjoint` (smooth-mode reverse pass time
-over smooth forward time on the 1M-pin design) and `batched` (256 uneven
-designs timed as one batch against the sum of the same designs timed one
-after another on one stream, each context tuned for itself).
+Three side measurements ride along: `incremental` (sta_update_timing_incremental
+after k random nets of the same design were re-capped), `adjoint` (smooth-mode
+reverse pass time over smooth forward time on the 1M-pin design) and `batched`
+(256 uneven designs timed as one batch against the sum of the same designs
+timed one after another on one stream, each context tuned for itself).
 """
 from __future__ import annotations
 
@@ -152,6 +153,42 @@ def batched_vs_per_design(steps: int, n_designs: int) -> dict:
             "batched_pins_per_s": pins / (t_batch * 1e-3)}
 
 
+def incremental_updates(design, sched: int, blocks: int, full_ms: float, sizes=(1, 100, 10000), reps: int = 3) -> dict:
+    """sta_update_timing_incremental after the caps of k random nets changed
+    (x1.5 or /1.5 on every node of each), median of `reps` calls per k, timed
+    with events around the call (its host work included)."""
+    import numpy as np
+    import torch
+    from paper_2511_11660_amd.sta import STA
+    s = STA(design, sched=sched, sweep_blocks=blocks, device=0)
+    stream = torch.cuda.current_stream()
+    caps = design.cap_ff.astype(np.float32).copy()
+    nnp = np.asarray(design.net_node_ptr)
+    rng = np.random.default_rng(11)
+    s.update(stream)
+    s.update_incremental(np.zeros(0, np.int32), stream)  # allocations of the first call
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    out = {"workload": "10M-pin design, k random nets re-capped", "full_ms": full_ms, "ms": {}}
+    for k in sizes:
+        ts = []
+        for rep in range(reps):
+            nets = rng.choice(design.n_nets, k, replace=False).astype(np.int32)
+            f = np.float32(1.5 if rep % 2 == 0 else 1 / 1.5)
+            for n in nets:
+                caps[nnp[n]:nnp[n + 1]] *= f
+            s.set_wire_caps(caps, stream)
+            torch.cuda.synchronize()
+            ev0.record(stream)
+            s.update_incremental(nets, stream)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            ts.append(ev0.elapsed_time(ev1))
+        out["ms"][str(k)] = sorted(ts)[len(ts) // 2]
+    s.close()
+    return out
+
+
 _SCHED_NAMES = {0: "persistent", 1: "per-level", 2: "graph"}
 
 
@@ -283,6 +320,8 @@ def main() -> int:
         "tns_ps": [float(x) for x in wns_tns["tns"]],
     }
     if not args.no_side:
+        print("[bench] incremental updates", file=sys.stderr, flush=True)
+        out["incremental"] = incremental_updates(design, sched, s_blocks, ms)
         print("[bench] adjoint ratio (1M-pin smooth)", file=sys.stderr, flush=True)
         out["adjoint"] = adjoint_ratio(args.steps)
         print("[bench] batched vs per-design", file=sys.stderr, flush=True)

@@ -187,15 +187,20 @@ sta_status sta_update_timing(sta_ctx *ctx, void *stream);
  * sta_update_timing would give.  A net whose caps changed but is not listed
  * leaves stale results (not detected).
  *
- *   nets [n_nets]   caller net ids (duplicates allowed), in `mem` memory; a
- *                   device list is copied to the host first (synchronizes
- *                   `stream`); n_nets = 0 recomputes nothing but the reports
+ *   nets [n_nets]   caller net ids (duplicates allowed), in `mem` memory.  A
+ *                   host list may be reused when the call returns.  A device
+ *                   list is read back to check the ids (synchronizes
+ *                   `stream`) and then read again by the device, so it must
+ *                   stay unchanged until `stream` has passed the call.
+ *                   n_nets = 0 recomputes nothing but the reports.
  *
  * Errors: STA_E_STATE (NULL context, or no full update yet), STA_E_ARG (bad
- * list or id), STA_E_UNSUPPORTED (batched context).  Without cooperative
- * launch support the call runs a full update.  Allocates device queues and
- * pinned staging (about 4 bytes per driver, chunk and RC chunk) on first use;
- * asynchronous on `stream` otherwise. */
+ * list or id; nothing is enqueued), STA_E_UNSUPPORTED (batched context).
+ * Allocates device queues and flags (about 4 bytes per driver, sink, chunk
+ * and RC chunk) and pinned staging for the list on first use (the staging
+ * grows with the longest list).  The call waits for the device twice (where
+ * a small-cone sweep hands over to per-level launches); the rest is
+ * asynchronous on `stream`. */
 sta_status sta_update_timing_incremental(sta_ctx *ctx, const int32_t *nets, int32_t n_nets, sta_mem mem,
                                          void *stream);
 

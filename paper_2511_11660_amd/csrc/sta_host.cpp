@@ -124,6 +124,7 @@ struct sta_ctx {
   void *sort_temp = nullptr;
   size_t sort_bytes = 0;
   std::vector<int4> ph_fwd, ph_bwd, ph_adj;  // sweep phases (kind, first item, count, level)
+  std::vector<int2> lvl_reg;           // per level: first slot, end of the slots in regular chunks
   int n_pieces = 0;
   hipEvent_t ev[10]{};  // 0..6 update phases, 7..9 adjoint phases
   hipStream_t cap_stream = nullptr;   // graph schedule: capture stream
@@ -142,24 +143,19 @@ struct sta_ctx {
   double *b_partials = nullptr, *b_out = nullptr;
   uint64_t *keys64 = nullptr, *keys64_out = nullptr;
   int key_bits = 32;
-  // incremental update: host maps from the layout; device queues made on first use
-  std::vector<int32_t> h_net_slot;     // net -> driver slot
-  std::vector<int32_t> h_rc_pos;       // slot -> RC position of a small net, or -1 - wide-net index
-  std::vector<int32_t> h_rc_chunk;     // RC position -> RC chunk
-  std::vector<int2> h_rc_chunks;
-  std::vector<BigNet> h_big;
+  // incremental update: maps from the layout; device queues made on first use
   int32_t *inc_chunk_of = nullptr;     // [n_drv]
   int2 *inc_chunk_ph = nullptr;        // [n_chunks]
+  int32_t *inc_slot_rc = nullptr;      // [n_drv] RC chunk of the slot's net, or -1 - wide-net index
   bool inc_ready = false;
   IncArgs inc{};
   uint32_t *inc_buf = nullptr;         // flags, queue lengths, recomputed-net bytes (cleared per update)
-  int inc_words = 0, inc_grid = 0;
-  int32_t *inc_slots = nullptr;        // [n_drv] seeded driver slots
-  int2 *inc_rc = nullptr, *inc_blk = nullptr;  // RC chunks and wide-net blocks to recompute
-  int32_t *inc_host = nullptr;         // pinned staging of the three lists
+  int inc_words = 0, inc_grid = 0, inc_max_items = 0;
+  int32_t *inc_stop = nullptr;         // pinned readback of the queued sweeps' stop phases
+  int32_t *inc_nets = nullptr;         // device copy of the caller's net list
+  int32_t *inc_host = nullptr;         // pinned staging of the list
+  int inc_cap = 0;                     // capacity of both (ids)
   hipEvent_t inc_ev = nullptr;         // staging reusable once this has passed
-  std::vector<int32_t> inc_ids, inc_rs;
-  std::vector<uint8_t> inc_seen_slot, inc_seen_rc;
 
   template <class T>
   sta_status alloc(T **out_p, size_t n) {
@@ -188,6 +184,7 @@ struct sta_ctx {
     if (ev_join) (void)hipEventDestroy(ev_join);
     if (inc_ev) (void)hipEventDestroy(inc_ev);
     if (inc_host) (void)hipHostFree(inc_host);
+    if (inc_stop) (void)hipHostFree(inc_stop);
   }
 };
 
@@ -529,6 +526,19 @@ static sta_status build_layout(sta_ctx *C, const Inputs &I, const std::vector<in
     drv_pin.resize(NPI + NC);
     for (int p = 0; p < NP; ++p)
       if (I.pin_kind[p] == STA_PIN_CELL_OUT) drv_pin[fill[cell_level[I.cell_of_pin[p]]]++] = p;
+  }
+  // within a level, drivers with more than kSplitSinks sinks go last: the
+  // other chunks of the level are then runs of kChunk slots from the level's
+  // first slot, which a per-level kernel computes from its block index
+  const auto fanout_of = [&](int p) {
+    const int n = I.net_of_drv[p];
+    return n < 0 ? 0 : I.net_sink_ptr[n + 1] - I.net_sink_ptr[n];
+  };
+  C->lvl_reg.assign(L + 1, make_int2(0, 0));
+  for (int l = 0; l <= L; ++l) {
+    auto b = drv_pin.begin() + lvl_ptr[l], e = drv_pin.begin() + lvl_ptr[l + 1];
+    auto mid = std::stable_partition(b, e, [&](int p) { return fanout_of(p) <= kSplitSinks; });
+    C->lvl_reg[l] = make_int2(lvl_ptr[l], lvl_ptr[l] + (int)(mid - b));
   }
   const int ND = NPI + NC;
   C->n_drv = ND;
@@ -948,15 +958,11 @@ static sta_status build_layout(sta_ctx *C, const Inputs &I, const std::vector<in
       for (int c = lvl_cbeg[l]; c < lvl_cbeg[l + 1]; ++c) chunk_ph[c] = make_int2(fph[l], bph[l]);
     STA_TRY(C->upload(&C->inc_chunk_of, chunk_of));
     STA_TRY(C->upload(&C->inc_chunk_ph, chunk_ph));
-    C->h_net_slot = net_slot;
-    C->h_rc_pos.assign(ND, 0);
-    for (size_t j = 0; j < rc_order.size(); ++j) C->h_rc_pos[rc_order[j]] = (int32_t)j;
-    for (size_t i = 0; i < big.size(); ++i) C->h_rc_pos[big[i].x] = -1 - (int32_t)i;
-    C->h_rc_chunk.assign(rc_order.size(), 0);
+    std::vector<int32_t> slot_rc(ND, 0);
     for (size_t r = 0; r < rc_chunks.size(); ++r)
-      for (int j = rc_chunks[r].x; j < rc_chunks[r].y; ++j) C->h_rc_chunk[j] = (int32_t)r;
-    C->h_rc_chunks = rc_chunks;
-    C->h_big = big;
+      for (int j = rc_chunks[r].x; j < rc_chunks[r].y; ++j) slot_rc[rc_order[j]] = (int32_t)r;
+    for (size_t i = 0; i < big.size(); ++i) slot_rc[big[i].x] = -1 - (int32_t)i;
+    STA_TRY(C->upload(&C->inc_slot_rc, slot_rc));
   }
   {
     // one launched block per (wide net, segment); per-net barrier counters
@@ -1379,7 +1385,7 @@ static sta_status enqueue_update(sta_ctx *C, hipStream_t s, bool prof) {
   if (!per_level) {
     HIP_TRY(launch_forward(D, C->sweep_grid, C->coop, s));
   } else {
-    for (const int4 &ph : C->ph_fwd) HIP_TRY(launch_forward_phase(D, ph, s));
+    for (const int4 &ph : C->ph_fwd) HIP_TRY(launch_forward_phase(D, ph, C->lvl_reg[ph.w], s));
   }
   if (prof) HIP_TRY(hipEventRecord(C->ev[3], s));
   if (!smooth) {  // the smooth objective needs arrivals only; it skips the RAT sweep
@@ -1438,11 +1444,21 @@ extern "C" sta_status sta_update_timing(sta_ctx *C, void *stream) {
   return STA_OK;
 }
 
+// The phase where a queued incremental sweep stopped (waits for it).
+static sta_status read_stop(sta_ctx *C, int which, int *stop, hipStream_t s) {
+  HIP_TRY(hipMemcpyAsync(C->inc_stop + which, C->inc.stop + which, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  *stop = C->inc_stop[which];
+  return STA_OK;
+}
+
 // Device queues and staging of the incremental update, made on first use.
 static sta_status inc_prepare(sta_ctx *C) {
   if (C->inc_ready) return STA_OK;
   const int n_ph = (int)(C->ph_fwd.size() + C->ph_bwd.size());
-  const int64_t words = 2 * (int64_t)C->n_chunks + n_ph + ((int64_t)C->n_drv + 3) / 4;
+  const int64_t n_big = std::max(C->n_big, 1);
+  const int64_t words =
+      2 * (int64_t)C->n_chunks + n_ph + ((int64_t)C->n_drv + 3) / 4 + 2 + C->n_rc_chunks + n_big;
   if (words >= INT32_MAX) return fail(STA_E_UNSUPPORTED, "design too large for the incremental queues");
   STA_TRY(C->alloc(&C->inc_buf, (size_t)words));
   C->inc_words = (int)words;
@@ -1450,26 +1466,36 @@ static sta_status inc_prepare(sta_ctx *C) {
   I.flag = C->inc_buf;
   I.cnt = I.flag + 2 * (size_t)C->n_chunks;
   I.rcd = reinterpret_cast<uint8_t *>(I.cnt + n_ph);
+  I.stop = reinterpret_cast<int32_t *>(C->inc_buf + words - 2 - C->n_rc_chunks - n_big);
+  I.rc_flag = C->inc_buf + words - C->n_rc_chunks - n_big;
+  I.wide_flag = I.rc_flag + C->n_rc_chunks;
+  I.net_slot = C->net_slot;
+  I.slot_rc = C->inc_slot_rc;
   STA_TRY(C->alloc(&I.wl_c, 2 * (size_t)C->n_chunks));
   STA_TRY(C->alloc(&I.wl_p, 2 * (size_t)std::max(C->n_pieces, 1)));
   I.chunk_of = C->inc_chunk_of;
   I.chunk_ph = C->inc_chunk_ph;
+  int32_t *scc;
+  int4 *fcc = nullptr;
+  STA_TRY(C->alloc(&scc, (size_t)std::max(C->n_sinks, 1)));
+  if (C->D.fanin4) STA_TRY(C->alloc(&fcc, (size_t)C->n_drv));
+  HIP_TRY(launch_inc_maps(C->D, C->inc_chunk_of, scc, fcc, nullptr));
+  HIP_TRY(hipDeviceSynchronize());
+  I.sink_cc = scc;
+  I.fanin_cc = fcc;
   I.n_chunks = C->n_chunks;
   I.n_pieces = C->n_pieces;
-  STA_TRY(C->alloc(&C->inc_slots, (size_t)C->n_drv));
-  STA_TRY(C->alloc(&C->inc_rc, (size_t)std::max(C->n_rc_chunks, 1)));
-  STA_TRY(C->alloc(&C->inc_blk, (size_t)std::max(C->wide.n_blk, 1)));
-  const size_t stage = (size_t)C->n_drv + 2 * (size_t)C->n_rc_chunks + 2 * (size_t)C->wide.n_blk + 1;
-  HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&C->inc_host), stage * sizeof(int32_t), hipHostMallocDefault));
   HIP_TRY(hipEventCreateWithFlags(&C->inc_ev, hipEventDisableTiming));
-  // one block per compute unit (fewer blocks make the per-phase wait
-  // cheaper; a small cone has little work per phase), within the
-  // cooperative limit; sweep_blocks overrides
+  HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&C->inc_stop), 2 * sizeof(int32_t), hipHostMallocDefault));
+  // queued sweeps: few blocks (the per-phase wait is cheaper with fewer
+  // pollers, and a small cone has little work per phase), within the
+  // cooperative limit; sweep_blocks overrides.  They hand over to per-phase
+  // launches at the first phase with more than kIncMaxItems items: a non-empty
+  // phase costs about as much either way, an empty one far less queued.
   const int per_cu = inc_blocks_per_cu(sweep_lds_bytes(C->D));
   const int cap = per_cu * std::max(C->n_cu, 1);
-  C->inc_grid = C->opt.sweep_blocks > 0 ? std::min(C->opt.sweep_blocks, cap) : std::min(std::max(C->n_cu, 1), cap);
-  C->inc_seen_slot.assign(C->n_drv, 0);
-  C->inc_seen_rc.assign(C->n_rc_chunks, 0);
+  C->inc_grid = !C->coop ? 0 : C->opt.sweep_blocks > 0 ? std::min(C->opt.sweep_blocks, cap) : std::min(kIncBlocks, cap);
+  C->inc_max_items = kIncMaxItems;
   C->inc_ready = true;
   return STA_OK;
 }
@@ -1484,65 +1510,59 @@ extern "C" sta_status sta_update_timing_incremental(sta_ctx *C, const int32_t *n
   if (!C->updated) return fail(STA_E_STATE, "incremental update before a full sta_update_timing");
   HIP_TRY(hipSetDevice(C->device));
   hipStream_t s = static_cast<hipStream_t>(stream);
-  std::vector<int32_t> &ids = C->inc_ids;
-  ids.resize((size_t)n_nets);
-  if (n_nets > 0) {
-    if (mem == STA_DEVICE) {
-      HIP_TRY(hipMemcpyAsync(ids.data(), nets, (size_t)n_nets * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-      HIP_TRY(hipStreamSynchronize(s));
-    } else {
-      std::memcpy(ids.data(), nets, (size_t)n_nets * sizeof(int32_t));
-    }
+  STA_TRY(inc_prepare(C));
+  HIP_TRY(hipEventSynchronize(C->inc_ev));  // the staging buffer's previous upload has been read
+  if (n_nets > C->inc_cap) {  // grows geometrically; the old device buffer stays with the context
+    const int cap = std::max(n_nets, 2 * C->inc_cap);
+    if (C->inc_host) HIP_TRY(hipHostFree(C->inc_host));
+    C->inc_host = nullptr;
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&C->inc_host), (size_t)cap * sizeof(int32_t),
+                          hipHostMallocDefault));
+    STA_TRY(C->alloc(&C->inc_nets, (size_t)cap));
+    C->inc_cap = cap;
+  }
+  // ids are checked on the host (a device list is read back first); the
+  // device then takes the list as it is (a device list in place)
+  const int32_t *h = nets;
+  if (mem == STA_DEVICE && n_nets > 0) {
+    HIP_TRY(hipMemcpyAsync(C->inc_host, nets, (size_t)n_nets * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    h = C->inc_host;
   }
   for (int32_t i = 0; i < n_nets; ++i)
-    if (ids[i] < 0 || ids[i] >= C->n_nets) return fail(STA_E_ARG, "nets[%d] = %d out of range", i, ids[i]);
-  if (!C->coop) return sta_update_timing(C, stream);  // no resident-grid launch: a full update, same result
-  STA_TRY(inc_prepare(C));
-  HIP_TRY(hipEventSynchronize(C->inc_ev));  // the staging buffer's previous uploads have been read
-  // distinct driver slots; the RC chunks and wide-net blocks that recompute them
-  int32_t *h_slots = C->inc_host;
-  int2 *h_rc = reinterpret_cast<int2 *>(h_slots + C->n_drv);
-  int2 *h_blk = h_rc + C->n_rc_chunks;
-  int ns = 0, nr = 0, nb = 0;
-  std::vector<int32_t> &rs = C->inc_rs;
-  rs.clear();
-  for (int32_t n : ids) {
-    const int x = C->h_net_slot[n];
-    if (C->inc_seen_slot[x]) continue;
-    C->inc_seen_slot[x] = 1;
-    h_slots[ns++] = x;
-    const int j = C->h_rc_pos[x];
-    if (j >= 0) {
-      const int r = C->h_rc_chunk[j];
-      if (!C->inc_seen_rc[r]) {
-        C->inc_seen_rc[r] = 1;
-        rs.push_back(r);
-        h_rc[nr++] = C->h_rc_chunks[r];
-      }
-    } else {
-      const int i = -1 - j;
-      for (int b = 0; b < C->h_big[i].nblk; ++b) h_blk[nb++] = make_int2(i, b);
-    }
+    if (h[i] < 0 || h[i] >= C->n_nets) return fail(STA_E_ARG, "nets[%d] = %d out of range", i, h[i]);
+  const int32_t *d_nets = nets;
+  if (mem == STA_HOST && n_nets > 0) {
+    std::memcpy(C->inc_host, nets, (size_t)n_nets * sizeof(int32_t));
+    HIP_TRY(hipMemcpyAsync(C->inc_nets, C->inc_host, (size_t)n_nets * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipEventRecord(C->inc_ev, s));
+    d_nets = C->inc_nets;
   }
-  for (int i = 0; i < ns; ++i) C->inc_seen_slot[h_slots[i]] = 0;
-  for (int32_t r : rs) C->inc_seen_rc[r] = 0;
   const DevDesign &D = C->D;
   HIP_TRY(launch_reset_counters(C->inc_buf, C->inc_words, s));
   HIP_TRY(launch_reset_counters(D.counters, n_counters(D.n_ph_fwd + D.n_ph_bwd), s));
-  if (ns > 0) HIP_TRY(hipMemcpyAsync(C->inc_slots, h_slots, (size_t)ns * sizeof(int32_t), hipMemcpyHostToDevice, s));
-  if (nr > 0) HIP_TRY(hipMemcpyAsync(C->inc_rc, h_rc, (size_t)nr * sizeof(int2), hipMemcpyHostToDevice, s));
-  if (nb > 0) HIP_TRY(hipMemcpyAsync(C->inc_blk, h_blk, (size_t)nb * sizeof(int2), hipMemcpyHostToDevice, s));
-  HIP_TRY(hipEventRecord(C->inc_ev, s));
-  HIP_TRY(launch_inc_seed(D, C->inc, C->inc_slots, ns, s));
-  if (nr > 0) HIP_TRY(launch_rc(D, C->inc_rc, nr, s));
-  if (nb > 0) {
-    WideNets W = C->wide;
-    W.blk = C->inc_blk;
-    W.n_blk = nb;
-    HIP_TRY(launch_rc_wide(D, W, s));
+  HIP_TRY(launch_inc_seed(D, C->inc, d_nets, n_nets, s));
+  // the RC chunks and wide nets holding a listed net (the others return at once)
+  if (C->n_rc_chunks > 0) HIP_TRY(launch_rc(D, C->rc_chunks, C->n_rc_chunks, s, C->inc.rc_flag));
+  if (C->n_big > 0) HIP_TRY(launch_rc_wide(D, C->wide, s, C->inc.wide_flag));
+  // queued forward sweep while the cone is small, then per-phase launches
+  int stop = 0;
+  if (C->inc_grid > 0) {
+    HIP_TRY(launch_inc_queues(D, C->inc, false, s));
+    HIP_TRY(launch_inc_forward(D, C->inc, C->inc_grid, C->inc_max_items, s));
+    STA_TRY(read_stop(C, 0, &stop, s));
   }
-  HIP_TRY(launch_inc_forward(D, C->inc, C->inc_grid, s));
-  if (C->opt.mode != 1) HIP_TRY(launch_inc_backward(D, C->inc, C->inc_grid, s));
+  for (int k = stop; k < (int)C->ph_fwd.size(); ++k)
+    HIP_TRY(launch_inc_forward_phase(D, C->inc, C->ph_fwd[k], C->lvl_reg[C->ph_fwd[k].w], s));
+  if (C->opt.mode != 1) {
+    stop = 0;
+    if (C->inc_grid > 0) {
+      HIP_TRY(launch_inc_queues(D, C->inc, true, s));
+      HIP_TRY(launch_inc_backward(D, C->inc, C->inc_grid, C->inc_max_items, s));
+      STA_TRY(read_stop(C, 1, &stop, s));
+    }
+    for (int k = stop; k < (int)C->ph_bwd.size(); ++k) HIP_TRY(launch_inc_backward_phase(D, C->inc, C->ph_bwd[k], s));
+  }
   STA_TRY(enqueue_reduce(C, s));
   STA_TRY(enqueue_sort(C, s));
   C->timed = false;
@@ -1562,12 +1582,8 @@ extern "C" sta_status sta_backward(sta_ctx *C, float g_tns, float g_wns, float *
   const bool prof = C->opt.profile != 0;
   const DevDesign &D = C->D;
   if (prof) HIP_TRY(hipEventRecord(C->ev[7], s));
-  HIP_TRY(launch_reset_counters(D.counters, n_counters(D.n_ph_fwd + D.n_ph_bwd), s));
-  if (C->opt.sched == STA_SCHED_PERSISTENT) {
-    HIP_TRY(launch_adjoint(D, g_tns, g_wns, C->sweep_grid, C->coop, s));
-  } else {
-    for (const int4 &ph : C->ph_adj) HIP_TRY(launch_adjoint_phase(D, g_tns, g_wns, ph, s));
-  }
+  // the reverse sweep runs one launch per level in every schedule
+  for (const int4 &ph : C->ph_adj) HIP_TRY(launch_adjoint_phase(D, g_tns, g_wns, ph, s));
   if (prof) HIP_TRY(hipEventRecord(C->ev[8], s));
   STA_TRY(enqueue_rc(C, s, true));
   if (prof) HIP_TRY(hipEventRecord(C->ev[9], s));

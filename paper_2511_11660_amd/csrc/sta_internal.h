@@ -169,34 +169,51 @@ struct WideNets {
 };
 
 // incremental update: per-sweep queues of the chunks and pieces to recompute
+constexpr int kIncBlocks = 64;    // default grid of the queued sweeps
+constexpr int kIncMaxItems = 16;  // a queued sweep hands over at the first phase with more items
 struct IncArgs {
   uint32_t *flag;            // [2 n_chunks] queued for the forward / backward sweep
   uint32_t *cnt;             // [n_ph_fwd + n_ph_bwd] queue length of each phase
   int32_t *wl_c;             // [2 n_chunks] queued chunks, each phase's at its first chunk id
   int32_t *wl_p;             // [2 n_pieces] queued pieces, likewise
   const int32_t *chunk_of;   // [n_drv] chunk of each driver slot
+  const int32_t *sink_cc;    // [n_sinks] chunk of the sink's consumer, -1 at an endpoint
+  const int4 *fanin_cc;      // [n_drv] chunks of the cell's inline input sinks' drivers; NULL without inline fanins
   const int2 *chunk_ph;      // [n_chunks] (forward phase, backward phase index) of each chunk
   uint8_t *rcd;              // [n_drv] 1: the driver's net was recomputed
+  uint32_t *rc_flag;         // [n_rc_chunks] 1: the RC chunk holds a changed net
+  uint32_t *wide_flag;       // [n_big] 1: the wide net changed
+  const int32_t *net_slot;   // [n_nets] caller net id -> driver slot
+  const int32_t *slot_rc;    // [n_drv] RC chunk of the slot's net, or -1 - wide-net index
+  int32_t *stop;             // [2] phase where the queued forward / backward sweep stopped
   int n_chunks, n_pieces;
 };
-hipError_t launch_inc_seed(const DevDesign &D, const IncArgs &I, const int32_t *slots, int n, hipStream_t s);
-hipError_t launch_inc_forward(const DevDesign &D, const IncArgs &I, int grid, hipStream_t s);
-hipError_t launch_inc_backward(const DevDesign &D, const IncArgs &I, int grid, hipStream_t s);
+hipError_t launch_inc_maps(const DevDesign &D, const int32_t *chunk_of, int32_t *sink_cc, int4 *fanin_cc,
+                           hipStream_t s);
+hipError_t launch_inc_seed(const DevDesign &D, const IncArgs &I, const int32_t *nets, int n, hipStream_t s);
+// queued sweeps: stop (and record the phase) at the first phase with more than max_items items
+hipError_t launch_inc_forward(const DevDesign &D, const IncArgs &I, int grid, int max_items, hipStream_t s);
+hipError_t launch_inc_backward(const DevDesign &D, const IncArgs &I, int grid, int max_items, hipStream_t s);
+hipError_t launch_inc_queues(const DevDesign &D, const IncArgs &I, bool backward, hipStream_t s);
+// flagged per-phase continuation (one launch per phase; unflagged chunks return at once)
+hipError_t launch_inc_forward_phase(const DevDesign &D, const IncArgs &I, int4 phase, int2 reg, hipStream_t s);
+hipError_t launch_inc_backward_phase(const DevDesign &D, const IncArgs &I, int4 phase, hipStream_t s);
 int inc_blocks_per_cu(size_t lds_bytes);
-hipError_t launch_rc(const DevDesign &D, const int2 *chunks, int n_chunks, hipStream_t s);
-hipError_t launch_rc_wide(const DevDesign &D, const WideNets &W, hipStream_t s);
+// only: optional per-chunk / per-wide-net flags, unflagged ones skipped
+hipError_t launch_rc(const DevDesign &D, const int2 *chunks, int n_chunks, hipStream_t s,
+                     const uint32_t *only = nullptr);
+hipError_t launch_rc_wide(const DevDesign &D, const WideNets &W, hipStream_t s, const uint32_t *only = nullptr);
 hipError_t launch_rc_adjoint_wide(const DevDesign &D, const WideNets &W, hipStream_t s);
 // Persistent sweeps: with coop, the level-major static schedule on a
 // cooperative (co-resident) grid; otherwise the ticket schedule.
 hipError_t launch_forward(const DevDesign &D, int persistent_grid, bool coop, hipStream_t s);
-hipError_t launch_forward_phase(const DevDesign &D, int4 phase, hipStream_t s);
+// reg: the level's first slot and the end of its slots in regular (kChunk-slot) chunks
+hipError_t launch_forward_phase(const DevDesign &D, int4 phase, int2 reg, hipStream_t s);
 hipError_t launch_backward(const DevDesign &D, int persistent_grid, bool coop, hipStream_t s);
 hipError_t launch_backward_phase(const DevDesign &D, int4 phase, hipStream_t s);
 hipError_t launch_reset_counters(uint32_t *counters, int n, hipStream_t s);
 hipError_t launch_reduce_smooth(const DevDesign &D, double *partials, double *out, uint32_t *keys,
                                 int32_t *vals, hipStream_t s);
-hipError_t launch_adjoint(const DevDesign &D, float g_tns, float g_wns, int persistent_grid, bool coop,
-                          hipStream_t s);
 hipError_t launch_adjoint_phase(const DevDesign &D, float g_tns, float g_wns, int4 phase, hipStream_t s);
 hipError_t launch_rc_adjoint(const DevDesign &D, const int2 *chunks, int n_chunks, hipStream_t s);
 hipError_t launch_scatter_grads(const DevDesign &D, const int32_t *node_src, int64_t n_nodes,

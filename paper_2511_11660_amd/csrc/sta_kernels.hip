@@ -31,6 +31,18 @@ __device__ __forceinline__ void wave_sync() {
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 
+// The hardware deals consecutive block ids to the 8 XCDs in turn.  For a grid
+// of 8 * ceil(n / 8) blocks this returns the item of the calling block such
+// that each XCD takes one contiguous run of items, so the cache lines a run
+// writes are filled in one L2 instead of being written back in parts by
+// several (items >= n: the block has none).
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_major(int n) {
+  const int per = (n + kXcds - 1) / kXcds;
+  return (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds);
+}
+__host__ __device__ inline int xcd_grid(int n) { return kXcds * ((n + kXcds - 1) / kXcds); }
+
 // Monotone float <-> int map for integer atomic min/max (signed compare).
 __device__ __forceinline__ int f2key(float f) {
   int k = __float_as_int(f);
@@ -54,11 +66,17 @@ struct AxisPos {
 
 // Segment = largest i with ax[i] <= X, kept in [0, n-2] (off-table points
 // extrapolate along the boundary segment); t = (X - ax[i]) / (ax[i+1] - ax[i]).
+// The axis is strictly increasing, so i is the number of interior points
+// ax[1..n-2] that are <= X: all of them are read at once (points past n-1 lie
+// inside the type's packed block and are masked), then ax[i] and the
+// reciprocal width, two dependent LDS round trips in all.
 __device__ __forceinline__ AxisPos axis_find(const float *ax, const float *rd, int n, float X) {
+  float a[kMaxAxis - 2];
+#pragma unroll
+  for (int m = 1; m < kMaxAxis - 1; ++m) a[m - 1] = ax[m];
   int i = 0;
 #pragma unroll
-  for (int m = 1; m < kMaxAxis - 1; ++m)
-    if (m <= n - 2 && ax[m] <= X) i = m;
+  for (int m = 1; m < kMaxAxis - 1; ++m) i += (m <= n - 2 && a[m - 1] <= X) ? 1 : 0;
   return {i, (X - ax[i]) * rd[i]};
 }
 
@@ -89,6 +107,21 @@ __device__ __forceinline__ float4 slack4(float4 at, float4 rat) {
 
 __device__ __forceinline__ float2 ep_slack2(float4 at, float4 rat) {
   return make_float2(fminf(at.x - rat.x, at.y - rat.y), fminf(rat.z - at.z, rat.w - at.w));
+}
+
+// Bitwise equality (an incremental update stops where a recomputed value is
+// bitwise unchanged; -0 and +0 count as different).
+__device__ __forceinline__ bool same_bits(const PinState &a, const PinState &b) {
+  return __float_as_uint(a.at.x) == __float_as_uint(b.at.x) && __float_as_uint(a.at.y) == __float_as_uint(b.at.y) &&
+         __float_as_uint(a.at.z) == __float_as_uint(b.at.z) && __float_as_uint(a.at.w) == __float_as_uint(b.at.w) &&
+         __float_as_uint(a.slew.x) == __float_as_uint(b.slew.x) &&
+         __float_as_uint(a.slew.y) == __float_as_uint(b.slew.y) &&
+         __float_as_uint(a.slew.z) == __float_as_uint(b.slew.z) && __float_as_uint(a.slew.w) == __float_as_uint(b.slew.w);
+}
+
+__device__ __forceinline__ bool same_bits4(float4 a, float4 b) {
+  return __float_as_uint(a.x) == __float_as_uint(b.x) && __float_as_uint(a.y) == __float_as_uint(b.y) &&
+         __float_as_uint(a.z) == __float_as_uint(b.z) && __float_as_uint(a.w) == __float_as_uint(b.w);
 }
 
 // Accesses to values that one wave writes and another wave of the same
@@ -415,18 +448,72 @@ __device__ __forceinline__ void merge_view(const DevDesign &D, const CellCtx &cc
   }
 }
 
-__global__ __launch_bounds__(kSweepBlock) void k_forward(DevDesign D, int c0, int c1) {
+// merge_view without divergent branches, for the inline-fanin path where all
+// four lanes of a driver run every fanin slot together (an empty slot is
+// masked by valid).  The two lanes of one early/late half share their x-axis
+// searches: lane (el, ro) searches the input slew of transition ri = ro and
+// takes the other transition's search from its neighbour.  Candidates,
+// comparisons and the log-sum-exp updates are merge_view's, in its order, so
+// the results are the same bits.
+__device__ __forceinline__ void merge_view_pair(const DevDesign &D, const CellCtx &cc, int el, int ro,
+                                                const float ia[2], const float is[2], bool valid, int pos,
+                                                float &at, float &sl, int &cr, float &lse) {
+  const TabLayout lay{D.nx, D.ny};
+  const float g = D.gamma;
+  const AxisPos mine = axis_find(cc.tb + lay.xa(), cc.tb + lay.rdx(), D.nx, is[ro]);
+  AxisPos other;
+  other.i = __shfl_xor(mine.i, 1);
+  other.t = __shfl_xor(mine.t, 1);
+#pragma unroll
+  for (int ri = 0; ri < 2; ++ri) {
+    const AxisPos px = ri == ro ? mine : other;
+    const bool m = valid && arc_maps(cc.sense, ri, ro);
+    const float dl = bilerp(cc.tb + lay.tab(ro), D.ny, px, cc.py);
+    const float os = bilerp(cc.tb + lay.tab(2 + ro), D.ny, px, cc.py);
+    const float cand = ia[ri] + dl;
+    const bool better = m && (el ? cand > at : cand < at);
+    if (g > 0.0f) {
+      const float up = lse * expf((at - cand) / g) + 1.0f;
+      const float add = lse + expf((cand - at) / g);
+      if (el && m) lse = better ? up : add;
+    }
+    at = better ? cand : at;
+    cr = better ? pos * 2 + ri : cr;
+    if (m) sl = el ? fmaxf(sl, os) : fminf(sl, os);
+  }
+}
+
+// With kInc (incremental continuation, IncArgs valid) an unflagged chunk
+// returns at once; a flagged one compares its results bitwise with the stored
+// ones, rewrites the sinks only of drivers that changed or whose net was
+// recomputed, and flags the consumers of changed sinks and itself for the
+// backward sweep.
+template <bool kInc>
+__global__ __launch_bounds__(kSweepBlock) void k_forward(DevDesign D, int c0, int xb, int xr, IncArgs I) {
   extern __shared__ __align__(32) unsigned char smem[];
   static_assert(kSweepBlock == 4 * kChunk, "one thread per driver view");
   const int c = c0 + blockIdx.x;
+  // (incremental: the chunk's flag is requested with the first loads and
+  // tested before the input gathers and the library staging)
+  uint32_t flagged = 1u;
+  if constexpr (kInc) flagged = I.flag[c];
   const int tid = threadIdx.x, dv = tid >> 2, v = tid & 3, el = v >> 1, ro = v & 1;
-  const int4 cr4 = D.chunk_rec[c];
-  const int x0 = __builtin_amdgcn_readfirstlane(cr4.x), x1 = __builtin_amdgcn_readfirstlane(cr4.y);
-  const int s0 = __builtin_amdgcn_readfirstlane(cr4.z), s1 = __builtin_amdgcn_readfirstlane(cr4.w);
-  const int smax = max(s1 - 1, 0);
-  const int sA = min(s0 + tid, smax);
-  const int dA = D.sink_drv[sA];
-  const float2 wA = D.dq[sA];
+  // regular chunks are the level's runs of kChunk slots from xb (no record
+  // load on the path to the fanin gathers); a high-fanout driver's own chunk
+  // comes after them and is read from its record
+  int x0, x1, s0, s1;
+  if ((int)blockIdx.x * kChunk < xr - xb) {
+    x0 = xb + (int)blockIdx.x * kChunk;
+    x1 = min(x0 + kChunk, xr);
+    s0 = __builtin_amdgcn_readfirstlane(D.sink_ptr[x0]);
+    s1 = __builtin_amdgcn_readfirstlane(D.sink_ptr[x1]);
+  } else {
+    const int4 cr4 = D.chunk_rec[c];
+    x0 = __builtin_amdgcn_readfirstlane(cr4.x);
+    x1 = __builtin_amdgcn_readfirstlane(cr4.y);
+    s0 = __builtin_amdgcn_readfirstlane(cr4.z);
+    s1 = __builtin_amdgcn_readfirstlane(cr4.w);
+  }
   const int x = x0 + dv;
   const bool live = x < x1;
   const int xc = live ? x : x0;
@@ -444,6 +531,9 @@ __global__ __launch_bounds__(kSweepBlock) void k_forward(DevDesign D, int c0, in
     L = D.L_net[xc];
     if (inl) f4 = D.fanin4[xc];
   }
+  if constexpr (kInc) {
+    if (__builtin_amdgcn_readfirstlane(flagged) == 0u) return;
+  }
   // input states of this view's early/late half: AT and slew of (el, rise/fall)
   const int fs[4] = {f4.x, f4.y, f4.z, f4.w};
   float2 iat[4], isl[4];
@@ -453,8 +543,23 @@ __global__ __launch_bounds__(kSweepBlock) void k_forward(DevDesign D, int c0, in
     iat[k] = *reinterpret_cast<const float2 *>(st + 2 * el);
     isl[k] = *reinterpret_cast<const float2 *>(st + 4 + 2 * el);
   }
+  const int sA = min(s0 + tid, max(s1 - 1, 0));
+  const int dA = D.sink_drv[sA];
+  const float2 wA = D.dq[sA];
+  float old_at = 0.0f, old_sl = 0.0f;
+  bool rcd = false;
+  PinState oldA{};
+  int ccA = -1;
+  if constexpr (kInc) {
+    old_at = reinterpret_cast<const float *>(D.drv_state + xc)[v];
+    old_sl = reinterpret_cast<const float *>(D.drv_state + xc)[4 + v];
+    rcd = I.rcd[xc] != 0;
+    oldA = D.sink_state[sA];
+    ccA = I.sink_cc[sA];
+  }
   const LdsLib lib = load_lib(D, smem);
   PinState *wst = reinterpret_cast<PinState *>(smem + lib_lds_bytes(D.n_types, D.tstride));
+  int *s_redo = reinterpret_cast<int *>(wst + kChunk);  // [kChunk], incremental only
   __syncthreads();
   float at_v, sl_v;
   int cr_v = -1;
@@ -469,9 +574,9 @@ __global__ __launch_bounds__(kSweepBlock) void k_forward(DevDesign D, int c0, in
     if (inl) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        if (fs[k] < 0) continue;
+        if (__ballot(fs[k] >= 0) == 0) continue;  // no lane of the wave has this input
         const float ia[2] = {iat[k].x, iat[k].y}, is[2] = {isl[k].x, isl[k].y};
-        merge_view(D, cc, el, ro, ia, is, k, at_v, sl_v, cr_v, lse);
+        merge_view_pair(D, cc, el, ro, ia, is, fs[k] >= 0, k, at_v, sl_v, cr_v, lse);
       }
     } else {
       const int f0 = D.fanin_ptr[xc], f1 = D.fanin_ptr[xc + 1];
@@ -487,31 +592,70 @@ __global__ __launch_bounds__(kSweepBlock) void k_forward(DevDesign D, int c0, in
   uint32_t cw = (uint32_t)(cr_v & 0xff) << (8 * v);
   cw |= __shfl_xor(cw, 1);
   cw |= __shfl_xor(cw, 2);
+  bool moved = true;
+  if constexpr (kInc) {
+    int ch = (__float_as_uint(at_v) != __float_as_uint(old_at) || __float_as_uint(sl_v) != __float_as_uint(old_sl));
+    ch |= __shfl_xor(ch, 1);
+    ch |= __shfl_xor(ch, 2);
+    moved = ch != 0;
+  }
   if (live) {
-    float *o = reinterpret_cast<float *>(D.drv_state + x);
-    o[v] = at_v;
-    o[4 + v] = sl_v;
+    if (moved) {
+      float *o = reinterpret_cast<float *>(D.drv_state + x);
+      o[v] = at_v;
+      o[4 + v] = sl_v;
+    }
     if (v == 0) D.drv_crit[x] = pis ? 0xffffffffu : cw;
     float *w = reinterpret_cast<float *>(wst + dv);
     w[v] = at_v;
     w[4 + v] = sl_v;
   }
-  __syncthreads();
-  auto emit = [&](int s, int drv, float2 w) {
+  if constexpr (kInc) {
+    const int redo = live && (moved || rcd);
+    if (v == 0) s_redo[dv] = redo;
+    if (__syncthreads_or(redo) == 0) return;
+    if (tid == 0) I.flag[I.n_chunks + c] = 1u;
+  } else {
+    __syncthreads();
+  }
+  // (incremental: old is the sink's stored state, cc its consumer's chunk)
+  auto emit = [&](int s, int drv, float2 w, const PinState &old, int cc) {
+    if constexpr (kInc) {
+      if (s_redo[drv - x0] == 0) return;
+    }
     const PinState ds = wst[drv - x0];
     PinState o;
     o.at = make_float4(ds.at.x + w.x, ds.at.y + w.x, ds.at.z + w.x, ds.at.w + w.x);
     o.slew = make_float4(sqrtf(ds.slew.x * ds.slew.x + w.y), sqrtf(ds.slew.y * ds.slew.y + w.y),
                          sqrtf(ds.slew.z * ds.slew.z + w.y), sqrtf(ds.slew.w * ds.slew.w + w.y));
-    D.sink_state[s] = o;
+    if constexpr (kInc) {
+      if (same_bits(o, old)) return;
+      D.sink_state[s] = o;
+      if (cc >= 0) I.flag[cc] = 1u;
+    } else {
+      D.sink_state[s] = o;
+    }
   };
-  if (s0 + tid < s1) emit(s0 + tid, dA, wA);
-  for (int s = s0 + tid + kSweepBlock; s < s1; s += kSweepBlock) emit(s, D.sink_drv[s], D.dq[s]);
+  if (s0 + tid < s1) emit(s0 + tid, dA, wA, oldA, ccA);
+  for (int s = s0 + tid + kSweepBlock; s < s1; s += kSweepBlock) {
+    if constexpr (kInc)
+      emit(s, D.sink_drv[s], D.dq[s], D.sink_state[s], I.sink_cc[s]);
+    else
+      emit(s, D.sink_drv[s], D.dq[s], oldA, ccA);
+  }
 }
 
-__global__ __launch_bounds__(kSweepBlock) void k_forward_pieces(DevDesign D, int j0, int j1) {
+__device__ void inc_fwd_piece(const DevDesign &D, const IncArgs &I, int j);
+
+template <bool kInc>
+__global__ __launch_bounds__(kSweepBlock) void k_forward_pieces(DevDesign D, int j0, int j1, IncArgs I) {
   const int j = j0 + blockIdx.x * (kSweepBlock / kWave) + threadIdx.x / kWave;
-  if (j < j1) fwd_piece<false>(D, j);
+  if (j >= j1) return;
+  if constexpr (kInc) {
+    if (I.flag[I.n_chunks + D.piece_rec[j].w] != 0u) inc_fwd_piece(D, I, j);
+  } else {
+    fwd_piece<false>(D, j);
+  }
 }
 
 // ------------------------------------------------------------ backward
@@ -679,9 +823,15 @@ __device__ void bwd_piece(const DevDesign &D, const LdsLib &lib, int j) {
 // views each), merging RAT_s - d into LDS keys; then thread 4 d + v finishes
 // view v of driver d (endpoint constraint, pieces, slacks).  Sweep-independent
 // loads are requested before the library is staged.
-__global__ __launch_bounds__(kSweepBlock) void k_backward(DevDesign D, int c0, int c1) {
+// With kInc an unflagged chunk returns at once; a flagged one compares each
+// driver's RAT bitwise with the stored one and, where it changed or the
+// driver's net was recomputed, flags the chunks of the cell's input sinks.
+template <bool kInc>
+__global__ __launch_bounds__(kSweepBlock) void k_backward(DevDesign D, int c0, int c1, IncArgs I) {
   extern __shared__ __align__(32) unsigned char smem[];
   const int c = c0 + blockIdx.x;
+  uint32_t flagged = 1u;  // (incremental: tested once the first loads are in flight)
+  if constexpr (kInc) flagged = I.flag[I.n_chunks + c];
   const int tid = threadIdx.x, el = tid & 1, dv = tid >> 2, v = tid & 3;
   const int4 cr4 = D.chunk_rec[c];
   const int x0 = __builtin_amdgcn_readfirstlane(cr4.x), x1 = __builtin_amdgcn_readfirstlane(cr4.y);
@@ -704,6 +854,15 @@ __global__ __launch_bounds__(kSweepBlock) void k_backward(DevDesign D, int c0, i
   const int e = D.drv_ep[xc];
   const float Av = reinterpret_cast<const float *>(D.drv_state + xc)[v];
   const int2 pcs = D.chunk_pieces[c];
+  float old_r = 0.0f;
+  bool rcd = false;
+  int4 fcc = make_int4(-1, -1, -1, -1);
+  if constexpr (kInc) {
+    old_r = reinterpret_cast<const float *>(&D.cons_rec[xc].rat)[v];
+    rcd = I.rcd[xc] != 0;
+    if (I.fanin_cc) fcc = I.fanin_cc[xc];
+    if (__builtin_amdgcn_readfirstlane(flagged) == 0u) return;
+  }
   const LdsLib lib = load_lib(D, smem);
   int *wacc = reinterpret_cast<int *>(smem + lib_lds_bytes(D.n_types, D.tstride));
   wacc[tid] = f2key((v >> 1) ? kInf : -kInf);
@@ -723,15 +882,17 @@ __global__ __launch_bounds__(kSweepBlock) void k_backward(DevDesign D, int c0, i
       const float *tb = lib.tab + t * D.tstride;
       const AxisPos py = axis_find(tb + lay.ya(), tb + lay.rdy(), D.ny, Lt.x);
       const float ro_[2] = {Ro.x, Ro.y}, is[2] = {sl.x, sl.y};
+      // every (ri, ro) pair evaluated, unmapped ones masked: min / max are
+      // exact, so the result does not depend on the evaluation order
 #pragma unroll
       for (int ri = 0; ri < 2; ++ri) {
         const AxisPos px = axis_find(tb + lay.xa(), tb + lay.rdx(), D.nx, is[ri]);
         float best = el ? kInf : -kInf;
 #pragma unroll
         for (int ro = 0; ro < 2; ++ro) {
-          if (!arc_maps(sense, ri, ro)) continue;
           const float cand = ro_[ro] - bilerp(tb + lay.tab(ro), D.ny, px, py);
-          best = el ? fminf(best, cand) : fmaxf(best, cand);
+          const float nb = el ? fminf(best, cand) : fmaxf(best, cand);
+          best = arc_maps(sense, ri, ro) ? nb : best;
         }
         r[ri] = best;
       }
@@ -777,14 +938,35 @@ __global__ __launch_bounds__(kSweepBlock) void k_backward(DevDesign D, int c0, i
     reinterpret_cast<float *>(D.drv_slack + x)[v] = sk;
     if (e >= 0 && (v & 1) == 0) reinterpret_cast<float *>(D.ep_slack + e)[v >> 1] = skm;
   }
+  if constexpr (kInc) {
+    int ch = __float_as_uint(R) != __float_as_uint(old_r);
+    ch |= __shfl_xor(ch, 1);
+    ch |= __shfl_xor(ch, 2);
+    if (live && v == 0 && (ch || rcd) && x >= D.n_pi) {
+      if (I.fanin_cc) {
+        const int fc[4] = {fcc.x, fcc.y, fcc.z, fcc.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          if (fc[k] >= 0) I.flag[I.n_chunks + fc[k]] = 1u;
+      } else {
+        for (int f = D.fanin_ptr[x]; f < D.fanin_ptr[x + 1]; ++f)
+          I.flag[I.n_chunks + I.chunk_of[D.sink_drv[D.fanin_sink[f]]]] = 1u;
+      }
+    }
+  }
 }
 
-__global__ __launch_bounds__(kSweepBlock) void k_backward_pieces(DevDesign D, int j0, int j1) {
+template <bool kInc>
+__global__ __launch_bounds__(kSweepBlock) void k_backward_pieces(DevDesign D, int j0, int j1, IncArgs I) {
   extern __shared__ __align__(32) unsigned char smem[];
   const LdsLib lib = load_lib(D, smem);
   __syncthreads();
   const int j = j0 + blockIdx.x * (kSweepBlock / kWave) + threadIdx.x / kWave;
-  if (j < j1) bwd_piece<false>(D, lib, j);
+  if (j >= j1) return;
+  if constexpr (kInc) {
+    if (I.flag[I.n_chunks + D.piece_rec[j].w] == 0u) return;
+  }
+  bwd_piece<false>(D, lib, j);
 }
 
 // ------------------------------------------------ persistent sweeps
@@ -803,21 +985,13 @@ __global__ __launch_bounds__(kSweepBlock) void k_backward_pieces(DevDesign D, in
 // the two regions into a lane-0-only path and the other lanes re-entered the
 // loop without a ticket.)
 
-template <bool kCoh>
-__device__ void adj_chunk(const DevDesign &D, const LdsLib &lib, float g_tns, float g_wns, int c);
-
-constexpr int kSweepFwd = 0, kSweepBwd = 1, kSweepAdj = 2;
+constexpr int kSweepFwd = 0, kSweepBwd = 1;
 
 __device__ __forceinline__ const int4 *sweep_phases(const DevDesign &D, int kind, int &n, int &ctr_base) {
   if (kind == kSweepBwd) {
     n = D.n_ph_bwd;
     ctr_base = D.n_ph_fwd;
     return D.phases + D.n_ph_fwd;
-  }
-  if (kind == kSweepAdj) {
-    n = D.n_ph_adj;
-    ctr_base = 0;  // the forward counters, cleared before the adjoint sweep
-    return D.phases + D.n_ph_fwd + D.n_ph_bwd;
   }
   n = D.n_ph_fwd;
   ctr_base = 0;
@@ -882,8 +1056,6 @@ template <>
 __device__ __forceinline__ FwdPre sweep_pre<kSweepFwd>(const DevDesign &D, int c) { return fwd_prefetch(D, c); }
 template <>
 __device__ __forceinline__ BwdPre sweep_pre<kSweepBwd>(const DevDesign &D, int c) { return bwd_prefetch(D, c); }
-template <>
-__device__ __forceinline__ int sweep_pre<kSweepAdj>(const DevDesign &, int c) { return c; }
 
 // (Dispatch is by template constant rather than lambdas: a lambda capturing
 // the by-value kernel argument D by reference forces D into scratch memory.)
@@ -892,10 +1064,8 @@ __device__ __forceinline__ void sweep_chunk(const DevDesign &D, const LdsLib &li
                                             float g_tns, float g_wns, const typename SweepPre<kKind>::type &p) {
   if constexpr (kKind == kSweepFwd) {
     fwd_finish<true>(D, lib, reinterpret_cast<PinState *>(wsm) + wave * kWave, p);
-  } else if constexpr (kKind == kSweepBwd) {
-    bwd_finish<true>(D, lib, reinterpret_cast<int *>(wsm) + wave * kWave * 4, p);
   } else {
-    adj_chunk<true>(D, lib, g_tns, g_wns, p);
+    bwd_finish<true>(D, lib, reinterpret_cast<int *>(wsm) + wave * kWave * 4, p);
   }
 }
 
@@ -998,38 +1168,31 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(DevDesign D, float g_tns,
 // ------------------------------------------------- incremental update
 //
 // After the caps of a few nets change, only their fan-out cone needs new
-// arrivals and only the fan-in cone of what changed needs new RATs.  The
-// sweeps walk the same phases as a full update, but each phase processes only
-// the items queued for it: a chunk is queued for the forward sweep when a net
-// of its drivers was recomputed (seeded) or when a sink feeding one of its
-// drivers changed value; for the backward sweep when its forward pass changed
-// a driver state, or when a consumer of one of its sinks changed its RAT or
-// load.  "Changed" is a bitwise comparison with the stored value, so a queued
-// chunk whose result is unchanged stops the cone there.  Every queued chunk is
-// recomputed with the same code as a full update, so the result is bitwise
-// the full update's.  Queueing targets a strictly later phase (a consumer is
-// at a higher level, a fan-in driver at a lower one), so a phase's queue is
-// complete once the previous phases are, and all blocks read its length after
-// waiting for the last non-empty phase.
+// arrivals and only the fan-in cone of what changed needs new RATs.  A chunk
+// is flagged for the forward sweep when a net of its drivers was recomputed
+// (seeded) or when a sink feeding one of its drivers changed value; for the
+// backward sweep when its forward pass changed a driver state (or its net was
+// recomputed), or when a consumer of one of its sinks changed its RAT or load.
+// "Changed" is a bitwise comparison with the stored value, so a flagged chunk
+// whose result is unchanged stops the cone there.  A flagged chunk is
+// recomputed with the same arithmetic as a full update, so the result is
+// bitwise the full update's.  Flags always point to a strictly later phase (a
+// consumer is at a higher level, a fan-in driver at a lower one).
+//
+// Two schedules share the flags.  While the cone is small, one cooperative
+// launch per sweep walks per-phase queues of the flagged items (queue lengths
+// are final once the previous phases are complete, so every block reads the
+// same length after waiting for the last non-empty phase).  At the first
+// phase whose queue exceeds a threshold the whole grid stops, records the
+// phase, and the host continues with one launch per remaining phase whose
+// blocks return at once for unflagged chunks.  The backward queues are built
+// from the backward flags after the forward sweep.
 
 __device__ __forceinline__ void st_coh_i32(int32_t *p, int32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ int32_t ld_coh_i32(const int32_t *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ bool same_bits(const PinState &a, const PinState &b) {
-  return __float_as_uint(a.at.x) == __float_as_uint(b.at.x) && __float_as_uint(a.at.y) == __float_as_uint(b.at.y) &&
-         __float_as_uint(a.at.z) == __float_as_uint(b.at.z) && __float_as_uint(a.at.w) == __float_as_uint(b.at.w) &&
-         __float_as_uint(a.slew.x) == __float_as_uint(b.slew.x) &&
-         __float_as_uint(a.slew.y) == __float_as_uint(b.slew.y) &&
-         __float_as_uint(a.slew.z) == __float_as_uint(b.slew.z) && __float_as_uint(a.slew.w) == __float_as_uint(b.slew.w);
-}
-
-__device__ __forceinline__ bool same_bits4(float4 a, float4 b) {
-  return __float_as_uint(a.x) == __float_as_uint(b.x) && __float_as_uint(a.y) == __float_as_uint(b.y) &&
-         __float_as_uint(a.z) == __float_as_uint(b.z) && __float_as_uint(a.w) == __float_as_uint(b.w);
 }
 
 // Queue chunk c for the forward sweep (once).
@@ -1098,7 +1261,7 @@ __device__ void inc_fwd_chunk(const DevDesign &D, const LdsLib &lib, PinState *w
   wave_sync();
   if (redo == 0) return;
   if (lane == 0) {
-    inc_queue_bwd(D, I, c);
+    I.flag[I.n_chunks + c] = 1u;  // backward queues are built from these flags
     const int2 pcs = D.chunk_pieces[c];
     if (pcs.y > 0) {  // a high-fanout driver: its remaining sinks in the pieces phase that follows
       const int k = I.chunk_ph[c].x + 1;
@@ -1119,8 +1282,8 @@ __device__ void inc_fwd_chunk(const DevDesign &D, const LdsLib &lib, PinState *w
                          sqrtf(ds.slew.z * ds.slew.z + w.y), sqrtf(ds.slew.w * ds.slew.w + w.y));
     if (same_bits(o, D.sink_state[s])) continue;
     st_state<true>(D.sink_state + s, o);
-    const int cons = D.sink_cons[s];
-    if (cons >= 0) inc_queue_fwd(D, I, I.chunk_of[cons]);
+    const int cc = I.sink_cc[s];
+    if (cc >= 0) inc_queue_fwd(D, I, cc);
   }
   wave_sync();
 }
@@ -1139,8 +1302,8 @@ __device__ void inc_fwd_piece(const DevDesign &D, const IncArgs &I, int j) {
                          sqrtf(ds.slew.z * ds.slew.z + w.y), sqrtf(ds.slew.w * ds.slew.w + w.y));
     if (same_bits(o, D.sink_state[s])) continue;
     st_state<true>(D.sink_state + s, o);
-    const int cons = D.sink_cons[s];
-    if (cons >= 0) inc_queue_fwd(D, I, I.chunk_of[cons]);
+    const int cc = I.sink_cc[s];
+    if (cc >= 0) inc_queue_fwd(D, I, cc);
   }
 }
 
@@ -1193,12 +1356,12 @@ __device__ void inc_bwd_chunk(const DevDesign &D, const LdsLib &lib, int *wacc, 
     D.drv_slack[x] = slack4(p.A, R);
     if (p.e >= 0) D.ep_slack[p.e] = ep_slack2(p.A, R);
     if ((moved || rcd) && x >= D.n_pi) {
-      if (D.fanin4) {
-        const int4 f4 = D.fanin4[x];
-        const int fs[4] = {f4.x, f4.y, f4.z, f4.w};
+      if (I.fanin_cc) {
+        const int4 f4 = I.fanin_cc[x];
+        const int fc[4] = {f4.x, f4.y, f4.z, f4.w};
 #pragma unroll
         for (int k = 0; k < 4; ++k)
-          if (fs[k] >= 0) inc_queue_bwd(D, I, I.chunk_of[D.sink_drv[fs[k]]]);
+          if (fc[k] >= 0) inc_queue_bwd(D, I, fc[k]);
       } else {
         for (int f = D.fanin_ptr[x]; f < D.fanin_ptr[x + 1]; ++f)
           inc_queue_bwd(D, I, I.chunk_of[D.sink_drv[D.fanin_sink[f]]]);
@@ -1213,7 +1376,7 @@ __device__ void inc_bwd_chunk(const DevDesign &D, const LdsLib &lib, int *wacc, 
 // the last non-empty phase has completed (all blocks are resident: cooperative
 // launch), so all blocks agree on it and every loop ends.
 template <int kKind>
-__global__ __launch_bounds__(kSweepBlock) void k_inc_sweep(DevDesign D, IncArgs I) {
+__global__ __launch_bounds__(kSweepBlock) void k_inc_sweep(DevDesign D, IncArgs I, int max_items) {
   extern __shared__ __align__(32) unsigned char smem[];
   __shared__ uint32_t s_n[2];
   constexpr int kWaves = kSweepBlock / kWave;
@@ -1239,6 +1402,10 @@ __global__ __launch_bounds__(kSweepBlock) void k_inc_sweep(DevDesign D, IncArgs 
     const int n = (int)__builtin_amdgcn_readfirstlane(s_n[k & 1]);
     wait_k = -1;  // the last non-empty phase has completed
     if (n == 0) continue;
+    if (n > max_items) {  // every block sees the same n: all stop here
+      if (blockIdx.x == 0 && threadIdx.x == 0) I.stop[kKind == kSweepBwd] = k;
+      return;
+    }
     const int4 P = ph[k];
     const int kind = __builtin_amdgcn_readfirstlane(P.x), first = __builtin_amdgcn_readfirstlane(P.y);
     int mine = 0;
@@ -1266,15 +1433,82 @@ __global__ __launch_bounds__(kSweepBlock) void k_inc_sweep(DevDesign D, IncArgs 
     wait_k = k;
     wait_n = (uint32_t)n;
   }
+  if (blockIdx.x == 0 && threadIdx.x == 0) I.stop[kKind == kSweepBwd] = n_ph;
 }
 
-// Seeds an incremental update: the drivers of the recomputed nets.
-__global__ void k_inc_seed(DevDesign D, IncArgs I, const int32_t *slots, int n) {
+// Queues from flags, one block per phase of the sweep, in ascending id order
+// and without atomics: the forward queues from the seeded forward flags (its
+// pieces phases start empty: a high-fanout driver's chunk queues its pieces
+// when it changes), the backward queues from the backward flags the forward
+// sweep left (a flagged chunk's pieces included).
+template <int kKind>
+__global__ __launch_bounds__(256) void k_inc_queues(DevDesign D, IncArgs I) {
+  __shared__ int s_cnt[256 / kWave];
+  constexpr bool kBwd = kKind == kSweepBwd;
+  const int k = (kBwd ? D.n_ph_fwd : 0) + blockIdx.x;
+  const int4 P = D.phases[k];
+  const bool pieces = P.x == kItemPiece;
+  if (!kBwd && pieces) {
+    if (threadIdx.x == 0) I.cnt[k] = 0u;
+    return;
+  }
+  const int fo = kBwd ? I.n_chunks : 0;
+  int32_t *wl = pieces ? I.wl_p + (kBwd ? I.n_pieces : 0) + P.y : I.wl_c + fo + P.y;
+  const int wave = threadIdx.x / kWave, lane = lane_id();
+  int total = 0;
+  for (int b = 0; b < P.z; b += 256) {
+    const int i = b + (int)threadIdx.x;
+    bool f = false;
+    if (i < P.z) {
+      const int owner = pieces ? D.piece_rec[P.y + i].w : P.y + i;
+      f = I.flag[fo + owner] != 0u;
+    }
+    const uint64_t m = __ballot(f);
+    if (lane == 0) s_cnt[wave] = __popcll(m);
+    __syncthreads();
+    int before = total;
+    for (int w = 0; w < wave; ++w) before += s_cnt[w];
+    if (f) wl[before + __popcll(m & ((1ull << lane) - 1))] = P.y + i;
+    for (int w = 0; w < 256 / kWave; ++w) total += s_cnt[w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) I.cnt[k] = (uint32_t)total;
+}
+
+// The flag targets of the incremental sweeps: per sink the chunk of its
+// consumer (-1 at an endpoint), per driver the chunks holding the drivers of
+// its cell's inline input sinks (-1 padded).
+__global__ void k_inc_maps(DevDesign D, const int32_t *chunk_of, int32_t *sink_cc, int4 *fanin_cc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < D.n_sinks) {
+    const int cons = D.sink_cons[i];
+    sink_cc[i] = cons >= 0 ? chunk_of[cons] : -1;
+  }
+  if (fanin_cc && i < D.n_drv) {
+    const int4 f = D.fanin4[i];
+    const int fs[4] = {f.x, f.y, f.z, f.w};
+    int o[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) o[k] = fs[k] >= 0 ? chunk_of[D.sink_drv[fs[k]]] : -1;
+    fanin_cc[i] = make_int4(o[0], o[1], o[2], o[3]);
+  }
+}
+
+// Seeds an incremental update from the caller's net ids: per net its driver
+// ("net recomputed"), the forward flag of the driver's chunk, and the flag of
+// the RC chunk or wide net that recomputes it (plain stores of 1; the queues
+// are built from the flags afterwards, without atomics).
+__global__ void k_inc_seed(DevDesign D, IncArgs I, const int32_t *nets, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const int x = slots[i];
+  const int x = I.net_slot[nets[i]];
   I.rcd[x] = 1;
-  inc_queue_fwd(D, I, I.chunk_of[x]);
+  I.flag[I.chunk_of[x]] = 1u;
+  const int r = I.slot_rc[x];
+  if (r >= 0)
+    I.rc_flag[r] = 1u;
+  else
+    I.wide_flag[-1 - r] = 1u;
 }
 
 // ------------------------------------------------------------------ RC
@@ -1283,14 +1517,19 @@ __global__ void k_inc_seed(DevDesign D, IncArgs I, const int32_t *slots, int n) 
 //   load = subtree sum of C^ (bottom-up), d = d(parent) + R load (top-down),
 //   ld = subtree sum of C^ d (bottom-up), m2 = m2(parent) + R ld (top-down).
 // On return A holds m2 and B holds d; the result is the root load.
+// On entry A holds C^ (staged); four passes, the C^ d products formed in the
+// d pass (a node's load is not read again once its d is known).
 __device__ __forceinline__ float rc_tree_lds(const uint8_t *par, const float *R, const float *C,
                                              float *A, float *B, int b, int m) {
-  for (int k = 0; k < m; ++k) A[b + k] = C[b + k];
   for (int k = m - 1; k >= 1; --k) A[b + par[b + k]] += A[b + k];
   const float load = A[b];
   B[b] = 0.0f;
-  for (int k = 1; k < m; ++k) B[b + k] = B[b + par[b + k]] + R[b + k] * A[b + k];
-  for (int k = 0; k < m; ++k) A[b + k] = C[b + k] * B[b + k];
+  A[b] = 0.0f;
+  for (int k = 1; k < m; ++k) {
+    const float d = B[b + par[b + k]] + R[b + k] * A[b + k];
+    B[b + k] = d;
+    A[b + k] = C[b + k] * d;
+  }
   for (int k = m - 1; k >= 1; --k) A[b + par[b + k]] += A[b + k];
   A[b] = 0.0f;
   for (int k = 1; k < m; ++k) A[b + k] = A[b + par[b + k]] + R[b + k] * A[b + k];
@@ -1543,9 +1782,12 @@ __device__ void rc_wide_net(const DevDesign &D, const BigNet &B, const WideNets 
 
 // Wide nets: blocks of 1024 threads, several per net (launched on a side
 // stream so they overlap the small-net kernel).
-__global__ __launch_bounds__(kWideBlock) void k_rc_wide(DevDesign D, WideNets W) {
+// only: optional per-wide-net flags; the blocks of an unflagged net return
+// together, before touching the net's barrier counters.
+__global__ __launch_bounds__(kWideBlock) void k_rc_wide(DevDesign D, WideNets W, const uint32_t *only) {
   __shared__ double s_w[kWideBlock / kWave + 1];
   const int2 nb = W.blk[blockIdx.x];
+  if (only && only[nb.x] == 0u) return;
   const BigNet &B = W.big[nb.x];
   WideCtx c = wide_ctx(B, W, nb.y, nb.x);
   rc_wide_net(D, B, W, c, s_w);
@@ -1555,7 +1797,7 @@ __global__ __launch_bounds__(kWideBlock) void k_rc_wide(DevDesign D, WideNets W)
 // C^ = C + lumped pin caps.  Each thread requests all of its (clamped,
 // unpredicated) loads before its first LDS store.
 __device__ __forceinline__ void stage_rc_nodes(const DevDesign &D, int k0, int nk, uint8_t *par, float *R,
-                                               float *C) {
+                                               float *C, float *A) {
   constexpr int kPer = kRcChunkNodes / kRcBlock;
   const int tid = threadIdx.x;
   const int last = k0 + max(nk - 1, 0);
@@ -1576,6 +1818,7 @@ __device__ __forceinline__ void stage_rc_nodes(const DevDesign &D, int k0, int n
       par[i] = p[u];
       R[i] = r[u];
       C[i] = c[u] + pc[u];
+      A[i] = C[i];
     }
   }
 }
@@ -1584,16 +1827,17 @@ __device__ __forceinline__ void stage_rc_nodes(const DevDesign &D, int k0, int n
 // consecutive in RC order): coalesced staging of parent/R/C into LDS, one net
 // per thread, each thread writing its net's load and sink moments.  Block 0
 // also clears the sweep counters for the launches that follow.
+// only: optional per-chunk flags (incremental update: unflagged chunks return).
 __global__ __launch_bounds__(kRcBlock) void k_rc(DevDesign D, const int2 *chunks, int n_chunks,
-                                                 uint32_t *counters, int n_counters) {
+                                                 uint32_t *counters, int n_counters, const uint32_t *only) {
   __shared__ uint8_t s_par[kRcChunkNodes];
   __shared__ float s_R[kRcChunkNodes], s_C[kRcChunkNodes], s_A[kRcChunkNodes], s_B[kRcChunkNodes];
   __shared__ int s_base[kRcBlock + 1];
   const int tid = threadIdx.x;
   if (blockIdx.x == 0)
     for (int i = tid; i < n_counters; i += kRcBlock) counters[i] = 0u;
-  const int ci = blockIdx.x;
-  if (ci >= n_chunks) return;
+  const int ci = xcd_major(n_chunks);
+  if (ci >= n_chunks || (only && only[ci] == 0u)) return;
   const int2 ch = chunks[ci];
   const int j0 = ch.x, j1 = ch.y;
   const int k0 = D.rc_start[j0], nk = D.rc_start[j1] - k0;
@@ -1601,8 +1845,13 @@ __global__ __launch_bounds__(kRcBlock) void k_rc(DevDesign D, const int2 *chunks
   const int jc = j < j1 ? j : j0;
   const int x = D.rc_order[jc];
   const int2 sr = D.rc_sinks[jc];
-  stage_rc_nodes(D, k0, nk, s_par, s_R, s_C);
+  stage_rc_nodes(D, k0, nk, s_par, s_R, s_C, s_A);
   for (int i = tid; i <= j1 - j0; i += kRcBlock) s_base[i] = D.rc_start[j0 + i] - k0;
+  // the first sinks' node ids, in flight across the tree passes
+  constexpr int kPre = 4;
+  int sn[kPre];
+#pragma unroll
+  for (int u = 0; u < kPre; ++u) sn[u] = D.sink_node[min(sr.x + u, max(sr.y - 1, 0))];
   __syncthreads();
   if (j < j1) {
     const int b = s_base[tid], m = s_base[tid + 1] - b;
@@ -1610,7 +1859,15 @@ __global__ __launch_bounds__(kRcBlock) void k_rc(DevDesign D, const int2 *chunks
     const float L = rc_tree_lds(s_par, s_R, s_C, s_A, s_B, b, m);
     D.L_net[x] = L;
     D.cons_rec[x].L = L;
-    for (int s = s0; s < s1; ++s) {
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) {
+      if (s0 + u < s1) {
+        const int k = b + sn[u];
+        const float d = s_B[k];
+        D.dq[s0 + u] = make_float2(d, fmaxf(0.0f, 2.0f * s_A[k] - d * d));
+      }
+    }
+    for (int s = s0 + kPre; s < s1; ++s) {
       const int k = b + D.sink_node[s];
       const float d = s_B[k];
       D.dq[s] = make_float2(d, fmaxf(0.0f, 2.0f * s_A[k] - d * d));
@@ -1835,7 +2092,6 @@ __device__ __forceinline__ float2 endpoint_seed(const DevDesign &D, float g_tns,
 // log-sum-exp arrival merge, the slew merge's subgradient to its winner, and
 // the NLDM partials.  Every input sink has this cell as its only consumer, so
 // its gradient is written here, once; nothing is accumulated atomically.
-template <bool kCoh>
 __device__ void cell_adjoint(const DevDesign &D, const LdsLib &lib, int x, const PinState &me, float gA0,
                              float gA1, float gS0, float gS1) {
   const int t = D.cell_type[x];
@@ -1899,58 +2155,85 @@ __device__ void cell_adjoint(const DevDesign &D, const LdsLib &lib, int x, const
         }
       }
     }
-    st4<kCoh>(D.g_sink + sidx, make_float4(giA[0], giA[1], giS[0], giS[1]));
+    D.g_sink[sidx] = make_float4(giA[0], giA[1], giS[0], giS[1]);
     D.g_arc[f] = make_float2(ga[0], ga[1]);
   }
   D.g_load[x] = gL;
 }
 
-// One chunk of the reverse sweep: each lane owns a driver, sums its sinks'
-// gradients in sink order (d slew_s / d slew_drv = slew_drv / slew_s), records
-// dJ/dd and dJ/dq per sink for the RC adjoint, and then pushes through its own
-// cell to the cell's input sinks.
-template <bool kCoh>
-__device__ void adj_chunk(const DevDesign &D, const LdsLib &lib, float g_tns, float g_wns, int c) {
+// Per-level reverse sweep: one block per chunk.  The chunk's sinks (all of
+// them, also those a high-fanout driver leaves to pieces in the forward
+// sweep) are taken 256 at a time, one per thread, with coalesced loads: each
+// thread forms its sink's contribution to its driver's gradient and writes
+// dJ/dd, dJ/dq; then the thread of each driver adds its sinks' contributions
+// in sink order after its own endpoint seed (a fixed order, so the gradients
+// are reproducible) and pushes through its cell.
+__global__ __launch_bounds__(kSweepBlock) void k_adjoint(DevDesign D, float g_tns, float g_wns, int c0, int c1) {
+  extern __shared__ __align__(32) unsigned char smem[];
+  const int c = c0 + blockIdx.x;
+  const int tid = threadIdx.x;
   const int4 cr = D.chunk_rec[c];
-  const int x = cr.x + lane_id();
-  if (x >= cr.y) return;
-  const PinState me = D.drv_state[x];
+  const int x0 = __builtin_amdgcn_readfirstlane(cr.x), x1 = __builtin_amdgcn_readfirstlane(cr.y);
+  const int sb = __builtin_amdgcn_readfirstlane(cr.z);
+  const int se = __builtin_amdgcn_readfirstlane(D.sink_ptr[x1]);
+  const int sAc = min(sb + tid, max(se - 1, 0));
+  const PinState ssA = D.sink_state[sAc];
+  const int consA = D.sink_cons[sAc], drvA = D.sink_drv[sAc];
+  const float4 gA4 = D.g_sink[sAc];
+  const int x = x0 + tid;
+  const bool drv = tid < kChunk && x < x1;
+  const int xc = drv ? x : x0;
+  const PinState me = D.drv_state[xc];
+  const int e = D.drv_ep[xc];
+  const int sp0 = D.sink_ptr[xc], sp1 = D.sink_ptr[xc + 1];
+  const LdsLib lib = load_lib(D, smem);
+  float2 *dsl = reinterpret_cast<float2 *>(smem + lib_lds_bytes(D.n_types, D.tstride));  // [kChunk]
+  float4 *cb = reinterpret_cast<float4 *>(dsl + kChunk);                                  // [kSweepBlock]
+  if (tid < kChunk) dsl[tid] = make_float2(me.slew.z, me.slew.w);
+  __syncthreads();
   float gA0 = 0.0f, gA1 = 0.0f, gS0 = 0.0f, gS1 = 0.0f;
-  const int e = D.drv_ep[x];
-  if (e >= 0) {
+  if (drv && e >= 0) {
     const float2 sd = endpoint_seed(D, g_tns, g_wns, e, me.at);
     gA0 = sd.x;
     gA1 = sd.y;
   }
-  for (int s = D.sink_ptr[x]; s < D.sink_ptr[x + 1]; ++s) {
-    const PinState ss = D.sink_state[s];
-    const int cons = D.sink_cons[s];
-    float4 gs;
-    if (cons < 0) {
-      const float2 sd = endpoint_seed(D, g_tns, g_wns, -1 - cons, ss.at);
-      gs = make_float4(sd.x, sd.y, 0.0f, 0.0f);
-    } else {
-      gs = ld4<kCoh>(D.g_sink + s);
+  for (int r0 = sb; r0 < se; r0 += kSweepBlock) {
+    const int s = r0 + tid;
+    if (s < se) {
+      const bool first = r0 == sb;
+      const PinState ss = first ? ssA : D.sink_state[s];
+      const int cons = first ? consA : D.sink_cons[s];
+      const int dr = first ? drvA : D.sink_drv[s];
+      float4 gs;
+      if (cons < 0) {
+        const float2 sd = endpoint_seed(D, g_tns, g_wns, -1 - cons, ss.at);
+        gs = make_float4(sd.x, sd.y, 0.0f, 0.0f);
+      } else {
+        gs = first ? gA4 : D.g_sink[s];
+      }
+      const float2 ms = dsl[dr - x0];
+      cb[tid] = make_float4(gs.x, gs.y, gs.z * (ms.x / ss.slew.z), gs.w * (ms.y / ss.slew.w));
+      D.g_dq[s] = make_float2(gs.x + gs.y, gs.z / (2.0f * ss.slew.z) + gs.w / (2.0f * ss.slew.w));
     }
-    gA0 += gs.x;
-    gA1 += gs.y;
-    gS0 += gs.z * (me.slew.z / ss.slew.z);
-    gS1 += gs.w * (me.slew.w / ss.slew.w);
-    D.g_dq[s] = make_float2(gs.x + gs.y, gs.z / (2.0f * ss.slew.z) + gs.w / (2.0f * ss.slew.w));
+    __syncthreads();
+    if (drv) {
+      const int a = max(sp0, r0), b = min(sp1, r0 + kSweepBlock);
+      for (int k = a; k < b; ++k) {
+        const float4 v = cb[k - r0];
+        gA0 += v.x;
+        gA1 += v.y;
+        gS0 += v.z;
+        gS1 += v.w;
+      }
+    }
+    __syncthreads();
   }
-  if (x >= D.n_pi) {
-    cell_adjoint<kCoh>(D, lib, x, me, gA0, gA1, gS0, gS1);
-  } else {
-    D.g_load[x] = 0.0f;
+  if (drv) {
+    if (x >= D.n_pi)
+      cell_adjoint(D, lib, x, me, gA0, gA1, gS0, gS1);
+    else
+      D.g_load[x] = 0.0f;
   }
-}
-
-__global__ __launch_bounds__(kSweepBlock) void k_adjoint(DevDesign D, float g_tns, float g_wns, int c0, int c1) {
-  extern __shared__ __align__(32) unsigned char smem[];
-  const LdsLib lib = load_lib(D, smem);
-  __syncthreads();
-  const int c = c0 + blockIdx.x * (kSweepBlock / kWave) + threadIdx.x / kWave;
-  if (c < c1) adj_chunk<false>(D, lib, g_tns, g_wns, c);
 }
 
 // ------------------------------------------------------------ RC adjoint
@@ -2039,7 +2322,7 @@ __global__ __launch_bounds__(kRcBlock) void k_rc_adjoint(DevDesign D, const int2
   __shared__ float s_E[kRcChunkNodes], s_F[kRcChunkNodes];
   __shared__ int s_base[kRcBlock + 1];
   const int tid = threadIdx.x;
-  const int ci = blockIdx.x;
+  const int ci = xcd_major(n_chunks);
   if (ci >= n_chunks) return;
   const int2 ch = chunks[ci];
   const int j0 = ch.x, j1 = ch.y;
@@ -2048,7 +2331,7 @@ __global__ __launch_bounds__(kRcBlock) void k_rc_adjoint(DevDesign D, const int2
   const int jc = j < j1 ? j : j0;
   const int x = D.rc_order[jc];
   const int2 sr = D.rc_sinks[jc];
-  stage_rc_nodes(D, k0, nk, s_par, s_R, s_C);
+  stage_rc_nodes(D, k0, nk, s_par, s_R, s_C, s_A);
   for (int i = tid; i <= j1 - j0; i += kRcBlock) s_base[i] = D.rc_start[j0 + i] - k0;
   __syncthreads();
   if (j < j1) {
@@ -2393,8 +2676,7 @@ template <bool kCoop>
 static int sweep_occupancy(size_t lds_bytes) {
   int n = 1 << 30;
   const void *ks[] = {reinterpret_cast<const void *>(&k_sweep<kSweepFwd, kCoop>),
-                      reinterpret_cast<const void *>(&k_sweep<kSweepBwd, kCoop>),
-                      reinterpret_cast<const void *>(&k_sweep<kSweepAdj, kCoop>)};
+                      reinterpret_cast<const void *>(&k_sweep<kSweepBwd, kCoop>)};
   for (const void *k : ks) {
     int b = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k, kSweepBlock, lds_bytes) != hipSuccess) return 0;
@@ -2423,16 +2705,16 @@ static hipError_t launch_sweep(const DevDesign &D, float g_tns, float g_wns, int
   return hipGetLastError();
 }
 
-hipError_t launch_rc(const DevDesign &D, const int2 *chunks, int n_chunks, hipStream_t s) {
+hipError_t launch_rc(const DevDesign &D, const int2 *chunks, int n_chunks, hipStream_t s, const uint32_t *only) {
   const int n_ctr = n_counters(D.n_ph_fwd + D.n_ph_bwd);
-  hipLaunchKernelGGL(k_rc, dim3(n_chunks > 0 ? n_chunks : 1), dim3(kRcBlock), 0, s, D, chunks, n_chunks, D.counters,
-                     n_ctr);
+  hipLaunchKernelGGL(k_rc, dim3(xcd_grid(n_chunks > 0 ? n_chunks : 1)), dim3(kRcBlock), 0, s, D, chunks, n_chunks,
+                     D.counters, n_ctr, only);
   return hipGetLastError();
 }
 
-hipError_t launch_rc_wide(const DevDesign &D, const WideNets &W, hipStream_t s) {
+hipError_t launch_rc_wide(const DevDesign &D, const WideNets &W, hipStream_t s, const uint32_t *only) {
   if (W.n_big <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_rc_wide, dim3(W.n_blk), dim3(kWideBlock), 0, s, D, W);
+  hipLaunchKernelGGL(k_rc_wide, dim3(W.n_blk), dim3(kWideBlock), 0, s, D, W, only);
   return hipGetLastError();
 }
 
@@ -2446,14 +2728,42 @@ hipError_t launch_forward(const DevDesign &D, int grid, bool coop, hipStream_t s
   return launch_sweep<kSweepFwd>(D, 0.0f, 0.0f, grid, coop, s);
 }
 
-hipError_t launch_forward_phase(const DevDesign &D, int4 ph, hipStream_t s) {
+template <bool kInc>
+static hipError_t forward_phase(const DevDesign &D, const IncArgs &I, int4 ph, int2 reg, hipStream_t s) {
   if (ph.z <= 0) return hipSuccess;
   const int per = kSweepBlock / kWave;
   if (ph.x == kItemPiece)
-    hipLaunchKernelGGL(k_forward_pieces, dim3(blocks_for(ph.z, per)), dim3(kSweepBlock), 0, s, D, ph.y, ph.y + ph.z);
+    hipLaunchKernelGGL(k_forward_pieces<kInc>, dim3(blocks_for(ph.z, per)), dim3(kSweepBlock), 0, s, D, ph.y,
+                       ph.y + ph.z, I);
   else
-    hipLaunchKernelGGL(k_forward, dim3(ph.z), dim3(kSweepBlock), sweep_lds_bytes(D), s, D, ph.y, ph.y + ph.z);
+    hipLaunchKernelGGL(k_forward<kInc>, dim3(ph.z), dim3(kSweepBlock), sweep_lds_bytes(D), s, D, ph.y, reg.x, reg.y,
+                       I);
   return hipGetLastError();
+}
+
+template <bool kInc>
+static hipError_t backward_phase(const DevDesign &D, const IncArgs &I, int4 ph, hipStream_t s) {
+  if (ph.z <= 0) return hipSuccess;
+  const int per = kSweepBlock / kWave;
+  if (ph.x == kItemPiece)
+    hipLaunchKernelGGL(k_backward_pieces<kInc>, dim3(blocks_for(ph.z, per)), dim3(kSweepBlock), sweep_lds_bytes(D),
+                       s, D, ph.y, ph.y + ph.z, I);
+  else
+    hipLaunchKernelGGL(k_backward<kInc>, dim3(ph.z), dim3(kSweepBlock), sweep_lds_bytes(D), s, D, ph.y, ph.y + ph.z,
+                       I);
+  return hipGetLastError();
+}
+
+hipError_t launch_forward_phase(const DevDesign &D, int4 ph, int2 reg, hipStream_t s) {
+  return forward_phase<false>(D, IncArgs{}, ph, reg, s);
+}
+
+hipError_t launch_inc_forward_phase(const DevDesign &D, const IncArgs &I, int4 ph, int2 reg, hipStream_t s) {
+  return forward_phase<true>(D, I, ph, reg, s);
+}
+
+hipError_t launch_inc_backward_phase(const DevDesign &D, const IncArgs &I, int4 ph, hipStream_t s) {
+  return backward_phase<true>(D, I, ph, s);
 }
 
 hipError_t launch_backward(const DevDesign &D, int grid, bool coop, hipStream_t s) {
@@ -2461,14 +2771,7 @@ hipError_t launch_backward(const DevDesign &D, int grid, bool coop, hipStream_t 
 }
 
 hipError_t launch_backward_phase(const DevDesign &D, int4 ph, hipStream_t s) {
-  if (ph.z <= 0) return hipSuccess;
-  const int per = kSweepBlock / kWave;
-  if (ph.x == kItemPiece)
-    hipLaunchKernelGGL(k_backward_pieces, dim3(blocks_for(ph.z, per)), dim3(kSweepBlock), sweep_lds_bytes(D), s, D,
-                       ph.y, ph.y + ph.z);
-  else
-    hipLaunchKernelGGL(k_backward, dim3(ph.z), dim3(kSweepBlock), sweep_lds_bytes(D), s, D, ph.y, ph.y + ph.z);
-  return hipGetLastError();
+  return backward_phase<false>(D, IncArgs{}, ph, s);
 }
 
 hipError_t launch_reduce_smooth(const DevDesign &D, double *partials, double *out, uint32_t *keys, int32_t *vals,
@@ -2477,21 +2780,17 @@ hipError_t launch_reduce_smooth(const DevDesign &D, double *partials, double *ou
   return hipGetLastError();
 }
 
-hipError_t launch_adjoint(const DevDesign &D, float g_tns, float g_wns, int grid, bool coop, hipStream_t s) {
-  return launch_sweep<kSweepAdj>(D, g_tns, g_wns, grid, coop, s);
-}
 
 hipError_t launch_adjoint_phase(const DevDesign &D, float g_tns, float g_wns, int4 ph, hipStream_t s) {
   if (ph.z <= 0) return hipSuccess;
-  const int per = kSweepBlock / kWave;
-  hipLaunchKernelGGL(k_adjoint, dim3(blocks_for(ph.z, per)), dim3(kSweepBlock), sweep_lds_bytes(D), s, D, g_tns,
-                     g_wns, ph.y, ph.y + ph.z);
+  hipLaunchKernelGGL(k_adjoint, dim3(ph.z), dim3(kSweepBlock), sweep_lds_bytes(D), s, D, g_tns, g_wns, ph.y,
+                     ph.y + ph.z);
   return hipGetLastError();
 }
 
 hipError_t launch_rc_adjoint(const DevDesign &D, const int2 *chunks, int n_chunks, hipStream_t s) {
   if (n_chunks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_rc_adjoint, dim3(n_chunks), dim3(kRcBlock), 0, s, D, chunks, n_chunks);
+  hipLaunchKernelGGL(k_rc_adjoint, dim3(xcd_grid(n_chunks)), dim3(kRcBlock), 0, s, D, chunks, n_chunks);
   return hipGetLastError();
 }
 
@@ -2508,20 +2807,31 @@ hipError_t launch_scatter_grads(const DevDesign &D, const int32_t *node_src, int
 }
 
 template <int kKind>
-static hipError_t launch_inc(const DevDesign &D, const IncArgs &I, int grid, hipStream_t s) {
+static hipError_t launch_inc(const DevDesign &D, const IncArgs &I, int grid, int max_items, hipStream_t s) {
   DevDesign a = D;
   IncArgs b = I;
-  void *args[] = {&a, &b};
+  int m = max_items;
+  void *args[] = {&a, &b, &m};
   return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_inc_sweep<kKind>), dim3(grid),
                                     dim3(kSweepBlock), args, (unsigned)sweep_lds_bytes(D), s);
 }
 
-hipError_t launch_inc_forward(const DevDesign &D, const IncArgs &I, int grid, hipStream_t s) {
-  return launch_inc<kSweepFwd>(D, I, grid, s);
+hipError_t launch_inc_forward(const DevDesign &D, const IncArgs &I, int grid, int max_items, hipStream_t s) {
+  return launch_inc<kSweepFwd>(D, I, grid, max_items, s);
 }
 
-hipError_t launch_inc_backward(const DevDesign &D, const IncArgs &I, int grid, hipStream_t s) {
-  return launch_inc<kSweepBwd>(D, I, grid, s);
+hipError_t launch_inc_backward(const DevDesign &D, const IncArgs &I, int grid, int max_items, hipStream_t s) {
+  return launch_inc<kSweepBwd>(D, I, grid, max_items, s);
+}
+
+hipError_t launch_inc_queues(const DevDesign &D, const IncArgs &I, bool backward, hipStream_t s) {
+  const int n = backward ? D.n_ph_bwd : D.n_ph_fwd;
+  if (n <= 0) return hipSuccess;
+  if (backward)
+    hipLaunchKernelGGL(k_inc_queues<kSweepBwd>, dim3(n), dim3(256), 0, s, D, I);
+  else
+    hipLaunchKernelGGL(k_inc_queues<kSweepFwd>, dim3(n), dim3(256), 0, s, D, I);
+  return hipGetLastError();
 }
 
 int inc_blocks_per_cu(size_t lds_bytes) {
@@ -2536,9 +2846,17 @@ int inc_blocks_per_cu(size_t lds_bytes) {
   return n;
 }
 
-hipError_t launch_inc_seed(const DevDesign &D, const IncArgs &I, const int32_t *slots, int n, hipStream_t s) {
+hipError_t launch_inc_maps(const DevDesign &D, const int32_t *chunk_of, int32_t *sink_cc, int4 *fanin_cc,
+                           hipStream_t s) {
+  const int n = D.n_sinks > D.n_drv ? D.n_sinks : D.n_drv;
+  hipLaunchKernelGGL(k_inc_maps, dim3(blocks_for(n > 0 ? n : 1, 256)), dim3(256), 0, s, D, chunk_of, sink_cc,
+                     fanin_cc);
+  return hipGetLastError();
+}
+
+hipError_t launch_inc_seed(const DevDesign &D, const IncArgs &I, const int32_t *nets, int n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_inc_seed, dim3(blocks_for(n, 256)), dim3(256), 0, s, D, I, slots, n);
+  hipLaunchKernelGGL(k_inc_seed, dim3(blocks_for(n, 256)), dim3(256), 0, s, D, I, nets, n);
   return hipGetLastError();
 }
 
@@ -2553,17 +2871,23 @@ hipError_t launch_reduce(const DevDesign &D, double *partials, double *out, uint
   return hipGetLastError();
 }
 
+// Endpoint orders: rocPRIM's stable onesweep radix sort at every size above
+// one block (its default picks a merge-sort path below 2^20 items, about 20
+// launches per sort on a million endpoints).
+using EpSortConfig = rocprim::radix_sort_config<rocprim::default_config, rocprim::default_config,
+                                                rocprim::default_config, 0>;
+
 size_t sort_temp_bytes(int n) {
   size_t bytes = 0;
-  (void)hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (const uint32_t *)nullptr, (uint32_t *)nullptr,
-                                     (const int32_t *)nullptr, (int32_t *)nullptr, n);
+  (void)rocprim::radix_sort_pairs<EpSortConfig>(nullptr, bytes, (const uint32_t *)nullptr, (uint32_t *)nullptr,
+                                                (const int32_t *)nullptr, (int32_t *)nullptr, (unsigned)n);
   return bytes;
 }
 
 hipError_t sort_endpoints(void *temp, size_t temp_bytes, const uint32_t *keys_in, uint32_t *keys_out,
                           const int32_t *vals_in, int32_t *vals_out, int n, hipStream_t s) {
-  return hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, keys_in, keys_out, vals_in, vals_out, n, 0, 32,
-                                            s);
+  return rocprim::radix_sort_pairs<EpSortConfig>(temp, temp_bytes, keys_in, keys_out, vals_in, vals_out,
+                                                 (unsigned)n, 0, 32, s);
 }
 
 hipError_t launch_reduce_batch(const DevDesign &D, const int32_t *ep_off, int n_designs, double *partials,
@@ -2577,15 +2901,16 @@ hipError_t launch_reduce_batch(const DevDesign &D, const int32_t *ep_off, int n_
 
 size_t sort_temp_bytes64(int n, int end_bit) {
   size_t bytes = 0;
-  (void)hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (const uint64_t *)nullptr, (uint64_t *)nullptr,
-                                           (const int32_t *)nullptr, (int32_t *)nullptr, n, 0, end_bit);
+  (void)rocprim::radix_sort_pairs<EpSortConfig>(nullptr, bytes, (const uint64_t *)nullptr, (uint64_t *)nullptr,
+                                                (const int32_t *)nullptr, (int32_t *)nullptr, (unsigned)n, 0,
+                                                (unsigned)end_bit);
   return bytes;
 }
 
 hipError_t sort_endpoints64(void *temp, size_t temp_bytes, const uint64_t *keys_in, uint64_t *keys_out,
                             const int32_t *vals_in, int32_t *vals_out, int n, int end_bit, hipStream_t s) {
-  return hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, keys_in, keys_out, vals_in, vals_out, n, 0, end_bit,
-                                            s);
+  return rocprim::radix_sort_pairs<EpSortConfig>(temp, temp_bytes, keys_in, keys_out, vals_in, vals_out,
+                                                 (unsigned)n, 0, (unsigned)end_bit, s);
 }
 
 size_t level_sort_temp_bytes(int n) {

@@ -79,9 +79,13 @@ def _chain(d, sizes, seed, check_oracle=True, **opts):
     full.close()
 
 
-def test_incremental_tiny_chain():
+# blocks = 1: a one-block queued sweep, which hands over to per-phase launches
+# at the first phase with more than 16 items; both schedules and the
+# hand-over are covered
+@pytest.mark.parametrize("blocks", [0, 1])
+def test_incremental_tiny_chain(blocks):
     d = synth.generate(synth.tiny_config(seed=31, dangling_policy=1))
-    _chain(d, [1, 1, 5, 40, 0, d.n_nets // 10, d.n_nets], seed=1)
+    _chain(d, [1, 1, 5, 40, 0, d.n_nets // 10, d.n_nets], seed=1, sweep_blocks=blocks)
 
 
 def test_incremental_wide_rc_nets():
@@ -90,17 +94,19 @@ def test_incremental_wide_rc_nets():
     _chain(d, [3, 30, 300], seed=2, big_net_nodes=40)
 
 
-def test_incremental_mid_design():
+@pytest.mark.parametrize("blocks", [0, 1])
+def test_incremental_mid_design(blocks):
     d = synth.generate(synth.mid_config(n_cells=60_000, n_levels=40, seed=33))
-    _chain(d, [1, 10, 100, 3000], seed=3)
+    _chain(d, [1, 10, 100, 3000], seed=3, sweep_blocks=blocks)
 
 
-def test_incremental_split_high_fanout_drivers():
+@pytest.mark.parametrize("blocks", [0, 1])
+def test_incremental_split_high_fanout_drivers(blocks):
     cfg = synth.mid_config(seed=34, n_cells=8_000, n_levels=12, n_hf=3, hf_min=1500, hf_max=3000)
     d = synth.generate(cfg)
     hf = np.argsort(np.diff(d.net_sink_ptr))[-3:]  # the high-fanout nets themselves
     rng = np.random.default_rng(4)
-    inc, full = STA(d), STA(d)
+    inc, full = STA(d, sweep_blocks=blocks), STA(d, sweep_blocks=blocks)
     inc.update()
     caps = d.cap_ff.astype(np.float32).copy()
     for i, nets in enumerate([hf[:1], hf, np.concatenate([hf, rng.choice(d.n_nets, 50, replace=False)])]):
@@ -136,10 +142,12 @@ def test_incremental_duplicates_pi_nets_and_device_list():
     full.close()
 
 
-def test_incremental_smooth_mode():
+@pytest.mark.parametrize("blocks", [0, 1])
+def test_incremental_smooth_mode(blocks):
     d = synth.generate(synth.mid_config(n_cells=20_000, n_levels=25, seed=36))
     rng = np.random.default_rng(6)
-    inc, full = STA(d, mode=1, gamma_ps=5.0), STA(d, mode=1, gamma_ps=5.0)
+    inc = STA(d, mode=1, gamma_ps=5.0, sweep_blocks=blocks)
+    full = STA(d, mode=1, gamma_ps=5.0, sweep_blocks=blocks)
     inc.update()
     caps = d.cap_ff.astype(np.float32).copy()
     for k in (1, 50, 2000):
