@@ -119,7 +119,6 @@ struct sta_ctx {
   int n_fanin = 0;
   bool updated = false;
   double *partials = nullptr, *out = nullptr;
-  uint32_t *keys = nullptr, *keys_out = nullptr;
   int32_t *vals = nullptr, *order = nullptr;
   void *sort_temp = nullptr;
   size_t sort_bytes = 0;
@@ -141,8 +140,8 @@ struct sta_ctx {
   std::vector<int64_t> node_off;
   int32_t *d_ep_off = nullptr;
   double *b_partials = nullptr, *b_out = nullptr;
-  uint64_t *keys64 = nullptr, *keys64_out = nullptr;
-  int key_bits = 32;
+  uint64_t *keys64 = nullptr, *keys64_out = nullptr;  // [2 n_ep] endpoint sort keys
+  int key_bits = 33, design_bits = 0;
   // incremental update: maps from the layout; device queues made on first use
   int32_t *inc_chunk_of = nullptr;     // [n_drv]
   int2 *inc_chunk_ph = nullptr;        // [n_chunks]
@@ -797,6 +796,7 @@ static sta_status build_layout(sta_ctx *C, const Inputs &I, const std::vector<in
   int max_in = 0;
   for (int t = 0; t < lib.n_types; ++t) max_in = std::max(max_in, (int)lib.n_inputs[t]);
   C->max_in = std::max(max_in, 1);
+  C->D.max_in = C->max_in;
   std::vector<int4> fanin4;
   if (max_in <= 4) {
     fanin4.assign(ND, make_int4(-1, -1, -1, -1));
@@ -1001,11 +1001,12 @@ static sta_status build_layout(sta_ctx *C, const Inputs &I, const std::vector<in
   HIP_TRY(hipMemset(C->out, 0, 8 * sizeof(double)));
   D.norm = C->out + 4;
   const int ne = std::max(C->n_ep, 1);
-  STA_TRY(C->alloc(&C->keys, 2 * (size_t)ne));
-  STA_TRY(C->alloc(&C->keys_out, 2 * (size_t)ne));
-  STA_TRY(C->alloc(&C->vals, ne));
+  STA_TRY(C->alloc(&C->keys64, 2 * (size_t)ne));
+  STA_TRY(C->alloc(&C->keys64_out, 2 * (size_t)ne));
+  STA_TRY(C->alloc(&C->vals, 2 * (size_t)ne));
   STA_TRY(C->alloc(&C->order, 2 * (size_t)ne));
-  C->sort_bytes = sort_temp_bytes(ne);
+  C->key_bits = 33;
+  C->sort_bytes = sort_temp_bytes64(2 * ne, C->key_bits);
   unsigned char *st;
   STA_TRY(C->alloc(&st, C->sort_bytes));
   C->sort_temp = st;
@@ -1271,12 +1272,11 @@ extern "C" sta_status sta_batch_create(int32_t n_designs, const sta_graph_desc *
   STA_TRY(C->alloc(&C->b_out, (size_t)n_designs * 4));
   HIP_TRY(hipMemset(C->b_out, 0, (size_t)n_designs * 4 * sizeof(double)));
   const int ne = std::max(C->n_ep, 1);
-  STA_TRY(C->alloc(&C->keys64, 2 * (size_t)ne));
-  STA_TRY(C->alloc(&C->keys64_out, 2 * (size_t)ne));
   int bits = 0;
   while ((1 << bits) < n_designs) ++bits;
-  C->key_bits = 32 + bits;
-  const size_t tb = sort_temp_bytes64(ne, C->key_bits);
+  C->design_bits = bits;
+  C->key_bits = 33 + bits;
+  const size_t tb = sort_temp_bytes64(2 * ne, C->key_bits);
   if (tb > C->sort_bytes) {
     unsigned char *st;
     STA_TRY(C->alloc(&st, tb));
@@ -1347,28 +1347,21 @@ static sta_status enqueue_reduce(sta_ctx *C, hipStream_t s) {
   const DevDesign &D = C->D;
   const bool sort = C->opt.sort_endpoints && C->n_ep > 0;
   if (C->opt.mode == 1)
-    HIP_TRY(launch_reduce_smooth(D, C->partials, C->out, sort ? C->keys : nullptr, sort ? C->vals : nullptr, s));
+    HIP_TRY(launch_reduce_smooth(D, C->partials, C->out, sort ? C->keys64 : nullptr, sort ? C->vals : nullptr, s));
   else if (C->batched)
-    HIP_TRY(launch_reduce_batch(D, C->d_ep_off, C->n_designs, C->b_partials, C->b_out,
+    HIP_TRY(launch_reduce_batch(D, C->d_ep_off, C->n_designs, C->design_bits, C->b_partials, C->b_out,
                                 sort ? C->keys64 : nullptr, sort ? C->vals : nullptr, s));
   else
-    HIP_TRY(launch_reduce(D, C->partials, C->out, sort ? C->keys : nullptr, sort ? C->vals : nullptr, s));
+    HIP_TRY(launch_reduce(D, C->partials, C->out, sort ? C->keys64 : nullptr, sort ? C->vals : nullptr, s));
   return STA_OK;
 }
 
 // Endpoint order per early/late from the keys the reduction wrote.
 static sta_status enqueue_sort(sta_ctx *C, hipStream_t s) {
   if (!C->opt.sort_endpoints || C->n_ep <= 0) return STA_OK;
-  for (int el = 0; el < 2; ++el) {
-    if (C->batched)
-      HIP_TRY(sort_endpoints64(C->sort_temp, C->sort_bytes, C->keys64 + (size_t)el * C->n_ep,
-                               C->keys64_out + (size_t)el * C->n_ep, C->vals, C->order + (size_t)el * C->n_ep,
-                               C->n_ep, C->key_bits, s));
-    else
-      HIP_TRY(sort_endpoints(C->sort_temp, C->sort_bytes, C->keys + (size_t)el * C->n_ep,
-                             C->keys_out + (size_t)el * C->n_ep, C->vals, C->order + (size_t)el * C->n_ep,
-                             C->n_ep, s));
-  }
+  // both orders in one sort: the early/late bit is above the (design and) slack bits
+  HIP_TRY(sort_endpoints64(C->sort_temp, C->sort_bytes, C->keys64, C->keys64_out, C->vals, C->order,
+                           2 * C->n_ep, C->key_bits, s));
   return STA_OK;
 }
 

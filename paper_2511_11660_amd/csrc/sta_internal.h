@@ -63,6 +63,7 @@ struct DevDesign {
   int32_t n_drv, n_pi, n_sinks, n_ep, n_cell_levels;
   int32_t n_types, nx, ny, tstride;
   int32_t n_chunks;
+  int32_t max_in;             // most inputs of any library type
 
   // driver slots
   const int32_t *sink_ptr;    // [n_drv+1]
@@ -212,23 +213,26 @@ hipError_t launch_forward_phase(const DevDesign &D, int4 phase, int2 reg, hipStr
 hipError_t launch_backward(const DevDesign &D, int persistent_grid, bool coop, hipStream_t s);
 hipError_t launch_backward_phase(const DevDesign &D, int4 phase, hipStream_t s);
 hipError_t launch_reset_counters(uint32_t *counters, int n, hipStream_t s);
-hipError_t launch_reduce_smooth(const DevDesign &D, double *partials, double *out, uint32_t *keys,
+// keys (when not NULL): [2 n_ep] endpoint sort keys, (early/late, slack) with
+// early/late above the slack bits, and their endpoint indices in vals
+hipError_t launch_reduce_smooth(const DevDesign &D, double *partials, double *out, uint64_t *keys,
                                 int32_t *vals, hipStream_t s);
 hipError_t launch_adjoint_phase(const DevDesign &D, float g_tns, float g_wns, int4 phase, hipStream_t s);
 hipError_t launch_rc_adjoint(const DevDesign &D, const int2 *chunks, int n_chunks, hipStream_t s);
 hipError_t launch_scatter_grads(const DevDesign &D, const int32_t *node_src, int64_t n_nodes,
                                 float *grad_cap, const int32_t *pin_loc, int n_pins, float *grad_load,
                                 const int32_t *arc_src, int n_arcs, float4 *grad_arc, hipStream_t s);
-hipError_t launch_reduce(const DevDesign &D, double *partials, double *out, uint32_t *keys,
+hipError_t launch_reduce(const DevDesign &D, double *partials, double *out, uint64_t *keys,
                          int32_t *vals, hipStream_t s);
 hipError_t sort_endpoints(void *temp, size_t temp_bytes, const uint32_t *keys_in,
                           uint32_t *keys_out, const int32_t *vals_in, int32_t *vals_out, int n,
                           hipStream_t s);
 size_t sort_temp_bytes(int n);
 // batches: per-design reductions (out[d][4] = early WNS, late WNS, early TNS,
-// late TNS) and the design-major endpoint sort on 64-bit keys
-hipError_t launch_reduce_batch(const DevDesign &D, const int32_t *ep_off, int n_designs, double *partials,
-                               double *out, uint64_t *keys, int32_t *vals, hipStream_t s);
+// late TNS) and the endpoint sort keys (early/late, design, slack), the design
+// in dbits bits above the slack
+hipError_t launch_reduce_batch(const DevDesign &D, const int32_t *ep_off, int n_designs, int dbits,
+                               double *partials, double *out, uint64_t *keys, int32_t *vals, hipStream_t s);
 size_t sort_temp_bytes64(int n, int end_bit);
 hipError_t sort_endpoints64(void *temp, size_t temp_bytes, const uint64_t *keys_in, uint64_t *keys_out,
                             const int32_t *vals_in, int32_t *vals_out, int n, int end_bit, hipStream_t s);

@@ -31,6 +31,16 @@ __device__ __forceinline__ void wave_sync() {
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 
+// Block barrier that orders LDS accesses only.  __syncthreads also waits for
+// the block's global stores to complete (a workgroup-scope fence on every
+// address space); where no thread of the block reads back another's global
+// stores, that wait only lengthens the level's critical path.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // The hardware deals consecutive block ids to the 8 XCDs in turn.  For a grid
 // of 8 * ceil(n / 8) blocks this returns the item of the calling block such
 // that each XCD takes one contiguous run of items, so the cache lines a run
@@ -483,12 +493,87 @@ __device__ __forceinline__ void merge_view_pair(const DevDesign &D, const CellCt
   }
 }
 
+// The inline-fanin merge of one view over kSlots fanin slots, staged so that
+// every LDS access of a stage is independent of the others: the cell's x axis
+// once, the segment of each slot's input slew (ALU), each segment's axis
+// point and reciprocal width, the searches shared across the lane pair, all
+// bilinear corners, then the merges in (slot, input transition) order.  Each
+// value is computed by the expressions of axis_find, bilerp and
+// merge_view_pair, so the results are the same bits.
+template <int kSlots>
+__device__ __forceinline__ void merge_slots(const DevDesign &D, const CellCtx &cc, int el, int ro, const float2 *iat,
+                                            const float2 *isl, const int *fs, float &at, float &sl, int &cr,
+                                            float &lse) {
+  const TabLayout lay{D.nx, D.ny};
+  const float *xa = cc.tb + lay.xa(), *rdx = cc.tb + lay.rdx();
+  float a[kMaxAxis - 2];
+#pragma unroll
+  for (int m = 1; m < kMaxAxis - 1; ++m) a[m - 1] = xa[m];
+  float X[kSlots];
+  int seg[kSlots];
+#pragma unroll
+  for (int k = 0; k < kSlots; ++k) {
+    X[k] = ro ? isl[k].y : isl[k].x;
+    int i = 0;
+#pragma unroll
+    for (int m = 1; m < kMaxAxis - 1; ++m) i += (m <= D.nx - 2 && a[m - 1] <= X[k]) ? 1 : 0;
+    seg[k] = i;
+  }
+  float ax[kSlots], rd[kSlots];
+#pragma unroll
+  for (int k = 0; k < kSlots; ++k) {
+    ax[k] = xa[seg[k]];
+    rd[k] = rdx[seg[k]];
+  }
+  AxisPos mine[kSlots], other[kSlots];  // (static indices only: no private-memory arrays)
+#pragma unroll
+  for (int k = 0; k < kSlots; ++k) {
+    mine[k] = AxisPos{seg[k], (X[k] - ax[k]) * rd[k]};
+    other[k].i = __shfl_xor(mine[k].i, 1);
+    other[k].t = __shfl_xor(mine[k].t, 1);
+  }
+  float dl[kSlots][2], os[kSlots][2];
+#pragma unroll
+  for (int k = 0; k < kSlots; ++k) {
+#pragma unroll
+    for (int ri = 0; ri < 2; ++ri) {
+      AxisPos px;
+      px.i = ri == ro ? mine[k].i : other[k].i;
+      px.t = ri == ro ? mine[k].t : other[k].t;
+      dl[k][ri] = bilerp(cc.tb + lay.tab(ro), D.ny, px, cc.py);
+      os[k][ri] = bilerp(cc.tb + lay.tab(2 + ro), D.ny, px, cc.py);
+    }
+  }
+  const float g = D.gamma;
+#pragma unroll
+  for (int k = 0; k < kSlots; ++k) {
+    const float ia[2] = {iat[k].x, iat[k].y};
+#pragma unroll
+    for (int ri = 0; ri < 2; ++ri) {
+      const bool m = fs[k] >= 0 && arc_maps(cc.sense, ri, ro);
+      const float cand = ia[ri] + dl[k][ri];
+      const bool better = m && (el ? cand > at : cand < at);
+      if (g > 0.0f) {
+        const float up = lse * expf((at - cand) / g) + 1.0f;
+        const float add = lse + expf((cand - at) / g);
+        lse = (el && m) ? (better ? up : add) : lse;
+      }
+      at = better ? cand : at;
+      cr = better ? k * 2 + ri : cr;
+      sl = m ? (el ? fmaxf(sl, os[k][ri]) : fminf(sl, os[k][ri])) : sl;
+    }
+  }
+}
+
 // With kInc (incremental continuation, IncArgs valid) an unflagged chunk
 // returns at once; a flagged one compares its results bitwise with the stored
 // ones, rewrites the sinks only of drivers that changed or whose net was
 // recomputed, and flags the consumers of changed sinks and itself for the
 // backward sweep.
-template <bool kInc>
+// kSlots: inline fanin slots to merge (the library's most inputs, <= 4), so
+// the slot loop is straight-line code whose table loads can all be issued
+// together; a cell with fewer inputs masks its empty slots.
+template <bool kInc, int kSlots>
 __global__ __launch_bounds__(kSweepBlock) void k_forward(DevDesign D, int c0, int xb, int xr, IncArgs I) {
   extern __shared__ __align__(32) unsigned char smem[];
   static_assert(kSweepBlock == 4 * kChunk, "one thread per driver view");
@@ -538,7 +623,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_forward(DevDesign D, int c0, in
   const int fs[4] = {f4.x, f4.y, f4.z, f4.w};
   float2 iat[4], isl[4];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < kSlots; ++k) {
     const float *st = reinterpret_cast<const float *>(D.sink_state + max(fs[k], 0));
     iat[k] = *reinterpret_cast<const float2 *>(st + 2 * el);
     isl[k] = *reinterpret_cast<const float2 *>(st + 4 + 2 * el);
@@ -560,7 +645,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_forward(DevDesign D, int c0, in
   const LdsLib lib = load_lib(D, smem);
   PinState *wst = reinterpret_cast<PinState *>(smem + lib_lds_bytes(D.n_types, D.tstride));
   int *s_redo = reinterpret_cast<int *>(wst + kChunk);  // [kChunk], incremental only
-  __syncthreads();
+  lds_barrier();
   float at_v, sl_v;
   int cr_v = -1;
   if (pis) {
@@ -572,12 +657,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_forward(DevDesign D, int c0, in
     sl_v = el ? -kInf : kInf;
     float lse = 0.0f;
     if (inl) {
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        if (__ballot(fs[k] >= 0) == 0) continue;  // no lane of the wave has this input
-        const float ia[2] = {iat[k].x, iat[k].y}, is[2] = {isl[k].x, isl[k].y};
-        merge_view_pair(D, cc, el, ro, ia, is, fs[k] >= 0, k, at_v, sl_v, cr_v, lse);
-      }
+      merge_slots<kSlots>(D, cc, el, ro, iat, isl, fs, at_v, sl_v, cr_v, lse);
     } else {
       const int f0 = D.fanin_ptr[xc], f1 = D.fanin_ptr[xc + 1];
       for (int f = f0; f < f1; ++f) {
@@ -616,7 +696,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_forward(DevDesign D, int c0, in
     if (__syncthreads_or(redo) == 0) return;
     if (tid == 0) I.flag[I.n_chunks + c] = 1u;
   } else {
-    __syncthreads();
+    lds_barrier();
   }
   // (incremental: old is the sink's stored state, cc its consumer's chunk)
   auto emit = [&](int s, int drv, float2 w, const PinState &old, int cc) {
@@ -866,7 +946,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_backward(DevDesign D, int c0, i
   const LdsLib lib = load_lib(D, smem);
   int *wacc = reinterpret_cast<int *>(smem + lib_lds_bytes(D.n_types, D.tstride));
   wacc[tid] = f2key((v >> 1) ? kInf : -kInf);
-  __syncthreads();
+  lds_barrier();
   const TabLayout lay{D.nx, D.ny};
   auto sink = [&](int s, float2 at, float2 sl, int cons, float d, int drv) {
     float r[2];
@@ -880,13 +960,30 @@ __global__ __launch_bounds__(kSweepBlock) void k_backward(DevDesign D, int c0, i
       const int t = __float_as_int(Lt.y);
       const int sense = lib.sense[t];
       const float *tb = lib.tab + t * D.tstride;
-      const AxisPos py = axis_find(tb + lay.ya(), tb + lay.rdy(), D.ny, Lt.x);
       const float ro_[2] = {Ro.x, Ro.y}, is[2] = {sl.x, sl.y};
-      // every (ri, ro) pair evaluated, unmapped ones masked: min / max are
-      // exact, so the result does not depend on the evaluation order
+      // staged as in merge_slots: both axes, then the three segments' points
+      // and widths, then all corners; every (ri, ro) pair evaluated and the
+      // unmapped ones masked (min / max are exact, so the order is free)
+      const float *xa = tb + lay.xa(), *ya = tb + lay.ya();
+      float ax6[kMaxAxis - 2], ay6[kMaxAxis - 2];
+#pragma unroll
+      for (int m = 1; m < kMaxAxis - 1; ++m) {
+        ax6[m - 1] = xa[m];
+        ay6[m - 1] = ya[m];
+      }
+      int iy = 0, ix[2] = {0, 0};
+#pragma unroll
+      for (int m = 1; m < kMaxAxis - 1; ++m) {
+        iy += (m <= D.ny - 2 && ay6[m - 1] <= Lt.x) ? 1 : 0;
+        ix[0] += (m <= D.nx - 2 && ax6[m - 1] <= is[0]) ? 1 : 0;
+        ix[1] += (m <= D.nx - 2 && ax6[m - 1] <= is[1]) ? 1 : 0;
+      }
+      const float y0 = ya[iy], ry = tb[lay.rdy() + iy];
+      const float x0[2] = {xa[ix[0]], xa[ix[1]]}, rx[2] = {tb[lay.rdx() + ix[0]], tb[lay.rdx() + ix[1]]};
+      const AxisPos py{iy, (Lt.x - y0) * ry};
 #pragma unroll
       for (int ri = 0; ri < 2; ++ri) {
-        const AxisPos px = axis_find(tb + lay.xa(), tb + lay.rdx(), D.nx, is[ri]);
+        const AxisPos px{ix[ri], (is[ri] - x0[ri]) * rx[ri]};
         float best = el ? kInf : -kInf;
 #pragma unroll
         for (int ro = 0; ro < 2; ++ro) {
@@ -920,7 +1017,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_backward(DevDesign D, int c0, i
     ld_half(sj, at, sl);
     sink(sj, at, sl, D.sink_cons[sj], D.dq[sj].x, D.sink_drv[sj]);
   }
-  __syncthreads();
+  lds_barrier();
   float R = key2f(wacc[tid]);
   const bool late = (v >> 1) != 0;
   if (live && e >= 0) {
@@ -960,7 +1057,7 @@ template <bool kInc>
 __global__ __launch_bounds__(kSweepBlock) void k_backward_pieces(DevDesign D, int j0, int j1, IncArgs I) {
   extern __shared__ __align__(32) unsigned char smem[];
   const LdsLib lib = load_lib(D, smem);
-  __syncthreads();
+  lds_barrier();
   const int j = j0 + blockIdx.x * (kSweepBlock / kWave) + threadIdx.x / kWave;
   if (j >= j1) return;
   if constexpr (kInc) {
@@ -1852,7 +1949,7 @@ __global__ __launch_bounds__(kRcBlock) void k_rc(DevDesign D, const int2 *chunks
   int sn[kPre];
 #pragma unroll
   for (int u = 0; u < kPre; ++u) sn[u] = D.sink_node[min(sr.x + u, max(sr.y - 1, 0))];
-  __syncthreads();
+  lds_barrier();
   if (j < j1) {
     const int b = s_base[tid], m = s_base[tid + 1] - b;
     const int s0 = sr.x, s1 = sr.y;
@@ -1881,7 +1978,7 @@ __global__ __launch_bounds__(kRcBlock) void k_rc(DevDesign D, const int2 *chunks
 // FP64 with a fixed partition and tree so results are bitwise reproducible;
 // also writes the radix-sort keys of the endpoint order.
 __global__ __launch_bounds__(256) void k_reduce(DevDesign D, double *partials, double *out,
-                                               uint32_t *keys, int32_t *vals) {
+                                               uint64_t *keys, int32_t *vals) {
   __shared__ double sh[4][256];
   const int n = D.n_ep;
   const int per = (n + kReduceBlocks - 1) / kReduceBlocks;
@@ -1893,10 +1990,11 @@ __global__ __launch_bounds__(256) void k_reduce(DevDesign D, double *partials, d
     w1 = fmin(w1, (double)s.y);
     if (s.x < 0.0f) t0 += (double)s.x;
     if (s.y < 0.0f) t1 += (double)s.y;
-    if (keys) {
+    if (keys) {  // one sort for both orders: early/late in bit 32
       keys[e] = f2ukey(s.x);
-      keys[n + e] = f2ukey(s.y);
+      keys[n + e] = (1ull << 32) | f2ukey(s.y);
       vals[e] = e;
+      vals[n + e] = e;
     }
   }
   const int tid = threadIdx.x;
@@ -1940,7 +2038,7 @@ __global__ __launch_bounds__(256) void k_reduce(DevDesign D, double *partials, d
 // Sort keys carry the design in their high 32 bits (design-major order);
 // values are design-local endpoint indices.
 __global__ __launch_bounds__(256) void k_reduce_batch(DevDesign D, const int32_t *ep_off, double *partials,
-                                                     uint64_t *keys, int32_t *vals) {
+                                                     uint64_t *keys, int32_t *vals, int dbits) {
   __shared__ double sh[4][256];
   const int dsg = blockIdx.y;
   const int e0 = ep_off[dsg];
@@ -1954,10 +2052,11 @@ __global__ __launch_bounds__(256) void k_reduce_batch(DevDesign D, const int32_t
     w1 = fmin(w1, (double)s.y);
     if (s.x < 0.0f) t0 += (double)s.x;
     if (s.y < 0.0f) t1 += (double)s.y;
-    if (keys) {
+    if (keys) {  // (early/late, design, slack): one sort for both orders of every design
       keys[e0 + e] = ((uint64_t)dsg << 32) | f2ukey(s.x);
-      keys[D.n_ep + e0 + e] = ((uint64_t)dsg << 32) | f2ukey(s.y);
+      keys[D.n_ep + e0 + e] = (1ull << (32 + dbits)) | ((uint64_t)dsg << 32) | f2ukey(s.y);
       vals[e0 + e] = e;
+      vals[D.n_ep + e0 + e] = e;
     }
   }
   const int tid = threadIdx.x;
@@ -2000,7 +2099,7 @@ __global__ void k_reduce_batch_final(const double *partials, double *out, int n_
 //   out[4], out[5] = max shift M and denominator e^{-M} + sum e^{-s/g - M}.
 // The max-shifted sum is combined as (M, S) pairs so it never overflows.
 __global__ __launch_bounds__(256) void k_reduce_smooth(DevDesign D, double *partials, double *out,
-                                                      uint32_t *keys, int32_t *vals) {
+                                                      uint64_t *keys, int32_t *vals) {
   __shared__ double sh[5][256];
   const int n = D.n_ep;
   const double g = D.gamma;
@@ -2028,8 +2127,9 @@ __global__ __launch_bounds__(256) void k_reduce_smooth(DevDesign D, double *part
     }
     if (keys) {
       keys[e] = f2ukey(se);
-      keys[n + e] = f2ukey(sl);
+      keys[n + e] = (1ull << 32) | f2ukey(sl);
       vals[e] = e;
+      vals[n + e] = e;
     }
   }
   const int tid = threadIdx.x;
@@ -2190,7 +2290,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_adjoint(DevDesign D, float g_tn
   float2 *dsl = reinterpret_cast<float2 *>(smem + lib_lds_bytes(D.n_types, D.tstride));  // [kChunk]
   float4 *cb = reinterpret_cast<float4 *>(dsl + kChunk);                                  // [kSweepBlock]
   if (tid < kChunk) dsl[tid] = make_float2(me.slew.z, me.slew.w);
-  __syncthreads();
+  lds_barrier();
   float gA0 = 0.0f, gA1 = 0.0f, gS0 = 0.0f, gS1 = 0.0f;
   if (drv && e >= 0) {
     const float2 sd = endpoint_seed(D, g_tns, g_wns, e, me.at);
@@ -2215,7 +2315,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_adjoint(DevDesign D, float g_tn
       cb[tid] = make_float4(gs.x, gs.y, gs.z * (ms.x / ss.slew.z), gs.w * (ms.y / ss.slew.w));
       D.g_dq[s] = make_float2(gs.x + gs.y, gs.z / (2.0f * ss.slew.z) + gs.w / (2.0f * ss.slew.w));
     }
-    __syncthreads();
+    lds_barrier();
     if (drv) {
       const int a = max(sp0, r0), b = min(sp1, r0 + kSweepBlock);
       for (int k = a; k < b; ++k) {
@@ -2226,7 +2326,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_adjoint(DevDesign D, float g_tn
         gS1 += v.w;
       }
     }
-    __syncthreads();
+    lds_barrier();
   }
   if (drv) {
     if (x >= D.n_pi)
@@ -2735,9 +2835,18 @@ static hipError_t forward_phase(const DevDesign &D, const IncArgs &I, int4 ph, i
   if (ph.x == kItemPiece)
     hipLaunchKernelGGL(k_forward_pieces<kInc>, dim3(blocks_for(ph.z, per)), dim3(kSweepBlock), 0, s, D, ph.y,
                        ph.y + ph.z, I);
+  else if (D.max_in <= 1)
+    hipLaunchKernelGGL((k_forward<kInc, 1>), dim3(ph.z), dim3(kSweepBlock), sweep_lds_bytes(D), s, D, ph.y, reg.x,
+                       reg.y, I);
+  else if (D.max_in == 2)
+    hipLaunchKernelGGL((k_forward<kInc, 2>), dim3(ph.z), dim3(kSweepBlock), sweep_lds_bytes(D), s, D, ph.y, reg.x,
+                       reg.y, I);
+  else if (D.max_in == 3)
+    hipLaunchKernelGGL((k_forward<kInc, 3>), dim3(ph.z), dim3(kSweepBlock), sweep_lds_bytes(D), s, D, ph.y, reg.x,
+                       reg.y, I);
   else
-    hipLaunchKernelGGL(k_forward<kInc>, dim3(ph.z), dim3(kSweepBlock), sweep_lds_bytes(D), s, D, ph.y, reg.x, reg.y,
-                       I);
+    hipLaunchKernelGGL((k_forward<kInc, 4>), dim3(ph.z), dim3(kSweepBlock), sweep_lds_bytes(D), s, D, ph.y, reg.x,
+                       reg.y, I);
   return hipGetLastError();
 }
 
@@ -2774,7 +2883,7 @@ hipError_t launch_backward_phase(const DevDesign &D, int4 ph, hipStream_t s) {
   return backward_phase<false>(D, IncArgs{}, ph, s);
 }
 
-hipError_t launch_reduce_smooth(const DevDesign &D, double *partials, double *out, uint32_t *keys, int32_t *vals,
+hipError_t launch_reduce_smooth(const DevDesign &D, double *partials, double *out, uint64_t *keys, int32_t *vals,
                                 hipStream_t s) {
   hipLaunchKernelGGL(k_reduce_smooth, dim3(kReduceBlocks), dim3(256), 0, s, D, partials, out, keys, vals);
   return hipGetLastError();
@@ -2865,7 +2974,7 @@ hipError_t launch_reset_counters(uint32_t *counters, int n, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_reduce(const DevDesign &D, double *partials, double *out, uint32_t *keys, int32_t *vals,
+hipError_t launch_reduce(const DevDesign &D, double *partials, double *out, uint64_t *keys, int32_t *vals,
                          hipStream_t s) {
   hipLaunchKernelGGL(k_reduce, dim3(kReduceBlocks), dim3(256), 0, s, D, partials, out, keys, vals);
   return hipGetLastError();
@@ -2873,7 +2982,8 @@ hipError_t launch_reduce(const DevDesign &D, double *partials, double *out, uint
 
 // Endpoint orders: rocPRIM's stable onesweep radix sort at every size above
 // one block (its default picks a merge-sort path below 2^20 items, about 20
-// launches per sort on a million endpoints).
+// launches per sort on a million endpoints).  Both orders of an update are
+// one sort of (early/late, [design,] slack) keys.
 using EpSortConfig = rocprim::radix_sort_config<rocprim::default_config, rocprim::default_config,
                                                 rocprim::default_config, 0>;
 
@@ -2890,10 +3000,10 @@ hipError_t sort_endpoints(void *temp, size_t temp_bytes, const uint32_t *keys_in
                                                  (unsigned)n, 0, 32, s);
 }
 
-hipError_t launch_reduce_batch(const DevDesign &D, const int32_t *ep_off, int n_designs, double *partials,
-                               double *out, uint64_t *keys, int32_t *vals, hipStream_t s) {
+hipError_t launch_reduce_batch(const DevDesign &D, const int32_t *ep_off, int n_designs, int dbits,
+                               double *partials, double *out, uint64_t *keys, int32_t *vals, hipStream_t s) {
   hipLaunchKernelGGL(k_reduce_batch, dim3(kReduceBlocks, n_designs), dim3(256), 0, s, D, ep_off, partials, keys,
-                     vals);
+                     vals, dbits);
   hipLaunchKernelGGL(k_reduce_batch_final, dim3(blocks_for(n_designs, 256)), dim3(256), 0, s, partials, out,
                      n_designs);
   return hipGetLastError();
