@@ -105,19 +105,20 @@ def adjoint_ratio(steps: int) -> dict:
     r = s.autotune(reps=3)
     stream = torch.cuda.current_stream()
     gc = torch.empty(int(d.n_nodes), dtype=torch.float32, device="cuda")
+    gr = torch.empty(int(d.n_nodes), dtype=torch.float32, device="cuda")
     gl = torch.empty(d.n_pins, dtype=torch.float32, device="cuda")
     ga = torch.empty((int(d.cell_in_ptr[-1]), 4), dtype=torch.float32, device="cuda")
     from paper_2511_11660_amd.sta import STA_DEVICE, sta_backward
     for _ in range(3):
         s.update(stream)
-        sta_backward(s.ctx, 1.0, 0.0, gc, gl, ga, STA_DEVICE, stream)
+        sta_backward(s.ctx, 1.0, 0.0, gc, gr, gl, ga, STA_DEVICE, stream)
     t_fwd = _time_updates([s], stream, steps)
     s.update(stream)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     ev0.record(stream)
     for _ in range(steps):
-        sta_backward(s.ctx, 1.0, 0.0, gc, gl, ga, STA_DEVICE, stream)
+        sta_backward(s.ctx, 1.0, 0.0, gc, gr, gl, ga, STA_DEVICE, stream)
     ev1.record(stream)
     torch.cuda.synchronize()
     t_bwd = ev0.elapsed_time(ev1) / steps
@@ -189,6 +190,48 @@ def incremental_updates(design, sched: int, blocks: int, full_ms: float, sizes=(
     return out
 
 
+def rc_estimate_side(design, reps: int = 5) -> dict:
+    """sta_estimate_rc on the whole design with every input and output in HBM
+    (synthetic placement), median of `reps` calls timed with events around
+    the call (its two host waits included)."""
+    import numpy as np
+    import torch
+    from paper_2511_11660_amd import synth
+    from paper_2511_11660_amd.sta import STA_DEVICE, sta_estimate_rc, sta_graph_desc, sta_wire_params
+    x, y = synth.place(design, seed=1)
+    dev = {k: torch.from_numpy(np.ascontiguousarray(getattr(design, k), np.int32)).cuda()
+           for k in ("net_driver", "net_sink_ptr", "net_sink_pin")}
+    dx, dy = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    g = sta_graph_desc(design.n_pins, design.n_cells, design.n_nets, design.n_pi, design.n_po, None, None, None,
+                       None, None, dev["net_driver"].data_ptr(), dev["net_sink_ptr"].data_ptr(),
+                       dev["net_sink_pin"].data_ptr(), STA_DEVICE)
+    nn, ns = design.n_nets, int(design.net_sink_ptr[-1])
+    nodes = nn + 2 * ns
+    ptr = torch.empty(nn + 1, dtype=torch.int64, device="cuda")
+    par = torch.empty(nodes, dtype=torch.int32, device="cuda")
+    res = torch.empty(nodes, dtype=torch.float32, device="cuda")
+    cap = torch.empty(nodes, dtype=torch.float32, device="cuda")
+    sink = torch.empty(ns, dtype=torch.int32, device="cuda")
+    w = sta_wire_params(0.002, 0.002, 0.2, 0.2)
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ts = []
+    for _ in range(reps + 1):
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        sta_estimate_rc(g, dx, dy, w, ptr, par, res, cap, sink, STA_DEVICE, stream)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ts.append(ev0.elapsed_time(ev1))
+    ms = sorted(ts[1:])[reps // 2]
+    # net CSR and driver (12 B/net), sink pins (4 B/sink), positions of every
+    # net pin (8 B), outputs: node_ptr 8 B/net, 12 B/node, sink_node 4 B/sink
+    algo = 12 * nn + 4 * ns + 8 * (nn + ns) + 8 * nn + 12 * nodes + 4 * ns
+    return {"workload": "10M-pin design, synthetic placement, all arrays in HBM", "nets": nn, "sinks": ns,
+            "max_fanout": int(np.diff(design.net_sink_ptr).max()), "ms": ms,
+            "pins_per_s": (nn + ns) / (ms * 1e-3), "algorithmic_GBps": algo / (ms * 1e-3) / 1e9}
+
+
 _SCHED_NAMES = {0: "persistent", 1: "per-level", 2: "graph"}
 
 
@@ -220,7 +263,9 @@ def main() -> int:
     ap.add_argument("--sched", default="auto",
                     help="auto (tuned at setup), 0 persistent, 1 one launch per level, 2 HIP graph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-side", action="store_true", help="skip the adjoint and batched side measurements")
+    ap.add_argument("--no-side", action="store_true", help="skip every side measurement")
+    ap.add_argument("--side", default="incremental,rc_estimate,adjoint,batched",
+                    help="comma list of side measurements to run")
     ap.add_argument("--batch-designs", type=int, default=256)
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (counter calibration)")
@@ -319,11 +364,17 @@ def main() -> int:
         "wns_ps": [float(x) for x in wns_tns["wns"]],
         "tns_ps": [float(x) for x in wns_tns["tns"]],
     }
-    if not args.no_side:
+    side = set() if args.no_side else set(args.side.split(","))
+    if "incremental" in side:
         print("[bench] incremental updates", file=sys.stderr, flush=True)
         out["incremental"] = incremental_updates(design, sched, s_blocks, ms)
+    if "rc_estimate" in side:
+        print("[bench] RC estimation from pin positions", file=sys.stderr, flush=True)
+        out["rc_estimate"] = rc_estimate_side(design)
+    if "adjoint" in side:
         print("[bench] adjoint ratio (1M-pin smooth)", file=sys.stderr, flush=True)
         out["adjoint"] = adjoint_ratio(args.steps)
+    if "batched" in side:
         print("[bench] batched vs per-design", file=sys.stderr, flush=True)
         out["batched"] = batched_vs_per_design(args.steps, args.batch_designs)
     if not args.no_cpu_baseline:

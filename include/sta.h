@@ -260,6 +260,9 @@ sta_status sta_get_phase_times(sta_ctx *ctx, float *ms, int32_t *n);
  * gradient of J = g_tns TNS_g + g_wns WNS_g with respect to:
  *   grad_wire_cap  [n_nodes]    every RC node's ground cap, caller node order
  *                               (through the RC moments and the driver's load);
+ *   grad_wire_res  [n_nodes]    every segment's resistance (parent -> node),
+ *                               caller node order, through the RC moments
+ *                               (0 at net roots);
  *   grad_pin_load  [n_pins]     each cell output's NLDM load (partial through
  *                               the lookups only; 0 on other pins);
  *   grad_arc_delay [n_arcs][4]  each cell arc's additive delay per output view
@@ -269,8 +272,8 @@ sta_status sta_get_phase_times(sta_ctx *ctx, float *ms, int32_t *n);
  * sweep recomputes delays, softmax weights and table partials from them.
  * Gradients are accumulated in a fixed order (bitwise reproducible).
  * STA_E_STATE if the context is not in mode 1 or was never updated. */
-sta_status sta_backward(sta_ctx *ctx, float g_tns, float g_wns, float *grad_wire_cap, float *grad_pin_load,
-                        float *grad_arc_delay, sta_mem dst, void *stream);
+sta_status sta_backward(sta_ctx *ctx, float g_tns, float g_wns, float *grad_wire_cap, float *grad_wire_res,
+                        float *grad_pin_load, float *grad_arc_delay, sta_mem dst, void *stream);
 
 /* Batched form (not in the paper; the paper's flows time one design per call).
  * Times n_designs independent designs that share one cell library (one
@@ -357,6 +360,72 @@ typedef struct {
 sta_status sta_report_paths(sta_ctx *ctx, const sta_path_query *q, int32_t *n_paths, int32_t *path_ptr,
                             int32_t *path_pin, int8_t *path_rf, float *path_slack, int32_t *path_endpoint,
                             sta_mem dst, void *stream);
+
+/* RC trees estimated from pin positions (§III "Parasitics (RC) inputs": in
+ * placement flows the timer derives each net's RC tree itself from pin
+ * coordinates and per-unit-length resistance and capacitance along x and y).
+ * Per net: a rectilinear minimum spanning tree grown from the driver by
+ * Prim's rule (Manhattan distances evaluated in FP32; the next pin is the
+ * outside pin nearest to the tree, ties to the lower pin index, pin 0 the
+ * driver and pins 1..k the sinks in net_sink_pin order; its parent is the
+ * earliest-joined tree pin at that distance).  Each tree edge parent -> pin
+ * is wired as an L, along x to a corner at (x_pin, y_parent), then along y
+ * to the pin.  The t-th pin to join owns net-local nodes 2t-1 (corner,
+ * parent = the parent pin's node, R = r_x |dx|, C = c_x |dx|) and 2t (the
+ * pin, parent 2t-1, R = r_y |dy|, C = c_y |dy|): FP32 products, each
+ * segment's capacitance lumped at its far node; node 0 is the driver with
+ * R = C = 0.  A net of k sinks has 2k+1 nodes, net n starts at node
+ * n + 2 * net_sink_ptr[n], so the output is an sta_rc_desc of
+ * n_nets + 2 * n_sinks nodes, ready for sta_create.  The paper builds FLUTE
+ * Steiner trees here; the spanning tree is a documented stand-in (its wire
+ * length is at most 1.5x the Steiner minimum).
+ *
+ *   g          netlist (only n_pins, n_nets and the net CSR are read), host or
+ *              device memory per g->mem
+ *   pin_x/y    [n_pins] positions (um), finite and at most 1e18 in
+ *              magnitude; `mem` memory
+ *   w          unit wire values, finite and >= 0; host memory
+ *   outputs    net_node_ptr [n_nets+1], parent / res_kohm / cap_ff
+ *              [n_nets + 2 n_sinks], sink_node [n_sinks]; `mem` memory,
+ *              caller-allocated
+ * Nets may have at most 12287 sinks (else STA_E_UNSUPPORTED).  Malformed
+ * net CSR, a pin index out of range or a position out of range give
+ * STA_E_ARG; they are checked on the device before any tree is built, and
+ * then no output is written.  Allocates device scratch; synchronizes
+ * `stream` twice (after the check and at the end). */
+typedef struct {
+  float r_x, r_y;              /* kOhm per um along x, y */
+  float c_x, c_y;              /* fF per um along x, y */
+} sta_wire_params;
+sta_status sta_estimate_rc(const sta_graph_desc *g, const float *pin_x, const float *pin_y,
+                           const sta_wire_params *w, int64_t *net_node_ptr, int32_t *parent, float *res_kohm,
+                           float *cap_ff, int32_t *sink_node, sta_mem mem, void *stream);
+
+/* Gradient to pin positions through estimated RC trees (the placement side
+ * of §III "Parasitics (RC) inputs": with the trees of sta_estimate_rc held
+ * fixed, each L-shaped edge from parent pin p to pin c sets R and C of its
+ * corner node from |x_c - x_p| and of its pin node from |y_c - y_p|).  Given
+ * dJ/dR and dJ/dC per node (e.g. grad_wire_res and grad_wire_cap of
+ * sta_backward on a context created from those trees), writes
+ *   dJ/dx_c += sgn(x_c - x_p) (r_x dJ/dR_corner + c_x dJ/dC_corner),
+ *   dJ/dx_p -= the same,  and likewise along y with the pin node,
+ * with sgn(0) = 0 (the zero subgradient of a segment of no length).  Pins on
+ * no net get 0; a pin on several nets gets an unspecified one of them (the
+ * netlists of sta_create have every pin on one net).
+ *
+ *   g, pin_x/y, w        as for sta_estimate_rc (same positions)
+ *   parent, sink_node    the trees sta_estimate_rc wrote for them
+ *   grad_res, grad_cap   [n_nets + 2 n_sinks] per node; `mem` memory
+ *   grad_x, grad_y       [n_pins] outputs; `mem` memory
+ * Terms are added in a fixed order (nets up to 64 pins, in FP32) or as
+ * integers of 2^-48 of the net's largest term (larger nets), so results are
+ * bitwise reproducible.  Errors as sta_estimate_rc, plus STA_E_ARG for a
+ * sink_node or corner parent that no estimated tree has.  Allocates device
+ * scratch; synchronizes `stream`. */
+sta_status sta_estimate_rc_backward(const sta_graph_desc *g, const float *pin_x, const float *pin_y,
+                                    const sta_wire_params *w, const int32_t *parent, const int32_t *sink_node,
+                                    const float *grad_res, const float *grad_cap, float *grad_x, float *grad_y,
+                                    sta_mem mem, void *stream);
 
 /* Name of a status code; message of the calling thread's last error. */
 const char *sta_status_string(sta_status s);

@@ -42,6 +42,7 @@ class _ODesign(ctypes.Structure):
         ("pi_at", _PF), ("pi_slew", _PF), ("po_rat", _PF),
         ("dangling_rat", ctypes.c_float * 4),
         ("dangling_policy", ctypes.c_int32),
+        ("res64", _PD),
     ]
 
 
@@ -100,7 +101,7 @@ class _Keep:
         return _ptr(a, typ)
 
 
-def _odesign(d, keep: _Keep) -> _ODesign:
+def _odesign(d, keep: _Keep, wire_res=None) -> _ODesign:
     i32 = lambda a: keep(a, np.int32, _P32)  # noqa: E731
     f32 = lambda a: keep(a, np.float32, _PF)  # noqa: E731
     od = _ODesign()
@@ -124,6 +125,7 @@ def _odesign(d, keep: _Keep) -> _ODesign:
     for v in range(4):
         od.dangling_rat[v] = float(d.dangling_rat[v])
     od.dangling_policy = int(d.dangling_policy)
+    od.res64 = None if wire_res is None else keep(wire_res, np.float64, _PD)
     return od
 
 
@@ -248,13 +250,14 @@ def _smooth_finish(r, o):
     return r
 
 
-def smooth_sta(d, gamma, wire_cap=None):
+def smooth_sta(d, gamma, wire_cap=None, wire_res=None):
     """Smooth forward: late AT merges by log-sum-exp (temperature gamma), smooth
-    late endpoint slack, TNS_g and WNS_g."""
+    late endpoint slack, TNS_g and WNS_g.  wire_cap / wire_res (FP64, caller
+    node order) override the design's node caps / segment resistances."""
     lib, keep = _load(), _Keep()
     lib.orc_smooth_sta.restype = ctypes.c_int
     lib.orc_smooth_sta.argtypes = [ctypes.POINTER(_ODesign), _PD, ctypes.c_double, ctypes.POINTER(_OSmooth)]
-    od = _odesign(d, keep)
+    od = _odesign(d, keep, wire_res)
     r, o = _smooth_struct(d)
     wc = None if wire_cap is None else keep(wire_cap, np.float64, _PD)
     if lib.orc_smooth_sta(ctypes.byref(od), wc, float(gamma), ctypes.byref(o)):
@@ -262,22 +265,24 @@ def smooth_sta(d, gamma, wire_cap=None):
     return _smooth_finish(r, o)
 
 
-def smooth_adjoint(d, gamma, g_tns=1.0, g_wns=0.0, wire_cap=None):
-    """Gradient of g_tns*TNS_g + g_wns*WNS_g: per RC node cap (caller node
-    order), per pin NLDM load (cell outputs), per arc and late view delay."""
+def smooth_adjoint(d, gamma, g_tns=1.0, g_wns=0.0, wire_cap=None, wire_res=None):
+    """Gradient of g_tns*TNS_g + g_wns*WNS_g: per RC node cap and segment
+    resistance (caller node order), per pin NLDM load (cell outputs), per arc
+    and late view delay."""
     lib, keep = _load(), _Keep()
     lib.orc_smooth_adjoint.restype = ctypes.c_int
     lib.orc_smooth_adjoint.argtypes = [ctypes.POINTER(_ODesign), _PD, ctypes.c_double, ctypes.c_double,
-                                       ctypes.c_double, _PD, _PD, _PD, ctypes.POINTER(_OSmooth)]
-    od = _odesign(d, keep)
+                                       ctypes.c_double, _PD, _PD, _PD, _PD, ctypes.POINTER(_OSmooth)]
+    od = _odesign(d, keep, wire_res)
     r, o = _smooth_struct(d)
     gc = np.zeros(int(d.n_nodes))
+    gr = np.zeros(int(d.n_nodes))
     gl = np.zeros(d.n_pins)
     ga = np.zeros((int(d.cell_in_ptr[-1]), 4))
     wc = None if wire_cap is None else keep(wire_cap, np.float64, _PD)
     if lib.orc_smooth_adjoint(ctypes.byref(od), wc, float(gamma), float(g_tns), float(g_wns),
-                              _ptr(gc, _PD), _ptr(gl, _PD), _ptr(ga, _PD), ctypes.byref(o)):
+                              _ptr(gc, _PD), _ptr(gr, _PD), _ptr(gl, _PD), _ptr(ga, _PD), ctypes.byref(o)):
         raise ValueError("combinational cycle")
     r = _smooth_finish(r, o)
-    r["grad_wire_cap"], r["grad_pin_load"], r["grad_arc_delay"] = gc, gl, ga
+    r["grad_wire_cap"], r["grad_wire_res"], r["grad_pin_load"], r["grad_arc_delay"] = gc, gr, gl, ga
     return r

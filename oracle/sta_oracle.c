@@ -48,7 +48,12 @@ typedef struct {
   const float *pi_at, *pi_slew, *po_rat; /* [n_pi][4], [n_pi][4], [n_po][4] */
   float dangling_rat[4];
   int32_t dangling_policy; /* 1: cell outputs without fanout are endpoints */
+  const double *res64;     /* FP64 segment resistances overriding res_kohm when non-NULL */
 } orc_design;
+
+static double seg_res(const orc_design *D, int64_t k) {
+  return D->res64 ? D->res64[k] : (double)D->res_kohm[k];
+}
 
 typedef struct {
   int32_t *level, *level_order;    /* [n_pins] */
@@ -204,7 +209,7 @@ void orc_rc(const orc_design *D, const double *wire_cap, double *L_net, double *
   for (int32_t n = 0; n < D->n_nets; n++) {
     int64_t base = D->net_node_ptr[n], m = D->net_node_ptr[n + 1] - base;
     for (int64_t k = 0; k < m; k++) {
-      R[k] = (double)D->res_kohm[base + k];
+      R[k] = seg_res(D, base + k);
       Chat[k] = wire_cap ? wire_cap[base + k] : (double)D->cap_ff[base + k];
     }
     for (int32_t s = D->net_sink_ptr[n]; s < D->net_sink_ptr[n + 1]; s++) Chat[D->sink_node[s]] += pc[s];
@@ -585,12 +590,14 @@ int orc_smooth_sta(const orc_design *D, const double *wire_cap, double gamma, or
 }
 
 /* Gradient of J = g_tns TNS_g + g_wns WNS_g with respect to every RC node's
- * ground cap (caller node order), every cell output's NLDM load (the partial
- * through the lookups only, per pin) and every cell arc's additive delay per
- * late output view (arcs in cell_in_pin order, [n_arcs][4], early views 0).
- * Reverse mode over the smooth forward, in reverse level order. */
+ * ground cap and every segment's resistance (caller node order; grad_res may
+ * be NULL), every cell output's NLDM load (the partial through the lookups
+ * only, per pin) and every cell arc's additive delay per late output view
+ * (arcs in cell_in_pin order, [n_arcs][4], early views 0).  Reverse mode over
+ * the smooth forward, in reverse level order. */
 int orc_smooth_adjoint(const orc_design *D, const double *wire_cap, double gamma, double g_tns, double g_wns,
-                       double *grad_cap, double *grad_load, double *grad_arc, orc_smooth_result *fwd) {
+                       double *grad_cap, double *grad_res, double *grad_load, double *grad_arc,
+                       orc_smooth_result *fwd) {
   int32_t NP = D->n_pins, nl;
   int32_t NS = D->net_sink_ptr[D->n_nets];
   int32_t *level = malloc(sizeof(int32_t) * (size_t)NP), *order = malloc(sizeof(int32_t) * (size_t)NP);
@@ -694,7 +701,11 @@ int orc_smooth_adjoint(const orc_design *D, const double *wire_cap, double gamma
    * so, with gd_v = dJ/dd_v - 2 d_v dJ/dq_v and gm_v = 2 dJ/dq_v at sink nodes,
    *   dJ/dC_k = gL + sum_{a on path(k)} R_a Gd(a) + d_k H_k + sum_{a on path(k)} R_a K(a)
    *   Gd(a) = subtree sum of gd, H_j = sum_{a on path(j)} R_a Gm(a),
-   *   Gm(a) = subtree sum of gm, K(a) = subtree sum of C^ H. */
+   *   Gm(a) = subtree sum of gm, K(a) = subtree sum of C^ H.
+   * A segment's resistance enters d_v as R_k S1_k (S1 = downstream cap) on
+   * every path through k, and m2_v as R_k S2_k (S2 = subtree sum of C^ d)
+   * plus through the d_j inside S2 of the segments above, which gives
+   *   dJ/dR_k = S1_k (Gd(k) + K(k)) + S2_k Gm(k),   dJ/dR_root = 0. */
   double *pc = malloc(sizeof(double) * (size_t)(NS > 0 ? NS : 1));
   sink_pincaps(D, &R, pc);
   int64_t maxm = 1;
@@ -712,7 +723,7 @@ int orc_smooth_adjoint(const orc_design *D, const double *wire_cap, double gamma
     int64_t base = D->net_node_ptr[n], m = D->net_node_ptr[n + 1] - base;
     const int32_t *par = D->parent + base;
     for (int64_t k = 0; k < m; k++) {
-      Rv[k] = (double)D->res_kohm[base + k];
+      Rv[k] = seg_res(D, base + k);
       Ch[k] = wire_cap ? wire_cap[base + k] : (double)D->cap_ff[base + k];
       Gd[k] = Gm[k] = 0.0;
     }
@@ -737,6 +748,10 @@ int orc_smooth_adjoint(const orc_design *D, const double *wire_cap, double gamma
     }
     for (int64_t k = 0; k < m; k++) K[k] = Ch[k] * H[k];
     for (int64_t k = m - 1; k >= 1; k--) K[par[k]] += K[k];
+    if (grad_res) {
+      grad_res[base] = 0.0;
+      for (int64_t k = 1; k < m; k++) grad_res[base + k] = load[k] * (Gd[k] + K[k]) + ld[k] * Gm[k];
+    }
     PB[0] = 0.0;
     for (int64_t k = 1; k < m; k++) PB[k] = PB[par[k]] + Rv[k] * K[k];
     for (int64_t k = 0; k < m; k++) grad_cap[base + k] = gL[n] + PA[k] + dd[k] * H[k] + PB[k];

@@ -46,7 +46,8 @@ def build_sta() -> str:
     without a hard dependency on one HIP runtime copy: the process supplies it
     (the binding preloads the runtime the process already uses, so torch and
     this library share one HIP/HSA runtime, its streams and allocations)."""
-    srcs = [os.path.join(CSRC, "sta_kernels.hip"), os.path.join(CSRC, "sta_host.cpp")]
+    srcs = [os.path.join(CSRC, "sta_kernels.hip"), os.path.join(CSRC, "sta_rc_estimate.hip"),
+            os.path.join(CSRC, "sta_host.cpp")]
     objs = []
     bdir = os.path.join(CSRC, "_build")
     os.makedirs(bdir, exist_ok=True)

@@ -1,0 +1,55 @@
+// Internal interface of the RC estimator (sta_rc_estimate.hip), shared with
+// the host entry point.  Kept apart from the timing kernels' header.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace sta {
+
+// RC estimation from pin positions (sta_rc_estimate.hip)
+constexpr int kEstMaxPins = 12288;  // largest net (driver + sinks) the estimator takes
+struct EstArgs {
+  int n_nets;
+  const int32_t *driver, *sink_ptr, *sink_pin;  // caller net CSR
+  const float *x, *y;                           // [n_pins] positions (um)
+  float rx, ry, cx, cy;                         // kOhm / um and fF / um along x, y
+  int64_t *node_ptr;                            // outputs: RC CSR of every net
+  int32_t *parent;
+  float *res, *cap;
+  int32_t *sink_node;
+};
+// st[6] (caller-initialized to {0, 0, 0, ~0, ~0, ~0}): nets of 9..64 pins,
+// nets above 64 pins, their largest sink count, first bad net, first bad sink
+// entry, first pin position not finite or beyond 1e18 in magnitude
+hipError_t launch_est_check(const EstArgs &A, int n_pins, int n_sinks, int32_t *mid, int32_t *big, uint32_t *st,
+                            hipStream_t s);
+// n_mid = st[0], n_big = st[1] as read back by the host; the kernels read
+// the counts from st as well
+hipError_t launch_est(const EstArgs &A, const int32_t *mid, const int32_t *big, const uint32_t *st, uint32_t n_mid,
+                      uint32_t n_big, hipStream_t s);
+
+// Gradient of an objective J with respect to pin positions, through the
+// estimated trees (same net CSR and positions as the estimation).
+struct EstGradArgs {
+  int n_nets;
+  const int32_t *driver, *sink_ptr, *sink_pin;
+  const float *x, *y;
+  float rx, ry, cx, cy;
+  const int32_t *parent, *sink_node;  // the estimated trees (net n at node n + 2 sink_ptr[n])
+  const float *g_res, *g_cap;         // dJ/dR, dJ/dC per node
+  float *gx, *gy;                     // [n_pins] outputs (pins on no net untouched)
+};
+// st[3] (caller-initialized to {0, 0, ~0}): nets of 9..64 pins, nets above
+// 64 pins, first sink with a bad tree entry; off[n_nets] / *total (zeroed by
+// the caller): accumulator offsets of the big nets and their sum
+hipError_t launch_estg_check(const EstGradArgs &G, int n_sinks, int32_t *mid, int32_t *big, int64_t *off,
+                             unsigned long long *total, uint32_t *st, hipStream_t s);
+// the sink checks of the nets above 64 pins (count read from st[1] on the
+// device), stream-ordered after launch_estg_check
+hipError_t launch_estg_check_big(const EstGradArgs &G, const int32_t *big, uint32_t *st, hipStream_t s);
+// acc: 2 * total zeroed int64 accumulators
+hipError_t launch_estg(const EstGradArgs &G, const int32_t *mid, const int32_t *big, const uint32_t *st,
+                       const int64_t *off, unsigned long long *acc, uint32_t n_mid, uint32_t n_big, hipStream_t s);
+
+}  // namespace sta

@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "sta.h"
+#include "sta_est.h"
 #include "sta_internal.h"
 
 using namespace sta;
@@ -994,6 +995,7 @@ static sta_status build_layout(sta_ctx *C, const Inputs &I, const std::vector<in
     STA_TRY(C->alloc(&D.g_load, ND));
     STA_TRY(C->alloc(&D.g_arc, std::max(C->n_fanin, 1)));
     STA_TRY(C->alloc(&D.g_cap, NN));
+    STA_TRY(C->alloc(&D.g_res, NN));
   }
   STA_TRY(C->alloc(&C->big_scratch, (size_t)std::max<int64_t>(big_scr, 1)));
   STA_TRY(C->alloc(&C->partials, 8 * kReduceBlocks));
@@ -1563,8 +1565,266 @@ extern "C" sta_status sta_update_timing_incremental(sta_ctx *C, const int32_t *n
   return STA_OK;
 }
 
+namespace {
+// Device buffers of a call that has no context, freed when it returns.
+struct CallScratch {
+  std::vector<std::unique_ptr<DevMem>> mem;
+  template <typename T>
+  sta_status alloc(T **out_p, size_t n) {
+    auto m = std::make_unique<DevMem>();
+    hipError_t e = hipMalloc(&m->p, std::max<size_t>(n, 1) * sizeof(T));
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+    *out_p = static_cast<T *>(m->p);
+    mem.push_back(std::move(m));
+    return STA_OK;
+  }
+};
+}  // namespace
+
+// RC trees from pin positions (no context; see sta.h).  Host inputs go up to
+// scratch buffers, every input is checked by one device pass whose result the
+// host reads before the estimation kernels start, host outputs come back.
+extern "C" sta_status sta_estimate_rc(const sta_graph_desc *g, const float *pin_x, const float *pin_y,
+                                      const sta_wire_params *w, int64_t *net_node_ptr, int32_t *parent,
+                                      float *res_kohm, float *cap_ff, int32_t *sink_node, sta_mem mem,
+                                      void *stream) {
+  if (!g || !w) return fail(STA_E_ARG, "NULL graph or wire parameters");
+  if (mem != STA_HOST && mem != STA_DEVICE) return fail(STA_E_ARG, "bad mem");
+  if (g->mem != STA_HOST && g->mem != STA_DEVICE) return fail(STA_E_ARG, "bad graph mem");
+  if (g->n_nets < 0 || g->n_pins < 0) return fail(STA_E_ARG, "negative sizes");
+  for (float v : {w->r_x, w->r_y, w->c_x, w->c_y})
+    if (!std::isfinite(v) || v < 0.0f) return fail(STA_E_ARG, "wire parameters must be finite and >= 0");
+  const int NN = g->n_nets, NP = g->n_pins;
+  if (!net_node_ptr || !g->net_sink_ptr || (NN > 0 && !g->net_driver) || (NP > 0 && (!pin_x || !pin_y)))
+    return fail(STA_E_ARG, "NULL array");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  CallScratch tmp;  // freed on return, after the final synchronization or an error
+  int32_t n_sinks = 0;
+  if (g->mem == STA_HOST) {
+    n_sinks = g->net_sink_ptr[NN];
+  } else {
+    HIP_TRY(hipMemcpyAsync(&n_sinks, g->net_sink_ptr + NN, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  if (n_sinks < 0) return fail(STA_E_ARG, "net_sink_ptr[n_nets] < 0");
+  if (n_sinks > 0 && !g->net_sink_pin) return fail(STA_E_ARG, "NULL net_sink_pin");
+  const int64_t n_nodes = (int64_t)NN + 2 * (int64_t)n_sinks;
+  if (n_nodes > 0 && (!parent || !res_kohm || !cap_ff)) return fail(STA_E_ARG, "NULL RC output array");
+  if (n_sinks > 0 && !sink_node) return fail(STA_E_ARG, "NULL sink_node");
+  EstArgs A{};
+  A.n_nets = NN;
+  A.rx = w->r_x;
+  A.ry = w->r_y;
+  A.cx = w->c_x;
+  A.cy = w->c_y;
+  auto up = [&](auto **dst, const auto *src, size_t n) -> sta_status {
+    STA_TRY(tmp.alloc(dst, std::max<size_t>(n, 1)));
+    if (n > 0) HIP_TRY(hipMemcpyAsync(*dst, src, n * sizeof(*src), hipMemcpyHostToDevice, s));
+    return STA_OK;
+  };
+  if (g->mem == STA_HOST) {
+    int32_t *d_drv, *d_nsp, *d_pin;
+    STA_TRY(up(&d_drv, g->net_driver, (size_t)NN));
+    STA_TRY(up(&d_nsp, g->net_sink_ptr, (size_t)NN + 1));
+    STA_TRY(up(&d_pin, g->net_sink_pin, (size_t)n_sinks));
+    A.driver = d_drv;
+    A.sink_ptr = d_nsp;
+    A.sink_pin = d_pin;
+  } else {
+    A.driver = g->net_driver;
+    A.sink_ptr = g->net_sink_ptr;
+    A.sink_pin = g->net_sink_pin;
+  }
+  if (mem == STA_HOST) {
+    float *dx, *dy;
+    STA_TRY(up(&dx, pin_x, (size_t)NP));
+    STA_TRY(up(&dy, pin_y, (size_t)NP));
+    A.x = dx;
+    A.y = dy;
+    STA_TRY(tmp.alloc(&A.node_ptr, (size_t)NN + 1));
+    STA_TRY(tmp.alloc(&A.parent, (size_t)std::max<int64_t>(n_nodes, 1)));
+    STA_TRY(tmp.alloc(&A.res, (size_t)std::max<int64_t>(n_nodes, 1)));
+    STA_TRY(tmp.alloc(&A.cap, (size_t)std::max<int64_t>(n_nodes, 1)));
+    STA_TRY(tmp.alloc(&A.sink_node, (size_t)std::max(n_sinks, 1)));
+  } else {
+    A.x = pin_x;
+    A.y = pin_y;
+    A.node_ptr = net_node_ptr;
+    A.parent = parent;
+    A.res = res_kohm;
+    A.cap = cap_ff;
+    A.sink_node = sink_node;
+  }
+  int32_t *mid, *big;
+  uint32_t *st;
+  STA_TRY(tmp.alloc(&mid, (size_t)NN));
+  STA_TRY(tmp.alloc(&big, (size_t)NN));
+  STA_TRY(tmp.alloc(&st, 6));
+  const uint32_t st0[6] = {0u, 0u, 0u, ~0u, ~0u, ~0u};
+  HIP_TRY(hipMemcpyAsync(st, st0, sizeof st0, hipMemcpyHostToDevice, s));
+  HIP_TRY(launch_est_check(A, NP, n_sinks, mid, big, st, s));
+  uint32_t h[6];
+  HIP_TRY(hipMemcpyAsync(h, st, sizeof h, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (h[3] != ~0u) return fail(STA_E_ARG, "net %u: bad net_sink_ptr or net_driver", h[3]);
+  if (h[4] != ~0u) return fail(STA_E_ARG, "net_sink_pin[%u] out of range", h[4]);
+  if (h[5] != ~0u) return fail(STA_E_ARG, "pin %u: position not finite or beyond 1e18 in magnitude", h[5]);
+  if (h[1] > 0 && (int64_t)h[2] + 1 > kEstMaxPins)
+    return fail(STA_E_UNSUPPORTED, "a net has %u sinks (at most %d)", h[2], kEstMaxPins - 1);
+  if (NN == 0) {
+    const int64_t zero = 0;
+    HIP_TRY(hipMemcpyAsync(A.node_ptr, &zero, sizeof zero, hipMemcpyHostToDevice, s));
+  }
+  HIP_TRY(launch_est(A, mid, big, st, h[0], h[1], s));
+  if (mem == STA_HOST) {
+    HIP_TRY(hipMemcpyAsync(net_node_ptr, A.node_ptr, ((size_t)NN + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    if (n_nodes > 0) {
+      HIP_TRY(hipMemcpyAsync(parent, A.parent, n_nodes * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipMemcpyAsync(res_kohm, A.res, n_nodes * sizeof(float), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipMemcpyAsync(cap_ff, A.cap, n_nodes * sizeof(float), hipMemcpyDeviceToHost, s));
+    }
+    if (n_sinks > 0)
+      HIP_TRY(hipMemcpyAsync(sink_node, A.sink_node, n_sinks * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  return STA_OK;
+}
+
+// Gradient to pin positions through estimated trees (no context; see sta.h).
+extern "C" sta_status sta_estimate_rc_backward(const sta_graph_desc *g, const float *pin_x, const float *pin_y,
+                                               const sta_wire_params *w, const int32_t *parent,
+                                               const int32_t *sink_node, const float *grad_res,
+                                               const float *grad_cap, float *grad_x, float *grad_y, sta_mem mem,
+                                               void *stream) {
+  if (!g || !w) return fail(STA_E_ARG, "NULL graph or wire parameters");
+  if (mem != STA_HOST && mem != STA_DEVICE) return fail(STA_E_ARG, "bad mem");
+  if (g->mem != STA_HOST && g->mem != STA_DEVICE) return fail(STA_E_ARG, "bad graph mem");
+  if (g->n_nets < 0 || g->n_pins < 0) return fail(STA_E_ARG, "negative sizes");
+  for (float v : {w->r_x, w->r_y, w->c_x, w->c_y})
+    if (!std::isfinite(v) || v < 0.0f) return fail(STA_E_ARG, "wire parameters must be finite and >= 0");
+  const int NN = g->n_nets, NP = g->n_pins;
+  if (!g->net_sink_ptr || (NN > 0 && !g->net_driver) || (NP > 0 && (!pin_x || !pin_y || !grad_x || !grad_y)))
+    return fail(STA_E_ARG, "NULL array");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  CallScratch tmp;
+  int32_t n_sinks = 0;
+  if (g->mem == STA_HOST) {
+    n_sinks = g->net_sink_ptr[NN];
+  } else {
+    HIP_TRY(hipMemcpyAsync(&n_sinks, g->net_sink_ptr + NN, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  if (n_sinks < 0) return fail(STA_E_ARG, "net_sink_ptr[n_nets] < 0");
+  if (n_sinks > 0 && (!g->net_sink_pin || !sink_node)) return fail(STA_E_ARG, "NULL sink array");
+  const int64_t n_nodes = (int64_t)NN + 2 * (int64_t)n_sinks;
+  if (n_nodes > 0 && (!parent || !grad_res || !grad_cap)) return fail(STA_E_ARG, "NULL node array");
+  auto up = [&](auto **dst, const auto *src, size_t n) -> sta_status {
+    STA_TRY(tmp.alloc(dst, std::max<size_t>(n, 1)));
+    if (n > 0) HIP_TRY(hipMemcpyAsync(*dst, src, n * sizeof(*src), hipMemcpyHostToDevice, s));
+    return STA_OK;
+  };
+  EstArgs A{};
+  EstGradArgs G{};
+  A.n_nets = G.n_nets = NN;
+  A.rx = G.rx = w->r_x;
+  A.ry = G.ry = w->r_y;
+  A.cx = G.cx = w->c_x;
+  A.cy = G.cy = w->c_y;
+  if (g->mem == STA_HOST) {
+    int32_t *d_drv, *d_nsp, *d_pin;
+    STA_TRY(up(&d_drv, g->net_driver, (size_t)NN));
+    STA_TRY(up(&d_nsp, g->net_sink_ptr, (size_t)NN + 1));
+    STA_TRY(up(&d_pin, g->net_sink_pin, (size_t)n_sinks));
+    A.driver = d_drv;
+    A.sink_ptr = d_nsp;
+    A.sink_pin = d_pin;
+  } else {
+    A.driver = g->net_driver;
+    A.sink_ptr = g->net_sink_ptr;
+    A.sink_pin = g->net_sink_pin;
+  }
+  G.driver = A.driver;
+  G.sink_ptr = A.sink_ptr;
+  G.sink_pin = A.sink_pin;
+  if (mem == STA_HOST) {
+    float *dx, *dy, *gr, *gc, *ox, *oy;
+    int32_t *par, *snode;
+    STA_TRY(up(&dx, pin_x, (size_t)NP));
+    STA_TRY(up(&dy, pin_y, (size_t)NP));
+    STA_TRY(up(&par, parent, (size_t)n_nodes));
+    STA_TRY(up(&snode, sink_node, (size_t)n_sinks));
+    STA_TRY(up(&gr, grad_res, (size_t)n_nodes));
+    STA_TRY(up(&gc, grad_cap, (size_t)n_nodes));
+    STA_TRY(tmp.alloc(&ox, (size_t)std::max(NP, 1)));
+    STA_TRY(tmp.alloc(&oy, (size_t)std::max(NP, 1)));
+    A.x = G.x = dx;
+    A.y = G.y = dy;
+    G.parent = par;
+    G.sink_node = snode;
+    G.g_res = gr;
+    G.g_cap = gc;
+    G.gx = ox;
+    G.gy = oy;
+  } else {
+    A.x = G.x = pin_x;
+    A.y = G.y = pin_y;
+    G.parent = parent;
+    G.sink_node = sink_node;
+    G.g_res = grad_res;
+    G.g_cap = grad_cap;
+    G.gx = grad_x;
+    G.gy = grad_y;
+  }
+  if (NP > 0) {
+    HIP_TRY(hipMemsetAsync(G.gx, 0, NP * sizeof(float), s));
+    HIP_TRY(hipMemsetAsync(G.gy, 0, NP * sizeof(float), s));
+  }
+  // checks: net CSR and positions as for the estimation, then the tree arrays
+  int32_t *mid, *big, *mid2, *big2;
+  int64_t *off;
+  uint32_t *st;
+  unsigned long long *total;
+  STA_TRY(tmp.alloc(&mid, (size_t)NN));
+  STA_TRY(tmp.alloc(&big, (size_t)NN));
+  STA_TRY(tmp.alloc(&mid2, (size_t)NN));
+  STA_TRY(tmp.alloc(&big2, (size_t)NN));
+  STA_TRY(tmp.alloc(&off, (size_t)NN));
+  STA_TRY(tmp.alloc(&st, 9));
+  STA_TRY(tmp.alloc(&total, 1));
+  const uint32_t st0[9] = {0u, 0u, 0u, ~0u, ~0u, ~0u, 0u, 0u, ~0u};
+  HIP_TRY(hipMemcpyAsync(st, st0, sizeof st0, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemsetAsync(total, 0, sizeof(unsigned long long), s));
+  HIP_TRY(launch_est_check(A, NP, n_sinks, mid, big, st, s));
+  uint32_t h[9];
+  HIP_TRY(hipMemcpyAsync(h, st, 6 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (h[3] != ~0u) return fail(STA_E_ARG, "net %u: bad net_sink_ptr or net_driver", h[3]);
+  if (h[4] != ~0u) return fail(STA_E_ARG, "net_sink_pin[%u] out of range", h[4]);
+  if (h[5] != ~0u) return fail(STA_E_ARG, "pin %u: position not finite or beyond 1e18 in magnitude", h[5]);
+  if (h[1] > 0 && (int64_t)h[2] + 1 > kEstMaxPins)
+    return fail(STA_E_UNSUPPORTED, "a net has %u sinks (at most %d)", h[2], kEstMaxPins - 1);
+  HIP_TRY(launch_estg_check(G, n_sinks, mid2, big2, off, total, st + 6, s));
+  HIP_TRY(launch_estg_check_big(G, big2, st + 6, s));
+  unsigned long long tot = 0;
+  HIP_TRY(hipMemcpyAsync(h + 6, st + 6, 3 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(&tot, total, sizeof tot, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (h[8] != ~0u) return fail(STA_E_ARG, "sink %u: sink_node or its corner's parent is not an estimated tree", h[8]);
+  unsigned long long *acc;
+  STA_TRY(tmp.alloc(&acc, (size_t)std::max<unsigned long long>(2 * tot, 1)));
+  if (tot > 0) HIP_TRY(hipMemsetAsync(acc, 0, 2 * tot * sizeof(unsigned long long), s));
+  HIP_TRY(launch_estg(G, mid2, big2, st + 6, off, acc, h[6], h[7], s));
+  if (mem == STA_HOST && NP > 0) {
+    HIP_TRY(hipMemcpyAsync(grad_x, G.gx, NP * sizeof(float), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(grad_y, G.gy, NP * sizeof(float), hipMemcpyDeviceToHost, s));
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  return STA_OK;
+}
+
 extern "C" sta_status sta_backward(sta_ctx *C, float g_tns, float g_wns, float *grad_wire_cap,
-                                   float *grad_pin_load, float *grad_arc_delay, sta_mem dst, void *stream) {
+                                   float *grad_wire_res, float *grad_pin_load, float *grad_arc_delay, sta_mem dst,
+                                   void *stream) {
   if (!C) return fail(STA_E_STATE, "NULL context");
   if (C->opt.mode != 1) return fail(STA_E_STATE, "sta_backward needs a context created with mode 1 (smooth)");
   if (!C->updated) return fail(STA_E_STATE, "sta_backward before sta_update_timing");
@@ -1581,21 +1841,24 @@ extern "C" sta_status sta_backward(sta_ctx *C, float g_tns, float g_wns, float *
   STA_TRY(enqueue_rc(C, s, true));
   if (prof) HIP_TRY(hipEventRecord(C->ev[9], s));
   C->bwd_timed = prof;
-  if (!grad_wire_cap && !grad_pin_load && !grad_arc_delay) return STA_OK;
+  if (!grad_wire_cap && !grad_wire_res && !grad_pin_load && !grad_arc_delay) return STA_OK;
   if (dst == STA_DEVICE) {
-    HIP_TRY(launch_scatter_grads(D, C->node_src, C->n_nodes, grad_wire_cap, C->pin_loc, C->n_pins, grad_pin_load,
-                                 C->arc_src, C->n_fanin, reinterpret_cast<float4 *>(grad_arc_delay), s));
+    HIP_TRY(launch_scatter_grads(D, C->node_src, C->n_nodes, grad_wire_cap, grad_wire_res, C->pin_loc, C->n_pins,
+                                 grad_pin_load, C->arc_src, C->n_fanin, reinterpret_cast<float4 *>(grad_arc_delay),
+                                 s));
     return STA_OK;
   }
   sta_ctx tmp;
-  float *gc = nullptr, *gl = nullptr;
+  float *gc = nullptr, *gr = nullptr, *gl = nullptr;
   float4 *ga = nullptr;
   if (grad_wire_cap) STA_TRY(tmp.alloc(&gc, (size_t)C->n_nodes));
+  if (grad_wire_res) STA_TRY(tmp.alloc(&gr, (size_t)C->n_nodes));
   if (grad_pin_load) STA_TRY(tmp.alloc(&gl, C->n_pins));
   if (grad_arc_delay) STA_TRY(tmp.alloc(&ga, std::max(C->n_fanin, 1)));
-  HIP_TRY(launch_scatter_grads(D, C->node_src, C->n_nodes, gc, C->pin_loc, C->n_pins, gl, C->arc_src, C->n_fanin,
-                               ga, s));
+  HIP_TRY(launch_scatter_grads(D, C->node_src, C->n_nodes, gc, gr, C->pin_loc, C->n_pins, gl, C->arc_src,
+                               C->n_fanin, ga, s));
   STA_TRY(deliver(grad_wire_cap, gc, (size_t)C->n_nodes * 4, STA_HOST, s));
+  STA_TRY(deliver(grad_wire_res, gr, (size_t)C->n_nodes * 4, STA_HOST, s));
   STA_TRY(deliver(grad_pin_load, gl, (size_t)C->n_pins * 4, STA_HOST, s));
   STA_TRY(deliver(grad_arc_delay, ga, (size_t)C->n_fanin * 16, STA_HOST, s));
   HIP_TRY(hipStreamSynchronize(s));

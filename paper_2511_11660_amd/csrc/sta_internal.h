@@ -116,6 +116,7 @@ struct DevDesign {
   float *g_load;                // [n_drv] dJ/d(NLDM load) of each cell output
   float2 *g_arc;                // [n_fanin] dJ/d(arc delay), late rise / fall output view
   float *g_cap;                 // [n_nodes] dJ/d(node cap), layout order
+  float *g_res;                 // [n_nodes] dJ/d(segment resistance), layout order
   double *norm;                 // [2] WNS_g normalisation (max shift M, denominator)
 
   // sweep schedule
@@ -142,7 +143,7 @@ struct BigNet {
 };
 constexpr int kWideBlock = 1024;            // threads per wide-net block
 constexpr int kWideSeg = 8192;              // preorder nodes per wide-net block
-constexpr int kBigScratch = 9;
+constexpr int kBigScratch = 11;
 
 // Packed-table offsets for one type.
 struct TabLayout {
@@ -219,8 +220,8 @@ hipError_t launch_reduce_smooth(const DevDesign &D, double *partials, double *ou
                                 int32_t *vals, hipStream_t s);
 hipError_t launch_adjoint_phase(const DevDesign &D, float g_tns, float g_wns, int4 phase, hipStream_t s);
 hipError_t launch_rc_adjoint(const DevDesign &D, const int2 *chunks, int n_chunks, hipStream_t s);
-hipError_t launch_scatter_grads(const DevDesign &D, const int32_t *node_src, int64_t n_nodes,
-                                float *grad_cap, const int32_t *pin_loc, int n_pins, float *grad_load,
+hipError_t launch_scatter_grads(const DevDesign &D, const int32_t *node_src, int64_t n_nodes, float *grad_cap,
+                                float *grad_res, const int32_t *pin_loc, int n_pins, float *grad_load,
                                 const int32_t *arc_src, int n_arcs, float4 *grad_arc, hipStream_t s);
 hipError_t launch_reduce(const DevDesign &D, double *partials, double *out, uint64_t *keys,
                          int32_t *vals, hipStream_t s);

@@ -2346,6 +2346,10 @@ __global__ __launch_bounds__(kSweepBlock) void k_adjoint(DevDesign D, float g_tn
 //   dJ/dC_k = dJ/dL + PA_k + d_k H_k + PB_k,
 //   PA_k = path sum of R Gd, H_k = path sum of R Gm, PB_k = path sum of R K,
 //   Gd, Gm = subtree sums of gd, gm, K = subtree sum of C^ H.
+// A segment's resistance enters d_v as R_k S1_k (S1 = downstream cap) and m2_v
+// as R_k S2_k (S2 = subtree sum of C^ d) plus through the d_j inside the S2 of
+// the segments above it, so
+//   dJ/dR_k = S1_k (Gd_k + K_k) + S2_k Gm_k   (0 at the root).
 // (dJ/dq is dropped where the clamp q = max(0, .) is active.)
 
 __device__ void rc_adjoint_wide(const DevDesign &D, const BigNet &B, const WideNets &W, WideCtx &c, double *s_w) {
@@ -2361,14 +2365,16 @@ __device__ void rc_adjoint_wide(const DevDesign &D, const BigNet &B, const WideN
   const float2 *gdq = D.g_dq + D.sink_ptr[x];
   const int st = m + 1;
   double *A = W.scratch + B.scr, *P = A + st, *X = P + st, *Y = X + st, *Z = Y + st;
-  double *G1 = Z + st, *G2 = G1 + st, *T = G2 + st, *V = T + st;
-  // forward moments: Y = d, Z = m2
+  double *G1 = Z + st, *G2 = G1 + st, *T = G2 + st, *V = T + st, *S1 = V + st, *DR = S1 + st;
+  // forward moments: Y = d, Z = m2; S1 = downstream cap, DR = S2 for now
   seg_map(c.k0, c.k1, [=](int k) { return (double)Cw[k] + (double)pc[k]; }, [=](int k, double v) { stc(A + k, v); });
   wide_scan(c, A, P, true, s_w);
+  seg_map(c.k0, c.k1, [=](int k) { return ldc(P + end[k]) - ldc(P + k); }, [=](int k, double v) { stc(S1 + k, v); });
   wide_edge(c, R, P, end, X);
   wide_path_sum(c, X, egp, egl, V, Y, s_w);
   seg_map(c.k0, c.k1, [=](int k) { return ldc(A + k) * ldc(Y + k); }, [=](int k, double v) { stc(X + k, v); });
   wide_scan(c, X, P, true, s_w);
+  seg_map(c.k0, c.k1, [=](int k) { return ldc(P + end[k]) - ldc(P + k); }, [=](int k, double v) { stc(DR + k, v); });
   wide_edge(c, R, P, end, X);
   wide_path_sum(c, X, egp, egl, V, Z, s_w);
   // sink-node seeds, sinks of a node in sink order
@@ -2388,6 +2394,10 @@ __device__ void rc_adjoint_wide(const DevDesign &D, const BigNet &B, const WideN
   wide_scan(c, G1, P, true, s_w);                           // Gd = subtree sums
   seg_map(c.k0, c.k1, [=](int k) { return ldc(P + end[k]) - ldc(P + k); }, [=](int k, double v) { stc(G1 + k, v); });
   wide_scan(c, G2, P, true, s_w);                           // Gm
+  // DR = S2 Gm + S1 Gd (K follows below); each k stays with its thread
+  seg_map(c.k0, c.k1,
+          [=](int k) { return ldc(DR + k) * (ldc(P + end[k]) - ldc(P + k)) + ldc(S1 + k) * ldc(G1 + k); },
+          [=](int k, double v) { stc(DR + k, v); });
   wide_edge(c, R, P, end, X);
   wide_path_sum(c, X, egp, egl, V, T, s_w);                 // H = path sum of R Gm
   seg_map(c.k0, c.k1, [=](int k) { return k ? (double)R[k] * ldc(G1 + k) : 0.0; },
@@ -2396,6 +2406,9 @@ __device__ void rc_adjoint_wide(const DevDesign &D, const BigNet &B, const WideN
   wide_path_sum(c, X, egp, egl, V, G1, s_w);                // PA = path sum of R Gd
   seg_map(c.k0, c.k1, [=](int k) { return ldc(A + k) * ldc(T + k); }, [=](int k, double v) { stc(X + k, v); });
   wide_scan(c, X, P, true, s_w);                            // K = subtree sum of C^ H
+  float *gres = D.g_res + k0;
+  seg_map(c.k0, c.k1, [=](int k) { return k ? (float)(ldc(DR + k) + ldc(S1 + k) * (ldc(P + end[k]) - ldc(P + k))) : 0.0f; },
+          [=](int k, float v) { gres[k] = v; });
   wide_edge(c, R, P, end, X);
   wide_path_sum(c, X, egp, egl, V, G2, s_w);                // PB = path sum of R K
   const double gL = (double)D.g_load[x];
@@ -2419,7 +2432,7 @@ __global__ __launch_bounds__(kWideBlock) void k_rc_adjoint_wide(DevDesign D, Wid
 __global__ __launch_bounds__(kRcBlock) void k_rc_adjoint(DevDesign D, const int2 *chunks, int n_chunks) {
   __shared__ uint8_t s_par[kRcChunkNodes];
   __shared__ float s_R[kRcChunkNodes], s_C[kRcChunkNodes], s_A[kRcChunkNodes], s_B[kRcChunkNodes];
-  __shared__ float s_E[kRcChunkNodes], s_F[kRcChunkNodes];
+  __shared__ float s_E[kRcChunkNodes], s_F[kRcChunkNodes], s_G[kRcChunkNodes];
   __shared__ int s_base[kRcBlock + 1];
   const int tid = threadIdx.x;
   const int ci = xcd_major(n_chunks);
@@ -2437,7 +2450,7 @@ __global__ __launch_bounds__(kRcBlock) void k_rc_adjoint(DevDesign D, const int2
   if (j < j1) {
     const int b = s_base[tid], m = s_base[tid + 1] - b;
     const uint8_t *par = s_par;
-    float *A = s_A, *B = s_B, *C = s_C, *E = s_E, *F = s_F, *R = s_R;
+    float *A = s_A, *B = s_B, *C = s_C, *E = s_E, *F = s_F, *G = s_G, *R = s_R;
     (void)rc_tree_lds(par, R, C, A, B, b, m);  // A = m2, B = d
     for (int k = 0; k < m; ++k) E[b + k] = F[b + k] = 0.0f;
     for (int s = sr.x; s < sr.y; ++s) {
@@ -2453,27 +2466,37 @@ __global__ __launch_bounds__(kRcBlock) void k_rc_adjoint(DevDesign D, const int2
     }
     A[b] = 0.0f;  // H
     for (int k = 1; k < m; ++k) A[b + k] = A[b + par[b + k]] + R[b + k] * F[b + k];
-    E[b] = 0.0f;  // PA, in place (parents first)
-    for (int k = 1; k < m; ++k) E[b + k] = E[b + par[b + k]] + R[b + k] * E[b + k];
+    for (int k = 0; k < m; ++k) G[b + k] = C[b + k] * B[b + k];  // S2
+    for (int k = m - 1; k >= 1; --k) G[b + par[b + k]] += G[b + k];
+    for (int k = 0; k < m; ++k) G[b + k] *= F[b + k];  // S2 Gm
     for (int k = 0; k < m; ++k) F[b + k] = C[b + k] * A[b + k];  // K
     for (int k = m - 1; k >= 1; --k) F[b + par[b + k]] += F[b + k];
-    F[b] = 0.0f;  // PB
+    for (int k = 0; k < m; ++k) F[b + k] += E[b + k];  // Gd + K
+    for (int k = 0; k < m; ++k) E[b + k] = C[b + k];  // S1
+    for (int k = m - 1; k >= 1; --k) E[b + par[b + k]] += E[b + k];
+    G[b] = 0.0f;
+    for (int k = 1; k < m; ++k) G[b + k] += E[b + k] * F[b + k];  // dJ/dR
+    F[b] = 0.0f;  // PA + PB = path sum of R (Gd + K), in place (parents first)
     for (int k = 1; k < m; ++k) F[b + k] = F[b + par[b + k]] + R[b + k] * F[b + k];
     const float gL = D.g_load[x];
-    for (int k = 0; k < m; ++k) C[b + k] = gL + E[b + k] + B[b + k] * A[b + k] + F[b + k];
+    for (int k = 0; k < m; ++k) C[b + k] = gL + F[b + k] + B[b + k] * A[b + k];
   }
   __syncthreads();
-  for (int i = tid; i < nk; i += kRcBlock) D.g_cap[k0 + i] = s_C[i];
+  for (int i = tid; i < nk; i += kRcBlock) {
+    D.g_cap[k0 + i] = s_C[i];
+    D.g_res[k0 + i] = s_G[i];
+  }
 }
 
 // Gradients back to caller order: node caps by the node permutation, NLDM
 // loads per cell-output pin (0 elsewhere), arc delays per caller arc (early
 // views 0).
-__global__ void k_scatter_grads(DevDesign D, const int32_t *node_src, int64_t n_nodes, float *grad_cap,
+__global__ void k_scatter_grads(DevDesign D, const int32_t *node_src, int64_t n_nodes, float *grad_cap, float *grad_res,
                                 const int32_t *pin_loc, int n_pins, float *grad_load, const int32_t *arc_src,
                                 int n_arcs, float4 *grad_arc) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (grad_cap && i < n_nodes) grad_cap[node_src[i]] = D.g_cap[i];
+  if (grad_res && i < n_nodes) grad_res[node_src[i]] = D.g_res[i];
   if (grad_load && i < n_pins) {
     const int loc = pin_loc[i];
     grad_load[i] = (loc >= D.n_pi) ? D.g_load[loc] : 0.0f;
@@ -2904,14 +2927,14 @@ hipError_t launch_rc_adjoint(const DevDesign &D, const int2 *chunks, int n_chunk
 }
 
 hipError_t launch_scatter_grads(const DevDesign &D, const int32_t *node_src, int64_t n_nodes, float *grad_cap,
-                                const int32_t *pin_loc, int n_pins, float *grad_load, const int32_t *arc_src,
-                                int n_arcs, float4 *grad_arc, hipStream_t s) {
+                                float *grad_res, const int32_t *pin_loc, int n_pins, float *grad_load,
+                                const int32_t *arc_src, int n_arcs, float4 *grad_arc, hipStream_t s) {
   int64_t n = n_nodes;
   if (n_pins > n) n = n_pins;
   if (n_arcs > n) n = n_arcs;
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_scatter_grads, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, D, node_src, n_nodes,
-                     grad_cap, pin_loc, n_pins, grad_load, arc_src, n_arcs, grad_arc);
+                     grad_cap, grad_res, pin_loc, n_pins, grad_load, arc_src, n_arcs, grad_arc);
   return hipGetLastError();
 }
 

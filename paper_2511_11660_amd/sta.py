@@ -81,6 +81,11 @@ class sta_path_query(ctypes.Structure):
                 ("el", ctypes.c_int32)]
 
 
+class sta_wire_params(ctypes.Structure):
+    _fields_ = [("r_x", ctypes.c_float), ("r_y", ctypes.c_float), ("c_x", ctypes.c_float),
+                ("c_y", ctypes.c_float)]
+
+
 # (name, restype, argtypes) of every exported function
 _SIGS = [
     ("sta_options_default", None, [ctypes.POINTER(sta_options)]),
@@ -98,7 +103,7 @@ _SIGS = [
     ("sta_report_endpoints", ctypes.c_int, [_VP, _VP, ctypes.c_int, _VP]),
     ("sta_get_info", ctypes.c_int, [_VP, ctypes.POINTER(sta_info)]),
     ("sta_get_phase_times", ctypes.c_int, [_VP, _PF, _P32]),
-    ("sta_backward", ctypes.c_int, [_VP, ctypes.c_float, ctypes.c_float, _VP, _VP, _VP, ctypes.c_int, _VP]),
+    ("sta_backward", ctypes.c_int, [_VP, ctypes.c_float, ctypes.c_float, _VP, _VP, _VP, _VP, ctypes.c_int, _VP]),
     ("sta_batch_create", ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(sta_graph_desc),
                                         ctypes.POINTER(sta_rc_desc), ctypes.POINTER(sta_lib_desc),
                                         ctypes.POINTER(sta_constraints), ctypes.POINTER(sta_options),
@@ -108,6 +113,11 @@ _SIGS = [
     ("sta_autotune", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.POINTER(sta_tune_result), _VP]),
     ("sta_report_paths", ctypes.c_int, [_VP, ctypes.POINTER(sta_path_query), _P32, _VP, _VP, _VP, _VP, _VP,
                                         ctypes.c_int, _VP]),
+    ("sta_estimate_rc", ctypes.c_int, [ctypes.POINTER(sta_graph_desc), _VP, _VP, ctypes.POINTER(sta_wire_params),
+                                       _VP, _VP, _VP, _VP, _VP, ctypes.c_int, _VP]),
+    ("sta_estimate_rc_backward", ctypes.c_int, [ctypes.POINTER(sta_graph_desc), _VP, _VP,
+                                                ctypes.POINTER(sta_wire_params), _VP, _VP, _VP, _VP, _VP, _VP,
+                                                ctypes.c_int, _VP]),
     ("sta_status_string", ctypes.c_char_p, [ctypes.c_int]),
     ("sta_last_error", ctypes.c_char_p, []),
 ]
@@ -272,9 +282,9 @@ def sta_get_phase_times(ctx: int) -> np.ndarray:
     return np.array(list(ms)[: n.value], dtype=np.float64)
 
 
-def sta_backward(ctx: int, g_tns: float, g_wns: float, grad_wire_cap=None, grad_pin_load=None,
+def sta_backward(ctx: int, g_tns: float, g_wns: float, grad_wire_cap=None, grad_wire_res=None, grad_pin_load=None,
                  grad_arc_delay=None, dst: int = STA_HOST, stream=None) -> None:
-    _check(load().sta_backward(ctx, float(g_tns), float(g_wns), _addr(grad_wire_cap),
+    _check(load().sta_backward(ctx, float(g_tns), float(g_wns), _addr(grad_wire_cap), _addr(grad_wire_res),
                                _addr(grad_pin_load), _addr(grad_arc_delay), dst, _stream(stream)))
 
 
@@ -338,6 +348,104 @@ def sta_report_paths(ctx: int, k: int, per_endpoint: int = 1, slack_below: float
         out.append({"slack": float(slack[i]), "endpoint": int(ep[i]), "pins": pins[a:b].tolist(),
                     "rf": rf[a:b].tolist()})
     return out
+
+
+def sta_estimate_rc(graph: sta_graph_desc, pin_x, pin_y, wire: sta_wire_params, net_node_ptr, parent, res_kohm,
+                    cap_ff, sink_node, mem: int = STA_HOST, stream=None) -> None:
+    _check(load().sta_estimate_rc(ctypes.byref(graph), _addr(pin_x), _addr(pin_y), ctypes.byref(wire),
+                                  _addr(net_node_ptr), _addr(parent), _addr(res_kohm), _addr(cap_ff),
+                                  _addr(sink_node), mem, _stream(stream)))
+
+
+def estimate_rc(d, pin_x, pin_y, r_x, r_y, c_x, c_y, stream=None) -> dict:
+    """RC trees of every net of a synth.Design-shaped object from pin
+    positions, as host arrays in the RC-CSR layout (keys as in synth.Design:
+    net_node_ptr, parent, res_kohm, cap_ff, sink_node).  Positions may be
+    numpy arrays (host) or cuda tensors (device; outputs are then cuda tensors
+    too)."""
+    keep: list = []
+
+    def a(x, dt):
+        x = np.ascontiguousarray(x, dtype=dt)
+        keep.append(x)
+        return x.ctypes.data
+
+    g = sta_graph_desc(d.n_pins, d.n_cells, d.n_nets, d.n_pi, d.n_po, None, None, None, None, None,
+                       a(d.net_driver, np.int32), a(d.net_sink_ptr, np.int32),
+                       a(d.net_sink_pin, np.int32), STA_HOST)
+    n_sinks = int(np.asarray(d.net_sink_ptr)[-1])
+    n_nodes = d.n_nets + 2 * n_sinks
+    w = sta_wire_params(r_x, r_y, c_x, c_y)
+    if hasattr(pin_x, "data_ptr"):
+        import torch
+        dev = pin_x.device
+        pin_x = pin_x.contiguous().float()
+        pin_y = pin_y.contiguous().float()
+        out = {"net_node_ptr": torch.empty(d.n_nets + 1, dtype=torch.int64, device=dev),
+               "parent": torch.empty(max(n_nodes, 1), dtype=torch.int32, device=dev),
+               "res_kohm": torch.empty(max(n_nodes, 1), dtype=torch.float32, device=dev),
+               "cap_ff": torch.empty(max(n_nodes, 1), dtype=torch.float32, device=dev),
+               "sink_node": torch.empty(max(n_sinks, 1), dtype=torch.int32, device=dev)}
+        if stream is None:
+            stream = torch.cuda.current_stream(dev)
+        mem = STA_DEVICE
+    else:
+        pin_x = np.ascontiguousarray(pin_x, np.float32)
+        pin_y = np.ascontiguousarray(pin_y, np.float32)
+        out = {"net_node_ptr": np.zeros(d.n_nets + 1, np.int64), "parent": np.zeros(n_nodes, np.int32),
+               "res_kohm": np.zeros(n_nodes, np.float32), "cap_ff": np.zeros(n_nodes, np.float32),
+               "sink_node": np.zeros(n_sinks, np.int32)}
+        mem = STA_HOST
+    sta_estimate_rc(g, pin_x, pin_y, w, out["net_node_ptr"], out["parent"], out["res_kohm"], out["cap_ff"],
+                    out["sink_node"], mem, stream)
+    if mem == STA_DEVICE:
+        out = {k: (v[:n_nodes] if k in ("parent", "res_kohm", "cap_ff") else v) for k, v in out.items()}
+        out["sink_node"] = out["sink_node"][:n_sinks]
+    return out
+
+
+def sta_estimate_rc_backward(graph: sta_graph_desc, pin_x, pin_y, wire: sta_wire_params, parent, sink_node,
+                             grad_res, grad_cap, grad_x, grad_y, mem: int = STA_HOST, stream=None) -> None:
+    _check(load().sta_estimate_rc_backward(ctypes.byref(graph), _addr(pin_x), _addr(pin_y), ctypes.byref(wire),
+                                           _addr(parent), _addr(sink_node), _addr(grad_res), _addr(grad_cap),
+                                           _addr(grad_x), _addr(grad_y), mem, _stream(stream)))
+
+
+def _net_graph(d, keep: list) -> sta_graph_desc:
+    def a(x, dt):
+        x = np.ascontiguousarray(x, dtype=dt)
+        keep.append(x)
+        return x.ctypes.data
+
+    return sta_graph_desc(d.n_pins, d.n_cells, d.n_nets, d.n_pi, d.n_po, None, None, None, None, None,
+                          a(d.net_driver, np.int32), a(d.net_sink_ptr, np.int32), a(d.net_sink_pin, np.int32),
+                          STA_HOST)
+
+
+def estimate_rc_backward(d, pin_x, pin_y, rc, r_x, r_y, c_x, c_y, grad_res, grad_cap, stream=None):
+    """(dJ/dx, dJ/dy) per pin through the trees `rc` of estimate_rc, from
+    dJ/dR and dJ/dC per node.  Host numpy arrays in and out, or cuda tensors
+    in and out."""
+    keep: list = []
+    g = _net_graph(d, keep)
+    w = sta_wire_params(r_x, r_y, c_x, c_y)
+    if hasattr(pin_x, "data_ptr"):
+        import torch
+        dev = pin_x.device
+        args = [t.contiguous() for t in (pin_x.float(), pin_y.float(), rc["parent"], rc["sink_node"],
+                                         grad_res.float(), grad_cap.float())]
+        gx = torch.empty(max(d.n_pins, 1), dtype=torch.float32, device=dev)
+        gy = torch.empty(max(d.n_pins, 1), dtype=torch.float32, device=dev)
+        sta_estimate_rc_backward(g, args[0], args[1], w, args[2], args[3], args[4], args[5], gx, gy, STA_DEVICE,
+                                 stream if stream is not None else torch.cuda.current_stream(dev))
+        return gx[: d.n_pins], gy[: d.n_pins]
+    arrs = [np.ascontiguousarray(v, dt) for v, dt in ((pin_x, np.float32), (pin_y, np.float32),
+                                                       (rc["parent"], np.int32), (rc["sink_node"], np.int32),
+                                                       (grad_res, np.float32), (grad_cap, np.float32))]
+    gx = np.zeros(d.n_pins, np.float32)
+    gy = np.zeros(d.n_pins, np.float32)
+    sta_estimate_rc_backward(g, *arrs[:2], w, *arrs[2:], gx, gy, STA_HOST, stream)
+    return gx, gy
 
 
 PHASES = ("rc_small", "rc_big", "forward", "backward", "reduce", "sort", "adjoint_sweep", "adjoint_rc")
@@ -472,11 +580,12 @@ class STA:
     def backward(self, g_tns=1.0, g_wns=0.0):
         """Host gradients of g_tns*TNS_g + g_wns*WNS_g (smooth mode)."""
         gc = np.zeros(int(self.info.n_nodes), np.float32)
+        gr = np.zeros(int(self.info.n_nodes), np.float32)
         gl = np.zeros(self.info.n_pins, np.float32)
         n_arcs = self._n_arcs
         ga = np.zeros((max(n_arcs, 1), 4), np.float32)
-        sta_backward(self.ctx, g_tns, g_wns, gc, gl, ga)
-        return {"grad_wire_cap": gc, "grad_pin_load": gl, "grad_arc_delay": ga[:n_arcs]}
+        sta_backward(self.ctx, g_tns, g_wns, gc, gr, gl, ga)
+        return {"grad_wire_cap": gc, "grad_wire_res": gr, "grad_pin_load": gl, "grad_arc_delay": ga[:n_arcs]}
 
 
 def _smooth_function():
@@ -503,7 +612,7 @@ def _smooth_function():
         def backward(ctx, grad_out):
             g = grad_out.detach().cpu()
             grad = torch.empty(ctx.n, dtype=torch.float32, device=grad_out.device)
-            sta_backward(ctx.timer.ctx, float(g[0]), float(g[1]), grad, None, None, STA_DEVICE,
+            sta_backward(ctx.timer.ctx, float(g[0]), float(g[1]), grad, None, None, None, STA_DEVICE,
                          torch.cuda.current_stream())
             return grad, None
 

@@ -284,3 +284,59 @@ def stats(d: Design) -> dict:
         "nodes_per_net_max": int(nodes.max()),
         "nodes_per_sink": float((d.n_nodes - d.n_nets) / max(1, d.n_sinks)),
     }
+
+
+def place(d: Design, seed: int = 1, sigma_um: float = 6.0, cell_pitch_um: float = 2.0):
+    """Synthetic placement (pin positions for RC estimation): PIs uniform on a
+    square die of side cell_pitch_um * sqrt(cells + PIs); each cell at the
+    position of the driver of its first input plus a seeded Gaussian offset
+    (sigma_um per axis), clamped to the die; every pin at its cell's position,
+    a PO at its driver's.  Nets are then mostly local, with the wire lengths a
+    placer leaves.  Returns float32 (x, y) in micrometres per caller pin."""
+    rng = np.random.default_rng(seed)
+    side = float(cell_pitch_um * np.sqrt(d.n_cells + d.n_pi))
+    x = np.full(d.n_pins, np.nan, np.float64)
+    y = np.full(d.n_pins, np.nan, np.float64)
+    kind = np.asarray(d.pin_kind)
+    pis = np.flatnonzero(kind == 0)
+    x[pis] = rng.uniform(0.0, side, pis.size)
+    y[pis] = rng.uniform(0.0, side, pis.size)
+    # driver pin of every sink pin
+    nsp = np.asarray(d.net_sink_ptr)
+    drv_of = np.full(d.n_pins, -1, np.int64)
+    drv_of[np.asarray(d.net_sink_pin)] = np.repeat(np.asarray(d.net_driver), np.diff(nsp))
+    first_in = np.asarray(d.cell_in_pin)[np.asarray(d.cell_in_ptr)[:-1]]
+    src = drv_of[first_in]  # pin whose position a cell copies
+    out = np.asarray(d.cell_out_pin)
+    ox = rng.normal(0.0, sigma_um, d.n_cells)
+    oy = rng.normal(0.0, sigma_um, d.n_cells)
+    todo = np.ones(d.n_cells, bool)
+    while todo.any():  # cells whose first input's driver is placed, level by level
+        ready = todo & ~np.isnan(x[src])
+        if not ready.any():
+            raise ValueError("placement: unplaced drivers (cycle?)")
+        c = np.flatnonzero(ready)
+        x[out[c]] = np.clip(x[src[c]] + ox[c], 0.0, side)
+        y[out[c]] = np.clip(y[src[c]] + oy[c], 0.0, side)
+        todo[c] = False
+    cell_of_in = np.repeat(np.arange(d.n_cells), np.diff(np.asarray(d.cell_in_ptr)))
+    cin = np.asarray(d.cell_in_pin)
+    x[cin] = x[out[cell_of_in]]
+    y[cin] = y[out[cell_of_in]]
+    pos = np.flatnonzero(kind == 3)
+    x[pos] = x[drv_of[pos]]
+    y[pos] = y[drv_of[pos]]
+    return x.astype(np.float32), y.astype(np.float32)
+
+
+def with_rc(d: Design, rc: dict) -> Design:
+    """A copy of d with its RC trees replaced (an RC-CSR dict as returned by
+    the RC estimation)."""
+    e = d.copy()
+    e.net_node_ptr = np.asarray(rc["net_node_ptr"], np.int64).copy()
+    e.parent = np.asarray(rc["parent"], np.int32).copy()
+    e.res_kohm = np.asarray(rc["res_kohm"], np.float32).copy()
+    e.cap_ff = np.asarray(rc["cap_ff"], np.float32).copy()
+    e.sink_node = np.asarray(rc["sink_node"], np.int32).copy()
+    e.n_nodes = int(e.net_node_ptr[-1])
+    return e

@@ -153,6 +153,24 @@ def test_null_context_calls_are_state_errors():
     assert e.value.status == S.STA_E_STATE
 
 
+def test_estimate_rc_host_checks():
+    d = synth.generate(synth.tiny_config(seed=5))
+    x, y = synth.place(d, seed=2)
+    for bad in ((-1.0, 0.0, 0.1, 0.1), (0.001, float("nan"), 0.1, 0.1), (0.001, 0.001, float("inf"), 0.1)):
+        with pytest.raises(S.StaError) as e:
+            S.estimate_rc(d, x, y, *bad)
+        assert e.value.status == S.STA_E_ARG
+    w = S.sta_wire_params(0.001, 0.001, 0.1, 0.1)
+    g = S.sta_graph_desc()
+    g.n_nets, g.n_pins, g.mem = 1, 1, 7
+    assert S.load().sta_estimate_rc(ctypes.byref(g), None, None, ctypes.byref(w), None, None, None, None, None,
+                                    S.STA_HOST, None) == S.STA_E_ARG
+    if not _has_gpu():  # valid input: the first device call fails
+        with pytest.raises(S.StaError) as e:
+            S.estimate_rc(d, x, y, 0.001, 0.001, 0.1, 0.1)
+        assert e.value.status == S.STA_E_DEVICE
+
+
 def _batch(designs, **opts):
     keep = []
     descs = [S.descriptors(d, keep) for d in designs]

@@ -72,6 +72,33 @@ def test_adjoint_matches_central_differences(small, g_tns, g_wns):
     assert checked >= 40
 
 
+@pytest.mark.parametrize("g_tns,g_wns", [(1.0, 0.0), (0.0, 1.0)])
+def test_resistance_gradient_matches_central_differences(small, g_tns, g_wns):
+    """dJ/dR per segment against central differences of the FP64 objective
+    with the segment's resistance moved by +-h (an FP64 override, so the step
+    is exact)."""
+    d, gamma = small, 5.0
+    base = d.res_kohm.astype(np.float64)
+    adj = oracle.smooth_adjoint(d, gamma, g_tns, g_wns, wire_res=base)
+    J = lambda r: g_tns * r["tns"] + g_wns * r["wns"]  # noqa: E731
+    assert np.all(adj["grad_wire_res"][d.net_node_ptr[:-1]] == 0.0)
+    checked = 0
+    for k in _fd_segments(d, 60, seed=9):
+        h = 1e-3 * max(base[k], 1e-3)
+        rp_, rm_ = base.copy(), base.copy()
+        rp_[k] += h
+        rm_[k] -= h
+        rp, rm = oracle.smooth_sta(d, gamma, wire_res=rp_), oracle.smooth_sta(d, gamma, wire_res=rm_)
+        if rp["sig"] != adj["sig"] or rm["sig"] != adj["sig"]:
+            continue
+        fd = (J(rp) - J(rm)) / (2 * h)
+        g = adj["grad_wire_res"][k]
+        assert abs(g - fd) <= 1e-5 * max(1.0, abs(fd)) + 1e-6, (k, g, fd)
+        checked += 1
+    assert checked >= 40
+    assert np.abs(adj["grad_wire_res"]).max() > 0
+
+
 def test_adjoint_pin_load_and_arc_delay_by_differences(small):
     """The pin-load gradient is the partial through the NLDM lookups: checked
     by shifting every load axis of a cell's type?  Instead: the arc-delay

@@ -42,7 +42,7 @@ def _check_smooth(d, sched, big_net_nodes=0, g_tns=0.6, g_wns=0.4):
     assert sl["wns"][1] == pytest.approx(o["wns"], rel=1e-5, abs=1e-2)
     g = s.backward(g_tns, g_wns)
     s.close()
-    for name in ("grad_wire_cap", "grad_pin_load", "grad_arc_delay"):
+    for name in ("grad_wire_cap", "grad_wire_res", "grad_pin_load", "grad_arc_delay"):
         _close(name, g[name], o[name], 1e-3, _grad_scale(o[name]))
 
 
@@ -94,7 +94,7 @@ def test_smooth_1m_pins_adjoint():
     s.close()
     o = oracle.smooth_adjoint(d, GAMMA, 1.0, 0.0)
     assert sl["tns"][1] == pytest.approx(o["tns"], rel=1e-5)
-    for name in ("grad_wire_cap", "grad_pin_load", "grad_arc_delay"):
+    for name in ("grad_wire_cap", "grad_wire_res", "grad_pin_load", "grad_arc_delay"):
         _close(name, g[name], o[name], 1e-3, _grad_scale(o[name]))
 
 
