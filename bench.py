@@ -224,12 +224,29 @@ def rc_estimate_side(design, reps: int = 5) -> dict:
         torch.cuda.synchronize()
         ts.append(ev0.elapsed_time(ev1))
     ms = sorted(ts[1:])[reps // 2]
+    # the gradient to positions through the same trees, from random node gradients
+    from paper_2511_11660_amd.sta import sta_estimate_rc_backward
+    gen = torch.Generator(device="cuda").manual_seed(3)
+    g_res = torch.rand(nodes, device="cuda", generator=gen) - 0.5
+    g_cap = torch.rand(nodes, device="cuda", generator=gen) - 0.5
+    gx = torch.empty(design.n_pins, dtype=torch.float32, device="cuda")
+    gy = torch.empty_like(gx)
+    tb = []
+    for _ in range(reps + 1):
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        sta_estimate_rc_backward(g, dx, dy, w, par, sink, g_res, g_cap, gx, gy, STA_DEVICE, stream)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        tb.append(ev0.elapsed_time(ev1))
+    ms_b = sorted(tb[1:])[reps // 2]
     # net CSR and driver (12 B/net), sink pins (4 B/sink), positions of every
     # net pin (8 B), outputs: node_ptr 8 B/net, 12 B/node, sink_node 4 B/sink
     algo = 12 * nn + 4 * ns + 8 * (nn + ns) + 8 * nn + 12 * nodes + 4 * ns
     return {"workload": "10M-pin design, synthetic placement, all arrays in HBM", "nets": nn, "sinks": ns,
             "max_fanout": int(np.diff(design.net_sink_ptr).max()), "ms": ms,
-            "pins_per_s": (nn + ns) / (ms * 1e-3), "algorithmic_GBps": algo / (ms * 1e-3) / 1e9}
+            "pins_per_s": (nn + ns) / (ms * 1e-3), "algorithmic_GBps": algo / (ms * 1e-3) / 1e9,
+            "backward_ms": ms_b}
 
 
 _SCHED_NAMES = {0: "persistent", 1: "per-level", 2: "graph"}

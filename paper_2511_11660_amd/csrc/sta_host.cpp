@@ -1331,7 +1331,7 @@ extern "C" sta_status sta_set_wire_caps(sta_ctx *C, const float *cap_ff, sta_mem
 
 // RC pass (or its adjoint): wide nets on the side stream, forked from and
 // joined back into s around the small-net kernel, so the two overlap.
-static sta_status enqueue_rc(sta_ctx *C, hipStream_t s, bool adjoint) {
+static sta_status enqueue_rc(sta_ctx *C, hipStream_t s, bool adjoint, bool res = false) {
   const DevDesign &D = C->D;
   if (C->n_big > 0) {
     HIP_TRY(hipEventRecord(C->ev_fork, s));
@@ -1339,7 +1339,8 @@ static sta_status enqueue_rc(sta_ctx *C, hipStream_t s, bool adjoint) {
     HIP_TRY(adjoint ? launch_rc_adjoint_wide(D, C->wide, C->side) : launch_rc_wide(D, C->wide, C->side));
     HIP_TRY(hipEventRecord(C->ev_join, C->side));
   }
-  HIP_TRY(adjoint ? launch_rc_adjoint(D, C->rc_chunks, C->n_rc_chunks, s) : launch_rc(D, C->rc_chunks, C->n_rc_chunks, s));
+  HIP_TRY(adjoint ? launch_rc_adjoint(D, C->rc_chunks, C->n_rc_chunks, res, s)
+                  : launch_rc(D, C->rc_chunks, C->n_rc_chunks, s));
   if (C->n_big > 0) HIP_TRY(hipStreamWaitEvent(s, C->ev_join, 0));
   return STA_OK;
 }
@@ -1838,7 +1839,7 @@ extern "C" sta_status sta_backward(sta_ctx *C, float g_tns, float g_wns, float *
   // the reverse sweep runs one launch per level in every schedule
   for (const int4 &ph : C->ph_adj) HIP_TRY(launch_adjoint_phase(D, g_tns, g_wns, ph, s));
   if (prof) HIP_TRY(hipEventRecord(C->ev[8], s));
-  STA_TRY(enqueue_rc(C, s, true));
+  STA_TRY(enqueue_rc(C, s, true, grad_wire_res != nullptr));
   if (prof) HIP_TRY(hipEventRecord(C->ev[9], s));
   C->bwd_timed = prof;
   if (!grad_wire_cap && !grad_wire_res && !grad_pin_load && !grad_arc_delay) return STA_OK;

@@ -219,7 +219,8 @@ hipError_t launch_reset_counters(uint32_t *counters, int n, hipStream_t s);
 hipError_t launch_reduce_smooth(const DevDesign &D, double *partials, double *out, uint64_t *keys,
                                 int32_t *vals, hipStream_t s);
 hipError_t launch_adjoint_phase(const DevDesign &D, float g_tns, float g_wns, int4 phase, hipStream_t s);
-hipError_t launch_rc_adjoint(const DevDesign &D, const int2 *chunks, int n_chunks, hipStream_t s);
+// res: also dJ/dR (D.g_res) for the small nets; the wide nets always write it
+hipError_t launch_rc_adjoint(const DevDesign &D, const int2 *chunks, int n_chunks, bool res, hipStream_t s);
 hipError_t launch_scatter_grads(const DevDesign &D, const int32_t *node_src, int64_t n_nodes, float *grad_cap,
                                 float *grad_res, const int32_t *pin_loc, int n_pins, float *grad_load,
                                 const int32_t *arc_src, int n_arcs, float4 *grad_arc, hipStream_t s);

@@ -2429,10 +2429,12 @@ __global__ __launch_bounds__(kWideBlock) void k_rc_adjoint_wide(DevDesign D, Wid
   rc_adjoint_wide(D, B, W, c, s_w);
 }
 
+// kRes: also dJ/dR per segment (one more LDS array; only when it is asked for).
+template <bool kRes>
 __global__ __launch_bounds__(kRcBlock) void k_rc_adjoint(DevDesign D, const int2 *chunks, int n_chunks) {
   __shared__ uint8_t s_par[kRcChunkNodes];
   __shared__ float s_R[kRcChunkNodes], s_C[kRcChunkNodes], s_A[kRcChunkNodes], s_B[kRcChunkNodes];
-  __shared__ float s_E[kRcChunkNodes], s_F[kRcChunkNodes], s_G[kRcChunkNodes];
+  __shared__ float s_E[kRcChunkNodes], s_F[kRcChunkNodes], s_G[kRes ? kRcChunkNodes : 1];
   __shared__ int s_base[kRcBlock + 1];
   const int tid = threadIdx.x;
   const int ci = xcd_major(n_chunks);
@@ -2466,16 +2468,20 @@ __global__ __launch_bounds__(kRcBlock) void k_rc_adjoint(DevDesign D, const int2
     }
     A[b] = 0.0f;  // H
     for (int k = 1; k < m; ++k) A[b + k] = A[b + par[b + k]] + R[b + k] * F[b + k];
-    for (int k = 0; k < m; ++k) G[b + k] = C[b + k] * B[b + k];  // S2
-    for (int k = m - 1; k >= 1; --k) G[b + par[b + k]] += G[b + k];
-    for (int k = 0; k < m; ++k) G[b + k] *= F[b + k];  // S2 Gm
+    if constexpr (kRes) {
+      for (int k = 0; k < m; ++k) G[b + k] = C[b + k] * B[b + k];  // S2
+      for (int k = m - 1; k >= 1; --k) G[b + par[b + k]] += G[b + k];
+      for (int k = 0; k < m; ++k) G[b + k] *= F[b + k];  // S2 Gm
+    }
     for (int k = 0; k < m; ++k) F[b + k] = C[b + k] * A[b + k];  // K
     for (int k = m - 1; k >= 1; --k) F[b + par[b + k]] += F[b + k];
     for (int k = 0; k < m; ++k) F[b + k] += E[b + k];  // Gd + K
-    for (int k = 0; k < m; ++k) E[b + k] = C[b + k];  // S1
-    for (int k = m - 1; k >= 1; --k) E[b + par[b + k]] += E[b + k];
-    G[b] = 0.0f;
-    for (int k = 1; k < m; ++k) G[b + k] += E[b + k] * F[b + k];  // dJ/dR
+    if constexpr (kRes) {
+      for (int k = 0; k < m; ++k) E[b + k] = C[b + k];  // S1
+      for (int k = m - 1; k >= 1; --k) E[b + par[b + k]] += E[b + k];
+      G[b] = 0.0f;
+      for (int k = 1; k < m; ++k) G[b + k] += E[b + k] * F[b + k];  // dJ/dR
+    }
     F[b] = 0.0f;  // PA + PB = path sum of R (Gd + K), in place (parents first)
     for (int k = 1; k < m; ++k) F[b + k] = F[b + par[b + k]] + R[b + k] * F[b + k];
     const float gL = D.g_load[x];
@@ -2484,7 +2490,7 @@ __global__ __launch_bounds__(kRcBlock) void k_rc_adjoint(DevDesign D, const int2
   __syncthreads();
   for (int i = tid; i < nk; i += kRcBlock) {
     D.g_cap[k0 + i] = s_C[i];
-    D.g_res[k0 + i] = s_G[i];
+    if constexpr (kRes) D.g_res[k0 + i] = s_G[i];
   }
 }
 
@@ -2920,9 +2926,12 @@ hipError_t launch_adjoint_phase(const DevDesign &D, float g_tns, float g_wns, in
   return hipGetLastError();
 }
 
-hipError_t launch_rc_adjoint(const DevDesign &D, const int2 *chunks, int n_chunks, hipStream_t s) {
+hipError_t launch_rc_adjoint(const DevDesign &D, const int2 *chunks, int n_chunks, bool res, hipStream_t s) {
   if (n_chunks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_rc_adjoint, dim3(xcd_grid(n_chunks)), dim3(kRcBlock), 0, s, D, chunks, n_chunks);
+  if (res)
+    hipLaunchKernelGGL(k_rc_adjoint<true>, dim3(xcd_grid(n_chunks)), dim3(kRcBlock), 0, s, D, chunks, n_chunks);
+  else
+    hipLaunchKernelGGL(k_rc_adjoint<false>, dim3(xcd_grid(n_chunks)), dim3(kRcBlock), 0, s, D, chunks, n_chunks);
   return hipGetLastError();
 }
 

@@ -68,6 +68,17 @@ __device__ __forceinline__ uint32_t wave_min(uint32_t v) {
   return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
+// Minimum within each row of 16 lanes (all active), as a uniform value: the
+// row-shift scan of wave_min, read at lane 15 (row 0; every row holds the
+// same 16 values where this is used).
+__device__ __forceinline__ uint32_t row_min16(uint32_t v) {
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)kNone, (int)v, 0x111, 0xf, 0xf, false));
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)kNone, (int)v, 0x112, 0xf, 0xf, false));
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)kNone, (int)v, 0x114, 0xf, 0xf, false));
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)kNone, (int)v, 0x118, 0xf, 0xf, false));
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 15);
+}
+
 // Non-negative floats order like their bit patterns.
 __device__ __forceinline__ uint32_t key_of(float d) { return __float_as_uint(d); }
 
@@ -244,17 +255,18 @@ __device__ __forceinline__ void est_block_net(const EstArgs &A, int n, int s0, i
       s_loc[buf][wave] = PinLoc{wx, wy};
     }
     __syncthreads();
-    uint32_t bk = s_key[buf][0], bi = s_idx[buf][0];
-    PinLoc bl = s_loc[buf][0];
-#pragma unroll
-    for (int w = 1; w < 1024 / kWave; ++w) {
-      const uint32_t k2 = s_key[buf][w], i2 = s_idx[buf][w];
-      const bool b = k2 < bk || (k2 == bk && i2 < bi);
-      bk = b ? k2 : bk;
-      bi = b ? i2 : bi;
-      bl.x = b ? s_loc[buf][w].x : bl.x;
-      bl.y = b ? s_loc[buf][w].y : bl.y;
-    }
+    // the 16 wave winners, one per lane of each row: row minima by DPP, so
+    // the reduction costs every wave a few vector instructions
+    const int e = lane & (1024 / kWave - 1);
+    const uint32_t ek = s_key[buf][e], ei = s_idx[buf][e];
+    const PinLoc el = s_loc[buf][e];
+    const uint32_t bk = row_min16(ek);
+    const uint32_t bi = row_min16(ek == bk ? ei : kNone);
+    const uint64_t hit = __ballot(ek == bk && ei == bi);
+    const uint32_t we = (uint32_t)__builtin_ctzll(hit);  // nonempty: some entry holds the minimum
+    PinLoc bl;
+    bl.x = lane_float(el.x, we);
+    bl.y = lane_float(el.y, we);
     const int j = (int)__builtin_amdgcn_readfirstlane((int)bi);
     const float xj = bl.x, yj = bl.y;
     const int ju = j >> 10;

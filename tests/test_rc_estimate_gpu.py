@@ -5,7 +5,9 @@ generated design, a fanout ladder across the lane-per-net / wave-per-net /
 block-per-net splits (8 and 64 pins) up to the largest supported net, integer-grid and
 coincident positions (distance ties everywhere), device-resident inputs,
 sampled checks on 1.2M- and 12M-pin designs, timing on the estimated trees,
-and the error paths."""
+and the error paths.  Then the gradient to positions through the trees
+(sta_estimate_rc_backward) against the oracle's, alone on random node
+gradients and chained after the smooth timing adjoint."""
 from types import SimpleNamespace
 
 import numpy as np
@@ -15,7 +17,7 @@ import oracle
 from oracle import rc_estimate as R
 from paper_2511_11660_amd import synth
 from paper_2511_11660_amd.sta import (STA, STA_E_ARG, STA_E_UNSUPPORTED, STA_DEVICE, StaError, estimate_rc,
-                                      sta_estimate_rc, sta_graph_desc, sta_wire_params)
+                                      estimate_rc_backward, sta_estimate_rc, sta_graph_desc, sta_wire_params)
 from parity import compare_full, run_gpu
 
 pytestmark = pytest.mark.gpu
@@ -191,3 +193,96 @@ def test_errors():
     assert _status(huge, z, z) == STA_E_UNSUPPORTED
     # the library stays usable after the errors
     _assert_same(estimate_rc(d, x, y, *WIRE), R.estimate_rc(d, x, y, *WIRE))
+
+
+# ------------------------------------------------------------ gradient to positions
+
+def _grad_close(got, ref, what):
+    g = got.cpu().numpy() if hasattr(got, "cpu") else got
+    scale = 1e-5 * max(1.0, float(np.abs(ref).max()))
+    err = np.abs(g.astype(np.float64) - ref)
+    bad = np.flatnonzero(err > scale + 1e-5 * np.abs(ref))
+    assert bad.size == 0, f"{what}: {bad[:5].tolist()} {g[bad[:3]]} vs {ref[bad[:3]]}"
+
+
+@pytest.mark.parametrize("kind", ["design", "ladder", "grid"])
+def test_position_gradient_matches_oracle(kind):
+    """Random dJ/dR, dJ/dC per node through the trees: every tier (lane,
+    wave, block up to 12,287 sinks) against the FP64 oracle, and a second
+    call bitwise equal to the first."""
+    if kind == "design":
+        d = synth.generate(synth.tiny_config(seed=4))
+        x, y = synth.place(d, seed=5)
+    else:
+        d = _nets(LADDER + [5] * 30, seed=3)
+        rng = np.random.default_rng(12)
+        if kind == "ladder":
+            x = rng.uniform(0.0, 300.0, d.n_pins).astype(np.float32)
+            y = rng.uniform(0.0, 300.0, d.n_pins).astype(np.float32)
+        else:  # coincident coordinates: zero-length segments, sgn(0) = 0
+            x = rng.integers(0, 6, d.n_pins).astype(np.float32)
+            y = rng.integers(0, 6, d.n_pins).astype(np.float32)
+    rc = estimate_rc(d, x, y, *WIRE)
+    nn = rc["parent"].size
+    rng = np.random.default_rng(13)
+    gR = rng.uniform(-1.0, 1.0, nn).astype(np.float32)
+    gC = rng.uniform(-1.0, 1.0, nn).astype(np.float32)
+    ox, oy = R.estimate_rc_backward(d, x, y, rc, *WIRE, gR, gC)
+    gx, gy = estimate_rc_backward(d, x, y, rc, *WIRE, gR, gC)
+    _grad_close(gx, ox, "dJ/dx")
+    _grad_close(gy, oy, "dJ/dy")
+    gx2, gy2 = estimate_rc_backward(d, x, y, rc, *WIRE, gR, gC)
+    assert np.array_equal(gx.view(np.uint32), gx2.view(np.uint32))
+    assert np.array_equal(gy.view(np.uint32), gy2.view(np.uint32))
+
+
+def test_position_gradient_device_arrays():
+    import torch
+    d = _nets([0, 3, 12, 70, 2000], seed=9)
+    rng = np.random.default_rng(14)
+    x = rng.uniform(0.0, 80.0, d.n_pins).astype(np.float32)
+    y = rng.uniform(0.0, 80.0, d.n_pins).astype(np.float32)
+    rc = estimate_rc(d, x, y, *WIRE)
+    gR = rng.uniform(-1.0, 1.0, rc["parent"].size).astype(np.float32)
+    gC = rng.uniform(-1.0, 1.0, rc["parent"].size).astype(np.float32)
+    hx, hy = estimate_rc_backward(d, x, y, rc, *WIRE, gR, gC)
+    cu = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    dx, dy = estimate_rc_backward(d, cu(x), cu(y), {k: cu(v) for k, v in rc.items()}, *WIRE, cu(gR), cu(gC))
+    assert np.array_equal(dx.cpu().numpy().view(np.uint32), hx.view(np.uint32))
+    assert np.array_equal(dy.cpu().numpy().view(np.uint32), hy.view(np.uint32))
+
+
+def test_timing_gradient_reaches_positions():
+    """Positions -> estimated trees -> smooth timing -> adjoint -> position
+    gradient, against the same chain through the FP64 oracle."""
+    gamma = 5.0
+    d = synth.generate(synth.tiny_config(seed=10, dangling_policy=1))
+    x, y = synth.place(d, seed=4)
+    rc = estimate_rc(d, x, y, *WIRE)
+    e = synth.with_rc(d, rc)
+    t = STA(e, mode=1, gamma_ps=gamma, sched=1)
+    t.update()
+    g = t.backward(1.0, 0.0)
+    t.close()
+    gx, gy = estimate_rc_backward(d, x, y, rc, *WIRE, g["grad_wire_res"], g["grad_wire_cap"])
+    o = oracle.smooth_adjoint(synth.with_rc(d, R.estimate_rc(d, x, y, *WIRE)), gamma, 1.0, 0.0)
+    ox, oy = R.estimate_rc_backward(d, x, y, rc, *WIRE, o["grad_wire_res"], o["grad_wire_cap"])
+    for got, ref in ((gx, ox), (gy, oy)):
+        scale = 1e-4 * max(1.0, float(np.abs(ref).max()))
+        assert np.all(np.abs(got - ref) <= scale + 1e-3 * np.abs(ref))
+    assert np.abs(ox).max() > 0
+
+
+def test_position_gradient_rejects_a_foreign_tree():
+    d = _nets([3, 2, 70], seed=5)
+    rng = np.random.default_rng(1)
+    x = rng.uniform(0.0, 10.0, d.n_pins).astype(np.float32)
+    y = rng.uniform(0.0, 10.0, d.n_pins).astype(np.float32)
+    rc = estimate_rc(d, x, y, *WIRE)
+    z = np.zeros(rc["parent"].size, np.float32)
+    for key, idx, val in (("sink_node", 0, 3), ("sink_node", 4, 40), ("parent", 1, 1), ("parent", 13, 200)):
+        bad = {k: v.copy() for k, v in rc.items()}
+        bad[key][idx] = val
+        with pytest.raises(StaError) as e:
+            estimate_rc_backward(d, x, y, bad, *WIRE, z, z)
+        assert e.value.status == STA_E_ARG, (key, idx)
