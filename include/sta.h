@@ -133,6 +133,10 @@ typedef struct {
   int32_t device;              /* HIP device ordinal; -1 = current device */
   int32_t sweep_blocks;        /* persistent sweep grid (blocks of 256 threads); 0 = every block slot
                                   the device can hold resident (any value >= 1 is deadlock-free) */
+  int32_t delay_model;         /* net delay: 0 Elmore (first moment); 1 reduced-order model (§III
+                                  "Delay models": Arnoldi iterations, here two steps in the G inner
+                                  product from the Elmore vector; the 50% time of the projected step
+                                  response; hard mode only) */
 } sta_options;
 
 typedef struct {

@@ -43,6 +43,7 @@ class _ODesign(ctypes.Structure):
         ("dangling_rat", ctypes.c_float * 4),
         ("dangling_policy", ctypes.c_int32),
         ("res64", _PD),
+        ("delay64", _PD),
     ]
 
 
@@ -101,7 +102,7 @@ class _Keep:
         return _ptr(a, typ)
 
 
-def _odesign(d, keep: _Keep, wire_res=None) -> _ODesign:
+def _odesign(d, keep: _Keep, wire_res=None, sink_delay=None) -> _ODesign:
     i32 = lambda a: keep(a, np.int32, _P32)  # noqa: E731
     f32 = lambda a: keep(a, np.float32, _PF)  # noqa: E731
     od = _ODesign()
@@ -126,6 +127,7 @@ def _odesign(d, keep: _Keep, wire_res=None) -> _ODesign:
         od.dangling_rat[v] = float(d.dangling_rat[v])
     od.dangling_policy = int(d.dangling_policy)
     od.res64 = None if wire_res is None else keep(wire_res, np.float64, _PD)
+    od.delay64 = None if sink_delay is None else keep(sink_delay, np.float64, _PD)
     return od
 
 
@@ -176,10 +178,12 @@ def nldm(xa, ya, table, X, Y):
                         float(X), float(Y))
 
 
-def sta(d, wire_cap=None):
-    """Full analysis: levels, RC, AT/slew, RAT, slack, crit, endpoints, WNS/TNS."""
+def sta(d, wire_cap=None, sink_delay=None):
+    """Full analysis: levels, RC, AT/slew, RAT, slack, crit, endpoints, WNS/TNS.
+    sink_delay (FP64, caller sink order) replaces the Elmore net delays, e.g.
+    by the reduced-order delays of oracle.arnoldi.sink_delays."""
     lib, keep = _load(), _Keep()
-    od = _odesign(d, keep)
+    od = _odesign(d, keep, sink_delay=sink_delay)
     NP = d.n_pins
     r = {
         "level": np.zeros(NP, np.int32), "level_order": np.zeros(NP, np.int32),

@@ -49,6 +49,7 @@ typedef struct {
   float dangling_rat[4];
   int32_t dangling_policy; /* 1: cell outputs without fanout are endpoints */
   const double *res64;     /* FP64 segment resistances overriding res_kohm when non-NULL */
+  const double *delay64;   /* per-sink net delays overriding the Elmore delay when non-NULL */
 } orc_design;
 
 static double seg_res(const orc_design *D, int64_t k) {
@@ -218,7 +219,7 @@ void orc_rc(const orc_design *D, const double *wire_cap, double *L_net, double *
     for (int32_t s = D->net_sink_ptr[n]; s < D->net_sink_ptr[n + 1]; s++) {
       int32_t k = D->sink_node[s];
       double q = 2.0 * m2[k] - d[k] * d[k];
-      d_sink[s] = d[k];
+      d_sink[s] = D->delay64 ? D->delay64[s] : d[k];
       q_sink[s] = q > 0.0 ? q : 0.0;
     }
   }

@@ -202,6 +202,7 @@ void sta_options_default(sta_options *o) {
   o->profile = 0;
   o->device = -1;
   o->sweep_blocks = 0;
+  o->delay_model = 0;
 }
 
 const char *sta_status_string(sta_status s) {
@@ -989,6 +990,7 @@ static sta_status build_layout(sta_ctx *C, const Inputs &I, const std::vector<in
   STA_TRY(C->upload(&C->arc_src, arc_src));
   STA_TRY(C->upload(&p32, ep_loc)); D.ep_loc = p32;
   D.gamma = C->opt.mode == 1 ? C->opt.gamma_ps : 0.0f;
+  D.delay_model = C->opt.delay_model;
   if (C->opt.mode == 1) {
     STA_TRY(C->alloc(&D.g_sink, NS));
     STA_TRY(C->alloc(&D.g_dq, NS));
@@ -1060,6 +1062,9 @@ static sta_status check_options(const sta_options &o) {
   if (o.big_net_nodes < 0) return fail(STA_E_ARG, "big_net_nodes < 0");
   if (o.dangling_policy != 0 && o.dangling_policy != 1) return fail(STA_E_ARG, "bad dangling_policy");
   if (o.sweep_blocks < 0) return fail(STA_E_ARG, "sweep_blocks < 0");
+  if (o.delay_model != 0 && o.delay_model != 1) return fail(STA_E_ARG, "delay_model must be 0 or 1");
+  if (o.delay_model == 1 && o.mode == 1)
+    return fail(STA_E_UNSUPPORTED, "the reduced-order delay model has no adjoint (smooth mode)");
   return STA_OK;
 }
 

@@ -110,6 +110,7 @@ struct DevDesign {
   // smooth (differentiable) mode: gamma > 0 turns late arrival merges into
   // log-sum-exp; the adjoint writes the g_* arrays
   float gamma;
+  int delay_model;              // 0 Elmore, 1 reduced-order (Arnoldi, two poles)
   const int32_t *ep_loc;        // [n_ep] endpoint pin: driver slot (>= 0) or -1 - sink slot
   float4 *g_sink;               // [n_sinks] dJ/d(late AT R, F), dJ/d(late slew R, F)
   float2 *g_dq;                 // [n_sinks] dJ/d(Elmore delay), dJ/d(spread q)
@@ -240,7 +241,7 @@ hipError_t sort_endpoints64(void *temp, size_t temp_bytes, const uint64_t *keys_
                             const int32_t *vals_in, int32_t *vals_out, int n, int end_bit, hipStream_t s);
 int sweep_blocks_per_cu(size_t lds_bytes);
 int coop_blocks_per_cu(size_t lds_bytes);
-size_t sweep_lds_bytes(const DevDesign &D);
+size_t sweep_lds_bytes(const DevDesign &D, int chunks_per_block = 1);
 
 // levelization
 hipError_t launch_level_init(int32_t *pending, int32_t *cell_level, const int32_t *cell_nin,

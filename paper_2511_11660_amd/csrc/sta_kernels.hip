@@ -188,30 +188,61 @@ struct LdsLib {
   const int *sense;
 };
 
-// The packed tables are padded to a multiple of 4 floats; every thread issues
-// all of its 16-byte loads before its LDS stores, so staging costs about one
-// memory round trip rather than one per 256 floats.
-__device__ LdsLib load_lib(const DevDesign &D, unsigned char *smem) {
-  float *tab = reinterpret_cast<float *>(smem);
+// Library staging into LDS (packed tables padded to a multiple of 4 floats,
+// then the sense codes), split in two so a level kernel can keep the loads in
+// flight under its dependent gathers: lib_issue requests up to kLibRegs float4
+// per thread into registers at kernel entry, all together; lib_store writes
+// them with unpredicated stores (a lane past the end rewrites the last element
+// with its own copy of it: a predicated store would let the compiler sink each
+// load into its branch, one round trip per element) and stages any remainder
+// of a library larger than kLibRegs x blockDim float4 element by element.
+constexpr int kLibRegs = 8;
+struct LibRegs {
+  float4 v[kLibRegs];
+};
+
+__device__ __forceinline__ LibRegs lib_issue(const DevDesign &D) {
+  LibRegs r;
   const int n4 = (D.n_types * D.tstride + 3) >> 2;
   const float4 *src = reinterpret_cast<const float4 *>(D.tables);
+#pragma unroll
+  for (int u = 0; u < kLibRegs; ++u)  // clamped, unpredicated
+    r.v[u] = src[min(u * (int)blockDim.x + (int)threadIdx.x, n4 - 1)];
+  return r;
+}
+
+__device__ __forceinline__ LdsLib lib_store(const DevDesign &D, unsigned char *smem, LibRegs r) {
+  float *tab = reinterpret_cast<float *>(smem);
+  const int n4 = (D.n_types * D.tstride + 3) >> 2;
   float4 *dst = reinterpret_cast<float4 *>(tab);
-  constexpr int kU = 8;
-  for (int b = 0; b < n4; b += kU * (int)blockDim.x) {
-    float4 v[kU];
+  __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {  // clamped, unpredicated: all loads in flight together
-      const int i = min(b + u * (int)blockDim.x + (int)threadIdx.x, n4 - 1);
-      v[u] = src[i];
-    }
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const int i = b + u * (int)blockDim.x + (int)threadIdx.x;
-      if (i < n4) dst[i] = v[u];
-    }
-  }
+  for (int u = 0; u < kLibRegs; ++u) dst[min(u * (int)blockDim.x + (int)threadIdx.x, n4 - 1)] = r.v[u];
+  const float4 *src = reinterpret_cast<const float4 *>(D.tables);
+  for (int i = kLibRegs * (int)blockDim.x + (int)threadIdx.x; i < n4; i += blockDim.x) dst[i] = src[i];
   int *sense = reinterpret_cast<int *>(tab + 4 * n4);
   for (int i = threadIdx.x; i < D.n_types; i += blockDim.x) sense[i] = D.sense[i];
+  return {tab, sense};
+}
+
+// Both halves back to back (kernels with nothing to overlap the staging with).
+__device__ __forceinline__ LdsLib load_lib(const DevDesign &D, unsigned char *smem) {
+  float *tab = reinterpret_cast<float *>(smem);
+  const int n4 = (D.n_types * D.tstride + 3) >> 2, t = threadIdx.x, B = blockDim.x;
+  const float4 *src = reinterpret_cast<const float4 *>(D.tables);
+  float4 *dst = reinterpret_cast<float4 *>(tab);
+  for (int b = 0; b < n4; b += 4 * B) {  // four loads in flight, then four stores
+    const int i0 = min(b + t, n4 - 1), i1 = min(b + B + t, n4 - 1);
+    const int i2 = min(b + 2 * B + t, n4 - 1), i3 = min(b + 3 * B + t, n4 - 1);
+    const float4 v0 = src[i0], v1 = src[i1], v2 = src[i2], v3 = src[i3];
+    __builtin_amdgcn_sched_barrier(0);
+    dst[i0] = v0;
+    dst[i1] = v1;
+    dst[i2] = v2;
+    dst[i3] = v3;
+  }
+  int *sense = reinterpret_cast<int *>(tab + 4 * n4);
+  for (int i = t; i < D.n_types; i += B) sense[i] = D.sense[i];
   return {tab, sense};
 }
 
@@ -573,22 +604,33 @@ __device__ __forceinline__ void merge_slots(const DevDesign &D, const CellCtx &c
 // kSlots: inline fanin slots to merge (the library's most inputs, <= 4), so
 // the slot loop is straight-line code whose table loads can all be issued
 // together; a cell with fewer inputs masks its empty slots.
-template <bool kInc, int kSlots>
-__global__ __launch_bounds__(kSweepBlock) void k_forward(DevDesign D, int c0, int xb, int xr, IncArgs I) {
+// kCpb: chunks per block (256 threads each).  Two chunks share one staging of
+// the library, which halves the LDS fill traffic of a level; a block's second
+// chunk past the phase's n chunks only reaches the barriers (reads clamped to
+// the last chunk, nothing written).  The incremental kernels keep one.
+template <bool kInc, int kSlots, int kCpb>
+__global__ __launch_bounds__(kSweepBlock * kCpb) void k_forward(DevDesign D, int c0, int xb, int xr, int n,
+                                                                 IncArgs I) {
   extern __shared__ __align__(32) unsigned char smem[];
   static_assert(kSweepBlock == 4 * kChunk, "one thread per driver view");
-  const int c = c0 + blockIdx.x;
+  static_assert(kCpb == 1 || !kInc, "incremental chunks return early: one chunk per block");
+  const LibRegs lib_r = lib_issue(D);  // in flight under the metadata and fanin gathers
+  const int half = (int)threadIdx.x / kSweepBlock, tid = (int)threadIdx.x % kSweepBlock;
+  const int cb_raw = (int)blockIdx.x * kCpb + half;
+  const bool active = cb_raw < n;
+  const int cb = active ? cb_raw : n - 1;
+  const int c = c0 + cb;
   // (incremental: the chunk's flag is requested with the first loads and
   // tested before the input gathers and the library staging)
   uint32_t flagged = 1u;
   if constexpr (kInc) flagged = I.flag[c];
-  const int tid = threadIdx.x, dv = tid >> 2, v = tid & 3, el = v >> 1, ro = v & 1;
+  const int dv = tid >> 2, v = tid & 3, el = v >> 1, ro = v & 1;
   // regular chunks are the level's runs of kChunk slots from xb (no record
   // load on the path to the fanin gathers); a high-fanout driver's own chunk
   // comes after them and is read from its record
   int x0, x1, s0, s1;
-  if ((int)blockIdx.x * kChunk < xr - xb) {
-    x0 = xb + (int)blockIdx.x * kChunk;
+  if (cb * kChunk < xr - xb) {
+    x0 = xb + cb * kChunk;
     x1 = min(x0 + kChunk, xr);
     s0 = __builtin_amdgcn_readfirstlane(D.sink_ptr[x0]);
     s1 = __builtin_amdgcn_readfirstlane(D.sink_ptr[x1]);
@@ -598,6 +640,10 @@ __global__ __launch_bounds__(kSweepBlock) void k_forward(DevDesign D, int c0, in
     x1 = __builtin_amdgcn_readfirstlane(cr4.y);
     s0 = __builtin_amdgcn_readfirstlane(cr4.z);
     s1 = __builtin_amdgcn_readfirstlane(cr4.w);
+  }
+  if (!active) {  // no drivers, no sinks
+    x1 = x0;
+    s1 = s0;
   }
   const int x = x0 + dv;
   const bool live = x < x1;
@@ -642,8 +688,8 @@ __global__ __launch_bounds__(kSweepBlock) void k_forward(DevDesign D, int c0, in
     oldA = D.sink_state[sA];
     ccA = I.sink_cc[sA];
   }
-  const LdsLib lib = load_lib(D, smem);
-  PinState *wst = reinterpret_cast<PinState *>(smem + lib_lds_bytes(D.n_types, D.tstride));
+  const LdsLib lib = lib_store(D, smem, lib_r);
+  PinState *wst = reinterpret_cast<PinState *>(smem + lib_lds_bytes(D.n_types, D.tstride)) + half * kChunk;
   int *s_redo = reinterpret_cast<int *>(wst + kChunk);  // [kChunk], incremental only
   lds_barrier();
   float at_v, sl_v;
@@ -906,16 +952,24 @@ __device__ void bwd_piece(const DevDesign &D, const LdsLib &lib, int j) {
 // With kInc an unflagged chunk returns at once; a flagged one compares each
 // driver's RAT bitwise with the stored one and, where it changed or the
 // driver's net was recomputed, flags the chunks of the cell's input sinks.
-template <bool kInc>
-__global__ __launch_bounds__(kSweepBlock) void k_backward(DevDesign D, int c0, int c1, IncArgs I) {
+// kCpb: chunks per block, as for k_forward.
+template <bool kInc, int kCpb>
+__global__ __launch_bounds__(kSweepBlock * kCpb) void k_backward(DevDesign D, int c0, int c1, IncArgs I) {
   extern __shared__ __align__(32) unsigned char smem[];
-  const int c = c0 + blockIdx.x;
+  static_assert(kCpb == 1 || !kInc, "incremental chunks return early: one chunk per block");
+  const LibRegs lib_r = lib_issue(D);  // in flight under the sink loads
+  const int half = (int)threadIdx.x / kSweepBlock, tid = (int)threadIdx.x % kSweepBlock;
+  const int c_raw = c0 + (int)blockIdx.x * kCpb + half;
+  const bool active = c_raw < c1;
+  const int c = active ? c_raw : c1 - 1;
   uint32_t flagged = 1u;  // (incremental: tested once the first loads are in flight)
   if constexpr (kInc) flagged = I.flag[I.n_chunks + c];
-  const int tid = threadIdx.x, el = tid & 1, dv = tid >> 2, v = tid & 3;
+  const int el = tid & 1, dv = tid >> 2, v = tid & 3;
   const int4 cr4 = D.chunk_rec[c];
-  const int x0 = __builtin_amdgcn_readfirstlane(cr4.x), x1 = __builtin_amdgcn_readfirstlane(cr4.y);
-  const int s0 = __builtin_amdgcn_readfirstlane(cr4.z), s1 = __builtin_amdgcn_readfirstlane(cr4.w);
+  const int x0 = __builtin_amdgcn_readfirstlane(cr4.x);
+  const int x1 = active ? __builtin_amdgcn_readfirstlane(cr4.y) : x0;  // past the phase: no drivers,
+  const int s0 = __builtin_amdgcn_readfirstlane(cr4.z);
+  const int s1 = active ? __builtin_amdgcn_readfirstlane(cr4.w) : s0;  // no sinks
   const int smax = max(s1 - 1, 0);
   const int sA = s0 + (tid >> 1), sAc = min(sA, smax);
   auto ld_half = [&](int s, float2 &at, float2 &sl) {
@@ -943,8 +997,8 @@ __global__ __launch_bounds__(kSweepBlock) void k_backward(DevDesign D, int c0, i
     if (I.fanin_cc) fcc = I.fanin_cc[xc];
     if (__builtin_amdgcn_readfirstlane(flagged) == 0u) return;
   }
-  const LdsLib lib = load_lib(D, smem);
-  int *wacc = reinterpret_cast<int *>(smem + lib_lds_bytes(D.n_types, D.tstride));
+  const LdsLib lib = lib_store(D, smem, lib_r);
+  int *wacc = reinterpret_cast<int *>(smem + lib_lds_bytes(D.n_types, D.tstride)) + half * kSweepBlock;
   wacc[tid] = f2key((v >> 1) ? kInf : -kInf);
   lds_barrier();
   const TabLayout lay{D.nx, D.ny};
@@ -1890,6 +1944,98 @@ __global__ __launch_bounds__(kWideBlock) void k_rc_wide(DevDesign D, WideNets W,
   rc_wide_net(D, B, W, c, s_w);
 }
 
+// ---- reduced-order (Arnoldi) net delay -------------------------------------
+//
+// The step response of the tree (root driven by a unit step) is projected on
+// the Krylov space {d, A d} of A = G^-1 C in the G inner product, where A is
+// self-adjoint, so Arnoldi is the Lanczos recurrence.  For vectors in the
+// range of A, <A x, A y>_G = x^T C A y, so the whole two-step process needs
+// only four sums over the net's non-root nodes,
+//   S1 = sum C^ d, S2 = sum C^ d^2, S3 = sum C^ d m2, S4 = sum C^ m2^2,
+// with d the Elmore delays and m2 = A d the second moments the RC pass already
+// forms (sum C^ m2 = S2 is one of the identities):
+//   alpha1 = S2 / S1,  beta1^2 = (S3 S1 - S2^2) / S1^2,
+//   alpha2 = (S4 - 2 alpha1 S3 + alpha1^2 S2) / (S1 beta1^2),
+// T = [[alpha1, beta1], [beta1, alpha2]] = U diag(tau) U^T, and at a node
+//   1 - Y(t) = sum_j a_j exp(-t / tau_j),
+//   a_j = u_1j (u_1j d + u_2j (m2 - alpha1 d) / beta1) / tau_j,
+// which keeps the node's first two time moments (d and m2).  beta1^2 at or
+// below 1e-24 alpha1^2 leaves the one-pole model a = d / alpha1,
+// tau = alpha1.  The delay is the first time the response reaches 1/2: 0 when
+// it starts at or above it, else 64 bisections of [0, t_hi], t_hi the first
+// doubling of the largest tau where 1 - Y < 1/2.  All in FP64.
+struct Red2 {
+  double tau0, tau1;      // kept poles (1.0 where absent: its weight is 0)
+  double u10, u20, u11, u21;  // first and second components of their eigenvectors
+  double alpha1, inv_b1;  // inv_b1 = 0 for the one-pole model
+  bool p0, p1;            // which poles are kept
+};
+
+__device__ Red2 red2_model(double S1, double S2, double S3, double S4) {
+  Red2 r{1.0, 1.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, false, false};
+  if (!(S1 > 0.0)) return r;
+  const double a1 = S2 / S1;
+  const double b1sq = (S3 * S1 - S2 * S2) / (S1 * S1);
+  r.alpha1 = a1;
+  if (!(b1sq > 1e-24 * a1 * a1)) {
+    if (a1 > 0.0) {
+      r.p0 = true;
+      r.tau0 = a1;
+      r.u10 = 1.0;
+    }
+    return r;
+  }
+  const double b1 = sqrt(b1sq);
+  const double a2 = (S4 - 2.0 * a1 * S3 + a1 * a1 * S2) / (S1 * b1sq);
+  const double h = 0.5 * (a1 - a2), rad = sqrt(h * h + b1sq), mean = 0.5 * (a1 + a2);
+  r.inv_b1 = 1.0 / b1;
+  // eigenvector of [[a1, b1], [b1, a2]] for lam: (b1, lam - a1) or (lam - a2, b1), the longer
+  auto vec = [&](double lam, double &v1, double &v2) {
+    v1 = b1;
+    v2 = lam - a1;
+    const double w1 = lam - a2, w2 = b1;
+    if (w1 * w1 + w2 * w2 > v1 * v1 + v2 * v2) {
+      v1 = w1;
+      v2 = w2;
+    }
+    const double nv = 1.0 / sqrt(v1 * v1 + v2 * v2);
+    v1 *= nv;
+    v2 *= nv;
+  };
+  const double l0 = mean + rad, l1 = mean - rad;
+  if (l0 > 0.0) {
+    r.p0 = true;
+    r.tau0 = l0;
+    vec(l0, r.u10, r.u20);
+  }
+  if (l1 > 0.0) {
+    r.p1 = true;
+    r.tau1 = l1;
+    vec(l1, r.u11, r.u21);
+  }
+  return r;
+}
+
+__device__ double red2_half_time(const Red2 &r, double d, double m2) {
+  if (!r.p0 && !r.p1) return 0.0;
+  const double e = (m2 - r.alpha1 * d) * r.inv_b1;  // 0 for the one-pole model
+  const double a0 = r.p0 ? r.u10 * (r.u10 * d + r.u20 * e) / r.tau0 : 0.0;
+  const double a1 = r.p1 ? r.u11 * (r.u11 * d + r.u21 * e) / r.tau1 : 0.0;
+  auto f = [&](double t) { return a0 * exp(-t / r.tau0) + a1 * exp(-t / r.tau1) - 0.5; };
+  if (f(0.0) <= 0.0) return 0.0;
+  double hi = fmax(r.p0 ? r.tau0 : 0.0, r.p1 ? r.tau1 : 0.0);
+  for (int i = 0; i < 1100 && f(hi) > 0.0; ++i) hi *= 2.0;
+  double lo = 0.0;
+  for (int i = 0; i < 64; ++i) {
+    const double mid = 0.5 * (lo + hi);
+    if (f(mid) > 0.0)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
 // Stages nodes [k0, k0 + nk) of one RC chunk into LDS: parent, R and
 // C^ = C + lumped pin caps.  Each thread requests all of its (clamped,
 // unpredicated) loads before its first LDS store.
@@ -1956,6 +2102,23 @@ __global__ __launch_bounds__(kRcBlock) void k_rc(DevDesign D, const int2 *chunks
     const float L = rc_tree_lds(s_par, s_R, s_C, s_A, s_B, b, m);
     D.L_net[x] = L;
     D.cons_rec[x].L = L;
+    if (D.delay_model == 1) {  // reduced-order delays replace the Elmore ones
+      double S1 = 0.0, S2 = 0.0, S3 = 0.0, S4 = 0.0;
+      for (int k = 1; k < m; ++k) {
+        const double c = s_C[b + k], d = s_B[b + k], m2 = s_A[b + k];
+        S1 += c * d;
+        S2 += c * d * d;
+        S3 += c * d * m2;
+        S4 += c * m2 * m2;
+      }
+      const Red2 r = red2_model(S1, S2, S3, S4);
+      for (int s = s0; s < s1; ++s) {
+        const int k = b + D.sink_node[s];
+        const float d = s_B[k];
+        D.dq[s] = make_float2((float)red2_half_time(r, d, s_A[k]), fmaxf(0.0f, 2.0f * s_A[k] - d * d));
+      }
+      return;
+    }
 #pragma unroll
     for (int u = 0; u < kPre; ++u) {
       if (s0 + u < s1) {
@@ -1969,6 +2132,47 @@ __global__ __launch_bounds__(kRcBlock) void k_rc(DevDesign D, const int2 *chunks
       const float d = s_B[k];
       D.dq[s] = make_float2(d, fmaxf(0.0f, 2.0f * s_A[k] - d * d));
     }
+  }
+}
+
+// Reduced-order delays of the wide nets from the FP64 d (Y) and m2 (A) the
+// wide kernel left in its scratch: one block per net, the four sums by a
+// fixed block reduction, then the net's sinks.
+__global__ __launch_bounds__(256) void k_rc_wide_reduced(DevDesign D, WideNets W, const uint32_t *only) {
+  __shared__ double s_sum[4][256 / kWave];
+  const int net = blockIdx.x;
+  if (only && only[net] == 0u) return;
+  const BigNet &B = W.big[net];
+  const int x = B.x, m = B.m, st = m + 1;
+  const int k0 = D.rc_ptr[x];
+  const double *M2 = W.scratch + B.scr, *Y = M2 + 3 * st;
+  const float *Cw = D.rc_cap + k0, *pc = W.pc + B.aux;
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int k = 1 + (int)threadIdx.x; k < m; k += 256) {
+    const double c = (double)Cw[k] + (double)pc[k], d = Y[k], m2 = M2[k];
+    v[0] += c * d;
+    v[1] += c * d * d;
+    v[2] += c * d * m2;
+    v[3] += c * m2 * m2;
+  }
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    for (int off = kWave / 2; off > 0; off >>= 1) v[i] += __shfl_down(v[i], off);
+    if (lane == 0) s_sum[i][wave] = v[i];
+  }
+  __syncthreads();
+  double S[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    S[i] = 0.0;
+    for (int w = 0; w < 256 / kWave; ++w) S[i] += s_sum[i][w];
+  }
+  const Red2 r = red2_model(S[0], S[1], S[2], S[3]);
+  const int s0 = D.sink_ptr[x], ns = D.sink_ptr[x + 1] - s0;
+  for (int j = threadIdx.x; j < ns; j += 256) {
+    const int k = D.sink_node[s0 + j];
+    D.dq[s0 + j].x = (float)red2_half_time(r, Y[k], M2[k]);
   }
 }
 
@@ -2795,9 +2999,9 @@ __global__ void k_paths_emit(DevDesign D, PathArgs A, const int32_t *sel, int n_
 
 // ------------------------------------------------------------ wrappers
 
-size_t sweep_lds_bytes(const DevDesign &D) {
+size_t sweep_lds_bytes(const DevDesign &D, int chunks_per_block) {
   const size_t per_wave = sizeof(PinState) * kWave;  // >= 4 ints per lane for the backward
-  return lib_lds_bytes(D.n_types, D.tstride) + per_wave * (kSweepBlock / kWave);
+  return lib_lds_bytes(D.n_types, D.tstride) + per_wave * (kSweepBlock / kWave) * chunks_per_block;
 }
 
 // Blocks per CU every sweep kernel of the given schedule can keep resident.
@@ -2844,6 +3048,7 @@ hipError_t launch_rc(const DevDesign &D, const int2 *chunks, int n_chunks, hipSt
 hipError_t launch_rc_wide(const DevDesign &D, const WideNets &W, hipStream_t s, const uint32_t *only) {
   if (W.n_big <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_rc_wide, dim3(W.n_blk), dim3(kWideBlock), 0, s, D, W, only);
+  if (D.delay_model == 1) hipLaunchKernelGGL(k_rc_wide_reduced, dim3(W.n_big), dim3(256), 0, s, D, W, only);
   return hipGetLastError();
 }
 
@@ -2857,6 +3062,17 @@ hipError_t launch_forward(const DevDesign &D, int grid, bool coop, hipStream_t s
   return launch_sweep<kSweepFwd>(D, 0.0f, 0.0f, grid, coop, s);
 }
 
+// Chunks per block of the full-update level kernels (the incremental
+// continuation keeps one).
+constexpr int kFullCpb = 2;
+
+template <bool kInc, int kSlots>
+static void launch_fwd_chunks(const DevDesign &D, const IncArgs &I, int4 ph, int2 reg, hipStream_t s) {
+  constexpr int cpb = kInc ? 1 : kFullCpb;
+  hipLaunchKernelGGL((k_forward<kInc, kSlots, cpb>), dim3(blocks_for(ph.z, cpb)), dim3(kSweepBlock * cpb),
+                     sweep_lds_bytes(D, cpb), s, D, ph.y, reg.x, reg.y, ph.z, I);
+}
+
 template <bool kInc>
 static hipError_t forward_phase(const DevDesign &D, const IncArgs &I, int4 ph, int2 reg, hipStream_t s) {
   if (ph.z <= 0) return hipSuccess;
@@ -2865,17 +3081,13 @@ static hipError_t forward_phase(const DevDesign &D, const IncArgs &I, int4 ph, i
     hipLaunchKernelGGL(k_forward_pieces<kInc>, dim3(blocks_for(ph.z, per)), dim3(kSweepBlock), 0, s, D, ph.y,
                        ph.y + ph.z, I);
   else if (D.max_in <= 1)
-    hipLaunchKernelGGL((k_forward<kInc, 1>), dim3(ph.z), dim3(kSweepBlock), sweep_lds_bytes(D), s, D, ph.y, reg.x,
-                       reg.y, I);
+    launch_fwd_chunks<kInc, 1>(D, I, ph, reg, s);
   else if (D.max_in == 2)
-    hipLaunchKernelGGL((k_forward<kInc, 2>), dim3(ph.z), dim3(kSweepBlock), sweep_lds_bytes(D), s, D, ph.y, reg.x,
-                       reg.y, I);
+    launch_fwd_chunks<kInc, 2>(D, I, ph, reg, s);
   else if (D.max_in == 3)
-    hipLaunchKernelGGL((k_forward<kInc, 3>), dim3(ph.z), dim3(kSweepBlock), sweep_lds_bytes(D), s, D, ph.y, reg.x,
-                       reg.y, I);
+    launch_fwd_chunks<kInc, 3>(D, I, ph, reg, s);
   else
-    hipLaunchKernelGGL((k_forward<kInc, 4>), dim3(ph.z), dim3(kSweepBlock), sweep_lds_bytes(D), s, D, ph.y, reg.x,
-                       reg.y, I);
+    launch_fwd_chunks<kInc, 4>(D, I, ph, reg, s);
   return hipGetLastError();
 }
 
@@ -2883,12 +3095,13 @@ template <bool kInc>
 static hipError_t backward_phase(const DevDesign &D, const IncArgs &I, int4 ph, hipStream_t s) {
   if (ph.z <= 0) return hipSuccess;
   const int per = kSweepBlock / kWave;
+  constexpr int cpb = kInc ? 1 : kFullCpb;
   if (ph.x == kItemPiece)
     hipLaunchKernelGGL(k_backward_pieces<kInc>, dim3(blocks_for(ph.z, per)), dim3(kSweepBlock), sweep_lds_bytes(D),
                        s, D, ph.y, ph.y + ph.z, I);
   else
-    hipLaunchKernelGGL(k_backward<kInc>, dim3(ph.z), dim3(kSweepBlock), sweep_lds_bytes(D), s, D, ph.y, ph.y + ph.z,
-                       I);
+    hipLaunchKernelGGL((k_backward<kInc, cpb>), dim3(blocks_for(ph.z, cpb)), dim3(kSweepBlock * cpb),
+                       sweep_lds_bytes(D, cpb), s, D, ph.y, ph.y + ph.z, I);
   return hipGetLastError();
 }
 

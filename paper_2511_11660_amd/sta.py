@@ -59,7 +59,8 @@ class sta_options(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("gamma_ps", ctypes.c_float),
                 ("dangling_policy", ctypes.c_int32), ("sched", ctypes.c_int32),
                 ("big_net_nodes", ctypes.c_int32), ("sort_endpoints", ctypes.c_int32),
-                ("profile", ctypes.c_int32), ("device", ctypes.c_int32), ("sweep_blocks", ctypes.c_int32)]
+                ("profile", ctypes.c_int32), ("device", ctypes.c_int32), ("sweep_blocks", ctypes.c_int32),
+                ("delay_model", ctypes.c_int32)]
 
 
 class sta_info(ctypes.Structure):

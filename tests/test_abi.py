@@ -153,6 +153,13 @@ def test_null_context_calls_are_state_errors():
     assert e.value.status == S.STA_E_STATE
 
 
+def test_reduced_order_delay_option_checks():
+    d = _tiny()
+    assert S.sta_options_default().delay_model == 0
+    _expect(d, S.STA_E_ARG, delay_model=2)
+    _expect(d, S.STA_E_UNSUPPORTED, delay_model=1, mode=1)
+
+
 def test_estimate_rc_host_checks():
     d = synth.generate(synth.tiny_config(seed=5))
     x, y = synth.place(d, seed=2)
