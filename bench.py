@@ -249,6 +249,20 @@ def rc_estimate_side(design, reps: int = 5) -> dict:
             "backward_ms": ms_b}
 
 
+def reduced_order_side(design, sched: int, blocks: int, steps: int, full_ms: float) -> dict:
+    """Full updates of the same design with the reduced-order (Arnoldi) net
+    delays instead of Elmore, same schedule."""
+    import torch
+    from paper_2511_11660_amd.sta import STA
+    s = STA(design, sched=sched, sweep_blocks=blocks, delay_model=1, device=0)
+    stream = torch.cuda.current_stream()
+    s.update(stream)
+    ms = _time_updates([s], stream, steps)
+    s.close()
+    return {"workload": "10M-pin design, reduced-order net delays", "ms": ms, "elmore_ms": full_ms,
+            "pins_per_s": design.n_pins / (ms * 1e-3)}
+
+
 _SCHED_NAMES = {0: "persistent", 1: "per-level", 2: "graph"}
 
 
@@ -281,7 +295,7 @@ def main() -> int:
                     help="auto (tuned at setup), 0 persistent, 1 one launch per level, 2 HIP graph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-side", action="store_true", help="skip every side measurement")
-    ap.add_argument("--side", default="incremental,rc_estimate,adjoint,batched",
+    ap.add_argument("--side", default="incremental,rc_estimate,reduced_order,adjoint,batched",
                     help="comma list of side measurements to run")
     ap.add_argument("--batch-designs", type=int, default=256)
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
@@ -388,6 +402,9 @@ def main() -> int:
     if "rc_estimate" in side:
         print("[bench] RC estimation from pin positions", file=sys.stderr, flush=True)
         out["rc_estimate"] = rc_estimate_side(design)
+    if "reduced_order" in side:
+        print("[bench] reduced-order delays", file=sys.stderr, flush=True)
+        out["reduced_order"] = reduced_order_side(design, sched, s_blocks, args.steps, ms)
     if "adjoint" in side:
         print("[bench] adjoint ratio (1M-pin smooth)", file=sys.stderr, flush=True)
         out["adjoint"] = adjoint_ratio(args.steps)

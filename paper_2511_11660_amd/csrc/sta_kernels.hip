@@ -208,6 +208,7 @@ __device__ __forceinline__ LibRegs lib_issue(const DevDesign &D) {
 #pragma unroll
   for (int u = 0; u < kLibRegs; ++u)  // clamped, unpredicated
     r.v[u] = src[min(u * (int)blockDim.x + (int)threadIdx.x, n4 - 1)];
+  __builtin_amdgcn_sched_barrier(0);  // all requested here, none moved past later waits
   return r;
 }
 
@@ -614,7 +615,6 @@ __global__ __launch_bounds__(kSweepBlock * kCpb) void k_forward(DevDesign D, int
   extern __shared__ __align__(32) unsigned char smem[];
   static_assert(kSweepBlock == 4 * kChunk, "one thread per driver view");
   static_assert(kCpb == 1 || !kInc, "incremental chunks return early: one chunk per block");
-  const LibRegs lib_r = lib_issue(D);  // in flight under the metadata and fanin gathers
   const int half = (int)threadIdx.x / kSweepBlock, tid = (int)threadIdx.x % kSweepBlock;
   const int cb_raw = (int)blockIdx.x * kCpb + half;
   const bool active = cb_raw < n;
@@ -628,23 +628,22 @@ __global__ __launch_bounds__(kSweepBlock * kCpb) void k_forward(DevDesign D, int
   // regular chunks are the level's runs of kChunk slots from xb (no record
   // load on the path to the fanin gathers); a high-fanout driver's own chunk
   // comes after them and is read from its record
-  int x0, x1, s0, s1;
-  if (cb * kChunk < xr - xb) {
+  // Load order matters: the wait for a load also waits for every load issued
+  // before it, so the fanin ids come first, then the library (in flight under
+  // the gathers), then the sink range (only needed for the stores).
+  const bool regular = cb * kChunk < xr - xb;
+  int x0, x1, s0v = 0, s1v = 0;
+  if (regular) {
     x0 = xb + cb * kChunk;
     x1 = min(x0 + kChunk, xr);
-    s0 = __builtin_amdgcn_readfirstlane(D.sink_ptr[x0]);
-    s1 = __builtin_amdgcn_readfirstlane(D.sink_ptr[x1]);
   } else {
     const int4 cr4 = D.chunk_rec[c];
     x0 = __builtin_amdgcn_readfirstlane(cr4.x);
     x1 = __builtin_amdgcn_readfirstlane(cr4.y);
-    s0 = __builtin_amdgcn_readfirstlane(cr4.z);
-    s1 = __builtin_amdgcn_readfirstlane(cr4.w);
+    s0v = cr4.z;
+    s1v = cr4.w;
   }
-  if (!active) {  // no drivers, no sinks
-    x1 = x0;
-    s1 = s0;
-  }
+  if (!active) x1 = x0;  // no drivers (and no sinks, below)
   const int x = x0 + dv;
   const bool live = x < x1;
   const int xc = live ? x : x0;
@@ -658,9 +657,14 @@ __global__ __launch_bounds__(kSweepBlock * kCpb) void k_forward(DevDesign D, int
     pa = reinterpret_cast<const float *>(D.pi_at + xc)[v];
     ps = reinterpret_cast<const float *>(D.pi_slew + xc)[v];
   } else {
+    if (inl) f4 = D.fanin4[xc];
     t = D.cell_type[xc];
     L = D.L_net[xc];
-    if (inl) f4 = D.fanin4[xc];
+  }
+  const LibRegs lib_r = lib_issue(D);
+  if (regular) {
+    s0v = D.sink_ptr[x0];
+    s1v = D.sink_ptr[x1];
   }
   if constexpr (kInc) {
     if (__builtin_amdgcn_readfirstlane(flagged) == 0u) return;
@@ -674,6 +678,8 @@ __global__ __launch_bounds__(kSweepBlock * kCpb) void k_forward(DevDesign D, int
     iat[k] = *reinterpret_cast<const float2 *>(st + 2 * el);
     isl[k] = *reinterpret_cast<const float2 *>(st + 4 + 2 * el);
   }
+  const int s0 = __builtin_amdgcn_readfirstlane(s0v);
+  const int s1 = active ? __builtin_amdgcn_readfirstlane(s1v) : s0;
   const int sA = min(s0 + tid, max(s1 - 1, 0));
   const int dA = D.sink_drv[sA];
   const float2 wA = D.dq[sA];
@@ -957,7 +963,6 @@ template <bool kInc, int kCpb>
 __global__ __launch_bounds__(kSweepBlock * kCpb) void k_backward(DevDesign D, int c0, int c1, IncArgs I) {
   extern __shared__ __align__(32) unsigned char smem[];
   static_assert(kCpb == 1 || !kInc, "incremental chunks return early: one chunk per block");
-  const LibRegs lib_r = lib_issue(D);  // in flight under the sink loads
   const int half = (int)threadIdx.x / kSweepBlock, tid = (int)threadIdx.x % kSweepBlock;
   const int c_raw = c0 + (int)blockIdx.x * kCpb + half;
   const bool active = c_raw < c1;
@@ -997,20 +1002,36 @@ __global__ __launch_bounds__(kSweepBlock * kCpb) void k_backward(DevDesign D, in
     if (I.fanin_cc) fcc = I.fanin_cc[xc];
     if (__builtin_amdgcn_readfirstlane(flagged) == 0u) return;
   }
+  // Load order matters (a wait covers every earlier load): the sink data
+  // above, then the library, then the first sink's consumer record, which
+  // thus travels while the library is stored and the block synchronizes.
+  // A consumer's (RAT of this half, (load, type)); an endpoint's RAT pair.
+  struct ConsIn {
+    float2 ro, lt;
+  };
+  auto ld_cons = [&](int cons) {  // unpredicated loads (an endpoint reads record 0's (load, type) unused)
+    ConsIn ci;
+    const float *rp = cons < 0 ? reinterpret_cast<const float *>(D.ep_rat + (-1 - cons))
+                               : reinterpret_cast<const float *>(&D.cons_rec[cons].rat);
+    ci.ro = *reinterpret_cast<const float2 *>(rp + 2 * el);
+    ci.lt = *reinterpret_cast<const float2 *>(&D.cons_rec[max(cons, 0)].L);
+    return ci;
+  };
+  const LibRegs lib_r = lib_issue(D);
+  const ConsIn ciA = ld_cons(consA);
   const LdsLib lib = lib_store(D, smem, lib_r);
   int *wacc = reinterpret_cast<int *>(smem + lib_lds_bytes(D.n_types, D.tstride)) + half * kSweepBlock;
   wacc[tid] = f2key((v >> 1) ? kInf : -kInf);
   lds_barrier();
   const TabLayout lay{D.nx, D.ny};
-  auto sink = [&](int s, float2 at, float2 sl, int cons, float d, int drv) {
+  auto sink = [&](int s, float2 at, float2 sl, int cons, float d, int drv, const ConsIn &ci) {
     float r[2];
     if (cons < 0) {
-      const float *er = reinterpret_cast<const float *>(D.ep_rat + (-1 - cons));
-      r[0] = er[2 * el];
-      r[1] = er[2 * el + 1];
+      r[0] = ci.ro.x;
+      r[1] = ci.ro.y;
     } else {
-      const float2 Ro = *reinterpret_cast<const float2 *>(reinterpret_cast<const float *>(&D.cons_rec[cons].rat) + 2 * el);
-      const float2 Lt = *reinterpret_cast<const float2 *>(&D.cons_rec[cons].L);
+      const float2 Ro = ci.ro;
+      const float2 Lt = ci.lt;
       const int t = __float_as_int(Lt.y);
       const int sense = lib.sense[t];
       const float *tb = lib.tab + t * D.tstride;
@@ -1065,11 +1086,12 @@ __global__ __launch_bounds__(kSweepBlock * kCpb) void k_backward(DevDesign D, in
       atomicMax(acc + 1, f2key(r[1] - d));
     }
   };
-  if (sA < s1) sink(sA, atA, slA, consA, dA, drvA);
+  if (sA < s1) sink(sA, atA, slA, consA, dA, drvA, ciA);
   for (int sj = sA + kSweepBlock / 2; sj < s1; sj += kSweepBlock / 2) {
     float2 at, sl;
     ld_half(sj, at, sl);
-    sink(sj, at, sl, D.sink_cons[sj], D.dq[sj].x, D.sink_drv[sj]);
+    const int cons = D.sink_cons[sj];
+    sink(sj, at, sl, cons, D.dq[sj].x, D.sink_drv[sj], ld_cons(cons));
   }
   lds_barrier();
   float R = key2f(wacc[tid]);
