@@ -629,8 +629,8 @@ __global__ __launch_bounds__(kSweepBlock * kCpb) void k_forward(DevDesign D, int
   // load on the path to the fanin gathers); a high-fanout driver's own chunk
   // comes after them and is read from its record
   // Load order matters: the wait for a load also waits for every load issued
-  // before it, so the fanin ids come first, then the library (in flight under
-  // the gathers), then the sink range (only needed for the stores).
+  // before it, so the cell's own loads (the fanin ids first) come first, then
+  // the library, then the sink range (only needed for the stores).
   const bool regular = cb * kChunk < xr - xb;
   int x0, x1, s0v = 0, s1v = 0;
   if (regular) {
@@ -648,19 +648,15 @@ __global__ __launch_bounds__(kSweepBlock * kCpb) void k_forward(DevDesign D, int
   const bool live = x < x1;
   const int xc = live ? x : x0;
   const bool pis = x0 < D.n_pi;  // level 0: primary inputs only
-  const bool inl = !pis && D.fanin4;
-  int t = 0;
-  float L = 0.0f;
-  int4 f4 = make_int4(-1, -1, -1, -1);
-  float pa = 0.0f, ps = 0.0f;
-  if (pis) {
-    pa = reinterpret_cast<const float *>(D.pi_at + xc)[v];
-    ps = reinterpret_cast<const float *>(D.pi_slew + xc)[v];
-  } else {
-    if (inl) f4 = D.fanin4[xc];
-    t = D.cell_type[xc];
-    L = D.L_net[xc];
-  }
+  // every load unconditional (all indices valid for PI and cell slots alike):
+  // a load under a branch makes the compiler wait for it at the branch's end
+  const bool inl = kSlots > 0 && !pis;
+  const int4 f4 = kSlots > 0 ? D.fanin4[xc] : make_int4(-1, -1, -1, -1);
+  const int t = D.cell_type[xc];
+  const float L = D.L_net[xc];
+  const int xpi = min(xc, max(D.n_pi - 1, 0));
+  const float pa = reinterpret_cast<const float *>(D.pi_at + xpi)[v];
+  const float ps = reinterpret_cast<const float *>(D.pi_slew + xpi)[v];
   const LibRegs lib_r = lib_issue(D);
   if (regular) {
     s0v = D.sink_ptr[x0];
@@ -708,7 +704,7 @@ __global__ __launch_bounds__(kSweepBlock * kCpb) void k_forward(DevDesign D, int
     at_v = el ? -kInf : kInf;
     sl_v = el ? -kInf : kInf;
     float lse = 0.0f;
-    if (inl) {
+    if constexpr (kSlots > 0) {
       merge_slots<kSlots>(D, cc, el, ro, iat, isl, fs, at_v, sl_v, cr_v, lse);
     } else {
       const int f0 = D.fanin_ptr[xc], f1 = D.fanin_ptr[xc + 1];
@@ -3102,6 +3098,8 @@ static hipError_t forward_phase(const DevDesign &D, const IncArgs &I, int4 ph, i
   if (ph.x == kItemPiece)
     hipLaunchKernelGGL(k_forward_pieces<kInc>, dim3(blocks_for(ph.z, per)), dim3(kSweepBlock), 0, s, D, ph.y,
                        ph.y + ph.z, I);
+  else if (!D.fanin4)  // a type of more than 4 inputs: fanins through the CSR
+    launch_fwd_chunks<kInc, 0>(D, I, ph, reg, s);
   else if (D.max_in <= 1)
     launch_fwd_chunks<kInc, 1>(D, I, ph, reg, s);
   else if (D.max_in == 2)
