@@ -2084,6 +2084,8 @@ __device__ __forceinline__ void stage_rc_nodes(const DevDesign &D, int k0, int n
   }
 }
 
+constexpr int kSinkRound = 8;  // sink node ids a lane requests together in the RC kernels
+
 // Small nets: one block per chunk of <= 256 nets (<= kRcChunkNodes nodes,
 // consecutive in RC order): coalesced staging of parent/R/C into LDS, one net
 // per thread, each thread writing its net's load and sink moments.  Block 0
@@ -2130,10 +2132,17 @@ __global__ __launch_bounds__(kRcBlock) void k_rc(DevDesign D, const int2 *chunks
         S4 += c * m2 * m2;
       }
       const Red2 r = red2_model(S1, S2, S3, S4);
-      for (int s = s0; s < s1; ++s) {
-        const int k = b + D.sink_node[s];
-        const float d = s_B[k];
-        D.dq[s] = make_float2((float)red2_half_time(r, d, s_A[k]), fmaxf(0.0f, 2.0f * s_A[k] - d * d));
+      for (int s = s0; s < s1; s += kSinkRound) {
+        int kk[kSinkRound];
+#pragma unroll
+        for (int u = 0; u < kSinkRound; ++u) kk[u] = D.sink_node[min(s + u, s1 - 1)];
+#pragma unroll
+        for (int u = 0; u < kSinkRound; ++u) {
+          const int k = b + kk[u];
+          const float d = s_B[k];
+          if (s + u < s1)
+            D.dq[s + u] = make_float2((float)red2_half_time(r, d, s_A[k]), fmaxf(0.0f, 2.0f * s_A[k] - d * d));
+        }
       }
       return;
     }
@@ -2145,10 +2154,19 @@ __global__ __launch_bounds__(kRcBlock) void k_rc(DevDesign D, const int2 *chunks
         D.dq[s0 + u] = make_float2(d, fmaxf(0.0f, 2.0f * s_A[k] - d * d));
       }
     }
-    for (int s = s0 + kPre; s < s1; ++s) {
-      const int k = b + D.sink_node[s];
-      const float d = s_B[k];
-      D.dq[s] = make_float2(d, fmaxf(0.0f, 2.0f * s_A[k] - d * d));
+    // the rest in rounds of kSinkRound: every node id of a round requested
+    // before any is used (clamped, unpredicated loads and stores: a lane past
+    // the net's last sink repeats that sink's write), one round trip a round
+    for (int s = s0 + kPre; s < s1; s += kSinkRound) {
+      int kk[kSinkRound];
+#pragma unroll
+      for (int u = 0; u < kSinkRound; ++u) kk[u] = D.sink_node[min(s + u, s1 - 1)];
+#pragma unroll
+      for (int u = 0; u < kSinkRound; ++u) {
+        const int k = b + kk[u];
+        const float d = s_B[k];
+        D.dq[min(s + u, s1 - 1)] = make_float2(d, fmaxf(0.0f, 2.0f * s_A[k] - d * d));
+      }
     }
   }
 }
@@ -2677,12 +2695,23 @@ __global__ __launch_bounds__(kRcBlock) void k_rc_adjoint(DevDesign D, const int2
     float *A = s_A, *B = s_B, *C = s_C, *E = s_E, *F = s_F, *G = s_G, *R = s_R;
     (void)rc_tree_lds(par, R, C, A, B, b, m);  // A = m2, B = d
     for (int k = 0; k < m; ++k) E[b + k] = F[b + k] = 0.0f;
-    for (int s = sr.x; s < sr.y; ++s) {
-      const int k = b + D.sink_node[s];
-      const float2 g = D.g_dq[s];
-      const float gq = (2.0f * A[k] - B[k] * B[k]) > 0.0f ? g.y : 0.0f;
-      E[k] += g.x - 2.0f * B[k] * gq;
-      F[k] += 2.0f * gq;
+    for (int s = sr.x; s < sr.y; s += kSinkRound) {  // (rounds as in k_rc; sinks in order)
+      int kk[kSinkRound];
+      float2 gg[kSinkRound];
+#pragma unroll
+      for (int u = 0; u < kSinkRound; ++u) {
+        kk[u] = D.sink_node[min(s + u, sr.y - 1)];
+        gg[u] = D.g_dq[min(s + u, sr.y - 1)];
+      }
+#pragma unroll
+      for (int u = 0; u < kSinkRound; ++u) {
+        const int k = b + kk[u];
+        const float gq = (2.0f * A[k] - B[k] * B[k]) > 0.0f ? gg[u].y : 0.0f;
+        if (s + u < sr.y) {
+          E[k] += gg[u].x - 2.0f * B[k] * gq;
+          F[k] += 2.0f * gq;
+        }
+      }
     }
     for (int k = m - 1; k >= 1; --k) {  // Gd, Gm
       E[b + par[b + k]] += E[b + k];
