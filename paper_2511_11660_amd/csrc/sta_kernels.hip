@@ -2039,19 +2039,32 @@ __device__ double red2_half_time(const Red2 &r, double d, double m2) {
   const double e = (m2 - r.alpha1 * d) * r.inv_b1;  // 0 for the one-pole model
   const double a0 = r.p0 ? r.u10 * (r.u10 * d + r.u20 * e) / r.tau0 : 0.0;
   const double a1 = r.p1 ? r.u11 * (r.u11 * d + r.u21 * e) / r.tau1 : 0.0;
-  auto f = [&](double t) { return a0 * exp(-t / r.tau0) + a1 * exp(-t / r.tau1) - 0.5; };
-  if (f(0.0) <= 0.0) return 0.0;
+  // a missing pole has a = 0; its rate is set to 0 so its term stays finite
+  const double k0 = r.p0 ? 1.0 / r.tau0 : 0.0, k1 = r.p1 ? 1.0 / r.tau1 : 0.0;
+  auto f = [&](double t) { return a0 * exp(-t * k0) + a1 * exp(-t * k1) - 0.5; };
+  if (a0 + a1 - 0.5 <= 0.0) return 0.0;
   double hi = fmax(r.p0 ? r.tau0 : 0.0, r.p1 ? r.tau1 : 0.0);
   for (int i = 0; i < 1100 && f(hi) > 0.0; ++i) hi *= 2.0;
-  double lo = 0.0;
-  for (int i = 0; i < 64; ++i) {
-    const double mid = 0.5 * (lo + hi);
-    if (f(mid) > 0.0)
-      lo = mid;
+  // The impulse response a0 k0 e^{-k0 t} + a1 k1 e^{-k1 t} changes sign at
+  // most once, so f has exactly one root in (0, hi]: Newton steps kept inside
+  // the bracket [lo, hi] (f(lo) > 0 >= f(hi)), a bisection whenever a step
+  // leaves it, until a step moves the iterate by under 1e-13 of itself.
+  double lo = 0.0, t = 0.5 * hi;
+  for (int i = 0; i < 200; ++i) {
+    const double e0 = exp(-t * k0), e1 = exp(-t * k1);
+    const double ft = a0 * e0 + a1 * e1 - 0.5;
+    const double dft = -(a0 * k0 * e0 + a1 * k1 * e1);
+    if (ft > 0.0)
+      lo = t;
     else
-      hi = mid;
+      hi = t;
+    double tn = t - ft / dft;
+    if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);  // also catches dft = 0 (NaN or inf)
+    const bool done = fabs(tn - t) <= 1e-13 * t || hi - lo <= 1e-15 * hi;
+    t = tn;
+    if (done) break;
   }
-  return 0.5 * (lo + hi);
+  return t;
 }
 
 // Stages nodes [k0, k0 + nk) of one RC chunk into LDS: parent, R and

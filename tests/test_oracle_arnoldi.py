@@ -96,3 +96,25 @@ def test_delays_are_positive_and_below_elmore_for_far_sinks(seed):
     got = AR.net_delays(parent, R, C, [far])[0]
     assert 0.0 < exact <= d[far - 1]
     assert got == pytest.approx(exact, rel=0.1)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_half_level_is_crossed_once(seed):
+    """At every node the two-pole response crosses one half exactly once on
+    t > 0 (the impulse response, a sum of two exponentials, changes sign at
+    most once), so any bracketing root finder of the half-time equation
+    lands on the root the bisection finds."""
+    rng = np.random.default_rng(40 + seed)
+    parent, R, C = _random_tree(rng, int(rng.integers(5, 40)))
+    a, tau = AR.model(parent, R, C)
+    t = np.linspace(0.0, 40.0 * float(tau.max()), 40001)
+    for i in range(a.shape[0]):
+        f = (a[i][None, :] * np.exp(-t[:, None] / tau[None, :])).sum(axis=1) - 0.5
+        s = np.sign(f)
+        s = s[s != 0]
+        assert np.count_nonzero(np.diff(s)) <= 1
+        th = AR.half_time(a[i], tau)
+        if f[0] > 0.0:
+            assert abs(float(np.sum(a[i] * np.exp(-th / tau))) - 0.5) < 1e-12
+        else:
+            assert th == 0.0
