@@ -2041,14 +2041,51 @@ __device__ double red2_half_time(const Red2 &r, double d, double m2) {
   const double a1 = r.p1 ? r.u11 * (r.u11 * d + r.u21 * e) / r.tau1 : 0.0;
   // a missing pole has a = 0; its rate is set to 0 so its term stays finite
   const double k0 = r.p0 ? 1.0 / r.tau0 : 0.0, k1 = r.p1 ? 1.0 / r.tau1 : 0.0;
-  auto f = [&](double t) { return a0 * exp(-t * k0) + a1 * exp(-t * k1) - 0.5; };
   if (a0 + a1 - 0.5 <= 0.0) return 0.0;
-  double hi = fmax(r.p0 ? r.tau0 : 0.0, r.p1 ? r.tau1 : 0.0);
-  for (int i = 0; i < 1100 && f(hi) > 0.0; ++i) hi *= 2.0;
+  const double tmax = fmax(r.p0 ? r.tau0 : 0.0, r.p1 ? r.tau1 : 0.0);
   // The impulse response a0 k0 e^{-k0 t} + a1 k1 e^{-k1 t} changes sign at
-  // most once, so f has exactly one root in (0, hi]: Newton steps kept inside
-  // the bracket [lo, hi] (f(lo) > 0 >= f(hi)), a bisection whenever a step
-  // leaves it, until a step moves the iterate by under 1e-13 of itself.
+  // most once, so f(t) = a0 e^{-k0 t} + a1 e^{-k1 t} - 1/2 has exactly one
+  // root in (0, inf).  Each solve below is Newton kept inside a bracket
+  // [lo, hi] with f(lo) > 0 >= f(hi) (the first doubling of tau_max), with a
+  // bisection whenever a step leaves it.
+  // 1) FP32 with the hardware exponential, from the Elmore delay times ln 2
+  //    (the one-pole answer), to about 1e-6.
+  const float a0f = (float)a0, a1f = (float)a1, k0f = (float)k0, k1f = (float)k1;
+  auto ff = [&](float t) { return a0f * __expf(-t * k0f) + a1f * __expf(-t * k1f) - 0.5f; };
+  float lof = 0.0f, hif = (float)tmax;
+  for (int i = 0; i < 300 && ff(hif) > 0.0f; ++i) hif *= 2.0f;
+  float tf = 0.6931472f * (float)d;
+  if (!(tf > lof && tf < hif)) tf = 0.5f * hif;
+  for (int i = 0; i < 60; ++i) {
+    const float e0 = __expf(-tf * k0f), e1 = __expf(-tf * k1f);
+    const float ft = a0f * e0 + a1f * e1 - 0.5f;
+    const float dft = -(a0f * k0f * e0 + a1f * k1f * e1);
+    if (ft > 0.0f)
+      lof = tf;
+    else
+      hif = tf;
+    float tn = tf - ft / dft;
+    if (!(tn > lof && tn < hif)) tn = 0.5f * (lof + hif);
+    const bool done = fabsf(tn - tf) <= 1e-6f * tf || hif - lof <= 1e-7f * hif;
+    tf = tn;
+    if (done) break;
+  }
+  // 2) One FP64 Newton step from there.  A step under 1e-5 of t means the
+  //    FP32 root was that close, and the step (quadratic convergence) leaves
+  //    an error near 1e-10 of t.
+  {
+    const double t = (double)tf;
+    const double e0 = exp(-t * k0), e1 = exp(-t * k1);
+    const double ft = a0 * e0 + a1 * e1 - 0.5;
+    const double dft = -(a0 * k0 * e0 + a1 * k1 * e1);
+    const double tn = t - ft / dft;
+    if (t > 0.0 && fabs(tn - t) <= 1e-5 * t) return tn;
+  }
+  // 3) Otherwise (FP32 too coarse for this model) the whole solve in FP64,
+  //    until a step moves t by under 1e-13 of itself.
+  auto f = [&](double t) { return a0 * exp(-t * k0) + a1 * exp(-t * k1) - 0.5; };
+  double hi = tmax;
+  for (int i = 0; i < 1100 && f(hi) > 0.0; ++i) hi *= 2.0;
   double lo = 0.0, t = 0.5 * hi;
   for (int i = 0; i < 200; ++i) {
     const double e0 = exp(-t * k0), e1 = exp(-t * k1);
@@ -2099,11 +2136,91 @@ __device__ __forceinline__ void stage_rc_nodes(const DevDesign &D, int k0, int n
 
 constexpr int kSinkRound = 8;  // sink node ids a lane requests together in the RC kernels
 
+// Reduced-order sink delays of one RC chunk, after every thread has run its
+// net's tree passes (d in s_B, m2 in s_A, C^ in s_C): each thread builds its
+// net's two-pole model into LDS, then the block's sinks are shared out evenly
+// (sink f of the chunk's concatenated sink lists goes to thread f mod the
+// block size), so a net with many sinks no longer holds up its wavefront.
+__device__ __forceinline__ void rc_reduced_sinks(const DevDesign &D, bool live, int2 sr, const float *s_C,
+                                                 const float *s_A, const float *s_B, const int *s_base) {
+  __shared__ double s_mod[8][kRcBlock];
+  __shared__ uint8_t s_pole[kRcBlock];
+  __shared__ int s_sx[kRcBlock], s_pf[kRcBlock + 1], s_wsum[kRcBlock / kWave];
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+  int cnt = 0;
+  if (live) {
+    const int b = s_base[tid], m = s_base[tid + 1] - b;
+    double S1 = 0.0, S2 = 0.0, S3 = 0.0, S4 = 0.0;
+    for (int k = 1; k < m; ++k) {
+      const double c = s_C[b + k], d = s_B[b + k], m2 = s_A[b + k];
+      S1 += c * d;
+      S2 += c * d * d;
+      S3 += c * d * m2;
+      S4 += c * m2 * m2;
+    }
+    const Red2 r = red2_model(S1, S2, S3, S4);
+    s_mod[0][tid] = r.tau0;
+    s_mod[1][tid] = r.tau1;
+    s_mod[2][tid] = r.u10;
+    s_mod[3][tid] = r.u20;
+    s_mod[4][tid] = r.u11;
+    s_mod[5][tid] = r.u21;
+    s_mod[6][tid] = r.alpha1;
+    s_mod[7][tid] = r.inv_b1;
+    s_pole[tid] = (uint8_t)((r.p0 ? 1 : 0) | (r.p1 ? 2 : 0));
+    cnt = sr.y - sr.x;
+  }
+  s_sx[tid] = sr.x;
+  // exclusive prefix of the sink counts: a scan per wavefront, then the
+  // wavefront totals
+  int v = cnt;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int y = __shfl_up(v, o, kWave);
+    v += lane >= o ? y : 0;
+  }
+  if (lane == kWave - 1) s_wsum[wave] = v;
+  lds_barrier();
+  int off = 0;
+  for (int w = 0; w < wave; ++w) off += s_wsum[w];
+  s_pf[tid + 1] = off + v;
+  if (tid == 0) s_pf[0] = 0;
+  lds_barrier();
+  const int total = s_pf[kRcBlock];
+  for (int f = tid; f < total; f += kRcBlock) {
+    int lo = 0, hi = kRcBlock;  // s_pf[lo] <= f < s_pf[hi]: lo owns sink f (its count is > 0)
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (s_pf[mid] <= f)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    const int sk = s_sx[lo] + (f - s_pf[lo]);
+    const int k = s_base[lo] + D.sink_node[sk];
+    Red2 r;
+    r.tau0 = s_mod[0][lo];
+    r.tau1 = s_mod[1][lo];
+    r.u10 = s_mod[2][lo];
+    r.u20 = s_mod[3][lo];
+    r.u11 = s_mod[4][lo];
+    r.u21 = s_mod[5][lo];
+    r.alpha1 = s_mod[6][lo];
+    r.inv_b1 = s_mod[7][lo];
+    r.p0 = (s_pole[lo] & 1) != 0;
+    r.p1 = (s_pole[lo] & 2) != 0;
+    const float d = s_B[k];
+    D.dq[sk] = make_float2((float)red2_half_time(r, d, s_A[k]), fmaxf(0.0f, 2.0f * s_A[k] - d * d));
+  }
+}
+
 // Small nets: one block per chunk of <= 256 nets (<= kRcChunkNodes nodes,
 // consecutive in RC order): coalesced staging of parent/R/C into LDS, one net
-// per thread, each thread writing its net's load and sink moments.  Block 0
-// also clears the sweep counters for the launches that follow.
+// per thread, each thread writing its net's load and sink moments (kRed: the
+// sink delays of the reduced-order model instead of Elmore's).  Block 0 also
+// clears the sweep counters for the launches that follow.
 // only: optional per-chunk flags (incremental update: unflagged chunks return).
+template <bool kRed>
 __global__ __launch_bounds__(kRcBlock) void k_rc(DevDesign D, const int2 *chunks, int n_chunks,
                                                  uint32_t *counters, int n_counters, const uint32_t *only) {
   __shared__ uint8_t s_par[kRcChunkNodes];
@@ -2129,36 +2246,21 @@ __global__ __launch_bounds__(kRcBlock) void k_rc(DevDesign D, const int2 *chunks
 #pragma unroll
   for (int u = 0; u < kPre; ++u) sn[u] = D.sink_node[min(sr.x + u, max(sr.y - 1, 0))];
   lds_barrier();
+  if constexpr (kRed) {  // reduced-order delays replace the Elmore ones
+    if (j < j1) {
+      const float L = rc_tree_lds(s_par, s_R, s_C, s_A, s_B, s_base[tid], s_base[tid + 1] - s_base[tid]);
+      D.L_net[x] = L;
+      D.cons_rec[x].L = L;
+    }
+    rc_reduced_sinks(D, j < j1, j < j1 ? sr : make_int2(0, 0), s_C, s_A, s_B, s_base);
+    return;
+  }
   if (j < j1) {
     const int b = s_base[tid], m = s_base[tid + 1] - b;
     const int s0 = sr.x, s1 = sr.y;
     const float L = rc_tree_lds(s_par, s_R, s_C, s_A, s_B, b, m);
     D.L_net[x] = L;
     D.cons_rec[x].L = L;
-    if (D.delay_model == 1) {  // reduced-order delays replace the Elmore ones
-      double S1 = 0.0, S2 = 0.0, S3 = 0.0, S4 = 0.0;
-      for (int k = 1; k < m; ++k) {
-        const double c = s_C[b + k], d = s_B[b + k], m2 = s_A[b + k];
-        S1 += c * d;
-        S2 += c * d * d;
-        S3 += c * d * m2;
-        S4 += c * m2 * m2;
-      }
-      const Red2 r = red2_model(S1, S2, S3, S4);
-      for (int s = s0; s < s1; s += kSinkRound) {
-        int kk[kSinkRound];
-#pragma unroll
-        for (int u = 0; u < kSinkRound; ++u) kk[u] = D.sink_node[min(s + u, s1 - 1)];
-#pragma unroll
-        for (int u = 0; u < kSinkRound; ++u) {
-          const int k = b + kk[u];
-          const float d = s_B[k];
-          if (s + u < s1)
-            D.dq[s + u] = make_float2((float)red2_half_time(r, d, s_A[k]), fmaxf(0.0f, 2.0f * s_A[k] - d * d));
-        }
-      }
-      return;
-    }
 #pragma unroll
     for (int u = 0; u < kPre; ++u) {
       if (s0 + u < s1) {
@@ -3100,8 +3202,11 @@ static hipError_t launch_sweep(const DevDesign &D, float g_tns, float g_wns, int
 
 hipError_t launch_rc(const DevDesign &D, const int2 *chunks, int n_chunks, hipStream_t s, const uint32_t *only) {
   const int n_ctr = n_counters(D.n_ph_fwd + D.n_ph_bwd);
-  hipLaunchKernelGGL(k_rc, dim3(xcd_grid(n_chunks > 0 ? n_chunks : 1)), dim3(kRcBlock), 0, s, D, chunks, n_chunks,
-                     D.counters, n_ctr, only);
+  const dim3 grid(xcd_grid(n_chunks > 0 ? n_chunks : 1));
+  if (D.delay_model == 1)
+    hipLaunchKernelGGL(k_rc<true>, grid, dim3(kRcBlock), 0, s, D, chunks, n_chunks, D.counters, n_ctr, only);
+  else
+    hipLaunchKernelGGL(k_rc<false>, grid, dim3(kRcBlock), 0, s, D, chunks, n_chunks, D.counters, n_ctr, only);
   return hipGetLastError();
 }
 
