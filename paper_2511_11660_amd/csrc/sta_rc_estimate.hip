@@ -210,10 +210,13 @@ __global__ __launch_bounds__(256) void k_est_wave(EstArgs A, const int32_t *list
 // l = tid + 1024 u, u < NL).  Per step only distances and parent nodes move;
 // the RC nodes are written after the last step, when every pin knows its join
 // step and its parent's node (the parent's pin comes from the join table).
+// Every pin's position is also kept in LDS, where each step reads the joining
+// pin's (a per-slot select of the candidate's position would cost three more
+// instructions per slot and step).
 template <int NL>
 __device__ __forceinline__ void est_block_net(const EstArgs &A, int n, int s0, int k, int64_t base,
                                               uint32_t (*s_key)[1024 / kWave], uint32_t (*s_idx)[1024 / kWave],
-                                              PinLoc (*s_loc)[1024 / kWave], uint16_t *s_join) {
+                                              PinLoc *s_pos, uint16_t *s_join) {
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   const float x0 = A.x[A.driver[n]], y0 = A.y[A.driver[n]];
   const float kNaN = __builtin_nanf("");
@@ -228,6 +231,7 @@ __device__ __forceinline__ void est_block_net(const EstArgs &A, int n, int s0, i
     const int pin = A.sink_pin[s0 + (valid ? l - 1 : 0)];
     x[u] = valid ? A.x[pin] : kNaN;  // NaN: never nearer than anything
     y[u] = valid ? A.y[pin] : kNaN;
+    if (valid) s_pos[l] = PinLoc{x[u], y[u]};
     dist[u] = valid ? manhattan(x[u], y[u], x0, y0) : kFar;
     pnode[u] = 0;
     tj[u] = 0;
@@ -235,40 +239,26 @@ __device__ __forceinline__ void est_block_net(const EstArgs &A, int n, int s0, i
     key = b ? dist[u] : key;
     ul = b ? u : ul;
   }
+  __syncthreads();  // s_pos complete
   for (int t = 1; t <= k; ++t) {
-    float kx = x[0], ky = y[0];
-#pragma unroll
-    for (int u = 1; u < NL; ++u) {
-      kx = ul == u ? x[u] : kx;
-      ky = ul == u ? y[u] : ky;
-    }
     const uint32_t wk = wave_min(key_of(key));
     const uint32_t wi = wave_min(key_of(key) == wk && key < kFar ? (uint32_t)(tid + ul * 1024) : kNone);
-    // the wave winner's position from its lane (l and its thread share the
-    // lane), read in uniform control flow
-    const uint32_t src = wi == kNone ? 0u : (wi & (kWave - 1));
-    const float wx = lane_float(kx, src), wy = lane_float(ky, src);
     const int buf = t & 1;
     if (lane == 0) {
       s_key[buf][wave] = wk;
       s_idx[buf][wave] = wi;
-      s_loc[buf][wave] = PinLoc{wx, wy};
     }
     __syncthreads();
     // the 16 wave winners, one per lane of each row: row minima by DPP, so
-    // the reduction costs every wave a few vector instructions
+    // the reduction costs every wave a few vector instructions; every row
+    // holds all 16, so the result is the same in every lane
     const int e = lane & (1024 / kWave - 1);
     const uint32_t ek = s_key[buf][e], ei = s_idx[buf][e];
-    const PinLoc el = s_loc[buf][e];
     const uint32_t bk = row_min16(ek);
     const uint32_t bi = row_min16(ek == bk ? ei : kNone);
-    const uint64_t hit = __ballot(ek == bk && ei == bi);
-    const uint32_t we = (uint32_t)__builtin_ctzll(hit);  // nonempty: some entry holds the minimum
-    PinLoc bl;
-    bl.x = lane_float(el.x, we);
-    bl.y = lane_float(el.y, we);
-    const int j = (int)__builtin_amdgcn_readfirstlane((int)bi);
-    const float xj = bl.x, yj = bl.y;
+    const int j = (int)__builtin_amdgcn_readfirstlane((int)bi);  // a pin outside the tree is left
+    const PinLoc pj = s_pos[j];
+    const float xj = pj.x, yj = pj.y;
     const int ju = j >> 10;
     if (tid == (j & 1023)) {  // the joining pin leaves the candidates
 #pragma unroll
@@ -313,7 +303,7 @@ __device__ __forceinline__ void est_block_net(const EstArgs &A, int n, int s0, i
 __global__ __launch_bounds__(1024) void k_est_block(EstArgs A, const int32_t *list, const uint32_t *count) {
   __shared__ uint32_t s_key[2][1024 / kWave];
   __shared__ uint32_t s_idx[2][1024 / kWave];
-  __shared__ PinLoc s_loc[2][1024 / kWave];
+  __shared__ PinLoc s_pos[kEstMaxPins];
   __shared__ uint16_t s_join[kEstMaxPins];
   const int nb = (int)*count;
   for (int b = blockIdx.x; b < nb; b += gridDim.x) {
@@ -323,7 +313,7 @@ __global__ __launch_bounds__(1024) void k_est_block(EstArgs A, const int32_t *li
     switch (k >> 10) {  // live slots - 1: pins 0..k over 1024 threads
 #define STA_EST_NET(c) \
   case c - 1:          \
-    est_block_net<c>(A, n, s0, k, base, s_key, s_idx, s_loc, s_join); \
+    est_block_net<c>(A, n, s0, k, base, s_key, s_idx, s_pos, s_join); \
     break;
       STA_EST_NET(1) STA_EST_NET(2) STA_EST_NET(3) STA_EST_NET(4) STA_EST_NET(5) STA_EST_NET(6)
       STA_EST_NET(7) STA_EST_NET(8) STA_EST_NET(9) STA_EST_NET(10) STA_EST_NET(11) STA_EST_NET(12)
