@@ -306,8 +306,8 @@ def main() -> int:
     if args.copy_calib:
         return copy_calibration(args.copy_calib, args.steps)
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is a design note "
-                                   "only (see DESIGN.md)", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "the timer runs on one GPU; splitting a design over several GPUs "
+                                   "is not implemented", "n_gpus": args.gpus}))
         return 2
 
     import numpy as np
