@@ -331,9 +331,50 @@ __global__ __launch_bounds__(1024) void k_est_block(EstArgs A, const int32_t *li
 // st[3] / st[4] / st[5] the first net (CSR or driver), sink entry and pin
 // position found malformed (kNone when none).  The host reads st before any
 // estimation kernel runs, so those never see a bad index or position.
-__global__ void k_est_check(EstArgs A, int n_pins, int n_sinks, int32_t *mid, int32_t *big, uint32_t *st) {
+// Exclusive prefix of c over a 256-thread block (a scan per wavefront, then
+// the wavefront totals); *total gets the block's sum.  Every thread calls it.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t c, uint32_t *s_w, uint32_t *total) {
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  int v = (int)c;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int y = __shfl_up(v, o, kWave);
+    v += lane >= o ? y : 0;
+  }
+  if (lane == kWave - 1) s_w[wave] = (uint32_t)v;
+  __syncthreads();
+  uint32_t off = 0, tot = 0;
+  for (int w = 0; w < 256 / kWave; ++w) {
+    off += w < wave ? s_w[w] : 0u;
+    tot += s_w[w];
+  }
+  *total = tot;
+  return off + (uint32_t)v - c;
+}
+
+__device__ __forceinline__ bool est_mid_net(const EstArgs &A, int n, int n_pins, int n_sinks) {
+  const int a = A.sink_ptr[n], b = A.sink_ptr[n + 1], drv = A.driver[n];
+  const bool ok = a >= 0 && b >= a && b <= n_sinks && (n > 0 || a == 0) && drv >= 0 && drv < n_pins;
+  return ok && b - a + 1 <= kWave && b - a + 1 > kLanePins;
+}
+
+// The mid list is filled without one atomic per net on a single counter (tens
+// of thousands of those serialized at one L2 address): each block counts its
+// mid nets first, reserves their slots with one atomic, then writes them.
+__global__ __launch_bounds__(256) void k_est_check(EstArgs A, int n_pins, int n_sinks, int32_t *mid, int32_t *big,
+                                                   uint32_t *st) {
+  __shared__ uint32_t s_w[256 / kWave];
+  __shared__ uint32_t s_base;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t top = max(max((int64_t)A.n_nets, (int64_t)n_sinks), (int64_t)n_pins);
+  uint32_t cnt = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < A.n_nets; i += stride)
+    cnt += est_mid_net(A, (int)i, n_pins, n_sinks) ? 1u : 0u;
+  uint32_t tot;
+  uint32_t pos = block_excl_scan(cnt, s_w, &tot);
+  if (threadIdx.x == 0) s_base = tot > 0 ? atomicAdd(&st[0], tot) : 0u;
+  __syncthreads();
+  pos += s_base;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < top; i += stride) {
     if (i < A.n_nets) {
       const int n = (int)i;
@@ -345,7 +386,7 @@ __global__ void k_est_check(EstArgs A, int n_pins, int n_sinks, int32_t *mid, in
         big[atomicAdd(&st[1], 1u)] = n;
         atomicMax(&st[2], (uint32_t)(b - a));
       } else if (b - a + 1 > kLanePins) {
-        mid[atomicAdd(&st[0], 1u)] = n;
+        mid[pos++] = n;
       }
     }
     if (i < n_sinks) {
@@ -547,10 +588,22 @@ __global__ __launch_bounds__(1024) void k_estg_block(EstGradArgs G, const int32_
 // first sink whose node or corner parent is not a valid estimated-tree entry
 // (kNone when none), off[] gets each big net's accumulator offset and
 // *total their sum.  The net CSR and positions are checked by k_est_check.
-__global__ void k_estg_check(EstGradArgs G, int n_sinks, int32_t *mid, int32_t *big, int64_t *off,
-                             unsigned long long *total, uint32_t *st) {
+__global__ __launch_bounds__(256) void k_estg_check(EstGradArgs G, int n_sinks, int32_t *mid, int32_t *big,
+                                                    int64_t *off, unsigned long long *total, uint32_t *st) {
+  __shared__ uint32_t s_w[256 / kWave];
+  __shared__ uint32_t s_base;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t top = max((int64_t)G.n_nets, (int64_t)n_sinks);
+  uint32_t cnt = 0;  // mid nets of this thread, slots reserved per block as in k_est_check
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < G.n_nets; i += stride) {
+    const int k = G.sink_ptr[i + 1] - G.sink_ptr[i];
+    cnt += k + 1 <= kWave && k + 1 > kLanePins ? 1u : 0u;
+  }
+  uint32_t tot;
+  uint32_t pos = block_excl_scan(cnt, s_w, &tot);
+  if (threadIdx.x == 0) s_base = tot > 0 ? atomicAdd(&st[0], tot) : 0u;
+  __syncthreads();
+  pos += s_base;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < top; i += stride) {
     if (i < G.n_nets) {
       const int n = (int)i;
@@ -560,7 +613,7 @@ __global__ void k_estg_check(EstGradArgs G, int n_sinks, int32_t *mid, int32_t *
         big[b] = n;
         off[b] = (int64_t)atomicAdd(total, (unsigned long long)(k + 1));
       } else if (k + 1 > kLanePins) {
-        mid[atomicAdd(&st[0], 1u)] = n;
+        mid[pos++] = n;
       }
     }
   }
