@@ -44,6 +44,8 @@ class _ODesign(ctypes.Structure):
         ("dangling_policy", ctypes.c_int32),
         ("res64", _PD),
         ("delay64", _PD),
+        ("load64", _PD),
+        ("arcd64", _PD),
     ]
 
 
@@ -102,7 +104,7 @@ class _Keep:
         return _ptr(a, typ)
 
 
-def _odesign(d, keep: _Keep, wire_res=None, sink_delay=None) -> _ODesign:
+def _odesign(d, keep: _Keep, wire_res=None, sink_delay=None, load_delta=None, arc_delta=None) -> _ODesign:
     i32 = lambda a: keep(a, np.int32, _P32)  # noqa: E731
     f32 = lambda a: keep(a, np.float32, _PF)  # noqa: E731
     od = _ODesign()
@@ -128,6 +130,8 @@ def _odesign(d, keep: _Keep, wire_res=None, sink_delay=None) -> _ODesign:
     od.dangling_policy = int(d.dangling_policy)
     od.res64 = None if wire_res is None else keep(wire_res, np.float64, _PD)
     od.delay64 = None if sink_delay is None else keep(sink_delay, np.float64, _PD)
+    od.load64 = None if load_delta is None else keep(load_delta, np.float64, _PD)
+    od.arcd64 = None if arc_delta is None else keep(arc_delta, np.float64, _PD)
     return od
 
 
@@ -254,14 +258,17 @@ def _smooth_finish(r, o):
     return r
 
 
-def smooth_sta(d, gamma, wire_cap=None, wire_res=None):
+def smooth_sta(d, gamma, wire_cap=None, wire_res=None, load_delta=None, arc_delta=None):
     """Smooth forward: late AT merges by log-sum-exp (temperature gamma), smooth
     late endpoint slack, TNS_g and WNS_g.  wire_cap / wire_res (FP64, caller
-    node order) override the design's node caps / segment resistances."""
+    node order) override the design's node caps / segment resistances.
+    load_delta [n_nets] and arc_delta [n_arcs][4] (FP64) perturb the loads the
+    NLDM lookups see and the cell-arc delays, for difference checks of the
+    adjoint."""
     lib, keep = _load(), _Keep()
     lib.orc_smooth_sta.restype = ctypes.c_int
     lib.orc_smooth_sta.argtypes = [ctypes.POINTER(_ODesign), _PD, ctypes.c_double, ctypes.POINTER(_OSmooth)]
-    od = _odesign(d, keep, wire_res)
+    od = _odesign(d, keep, wire_res, load_delta=load_delta, arc_delta=arc_delta)
     r, o = _smooth_struct(d)
     wc = None if wire_cap is None else keep(wire_cap, np.float64, _PD)
     if lib.orc_smooth_sta(ctypes.byref(od), wc, float(gamma), ctypes.byref(o)):

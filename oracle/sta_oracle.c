@@ -50,6 +50,12 @@ typedef struct {
   int32_t dangling_policy; /* 1: cell outputs without fanout are endpoints */
   const double *res64;     /* FP64 segment resistances overriding res_kohm when non-NULL */
   const double *delay64;   /* per-sink net delays overriding the Elmore delay when non-NULL */
+  /* Perturbation inputs of the smooth forward, for finite-difference pins of
+   * its adjoint (NULL: none).  load64[n] is added to net n's load as the NLDM
+   * lookups of its driver see it (not to the RC moments); arcd64[k][v] is
+   * added to the delay of cell arc k (cell_in_pin order) in view v. */
+  const double *load64;
+  const double *arcd64;
 } orc_design;
 
 static double seg_res(const orc_design *D, int64_t k) {
@@ -508,7 +514,7 @@ static int smooth_forward(const orc_design *D, const roles_t *R, const int32_t *
       }
     } else {
       int32_t c = R->cell_of[p], type = D->cell_type[c], sense = D->sense[type];
-      double load = out->L_net[R->drv_net[p]];
+      double load = out->L_net[R->drv_net[p]] + (D->load64 ? D->load64[R->drv_net[p]] : 0.0);
       const float *xa = D->slew_axis + (size_t)type * D->nx, *ya = D->load_axis + (size_t)type * D->ny;
       for (int el = 0; el < 2; el++)
         for (int r_o = 0; r_o < 2; r_o++) {
@@ -526,6 +532,7 @@ static int smooth_forward(const orc_design *D, const roles_t *R, const int32_t *
               double dl = nldm_d(D->nx, D->ny, xa, ya, tab_of(D, type, r_o), x, load, NULL, NULL, &seg);
               double cs = nldm_d(D->nx, D->ny, xa, ya, tab_of(D, type, 2 + r_o), x, load, NULL, NULL, NULL);
               if (el) sig = mix(sig, (uint64_t)seg);
+              if (D->arcd64) dl += D->arcd64[(size_t)k * 4 + el * 2 + r_o];
               z[nz++] = at[in * 4 + el * 2 + r_i] + dl;
               if (el ? z[nz - 1] > hard : z[nz - 1] < hard) hard = z[nz - 1];
               if (el ? cs > best_sl : cs < best_sl) {

@@ -83,3 +83,30 @@ def random_tree(rng, n_nodes):
     """Random rooted tree with parent[k] < k."""
     parent = [-1] + [int(rng.integers(0, k)) for k in range(1, n_nodes)]
     return parent
+
+
+def tie_design():
+    """Exact ties for the critical-fanin rule: a negative-unate NAND2 whose two
+    inputs hang on identical branches of one net (equal arrivals and slews), a
+    non-unate cell fed by a primary input whose rise and fall arrive together
+    (rise and fall candidates equal), and a positive-unate AND3 whose inputs B
+    and C hang on identical branches of the NAND2's output net (they tie for
+    the latest arrival; input A, straight from a primary input, is earliest).
+
+    pins: 0 PI0, 1 PI1, 2-3 NAND.A/B, 4 NAND.Y, 5 X.A, 6 X.Y, 7-9 AND.A/B/C,
+    10 AND.Y, 11-12 POs."""
+    kinds = [PI, PI, CIN, CIN, COUT, CIN, COUT, CIN, CIN, CIN, COUT, PO, PO]
+    cells = [(0, [2, 3], 4), (1, [5], 6), (2, [7, 8, 9], 10)]
+    nets = [single_segment_net(0, [2, 3], 0.02, 1.5), single_segment_net(1, [5, 7], 0.01, 0.75),
+            single_segment_net(4, [8, 9], 0.03, 1.25), single_segment_net(6, [11], 0.02, 1.0),
+            single_segment_net(10, [12], 0.02, 1.0)]
+    tables = np.stack([
+        np.stack([planar_table(9.0, 0.10, 1.3), planar_table(7.0, 0.12, 1.1),
+                  planar_table(4.0, 0.05, 2.0), planar_table(3.5, 0.04, 1.9)]),
+        np.stack([planar_table(6.0, 0.09, 1.0), planar_table(5.0, 0.08, 1.2),
+                  planar_table(3.0, 0.04, 1.5), planar_table(2.5, 0.03, 1.6)]),
+        np.stack([planar_table(11.0, 0.14, 1.4), planar_table(10.0, 0.13, 1.5),
+                  planar_table(5.0, 0.06, 2.2), planar_table(4.5, 0.05, 2.1)]),
+    ])
+    return make_design(kinds, cells, nets, n_inputs=[2, 1, 3], sense=[1, 2, 0], pin_cap=[1.0, 1.25, 0.75],
+                       tables=tables, po_rat=60.0, rat_early=5.0)

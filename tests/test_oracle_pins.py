@@ -501,3 +501,24 @@ def test_wire_cap_override_matches_design_caps():
     r0 = oracle.sta(d)
     r1 = oracle.sta(d, wire_cap=d.cap_ff.astype(np.float64))
     np.testing.assert_array_equal(r0["at"], r1["at"])
+
+
+def test_critical_fanin_tie_rule():
+    """Exact ties go to the lowest fanin position, then to the rising input
+    transition (R17): NAND2 inputs on identical branches, a non-unate cell
+    whose rise and fall candidates coincide, and an AND3 whose B and C tie for
+    the latest arrival while A is the earliest."""
+    from designs import tie_design
+    d = tie_design()
+    r = oracle.sta(d)
+    at = r["at"]
+    np.testing.assert_array_equal(at[2], at[3])   # identical branches
+    np.testing.assert_array_equal(at[8], at[9])
+    assert at[5, 0] == at[5, 1] and at[5, 2] == at[5, 3]
+    for v in range(4):
+        ro = v % 2
+        assert r["crit"][4, v] == 0 * 2 + (1 - ro)    # NAND2: input A, opposite transition
+        assert r["crit"][6, v] == 0                  # non-unate: rise before fall
+    assert list(r["crit"][10, 2:]) == [2 * 1 + 0, 2 * 1 + 1]   # AND3 late: B (tie with C)
+    assert list(r["crit"][10, :2]) == [0, 1]                  # AND3 early: A
+    assert at[7, 2] < at[8, 2]
