@@ -126,7 +126,7 @@ typedef struct {
   int32_t mode;                /* 0 hard max/min; 1 smooth late arrival merges (differentiable) */
   float gamma_ps;              /* smoothing temperature of mode 1 (> 0), e.g. 5 ps */
   int32_t dangling_policy;     /* 0: zero-fanout cell outputs unconstrained; 1: endpoints */
-  int32_t sched;               /* sta_sched */
+  int32_t sched;               /* sta_sched; default STA_SCHED_PER_LEVEL */
   int32_t big_net_nodes;       /* nets with more RC nodes go to the wide RC kernel; 0 = 255 */
   int32_t sort_endpoints;      /* 1: sta_update_timing also orders endpoints by slack */
   int32_t profile;             /* 1: record per-kernel HIP event times in sta_update_timing */

@@ -196,7 +196,7 @@ void sta_options_default(sta_options *o) {
   o->mode = 0;
   o->gamma_ps = 5.0f;
   o->dangling_policy = 0;
-  o->sched = STA_SCHED_PERSISTENT;
+  o->sched = STA_SCHED_PER_LEVEL;
   o->big_net_nodes = 0;
   o->sort_endpoints = 1;
   o->profile = 0;

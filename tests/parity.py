@@ -167,9 +167,11 @@ def _view_scale(S):
     return np.repeat(S, 2, axis=1)
 
 
-def compare_full(d, r, gpu, *, check_order=True):
+def compare_full(d, r, gpu, *, check_order=True, scales=None):
     """Compares a full GPU run (dict from STA.timing/slack/levels/rc) with the
-    oracle result r on design d.  Returns a dict of statistics."""
+    oracle result r on design d.  Returns a dict of statistics.  scales: the
+    magnitude_scales(d, r) triple, when the caller compares several runs
+    against one oracle result."""
     stats = {}
     lv, lo = gpu["levels"]
     np.testing.assert_array_equal(lv, r["level"])
@@ -188,7 +190,7 @@ def compare_full(d, r, gpu, *, check_order=True):
     qerr = np.abs(q - r["q_sink"])
     assert (qerr <= qt).all(), f"sink spread outside tolerance at {np.argwhere(qerr > qt)[:5].ravel().tolist()}"
     t = gpu["timing"]
-    U, M, S = magnitude_scales(d, r)
+    U, M, S = magnitude_scales(d, r) if scales is None else scales
     Uv, Mv = _view_scale(U), _view_scale(M)
     stats["at"] = check_close("AT", t["at"], r["at"], Uv)
     stats["slew"] = check_close("slew", t["slew"], r["slew"], _view_scale(S))
@@ -211,6 +213,22 @@ def compare_full(d, r, gpu, *, check_order=True):
         stats["order_ties"] = order_check(r["ep_pin"], r["ep_slack"], s["ep_slack"], r["ep_order"],
                                           s["ep_order"], ep_scale)
     return stats
+
+
+def assert_bitwise_equal(a, b, where=""):
+    """Two run_gpu dicts hold bit-identical results (levels, RC, timing,
+    critical fanins, slacks, WNS/TNS and endpoint order)."""
+    for x, y, k in zip(a["levels"], b["levels"], ("level", "level_order")):
+        assert np.array_equal(x, y), (where, k)
+    for x, y, k in zip(a["rc"], b["rc"], ("L_net", "d", "q")):
+        assert np.array_equal(x.view(np.uint32), y.view(np.uint32)), (where, k)
+    for k, v in a["timing"].items():
+        w = b["timing"][k]
+        assert v.dtype == w.dtype and np.array_equal(v.view(np.uint8), w.view(np.uint8)), (where, k)
+    for k in ("slack", "ep_slack", "ep_order", "wns", "tns"):
+        v, w = np.asarray(a["slack"][k]), np.asarray(b["slack"][k])
+        assert v.dtype == w.dtype and np.array_equal(v.view(np.uint8), w.view(np.uint8)), (where, k)
+    assert np.array_equal(a["ep_pin"], b["ep_pin"]), (where, "ep_pin")
 
 
 def run_gpu(sta_obj):

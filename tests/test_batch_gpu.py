@@ -129,3 +129,42 @@ def test_batch_autotune_and_wire_caps():
         r = s.slack()
         s.close()
         assert np.array_equal(wns[i], r["wns"]) and np.array_equal(tns[i], r["tns"]), (i, wns[i], r["wns"])
+
+
+# The benchmark's batch: 256 uneven designs (1k-200k cells, 10-80 levels,
+# 29M pins in all), run once as a union in the graph schedule the benchmark's
+# autotuner picks and once per level; every design's slice is then compared
+# bit for bit with the design timed alone and element by element with the
+# FP64 oracle, in groups of 32 designs per test.
+_BENCH_BATCH = {}
+_GROUPS = 8
+
+
+def _bench_batch():
+    if not _BENCH_BATCH:
+        designs = [synth.generate(c) for c in synth.batch_configs(256)]
+        parts, offs = _run_batch(designs, sched=STA_SCHED_GRAPH)
+        parts_pl, _ = _run_batch(designs, sched=STA_SCHED_PER_LEVEL)
+        for i in range(len(designs)):
+            _assert_same(parts[i], parts_pl[i], f"design {i}: graph vs per-level batch")
+        _BENCH_BATCH.update(designs=designs, parts=parts)
+    return _BENCH_BATCH
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("group", range(_GROUPS))
+def test_bench_batch_256(group):
+    b = _bench_batch()
+    designs, parts = b["designs"], b["parts"]
+    per = len(designs) // _GROUPS
+    for i in range(group * per, (group + 1) * per):
+        d = designs[i]
+        s = STA(d, sched=STA_SCHED_GRAPH)
+        s.update()
+        g = run_gpu(s)
+        s.close()
+        g["slack"]["wns"] = np.asarray(g["slack"]["wns"])
+        g["slack"]["tns"] = np.asarray(g["slack"]["tns"])
+        _assert_same(parts[i], g, f"design {i}")
+        compare_full(d, oracle.sta(d), parts[i])
+    print(f"[batch] designs {group * per}..{(group + 1) * per - 1} of the 256-design batch ok", flush=True)

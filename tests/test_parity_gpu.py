@@ -8,7 +8,7 @@ import oracle
 from designs import CIN, COUT, PI, PO, make_design, planar_table, single_segment_net
 from paper_2511_11660_amd import synth
 from paper_2511_11660_amd.sta import STA, STA_SCHED_GRAPH, STA_SCHED_PER_LEVEL, STA_SCHED_PERSISTENT
-from parity import compare_full, run_gpu
+from parity import assert_bitwise_equal, compare_full, magnitude_scales, run_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -68,11 +68,28 @@ def test_mid(sched):
     compare_full(d, r, _run(d, sched=sched))
 
 
-def test_1m_pins():
-    d = synth.generate(synth.mid_config())
+SCHEDS = (STA_SCHED_PERSISTENT, STA_SCHED_PER_LEVEL, STA_SCHED_GRAPH)
+
+
+def _all_schedules(d):
+    """Every schedule on one design: each against the FP64 oracle element by
+    element, and all of them bit-identical to each other (same per-pin
+    arithmetic in every schedule)."""
     r = oracle.sta(d)
-    stats = compare_full(d, r, _run(d))
-    print(stats)
+    scales = magnitude_scales(d, r)
+    first = None
+    for sched in SCHEDS:
+        g = _run(d, sched=sched)
+        print(f"[parity] sched={sched}", compare_full(d, r, g, scales=scales), flush=True)
+        if first is None:
+            first = g
+        else:
+            assert_bitwise_equal(first, g, f"schedule {sched} vs {SCHEDS[0]}")
+
+
+@pytest.mark.slow
+def test_1m_pins_every_schedule():
+    _all_schedules(synth.generate(synth.mid_config()))
 
 
 def test_determinism_and_repeat():
@@ -139,12 +156,10 @@ def test_single_cell_and_pi_to_po():
 
 
 @pytest.mark.slow
-def test_10m_pins_full():
-    """The benchmark's 10M-pin design at full size, persistent schedule."""
-    d = synth.generate(synth.large_config())
-    r = oracle.sta(d)
-    stats = compare_full(d, r, _run(d))
-    print(stats)
+def test_10m_pins_every_schedule():
+    """The benchmark's 10M-pin design at full size in every schedule, the
+    benchmark's own (per level, or its graph) included."""
+    _all_schedules(synth.generate(synth.large_config()))
 
 
 def _wide_cell_design(seed=11):
