@@ -405,6 +405,24 @@ sta_status sta_estimate_rc(const sta_graph_desc *g, const float *pin_x, const fl
                            const sta_wire_params *w, int64_t *net_node_ptr, int32_t *parent, float *res_kohm,
                            float *cap_ff, int32_t *sink_node, sta_mem mem, void *stream);
 
+/* sta_estimate_rc for callers that cannot allocate device memory (code
+ * under HIP graph capture nearby, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same trees, same outputs, bit for bit, and the same errors;
+ * but every array (the net CSR per g->mem, which must be STA_DEVICE,
+ * positions and outputs) is in device memory, and the call allocates
+ * nothing: its check words and its lists of nets of 9-64 pins and of more
+ * than 64 pins live in a fixed scratch array of the library (about 4.2 MiB
+ * per device, held until the process ends).  Those lists take at most
+ * 1,048,576 and 65,536 nets; a netlist with more gives STA_E_UNSUPPORTED
+ * before any tree is built.  Every call on one device shares that device's
+ * scratch, so calls that overlap on one device (other host threads, other
+ * streams) race and give undefined results; the call synchronizes `stream`
+ * twice (after the check and at the end), so calls from one thread do not
+ * overlap. */
+sta_status sta_estimate_rc_noalloc(const sta_graph_desc *g, const float *pin_x, const float *pin_y,
+                                   const sta_wire_params *w, int64_t *net_node_ptr, int32_t *parent,
+                                   float *res_kohm, float *cap_ff, int32_t *sink_node, void *stream);
+
 /* Gradient to pin positions through estimated RC trees (the placement side
  * of §III "Parasitics (RC) inputs": with the trees of sta_estimate_rc held
  * fixed, each L-shaped edge from parent pin p to pin c sets R and C of its

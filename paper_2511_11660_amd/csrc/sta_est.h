@@ -21,9 +21,19 @@ struct EstArgs {
 };
 // st[6] (caller-initialized to {0, 0, 0, ~0, ~0, ~0}): nets of 9..64 pins,
 // nets above 64 pins, their largest sink count, first bad net, first bad sink
-// entry, first pin position not finite or beyond 1e18 in magnitude
+// entry, first pin position not finite or beyond 1e18 in magnitude.  The mid
+// and big lists receive at most mid_cap and big_cap entries (the counts go on
+// counting); by default they are as long as there are nets.
 hipError_t launch_est_check(const EstArgs &A, int n_pins, int n_sinks, int32_t *mid, int32_t *big, uint32_t *st,
-                            hipStream_t s);
+                            hipStream_t s, uint32_t mid_cap = UINT32_MAX, uint32_t big_cap = UINT32_MAX);
+
+// Scratch of the allocation-free entry point: 256 bytes of check words, then
+// kEstNoallocMid mid-list entries, then kEstNoallocBig big-list entries.
+constexpr uint32_t kEstNoallocMid = 1u << 20, kEstNoallocBig = 1u << 16;
+constexpr size_t kEstScratchBytes = 256 + 4 * ((size_t)kEstNoallocMid + kEstNoallocBig);
+// Device address of that scratch on `device`, which must be the current
+// device; looked up once per device and kept.
+hipError_t est_noalloc_scratch(int device, unsigned char **ptr);
 // n_mid = st[0], n_big = st[1] as read back by the host; the kernels read
 // the counts from st as well
 hipError_t launch_est(const EstArgs &A, const int32_t *mid, const int32_t *big, const uint32_t *st, uint32_t n_mid,

@@ -1696,6 +1696,75 @@ extern "C" sta_status sta_estimate_rc(const sta_graph_desc *g, const float *pin_
   return STA_OK;
 }
 
+// The same trees with no allocation (see sta.h): every array in device memory,
+// the check words and net lists in the library's fixed device scratch.
+extern "C" sta_status sta_estimate_rc_noalloc(const sta_graph_desc *g, const float *pin_x, const float *pin_y,
+                                              const sta_wire_params *w, int64_t *net_node_ptr, int32_t *parent,
+                                              float *res_kohm, float *cap_ff, int32_t *sink_node, void *stream) {
+  if (!g || !w) return fail(STA_E_ARG, "NULL graph or wire parameters");
+  if (g->mem != STA_DEVICE) return fail(STA_E_ARG, "the allocation-free estimator takes the net CSR in device memory");
+  if (g->n_nets < 0 || g->n_pins < 0) return fail(STA_E_ARG, "negative sizes");
+  for (float v : {w->r_x, w->r_y, w->c_x, w->c_y})
+    if (!std::isfinite(v) || v < 0.0f) return fail(STA_E_ARG, "wire parameters must be finite and >= 0");
+  const int NN = g->n_nets, NP = g->n_pins;
+  if (!net_node_ptr || !g->net_sink_ptr || (NN > 0 && !g->net_driver) || (NP > 0 && (!pin_x || !pin_y)))
+    return fail(STA_E_ARG, "NULL array");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  unsigned char *scr = nullptr;
+  HIP_TRY(est_noalloc_scratch(dev, &scr));
+  int32_t n_sinks = 0;
+  HIP_TRY(hipMemcpyAsync(&n_sinks, g->net_sink_ptr + NN, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (n_sinks < 0) return fail(STA_E_ARG, "net_sink_ptr[n_nets] < 0");
+  if (n_sinks > 0 && !g->net_sink_pin) return fail(STA_E_ARG, "NULL net_sink_pin");
+  const int64_t n_nodes = (int64_t)NN + 2 * (int64_t)n_sinks;
+  if (n_nodes > 0 && (!parent || !res_kohm || !cap_ff)) return fail(STA_E_ARG, "NULL RC output array");
+  if (n_sinks > 0 && !sink_node) return fail(STA_E_ARG, "NULL sink_node");
+  EstArgs A{};
+  A.n_nets = NN;
+  A.rx = w->r_x;
+  A.ry = w->r_y;
+  A.cx = w->c_x;
+  A.cy = w->c_y;
+  A.driver = g->net_driver;
+  A.sink_ptr = g->net_sink_ptr;
+  A.sink_pin = g->net_sink_pin;
+  A.x = pin_x;
+  A.y = pin_y;
+  A.node_ptr = net_node_ptr;
+  A.parent = parent;
+  A.res = res_kohm;
+  A.cap = cap_ff;
+  A.sink_node = sink_node;
+  uint32_t *st = reinterpret_cast<uint32_t *>(scr);
+  int32_t *mid = reinterpret_cast<int32_t *>(scr + 256);
+  int32_t *big = mid + kEstNoallocMid;
+  const uint32_t st0[6] = {0u, 0u, 0u, ~0u, ~0u, ~0u};  // the last call's words are overwritten
+  HIP_TRY(hipMemcpyAsync(st, st0, sizeof st0, hipMemcpyHostToDevice, s));
+  HIP_TRY(launch_est_check(A, NP, n_sinks, mid, big, st, s, kEstNoallocMid, kEstNoallocBig));
+  uint32_t h[6];
+  HIP_TRY(hipMemcpyAsync(h, st, sizeof h, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (h[3] != ~0u) return fail(STA_E_ARG, "net %u: bad net_sink_ptr or net_driver", h[3]);
+  if (h[4] != ~0u) return fail(STA_E_ARG, "net_sink_pin[%u] out of range", h[4]);
+  if (h[5] != ~0u) return fail(STA_E_ARG, "pin %u: position not finite or beyond 1e18 in magnitude", h[5]);
+  if (h[1] > 0 && (int64_t)h[2] + 1 > kEstMaxPins)
+    return fail(STA_E_UNSUPPORTED, "a net has %u sinks (at most %d)", h[2], kEstMaxPins - 1);
+  if (h[0] > kEstNoallocMid || h[1] > kEstNoallocBig)
+    return fail(STA_E_UNSUPPORTED,
+                "%u nets of 9-64 pins and %u of more than 64 pins exceed the fixed scratch (at most %u and %u)", h[0],
+                h[1], kEstNoallocMid, kEstNoallocBig);
+  if (NN == 0) {
+    const int64_t zero = 0;
+    HIP_TRY(hipMemcpyAsync(A.node_ptr, &zero, sizeof zero, hipMemcpyHostToDevice, s));
+  }
+  HIP_TRY(launch_est(A, mid, big, st, h[0], h[1], s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return STA_OK;
+}
+
 // Gradient to pin positions through estimated trees (no context; see sta.h).
 extern "C" sta_status sta_estimate_rc_backward(const sta_graph_desc *g, const float *pin_x, const float *pin_y,
                                                const sta_wire_params *w, const int32_t *parent,

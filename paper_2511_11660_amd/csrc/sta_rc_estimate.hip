@@ -31,6 +31,8 @@
 // node of the tree pin that gives that distance, so the joining pin's owner
 // writes both of its RC nodes without asking anyone.
 #include <algorithm>
+#include <mutex>
+#include <vector>
 
 #include "sta_est.h"
 #include "sta_internal.h"
@@ -361,8 +363,10 @@ __device__ __forceinline__ bool est_mid_net(const EstArgs &A, int n, int n_pins,
 // The mid list is filled without one atomic per net on a single counter (tens
 // of thousands of those serialized at one L2 address): each block counts its
 // mid nets first, reserves their slots with one atomic, then writes them.
+// The lists hold at most mid_cap and big_cap entries; the counts in st[0] and
+// st[1] keep counting past them, so the host sees when a list was too short.
 __global__ __launch_bounds__(256) void k_est_check(EstArgs A, int n_pins, int n_sinks, int32_t *mid, int32_t *big,
-                                                   uint32_t *st) {
+                                                   uint32_t *st, uint32_t mid_cap, uint32_t big_cap) {
   __shared__ uint32_t s_w[256 / kWave];
   __shared__ uint32_t s_base;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -383,10 +387,12 @@ __global__ __launch_bounds__(256) void k_est_check(EstArgs A, int n_pins, int n_
       if (!ok) {
         atomicMin(&st[3], (uint32_t)n);
       } else if (b - a + 1 > kWave) {
-        big[atomicAdd(&st[1], 1u)] = n;
+        const uint32_t k = atomicAdd(&st[1], 1u);
+        if (k < big_cap) big[k] = n;
         atomicMax(&st[2], (uint32_t)(b - a));
       } else if (b - a + 1 > kLanePins) {
-        mid[pos++] = n;
+        if (pos < mid_cap) mid[pos] = n;
+        ++pos;
       }
     }
     if (i < n_sinks) {
@@ -653,12 +659,39 @@ inline int blocks_of(int64_t n, int b) { return (int)((n + b - 1) / b); }
 }  // namespace
 
 hipError_t launch_est_check(const EstArgs &A, int n_pins, int n_sinks, int32_t *mid, int32_t *big, uint32_t *st,
-                            hipStream_t s) {
+                            hipStream_t s, uint32_t mid_cap, uint32_t big_cap) {
   const int64_t top = std::max<int64_t>(std::max(A.n_nets, n_sinks), n_pins);
   if (top <= 0) return hipSuccess;
   const int grid = (int)std::min<int64_t>((top + 255) / 256, 8192);
-  hipLaunchKernelGGL(k_est_check, dim3(grid), dim3(256), 0, s, A, n_pins, n_sinks, mid, big, st);
+  const uint32_t all = (uint32_t)std::max(A.n_nets, 0);
+  hipLaunchKernelGGL(k_est_check, dim3(grid), dim3(256), 0, s, A, n_pins, n_sinks, mid, big, st,
+                     std::min(mid_cap, all), std::min(big_cap, all));
   return hipGetLastError();
+}
+
+// Fixed device scratch of sta_estimate_rc_noalloc: the six check words, then
+// the two net lists.  Each device the library runs on holds its own copy (its
+// address is looked up per device, below) until the process ends.
+static __device__ __align__(256) unsigned char scratch[kEstScratchBytes];
+
+hipError_t est_noalloc_scratch(int device, unsigned char **ptr) {
+  static std::mutex mu;
+  static std::vector<unsigned char *> addr;  // per device, filled on first use
+  std::lock_guard<std::mutex> lock(mu);
+  if (device < 0) return hipErrorInvalidDevice;
+  if ((size_t)device >= addr.size()) addr.resize((size_t)device + 1, nullptr);
+  if (!addr[(size_t)device]) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device) return hipErrorInvalidDevice;  // the caller makes the device current
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[(size_t)device] = static_cast<unsigned char *>(p);
+  }
+  *ptr = addr[(size_t)device];
+  return hipSuccess;
 }
 
 hipError_t launch_est(const EstArgs &A, const int32_t *mid, const int32_t *big, const uint32_t *st, uint32_t n_mid,

@@ -116,6 +116,8 @@ _SIGS = [
                                         ctypes.c_int, _VP]),
     ("sta_estimate_rc", ctypes.c_int, [ctypes.POINTER(sta_graph_desc), _VP, _VP, ctypes.POINTER(sta_wire_params),
                                        _VP, _VP, _VP, _VP, _VP, ctypes.c_int, _VP]),
+    ("sta_estimate_rc_noalloc", ctypes.c_int, [ctypes.POINTER(sta_graph_desc), _VP, _VP,
+                                               ctypes.POINTER(sta_wire_params), _VP, _VP, _VP, _VP, _VP, _VP]),
     ("sta_estimate_rc_backward", ctypes.c_int, [ctypes.POINTER(sta_graph_desc), _VP, _VP,
                                                 ctypes.POINTER(sta_wire_params), _VP, _VP, _VP, _VP, _VP, _VP,
                                                 ctypes.c_int, _VP]),
@@ -356,6 +358,13 @@ def sta_estimate_rc(graph: sta_graph_desc, pin_x, pin_y, wire: sta_wire_params, 
     _check(load().sta_estimate_rc(ctypes.byref(graph), _addr(pin_x), _addr(pin_y), ctypes.byref(wire),
                                   _addr(net_node_ptr), _addr(parent), _addr(res_kohm), _addr(cap_ff),
                                   _addr(sink_node), mem, _stream(stream)))
+
+
+def sta_estimate_rc_noalloc(graph: sta_graph_desc, pin_x, pin_y, wire: sta_wire_params, net_node_ptr, parent,
+                            res_kohm, cap_ff, sink_node, stream=None) -> None:
+    _check(load().sta_estimate_rc_noalloc(ctypes.byref(graph), _addr(pin_x), _addr(pin_y), ctypes.byref(wire),
+                                          _addr(net_node_ptr), _addr(parent), _addr(res_kohm), _addr(cap_ff),
+                                          _addr(sink_node), _stream(stream)))
 
 
 def estimate_rc(d, pin_x, pin_y, r_x, r_y, c_x, c_y, stream=None) -> dict:

@@ -178,6 +178,21 @@ def test_estimate_rc_host_checks():
         assert e.value.status == S.STA_E_DEVICE
 
 
+def test_estimate_rc_noalloc_host_checks():
+    """The allocation-free estimator takes device memory only and checks its
+    arguments before any device call."""
+    w = S.sta_wire_params(0.001, 0.001, 0.1, 0.1)
+    g = S.sta_graph_desc()
+    g.n_nets, g.n_pins, g.mem = 1, 1, S.STA_HOST
+    assert S.load().sta_estimate_rc_noalloc(ctypes.byref(g), None, None, ctypes.byref(w), None, None, None, None,
+                                            None, None) == S.STA_E_ARG
+    assert b"device memory" in S.load().sta_last_error()
+    g.mem = S.STA_DEVICE
+    bad = S.sta_wire_params(0.001, -1.0, 0.1, 0.1)
+    assert S.load().sta_estimate_rc_noalloc(ctypes.byref(g), None, None, ctypes.byref(bad), None, None, None, None,
+                                            None, None) == S.STA_E_ARG
+
+
 def _batch(designs, **opts):
     keep = []
     descs = [S.descriptors(d, keep) for d in designs]
