@@ -64,19 +64,37 @@ def measured_traffic(sweep: str, workload: str):
     return t.get("bytes_per_update")
 
 
+def host_cpu() -> dict:
+    """CPU model and the hardware threads this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 0
+    return {"cpu_model": model, "host_threads": n}
+
+
 def cpu_baseline(design, n_pins: int, runs: int = 3) -> dict:
     """The FP64 oracle (plain C, one thread) on the whole design, median of
-    `runs` full updates."""
+    `runs` updates.  Each is timed inside the oracle around what one
+    sta_update_timing does (RC, forward, backward, slacks, WNS/TNS, endpoint
+    order); the levelization and pin-role maps, which the GPU path builds once
+    at create, and the Python-side array copies are outside the timed part."""
     import oracle
-    ts = []
-    for _ in range(runs):
-        t0 = time.perf_counter()
-        oracle.sta(design)
-        ts.append(time.perf_counter() - t0)
+    ts = [oracle.sta(design)["update_seconds"] for _ in range(runs)]
     dt = sorted(ts)[len(ts) // 2]
     return {"value": n_pins / dt, "unit": "pins/s", "cores": 1, "kind": "oracle",
-            "sample": f"{runs} full FP64 updates of the same design ({n_pins} pins), single thread, "
-                      f"median {dt:.2f} s"}
+            "sample": f"{runs} FP64 updates of the same design ({n_pins} pins), RC through endpoint order "
+                      f"timed inside the oracle, single thread, median {dt:.2f} s",
+            **host_cpu()}
 
 
 def _time_updates(ctxs, stream, steps):
@@ -265,6 +283,47 @@ def reduced_order_side(design, sched: int, blocks: int, steps: int, full_ms: flo
             "elmore_ms": full_ms, "pins_per_s": design.n_pins / (ms * 1e-3)}
 
 
+def paths_side(design, sched: int, blocks: int, reps: int = 5) -> dict:
+    """sta_report_paths after one full update of the same design: the k worst
+    late paths (at most per_endpoint per endpoint) into device arrays, median
+    of `reps` calls timed with events around the call (its host waits
+    included)."""
+    import ctypes
+
+    import torch
+    from paper_2511_11660_amd.sta import STA, STA_DEVICE, load, sta_path_query
+    s = STA(design, sched=sched, sweep_blocks=blocks, device=0)
+    stream = torch.cuda.current_stream()
+    s.update(stream)
+    k, per_ep = 10000, 4
+    lmax = s.info.n_levels
+    dev = dict(device="cuda")
+    ptr = torch.empty(k + 1, dtype=torch.int32, **dev)
+    pins = torch.empty(k * lmax, dtype=torch.int32, **dev)
+    rf = torch.empty(k * lmax, dtype=torch.int8, **dev)
+    slack = torch.empty(k, dtype=torch.float32, **dev)
+    ep = torch.empty(k, dtype=torch.int32, **dev)
+    q = sta_path_query(k, per_ep, float("inf"), 1)
+    n = ctypes.c_int32(0)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ts = []
+    for _ in range(reps + 1):
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        rc = load().sta_report_paths(s.ctx, ctypes.byref(q), ctypes.byref(n), ptr.data_ptr(), pins.data_ptr(),
+                                     rf.data_ptr(), slack.data_ptr(), ep.data_ptr(), STA_DEVICE, stream.cuda_stream)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        if rc != 0:
+            raise RuntimeError(f"sta_report_paths failed: {rc}")
+        ts.append(ev0.elapsed_time(ev1))
+    n_pin_total = int(ptr[n.value].item()) if n.value > 0 else 0
+    s.close()
+    ms = sorted(ts[1:])[reps // 2]
+    return {"workload": "10M-pin design after a full update, worst late paths", "k": k, "per_endpoint": per_ep,
+            "paths": n.value, "path_pins": n_pin_total, "ms": ms, "paths_per_s": n.value / (ms * 1e-3)}
+
+
 _SCHED_NAMES = {0: "persistent", 1: "per-level", 2: "graph"}
 
 
@@ -295,9 +354,11 @@ def main() -> int:
     ap.add_argument("--workload", default="10M", choices=["10M", "1M", "tiny"])
     ap.add_argument("--sched", default="auto",
                     help="auto (tuned at setup), 0 persistent, 1 one launch per level, 2 HIP graph")
+    ap.add_argument("--overlap", type=int, default=1, choices=[0, 1],
+                    help="with --sched 1 or 2: side-stream phases on (1) or off (0); auto tunes it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-side", action="store_true", help="skip every side measurement")
-    ap.add_argument("--side", default="incremental,rc_estimate,reduced_order,adjoint,batched",
+    ap.add_argument("--side", default="incremental,rc_estimate,reduced_order,adjoint,batched,paths",
                     help="comma list of side measurements to run")
     ap.add_argument("--batch-designs", type=int, default=256)
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
@@ -323,7 +384,7 @@ def main() -> int:
     t_gen = time.perf_counter() - t0
     print(f"[bench] generated {design.n_pins} pins in {t_gen:.1f}s", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    s = STA(design, sched=0 if args.sched == "auto" else int(args.sched), device=0)
+    s = STA(design, sched=0 if args.sched == "auto" else int(args.sched), overlap=args.overlap, device=0)
     t_create = time.perf_counter() - t0
     info = s.info
     print(f"[bench] created context in {t_create:.1f}s: {info.n_cell_levels} cell levels, "
@@ -332,7 +393,7 @@ def main() -> int:
     tuned = None
     if args.sched == "auto":
         tuned = s.autotune(reps=5, stream=stream)
-        print(f"[bench] autotune: {_SCHED_NAMES[tuned.sched]} grid {tuned.sweep_blocks} "
+        print(f"[bench] autotune: {_SCHED_NAMES[tuned.sched]} grid {tuned.sweep_blocks} overlap {tuned.overlap} "
               f"({tuned.ms:.3f} ms, {tuned.n_tried} candidates)", file=sys.stderr, flush=True)
     sched, s_blocks = s.opts.sched, s.opts.sweep_blocks
     for _ in range(args.warmup):
@@ -365,6 +426,13 @@ def main() -> int:
     phase /= args.steps
     prof.close()
 
+    # the second denominator: a plain vector copy kernel of the library, 1 GiB
+    from paper_2511_11660_amd.sta import sta_measure_copy
+    cbuf = torch.empty(2 << 30, dtype=torch.uint8, device="cuda")
+    copy_ms = sta_measure_copy(cbuf[: 1 << 30], cbuf[1 << 30:], 1 << 30, 10, stream)
+    copy_gbps = 2 * (1 << 30) / (copy_ms * 1e-3) / 1e9
+    del cbuf
+
     n_arcs = int(design.cell_in_ptr[-1])
     ab = algorithmic_bytes(info, n_arcs)
     kern = {"forward": phase[PHASES.index("forward")], "backward": phase[PHASES.index("backward")],
@@ -388,12 +456,13 @@ def main() -> int:
         "config": {"workload": f"{args.workload}-pin synthetic STA design", "pins": info.n_pins,
                    "cells": info.n_cells, "nets": info.n_nets, "rc_nodes": int(info.n_nodes),
                    "cell_levels": info.n_cell_levels, "endpoints": info.n_endpoints,
-                   "views": 4, "schedule": _SCHED_NAMES[sched]},
+                   "views": 4, "schedule": _SCHED_NAMES[sched], "overlap": int(s.opts.overlap)},
         "hbm_frac_whole_update": ab["total"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "phase_ms": {k: float(v) for k, v in zip(PHASES, phase)},
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "algorithmic_bytes": ab[dom]},
+                     "traffic": traffic, "algorithmic_bytes": ab[dom],
+                     "copy_GBps": copy_gbps, "frac_of_copy": achieved / copy_gbps},
         "wns_ps": [float(x) for x in wns_tns["wns"]],
         "tns_ps": [float(x) for x in wns_tns["tns"]],
     }
@@ -410,6 +479,9 @@ def main() -> int:
     if "adjoint" in side:
         print("[bench] adjoint ratio (1M-pin smooth)", file=sys.stderr, flush=True)
         out["adjoint"] = adjoint_ratio(args.steps)
+    if "paths" in side:
+        print("[bench] top-k path report", file=sys.stderr, flush=True)
+        out["paths"] = paths_side(design, sched, s_blocks)
     if "batched" in side:
         print("[bench] batched vs per-design", file=sys.stderr, flush=True)
         out["batched"] = batched_vs_per_design(args.steps, args.batch_designs)

@@ -137,6 +137,10 @@ typedef struct {
                                   "Delay models": Arnoldi iterations, here two steps in the G inner
                                   product from the Elmore vector; the 50% time of the projected step
                                   response; hard mode only) */
+  int32_t overlap;             /* per-level and graph schedules: 1 (default) runs the RC pass in level
+                                  groups beside the forward sweep and WNS/TNS with the endpoint order
+                                  beside the backward sweep, on the context's own side streams; 0 runs
+                                  every phase in order on the caller's stream.  Results are identical */
 } sta_options;
 
 typedef struct {
@@ -328,6 +332,7 @@ typedef struct {
   int32_t sweep_blocks;        /* persistent grid (blocks of 256 threads) */
   float ms;                    /* mean update time of the choice */
   int32_t n_tried;             /* candidates timed */
+  int32_t overlap;             /* sta_options.overlap chosen */
 } sta_tune_result;
 sta_status sta_autotune(sta_ctx *ctx, int32_t reps, sta_tune_result *best, void *stream);
 
@@ -404,6 +409,14 @@ typedef struct {
 sta_status sta_estimate_rc(const sta_graph_desc *g, const float *pin_x, const float *pin_y,
                            const sta_wire_params *w, int64_t *net_node_ptr, int32_t *parent, float *res_kohm,
                            float *cap_ff, int32_t *sink_node, sta_mem mem, void *stream);
+
+/* Measurement helper: the achievable HBM bandwidth beside the published peak.
+ * Copies `bytes` (a positive multiple of 16) from src to dst, both
+ * caller-owned device buffers that should not overlap, with a plain
+ * vector-load / vector-store kernel, once to warm up and then `reps` times
+ * on `stream`, and writes the mean time of one copy (ms, HIP events) to *ms;
+ * a copy moves 2 * bytes.  Synchronizes `stream`. */
+sta_status sta_measure_copy(const void *src, void *dst, int64_t bytes, int32_t reps, void *stream, float *ms);
 
 /* sta_estimate_rc for callers that cannot allocate device memory (code
  * under HIP graph capture nearby, tight serving loops, harnesses that forbid

@@ -61,6 +61,7 @@ class _OResult(ctypes.Structure):
         ("ep_order", _P32),
         ("wns", ctypes.c_double * 2), ("tns", ctypes.c_double * 2),
         ("n_ep", ctypes.c_int32), ("n_levels", ctypes.c_int32),
+        ("update_s", ctypes.c_double),
     ]
 
 
@@ -223,6 +224,7 @@ def sta(d, wire_cap=None, sink_delay=None):
     r["q_sink"] = r["q_sink"][:d.n_sinks]
     r["wns"] = np.array([res.wns[0], res.wns[1]])
     r["tns"] = np.array([res.tns[0], res.tns[1]])
+    r["update_seconds"] = res.update_s  # RC through endpoint order, without levels and pin roles
     return r
 
 

@@ -114,6 +114,14 @@ struct sta_ctx {
   WideNets wide{};
   hipStream_t side = nullptr;          // wide-net RC kernels run here, overlapping the small nets
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipStream_t side2 = nullptr;         // RC groups beside the forward sweep; WNS/TNS and the
+  hipEvent_t ev_fwd = nullptr, ev_red = nullptr;  // endpoint order beside the backward sweep
+  // RC pass in groups of levels: group g serves levels [rc_grp_lvl[g],
+  // rc_grp_lvl[g+1]) and ends at RC chunk rc_grp_end[g]; wide nets are first
+  // needed at level wide_lvl
+  std::vector<int32_t> rc_grp_lvl, rc_grp_end;
+  std::vector<hipEvent_t> ev_rc;
+  int wide_lvl = INT32_MAX;
   float *big_pc = nullptr;
   double *big_scratch = nullptr;
   int32_t *arc_src = nullptr;
@@ -124,12 +132,14 @@ struct sta_ctx {
   void *sort_temp = nullptr;
   size_t sort_bytes = 0;
   std::vector<int4> ph_fwd, ph_bwd, ph_adj;  // sweep phases (kind, first item, count, level)
-  std::vector<int2> lvl_reg;           // per level: first slot, end of the slots in regular chunks
+  std::vector<int4> lvl_reg;           // per level: first slot, end of the slots in regular chunks,
+                                       // float4 granules of the largest type span of a block
   int n_pieces = 0;
   hipEvent_t ev[10]{};  // 0..6 update phases, 7..9 adjoint phases
   hipStream_t cap_stream = nullptr;   // graph schedule: capture stream
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
+  int graph_overlap = -1;             // sta_options.overlap the graph was captured with
   bool bwd_timed = false;
   bool events = false, timed = false;
   hipStream_t last_stream = nullptr;
@@ -182,6 +192,10 @@ struct sta_ctx {
     if (side) (void)hipStreamDestroy(side);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
+    if (side2) (void)hipStreamDestroy(side2);
+    if (ev_fwd) (void)hipEventDestroy(ev_fwd);
+    if (ev_red) (void)hipEventDestroy(ev_red);
+    for (auto &e : ev_rc) (void)hipEventDestroy(e);
     if (inc_ev) (void)hipEventDestroy(inc_ev);
     if (inc_host) (void)hipHostFree(inc_host);
     if (inc_stop) (void)hipHostFree(inc_stop);
@@ -203,6 +217,7 @@ void sta_options_default(sta_options *o) {
   o->device = -1;
   o->sweep_blocks = 0;
   o->delay_model = 0;
+  o->overlap = 1;
 }
 
 const char *sta_status_string(sta_status s) {
@@ -512,7 +527,11 @@ static sta_status build_layout(sta_ctx *C, const Inputs &I, const std::vector<in
   int big_thr = C->opt.big_net_nodes > 0 ? C->opt.big_net_nodes : kSmallNetMaxNodes;
   if (big_thr > kSmallNetMaxNodes) big_thr = kSmallNetMaxNodes;
 
-  // driver slots: PIs by pin id, then cells by (level, output pin id)
+  // driver slots: PIs by pin id, then cells by (level, type, RC node count of
+  // the output net, output pin id): a level's chunks then hold one or two
+  // cell types each, so a level kernel stages only those types' tables, and
+  // consecutive nets have near-equal RC trees, so the RC kernel can take nets
+  // in slot order (its outputs fill contiguous ranges) with balanced lanes
   std::vector<int32_t> drv_pin;
   drv_pin.reserve(NPI + NC);
   std::vector<int32_t> lvl_ptr(L + 2, 0);
@@ -527,6 +546,15 @@ static sta_status build_layout(sta_ctx *C, const Inputs &I, const std::vector<in
     drv_pin.resize(NPI + NC);
     for (int p = 0; p < NP; ++p)
       if (I.pin_kind[p] == STA_PIN_CELL_OUT) drv_pin[fill[cell_level[I.cell_of_pin[p]]]++] = p;
+    const auto nodes_of = [&](int p) {
+      const int n = I.net_of_drv[p];
+      return n < 0 ? (int64_t)0 : I.net_node_ptr[n + 1] - I.net_node_ptr[n];
+    };
+    for (int l = 1; l <= L; ++l)
+      std::stable_sort(drv_pin.begin() + lvl_ptr[l], drv_pin.begin() + lvl_ptr[l + 1], [&](int a, int b) {
+        const int ta = I.cell_type[I.cell_of_pin[a]], tb = I.cell_type[I.cell_of_pin[b]];
+        return ta != tb ? ta < tb : nodes_of(a) < nodes_of(b);
+      });
   }
   // within a level, drivers with more than kSplitSinks sinks go last: the
   // other chunks of the level are then runs of kChunk slots from the level's
@@ -535,11 +563,11 @@ static sta_status build_layout(sta_ctx *C, const Inputs &I, const std::vector<in
     const int n = I.net_of_drv[p];
     return n < 0 ? 0 : I.net_sink_ptr[n + 1] - I.net_sink_ptr[n];
   };
-  C->lvl_reg.assign(L + 1, make_int2(0, 0));
+  C->lvl_reg.assign(L + 1, make_int4(0, 0, 0, 0));
   for (int l = 0; l <= L; ++l) {
     auto b = drv_pin.begin() + lvl_ptr[l], e = drv_pin.begin() + lvl_ptr[l + 1];
     auto mid = std::stable_partition(b, e, [&](int p) { return fanout_of(p) <= kSplitSinks; });
-    C->lvl_reg[l] = make_int2(lvl_ptr[l], lvl_ptr[l] + (int)(mid - b));
+    C->lvl_reg[l] = make_int4(lvl_ptr[l], lvl_ptr[l] + (int)(mid - b), 0, 0);
   }
   const int ND = NPI + NC;
   C->n_drv = ND;
@@ -575,10 +603,7 @@ static sta_status build_layout(sta_ctx *C, const Inputs &I, const std::vector<in
   C->h_ep_pin = ep_pin;
 
   // nets in slot order, sinks net-major.  RC nodes net-major in "RC order":
-  // within each window of kRcSortWindow consecutive slots, small nets by
-  // ascending node count (ties by slot), so the 64 nets a wave walks in
-  // parallel have near-equal trees while a block's outputs stay within one
-  // window of slots; then the wide nets.  rc_ptr[x] is
+  // the small nets chunk by chunk (below), then the wide nets.  rc_ptr[x] is
   // the first node of net x; rc_start / rc_order list the small nets by RC
   // position.
   std::vector<int32_t> sink_ptr(ND + 1, 0), rc_ptr(ND + 1, 0), net_slot(g.n_nets), rc_m(ND);
@@ -592,14 +617,26 @@ static sta_status build_layout(sta_ctx *C, const Inputs &I, const std::vector<in
     if (NN >= INT32_MAX) return fail(STA_E_UNSUPPORTED, "too many RC nodes");
     rc_m[x] = (int32_t)m;
   }
-  std::vector<int32_t> rc_order, rc_start;
+  std::vector<int32_t> rc_order, rc_start, rc_chunk_slot0;
+  std::vector<int2> rc_chunks;
   {
     std::vector<int32_t> small, wide;
     for (int x = 0; x < ND; ++x) (rc_m[x] > big_thr ? wide : small).push_back(x);
-    std::stable_sort(small.begin(), small.end(), [&](int a, int b) {
-      const int wa = a / kRcSortWindow, wb = b / kRcSortWindow;
-      return wa != wb ? wa < wb : rc_m[a] < rc_m[b];
-    });
+    // RC chunks (one block each): runs of consecutive small nets in slot order,
+    // <= kRcBlock nets and <= kRcChunkNodes nodes, so a block's loads and sink
+    // delays fill one contiguous range; inside a chunk, RC positions by node
+    // count (ties by slot), so the 64 trees a wave walks have near-equal sizes
+    size_t j0 = 0;
+    while (j0 < small.size()) {
+      size_t j1 = j0;
+      int64_t nodes = 0;
+      while (j1 < small.size() && (int)(j1 - j0) < kRcBlock && nodes + rc_m[small[j1]] <= kRcChunkNodes)
+        nodes += rc_m[small[j1++]];
+      rc_chunk_slot0.push_back(small[j0]);
+      std::stable_sort(small.begin() + j0, small.begin() + j1, [&](int a, int b) { return rc_m[a] < rc_m[b]; });
+      rc_chunks.push_back(make_int2((int)j0, (int)j1));
+      j0 = j1;
+    }
     int32_t pos = 0;
     rc_start.reserve(small.size() + 1);
     for (int x : small) {
@@ -778,6 +815,36 @@ static sta_status build_layout(sta_ctx *C, const Inputs &I, const std::vector<in
   }
   lvl_cbeg[L + 1] = (int)chunk_rec.size();
   lvl_pbeg[L + 1] = (int)piece_rec.size();
+  // library types each chunk's cells use, as (lowest, highest); (0, -1) for none
+  std::vector<int2> chunk_trange(chunk_rec.size(), make_int2(0, -1));
+  for (size_t c = 0; c < chunk_rec.size(); ++c) {
+    int lo = INT32_MAX, hi = -1;
+    for (int x = chunk_rec[c].x; x < chunk_rec[c].y; ++x)
+      if (cell_type[x] >= 0) {
+        lo = std::min(lo, cell_type[x]);
+        hi = std::max(hi, cell_type[x]);
+      }
+    if (hi >= 0) chunk_trange[c] = make_int2(lo, hi);
+  }
+  // per level, the float4 granules of the widest type span of a block of the
+  // level kernels (chunks paired from the level's first, kLevelCpb a block),
+  // the LDS those kernels reserve for the tables
+  {
+    const int ts = TabLayout{lib.nx, lib.ny}.stride();
+    for (int l = 0; l <= L; ++l) {
+      int most = 0;
+      for (int c = lvl_cbeg[l]; c < lvl_cbeg[l + 1]; c += kLevelCpb) {
+        int lo = INT32_MAX, hi = -1;
+        for (int h = c; h < std::min(c + kLevelCpb, lvl_cbeg[l + 1]); ++h)
+          if (chunk_trange[h].y >= chunk_trange[h].x) {
+            lo = std::min(lo, chunk_trange[h].x);
+            hi = std::max(hi, chunk_trange[h].y);
+          }
+        if (hi >= lo) most = std::max(most, (((hi + 1) * ts + 3) >> 2) - ((lo * ts) >> 2));
+      }
+      C->lvl_reg[l].z = most;
+    }
+  }
   C->n_chunks = (int)chunk_rec.size();
   C->n_pieces = (int)piece_rec.size();
   C->ph_fwd.clear();
@@ -814,19 +881,30 @@ static sta_status build_layout(sta_ctx *C, const Inputs &I, const std::vector<in
     cons_rec[x].type = cell_type[x];
   }
 
-  // RC chunks: runs of RC positions, <= kRcBlock nets and <= kRcChunkNodes nodes
-  std::vector<int2> rc_chunks;
+  C->n_rc_chunks = (int)rc_chunks.size();
+  // level groups of the RC pass (levels [0,2), [2,4), [4,8), [8,16), then 16
+  // at a time): group g launches the RC chunks the levels before the next
+  // group need.  Chunks are in slot order.
   {
-    const int nsm = (int)rc_order.size();
-    int j0 = 0;
-    while (j0 < nsm) {
-      int j1 = j0;
-      while (j1 < nsm && j1 - j0 < kRcBlock && rc_start[j1 + 1] - rc_start[j0] <= kRcChunkNodes) ++j1;
-      rc_chunks.push_back(make_int2(j0, j1));
-      j0 = j1;
+    C->rc_grp_lvl.clear();
+    C->rc_grp_end.clear();
+    std::vector<int32_t> bounds;
+    for (int a = 0; a <= L; a = a < 2 ? 2 : (a < 16 ? 2 * a : a + 16)) bounds.push_back(a);
+    bounds.push_back(L + 1);
+    size_t r = 0;
+    for (size_t g = 0; g + 1 < bounds.size(); ++g) {
+      const int last_slot = lvl_ptr[bounds[g + 1]] - 1;
+      while (r < rc_chunks.size() && rc_chunk_slot0[r] <= last_slot) ++r;
+      C->rc_grp_lvl.push_back(bounds[g]);
+      C->rc_grp_end.push_back((int32_t)r);
+    }
+    C->rc_grp_end.back() = (int32_t)rc_chunks.size();
+    C->wide_lvl = INT32_MAX;
+    for (int x : big_x) {
+      const int l = (int)(std::upper_bound(lvl_ptr.begin(), lvl_ptr.end(), x) - lvl_ptr.begin()) - 1;
+      C->wide_lvl = std::min(C->wide_lvl, l);
     }
   }
-  C->n_rc_chunks = (int)rc_chunks.size();
 
   // packed library
   const TabLayout lay{lib.nx, lib.ny};
@@ -920,6 +998,8 @@ static sta_status build_layout(sta_ctx *C, const Inputs &I, const std::vector<in
     STA_TRY(C->upload(&p4i, piece_rec)); D.piece_rec = p4i;
     int2 *p2i;
     STA_TRY(C->upload(&p2i, chunk_pieces)); D.chunk_pieces = p2i;
+    int2 *tr;
+    STA_TRY(C->upload(&tr, chunk_trange)); D.chunk_trange = tr;
     STA_TRY(C->alloc(&D.piece_rat, std::max(C->n_pieces, 1)));
   }
   STA_TRY(C->alloc(&D.L_net, ND));
@@ -1027,6 +1107,11 @@ static sta_status build_layout(sta_ctx *C, const Inputs &I, const std::vector<in
   HIP_TRY(hipStreamCreateWithFlags(&C->side, hipStreamNonBlocking));
   HIP_TRY(hipEventCreateWithFlags(&C->ev_fork, hipEventDisableTiming));
   HIP_TRY(hipEventCreateWithFlags(&C->ev_join, hipEventDisableTiming));
+  HIP_TRY(hipStreamCreateWithFlags(&C->side2, hipStreamNonBlocking));
+  HIP_TRY(hipEventCreateWithFlags(&C->ev_fwd, hipEventDisableTiming));
+  HIP_TRY(hipEventCreateWithFlags(&C->ev_red, hipEventDisableTiming));
+  C->ev_rc.assign(C->rc_grp_lvl.size(), nullptr);
+  for (auto &e : C->ev_rc) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
 
   // persistent grid: every resident block slot on the device.  The level-major
   // cooperative kernels need every block resident, which the cooperative
@@ -1373,32 +1458,85 @@ static sta_status enqueue_sort(sta_ctx *C, hipStream_t s) {
   return STA_OK;
 }
 
-// Enqueues RC, both sweeps and the reduction on s (the body of one update,
-// without the endpoint sort).  With prof, events separate the phases.
-static sta_status enqueue_update(sta_ctx *C, hipStream_t s, bool prof) {
-  const DevDesign &D = C->D;
+// Enqueues RC, both sweeps, the reduction and (with sort) the endpoint sort
+// on s: one update.  Endpoint slacks need the arrivals only, so the reduction
+// and the sort run on a second stream beside a per-level backward sweep, which
+// is bound by its per-level latency; s waits for them at the end.  With prof,
+// everything runs in order on s and events separate the phases.
+static sta_status enqueue_update(sta_ctx *C, hipStream_t s, bool prof, bool sort) {
   const bool smooth = C->opt.mode == 1;
   const bool per_level = C->opt.sched != STA_SCHED_PERSISTENT;
+  // the per-level backward writes each driver's whole consumer record, so the
+  // RC pass leaves its load field alone there
+  C->D.rc_cons_l = per_level && !smooth ? 0 : 1;
+  const DevDesign &D = C->D;
+  // (not beside a persistent sweep: its blocks wait for each other, and no
+  // other kernel should hold the slots they are waiting to occupy)
+  const bool beside = !smooth && !prof && per_level && C->opt.overlap;
+  // RC in level groups on side2 (wide nets on side) while the per-level
+  // forward sweep runs: a level waits only for the groups up to its own
+  const bool grouped = per_level && !prof && C->opt.overlap;
   if (prof) HIP_TRY(hipEventRecord(C->ev[0], s));
-  STA_TRY(enqueue_rc(C, s, false));
+  if (grouped) {
+    HIP_TRY(hipEventRecord(C->ev_fork, s));
+    if (C->n_big > 0) {
+      HIP_TRY(hipStreamWaitEvent(C->side, C->ev_fork, 0));
+      HIP_TRY(launch_rc_wide(D, C->wide, C->side));
+      HIP_TRY(hipEventRecord(C->ev_join, C->side));
+    }
+    HIP_TRY(hipStreamWaitEvent(C->side2, C->ev_fork, 0));
+    int prev = 0;
+    for (size_t g = 0; g < C->rc_grp_end.size(); ++g) {
+      const int end = C->rc_grp_end[g];
+      if (end > prev || g == 0) HIP_TRY(launch_rc(D, C->rc_chunks + prev, end - prev, C->side2, nullptr, g == 0));
+      prev = end;
+      HIP_TRY(hipEventRecord(C->ev_rc[g], C->side2));
+    }
+  } else {
+    STA_TRY(enqueue_rc(C, s, false));
+  }
   if (prof) HIP_TRY(hipEventRecord(C->ev[1], s));
   if (prof) HIP_TRY(hipEventRecord(C->ev[2], s));
   if (!per_level) {
     HIP_TRY(launch_forward(D, C->sweep_grid, C->coop, s));
   } else {
-    for (const int4 &ph : C->ph_fwd) HIP_TRY(launch_forward_phase(D, ph, C->lvl_reg[ph.w], s));
+    size_t g = 0;
+    bool wide_done = !grouped || C->n_big == 0;
+    for (const int4 &ph : C->ph_fwd) {
+      for (; grouped && g < C->rc_grp_lvl.size() && C->rc_grp_lvl[g] <= ph.w; ++g)
+        HIP_TRY(hipStreamWaitEvent(s, C->ev_rc[g], 0));
+      if (!wide_done && ph.w >= C->wide_lvl) {
+        HIP_TRY(hipStreamWaitEvent(s, C->ev_join, 0));
+        wide_done = true;
+      }
+      HIP_TRY(launch_forward_phase(D, ph, C->lvl_reg[ph.w], s));
+    }
+    for (; grouped && g < C->rc_grp_lvl.size(); ++g) HIP_TRY(hipStreamWaitEvent(s, C->ev_rc[g], 0));
+    if (!wide_done) HIP_TRY(hipStreamWaitEvent(s, C->ev_join, 0));
   }
   if (prof) HIP_TRY(hipEventRecord(C->ev[3], s));
+  if (beside) {
+    HIP_TRY(hipEventRecord(C->ev_fwd, s));
+    HIP_TRY(hipStreamWaitEvent(C->side2, C->ev_fwd, 0));
+    STA_TRY(enqueue_reduce(C, C->side2));
+    if (sort) STA_TRY(enqueue_sort(C, C->side2));
+    HIP_TRY(hipEventRecord(C->ev_red, C->side2));
+  }
   if (!smooth) {  // the smooth objective needs arrivals only; it skips the RAT sweep
     if (!per_level) {
       HIP_TRY(launch_backward(D, C->sweep_grid, C->coop, s));
     } else {
-      for (const int4 &ph : C->ph_bwd) HIP_TRY(launch_backward_phase(D, ph, s));
+      for (const int4 &ph : C->ph_bwd) HIP_TRY(launch_backward_phase(D, ph, C->lvl_reg[ph.w], s));
     }
   }
   if (prof) HIP_TRY(hipEventRecord(C->ev[4], s));
-  STA_TRY(enqueue_reduce(C, s));
+  if (beside) {
+    HIP_TRY(hipStreamWaitEvent(s, C->ev_red, 0));
+  } else {
+    STA_TRY(enqueue_reduce(C, s));
+  }
   if (prof) HIP_TRY(hipEventRecord(C->ev[5], s));
+  if (sort && !beside) STA_TRY(enqueue_sort(C, s));
   return STA_OK;
 }
 
@@ -1406,10 +1544,17 @@ static sta_status enqueue_update(sta_ctx *C, hipStream_t s, bool prof) {
 // and replayed; it holds kernel nodes only (counters are cleared by a kernel,
 // never by a memset node).
 static sta_status ensure_graph(sta_ctx *C) {
+  if (C->graph_exec && C->graph_overlap != C->opt.overlap) {  // captured with the other stream layout
+    (void)hipGraphExecDestroy(C->graph_exec);
+    (void)hipGraphDestroy(C->graph);
+    C->graph_exec = nullptr;
+    C->graph = nullptr;
+  }
   if (C->graph_exec) return STA_OK;
+  C->graph_overlap = C->opt.overlap;
   if (!C->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&C->cap_stream, hipStreamNonBlocking));
   HIP_TRY(hipStreamBeginCapture(C->cap_stream, hipStreamCaptureModeThreadLocal));
-  sta_status st = enqueue_update(C, C->cap_stream, false);
+  sta_status st = enqueue_update(C, C->cap_stream, false, false);  // the sort stays outside the graph
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(C->cap_stream, &g);
   if (st != STA_OK) {
@@ -1434,10 +1579,10 @@ extern "C" sta_status sta_update_timing(sta_ctx *C, void *stream) {
     }
     HIP_TRY(hipGraphLaunch(C->graph_exec, s));
     if (prof) HIP_TRY(hipEventRecord(C->ev[5], s));
+    STA_TRY(enqueue_sort(C, s));
   } else {
-    STA_TRY(enqueue_update(C, s, prof));
+    STA_TRY(enqueue_update(C, s, prof, true));
   }
-  STA_TRY(enqueue_sort(C, s));
   if (prof) HIP_TRY(hipEventRecord(C->ev[6], s));
   C->timed = prof;
   C->last_stream = s;
@@ -1539,6 +1684,7 @@ extern "C" sta_status sta_update_timing_incremental(sta_ctx *C, const int32_t *n
     HIP_TRY(hipEventRecord(C->inc_ev, s));
     d_nets = C->inc_nets;
   }
+  C->D.rc_cons_l = 1;  // the incremental backward reads consumer records, whose loads it does not write
   const DevDesign &D = C->D;
   HIP_TRY(launch_reset_counters(C->inc_buf, C->inc_words, s));
   HIP_TRY(launch_reset_counters(D.counters, n_counters(D.n_ph_fwd + D.n_ph_bwd), s));
@@ -1693,6 +1839,34 @@ extern "C" sta_status sta_estimate_rc(const sta_graph_desc *g, const float *pin_
       HIP_TRY(hipMemcpyAsync(sink_node, A.sink_node, n_sinks * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   }
   HIP_TRY(hipStreamSynchronize(s));
+  return STA_OK;
+}
+
+// Copy bandwidth of a plain vector copy kernel (see sta.h).
+extern "C" sta_status sta_measure_copy(const void *src, void *dst, int64_t bytes, int32_t reps, void *stream,
+                                       float *ms) {
+  if (!src || !dst || !ms) return fail(STA_E_ARG, "NULL argument");
+  if (bytes <= 0 || bytes % 16 != 0) return fail(STA_E_ARG, "bytes must be a positive multiple of 16");
+  if (reps < 1) return fail(STA_E_ARG, "reps %d < 1", reps);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  hipError_t e = hipEventCreate(&e1);
+  if (e != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return hip_fail(e, "hipEventCreate");
+  }
+  e = launch_copy4(src, dst, bytes / 16, s);  // warm-up
+  if (e == hipSuccess) e = hipEventRecord(e0, s);
+  for (int i = 0; i < reps && e == hipSuccess; ++i) e = launch_copy4(src, dst, bytes / 16, s);
+  if (e == hipSuccess) e = hipEventRecord(e1, s);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float t = 0.0f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return hip_fail(e, "copy timing");
+  *ms = t / (float)reps;
   return STA_OK;
 }
 
@@ -2105,24 +2279,27 @@ extern "C" sta_status sta_autotune(sta_ctx *C, int32_t reps, sta_tune_result *be
   if (reps < 1) return fail(STA_E_ARG, "reps %d < 1", reps);
   HIP_TRY(hipSetDevice(C->device));
   hipStream_t s = static_cast<hipStream_t>(stream);
-  struct Cand { int sched, grid; };
+  struct Cand { int sched, grid, overlap; };
   std::vector<Cand> cands;
   const int max_per_cu = std::max(1, C->coop_max > 0 ? C->coop_max / std::max(1, C->n_cu)
                                                     : sweep_blocks_per_cu(sweep_lds_bytes(C->D)));
   const int max_grid = max_per_cu * C->n_cu;
-  for (int k = 1; k <= max_per_cu; ++k) cands.push_back({STA_SCHED_PERSISTENT, k * C->n_cu});
-  cands.push_back({STA_SCHED_PER_LEVEL, max_grid});
-  cands.push_back({STA_SCHED_GRAPH, max_grid});
+  for (int k = 1; k <= max_per_cu; ++k) cands.push_back({STA_SCHED_PERSISTENT, k * C->n_cu, 0});
+  for (int ov = 0; ov <= 1; ++ov) {
+    cands.push_back({STA_SCHED_PER_LEVEL, max_grid, ov});
+    cands.push_back({STA_SCHED_GRAPH, max_grid, ov});
+  }
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
   const sta_options saved = C->opt;
   C->opt.profile = 0;
-  sta_tune_result r{saved.sched, C->sweep_grid, 0.0f, 0};
+  sta_tune_result r{saved.sched, C->sweep_grid, 0.0f, 0, saved.overlap};
   float best_ms = INFINITY;
   sta_status st = STA_OK;
   for (const Cand &c : cands) {
     C->opt.sched = c.sched;
+    C->opt.overlap = c.overlap;
     C->sweep_grid = c.grid;
     C->coop = c.grid <= C->coop_max;
     st = sta_update_timing(C, s);  // warm-up (builds the graph once)
@@ -2144,6 +2321,7 @@ extern "C" sta_status sta_autotune(sta_ctx *C, int32_t reps, sta_tune_result *be
       best_ms = ms;
       r.sched = c.sched;
       r.sweep_blocks = c.grid;
+      r.overlap = c.overlap;
     }
   }
   (void)hipEventDestroy(e0);
@@ -2155,6 +2333,7 @@ extern "C" sta_status sta_autotune(sta_ctx *C, int32_t reps, sta_tune_result *be
     return st;
   }
   C->opt.sched = r.sched;
+  C->opt.overlap = r.overlap;
   C->sweep_grid = r.sweep_blocks;
   C->coop = r.sweep_blocks <= C->coop_max;
   r.ms = best_ms;

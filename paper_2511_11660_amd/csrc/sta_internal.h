@@ -2,7 +2,8 @@
 // (sta_kernels.hip).  Everything is level-sorted once at create time:
 //
 //   driver slots  [0, n_drv): the PIs (ascending pin id), then the cells in
-//                 ascending (cell level, output pin id).  Slot x drives net x.
+//                 ascending (cell level, type, output pin id), a level's
+//                 high-fanout drivers last.  Slot x drives net x.
 //                 Level l occupies [lvl_ptr[l], lvl_ptr[l+1]); level 0 = PIs.
 //   sink slots    [0, n_sinks): net-major, sinks of net x in
 //                 [sink_ptr[x], sink_ptr[x+1]) in the caller's sink order.
@@ -26,9 +27,9 @@ constexpr int kSweepBlock = 256;            // 4 waves, each wave owns one chunk
 constexpr int kChunk = kWave;               // driver slots per sweep chunk
 constexpr int kRcBlock = 256;               // one small net per thread
 constexpr int kRcChunkNodes = 2048;         // RC nodes staged in LDS per block
-constexpr int kRcSortWindow = 4096;         // slots within which small nets are ordered by size
 constexpr int kSmallNetMaxNodes = 255;      // parents fit in a byte
 constexpr int kReduceBlocks = 128;
+constexpr int kLevelCpb = 2;                // chunks per block of the full-update level kernels
 
 struct alignas(32) PinState {
   float4 at;
@@ -111,6 +112,8 @@ struct DevDesign {
   // log-sum-exp; the adjoint writes the g_* arrays
   float gamma;
   int delay_model;              // 0 Elmore, 1 reduced-order (Arnoldi, two poles)
+  int rc_cons_l;                // 1: the RC kernels also write cons_rec[].L (0 where the per-level
+                                // backward writes each driver's whole record)
   const int32_t *ep_loc;        // [n_ep] endpoint pin: driver slot (>= 0) or -1 - sink slot
   float4 *g_sink;               // [n_sinks] dJ/d(late AT R, F), dJ/d(late slew R, F)
   float2 *g_dq;                 // [n_sinks] dJ/d(Elmore delay), dJ/d(spread q)
@@ -127,6 +130,7 @@ struct DevDesign {
   int32_t n_ph_fwd, n_ph_bwd, n_ph_adj;
   const int4 *piece_rec;        // [n_pieces] (driver slot, first sink, end sink, owner chunk)
   const int2 *chunk_pieces;     // [n_chunks] (first piece, count) of a high-fanout driver's chunk
+  const int2 *chunk_trange;     // [n_chunks] (lowest, highest) library type of the chunk's cells; (0, -1): none
   float4 *piece_rat;            // [n_pieces] each piece's merge of RAT_s - d
   uint32_t *counters;
 };
@@ -199,22 +203,28 @@ hipError_t launch_inc_forward(const DevDesign &D, const IncArgs &I, int grid, in
 hipError_t launch_inc_backward(const DevDesign &D, const IncArgs &I, int grid, int max_items, hipStream_t s);
 hipError_t launch_inc_queues(const DevDesign &D, const IncArgs &I, bool backward, hipStream_t s);
 // flagged per-phase continuation (one launch per phase; unflagged chunks return at once)
-hipError_t launch_inc_forward_phase(const DevDesign &D, const IncArgs &I, int4 phase, int2 reg, hipStream_t s);
+hipError_t launch_inc_forward_phase(const DevDesign &D, const IncArgs &I, int4 phase, int4 reg, hipStream_t s);
 hipError_t launch_inc_backward_phase(const DevDesign &D, const IncArgs &I, int4 phase, hipStream_t s);
 int inc_blocks_per_cu(size_t lds_bytes);
-// only: optional per-chunk / per-wide-net flags, unflagged ones skipped
+// only: optional per-chunk / per-wide-net flags, unflagged ones skipped;
+// the first block also clears the sweep and reduction counters unless
+// clear_counters is false (a later launch of one update's RC pass in parts)
 hipError_t launch_rc(const DevDesign &D, const int2 *chunks, int n_chunks, hipStream_t s,
-                     const uint32_t *only = nullptr);
+                     const uint32_t *only = nullptr, bool clear_counters = true);
 hipError_t launch_rc_wide(const DevDesign &D, const WideNets &W, hipStream_t s, const uint32_t *only = nullptr);
 hipError_t launch_rc_adjoint_wide(const DevDesign &D, const WideNets &W, hipStream_t s);
 // Persistent sweeps: with coop, the level-major static schedule on a
 // cooperative (co-resident) grid; otherwise the ticket schedule.
 hipError_t launch_forward(const DevDesign &D, int persistent_grid, bool coop, hipStream_t s);
 // reg: the level's first slot and the end of its slots in regular (kChunk-slot) chunks
-hipError_t launch_forward_phase(const DevDesign &D, int4 phase, int2 reg, hipStream_t s);
+hipError_t launch_forward_phase(const DevDesign &D, int4 phase, int4 reg, hipStream_t s);
 hipError_t launch_backward(const DevDesign &D, int persistent_grid, bool coop, hipStream_t s);
-hipError_t launch_backward_phase(const DevDesign &D, int4 phase, hipStream_t s);
+// per-level backward (RATs pushed to the inputs by their consumers); reg as
+// for the forward: the level's first slot and the end of its regular chunks
+hipError_t launch_backward_phase(const DevDesign &D, int4 phase, int4 reg, hipStream_t s);
 hipError_t launch_reset_counters(uint32_t *counters, int n, hipStream_t s);
+// plain copy of n16 16-byte elements (bandwidth measurement)
+hipError_t launch_copy4(const void *src, void *dst, int64_t n16, hipStream_t s);
 // keys (when not NULL): [2 n_ep] endpoint sort keys, (early/late, slack) with
 // early/late above the slack bits, and their endpoint indices in vals
 hipError_t launch_reduce_smooth(const DevDesign &D, double *partials, double *out, uint64_t *keys,

@@ -186,7 +186,13 @@ __device__ __forceinline__ void st_state(PinState *p, const PinState &v) {
 struct LdsLib {
   const float *tab;
   const int *sense;
+  int shift;  // packed-table float index held at tab[0] (0: the whole library is staged)
 };
+
+// The LDS copy of type t's packed block.
+__device__ __forceinline__ const float *lib_type(const LdsLib &lib, const DevDesign &D, int t) {
+  return lib.tab + (t * D.tstride - lib.shift);
+}
 
 // Library staging into LDS (packed tables padded to a multiple of 4 floats,
 // then the sense codes), split in two so a level kernel can keep the loads in
@@ -223,7 +229,7 @@ __device__ __forceinline__ LdsLib lib_store(const DevDesign &D, unsigned char *s
   for (int i = kLibRegs * (int)blockDim.x + (int)threadIdx.x; i < n4; i += blockDim.x) dst[i] = src[i];
   int *sense = reinterpret_cast<int *>(tab + 4 * n4);
   for (int i = threadIdx.x; i < D.n_types; i += blockDim.x) sense[i] = D.sense[i];
-  return {tab, sense};
+  return {tab, sense, 0};
 }
 
 // Both halves back to back (kernels with nothing to overlap the staging with).
@@ -244,7 +250,52 @@ __device__ __forceinline__ LdsLib load_lib(const DevDesign &D, unsigned char *sm
   }
   int *sense = reinterpret_cast<int *>(tab + 4 * n4);
   for (int i = t; i < D.n_types; i += B) sense[i] = D.sense[i];
-  return {tab, sense};
+  return {tab, sense, 0};
+}
+
+// Staging of only the types [t_lo, t_hi] a block's cells use (within a level
+// the cells are ordered by type, so a block of two chunks usually needs one or
+// two types): one float4 per thread, requested at once, when the types' tables
+// fit the block; any remainder element by element.  The LDS image keeps the
+// whole-library layout (type t at t * tstride), so lookups are unchanged.
+struct LibSpan {
+  int f0, f1;  // float4 range [f0, f1) of the packed tables
+};
+
+__device__ __forceinline__ LibSpan lib_span(const DevDesign &D, int t_lo, int t_hi) {
+  // float4 granules covering floats [t_lo * tstride, (t_hi + 1) * tstride)
+  // (a type's block need not start on a granule: the edge granules copy a
+  // neighbour's floats to their own places, which is harmless)
+  return t_hi >= t_lo ? LibSpan{(t_lo * D.tstride) >> 2, ((t_hi + 1) * D.tstride + 3) >> 2} : LibSpan{0, 0};
+}
+
+__device__ __forceinline__ float4 lib_issue_span(const DevDesign &D, LibSpan sp) {
+  const float4 *src = reinterpret_cast<const float4 *>(D.tables);
+  const float4 v = src[min(sp.f0 + (int)threadIdx.x, max(sp.f1 - 1, 0))];  // clamped, unpredicated
+  __builtin_amdgcn_sched_barrier(0);
+  return v;
+}
+
+// The span's granules go to LDS from its start (lib_f4 granules reserved, the
+// most any block of the launch needs), then the sense codes of every type.
+__device__ __forceinline__ LdsLib lib_store_span(const DevDesign &D, unsigned char *smem, LibSpan sp, float4 v,
+                                                 int lib_f4) {
+  float *tab = reinterpret_cast<float *>(smem);
+  __builtin_amdgcn_sched_barrier(0);
+  if (sp.f1 > sp.f0) {
+    float4 *dst = reinterpret_cast<float4 *>(tab);  // dst[i - f0]: granule i of the packed tables
+    dst[min((int)threadIdx.x, sp.f1 - sp.f0 - 1)] = v;
+    const float4 *src = reinterpret_cast<const float4 *>(D.tables);
+    for (int i = (int)blockDim.x + (int)threadIdx.x; i < sp.f1 - sp.f0; i += blockDim.x) dst[i] = src[sp.f0 + i];
+  }
+  int *sense = reinterpret_cast<int *>(tab + 4 * lib_f4);
+  for (int i = threadIdx.x; i < D.n_types; i += blockDim.x) sense[i] = D.sense[i];
+  return {tab, sense, 4 * sp.f0};
+}
+
+// LDS bytes of a span image of lib_f4 granules and the sense codes.
+__host__ __device__ inline size_t span_lds_bytes(int lib_f4, int n_types) {
+  return ((size_t)lib_f4 * 16 + (size_t)n_types * 4 + 31) & ~(size_t)31;
 }
 
 __host__ __device__ inline size_t lib_lds_bytes(int n_types, int tstride) {
@@ -273,7 +324,7 @@ struct CellCtx {
 
 __device__ __forceinline__ CellCtx cell_ctx(const DevDesign &D, const LdsLib &lib, int t, float L) {
   const TabLayout lay{D.nx, D.ny};
-  const float *tb = lib.tab + t * D.tstride;
+  const float *tb = lib_type(lib, D, t);
   return {lib.sense[t], tb, axis_find(tb + lay.ya(), tb + lay.rdy(), D.ny, L)};
 }
 
@@ -611,7 +662,7 @@ __device__ __forceinline__ void merge_slots(const DevDesign &D, const CellCtx &c
 // the last chunk, nothing written).  The incremental kernels keep one.
 template <bool kInc, int kSlots, int kCpb>
 __global__ __launch_bounds__(kSweepBlock * kCpb) void k_forward(DevDesign D, int c0, int xb, int xr, int n,
-                                                                 IncArgs I) {
+                                                                 int lib_f4, IncArgs I) {
   extern __shared__ __align__(32) unsigned char smem[];
   static_assert(kSweepBlock == 4 * kChunk, "one thread per driver view");
   static_assert(kCpb == 1 || !kInc, "incremental chunks return early: one chunk per block");
@@ -657,7 +708,18 @@ __global__ __launch_bounds__(kSweepBlock * kCpb) void k_forward(DevDesign D, int
   const int xpi = min(xc, max(D.n_pi - 1, 0));
   const float pa = reinterpret_cast<const float *>(D.pi_at + xpi)[v];
   const float ps = reinterpret_cast<const float *>(D.pi_slew + xpi)[v];
-  const LibRegs lib_r = lib_issue(D);
+  // the types of the block's chunks (a chunk past the phase repeats the last)
+  int t_lo = INT32_MAX, t_hi = -1;
+#pragma unroll
+  for (int h = 0; h < kCpb; ++h) {
+    const int2 tr = D.chunk_trange[c0 + min((int)blockIdx.x * kCpb + h, n - 1)];
+    if (tr.y >= tr.x) {
+      t_lo = min(t_lo, tr.x);
+      t_hi = max(t_hi, tr.y);
+    }
+  }
+  const LibSpan span = lib_span(D, t_lo, t_hi);
+  const float4 lib_r = lib_issue_span(D, span);
   if (regular) {
     s0v = D.sink_ptr[x0];
     s1v = D.sink_ptr[x1];
@@ -690,8 +752,8 @@ __global__ __launch_bounds__(kSweepBlock * kCpb) void k_forward(DevDesign D, int
     oldA = D.sink_state[sA];
     ccA = I.sink_cc[sA];
   }
-  const LdsLib lib = lib_store(D, smem, lib_r);
-  PinState *wst = reinterpret_cast<PinState *>(smem + lib_lds_bytes(D.n_types, D.tstride)) + half * kChunk;
+  const LdsLib lib = lib_store_span(D, smem, span, lib_r, lib_f4);
+  PinState *wst = reinterpret_cast<PinState *>(smem + span_lds_bytes(lib_f4, D.n_types)) + half * kChunk;
   int *s_redo = reinterpret_cast<int *>(wst + kChunk);  // [kChunk], incremental only
   lds_barrier();
   float at_v, sl_v;
@@ -802,7 +864,7 @@ __device__ __forceinline__ float4 sink_rat(const DevDesign &D, const LdsLib &lib
   const int sense = lib.sense[t];
   const float Ro[4] = {Ro4.x, Ro4.y, Ro4.z, Ro4.w};
   const float is[4] = {ss.slew.x, ss.slew.y, ss.slew.z, ss.slew.w};
-  const float *tb = lib.tab + t * D.tstride;
+  const float *tb = lib_type(lib, D, t);
   const AxisPos py = axis_find(tb + lay.ya(), tb + lay.rdy(), D.ny, Lt.x);
   float r[4];
 #pragma unroll
@@ -882,7 +944,6 @@ __device__ void bwd_finish(const DevDesign &D, const LdsLib &lib, int *wacc, con
   wave_sync();
   auto sink = [&](int s, const PinState &ss, int cons, float d, int drv) {
     const float4 R = sink_rat<kCoh>(D, lib, ss, cons);
-    if (cons < 0) D.ep_slack[-1 - cons] = ep_slack2(ss.at, R);
     D.sink_rat[s] = R;
     D.sink_slack[s] = slack4(ss.at, R);
     int *acc = wacc + (drv - x0) * 4;
@@ -908,7 +969,6 @@ __device__ void bwd_finish(const DevDesign &D, const LdsLib &lib, int *wacc, con
     }
     st4<kCoh>(&D.cons_rec[x].rat, R);
     D.drv_slack[x] = slack4(p.A, R);
-    if (p.e >= 0) D.ep_slack[p.e] = ep_slack2(p.A, R);
   }
   wave_sync();
 }
@@ -931,7 +991,6 @@ __device__ void bwd_piece(const DevDesign &D, const LdsLib &lib, int j) {
     const int cons = D.sink_cons[s];
     const float d = D.dq[s].x;
     const float4 R = sink_rat<kCoh>(D, lib, ss, cons);
-    if (cons < 0) D.ep_slack[-1 - cons] = ep_slack2(ss.at, R);
     D.sink_rat[s] = R;
     D.sink_slack[s] = slack4(ss.at, R);
     acc = make_float4(fmaxf(acc.x, R.x - d), fmaxf(acc.y, R.y - d), fminf(acc.z, R.z - d), fminf(acc.w, R.w - d));
@@ -1030,7 +1089,7 @@ __global__ __launch_bounds__(kSweepBlock * kCpb) void k_backward(DevDesign D, in
       const float2 Lt = ci.lt;
       const int t = __float_as_int(Lt.y);
       const int sense = lib.sense[t];
-      const float *tb = lib.tab + t * D.tstride;
+      const float *tb = lib_type(lib, D, t);
       const float ro_[2] = {Ro.x, Ro.y}, is[2] = {sl.x, sl.y};
       // staged as in merge_slots: both axes, then the three segments' points
       // and widths, then all corners; every (ri, ro) pair evaluated and the
@@ -1072,7 +1131,6 @@ __global__ __launch_bounds__(kSweepBlock * kCpb) void k_backward(DevDesign D, in
     const float sk0 = el ? r[0] - at.x : at.x - r[0], sk1 = el ? r[1] - at.y : at.y - r[1];
     slk[2 * el] = sk0;
     slk[2 * el + 1] = sk1;
-    if (cons < 0) reinterpret_cast<float *>(D.ep_slack + (-1 - cons))[el] = fminf(sk0, sk1);
     int *acc = wacc + (drv - x0) * 4 + 2 * el;
     if (el) {
       atomicMin(acc + 0, f2key(r[0] - d));
@@ -1101,11 +1159,9 @@ __global__ __launch_bounds__(kSweepBlock * kCpb) void k_backward(DevDesign D, in
     R = late ? fminf(R, E) : fmaxf(R, E);
   }
   const float sk = late ? R - Av : Av - R;
-  const float skm = fminf(sk, __shfl_xor(sk, 1));  // min over rise/fall of this half
   if (live) {
     reinterpret_cast<float *>(&D.cons_rec[x].rat)[v] = R;
     reinterpret_cast<float *>(D.drv_slack + x)[v] = sk;
-    if (e >= 0 && (v & 1) == 0) reinterpret_cast<float *>(D.ep_slack + e)[v >> 1] = skm;
   }
   if constexpr (kInc) {
     int ch = __float_as_uint(R) != __float_as_uint(old_r);
@@ -1136,6 +1192,266 @@ __global__ __launch_bounds__(kSweepBlock) void k_backward_pieces(DevDesign D, in
     if (I.flag[I.n_chunks + D.piece_rec[j].w] == 0u) return;
   }
   bwd_piece<false>(D, lib, j);
+}
+
+// ------------------------------------------ backward with RATs pushed to inputs
+//
+// Per-level backward of the per-level and graph schedules.  The RAT of a sink
+// is its endpoint constraint, or its consumer cell's output RAT minus the arc
+// delay, merged over the output transitions the input transition reaches; here
+// the consumer computes it, when its own level runs.  The kernel of a level,
+// one 256-thread block per chunk (two chunks per block, as the forward):
+//  (a) threads 2 j + el take sink j of the chunk for the early or late half:
+//      its RAT (written by its consumer at a higher level, or its endpoint
+//      constraint), its slack, and RAT_s - d merged into its driver through
+//      LDS keys; then thread 4 d + v finishes view v of driver d (endpoint
+//      constraint, the pieces of a high-fanout driver, slack);
+//  (b) thread 4 d + v = (early/late, output transition ro) recomputes driver
+//      d's cell arc delays into ro from the inputs' stored slews (tables of the
+//      chunk's own types only: cells are ordered by type within a level) and,
+//      with its neighbour lane of the other ro, writes the RAT of every input
+//      sink.
+// Each input sink has one consumer, and min / max are exact, so every value
+// is the same bits as the sink-centric sweep's (sink_rat), which the
+// persistent and incremental schedules keep.  The arc-delay loads do not
+// depend on (a), so they are in flight while (a) runs.
+template <int kSlots>
+__device__ __forceinline__ void slot_delays(const DevDesign &D, const CellCtx &cc, int ro, const float2 *isl,
+                                            float (*dl)[2]) {
+  const TabLayout lay{D.nx, D.ny};
+  const float *xa = cc.tb + lay.xa(), *rdx = cc.tb + lay.rdx();
+  float a[kMaxAxis - 2];
+#pragma unroll
+  for (int m = 1; m < kMaxAxis - 1; ++m) a[m - 1] = xa[m];
+  float X[kSlots];
+  int seg[kSlots];
+#pragma unroll
+  for (int k = 0; k < kSlots; ++k) {
+    X[k] = ro ? isl[k].y : isl[k].x;
+    int i = 0;
+#pragma unroll
+    for (int m = 1; m < kMaxAxis - 1; ++m) i += (m <= D.nx - 2 && a[m - 1] <= X[k]) ? 1 : 0;
+    seg[k] = i;
+  }
+  float ax[kSlots], rd[kSlots];
+#pragma unroll
+  for (int k = 0; k < kSlots; ++k) {
+    ax[k] = xa[seg[k]];
+    rd[k] = rdx[seg[k]];
+  }
+  AxisPos mine[kSlots], other[kSlots];
+#pragma unroll
+  for (int k = 0; k < kSlots; ++k) {
+    mine[k] = AxisPos{seg[k], (X[k] - ax[k]) * rd[k]};
+    other[k].i = __shfl_xor(mine[k].i, 1);
+    other[k].t = __shfl_xor(mine[k].t, 1);
+  }
+#pragma unroll
+  for (int k = 0; k < kSlots; ++k) {
+#pragma unroll
+    for (int ri = 0; ri < 2; ++ri) {
+      AxisPos px;
+      px.i = ri == ro ? mine[k].i : other[k].i;
+      px.t = ri == ro ? mine[k].t : other[k].t;
+      dl[k][ri] = bilerp(cc.tb + lay.tab(ro), D.ny, px, cc.py);
+    }
+  }
+}
+
+// RAT of input transition ri = ro of one input, in the lane (el, ro): this
+// lane's candidate R_out(el, ro) - delay(ri -> ro) and the neighbour lane's
+// R_out(el, 1 - ro) - delay(ri -> 1 - ro), each where the arc maps.
+__device__ __forceinline__ float push_rat(int sense, int el, int ro, float Rv, float d_same, float d_cross,
+                                          bool valid) {
+  const float neutral = el ? kInf : -kInf;
+  const float own = valid && arc_maps(sense, ro, ro) ? Rv - d_same : neutral;
+  // what this lane offers its neighbour: its candidate for ri = 1 - ro
+  const float give = valid && arc_maps(sense, 1 - ro, ro) ? Rv - d_cross : neutral;
+  const float nb = __shfl_xor(give, 1);
+  return el ? fminf(own, nb) : fmaxf(own, nb);
+}
+
+template <int kSlots, int kCpb>
+__global__ __launch_bounds__(kSweepBlock * kCpb) void k_backward_push(DevDesign D, int c0, int xb, int xr, int n,
+                                                                       int lib_f4) {
+  extern __shared__ __align__(32) unsigned char smem[];
+  static_assert(kSweepBlock == 4 * kChunk, "one thread per driver view");
+  const int half = (int)threadIdx.x / kSweepBlock, tid = (int)threadIdx.x % kSweepBlock;
+  const int cb_raw = (int)blockIdx.x * kCpb + half;
+  const bool active = cb_raw < n;
+  const int cb = active ? cb_raw : n - 1;
+  const int c = c0 + cb;
+  const int dv = tid >> 2, v = tid & 3, el = v >> 1, ro = v & 1;
+  const int sel = tid & 1;  // early/late half of this thread's sinks in (a)
+  const bool regular = cb * kChunk < xr - xb;
+  int x0, x1, s0v = 0, s1v = 0;
+  if (regular) {
+    x0 = xb + cb * kChunk;
+    x1 = min(x0 + kChunk, xr);
+  } else {
+    const int4 cr4 = D.chunk_rec[c];
+    x0 = __builtin_amdgcn_readfirstlane(cr4.x);
+    x1 = __builtin_amdgcn_readfirstlane(cr4.y);
+    s0v = cr4.z;
+    s1v = cr4.w;
+  }
+  if (!active) x1 = x0;
+  const int x = x0 + dv;
+  const bool live = x < x1;
+  const int xc = live ? x : x0;
+  const bool pis = x0 < D.n_pi;
+  // (b)'s cell loads first (the fanin ids head the longest chain), every load
+  // unconditional
+  const int4 f4 = kSlots > 0 ? D.fanin4[xc] : make_int4(-1, -1, -1, -1);
+  const int t = max(D.cell_type[xc], 0);
+  const float L = D.L_net[xc];
+  const int e = D.drv_ep[xc];
+  const float Av = reinterpret_cast<const float *>(D.drv_state + xc)[v];
+  int t_lo = INT32_MAX, t_hi = -1;
+#pragma unroll
+  for (int h = 0; h < kCpb; ++h) {
+    const int2 tr = D.chunk_trange[c0 + min((int)blockIdx.x * kCpb + h, n - 1)];
+    if (tr.y >= tr.x) {
+      t_lo = min(t_lo, tr.x);
+      t_hi = max(t_hi, tr.y);
+    }
+  }
+  const LibSpan span = lib_span(D, t_lo, t_hi);
+  const float4 lib_r = lib_issue_span(D, span);
+  if (regular) {
+    s0v = D.sink_ptr[x0];
+    s1v = D.sink_ptr[x1];
+  }
+  const int fs[4] = {f4.x, f4.y, f4.z, f4.w};
+  float2 isl[4];
+#pragma unroll
+  for (int k = 0; k < kSlots; ++k)
+    isl[k] = *reinterpret_cast<const float2 *>(reinterpret_cast<const float *>(D.sink_state + max(fs[k], 0)) + 4 +
+                                               2 * el);
+  const int2 pcs = D.chunk_pieces[c];
+  const int s0 = __builtin_amdgcn_readfirstlane(s0v);
+  const int s1 = active ? __builtin_amdgcn_readfirstlane(s1v) : s0;
+  const int smax = max(s1 - 1, 0);
+  const int sA = s0 + (tid >> 1), sAc = min(sA, smax);
+  struct SinkIn {
+    float2 rat, at;
+    int cons, drv;
+    float d;
+  };
+  auto ld_sink = [&](int s) {  // unpredicated (an endpoint sink reads its stale sink_rat unused)
+    SinkIn q;
+    q.cons = D.sink_cons[s];
+    q.drv = D.sink_drv[s];
+    q.d = D.dq[s].x;
+    q.rat = *reinterpret_cast<const float2 *>(reinterpret_cast<const float *>(D.sink_rat + s) + 2 * sel);
+    q.at = *reinterpret_cast<const float2 *>(reinterpret_cast<const float *>(D.sink_state + s) + 2 * sel);
+    return q;
+  };
+  const SinkIn qA = ld_sink(sAc);
+  const LdsLib lib = lib_store_span(D, smem, span, lib_r, lib_f4);
+  int *wacc = reinterpret_cast<int *>(smem + span_lds_bytes(lib_f4, D.n_types)) + half * kSweepBlock;
+  wacc[tid] = f2key((v >> 1) ? kInf : -kInf);
+  lds_barrier();
+  // (a) the chunk's sinks
+  auto sink = [&](int s, const SinkIn &q) {
+    float2 r = q.rat;
+    if (q.cons < 0) {
+      r = *reinterpret_cast<const float2 *>(reinterpret_cast<const float *>(D.ep_rat + (-1 - q.cons)) + 2 * sel);
+      *reinterpret_cast<float2 *>(reinterpret_cast<float *>(D.sink_rat + s) + 2 * sel) = r;
+    }
+    const float sk0 = sel ? r.x - q.at.x : q.at.x - r.x, sk1 = sel ? r.y - q.at.y : q.at.y - r.y;
+    *reinterpret_cast<float2 *>(reinterpret_cast<float *>(D.sink_slack + s) + 2 * sel) = make_float2(sk0, sk1);
+    int *acc = wacc + (q.drv - x0) * 4 + 2 * sel;
+    if (sel) {
+      atomicMin(acc + 0, f2key(r.x - q.d));
+      atomicMin(acc + 1, f2key(r.y - q.d));
+    } else {
+      atomicMax(acc + 0, f2key(r.x - q.d));
+      atomicMax(acc + 1, f2key(r.y - q.d));
+    }
+  };
+  if (sA < s1) sink(sA, qA);
+  for (int sj = sA + kSweepBlock / 2; sj < s1; sj += kSweepBlock / 2) sink(sj, ld_sink(sj));
+  lds_barrier();
+  float R = key2f(wacc[tid]);
+  const bool late = el != 0;
+  if (live && e >= 0) {
+    const float E = reinterpret_cast<const float *>(D.ep_rat + e)[v];
+    R = late ? fminf(R, E) : fmaxf(R, E);
+  }
+  for (int k = 0; k < pcs.y; ++k) {  // a high-fanout driver (alone in its chunk): its pieces' merges
+    const float E = reinterpret_cast<const float *>(D.piece_rat + pcs.x + k)[v];
+    R = late ? fminf(R, E) : fmaxf(R, E);
+  }
+  // the driver's whole consumer record (RAT, NLDM load, type, padding) in
+  // 8-byte parts, thread v part v, so no part of it is left for another pass
+  const float r1 = __shfl_xor(R, 1), r2 = __shfl_xor(R, 2), r3 = __shfl_xor(R, 3);
+  const float2 part = v == 0 ? make_float2(R, r1)
+                      : v == 1 ? make_float2(r3, r2)
+                      : v == 2 ? make_float2(L, __int_as_float(D.cell_type[xc]))
+                               : make_float2(0.0f, 0.0f);
+  if (live) {
+    reinterpret_cast<float2 *>(&D.cons_rec[x])[v] = part;
+    reinterpret_cast<float *>(D.drv_slack + x)[v] = late ? R - Av : Av - R;
+  }
+  if (pis) return;  // (wave-uniform: a chunk is PIs only or cells only)
+  // (b) the RATs of the cells' input sinks
+  const CellCtx cc = cell_ctx(D, lib, t, L);
+  if constexpr (kSlots > 0) {
+    float dl[kSlots > 0 ? kSlots : 1][2];
+    slot_delays<kSlots>(D, cc, ro, isl, dl);
+#pragma unroll
+    for (int k = 0; k < kSlots; ++k) {
+      const float r = push_rat(cc.sense, el, ro, R, dl[k][ro], dl[k][1 - ro], fs[k] >= 0);
+      if (live && fs[k] >= 0) reinterpret_cast<float *>(D.sink_rat + fs[k])[2 * el + ro] = r;
+    }
+  } else {
+    const TabLayout lay{D.nx, D.ny};
+    const int f0 = D.fanin_ptr[xc], f1 = D.fanin_ptr[xc + 1];
+    for (int f = f0; f < f1; ++f) {  // the lane pair of (el, *) runs the same fanins together
+      const int sk = D.fanin_sink[f];
+      const float *st = reinterpret_cast<const float *>(D.sink_state + sk);
+      float dd[2];
+#pragma unroll
+      for (int ri = 0; ri < 2; ++ri) {
+        const AxisPos px = axis_find(cc.tb + lay.xa(), cc.tb + lay.rdx(), D.nx, st[4 + 2 * el + ri]);
+        dd[ri] = bilerp(cc.tb + lay.tab(ro), D.ny, px, cc.py);
+      }
+      const float r = push_rat(cc.sense, el, ro, R, dd[ro], dd[1 - ro], true);
+      if (live) reinterpret_cast<float *>(D.sink_rat + sk)[2 * el + ro] = r;
+    }
+  }
+}
+
+// A piece of a high-fanout driver's sinks (rounds of one wave): the sinks'
+// RATs as written by their consumers (or their endpoint constraints) and
+// slacks, and the piece's merge of RAT_s - d for the driver's chunk.
+__global__ __launch_bounds__(kSweepBlock) void k_backward_push_pieces(DevDesign D, int j0, int j1) {
+  const int j = j0 + blockIdx.x * (kSweepBlock / kWave) + threadIdx.x / kWave;
+  if (j >= j1) return;
+  const int4 pr = D.piece_rec[j];
+  const int sa = __builtin_amdgcn_readfirstlane(pr.y), sb = __builtin_amdgcn_readfirstlane(pr.z);
+  float4 acc = make_float4(-kInf, -kInf, kInf, kInf);
+  for (int s = sa + lane_id(); s < sb; s += kWave) {
+    const int cons = D.sink_cons[s];
+    const float d = D.dq[s].x;
+    const float4 at = D.sink_state[s].at;
+    float4 R = D.sink_rat[s];
+    if (cons < 0) {
+      R = D.ep_rat[-1 - cons];
+      D.sink_rat[s] = R;
+    }
+    D.sink_slack[s] = slack4(at, R);
+    acc = make_float4(fmaxf(acc.x, R.x - d), fmaxf(acc.y, R.y - d), fminf(acc.z, R.z - d), fminf(acc.w, R.w - d));
+  }
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    acc.x = fmaxf(acc.x, __shfl_xor(acc.x, off));
+    acc.y = fmaxf(acc.y, __shfl_xor(acc.y, off));
+    acc.z = fminf(acc.z, __shfl_xor(acc.z, off));
+    acc.w = fminf(acc.w, __shfl_xor(acc.w, off));
+  }
+  if (lane_id() == 0) D.piece_rat[j] = acc;
 }
 
 // ------------------------------------------------ persistent sweeps
@@ -1496,7 +1812,6 @@ __device__ void inc_bwd_chunk(const DevDesign &D, const LdsLib &lib, int *wacc, 
   wave_sync();
   auto sink = [&](int s, const PinState &ss, int cons, float d, int drv) {
     const float4 R = sink_rat<true>(D, lib, ss, cons);
-    if (cons < 0) D.ep_slack[-1 - cons] = ep_slack2(ss.at, R);
     D.sink_rat[s] = R;
     D.sink_slack[s] = slack4(ss.at, R);
     int *acc = wacc + (drv - x0) * 4;
@@ -1523,7 +1838,6 @@ __device__ void inc_bwd_chunk(const DevDesign &D, const LdsLib &lib, int *wacc, 
     const bool moved = !same_bits4(R, old);
     if (moved) st4<true>(&D.cons_rec[x].rat, R);
     D.drv_slack[x] = slack4(p.A, R);
-    if (p.e >= 0) D.ep_slack[p.e] = ep_slack2(p.A, R);
     if ((moved || rcd) && x >= D.n_pi) {
       if (I.fanin_cc) {
         const int4 f4 = I.fanin_cc[x];
@@ -1931,7 +2245,7 @@ __device__ void rc_wide_net(const DevDesign &D, const BigNet &B, const WideNets 
   wide_path_sum(c, X, egp, egl, V, A, s_w);                                // A: m2
   if (c.b == 0 && threadIdx.x == 0) {
     D.L_net[x] = (float)total;
-    D.cons_rec[x].L = (float)total;
+    if (D.rc_cons_l) D.cons_rec[x].L = (float)total;
   }
   // the net's sinks, split evenly over its blocks
   const int s0 = D.sink_ptr[x], ns = D.sink_ptr[x + 1] - s0;
@@ -2250,7 +2564,7 @@ __global__ __launch_bounds__(kRcBlock) void k_rc(DevDesign D, const int2 *chunks
     if (j < j1) {
       const float L = rc_tree_lds(s_par, s_R, s_C, s_A, s_B, s_base[tid], s_base[tid + 1] - s_base[tid]);
       D.L_net[x] = L;
-      D.cons_rec[x].L = L;
+      if (D.rc_cons_l) D.cons_rec[x].L = L;
     }
     rc_reduced_sinks(D, j < j1, j < j1 ? sr : make_int2(0, 0), s_C, s_A, s_B, s_base);
     return;
@@ -2260,7 +2574,7 @@ __global__ __launch_bounds__(kRcBlock) void k_rc(DevDesign D, const int2 *chunks
     const int s0 = sr.x, s1 = sr.y;
     const float L = rc_tree_lds(s_par, s_R, s_C, s_A, s_B, b, m);
     D.L_net[x] = L;
-    D.cons_rec[x].L = L;
+    if (D.rc_cons_l) D.cons_rec[x].L = L;
 #pragma unroll
     for (int u = 0; u < kPre; ++u) {
       if (s0 + u < s1) {
@@ -2329,6 +2643,18 @@ __global__ __launch_bounds__(256) void k_rc_wide_reduced(DevDesign D, WideNets W
 
 // ------------------------------------------------------------ reduction
 
+// Endpoint slack (early, late) from the endpoint's arrival and its given
+// required time, written for the reports as well.  An endpoint's RAT is its
+// constraint alone (a PO sink, or a cell output with no fanout), so this needs
+// only the forward sweep and the reduction can run beside the backward sweep.
+__device__ __forceinline__ float2 ep_slack_of(const DevDesign &D, int e) {
+  const int loc = D.ep_loc[e];
+  const float4 at = loc >= 0 ? D.drv_state[loc].at : D.sink_state[-1 - loc].at;
+  const float2 s = ep_slack2(at, D.ep_rat[e]);
+  D.ep_slack[e] = s;
+  return s;
+}
+
 // WNS = min(0, min slack), TNS = sum of negative slacks, per early/late, in
 // FP64 with a fixed partition and tree so results are bitwise reproducible;
 // also writes the radix-sort keys of the endpoint order.
@@ -2340,7 +2666,7 @@ __global__ __launch_bounds__(256) void k_reduce(DevDesign D, double *partials, d
   const int b0 = blockIdx.x * per, b1 = min(n, b0 + per);
   double w0 = 0.0, w1 = 0.0, t0 = 0.0, t1 = 0.0;
   for (int e = b0 + (int)threadIdx.x; e < b1; e += 256) {
-    const float2 s = D.ep_slack[e];
+    const float2 s = ep_slack_of(D, e);
     w0 = fmin(w0, (double)s.x);
     w1 = fmin(w1, (double)s.y);
     if (s.x < 0.0f) t0 += (double)s.x;
@@ -2402,7 +2728,7 @@ __global__ __launch_bounds__(256) void k_reduce_batch(DevDesign D, const int32_t
   const int b0 = blockIdx.x * per, b1 = min(n, b0 + per);
   double w0 = 0.0, w1 = 0.0, t0 = 0.0, t1 = 0.0;
   for (int e = b0 + (int)threadIdx.x; e < b1; e += 256) {
-    const float2 s = D.ep_slack[e0 + e];
+    const float2 s = ep_slack_of(D, e0 + e);
     w0 = fmin(w0, (double)s.x);
     w1 = fmin(w1, (double)s.y);
     if (s.x < 0.0f) t0 += (double)s.x;
@@ -2553,7 +2879,7 @@ __device__ void cell_adjoint(const DevDesign &D, const LdsLib &lib, int x, const
   const int sense = lib.sense[t];
   const float L = D.L_net[x];
   const TabLayout lay{D.nx, D.ny};
-  const float *tb = lib.tab + t * D.tstride;
+  const float *tb = lib_type(lib, D, t);
   const AxisPos py = axis_find(tb + lay.ya(), tb + lay.rdy(), D.ny, L);
   const float rdy = tb[lay.rdy() + py.i];
   const float g = D.gamma;
@@ -3161,6 +3487,11 @@ __global__ void k_paths_emit(DevDesign D, PathArgs A, const int32_t *sel, int n_
 
 // ------------------------------------------------------------ wrappers
 
+// The level kernels with a type-span image of lib_f4 granules.
+static size_t span_sweep_lds_bytes(const DevDesign &D, int lib_f4, int chunks_per_block) {
+  return span_lds_bytes(lib_f4, D.n_types) + sizeof(PinState) * kWave * (kSweepBlock / kWave) * chunks_per_block;
+}
+
 size_t sweep_lds_bytes(const DevDesign &D, int chunks_per_block) {
   const size_t per_wave = sizeof(PinState) * kWave;  // >= 4 ints per lane for the backward
   return lib_lds_bytes(D.n_types, D.tstride) + per_wave * (kSweepBlock / kWave) * chunks_per_block;
@@ -3200,8 +3531,9 @@ static hipError_t launch_sweep(const DevDesign &D, float g_tns, float g_wns, int
   return hipGetLastError();
 }
 
-hipError_t launch_rc(const DevDesign &D, const int2 *chunks, int n_chunks, hipStream_t s, const uint32_t *only) {
-  const int n_ctr = n_counters(D.n_ph_fwd + D.n_ph_bwd);
+hipError_t launch_rc(const DevDesign &D, const int2 *chunks, int n_chunks, hipStream_t s, const uint32_t *only,
+                     bool clear_counters) {
+  const int n_ctr = clear_counters ? n_counters(D.n_ph_fwd + D.n_ph_bwd) : 0;
   const dim3 grid(xcd_grid(n_chunks > 0 ? n_chunks : 1));
   if (D.delay_model == 1)
     hipLaunchKernelGGL(k_rc<true>, grid, dim3(kRcBlock), 0, s, D, chunks, n_chunks, D.counters, n_ctr, only);
@@ -3229,17 +3561,17 @@ hipError_t launch_forward(const DevDesign &D, int grid, bool coop, hipStream_t s
 
 // Chunks per block of the full-update level kernels (the incremental
 // continuation keeps one).
-constexpr int kFullCpb = 2;
+constexpr int kFullCpb = kLevelCpb;
 
 template <bool kInc, int kSlots>
-static void launch_fwd_chunks(const DevDesign &D, const IncArgs &I, int4 ph, int2 reg, hipStream_t s) {
+static void launch_fwd_chunks(const DevDesign &D, const IncArgs &I, int4 ph, int4 reg, hipStream_t s) {
   constexpr int cpb = kInc ? 1 : kFullCpb;
   hipLaunchKernelGGL((k_forward<kInc, kSlots, cpb>), dim3(blocks_for(ph.z, cpb)), dim3(kSweepBlock * cpb),
-                     sweep_lds_bytes(D, cpb), s, D, ph.y, reg.x, reg.y, ph.z, I);
+                     span_sweep_lds_bytes(D, reg.z, cpb), s, D, ph.y, reg.x, reg.y, ph.z, reg.z, I);
 }
 
 template <bool kInc>
-static hipError_t forward_phase(const DevDesign &D, const IncArgs &I, int4 ph, int2 reg, hipStream_t s) {
+static hipError_t forward_phase(const DevDesign &D, const IncArgs &I, int4 ph, int4 reg, hipStream_t s) {
   if (ph.z <= 0) return hipSuccess;
   const int per = kSweepBlock / kWave;
   if (ph.x == kItemPiece)
@@ -3272,11 +3604,11 @@ static hipError_t backward_phase(const DevDesign &D, const IncArgs &I, int4 ph, 
   return hipGetLastError();
 }
 
-hipError_t launch_forward_phase(const DevDesign &D, int4 ph, int2 reg, hipStream_t s) {
+hipError_t launch_forward_phase(const DevDesign &D, int4 ph, int4 reg, hipStream_t s) {
   return forward_phase<false>(D, IncArgs{}, ph, reg, s);
 }
 
-hipError_t launch_inc_forward_phase(const DevDesign &D, const IncArgs &I, int4 ph, int2 reg, hipStream_t s) {
+hipError_t launch_inc_forward_phase(const DevDesign &D, const IncArgs &I, int4 ph, int4 reg, hipStream_t s) {
   return forward_phase<true>(D, I, ph, reg, s);
 }
 
@@ -3288,8 +3620,52 @@ hipError_t launch_backward(const DevDesign &D, int grid, bool coop, hipStream_t 
   return launch_sweep<kSweepBwd>(D, 0.0f, 0.0f, grid, coop, s);
 }
 
-hipError_t launch_backward_phase(const DevDesign &D, int4 ph, hipStream_t s) {
-  return backward_phase<false>(D, IncArgs{}, ph, s);
+template <int kSlots>
+static void launch_bwd_push(const DevDesign &D, int4 ph, int4 reg, hipStream_t s) {
+  hipLaunchKernelGGL((k_backward_push<kSlots, kFullCpb>), dim3(blocks_for(ph.z, kFullCpb)),
+                     dim3(kSweepBlock * kFullCpb), span_sweep_lds_bytes(D, reg.z, kFullCpb), s, D, ph.y, reg.x,
+                     reg.y, ph.z, reg.z);
+}
+
+hipError_t launch_backward_phase(const DevDesign &D, int4 ph, int4 reg, hipStream_t s) {
+  if (ph.z <= 0) return hipSuccess;
+  if (ph.x == kItemPiece)
+    hipLaunchKernelGGL(k_backward_push_pieces, dim3(blocks_for(ph.z, kSweepBlock / kWave)), dim3(kSweepBlock), 0, s,
+                       D, ph.y, ph.y + ph.z);
+  else if (!D.fanin4)
+    launch_bwd_push<0>(D, ph, reg, s);
+  else if (D.max_in <= 1)
+    launch_bwd_push<1>(D, ph, reg, s);
+  else if (D.max_in == 2)
+    launch_bwd_push<2>(D, ph, reg, s);
+  else if (D.max_in == 3)
+    launch_bwd_push<3>(D, ph, reg, s);
+  else
+    launch_bwd_push<4>(D, ph, reg, s);
+  return hipGetLastError();
+}
+
+// Plain device copy in 16-byte elements (bandwidth measurement): each
+// thread moves four elements a round, all loads before the stores.
+__global__ __launch_bounds__(256) void k_copy4(const float4 *__restrict__ src, float4 *__restrict__ dst, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    const float4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+    dst[i] = a;
+    dst[i + stride] = b;
+    dst[i + 2 * stride] = c;
+    dst[i + 3 * stride] = d;
+  }
+  for (; i < n; i += stride) dst[i] = src[i];
+}
+
+hipError_t launch_copy4(const void *src, void *dst, int64_t n16, hipStream_t s) {
+  if (n16 <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((n16 + 255) / 256, 256 * 32);
+  hipLaunchKernelGGL(k_copy4, dim3((unsigned)blocks), dim3(256), 0, s, static_cast<const float4 *>(src),
+                     static_cast<float4 *>(dst), n16);
+  return hipGetLastError();
 }
 
 hipError_t launch_reduce_smooth(const DevDesign &D, double *partials, double *out, uint64_t *keys, int32_t *vals,

@@ -60,7 +60,7 @@ class sta_options(ctypes.Structure):
                 ("dangling_policy", ctypes.c_int32), ("sched", ctypes.c_int32),
                 ("big_net_nodes", ctypes.c_int32), ("sort_endpoints", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("device", ctypes.c_int32), ("sweep_blocks", ctypes.c_int32),
-                ("delay_model", ctypes.c_int32)]
+                ("delay_model", ctypes.c_int32), ("overlap", ctypes.c_int32)]
 
 
 class sta_info(ctypes.Structure):
@@ -74,7 +74,7 @@ class sta_info(ctypes.Structure):
 
 class sta_tune_result(ctypes.Structure):
     _fields_ = [("sched", ctypes.c_int32), ("sweep_blocks", ctypes.c_int32), ("ms", ctypes.c_float),
-                ("n_tried", ctypes.c_int32)]
+                ("n_tried", ctypes.c_int32), ("overlap", ctypes.c_int32)]
 
 
 class sta_path_query(ctypes.Structure):
@@ -116,6 +116,7 @@ _SIGS = [
                                         ctypes.c_int, _VP]),
     ("sta_estimate_rc", ctypes.c_int, [ctypes.POINTER(sta_graph_desc), _VP, _VP, ctypes.POINTER(sta_wire_params),
                                        _VP, _VP, _VP, _VP, _VP, ctypes.c_int, _VP]),
+    ("sta_measure_copy", ctypes.c_int, [_VP, _VP, ctypes.c_int64, ctypes.c_int32, _VP, _PF]),
     ("sta_estimate_rc_noalloc", ctypes.c_int, [ctypes.POINTER(sta_graph_desc), _VP, _VP,
                                                ctypes.POINTER(sta_wire_params), _VP, _VP, _VP, _VP, _VP, _VP]),
     ("sta_estimate_rc_backward", ctypes.c_int, [ctypes.POINTER(sta_graph_desc), _VP, _VP,
@@ -360,6 +361,13 @@ def sta_estimate_rc(graph: sta_graph_desc, pin_x, pin_y, wire: sta_wire_params, 
                                   _addr(sink_node), mem, _stream(stream)))
 
 
+def sta_measure_copy(src, dst, nbytes: int, reps: int = 10, stream=None) -> float:
+    """Mean ms of one plain device copy of nbytes from src to dst."""
+    ms = ctypes.c_float(0.0)
+    _check(load().sta_measure_copy(_addr(src), _addr(dst), int(nbytes), int(reps), _stream(stream), ctypes.byref(ms)))
+    return ms.value
+
+
 def sta_estimate_rc_noalloc(graph: sta_graph_desc, pin_x, pin_y, wire: sta_wire_params, net_node_ptr, parent,
                             res_kohm, cap_ff, sink_node, stream=None) -> None:
     _check(load().sta_estimate_rc_noalloc(ctypes.byref(graph), _addr(pin_x), _addr(pin_y), ctypes.byref(wire),
@@ -582,6 +590,7 @@ class STA:
         r = sta_autotune(self.ctx, reps, stream)
         self.opts.sched = r.sched
         self.opts.sweep_blocks = r.sweep_blocks
+        self.opts.overlap = r.overlap
         return r
 
     def phase_times(self):

@@ -68,7 +68,18 @@ def test_mid(sched):
     compare_full(d, r, _run(d, sched=sched))
 
 
-SCHEDS = (STA_SCHED_PERSISTENT, STA_SCHED_PER_LEVEL, STA_SCHED_GRAPH)
+def test_mid_every_schedule_bitwise():
+    """A 40-level design with high-fanout nets: every (schedule, overlap)
+    pair against the oracle and bit for bit against each other."""
+    _all_schedules(synth.generate(synth.mid_config(n_cells=30_000, n_levels=40, seed=25, n_hf=4, hf_min=1100,
+                                                   hf_max=2500)))
+
+
+# (schedule, overlap): the persistent sweeps; per-level launches and their
+# graph, each with every phase in stream order and with the RC groups and the
+# reduction on side streams
+SCHEDS = ((STA_SCHED_PERSISTENT, 0), (STA_SCHED_PER_LEVEL, 0), (STA_SCHED_PER_LEVEL, 1), (STA_SCHED_GRAPH, 0),
+          (STA_SCHED_GRAPH, 1))
 
 
 def _all_schedules(d):
@@ -78,13 +89,13 @@ def _all_schedules(d):
     r = oracle.sta(d)
     scales = magnitude_scales(d, r)
     first = None
-    for sched in SCHEDS:
-        g = _run(d, sched=sched)
-        print(f"[parity] sched={sched}", compare_full(d, r, g, scales=scales), flush=True)
+    for sched, ov in SCHEDS:
+        g = _run(d, sched=sched, overlap=ov)
+        print(f"[parity] sched={sched} overlap={ov}", compare_full(d, r, g, scales=scales), flush=True)
         if first is None:
             first = g
         else:
-            assert_bitwise_equal(first, g, f"schedule {sched} vs {SCHEDS[0]}")
+            assert_bitwise_equal(first, g, f"schedule {sched}/{ov} vs {SCHEDS[0]}")
 
 
 @pytest.mark.slow
