@@ -324,7 +324,7 @@ def paths_side(design, sched: int, blocks: int, reps: int = 5) -> dict:
             "paths": n.value, "path_pins": n_pin_total, "ms": ms, "paths_per_s": n.value / (ms * 1e-3)}
 
 
-_SCHED_NAMES = {0: "persistent", 1: "per-level", 2: "graph"}
+_SCHED_NAMES = {0: "persistent", 1: "per-level", 2: "graph", 3: "dataflow"}
 
 
 def copy_calibration(mib: int, reps: int) -> int:
@@ -353,7 +353,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="10M", choices=["10M", "1M", "tiny"])
     ap.add_argument("--sched", default="auto",
-                    help="auto (tuned at setup), 0 persistent, 1 one launch per level, 2 HIP graph")
+                    help="auto (tuned at setup), 0 persistent, 1 one launch per level, 2 HIP graph, 3 dataflow")
     ap.add_argument("--overlap", type=int, default=1, choices=[0, 1],
                     help="with --sched 1 or 2: side-stream phases on (1) or off (0); auto tunes it")
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -118,8 +118,11 @@ typedef struct {
 typedef enum {
   STA_SCHED_PERSISTENT = 0,    /* one launch per sweep, device-side level counters */
   STA_SCHED_PER_LEVEL = 1,     /* one launch per level */
-  STA_SCHED_GRAPH = 2          /* one launch per level, captured once in a HIP graph and replayed
+  STA_SCHED_GRAPH = 2,         /* one launch per level, captured once in a HIP graph and replayed
                                   (in-graph phases are not timed separately) */
+  STA_SCHED_FLOW = 3           /* one launch per sweep, no level barrier: each chunk waits only for the
+                                  chunks producing its inputs (per-chunk completion flags); needs library
+                                  types of at most 4 inputs and cooperative launch (else STA_E_UNSUPPORTED) */
 } sta_sched;
 
 typedef struct {

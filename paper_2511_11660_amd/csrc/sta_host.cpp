@@ -140,6 +140,11 @@ struct sta_ctx {
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   int graph_overlap = -1;             // sta_options.overlap the graph was captured with
+  bool flow_ok = false;               // the dataflow schedule is available
+  FlowArgs flow_fwd{}, flow_bwd{};
+  uint32_t *flow_err = nullptr;
+  uint32_t flow_epoch = 0;
+  int flow_grid = 0;
   bool bwd_timed = false;
   bool events = false, timed = false;
   hipStream_t last_stream = nullptr;
@@ -1040,6 +1045,61 @@ static sta_status build_layout(sta_ctx *C, const Inputs &I, const std::vector<in
       for (int c = lvl_cbeg[l]; c < lvl_cbeg[l + 1]; ++c) chunk_ph[c] = make_int2(fph[l], bph[l]);
     STA_TRY(C->upload(&C->inc_chunk_of, chunk_of));
     STA_TRY(C->upload(&C->inc_chunk_ph, chunk_ph));
+    // dataflow sweeps: items in sweep order, the forward item producing each
+    // inline input sink (its driver's chunk, or the piece holding it) and the
+    // backward item writing each sink's RAT (its consumer's chunk)
+    int most_pieces = 0;
+    for (const int2 &cp : chunk_pieces) most_pieces = std::max(most_pieces, cp.y);
+    C->flow_ok = !fanin4.empty() && most_pieces <= kSweepBlock;
+    if (C->flow_ok) {
+      std::vector<int2> fi, bi;
+      for (int l = 0; l <= L; ++l) {
+        for (int c = lvl_cbeg[l]; c < lvl_cbeg[l + 1]; ++c) fi.push_back(make_int2(kItemChunk, c));
+        for (int j = lvl_pbeg[l]; j < lvl_pbeg[l + 1]; ++j) fi.push_back(make_int2(kItemPiece, j));
+      }
+      for (int l = L; l >= 0; --l) {
+        for (int j = lvl_pbeg[l]; j < lvl_pbeg[l + 1]; ++j) bi.push_back(make_int2(kItemPiece, j));
+        for (int c = lvl_cbeg[l]; c < lvl_cbeg[l + 1]; ++c) bi.push_back(make_int2(kItemChunk, c));
+      }
+      const int NCH = (int)chunk_rec.size();
+      auto producer = [&](int f) {  // forward item that writes sink f
+        const int y = sink_drv[f], k = f - sink_ptr[y], c = chunk_of[y];
+        if (chunk_pieces[c].y > 0 && k >= kPieceSinks) return NCH + chunk_pieces[c].x + (k - kPieceSinks) / kPieceSinks;
+        return c;
+      };
+      std::vector<int4> fin(ND, make_int4(-1, -1, -1, -1));
+      for (int x = NPI; x < ND; ++x) {
+        const int fs[4] = {fanin4[x].x, fanin4[x].y, fanin4[x].z, fanin4[x].w};
+        int o[4];
+        for (int k = 0; k < 4; ++k) o[k] = fs[k] >= 0 ? producer(fs[k]) : -1;
+        fin[x] = make_int4(o[0], o[1], o[2], o[3]);
+      }
+      std::vector<int32_t> sitem(std::max(NS, 1), -1);
+      for (int f = 0; f < NS; ++f) sitem[f] = sink_cons[f] >= 0 ? chunk_of[sink_cons[f]] : -1;
+      int2 *p2;
+      STA_TRY(C->upload(&p2, fi));
+      C->flow_fwd.items = p2;
+      C->flow_fwd.n_items = (int)fi.size();
+      STA_TRY(C->upload(&p2, bi));
+      C->flow_bwd.items = p2;
+      C->flow_bwd.n_items = (int)bi.size();
+      int4 *p4;
+      STA_TRY(C->upload(&p4, fin));
+      int32_t *pi;
+      STA_TRY(C->upload(&pi, sitem));
+      const size_t nf = (size_t)NCH + std::max<size_t>(piece_rec.size(), 1);
+      uint32_t *flags;
+      STA_TRY(C->alloc(&flags, 2 * nf + 1));
+      HIP_TRY(hipMemset(flags, 0, (2 * nf + 1) * sizeof(uint32_t)));
+      for (FlowArgs *F : {&C->flow_fwd, &C->flow_bwd}) {
+        F->fin_item = p4;
+        F->sink_item = pi;
+        F->err = flags + 2 * nf;
+      }
+      C->flow_fwd.flag = flags;
+      C->flow_bwd.flag = flags + nf;
+      C->flow_err = flags + 2 * nf;
+    }
     std::vector<int32_t> slot_rc(ND, 0);
     for (size_t r = 0; r < rc_chunks.size(); ++r)
       for (int j = rc_chunks[r].x; j < rc_chunks[r].y; ++j) slot_rc[rc_order[j]] = (int32_t)r;
@@ -1128,6 +1188,11 @@ static sta_status build_layout(sta_ctx *C, const Inputs &I, const std::vector<in
   if (C->coop_max > 0) C->sweep_grid = C->coop_max;
   if (C->opt.sweep_blocks > 0) C->sweep_grid = C->opt.sweep_blocks;
   C->coop = C->sweep_grid <= C->coop_max;
+  C->flow_grid = coop_ok ? flow_blocks_per_cu(D) * C->n_cu : 0;
+  if (C->flow_grid <= 0) C->flow_ok = false;
+  if (C->opt.sched == STA_SCHED_FLOW && !C->flow_ok)
+    return fail(STA_E_UNSUPPORTED, "the dataflow schedule needs inline fanins (types of at most 4 inputs), at most "
+                                   "%d sink pieces per driver and cooperative launch", kSweepBlock);
   return STA_OK;
 }
 
@@ -1142,7 +1207,8 @@ static sta_status check_options(const sta_options &o) {
   if (o.mode != 0 && o.mode != 1) return fail(STA_E_ARG, "mode must be 0 (hard) or 1 (smooth)");
   if (o.mode == 1 && !(o.gamma_ps > 0.0f && std::isfinite(o.gamma_ps)))
     return fail(STA_E_ARG, "smooth mode needs a finite gamma_ps > 0");
-  if (o.sched != STA_SCHED_PERSISTENT && o.sched != STA_SCHED_PER_LEVEL && o.sched != STA_SCHED_GRAPH)
+  if (o.sched != STA_SCHED_PERSISTENT && o.sched != STA_SCHED_PER_LEVEL && o.sched != STA_SCHED_GRAPH &&
+      o.sched != STA_SCHED_FLOW)
     return fail(STA_E_ARG, "bad sched");
   if (o.big_net_nodes < 0) return fail(STA_E_ARG, "big_net_nodes < 0");
   if (o.dangling_policy != 0 && o.dangling_policy != 1) return fail(STA_E_ARG, "bad dangling_policy");
@@ -1465,6 +1531,23 @@ static sta_status enqueue_sort(sta_ctx *C, hipStream_t s) {
 // everything runs in order on s and events separate the phases.
 static sta_status enqueue_update(sta_ctx *C, hipStream_t s, bool prof, bool sort) {
   const bool smooth = C->opt.mode == 1;
+  if (C->opt.sched == STA_SCHED_FLOW) {  // RC, then one dataflow launch per sweep, in order on s
+    C->D.rc_cons_l = 1;
+    const DevDesign &D = C->D;
+    if (prof) HIP_TRY(hipEventRecord(C->ev[0], s));
+    STA_TRY(enqueue_rc(C, s, false));
+    if (prof) HIP_TRY(hipEventRecord(C->ev[1], s));
+    if (prof) HIP_TRY(hipEventRecord(C->ev[2], s));
+    C->flow_fwd.epoch = C->flow_bwd.epoch = ++C->flow_epoch;
+    HIP_TRY(launch_flow(D, C->flow_fwd, true, C->flow_grid, s));
+    if (prof) HIP_TRY(hipEventRecord(C->ev[3], s));
+    if (!smooth) HIP_TRY(launch_flow(D, C->flow_bwd, false, C->flow_grid, s));
+    if (prof) HIP_TRY(hipEventRecord(C->ev[4], s));
+    STA_TRY(enqueue_reduce(C, s));
+    if (prof) HIP_TRY(hipEventRecord(C->ev[5], s));
+    if (sort) STA_TRY(enqueue_sort(C, s));
+    return STA_OK;
+  }
   const bool per_level = C->opt.sched != STA_SCHED_PERSISTENT;
   // the per-level backward writes each driver's whole consumer record, so the
   // RC pass leaves its load field alone there
@@ -2130,6 +2213,17 @@ extern "C" sta_status sta_get_phase_times(sta_ctx *C, float *ms, int32_t *n) {
   return STA_OK;
 }
 
+// A dataflow sweep whose wait gave up leaves a raised error word (its
+// results are invalid); reports surface it.
+static sta_status check_flow(sta_ctx *C, hipStream_t s) {
+  if (!C->flow_err || C->flow_epoch == 0) return STA_OK;
+  uint32_t e = 0;
+  HIP_TRY(hipMemcpyAsync(&e, C->flow_err, sizeof e, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (e) return fail(STA_E_DEVICE, "a dataflow sweep wait timed out; results are invalid");
+  return STA_OK;
+}
+
 extern "C" sta_status sta_report_timing(sta_ctx *C, float *at, float *slew, float *rat, int8_t *crit,
                                         sta_mem dst, void *stream) {
   if (!C) return fail(STA_E_STATE, "NULL context");
@@ -2137,6 +2231,7 @@ extern "C" sta_status sta_report_timing(sta_ctx *C, float *at, float *slew, floa
   if (rat && C->opt.mode == 1) return fail(STA_E_STATE, "smooth mode computes no required times");
   HIP_TRY(hipSetDevice(C->device));
   hipStream_t s = static_cast<hipStream_t>(stream);
+  STA_TRY(check_flow(C, s));
   const size_t n4 = (size_t)C->n_pins * sizeof(float4);
   if (dst == STA_DEVICE) {
     HIP_TRY(launch_report_pins(C->D, C->pin_loc, C->n_pins, reinterpret_cast<float4 *>(at),
@@ -2168,6 +2263,7 @@ extern "C" sta_status sta_report_slack(sta_ctx *C, float *pin_slack, float *ep_s
   if (pin_slack && C->opt.mode == 1) return fail(STA_E_STATE, "smooth mode computes no pin slacks");
   HIP_TRY(hipSetDevice(C->device));
   hipStream_t s = static_cast<hipStream_t>(stream);
+  STA_TRY(check_flow(C, s));
   sta_ctx tmp;
   if (pin_slack) {
     float4 *ps = reinterpret_cast<float4 *>(pin_slack);
@@ -2289,6 +2385,7 @@ extern "C" sta_status sta_autotune(sta_ctx *C, int32_t reps, sta_tune_result *be
     cands.push_back({STA_SCHED_PER_LEVEL, max_grid, ov});
     cands.push_back({STA_SCHED_GRAPH, max_grid, ov});
   }
+  if (C->flow_ok) cands.push_back({STA_SCHED_FLOW, max_grid, 0});
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));

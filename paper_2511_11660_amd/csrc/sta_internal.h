@@ -219,6 +219,21 @@ hipError_t launch_forward(const DevDesign &D, int persistent_grid, bool coop, hi
 // reg: the level's first slot and the end of its slots in regular (kChunk-slot) chunks
 hipError_t launch_forward_phase(const DevDesign &D, int4 phase, int4 reg, hipStream_t s);
 hipError_t launch_backward(const DevDesign &D, int persistent_grid, bool coop, hipStream_t s);
+// Dataflow sweeps (one cooperative launch per sweep, per-item completion
+// flags instead of level barriers): the items of one sweep in order and the
+// producer items each item waits for.
+struct FlowArgs {
+  const int2 *items;         // [n_items] (kind, chunk or piece id) in sweep order
+  int n_items;
+  uint32_t *flag;            // [n_chunks + n_pieces] this sweep's flags: chunk c at c, piece j at n_chunks + j
+  const int4 *fin_item;      // [n_drv] forward item producing each inline input sink (-1: none)
+  const int32_t *sink_item;  // [n_sinks] backward item writing each sink's RAT (-1: an endpoint)
+  uint32_t epoch;            // the value a published item's flag holds in this update
+  uint32_t *err;             // raised if a wait gave up (results then invalid)
+};
+hipError_t launch_flow(const DevDesign &D, const FlowArgs &F, bool fwd, int grid, hipStream_t s);
+int flow_blocks_per_cu(const DevDesign &D);  // co-resident blocks of the flow kernels per CU
+
 // per-level backward (RATs pushed to the inputs by their consumers); reg as
 // for the forward: the level's first slot and the end of its regular chunks
 hipError_t launch_backward_phase(const DevDesign &D, int4 phase, int4 reg, hipStream_t s);

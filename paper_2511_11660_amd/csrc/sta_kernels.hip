@@ -1454,6 +1454,332 @@ __global__ __launch_bounds__(kSweepBlock) void k_backward_push_pieces(DevDesign 
   if (lane_id() == 0) D.piece_rat[j] = acc;
 }
 
+// ------------------------------------------------ dataflow sweeps
+//
+// The flow schedule: one cooperative launch per sweep, every block resident,
+// and no level barrier.  The sweep's items (the forward: per level its chunks,
+// then its sink pieces; the backward: per level descending, its pieces, then
+// its chunks) are dealt to the blocks round robin in that order; a block runs
+// its items in order, and an item waits only for the items that produce its
+// inputs, each of which publishes a completion flag (the update's epoch) once
+// its stores are complete.  Every item waits only for earlier items and each
+// block runs its items in order, so by induction over the item order every
+// item completes.  The library is staged into LDS once per block.
+//
+// Values produced and consumed inside one sweep (input sink states and driver
+// states forward, sink RATs and piece merges backward) and the flags are
+// written and read with agent-scope relaxed atomics, which are coherent across
+// the XCDs without an L2 write-back or invalidate; a producer waits for its
+// stores to complete (vmcnt 0) and for its whole block before one thread
+// stores the flag, and a consumer issues those loads only after its poll loop
+// has seen every flag it needs.  A poll gives up after kFlowSpin rounds and
+// raises err[0] (results are then wrong, but the kernel ends).
+constexpr uint32_t kFlowSpin = 1u << 20;
+
+__device__ __forceinline__ uint32_t ld_flag(const uint32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Block-wide wait until every thread's item ids (id < 0: none) show epoch.
+// Once any wait of the sweep has given up (err raised), every wait passes, so
+// the kernel drains quickly.  The exit is decided block-wide (every thread
+// leaves the loop together).
+__device__ __forceinline__ void flow_wait4(const uint32_t *flag, int4 ids, uint32_t epoch, uint32_t *err) {
+  const int q[4] = {ids.x, ids.y, ids.z, ids.w};
+  bool ready = false;
+  for (uint32_t spin = 0;; ++spin) {
+    bool all = true;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) all = all && (q[k] < 0 || ld_flag(flag + q[k]) == epoch);
+    const bool mine = all || ld_flag(err) != 0u;
+    ready = __syncthreads_and(mine);
+    if (ready || spin >= kFlowSpin) break;
+    __builtin_amdgcn_s_sleep(1);
+  }
+  if (!ready && threadIdx.x == 0) atomicOr(err, 1u);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);  // the coherent data loads stay after the poll
+}
+
+// Publishes item `id` once every store of the block has completed.
+__device__ __forceinline__ void flow_publish(uint32_t *flag, int id, uint32_t epoch) {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(flag + id, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ float2 ld_coh2(const float *p) {
+  const uint64_t u = __hip_atomic_load(reinterpret_cast<const uint64_t *>(p), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+  return make_float2(__uint_as_float((uint32_t)u), __uint_as_float((uint32_t)(u >> 32)));
+}
+
+__device__ __forceinline__ void st_coh1(float *p, float v) {
+  __hip_atomic_store(reinterpret_cast<uint32_t *>(p), __float_as_uint(v), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// One forward chunk: the per-level kernel's arithmetic (thread 4 d + v on
+// view v of driver d, the same merge order) on one 256-thread block.
+template <int kSlots>
+__device__ void flow_fwd_chunk(const DevDesign &D, const LdsLib &lib, PinState *wst, const FlowArgs &F, int c) {
+  const int tid = threadIdx.x;
+  const int dv = tid >> 2, v = tid & 3, el = v >> 1, ro = v & 1;
+  const int4 cr4 = D.chunk_rec[c];
+  const int x0 = __builtin_amdgcn_readfirstlane(cr4.x), x1 = __builtin_amdgcn_readfirstlane(cr4.y);
+  const int s0 = __builtin_amdgcn_readfirstlane(cr4.z), s1 = __builtin_amdgcn_readfirstlane(cr4.w);
+  const int x = x0 + dv;
+  const bool live = x < x1;
+  const int xc = live ? x : x0;
+  const bool pis = x0 < D.n_pi;
+  const int4 f4 = D.fanin4[xc];
+  const int t = D.cell_type[xc];
+  const float L = D.L_net[xc];
+  const int xpi = min(xc, max(D.n_pi - 1, 0));
+  const float pa = reinterpret_cast<const float *>(D.pi_at + xpi)[v];
+  const float ps = reinterpret_cast<const float *>(D.pi_slew + xpi)[v];
+  const int4 fi = pis ? make_int4(-1, -1, -1, -1) : F.fin_item[xc];
+  const int sA = min(s0 + tid, max(s1 - 1, 0));
+  const int dA = D.sink_drv[sA];
+  const float2 wA = D.dq[sA];
+  flow_wait4(F.flag, fi, F.epoch, F.err);
+  const int fs[4] = {f4.x, f4.y, f4.z, f4.w};
+  float2 iat[4], isl[4];
+#pragma unroll
+  for (int k = 0; k < kSlots; ++k) {
+    const float *st = reinterpret_cast<const float *>(D.sink_state + max(fs[k], 0));
+    iat[k] = ld_coh2(st + 2 * el);
+    isl[k] = ld_coh2(st + 4 + 2 * el);
+  }
+  float at_v, sl_v;
+  int cr_v = -1;
+  if (pis) {
+    at_v = pa;
+    sl_v = ps;
+  } else {
+    const CellCtx cc = cell_ctx(D, lib, t, L);
+    at_v = el ? -kInf : kInf;
+    sl_v = el ? -kInf : kInf;
+    float lse = 0.0f;
+    merge_slots<kSlots>(D, cc, el, ro, iat, isl, fs, at_v, sl_v, cr_v, lse);
+    if (el && D.gamma > 0.0f) at_v += D.gamma * logf(lse);
+  }
+  uint32_t cw = (uint32_t)(cr_v & 0xff) << (8 * v);
+  cw |= __shfl_xor(cw, 1);
+  cw |= __shfl_xor(cw, 2);
+  if (live) {
+    float *o = reinterpret_cast<float *>(D.drv_state + x);
+    st_coh1(o + v, at_v);  // the driver's pieces read it in this sweep
+    st_coh1(o + 4 + v, sl_v);
+    if (v == 0) D.drv_crit[x] = pis ? 0xffffffffu : cw;
+    float *w = reinterpret_cast<float *>(wst + dv);
+    w[v] = at_v;
+    w[4 + v] = sl_v;
+  }
+  lds_barrier();
+  auto emit = [&](int s, int drv, float2 w) {
+    const PinState ds = wst[drv - x0];
+    PinState o;
+    o.at = make_float4(ds.at.x + w.x, ds.at.y + w.x, ds.at.z + w.x, ds.at.w + w.x);
+    o.slew = make_float4(sqrtf(ds.slew.x * ds.slew.x + w.y), sqrtf(ds.slew.y * ds.slew.y + w.y),
+                         sqrtf(ds.slew.z * ds.slew.z + w.y), sqrtf(ds.slew.w * ds.slew.w + w.y));
+    st_state<true>(D.sink_state + s, o);
+  };
+  if (s0 + tid < s1) emit(s0 + tid, dA, wA);
+  for (int s = s0 + tid + kSweepBlock; s < s1; s += kSweepBlock) emit(s, D.sink_drv[s], D.dq[s]);
+}
+
+// One forward piece: sinks of a high-fanout driver from its published state.
+__device__ void flow_fwd_piece(const DevDesign &D, const FlowArgs &F, int j) {
+  const int4 pr = D.piece_rec[j];
+  const int x = __builtin_amdgcn_readfirstlane(pr.x);
+  const int sa = __builtin_amdgcn_readfirstlane(pr.y), sb = __builtin_amdgcn_readfirstlane(pr.z);
+  const int owner = __builtin_amdgcn_readfirstlane(pr.w);
+  flow_wait4(F.flag, make_int4(owner, -1, -1, -1), F.epoch, F.err);
+  const PinState ds = ld_state<true>(D.drv_state + x);
+  for (int s = sa + (int)threadIdx.x; s < sb; s += kSweepBlock) {
+    const float2 w = D.dq[s];
+    PinState o;
+    o.at = make_float4(ds.at.x + w.x, ds.at.y + w.x, ds.at.z + w.x, ds.at.w + w.x);
+    o.slew = make_float4(sqrtf(ds.slew.x * ds.slew.x + w.y), sqrtf(ds.slew.y * ds.slew.y + w.y),
+                         sqrtf(ds.slew.z * ds.slew.z + w.y), sqrtf(ds.slew.w * ds.slew.w + w.y));
+    st_state<true>(D.sink_state + s, o);
+  }
+}
+
+template <int kSlots>
+__global__ __launch_bounds__(kSweepBlock) void k_flow_fwd(DevDesign D, FlowArgs F) {
+  extern __shared__ __align__(32) unsigned char smem[];
+  const LdsLib lib = load_lib(D, smem);
+  PinState *wst = reinterpret_cast<PinState *>(smem + lib_lds_bytes(D.n_types, D.tstride));
+  __syncthreads();
+  for (int i = blockIdx.x; i < F.n_items; i += gridDim.x) {
+    const int2 it = F.items[i];
+    const int kind = __builtin_amdgcn_readfirstlane(it.x), id = __builtin_amdgcn_readfirstlane(it.y);
+    if (kind == kItemChunk) {
+      flow_fwd_chunk<kSlots>(D, lib, wst, F, id);
+      flow_publish(F.flag, id, F.epoch);
+    } else {
+      flow_fwd_piece(D, F, id);
+      flow_publish(F.flag, D.n_chunks + id, F.epoch);
+    }
+  }
+}
+
+// One backward chunk: the per-level push kernel's arithmetic on one block,
+// after the consumers of its sinks (and its pieces) have published.
+template <int kSlots>
+__device__ void flow_bwd_chunk(const DevDesign &D, const LdsLib &lib, int *wacc, const FlowArgs &F, int c) {
+  const int tid = threadIdx.x;
+  const int dv = tid >> 2, v = tid & 3, el = v >> 1, ro = v & 1;
+  const int sel = tid & 1;
+  const int4 cr4 = D.chunk_rec[c];
+  const int x0 = __builtin_amdgcn_readfirstlane(cr4.x), x1 = __builtin_amdgcn_readfirstlane(cr4.y);
+  const int s0 = __builtin_amdgcn_readfirstlane(cr4.z), s1 = __builtin_amdgcn_readfirstlane(cr4.w);
+  const int x = x0 + dv;
+  const bool live = x < x1;
+  const int xc = live ? x : x0;
+  const bool pis = x0 < D.n_pi;
+  const int4 f4 = D.fanin4[xc];
+  const int t = max(D.cell_type[xc], 0);
+  const float L = D.L_net[xc];
+  const int e = D.drv_ep[xc];
+  const float Av = reinterpret_cast<const float *>(D.drv_state + xc)[v];
+  const int2 pcs = D.chunk_pieces[c];
+  const int fs[4] = {f4.x, f4.y, f4.z, f4.w};
+  float2 isl[4];
+#pragma unroll
+  for (int k = 0; k < kSlots; ++k)
+    isl[k] = *reinterpret_cast<const float2 *>(reinterpret_cast<const float *>(D.sink_state + max(fs[k], 0)) + 4 +
+                                               2 * el);
+  wacc[tid] = f2key((v >> 1) ? kInf : -kInf);
+  // (a) the chunk's sinks, rounds of 128: wait for their consumers, then merge
+  for (int base = s0; base < s1; base += kSweepBlock / 2) {
+    const int s = base + (tid >> 1);
+    const int sc = min(s, s1 - 1);
+    const int cons = D.sink_cons[sc];
+    const int drv = D.sink_drv[sc];
+    const float d = D.dq[sc].x;
+    const float2 at = *reinterpret_cast<const float2 *>(reinterpret_cast<const float *>(D.sink_state + sc) + 2 * sel);
+    const int item = s < s1 ? F.sink_item[sc] : -1;
+    // the pieces of a high-fanout driver join the first round's wait
+    const int pw = base == s0 && tid < pcs.y ? D.n_chunks + pcs.x + tid : -1;
+    flow_wait4(F.flag, make_int4(item, pw, -1, -1), F.epoch, F.err);
+    if (s < s1) {
+      float2 r;
+      if (cons < 0) {
+        r = *reinterpret_cast<const float2 *>(reinterpret_cast<const float *>(D.ep_rat + (-1 - cons)) + 2 * sel);
+        *reinterpret_cast<float2 *>(reinterpret_cast<float *>(D.sink_rat + s) + 2 * sel) = r;
+      } else {
+        r = ld_coh2(reinterpret_cast<const float *>(D.sink_rat + s) + 2 * sel);
+      }
+      const float sk0 = sel ? r.x - at.x : at.x - r.x, sk1 = sel ? r.y - at.y : at.y - r.y;
+      *reinterpret_cast<float2 *>(reinterpret_cast<float *>(D.sink_slack + s) + 2 * sel) = make_float2(sk0, sk1);
+      int *acc = wacc + (drv - x0) * 4 + 2 * sel;
+      if (sel) {
+        atomicMin(acc + 0, f2key(r.x - d));
+        atomicMin(acc + 1, f2key(r.y - d));
+      } else {
+        atomicMax(acc + 0, f2key(r.x - d));
+        atomicMax(acc + 1, f2key(r.y - d));
+      }
+    }
+  }
+  lds_barrier();
+  float R = key2f(wacc[tid]);
+  const bool late = el != 0;
+  if (live && e >= 0) {
+    const float E = reinterpret_cast<const float *>(D.ep_rat + e)[v];
+    R = late ? fminf(R, E) : fmaxf(R, E);
+  }
+  for (int k = 0; k < pcs.y; ++k) {
+    const float2 E = ld_coh2(reinterpret_cast<const float *>(D.piece_rat + pcs.x + k) + 2 * el);
+    const float Ev = ro ? E.y : E.x;
+    R = late ? fminf(R, Ev) : fmaxf(R, Ev);
+  }
+  if (live) {
+    reinterpret_cast<float *>(&D.cons_rec[x].rat)[v] = R;
+    reinterpret_cast<float *>(D.drv_slack + x)[v] = late ? R - Av : Av - R;
+  }
+  if (!pis) {
+    const CellCtx cc = cell_ctx(D, lib, t, L);
+    float dl[kSlots][2];
+    slot_delays<kSlots>(D, cc, ro, isl, dl);
+#pragma unroll
+    for (int k = 0; k < kSlots; ++k) {
+      const float r = push_rat(cc.sense, el, ro, R, dl[k][ro], dl[k][1 - ro], fs[k] >= 0);
+      if (live && fs[k] >= 0) st_coh1(reinterpret_cast<float *>(D.sink_rat + fs[k]) + 2 * el + ro, r);
+    }
+  }
+  lds_barrier();  // wacc is reused by the block's next item
+}
+
+// One backward piece: RATs of a high-fanout driver's sinks once their
+// consumers have published, and the piece's merge for the driver's chunk.
+__device__ void flow_bwd_piece(const DevDesign &D, const FlowArgs &F, float4 *s_acc, int j) {
+  const int4 pr = D.piece_rec[j];
+  const int sa = __builtin_amdgcn_readfirstlane(pr.y), sb = __builtin_amdgcn_readfirstlane(pr.z);
+  float4 acc = make_float4(-kInf, -kInf, kInf, kInf);
+  for (int base = sa; base < sb; base += kSweepBlock) {
+    const int s = base + (int)threadIdx.x;
+    const int sc = min(s, sb - 1);
+    flow_wait4(F.flag, make_int4(s < sb ? F.sink_item[sc] : -1, -1, -1, -1), F.epoch, F.err);
+    if (s < sb) {
+      const int cons = D.sink_cons[s];
+      const float d = D.dq[s].x;
+      const float4 at = D.sink_state[s].at;
+      float4 R;
+      if (cons < 0) {
+        R = D.ep_rat[-1 - cons];
+        D.sink_rat[s] = R;
+      } else {
+        const float2 a = ld_coh2(reinterpret_cast<const float *>(D.sink_rat + s));
+        const float2 b = ld_coh2(reinterpret_cast<const float *>(D.sink_rat + s) + 2);
+        R = make_float4(a.x, a.y, b.x, b.y);
+      }
+      D.sink_slack[s] = slack4(at, R);
+      acc = make_float4(fmaxf(acc.x, R.x - d), fmaxf(acc.y, R.y - d), fminf(acc.z, R.z - d), fminf(acc.w, R.w - d));
+    }
+  }
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    acc.x = fmaxf(acc.x, __shfl_xor(acc.x, off));
+    acc.y = fmaxf(acc.y, __shfl_xor(acc.y, off));
+    acc.z = fminf(acc.z, __shfl_xor(acc.z, off));
+    acc.w = fminf(acc.w, __shfl_xor(acc.w, off));
+  }
+  const int w = threadIdx.x / kWave;
+  if (lane_id() == 0) s_acc[w] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float4 a = s_acc[0];
+    for (int k = 1; k < kSweepBlock / kWave; ++k)
+      a = make_float4(fmaxf(a.x, s_acc[k].x), fmaxf(a.y, s_acc[k].y), fminf(a.z, s_acc[k].z), fminf(a.w, s_acc[k].w));
+    st4<true>(D.piece_rat + j, a);
+  }
+  __syncthreads();
+}
+
+template <int kSlots>
+__global__ __launch_bounds__(kSweepBlock) void k_flow_bwd(DevDesign D, FlowArgs F) {
+  extern __shared__ __align__(32) unsigned char smem[];
+  const LdsLib lib = load_lib(D, smem);
+  int *wacc = reinterpret_cast<int *>(smem + lib_lds_bytes(D.n_types, D.tstride));
+  float4 *s_acc = reinterpret_cast<float4 *>(wacc + kSweepBlock);
+  __syncthreads();
+  for (int i = blockIdx.x; i < F.n_items; i += gridDim.x) {
+    const int2 it = F.items[i];
+    const int kind = __builtin_amdgcn_readfirstlane(it.x), id = __builtin_amdgcn_readfirstlane(it.y);
+    if (kind == kItemChunk) {
+      flow_bwd_chunk<kSlots>(D, lib, wacc, F, id);
+      flow_publish(F.flag, id, F.epoch);
+    } else {
+      flow_bwd_piece(D, F, s_acc, id);
+      flow_publish(F.flag, D.n_chunks + id, F.epoch);
+    }
+  }
+}
+
 // ------------------------------------------------ persistent sweeps
 //
 // A sweep is a list of phases in order (`Phase`: the chunks of one level, or
@@ -3625,6 +3951,40 @@ static void launch_bwd_push(const DevDesign &D, int4 ph, int4 reg, hipStream_t s
   hipLaunchKernelGGL((k_backward_push<kSlots, kFullCpb>), dim3(blocks_for(ph.z, kFullCpb)),
                      dim3(kSweepBlock * kFullCpb), span_sweep_lds_bytes(D, reg.z, kFullCpb), s, D, ph.y, reg.x,
                      reg.y, ph.z, reg.z);
+}
+
+template <int kSlots>
+static hipError_t launch_flow_k(const DevDesign &D, const FlowArgs &F, bool fwd, int grid, hipStream_t s) {
+  DevDesign a = D;
+  FlowArgs b = F;
+  void *args[] = {&a, &b};
+  const void *k = fwd ? reinterpret_cast<const void *>(&k_flow_fwd<kSlots>)
+                      : reinterpret_cast<const void *>(&k_flow_bwd<kSlots>);
+  return hipLaunchCooperativeKernel(k, dim3(grid), dim3(kSweepBlock), args, (unsigned)sweep_lds_bytes(D), s);
+}
+
+hipError_t launch_flow(const DevDesign &D, const FlowArgs &F, bool fwd, int grid, hipStream_t s) {
+  if (F.n_items <= 0) return hipSuccess;
+  switch (D.max_in <= 1 ? 1 : D.max_in) {
+    case 1: return launch_flow_k<1>(D, F, fwd, grid, s);
+    case 2: return launch_flow_k<2>(D, F, fwd, grid, s);
+    case 3: return launch_flow_k<3>(D, F, fwd, grid, s);
+    default: return launch_flow_k<4>(D, F, fwd, grid, s);
+  }
+}
+
+int flow_blocks_per_cu(const DevDesign &D) {
+  int n = 1 << 30;
+  const void *ks[] = {reinterpret_cast<const void *>(&k_flow_fwd<1>), reinterpret_cast<const void *>(&k_flow_bwd<1>),
+                      reinterpret_cast<const void *>(&k_flow_fwd<2>), reinterpret_cast<const void *>(&k_flow_bwd<2>),
+                      reinterpret_cast<const void *>(&k_flow_fwd<3>), reinterpret_cast<const void *>(&k_flow_bwd<3>),
+                      reinterpret_cast<const void *>(&k_flow_fwd<4>), reinterpret_cast<const void *>(&k_flow_bwd<4>)};
+  for (const void *k : ks) {
+    int b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k, kSweepBlock, sweep_lds_bytes(D)) != hipSuccess) return 0;
+    n = std::min(n, b);
+  }
+  return n;
 }
 
 hipError_t launch_backward_phase(const DevDesign &D, int4 ph, int4 reg, hipStream_t s) {

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libsta.so")
 
 STA_OK, STA_E_ARG, STA_E_CYCLE, STA_E_OOM, STA_E_DEVICE, STA_E_STATE, STA_E_UNSUPPORTED = range(7)
 STA_HOST, STA_DEVICE = 0, 1
-STA_SCHED_PERSISTENT, STA_SCHED_PER_LEVEL, STA_SCHED_GRAPH = 0, 1, 2
+STA_SCHED_PERSISTENT, STA_SCHED_PER_LEVEL, STA_SCHED_GRAPH, STA_SCHED_FLOW = 0, 1, 2, 3
 
 _P32 = ctypes.POINTER(ctypes.c_int32)
 _P64 = ctypes.POINTER(ctypes.c_int64)

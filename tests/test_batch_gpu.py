@@ -7,7 +7,8 @@ import pytest
 
 import oracle
 from paper_2511_11660_amd import synth
-from paper_2511_11660_amd.sta import (STA, STA_SCHED_GRAPH, STA_SCHED_PER_LEVEL, STA_SCHED_PERSISTENT)
+from paper_2511_11660_amd.sta import (STA, STA_SCHED_FLOW, STA_SCHED_GRAPH, STA_SCHED_PER_LEVEL,
+                                      STA_SCHED_PERSISTENT)
 from parity import compare_full, run_gpu
 
 pytestmark = pytest.mark.gpu
@@ -66,7 +67,7 @@ def _assert_same(a, b, where):
     assert np.array_equal(a["ep_pin"], b["ep_pin"]), (where, "ep_pin")
 
 
-@pytest.mark.parametrize("sched", [STA_SCHED_PERSISTENT, STA_SCHED_PER_LEVEL, STA_SCHED_GRAPH])
+@pytest.mark.parametrize("sched", [STA_SCHED_PERSISTENT, STA_SCHED_PER_LEVEL, STA_SCHED_GRAPH, STA_SCHED_FLOW])
 def test_batch_bit_identical_to_single_designs(sched):
     designs = _designs(6, 7_100_000, 200, 20_000)
     parts, offs = _run_batch(designs, sched=sched)
@@ -110,7 +111,7 @@ def test_batch_autotune_and_wire_caps():
     designs = _designs(4, 7_300_000, 500, 10_000)
     b = STA(designs)
     r = b.autotune(reps=2)
-    assert r.n_tried >= 3 and r.sched in (STA_SCHED_PERSISTENT, STA_SCHED_PER_LEVEL, STA_SCHED_GRAPH)
+    assert r.n_tried >= 3 and r.sched in (STA_SCHED_PERSISTENT, STA_SCHED_PER_LEVEL, STA_SCHED_GRAPH, STA_SCHED_FLOW)
     assert r.ms > 0
     print(f"[batch] autotune sched={r.sched} blocks={r.sweep_blocks} ms={r.ms:.3f}", flush=True)
     # new caps through the union node order reach every design: each design's

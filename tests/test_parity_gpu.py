@@ -7,7 +7,7 @@ import pytest
 import oracle
 from designs import CIN, COUT, PI, PO, make_design, planar_table, single_segment_net
 from paper_2511_11660_amd import synth
-from paper_2511_11660_amd.sta import STA, STA_SCHED_GRAPH, STA_SCHED_PER_LEVEL, STA_SCHED_PERSISTENT
+from paper_2511_11660_amd.sta import STA, STA_SCHED_FLOW, STA_SCHED_GRAPH, STA_SCHED_PER_LEVEL, STA_SCHED_PERSISTENT
 from parity import assert_bitwise_equal, compare_full, magnitude_scales, run_gpu
 
 pytestmark = pytest.mark.gpu
@@ -22,7 +22,7 @@ def _run(d, **opts):
     return out
 
 
-@pytest.mark.parametrize("sched", [STA_SCHED_PERSISTENT, STA_SCHED_PER_LEVEL, STA_SCHED_GRAPH])
+@pytest.mark.parametrize("sched", [STA_SCHED_PERSISTENT, STA_SCHED_PER_LEVEL, STA_SCHED_GRAPH, STA_SCHED_FLOW])
 def test_tiny(sched):
     d = synth.generate(synth.tiny_config())
     r = oracle.sta(d)
@@ -61,7 +61,7 @@ def test_high_fanout_nets():
     compare_full(d, r, _run(d))
 
 
-@pytest.mark.parametrize("sched", [STA_SCHED_PERSISTENT, STA_SCHED_PER_LEVEL, STA_SCHED_GRAPH])
+@pytest.mark.parametrize("sched", [STA_SCHED_PERSISTENT, STA_SCHED_PER_LEVEL, STA_SCHED_GRAPH, STA_SCHED_FLOW])
 def test_mid(sched):
     d = synth.generate(synth.mid_config(n_cells=60_000, n_levels=40, seed=12))
     r = oracle.sta(d)
@@ -77,9 +77,9 @@ def test_mid_every_schedule_bitwise():
 
 # (schedule, overlap): the persistent sweeps; per-level launches and their
 # graph, each with every phase in stream order and with the RC groups and the
-# reduction on side streams
+# reduction on side streams; the dataflow sweeps
 SCHEDS = ((STA_SCHED_PERSISTENT, 0), (STA_SCHED_PER_LEVEL, 0), (STA_SCHED_PER_LEVEL, 1), (STA_SCHED_GRAPH, 0),
-          (STA_SCHED_GRAPH, 1))
+          (STA_SCHED_GRAPH, 1), (STA_SCHED_FLOW, 0))
 
 
 def _all_schedules(d):

@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 from paper_2511_11660_amd import synth
-from paper_2511_11660_amd.sta import STA, STA_SCHED_GRAPH, STA_SCHED_PER_LEVEL, STA_SCHED_PERSISTENT
+from paper_2511_11660_amd.sta import STA, STA_SCHED_FLOW, STA_SCHED_GRAPH, STA_SCHED_PER_LEVEL, STA_SCHED_PERSISTENT
 
 pytestmark = pytest.mark.gpu
 GAMMA = 5.0
@@ -56,7 +56,7 @@ def _check_smooth(d, sched, big_net_nodes=0, g_tns=0.6, g_wns=0.4):
         _close(name, g[name], o[name], GRAD_REL, _grad_scale(o[name]))
 
 
-@pytest.mark.parametrize("sched", [STA_SCHED_PERSISTENT, STA_SCHED_PER_LEVEL, STA_SCHED_GRAPH])
+@pytest.mark.parametrize("sched", [STA_SCHED_PERSISTENT, STA_SCHED_PER_LEVEL, STA_SCHED_GRAPH, STA_SCHED_FLOW])
 @pytest.mark.parametrize("cfg", ["tiny", "mid"])
 def test_smooth_forward_and_adjoint(cfg, sched):
     d = synth.generate(synth.tiny_config(seed=8, dangling_policy=1) if cfg == "tiny" else
@@ -109,7 +109,7 @@ def test_smooth_1m_pins_adjoint():
         _close(name, g[name], o[name], GRAD_REL, _grad_scale(o[name]))
 
 
-@pytest.mark.parametrize("sched", [STA_SCHED_PERSISTENT, STA_SCHED_PER_LEVEL])
+@pytest.mark.parametrize("sched", [STA_SCHED_PERSISTENT, STA_SCHED_PER_LEVEL, STA_SCHED_FLOW])
 def test_smooth_with_split_high_fanout_drivers(sched):
     cfg = synth.mid_config(seed=24, n_cells=8_000, n_levels=12, n_hf=3, hf_min=1500, hf_max=3000)
     d = synth.generate(cfg)
