@@ -146,11 +146,15 @@ def adjoint_ratio(steps: int) -> dict:
             "ratio": t_bwd / t_fwd}
 
 
-def batched_vs_per_design(steps: int, n_designs: int) -> dict:
+def batched_vs_per_design(steps: int, n_designs: int, n_libs: int = 1) -> dict:
+    """The uneven batch timed as one union against the same designs one by
+    one; with n_libs > 1 design i takes library i mod n_libs (per-design
+    libraries, e.g. several technologies or corners in one batch)."""
     import torch
     from paper_2511_11660_amd import synth
     from paper_2511_11660_amd.sta import STA
-    designs = [synth.generate(c) for c in synth.batch_configs(n_designs)]
+    cfgs = synth.batch_configs(n_designs) if n_libs <= 1 else synth.mixed_batch_configs(n_designs, n_libs)
+    designs = [synth.generate(c) for c in cfgs]
     pins = sum(d.n_pins for d in designs)
     print(f"[bench] batch: {n_designs} designs, {pins} pins", file=sys.stderr, flush=True)
     stream = torch.cuda.current_stream()
@@ -166,7 +170,9 @@ def batched_vs_per_design(steps: int, n_designs: int) -> dict:
     t_seq = _time_updates(singles, stream, max(1, steps // 4))
     for s in singles:
         s.close()
-    return {"workload": f"{n_designs} uneven synthetic designs (1k-200k cells, 10-80 levels), shared library",
+    lib_note = "shared library" if n_libs <= 1 else f"design i with library i mod {n_libs}"
+    return {"workload": f"{n_designs} uneven synthetic designs (1k-200k cells, 10-80 levels), {lib_note}",
+            "libraries": max(1, n_libs),
             "designs": n_designs, "pins": pins, "schedule": _SCHED_NAMES[rb.sched],
             "batched_ms": t_batch, "per_design_sum_ms": t_seq, "speedup": t_seq / t_batch,
             "batched_pins_per_s": pins / (t_batch * 1e-3)}
@@ -188,7 +194,18 @@ def incremental_updates(design, sched: int, blocks: int, full_ms: float, sizes=(
     s.update_incremental(np.zeros(0, np.int32), stream)  # allocations of the first call
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    out = {"workload": "10M-pin design, k random nets re-capped", "full_ms": full_ms, "ms": {}}
+    # the reference: one full update timed the same way (events around a
+    # single call from an idle stream, its launch latency included)
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        s.update(stream)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ts.append(ev0.elapsed_time(ev1))
+    out = {"workload": "10M-pin design, k random nets re-capped", "full_ms": full_ms,
+           "full_single_call_ms": sorted(ts)[len(ts) // 2], "ms": {}}
     for k in sizes:
         ts = []
         for rep in range(reps):
@@ -358,7 +375,7 @@ def main() -> int:
                     help="with --sched 1 or 2: side-stream phases on (1) or off (0); auto tunes it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-side", action="store_true", help="skip every side measurement")
-    ap.add_argument("--side", default="incremental,rc_estimate,reduced_order,adjoint,batched,paths",
+    ap.add_argument("--side", default="incremental,rc_estimate,reduced_order,adjoint,batched,batched_libs,paths",
                     help="comma list of side measurements to run")
     ap.add_argument("--batch-designs", type=int, default=256)
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
@@ -433,6 +450,13 @@ def main() -> int:
     copy_gbps = 2 * (1 << 30) / (copy_ms * 1e-3) / 1e9
     del cbuf
 
+    # the latency floor of a level-synchronous sweep at this design's shape:
+    # one launch per level, each an index load, a 32-byte gather over the sink
+    # states and a 32-byte store for every sink of an average level
+    from paper_2511_11660_amd.sta import sta_measure_level_floor
+    n_lv = info.n_cell_levels + 1
+    floor_ms = sta_measure_level_floor(n_lv, max(1, info.n_sinks // n_lv), info.n_sinks, 5, stream)
+
     n_arcs = int(design.cell_in_ptr[-1])
     ab = algorithmic_bytes(info, n_arcs)
     kern = {"forward": phase[PHASES.index("forward")], "backward": phase[PHASES.index("backward")],
@@ -458,6 +482,9 @@ def main() -> int:
                    "cell_levels": info.n_cell_levels, "endpoints": info.n_endpoints,
                    "views": 4, "schedule": _SCHED_NAMES[sched], "overlap": int(s.opts.overlap)},
         "hbm_frac_whole_update": ab["total"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "level_floor": {"ms_per_sweep": floor_ms, "levels": n_lv, "items_per_level": max(1, info.n_sinks // n_lv),
+                        "forward_over_floor": kern["forward"] / floor_ms,
+                        "backward_over_floor": kern["backward"] / floor_ms},
         "phase_ms": {k: float(v) for k, v in zip(PHASES, phase)},
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
@@ -485,6 +512,9 @@ def main() -> int:
     if "batched" in side:
         print("[bench] batched vs per-design", file=sys.stderr, flush=True)
         out["batched"] = batched_vs_per_design(args.steps, args.batch_designs)
+    if "batched_libs" in side:
+        print("[bench] batched with per-design libraries vs per-design", file=sys.stderr, flush=True)
+        out["batched_libs"] = batched_vs_per_design(args.steps, args.batch_designs, n_libs=4)
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(design, info.n_pins)

@@ -296,7 +296,8 @@ sta_status sta_backward(sta_ctx *ctx, float g_tns, float g_wns, float *grad_wire
  * (one persistent launch per sweep, or one HIP graph replay with
  * STA_SCHED_GRAPH).  graphs, rcs and cons are arrays of n_designs
  * descriptors, each validated as sta_create would (errors name the design);
- * lib is the one shared library.  Per-pin results are bit-identical to timing
+ * lib is the one shared library (sta_batch_create_libs below takes one per
+ * design).  Per-pin results are bit-identical to timing
  * each design alone.  The union must stay within the single-context limits
  * (int32 pin, sink and node counts), else STA_E_UNSUPPORTED; batches time hard
  * mode only (opts->mode must be 0, else STA_E_UNSUPPORTED).
@@ -309,6 +310,23 @@ sta_status sta_backward(sta_ctx *ctx, float g_tns, float g_wns, float *grad_wire
 sta_status sta_batch_create(int32_t n_designs, const sta_graph_desc *graphs, const sta_rc_desc *rcs,
                             const sta_lib_desc *lib, const sta_constraints *cons, const sta_options *opts,
                             sta_ctx **out);
+
+/* sta_batch_create with a library per design: corners (one netlist under
+ * several libraries, e.g. slow / typical / fast) or designs of several
+ * technologies in one batch.  libs holds n_designs pointers; designs whose
+ * pointers are equal share that library's types, and design d's cell types
+ * index libs[d].  The context's library is the union of the distinct
+ * libraries, one after the other, each kept as given (its tables, pin caps,
+ * unateness and PO pin cap apply to its own designs), so per-pin results are
+ * bit-identical to timing each design alone with its own library.  Every
+ * library must have the same table shape (nx, ny) and the union at most 256
+ * types (else STA_E_UNSUPPORTED); the persistent, dataflow and path-report
+ * kernels also need the whole union in LDS (about five 32-type libraries of
+ * 7x7 tables), else sta_batch_create_libs returns STA_E_UNSUPPORTED for them
+ * at create.  Otherwise as sta_batch_create. */
+sta_status sta_batch_create_libs(int32_t n_designs, const sta_graph_desc *graphs, const sta_rc_desc *rcs,
+                                 const sta_lib_desc *const *libs, const sta_constraints *cons,
+                                 const sta_options *opts, sta_ctx **out);
 
 /* Concatenation offsets of a batched context, host arrays of n_designs + 1
  * entries each (any may be NULL): pin_off, ep_off (endpoint index ranges),
@@ -420,6 +438,17 @@ sta_status sta_estimate_rc(const sta_graph_desc *g, const float *pin_x, const fl
  * on `stream`, and writes the mean time of one copy (ms, HIP events) to *ms;
  * a copy moves 2 * bytes.  Synchronizes `stream`. */
 sta_status sta_measure_copy(const void *src, void *dst, int64_t bytes, int32_t reps, void *stream, float *ms);
+
+/* Measurement helper: the latency floor of a level-synchronous sweep on this
+ * device.  Times `levels` dependent launches, each of `items` threads doing
+ * only what bounds one level kernel's critical path (an index load, a 32-byte
+ * gather at that index, a 32-byte store) over `records` 32-byte records (at
+ * least items; make it as large as the design's pin state so the gathers miss
+ * the caches as the sweep's do), once to warm up and then `reps` times, and
+ * writes the mean ms of one such sweep to *ms.  Allocates and frees its own
+ * device buffers; synchronizes `stream`. */
+sta_status sta_measure_level_floor(int32_t levels, int32_t items, int64_t records, int32_t reps, void *stream,
+                                   float *ms);
 
 /* sta_estimate_rc for callers that cannot allocate device memory (code
  * under HIP graph capture nearby, tight serving loops, harnesses that forbid

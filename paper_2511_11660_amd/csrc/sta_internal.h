@@ -21,12 +21,13 @@
 namespace sta {
 
 constexpr int kWave = 64;
-constexpr int kMaxTypes = 64;
+constexpr int kMaxTypes = 256;
 constexpr int kMaxAxis = 8;
 constexpr int kSweepBlock = 256;            // 4 waves, each wave owns one chunk at a time
 constexpr int kChunk = kWave;               // driver slots per sweep chunk
 constexpr int kRcBlock = 256;               // one small net per thread
 constexpr int kRcChunkNodes = 2048;         // RC nodes staged in LDS per block
+constexpr int kRcSortWindow = 4096;         // slots within which small nets are ordered by size
 constexpr int kSmallNetMaxNodes = 255;      // parents fit in a byte
 constexpr int kReduceBlocks = 128;
 constexpr int kLevelCpb = 2;                // chunks per block of the full-update level kernels
@@ -240,6 +241,9 @@ hipError_t launch_backward_phase(const DevDesign &D, int4 phase, int4 reg, hipSt
 hipError_t launch_reset_counters(uint32_t *counters, int n, hipStream_t s);
 // plain copy of n16 16-byte elements (bandwidth measurement)
 hipError_t launch_copy4(const void *src, void *dst, int64_t n16, hipStream_t s);
+// one level-shaped launch: dst[off + i] = src[idx[off + i]] (+1 on one field)
+// for i < n, 32-byte records (latency floor measurement)
+hipError_t launch_level_floor(const int32_t *idx, const void *src, void *dst, int n, int off, hipStream_t s);
 // keys (when not NULL): [2 n_ep] endpoint sort keys, (early/late, slack) with
 // early/late above the slack bits, and their endpoint indices in vals
 hipError_t launch_reduce_smooth(const DevDesign &D, double *partials, double *out, uint64_t *keys,

@@ -4020,6 +4020,25 @@ __global__ __launch_bounds__(256) void k_copy4(const float4 *__restrict__ src, f
   for (; i < n; i += stride) dst[i] = src[i];
 }
 
+// The dependent chain of one level kernel reduced to its memory accesses:
+// an index load, a 32-byte gather at that index, a 32-byte store (latency
+// floor measurement).
+__global__ __launch_bounds__(256) void k_level_floor(const int32_t *__restrict__ idx, const PinState *__restrict__ src,
+                                                     PinState *__restrict__ dst, int n, int off) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  PinState v = src[idx[off + i]];
+  v.at.x += 1.0f;
+  dst[off + i] = v;
+}
+
+hipError_t launch_level_floor(const int32_t *idx, const void *src, void *dst, int n, int off, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_level_floor, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, idx,
+                     static_cast<const PinState *>(src), static_cast<PinState *>(dst), n, off);
+  return hipGetLastError();
+}
+
 hipError_t launch_copy4(const void *src, void *dst, int64_t n16, hipStream_t s) {
   if (n16 <= 0) return hipSuccess;
   const int64_t blocks = std::min<int64_t>((n16 + 255) / 256, 256 * 32);

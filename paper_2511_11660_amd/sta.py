@@ -109,6 +109,10 @@ _SIGS = [
                                         ctypes.POINTER(sta_rc_desc), ctypes.POINTER(sta_lib_desc),
                                         ctypes.POINTER(sta_constraints), ctypes.POINTER(sta_options),
                                         ctypes.POINTER(_VP)]),
+    ("sta_batch_create_libs", ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(sta_graph_desc),
+                                             ctypes.POINTER(sta_rc_desc), ctypes.POINTER(ctypes.POINTER(sta_lib_desc)),
+                                             ctypes.POINTER(sta_constraints), ctypes.POINTER(sta_options),
+                                             ctypes.POINTER(_VP)]),
     ("sta_batch_offsets", ctypes.c_int, [_VP, _P32, _P32, _P32, _P64]),
     ("sta_batch_report", ctypes.c_int, [_VP, _PD, _PD, _VP]),
     ("sta_autotune", ctypes.c_int, [_VP, ctypes.c_int32, ctypes.POINTER(sta_tune_result), _VP]),
@@ -117,6 +121,8 @@ _SIGS = [
     ("sta_estimate_rc", ctypes.c_int, [ctypes.POINTER(sta_graph_desc), _VP, _VP, ctypes.POINTER(sta_wire_params),
                                        _VP, _VP, _VP, _VP, _VP, ctypes.c_int, _VP]),
     ("sta_measure_copy", ctypes.c_int, [_VP, _VP, ctypes.c_int64, ctypes.c_int32, _VP, _PF]),
+    ("sta_measure_level_floor", ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
+                                               _VP, _PF]),
     ("sta_estimate_rc_noalloc", ctypes.c_int, [ctypes.POINTER(sta_graph_desc), _VP, _VP,
                                                ctypes.POINTER(sta_wire_params), _VP, _VP, _VP, _VP, _VP, _VP]),
     ("sta_estimate_rc_backward", ctypes.c_int, [ctypes.POINTER(sta_graph_desc), _VP, _VP,
@@ -305,6 +311,22 @@ def sta_batch_create(graphs, rcs, lib: sta_lib_desc, cons, opts: sta_options | N
     return ctx.value
 
 
+def sta_batch_create_libs(graphs, rcs, libs, cons, opts: sta_options | None = None) -> int:
+    """Batch with one library per design; equal entries of libs (the same
+    sta_lib_desc object) share one library."""
+    n = len(graphs)
+    if not (len(rcs) == len(cons) == len(libs) == n):
+        raise ValueError("graphs, rcs, libs and cons must have one entry per design")
+    ga = (sta_graph_desc * n)(*graphs)
+    ra = (sta_rc_desc * n)(*rcs)
+    ca = (sta_constraints * n)(*cons)
+    la = (ctypes.POINTER(sta_lib_desc) * n)(*[ctypes.pointer(l) for l in libs])
+    ctx = _VP()
+    _check(load().sta_batch_create_libs(n, ga, ra, la, ca, ctypes.byref(opts) if opts is not None else None,
+                                        ctypes.byref(ctx)))
+    return ctx.value
+
+
 def sta_batch_offsets(ctx: int):
     """(pin_off, ep_off, node_off) numpy arrays of n_designs + 1 entries."""
     n = ctypes.c_int32(0)
@@ -365,6 +387,14 @@ def sta_measure_copy(src, dst, nbytes: int, reps: int = 10, stream=None) -> floa
     """Mean ms of one plain device copy of nbytes from src to dst."""
     ms = ctypes.c_float(0.0)
     _check(load().sta_measure_copy(_addr(src), _addr(dst), int(nbytes), int(reps), _stream(stream), ctypes.byref(ms)))
+    return ms.value
+
+
+def sta_measure_level_floor(levels: int, items: int, records: int, reps: int = 5, stream=None) -> float:
+    """Mean ms of `levels` dependent level-shaped launches (see sta.h)."""
+    ms = ctypes.c_float(0.0)
+    _check(load().sta_measure_level_floor(int(levels), int(items), int(records), int(reps), _stream(stream),
+                                          ctypes.byref(ms)))
     return ms.value
 
 
@@ -496,6 +526,17 @@ def descriptors(d, keep: list):
     return g, rc, lib, cons
 
 
+def _lib_key(d) -> bytes:
+    """Identity of a design's library by content."""
+    import hashlib
+    h = hashlib.sha1()
+    h.update(np.int32([d.n_types, d.nx, d.ny]).tobytes())
+    for name in ("n_inputs", "sense", "pin_cap_ff", "slew_axis", "load_axis", "tables"):
+        h.update(np.ascontiguousarray(getattr(d, name)).tobytes())
+    h.update(np.float32(d.po_cap_ff).tobytes())
+    return h.digest()
+
+
 class STA:
     """One timing context on the current HIP device: of one design, or of a
     batch when given a list of designs that share one library."""
@@ -510,8 +551,16 @@ class STA:
         keep: list = []
         descs = [descriptors(d, keep) for d in designs]
         if batch:
-            self.ctx = sta_batch_create([x[0] for x in descs], [x[1] for x in descs], descs[0][2],
-                                        [x[3] for x in descs], o)
+            # designs whose library arrays are equal share one library descriptor
+            keys = [_lib_key(d) for d in designs]
+            if all(k == keys[0] for k in keys):
+                self.ctx = sta_batch_create([x[0] for x in descs], [x[1] for x in descs], descs[0][2],
+                                            [x[3] for x in descs], o)
+            else:
+                first = {}
+                libs = [descs[first.setdefault(k, i)][2] for i, k in enumerate(keys)]
+                self.ctx = sta_batch_create_libs([x[0] for x in descs], [x[1] for x in descs], libs,
+                                                 [x[3] for x in descs], o)
         else:
             g, rc, lib, cons = descs[0]
             self.ctx = sta_create(g, rc, lib, cons, o)

@@ -11,6 +11,7 @@ designs below bracket that range.
 from __future__ import annotations
 
 import ctypes
+import dataclasses
 import math
 import os
 from dataclasses import dataclass, field
@@ -269,6 +270,22 @@ def batch_configs(n_designs: int = 256, base_seed: int = 5_000_000,
         levels = min(levels, cells)
         out.append(mid_config(seed=seed, n_cells=cells, n_levels=levels, lib_seed=base_seed))
     return out
+
+
+def corner_configs(base: SynthConfig, lib_seeds=(11, 12, 13, 14)) -> list[SynthConfig]:
+    """The same netlist (base's seed and sizes) under one library per entry of
+    lib_seeds, as a batch of corners: the library streams are independent of
+    the netlist streams, so only the tables and pin caps differ."""
+    return [dataclasses.replace(base, lib_seed=int(ls)) for ls in lib_seeds]
+
+
+def mixed_batch_configs(n_designs: int = 256, n_libs: int = 4, base_seed: int = 5_000_000,
+                        min_cells: int = 1000, max_cells: int = 200_000) -> list[SynthConfig]:
+    """batch_configs with a library per design: design i takes library
+    i mod n_libs (seeds base_seed + 1_000_000 + j), e.g. designs of several
+    technologies or corners in one batch."""
+    out = batch_configs(n_designs, base_seed, min_cells, max_cells)
+    return [dataclasses.replace(c, lib_seed=base_seed + 1_000_000 + i % n_libs) for i, c in enumerate(out)]
 
 
 def stats(d: Design) -> dict:

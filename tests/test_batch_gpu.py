@@ -1,5 +1,5 @@
-"""Batched form on the GPU: several designs sharing one library timed as one
-union graph.  Each design's slice of the batched results is compared bit for
+"""Batched form on the GPU: several designs (sharing one library, or each
+with its own: corners) timed as one union graph.  Each design's slice of the batched results is compared bit for
 bit with the same design timed alone (same kernels, same per-pin arithmetic
 order, same reduction partition), and against the FP64 oracle per design."""
 import numpy as np
@@ -105,6 +105,47 @@ def test_batch_with_wide_nets_and_one_design():
     g = run_gpu(s)
     s.close()
     _assert_same(one[0], g, "single")
+
+
+def _single(d, **opts):
+    s = STA(d, **opts)
+    s.update()
+    g = run_gpu(s)
+    s.close()
+    g["slack"]["wns"] = np.asarray(g["slack"]["wns"])
+    g["slack"]["tns"] = np.asarray(g["slack"]["tns"])
+    return g
+
+
+@pytest.mark.parametrize("sched", [STA_SCHED_PERSISTENT, STA_SCHED_PER_LEVEL, STA_SCHED_GRAPH])
+def test_corner_batch(sched):
+    """One netlist under four libraries (corners) as one batch of per-design
+    libraries: each corner bit for bit as the netlist timed alone with that
+    library, and element by element against the FP64 oracle."""
+    cfgs = synth.corner_configs(synth.mid_config(n_cells=20_000, n_levels=25, seed=41, n_hf=2, hf_min=300,
+                                                 hf_max=900))
+    designs = [synth.generate(c) for c in cfgs]
+    assert np.array_equal(designs[0].net_sink_pin, designs[3].net_sink_pin)
+    assert not np.array_equal(designs[0].tables, designs[3].tables)
+    parts, _ = _run_batch(designs, sched=sched)
+    for i, d in enumerate(designs):
+        _assert_same(parts[i], _single(d, sched=sched), f"corner {i}")
+        if sched == STA_SCHED_PER_LEVEL:
+            compare_full(d, oracle.sta(d), parts[i])
+    # the corners differ (different libraries give different arrivals)
+    assert not np.array_equal(parts[0]["timing"]["at"], parts[3]["timing"]["at"])
+
+
+def test_mixed_library_batch():
+    """Uneven designs each with one of three libraries (shared by designs
+    with the same one): per design bit for bit as alone and against the
+    oracle."""
+    cfgs = synth.mixed_batch_configs(9, n_libs=3, base_seed=7_400_000, min_cells=200, max_cells=12_000)
+    designs = [synth.generate(c) for c in cfgs]
+    parts, _ = _run_batch(designs)
+    for i, d in enumerate(designs):
+        _assert_same(parts[i], _single(d), f"design {i}")
+        compare_full(d, oracle.sta(d), parts[i])
 
 
 def test_batch_autotune_and_wire_caps():
