@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -194,10 +195,8 @@ struct sta_ctx {
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
     if (graph) (void)hipGraphDestroy(graph);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
-    if (side) (void)hipStreamDestroy(side);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
-    if (side2) (void)hipStreamDestroy(side2);
     if (ev_fwd) (void)hipEventDestroy(ev_fwd);
     if (ev_red) (void)hipEventDestroy(ev_red);
     for (auto &e : ev_rc) (void)hipEventDestroy(e);
@@ -206,6 +205,39 @@ struct sta_ctx {
     if (inc_stop) (void)hipHostFree(inc_stop);
   }
 };
+
+// The two side streams of every context on a device: made once, by the
+// first context created on it, and kept until the process ends.  Streams made
+// later in a process that has run a cooperative launch ran the overlapped
+// per-level sequence (RC groups and the reduction beside the sweeps) at more
+// than twice its in-order time, while contexts created before that launch kept
+// their speed; sharing the first pair keeps every context on those.  Contexts
+// used at once from several caller streams stay correct (every use is ordered
+// by the context's own events) but share the pair's hardware queues.
+static hipError_t device_side_streams(int device, hipStream_t *a, hipStream_t *b) {
+  static std::mutex mu;
+  static std::vector<std::pair<hipStream_t, hipStream_t>> pool;
+  std::lock_guard<std::mutex> lock(mu);
+  if (device < 0) return hipErrorInvalidDevice;
+  if ((size_t)device >= pool.size()) pool.resize((size_t)device + 1, {nullptr, nullptr});
+  auto &p = pool[(size_t)device];
+  if (!p.first) {
+    hipError_t e = hipStreamCreateWithFlags(&p.first, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      p.first = nullptr;
+      return e;
+    }
+    e = hipStreamCreateWithFlags(&p.second, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      (void)hipStreamDestroy(p.first);
+      p = {nullptr, nullptr};
+      return e;
+    }
+  }
+  *a = p.first;
+  *b = p.second;
+  return hipSuccess;
+}
 
 extern "C" {
 
@@ -1180,10 +1212,9 @@ static sta_status build_layout(sta_ctx *C, const Inputs &I, const std::vector<in
   C->wide.egl = C->big_egl;
   C->wide.pc = C->big_pc;
   C->wide.scratch = C->big_scratch;
-  HIP_TRY(hipStreamCreateWithFlags(&C->side, hipStreamNonBlocking));
+  HIP_TRY(device_side_streams(C->device, &C->side, &C->side2));
   HIP_TRY(hipEventCreateWithFlags(&C->ev_fork, hipEventDisableTiming));
   HIP_TRY(hipEventCreateWithFlags(&C->ev_join, hipEventDisableTiming));
-  HIP_TRY(hipStreamCreateWithFlags(&C->side2, hipStreamNonBlocking));
   HIP_TRY(hipEventCreateWithFlags(&C->ev_fwd, hipEventDisableTiming));
   HIP_TRY(hipEventCreateWithFlags(&C->ev_red, hipEventDisableTiming));
   C->ev_rc.assign(C->rc_grp_lvl.size(), nullptr);
