@@ -241,7 +241,7 @@ def rc_estimate_side(design, reps: int = 5) -> dict:
                        None, None, dev["net_driver"].data_ptr(), dev["net_sink_ptr"].data_ptr(),
                        dev["net_sink_pin"].data_ptr(), STA_DEVICE)
     nn, ns = design.n_nets, int(design.net_sink_ptr[-1])
-    nodes = nn + 2 * ns
+    nodes = nn + 3 * ns
     ptr = torch.empty(nn + 1, dtype=torch.int64, device="cuda")
     par = torch.empty(nodes, dtype=torch.int32, device="cuda")
     res = torch.empty(nodes, dtype=torch.float32, device="cuda")

@@ -393,22 +393,28 @@ sta_status sta_report_paths(sta_ctx *ctx, const sta_path_query *q, int32_t *n_pa
 
 /* RC trees estimated from pin positions (§III "Parasitics (RC) inputs": in
  * placement flows the timer derives each net's RC tree itself from pin
- * coordinates and per-unit-length resistance and capacitance along x and y).
- * Per net: a rectilinear minimum spanning tree grown from the driver by
- * Prim's rule (Manhattan distances evaluated in FP32; the next pin is the
- * outside pin nearest to the tree, ties to the lower pin index, pin 0 the
- * driver and pins 1..k the sinks in net_sink_pin order; its parent is the
- * earliest-joined tree pin at that distance).  Each tree edge parent -> pin
- * is wired as an L, along x to a corner at (x_pin, y_parent), then along y
- * to the pin.  The t-th pin to join owns net-local nodes 2t-1 (corner,
- * parent = the parent pin's node, R = r_x |dx|, C = c_x |dx|) and 2t (the
- * pin, parent 2t-1, R = r_y |dy|, C = c_y |dy|): FP32 products, each
- * segment's capacitance lumped at its far node; node 0 is the driver with
- * R = C = 0.  A net of k sinks has 2k+1 nodes, net n starts at node
- * n + 2 * net_sink_ptr[n], so the output is an sta_rc_desc of
- * n_nets + 2 * n_sinks nodes, ready for sta_create.  The paper builds FLUTE
- * Steiner trees here; the spanning tree is a documented stand-in (its wire
- * length is at most 1.5x the Steiner minimum).
+ * coordinates and per-unit-length resistance and capacitance along x and y,
+ * as rectilinear Steiner trees).  Per net, the shortest-path heuristic of
+ * Takahashi and Matsuyama (1980) in the rectilinear plane (pin 0 the driver,
+ * pins 1..k the sinks in net_sink_pin order): the tree starts as the driver's
+ * point; step t = 1..k joins the outside pin nearest to the tree's wires
+ * (FP32 Manhattan distance to the nearest point q_t of a wire, ties to the
+ * lower pin index; a pin's nearest wire changes only to a strictly nearer
+ * one) along an L: wire 2t-1 along x from q_t to the corner K_t = (x_pin,
+ * q_t.y), wire 2t along y from K_t to the pin.  Where q_t lies inside a wire
+ * the wire is split there (a Steiner point).  Net-local nodes: the driver 0,
+ * and per step the attach point S_t, the corner K_t and the pin; the points
+ * on a wire (its start, the S points attached to it, its end) form a chain
+ * ordered by distance from the start (ties by step), each the parent of the
+ * next.  Nodes are numbered wire by wire (0, 1, ..., 2k; the S points of a
+ * wire, then its end), so every parent precedes its child.  A node's R and C
+ * are the unit values of its wire's axis times the coordinate distance to its
+ * parent (FP32 products), its piece's capacitance lumped at the node; the
+ * driver's are 0.  A net of k sinks has 3k+1 nodes, net n starts at node
+ * n + 3 * net_sink_ptr[n], so the output is an sta_rc_desc of
+ * n_nets + 3 * n_sinks nodes, ready for sta_create.  Its wire length never
+ * exceeds the rectilinear minimum spanning tree's.  The paper builds the
+ * Steiner trees with FLUTE, whose lookup tables it does not give.
  *
  *   g          netlist (only n_pins, n_nets and the net CSR are read), host or
  *              device memory per g->mem
@@ -416,7 +422,7 @@ sta_status sta_report_paths(sta_ctx *ctx, const sta_path_query *q, int32_t *n_pa
  *              magnitude; `mem` memory
  *   w          unit wire values, finite and >= 0; host memory
  *   outputs    net_node_ptr [n_nets+1], parent / res_kohm / cap_ff
- *              [n_nets + 2 n_sinks], sink_node [n_sinks]; `mem` memory,
+ *              [n_nets + 3 n_sinks], sink_node [n_sinks]; `mem` memory,
  *              caller-allocated
  * Nets may have at most 12287 sinks (else STA_E_UNSUPPORTED).  Malformed
  * net CSR, a pin index out of range or a position out of range give
@@ -469,26 +475,28 @@ sta_status sta_estimate_rc_noalloc(const sta_graph_desc *g, const float *pin_x, 
                                    float *res_kohm, float *cap_ff, int32_t *sink_node, void *stream);
 
 /* Gradient to pin positions through estimated RC trees (the placement side
- * of §III "Parasitics (RC) inputs": with the trees of sta_estimate_rc held
- * fixed, each L-shaped edge from parent pin p to pin c sets R and C of its
- * corner node from |x_c - x_p| and of its pin node from |y_c - y_p|).  Given
- * dJ/dR and dJ/dC per node (e.g. grad_wire_res and grad_wire_cap of
- * sta_backward on a context created from those trees), writes
- *   dJ/dx_c += sgn(x_c - x_p) (r_x dJ/dR_corner + c_x dJ/dC_corner),
- *   dJ/dx_p -= the same,  and likewise along y with the pin node,
- * with sgn(0) = 0 (the zero subgradient of a segment of no length).  Pins on
+ * of §III "Parasitics (RC) inputs").  With the trees of sta_estimate_rc held
+ * fixed, every node coordinate is a copy of one pin's coordinate (a wire's
+ * nearest point clamps a coordinate to the wire's ends), so a node piece of
+ * length |c_u - c_w| along x (u the node, w its parent) gives, from dJ/dR and
+ * dJ/dC of the node (e.g. grad_wire_res and grad_wire_cap of sta_backward on
+ * a context created from those trees),
+ *   dJ/dx of c_u's pin += sgn(c_u - c_w) (r_x dJ/dR + c_x dJ/dC),
+ *   dJ/dx of c_w's pin -= the same,  and likewise along y,
+ * with sgn(0) = 0 (the zero subgradient of a piece of no length).  Pins on
  * no net get 0; a pin on several nets gets an unspecified one of them (the
  * netlists of sta_create have every pin on one net).
  *
  *   g, pin_x/y, w        as for sta_estimate_rc (same positions)
  *   parent, sink_node    the trees sta_estimate_rc wrote for them
- *   grad_res, grad_cap   [n_nets + 2 n_sinks] per node; `mem` memory
+ *   grad_res, grad_cap   [n_nets + 3 n_sinks] per node; `mem` memory
  *   grad_x, grad_y       [n_pins] outputs; `mem` memory
- * Terms are added in a fixed order (nets up to 64 pins, in FP32) or as
- * integers of 2^-48 of the net's largest term (larger nets), so results are
- * bitwise reproducible.  Errors as sta_estimate_rc, plus STA_E_ARG for a
- * sink_node or corner parent that no estimated tree has.  Allocates device
- * scratch; synchronizes `stream`. */
+ * The trees are rebuilt from the positions and compared with parent and
+ * sink_node: a difference gives STA_E_ARG (the outputs are then undefined).
+ * Terms are added as integers of 2^-44 of the net's largest term per axis,
+ * exact in any order, so results are bitwise reproducible.  Errors as
+ * sta_estimate_rc otherwise.  Allocates device scratch; synchronizes
+ * `stream`. */
 sta_status sta_estimate_rc_backward(const sta_graph_desc *g, const float *pin_x, const float *pin_y,
                                     const sta_wire_params *w, const int32_t *parent, const int32_t *sink_node,
                                     const float *grad_res, const float *grad_cap, float *grad_x, float *grad_y,

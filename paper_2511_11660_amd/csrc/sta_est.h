@@ -18,6 +18,14 @@ struct EstArgs {
   int32_t *parent;
   float *res, *cap;
   int32_t *sink_node;
+  // gradient mode (the trees rebuilt, checked and differentiated)
+  const int32_t *g_parent, *g_sink_node;  // the caller's trees (net n at node n + 3 sink_ptr[n])
+  const float *g_res, *g_cap;             // dJ/dR, dJ/dC per node
+  float *gx, *gy;                         // [n_pins] outputs (pins on no net untouched)
+  uint32_t *step_src;                     // [n_sinks] scratch: source pins of each step's attach point
+  uint32_t *err;                          // lowest net whose tree differs from the caller's (~0 when none)
+  unsigned long long *acc;                // integer accumulators of the nets above 64 pins
+  const int64_t *acc_off;                 // their offsets (pins), by position in the big list
 };
 // st[6] (caller-initialized to {0, 0, 0, ~0, ~0, ~0}): nets of 9..64 pins,
 // nets above 64 pins, their largest sink count, first bad net, first bad sink
@@ -39,27 +47,12 @@ hipError_t est_noalloc_scratch(int device, unsigned char **ptr);
 hipError_t launch_est(const EstArgs &A, const int32_t *mid, const int32_t *big, const uint32_t *st, uint32_t n_mid,
                       uint32_t n_big, hipStream_t s);
 
-// Gradient of an objective J with respect to pin positions, through the
-// estimated trees (same net CSR and positions as the estimation).
-struct EstGradArgs {
-  int n_nets;
-  const int32_t *driver, *sink_ptr, *sink_pin;
-  const float *x, *y;
-  float rx, ry, cx, cy;
-  const int32_t *parent, *sink_node;  // the estimated trees (net n at node n + 2 sink_ptr[n])
-  const float *g_res, *g_cap;         // dJ/dR, dJ/dC per node
-  float *gx, *gy;                     // [n_pins] outputs (pins on no net untouched)
-};
-// st[3] (caller-initialized to {0, 0, ~0}): nets of 9..64 pins, nets above
-// 64 pins, first sink with a bad tree entry; off[n_nets] / *total (zeroed by
-// the caller): accumulator offsets of the big nets and their sum
-hipError_t launch_estg_check(const EstGradArgs &G, int n_sinks, int32_t *mid, int32_t *big, int64_t *off,
-                             unsigned long long *total, uint32_t *st, hipStream_t s);
-// the sink checks of the nets above 64 pins (count read from st[1] on the
-// device), stream-ordered after launch_estg_check
-hipError_t launch_estg_check_big(const EstGradArgs &G, const int32_t *big, uint32_t *st, hipStream_t s);
-// acc: 2 * total zeroed int64 accumulators
-hipError_t launch_estg(const EstGradArgs &G, const int32_t *mid, const int32_t *big, const uint32_t *st,
-                       const int64_t *off, unsigned long long *acc, uint32_t n_mid, uint32_t n_big, hipStream_t s);
+// Gradient mode over the same net lists: off[b] / *total get the big nets'
+// accumulator offsets and their pin total (count read from st[1] on the
+// device); acc needs 2 * total zeroed words before launch_est_grad.
+hipError_t launch_est_acc_offsets(const EstArgs &A, const int32_t *big, const uint32_t *st, int64_t *off,
+                                  unsigned long long *total, hipStream_t s);
+hipError_t launch_est_grad(const EstArgs &A, const int32_t *mid, const int32_t *big, const uint32_t *st,
+                           uint32_t n_mid, uint32_t n_big, hipStream_t s);
 
 }  // namespace sta

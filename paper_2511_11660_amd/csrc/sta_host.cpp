@@ -1970,7 +1970,7 @@ extern "C" sta_status sta_estimate_rc(const sta_graph_desc *g, const float *pin_
   }
   if (n_sinks < 0) return fail(STA_E_ARG, "net_sink_ptr[n_nets] < 0");
   if (n_sinks > 0 && !g->net_sink_pin) return fail(STA_E_ARG, "NULL net_sink_pin");
-  const int64_t n_nodes = (int64_t)NN + 2 * (int64_t)n_sinks;
+  const int64_t n_nodes = (int64_t)NN + 3 * (int64_t)n_sinks;
   if (n_nodes > 0 && (!parent || !res_kohm || !cap_ff)) return fail(STA_E_ARG, "NULL RC output array");
   if (n_sinks > 0 && !sink_node) return fail(STA_E_ARG, "NULL sink_node");
   EstArgs A{};
@@ -2158,7 +2158,7 @@ extern "C" sta_status sta_estimate_rc_noalloc(const sta_graph_desc *g, const flo
   HIP_TRY(hipStreamSynchronize(s));
   if (n_sinks < 0) return fail(STA_E_ARG, "net_sink_ptr[n_nets] < 0");
   if (n_sinks > 0 && !g->net_sink_pin) return fail(STA_E_ARG, "NULL net_sink_pin");
-  const int64_t n_nodes = (int64_t)NN + 2 * (int64_t)n_sinks;
+  const int64_t n_nodes = (int64_t)NN + 3 * (int64_t)n_sinks;
   if (n_nodes > 0 && (!parent || !res_kohm || !cap_ff)) return fail(STA_E_ARG, "NULL RC output array");
   if (n_sinks > 0 && !sink_node) return fail(STA_E_ARG, "NULL sink_node");
   EstArgs A{};
@@ -2230,7 +2230,7 @@ extern "C" sta_status sta_estimate_rc_backward(const sta_graph_desc *g, const fl
   }
   if (n_sinks < 0) return fail(STA_E_ARG, "net_sink_ptr[n_nets] < 0");
   if (n_sinks > 0 && (!g->net_sink_pin || !sink_node)) return fail(STA_E_ARG, "NULL sink array");
-  const int64_t n_nodes = (int64_t)NN + 2 * (int64_t)n_sinks;
+  const int64_t n_nodes = (int64_t)NN + 3 * (int64_t)n_sinks;
   if (n_nodes > 0 && (!parent || !grad_res || !grad_cap)) return fail(STA_E_ARG, "NULL node array");
   auto up = [&](auto **dst, const auto *src, size_t n) -> sta_status {
     STA_TRY(tmp.alloc(dst, std::max<size_t>(n, 1)));
@@ -2238,12 +2238,11 @@ extern "C" sta_status sta_estimate_rc_backward(const sta_graph_desc *g, const fl
     return STA_OK;
   };
   EstArgs A{};
-  EstGradArgs G{};
-  A.n_nets = G.n_nets = NN;
-  A.rx = G.rx = w->r_x;
-  A.ry = G.ry = w->r_y;
-  A.cx = G.cx = w->c_x;
-  A.cy = G.cy = w->c_y;
+  A.n_nets = NN;
+  A.rx = w->r_x;
+  A.ry = w->r_y;
+  A.cx = w->c_x;
+  A.cy = w->c_y;
   if (g->mem == STA_HOST) {
     int32_t *d_drv, *d_nsp, *d_pin;
     STA_TRY(up(&d_drv, g->net_driver, (size_t)NN));
@@ -2257,9 +2256,6 @@ extern "C" sta_status sta_estimate_rc_backward(const sta_graph_desc *g, const fl
     A.sink_ptr = g->net_sink_ptr;
     A.sink_pin = g->net_sink_pin;
   }
-  G.driver = A.driver;
-  G.sink_ptr = A.sink_ptr;
-  G.sink_pin = A.sink_pin;
   if (mem == STA_HOST) {
     float *dx, *dy, *gr, *gc, *ox, *oy;
     int32_t *par, *snode;
@@ -2271,45 +2267,43 @@ extern "C" sta_status sta_estimate_rc_backward(const sta_graph_desc *g, const fl
     STA_TRY(up(&gc, grad_cap, (size_t)n_nodes));
     STA_TRY(tmp.alloc(&ox, (size_t)std::max(NP, 1)));
     STA_TRY(tmp.alloc(&oy, (size_t)std::max(NP, 1)));
-    A.x = G.x = dx;
-    A.y = G.y = dy;
-    G.parent = par;
-    G.sink_node = snode;
-    G.g_res = gr;
-    G.g_cap = gc;
-    G.gx = ox;
-    G.gy = oy;
+    A.x = dx;
+    A.y = dy;
+    A.g_parent = par;
+    A.g_sink_node = snode;
+    A.g_res = gr;
+    A.g_cap = gc;
+    A.gx = ox;
+    A.gy = oy;
   } else {
-    A.x = G.x = pin_x;
-    A.y = G.y = pin_y;
-    G.parent = parent;
-    G.sink_node = sink_node;
-    G.g_res = grad_res;
-    G.g_cap = grad_cap;
-    G.gx = grad_x;
-    G.gy = grad_y;
+    A.x = pin_x;
+    A.y = pin_y;
+    A.g_parent = parent;
+    A.g_sink_node = sink_node;
+    A.g_res = grad_res;
+    A.g_cap = grad_cap;
+    A.gx = grad_x;
+    A.gy = grad_y;
   }
   if (NP > 0) {
-    HIP_TRY(hipMemsetAsync(G.gx, 0, NP * sizeof(float), s));
-    HIP_TRY(hipMemsetAsync(G.gy, 0, NP * sizeof(float), s));
+    HIP_TRY(hipMemsetAsync(A.gx, 0, NP * sizeof(float), s));
+    HIP_TRY(hipMemsetAsync(A.gy, 0, NP * sizeof(float), s));
   }
-  // checks: net CSR and positions as for the estimation, then the tree arrays
-  int32_t *mid, *big, *mid2, *big2;
+  // checks of the net CSR and positions, as for the estimation
+  int32_t *mid, *big;
   int64_t *off;
   uint32_t *st;
   unsigned long long *total;
   STA_TRY(tmp.alloc(&mid, (size_t)NN));
   STA_TRY(tmp.alloc(&big, (size_t)NN));
-  STA_TRY(tmp.alloc(&mid2, (size_t)NN));
-  STA_TRY(tmp.alloc(&big2, (size_t)NN));
-  STA_TRY(tmp.alloc(&off, (size_t)NN));
-  STA_TRY(tmp.alloc(&st, 9));
+  STA_TRY(tmp.alloc(&off, (size_t)std::max(NN, 1)));
+  STA_TRY(tmp.alloc(&st, 7));
   STA_TRY(tmp.alloc(&total, 1));
-  const uint32_t st0[9] = {0u, 0u, 0u, ~0u, ~0u, ~0u, 0u, 0u, ~0u};
+  STA_TRY(tmp.alloc(&A.step_src, (size_t)std::max(n_sinks, 1)));
+  const uint32_t st0[7] = {0u, 0u, 0u, ~0u, ~0u, ~0u, ~0u};
   HIP_TRY(hipMemcpyAsync(st, st0, sizeof st0, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemsetAsync(total, 0, sizeof(unsigned long long), s));
   HIP_TRY(launch_est_check(A, NP, n_sinks, mid, big, st, s));
-  uint32_t h[9];
+  uint32_t h[7];
   HIP_TRY(hipMemcpyAsync(h, st, 6 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   if (h[3] != ~0u) return fail(STA_E_ARG, "net %u: bad net_sink_ptr or net_driver", h[3]);
@@ -2317,20 +2311,26 @@ extern "C" sta_status sta_estimate_rc_backward(const sta_graph_desc *g, const fl
   if (h[5] != ~0u) return fail(STA_E_ARG, "pin %u: position not finite or beyond 1e18 in magnitude", h[5]);
   if (h[1] > 0 && (int64_t)h[2] + 1 > kEstMaxPins)
     return fail(STA_E_UNSUPPORTED, "a net has %u sinks (at most %d)", h[2], kEstMaxPins - 1);
-  HIP_TRY(launch_estg_check(G, n_sinks, mid2, big2, off, total, st + 6, s));
-  HIP_TRY(launch_estg_check_big(G, big2, st + 6, s));
+  // the large nets' integer accumulators
   unsigned long long tot = 0;
-  HIP_TRY(hipMemcpyAsync(h + 6, st + 6, 3 * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipMemcpyAsync(&tot, total, sizeof tot, hipMemcpyDeviceToHost, s));
+  if (h[1] > 0) {
+    HIP_TRY(launch_est_acc_offsets(A, big, st, off, total, s));
+    HIP_TRY(hipMemcpyAsync(&tot, total, sizeof tot, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  STA_TRY(tmp.alloc(&A.acc, (size_t)std::max<unsigned long long>(2 * tot, 1)));
+  if (tot > 0) HIP_TRY(hipMemsetAsync(A.acc, 0, 2 * tot * sizeof(unsigned long long), s));
+  A.acc_off = off;
+  A.err = st + 6;
+  // the trees rebuilt from the positions, checked against the caller's, and differentiated
+  HIP_TRY(launch_est_grad(A, mid, big, st, h[0], h[1], s));
+  HIP_TRY(hipMemcpyAsync(h + 6, st + 6, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  if (h[8] != ~0u) return fail(STA_E_ARG, "sink %u: sink_node or its corner's parent is not an estimated tree", h[8]);
-  unsigned long long *acc;
-  STA_TRY(tmp.alloc(&acc, (size_t)std::max<unsigned long long>(2 * tot, 1)));
-  if (tot > 0) HIP_TRY(hipMemsetAsync(acc, 0, 2 * tot * sizeof(unsigned long long), s));
-  HIP_TRY(launch_estg(G, mid2, big2, st + 6, off, acc, h[6], h[7], s));
+  if (h[6] != ~0u)
+    return fail(STA_E_ARG, "net %u: parent / sink_node are not the trees these positions give", h[6]);
   if (mem == STA_HOST && NP > 0) {
-    HIP_TRY(hipMemcpyAsync(grad_x, G.gx, NP * sizeof(float), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(grad_y, G.gy, NP * sizeof(float), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(grad_x, A.gx, NP * sizeof(float), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(grad_y, A.gy, NP * sizeof(float), hipMemcpyDeviceToHost, s));
   }
   HIP_TRY(hipStreamSynchronize(s));
   return STA_OK;

@@ -1,35 +1,44 @@
 // RC trees estimated from pin positions (§III "Parasitics (RC) inputs": for
 // placement flows the timer builds each net's RC tree itself from pin positions
-// and unit resistance / capacitance along x and y).  Per net: a rectilinear
-// minimum spanning tree grown by Prim's rule from the driver (Manhattan
-// distances in FP32, ties to the lower pin index, a pin's parent the first
-// tree pin at its distance), each tree edge wired as an L: along x from the
-// parent to a corner node, then along y to the pin.  The t-th pin to join is
-// RC nodes 2t-1 (corner) and 2t (pin); R and C of a piece are the unit values
-// times its length, C lumped at the piece's far node.  A net of k sinks has
-// 2k + 1 nodes, so net n starts at node n + 2 * (sinks of nets before n).
+// and unit resistance / capacitance along x and y, as rectilinear Steiner
+// trees).  Per net, the shortest-path heuristic of Takahashi and Matsuyama
+// taken to the rectilinear plane: the tree starts as the driver's point; each
+// step t joins the pin nearest to the tree's wires (FP32 Manhattan distance to
+// the nearest point of a wire, ties to the lower pin index) along an L from
+// that point q_t: segment 2t-1 along x to the corner (x_j, q_t.y), segment 2t
+// along y to the pin.  A pin keeps its nearest distance, segment and point;
+// a new segment replaces them only if strictly nearer (2t-1 before 2t).
 //
-// Three kernels by net size, so that no pin waits on a slot it cannot use:
-//   k_est_lane    one lane per net of at most 8 pins: the whole Prim loop in
-//                 the lane's registers (most nets of a netlist)
-//   k_est_wave    one wavefront per net of 9..64 pins, one pin per lane: each
-//                 Prim step is a wave minimum of the distance bits, then of
-//                 the lane indices holding it (DPP row shifts and row
-//                 broadcasts, no LDS), no barrier
-//   k_est_block   one 1024-thread block per larger net (up to kEstMaxPins
-//                 pins, up to kEstPer per thread in registers, as many slots
-//                 as the net needs): per step a thread, wave and block
-//                 minimum, the 16 wave winners through double-buffered LDS
-//                 with one barrier, then one branch-free pass that relaxes
-//                 the distances and finds the next thread minimum; the RC
-//                 nodes are written once the tree is complete
+// RC nodes: the driver D and per step the attach point S_t, the corner K_t
+// and the pin J_t (3k + 1 per net of k sinks, so net n starts at node
+// n + 3 * sink_ptr[n]).  The points on a segment (its start, the S of every
+// later step attached to it, its end) form a chain by distance from the start,
+// ties by step, each the parent of the next.  Nodes are numbered segment by
+// segment (0, 1, ..., 2k), each segment's S points then its end: every start
+// lies on an earlier segment, so parents precede children, and each index is
+// closed-form from three counts per step (splits on the segments 0, 2t-1, 2t)
+// and the step's rank on its own segment.  A node's R and C are its axis's unit
+// values times the coordinate distance to its parent, C lumped at the node.
 //
-// A pin in the tree carries distance +inf; since positions are finite and
-// bounded (checked first), every pin outside the tree has a finite distance,
-// so the minimum never picks a tree pin.  In the lane and wave kernels a
-// pin's owner keeps, besides its position and distance, the position and RC
-// node of the tree pin that gives that distance, so the joining pin's owner
-// writes both of its RC nodes without asking anyone.
+// Three kernels by net size (each pin a thread):
+//   k_est_group<8>   one net of at most 8 pins per 8 lanes
+//   k_est_group<64>  one net of 9..64 pins per wavefront
+//   k_est_block      one 1024-thread block per larger net (up to kEstMaxPins
+//                    pins, up to kEstPer per thread in registers)
+// Each runs the join loop (a group minimum of the distance bits, then of the
+// pin indices holding it; the winner's attach point and position broadcast),
+// records every step (attach point, segment, pin) in LDS, and then numbers
+// and writes the nodes with one thread per step: a pass over the net's steps
+// gives each step its rank and chain neighbours, a prefix sum over steps the
+// segment offsets.
+//
+// The gradient mode (sta_estimate_rc_backward) rebuilds the trees the same
+// way, checks them against the caller's, and sends each node's dJ/dR and
+// dJ/dC to the two pins whose coordinates bound its piece: every node
+// coordinate is a copy of one pin's (a clamp picks one of its candidates), so
+// a piece |c_u - c_w| along x adds sgn(c_u - c_w) (r_x dJ/dR + c_x dJ/dC) to
+// dJ/dx of c_u's pin and the negative to c_w's.  Terms are summed as integers
+// (each rounded to 2^-44 of the net's largest term), exact in any order.
 #include <algorithm>
 #include <mutex>
 #include <vector>
@@ -43,13 +52,9 @@ namespace {
 
 constexpr float kFar = __builtin_inff();
 constexpr uint32_t kNone = 0xffffffffu;  // identity of the unsigned minimum
-constexpr int kLanePins = 8;            // largest net of k_est_lane
+constexpr int kLanePins = 8;            // largest net of k_est_group<8>
 constexpr int kEstPer = kEstMaxPins / 1024;  // pins per thread of k_est_block
 constexpr float kMaxCoord = 1e18f;      // |x|, |y| bound: every distance stays finite
-
-struct PinLoc {
-  float x, y;
-};
 
 __device__ __forceinline__ float manhattan(float ax, float ay, float bx, float by) {
   return fabsf(ax - bx) + fabsf(ay - by);
@@ -88,243 +93,702 @@ __device__ __forceinline__ float lane_float(float v, uint32_t lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), (int)lane));
 }
 
-// Both RC nodes of the t-th pin to join, from its parent's position and node.
-__device__ __forceinline__ void emit_pin(const EstArgs &A, int64_t base, int t, float x, float y, float px, float py,
-                                         int pnode) {
-  const float lx = fabsf(x - px), ly = fabsf(y - py);
-  const int64_t a = base + 2 * t - 1, b = a + 1;
-  A.parent[a] = pnode;
-  A.res[a] = A.rx * lx;
-  A.cap[a] = A.cx * lx;
-  A.parent[b] = 2 * t - 1;
-  A.res[b] = A.ry * ly;
-  A.cap[b] = A.cy * ly;
+// A pin's nearest point of the tree so far: distance, segment, the point and
+// the net-local pins its two coordinates are copied from.
+struct Near {
+  float d, qx, qy;
+  int seg, sqx, sqy;
+};
+
+// The step just made: its attach point (and sources), the joined pin's
+// position and net-local index.
+struct Join {
+  float qx, qy, xj, yj;
+  int sqx, sqy, j;
+};
+
+// The nearest point of [lo, hi] to v, and the pin it is copied from.
+__device__ __forceinline__ void clamp_src(float v, int sv, float a, int sa, float b, int sb, float &c, int &sc) {
+  const bool sw = b < a;
+  const float lo = sw ? b : a, hi = sw ? a : b;
+  const int slo = sw ? sb : sa, shi = sw ? sa : sb;
+  const bool below = v < lo, above = v > hi;  // both false for NaN: c = NaN
+  c = below ? lo : (above ? hi : v);
+  sc = below ? slo : (above ? shi : sv);
 }
 
-__device__ __forceinline__ void emit_root(const EstArgs &A, int n, int64_t base) {
-  A.parent[base] = -1;
-  A.res[base] = 0.0f;
-  A.cap[base] = 0.0f;
-  A.node_ptr[n + 1] = base + 2 * (int64_t)(A.sink_ptr[n + 1] - A.sink_ptr[n]) + 1;
-  if (n == 0) A.node_ptr[0] = 0;
+// Offer pin (x, y) = net-local `self` the two segments of step t; a pin in the
+// tree (or padding) carries x = NaN and never takes one.
+__device__ __forceinline__ void sph_relax(float x, float y, int self, Near &n, const Join &J, int t) {
+  float c;
+  int sc;
+  clamp_src(x, self, J.qx, J.sqx, J.xj, J.j, c, sc);  // segment 2t-1: y = qy, x from qx to x_j
+  float d = fabsf(x - c) + fabsf(y - J.qy);
+  if (d < n.d) {
+    n.d = d;
+    n.seg = 2 * t - 1;
+    n.qx = c;
+    n.qy = J.qy;
+    n.sqx = sc;
+    n.sqy = J.sqy;
+  }
+  clamp_src(y, self, J.qy, J.sqy, J.yj, J.j, c, sc);  // segment 2t: x = x_j, y from qy to y_j
+  d = fabsf(x - J.xj) + fabsf(y - c);
+  if (d < n.d) {
+    n.d = d;
+    n.seg = 2 * t;
+    n.qx = J.xj;
+    n.qy = c;
+    n.sqx = J.j;
+    n.sqy = sc;
+  }
 }
 
-// One lane per net of at most kLanePins pins (the rest return at once).
-__global__ __launch_bounds__(256) void k_est_lane(EstArgs A) {
-  const int n = blockIdx.x * 256 + threadIdx.x;
-  if (n >= A.n_nets) return;
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int G>
+__device__ __forceinline__ uint32_t group_min(uint32_t v) {
+  if constexpr (G == kWave) {
+    return wave_min(v);
+  } else {
+#pragma unroll
+    for (int m = 1; m < G; m <<= 1) v = min(v, (uint32_t)__shfl_xor((int)v, m, G));
+    return v;
+  }
+}
+
+template <int G>
+__device__ __forceinline__ int group_incl_scan(int v) {
+  const int lane = (int)(threadIdx.x % G);
+#pragma unroll
+  for (int o = 1; o < G; o <<= 1) {
+    const int y = __shfl_up(v, o, G);
+    v += lane >= o ? y : 0;
+  }
+  return v;
+}
+
+// Fixed-point exponent for terms of magnitude up to m: a pin receives at most
+// 2 (3 kEstMaxPins) < 2^17 terms, so 2^e m 2^17 stays below 2^62.
+__device__ __forceinline__ int fix_exp(double m) { return m > 0.0 ? 44 - ilogb(m) : 0; }
+
+__device__ __forceinline__ long long to_fixed(double v, int e) { return __double2ll_rn(ldexp(v, e)); }
+
+__device__ __forceinline__ double sgn_d(float v) { return v > 0.0f ? 1.0 : (v < 0.0f ? -1.0 : 0.0); }
+
+// One net of at most G pins, a pin per lane of its group (G = 8: eight nets
+// per wavefront; G = 64: one).  Nets come from list[0 .. *count) or, with no
+// list, every net of at most G pins (the rest are skipped).
+template <int G, bool kGrad>
+__global__ __launch_bounds__(256) void k_est_group(EstArgs A, const int32_t *list, const uint32_t *count) {
+  constexpr int NG = 256 / G;
+  __shared__ float s_qx[NG][G], s_qy[NG][G], s_key[NG][G];
+  __shared__ int32_t s_rec[NG][G];                             // segment | pin << 16, by step
+  __shared__ uint32_t s_src[kGrad ? NG : 1][kGrad ? G : 1];    // source pins of q (x | y << 16), by step
+  __shared__ unsigned long long s_acc[kGrad ? NG : 1][kGrad ? 2 * G : 1];
+  const int grp = (int)(threadIdx.x / G), lane = (int)(threadIdx.x % G);
+  const int w = (int)blockIdx.x * NG + grp;
+  int n;
+  if (list) {
+    if (w >= (int)*count) return;
+    n = list[w];
+  } else {
+    if (w >= A.n_nets) return;
+    n = w;
+  }
   const int s0 = A.sink_ptr[n], k = A.sink_ptr[n + 1] - s0;
-  if (k + 1 > kLanePins) return;
-  const int64_t base = (int64_t)n + 2 * (int64_t)s0;
-  const int drv = A.driver[n];
-  float x[kLanePins], y[kLanePins], dist[kLanePins], px[kLanePins], py[kLanePins];
-  int pnode[kLanePins];
-#pragma unroll
-  for (int u = 0; u < kLanePins; ++u) {
-    const int pin = (u >= 1 && u <= k) ? A.sink_pin[s0 + u - 1] : drv;
-    x[u] = A.x[pin];
-    y[u] = A.y[pin];
-  }
-#pragma unroll
-  for (int u = 0; u < kLanePins; ++u) {
-    dist[u] = (u >= 1 && u <= k) ? manhattan(x[u], y[u], x[0], y[0]) : kFar;
-    px[u] = x[0];
-    py[u] = y[0];
-    pnode[u] = 0;
-  }
-  emit_root(A, n, base);
-  for (int t = 1; t <= k; ++t) {
-    float best = kFar;
-    int j = 0;
-#pragma unroll
-    for (int u = 1; u < kLanePins; ++u)  // ascending u: the first minimum wins ties
-      if (dist[u] < best) {
-        best = dist[u];
-        j = u;
-      }
-    float xj = x[1], yj = y[1], pxj = px[1], pyj = py[1];
-    int pnj = pnode[1];
-#pragma unroll
-    for (int u = 2; u < kLanePins; ++u)
-      if (u == j) {
-        xj = x[u];
-        yj = y[u];
-        pxj = px[u];
-        pyj = py[u];
-        pnj = pnode[u];
-      }
-    emit_pin(A, base, t, xj, yj, pxj, pyj, pnj);
-    A.sink_node[s0 + j - 1] = 2 * t;
-#pragma unroll
-    for (int u = 1; u < kLanePins; ++u) {
-      if (u == j) {
-        dist[u] = kFar;
-      } else if (dist[u] < kFar) {
-        const float d = manhattan(x[u], y[u], xj, yj);
-        if (d < dist[u]) {
-          dist[u] = d;
-          px[u] = xj;
-          py[u] = yj;
-          pnode[u] = 2 * t;
-        }
-      }
-    }
-  }
-}
-
-// One wavefront per net of list[0 .. *count).
-__global__ __launch_bounds__(256) void k_est_wave(EstArgs A, const int32_t *list, const uint32_t *count) {
-  const int w = blockIdx.x * (256 / kWave) + (int)(threadIdx.x / kWave);
-  if (w >= (int)*count) return;
-  const int n = list[w];
-  const int lane = threadIdx.x & (kWave - 1);
-  const int s0 = A.sink_ptr[n], k = A.sink_ptr[n + 1] - s0;
-  const int64_t base = (int64_t)n + 2 * (int64_t)s0;
+  if (k + 1 > G) return;  // the whole group leaves together
+  const int64_t base = (int64_t)n + 3 * (int64_t)s0;
   const bool valid = lane <= k;
-  const int pin = (lane == 0 || !valid) ? A.driver[n] : A.sink_pin[s0 + lane - 1];
-  const float x = A.x[pin], y = A.y[pin];
-  const float x0 = lane_float(x, 0), y0 = lane_float(y, 0);
-  float dist = (valid && lane > 0) ? manhattan(x, y, x0, y0) : kFar;
-  float px = x0, py = y0;
-  int pnode = 0;
-  if (lane == 0) emit_root(A, n, base);
+  const int drv = A.driver[n];
+  const int pin = (lane >= 1 && valid) ? A.sink_pin[s0 + lane - 1] : drv;
+  const float px = A.x[pin], py = A.y[pin];  // this lane's pin (the driver for lane 0 and padding)
+  const float x0 = A.x[drv], y0 = A.y[drv];
+  const float kNaN = __builtin_nanf("");
+  const bool live0 = valid && lane > 0;
+  float x = live0 ? px : kNaN, y = live0 ? py : kNaN;
+  Near nr{live0 ? manhattan(px, py, x0, y0) : kFar, x0, y0, 0, 0, 0};
   for (int t = 1; t <= k; ++t) {
-    const uint32_t kmin = wave_min(key_of(dist));
-    const uint32_t j = wave_min(key_of(dist) == kmin ? (uint32_t)lane : kNone);
-    const float xj = lane_float(x, j), yj = lane_float(y, j);
-    if (lane == (int)j) {
-      emit_pin(A, base, t, x, y, px, py, pnode);
-      A.sink_node[s0 + j - 1] = 2 * t;
-      dist = kFar;
-    } else if (dist < kFar) {
-      const float d = manhattan(x, y, xj, yj);
-      if (d < dist) {
-        dist = d;
-        px = xj;
-        py = yj;
-        pnode = 2 * t;
-      }
+    const uint32_t kmin = group_min<G>(key_of(nr.d));
+    const int j = (int)group_min<G>(key_of(nr.d) == kmin ? (uint32_t)lane : kNone);
+    Join J;
+    J.qx = __shfl(nr.qx, j, G);
+    J.qy = __shfl(nr.qy, j, G);
+    J.sqx = __shfl(nr.sqx, j, G);
+    J.sqy = __shfl(nr.sqy, j, G);
+    J.xj = __shfl(px, j, G);
+    J.yj = __shfl(py, j, G);
+    J.j = j;
+    if (lane == j) {
+      s_qx[grp][t] = nr.qx;
+      s_qy[grp][t] = nr.qy;
+      s_rec[grp][t] = nr.seg | (j << 16);
+      if constexpr (kGrad) s_src[grp][t] = (uint32_t)nr.sqx | ((uint32_t)nr.sqy << 16);
+      x = kNaN;
+      nr.d = kFar;
+    } else {
+      sph_relax(x, y, lane, nr, J, t);
     }
   }
+  wave_sync();
+  // ---- numbering: lane t handles step t
+  const int t = lane;
+  const bool act = t >= 1 && t <= k;
+  const int rec = act ? s_rec[grp][t] : 0;
+  // every step wrote its record; the clamps only keep each index in range
+  const int sg = min(rec & 0xffff, max(2 * (t - 1), 0)), jt = act ? min(max(rec >> 16, 1), k) : 0;
+  const float qx = act ? s_qx[grp][t] : 0.0f, qy = act ? s_qy[grp][t] : 0.0f;
+  const float xj = __shfl(px, jt, G), yj = __shfl(py, jt, G);
+  const int sc = (sg + 1) >> 1;  // the step that made segment sg (sg >= 1)
+  const bool axy = sg != 0 && (sg & 1) == 0;
+  const int js = sg != 0 ? min(s_rec[grp][sc] >> 16, k) : 0;
+  const float pxs = __shfl(px, js, G), pys = __shfl(py, js, G);
+  const float c0 = sg == 0 ? x0 : (axy ? s_qy[grp][sc] : s_qx[grp][sc]);  // start of segment sg along its axis
+  const float cend = sg == 0 ? x0 : (axy ? pys : pxs);
+  const float dir = cend < c0 ? -1.0f : 1.0f;
+  const float c = axy ? qy : qx;  // S_t along its segment's axis
+  const float key = dir * c;      // exact: distance order from the start
+  const float dirA = xj < qx ? -1.0f : 1.0f, dirB = yj < qy ? -1.0f : 1.0f;
+  if (act) s_key[grp][t] = key;
+  wave_sync();
+  int rank = 0, m0 = 0, mA = 0, mB = 0, predt = 0, bestAt = 0, bestBt = 0;
+  float predk = 0.0f, bestA = 0.0f, bestB = 0.0f;
+  for (int u = 1; u <= k; ++u) {  // ascending steps: ties in key go to the later step
+    const int su = s_rec[grp][u] & 0xffff;
+    const float ku = s_key[grp][u];
+    m0 += su == 0 ? 1 : 0;
+    if (su == sg && (ku < key || (ku == key && u < t))) {
+      if (rank == 0 || ku >= predk) {
+        predk = ku;
+        predt = u;
+      }
+      ++rank;
+    }
+    if (su == 2 * t - 1) {
+      if (mA == 0 || ku >= bestA) {
+        bestA = ku;
+        bestAt = u;
+      }
+      ++mA;
+    }
+    if (su == 2 * t && t > 0) {
+      if (mB == 0 || ku >= bestB) {
+        bestB = ku;
+        bestBt = u;
+      }
+      ++mB;
+    }
+  }
+  const int wv = act ? mA + mB + 2 : 0;
+  const int W = group_incl_scan<G>(wv);
+  const int offA = m0 + 1 + W - wv;  // first node of segment 2t-1
+  const int idxK = offA + mA;        // K_t closes segment 2t-1
+  const int idxJ = idxK + 1 + mB;    // J_t closes segment 2t
+  const int offA_s = __shfl(offA, sc, G), idxK_s = __shfl(idxK, sc, G);
+  const int offsg = sg == 0 ? 0 : ((sg & 1) ? offA_s : idxK_s + 1);
+  const int idxS = offsg + (sg == 0 ? 1 : 0) + rank;
+  const int idxS_s = __shfl(idxS, sc, G);
+  const int pS = rank > 0 ? idxS - 1 : (sg == 0 ? 0 : ((sg & 1) ? idxS_s : idxK_s));
+  const int pK = mA > 0 ? idxK - 1 : idxS;
+  const int pJ = mB > 0 ? idxJ - 1 : idxK;
+  const float cpS = rank > 0 ? dir * predk : c0;
+  const float cpK = mA > 0 ? dirA * bestA : qx;
+  const float cpJ = mB > 0 ? dirB * bestB : qy;
+  const float LS = fabsf(c - cpS), LK = fabsf(xj - cpK), LJ = fabsf(yj - cpJ);
+  const float ra = axy ? A.ry : A.rx, ca = axy ? A.cy : A.cx;
+  const bool inr = act && idxS >= 1 && idxK >= 1 && idxJ <= 3 * k && idxS <= 3 * k && idxK <= 3 * k;
+  if constexpr (!kGrad) {
+    if (inr) {
+      A.parent[base + idxS] = pS;
+      A.res[base + idxS] = ra * LS;
+      A.cap[base + idxS] = ca * LS;
+      A.parent[base + idxK] = pK;
+      A.res[base + idxK] = A.rx * LK;
+      A.cap[base + idxK] = A.cx * LK;
+      A.parent[base + idxJ] = pJ;
+      A.res[base + idxJ] = A.ry * LJ;
+      A.cap[base + idxJ] = A.cy * LJ;
+      A.sink_node[s0 + jt - 1] = idxJ;
+    }
+    if (lane == 0) {
+      A.parent[base] = -1;
+      A.res[base] = 0.0f;
+      A.cap[base] = 0.0f;
+      A.node_ptr[n + 1] = base + 3 * (int64_t)k + 1;
+      if (n == 0) A.node_ptr[0] = 0;
+    }
+  } else {
+    // the caller's trees must be these
+    const bool bad = act && (!inr || A.g_parent[base + idxS] != pS || A.g_parent[base + idxK] != pK ||
+                             A.g_parent[base + idxJ] != pJ || A.g_sink_node[s0 + jt - 1] != idxJ);
+    if (bad) atomicMin(A.err, (uint32_t)n);
+    // the pins bounding each piece along its axis
+    const uint32_t my = act ? s_src[grp][t] : 0u;
+    const int mx_ = (int)(my & 0xffff), my_ = (int)(my >> 16);
+    const uint32_t pr = s_src[grp][rank > 0 ? predt : (sg == 0 ? 0 : sc)];
+    const int uS = axy ? my_ : mx_;
+    const int wS = sg == 0 ? 0 : (axy ? (int)(pr >> 16) : (int)(pr & 0xffff));
+    const int wK = mA > 0 ? (int)(s_src[grp][bestAt] & 0xffff) : mx_;
+    const int wJ = mB > 0 ? (int)(s_src[grp][bestBt] >> 16) : my_;
+    double vS = 0.0, vK = 0.0, vJ = 0.0;
+    if (inr) {
+      vS = sgn_d(c - cpS) * ((double)ra * A.g_res[base + idxS] + (double)ca * A.g_cap[base + idxS]);
+      vK = sgn_d(xj - cpK) * ((double)A.rx * A.g_res[base + idxK] + (double)A.cx * A.g_cap[base + idxK]);
+      vJ = sgn_d(yj - cpJ) * ((double)A.ry * A.g_res[base + idxJ] + (double)A.cy * A.g_cap[base + idxJ]);
+    }
+    // largest term per axis over the net, as the bits of a non-negative float
+    const float mxf = (float)fmax(axy ? 0.0 : fabs(vS), fabs(vK));
+    const float myf = (float)fmax(axy ? fabs(vS) : 0.0, fabs(vJ));
+    const uint32_t bx = kNone - group_min<G>(kNone - __float_as_uint(mxf));
+    const uint32_t by = kNone - group_min<G>(kNone - __float_as_uint(myf));
+    // rounding up to float only raises the exponent by at most one: still in range
+    const int ex = fix_exp((double)__uint_as_float(bx)), ey = fix_exp((double)__uint_as_float(by));
+    s_acc[grp][2 * lane] = 0ull;
+    s_acc[grp][2 * lane + 1] = 0ull;
+    wave_sync();
+    if (inr) {
+      const int eS = axy ? ey : ex, oS = axy ? 1 : 0;
+      const long long iS = to_fixed(vS, eS), iK = to_fixed(vK, ex), iJ = to_fixed(vJ, ey);
+      atomicAdd(&s_acc[grp][2 * uS + oS], (unsigned long long)iS);
+      atomicAdd(&s_acc[grp][2 * wS + oS], (unsigned long long)(-iS));
+      atomicAdd(&s_acc[grp][2 * jt], (unsigned long long)iK);
+      atomicAdd(&s_acc[grp][2 * wK], (unsigned long long)(-iK));
+      atomicAdd(&s_acc[grp][2 * jt + 1], (unsigned long long)iJ);
+      atomicAdd(&s_acc[grp][2 * wJ + 1], (unsigned long long)(-iJ));
+    }
+    wave_sync();
+    if (valid) {
+      A.gx[pin] = (float)ldexp((double)(long long)s_acc[grp][2 * lane], -ex);
+      A.gy[pin] = (float)ldexp((double)(long long)s_acc[grp][2 * lane + 1], -ey);
+    }
+  }
+}
+
+// Exclusive prefix of c over a 1024-thread block; *total gets the block's
+// sum.  Every thread calls it; s_w (16 words) is free again on return.
+__device__ __forceinline__ uint32_t block_excl_scan1024(uint32_t c, uint32_t *s_w, uint32_t *total) {
+  const int lane = (int)(threadIdx.x & (kWave - 1)), wave = (int)(threadIdx.x / kWave);
+  int v = (int)c;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int y = __shfl_up(v, o, kWave);
+    v += lane >= o ? y : 0;
+  }
+  if (lane == kWave - 1) s_w[wave] = (uint32_t)v;
+  __syncthreads();
+  uint32_t off = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < 1024 / kWave; ++w) {
+    off += w < wave ? s_w[w] : 0u;
+    tot += s_w[w];
+  }
+  __syncthreads();
+  *total = tot;
+  return off + (uint32_t)v - c;
 }
 
 // One net of k_est_block with NL live register slots per thread (pin
-// l = tid + 1024 u, u < NL).  Per step only distances and parent nodes move;
-// the RC nodes are written after the last step, when every pin knows its join
-// step and its parent's node (the parent's pin comes from the join table).
-// Every pin's position is also kept in LDS, where each step reads the joining
-// pin's (a per-slot select of the candidate's position would cost three more
-// instructions per slot and step).
-template <int NL>
-__device__ __forceinline__ void est_block_net(const EstArgs &A, int n, int s0, int k, int64_t base,
+// l = tid + 1024 u, u < NL); step t is handled by thread (t - 1) % 1024 in
+// slot (t - 1) / 1024 once the joins are done.  LDS per step: the attach
+// point (later the step's key, then its segment offsets) and the segment |
+// pin record (later the index of its S node).
+template <int NL, bool kGrad>
+__device__ __forceinline__ void est_block_net(const EstArgs &A, int n, int s0, int k, int64_t base, int b,
                                               uint32_t (*s_key)[1024 / kWave], uint32_t (*s_idx)[1024 / kWave],
-                                              PinLoc *s_pos, uint16_t *s_join) {
-  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-  const float x0 = A.x[A.driver[n]], y0 = A.y[A.driver[n]];
+                                              float (*s_win)[1024 / kWave][6], float2 *s_q, int32_t *s_rec,
+                                              uint32_t *s_w) {
+  const int tid = (int)threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+  const int drv = A.driver[n];
+  const float x0 = A.x[drv], y0 = A.y[drv];
   const float kNaN = __builtin_nanf("");
-  float x[NL], y[NL], dist[NL];
-  int pnode[NL], tj[NL];
+  float x[NL], y[NL];
+  Near nr[NL];
   float key = kFar;
   int ul = 0;
 #pragma unroll
   for (int u = 0; u < NL; ++u) {
     const int l = tid + u * 1024;  // pin index in the net: 0 driver, 1..k sinks
-    const bool valid = l >= 1 && l <= k;
-    const int pin = A.sink_pin[s0 + (valid ? l - 1 : 0)];
-    x[u] = valid ? A.x[pin] : kNaN;  // NaN: never nearer than anything
-    y[u] = valid ? A.y[pin] : kNaN;
-    if (valid) s_pos[l] = PinLoc{x[u], y[u]};
-    dist[u] = valid ? manhattan(x[u], y[u], x0, y0) : kFar;
-    pnode[u] = 0;
-    tj[u] = 0;
-    const bool b = dist[u] < key;  // ascending l: the first minimum wins ties
-    key = b ? dist[u] : key;
-    ul = b ? u : ul;
+    const bool live = l >= 1 && l <= k;
+    const int pin = A.sink_pin[s0 + (live ? l - 1 : 0)];
+    x[u] = live ? A.x[pin] : kNaN;  // NaN: never nearer than anything
+    y[u] = live ? A.y[pin] : kNaN;
+    nr[u] = Near{live ? manhattan(x[u], y[u], x0, y0) : kFar, x0, y0, 0, 0, 0};
+    const bool bt = nr[u].d < key;  // ascending l: the first minimum wins ties
+    key = bt ? nr[u].d : key;
+    ul = bt ? u : ul;
   }
-  __syncthreads();  // s_pos complete
   for (int t = 1; t <= k; ++t) {
     const uint32_t wk = wave_min(key_of(key));
     const uint32_t wi = wave_min(key_of(key) == wk && key < kFar ? (uint32_t)(tid + ul * 1024) : kNone);
     const int buf = t & 1;
+    // the wave's winner publishes its attach point and position
+    if (wi != kNone && (int)(wi & 1023) == tid) {
+      float wqx = 0.0f, wqy = 0.0f, wx = 0.0f, wy = 0.0f;
+      int wsx = 0, wsy = 0;
+#pragma unroll
+      for (int u = 0; u < NL; ++u)
+        if (u == ul) {
+          wqx = nr[u].qx;
+          wqy = nr[u].qy;
+          wsx = nr[u].sqx;
+          wsy = nr[u].sqy;
+          wx = x[u];
+          wy = y[u];
+        }
+      s_win[buf][wave][0] = wqx;
+      s_win[buf][wave][1] = wqy;
+      s_win[buf][wave][2] = wx;
+      s_win[buf][wave][3] = wy;
+      if constexpr (kGrad) {
+        s_win[buf][wave][4] = __int_as_float(wsx);
+        s_win[buf][wave][5] = __int_as_float(wsy);
+      }
+    }
     if (lane == 0) {
       s_key[buf][wave] = wk;
       s_idx[buf][wave] = wi;
     }
     __syncthreads();
-    // the 16 wave winners, one per lane of each row: row minima by DPP, so
-    // the reduction costs every wave a few vector instructions; every row
-    // holds all 16, so the result is the same in every lane
     const int e = lane & (1024 / kWave - 1);
     const uint32_t ek = s_key[buf][e], ei = s_idx[buf][e];
     const uint32_t bk = row_min16(ek);
     const uint32_t bi = row_min16(ek == bk ? ei : kNone);
     const int j = (int)__builtin_amdgcn_readfirstlane((int)bi);  // a pin outside the tree is left
-    const PinLoc pj = s_pos[j];
-    const float xj = pj.x, yj = pj.y;
-    const int ju = j >> 10;
-    if (tid == (j & 1023)) {  // the joining pin leaves the candidates
-#pragma unroll
-      for (int u = 0; u < NL; ++u)
-        if (u == ju) {
-          x[u] = kNaN;
-          dist[u] = kFar;
-          tj[u] = t;
-        }
-    }
-    if (tid == 0) s_join[t] = (uint16_t)j;
+    const int jw = (j & 1023) / kWave, ju = j >> 10;
+    Join J;
+    J.qx = s_win[buf][jw][0];
+    J.qy = s_win[buf][jw][1];
+    J.xj = s_win[buf][jw][2];
+    J.yj = s_win[buf][jw][3];
+    J.sqx = kGrad ? __float_as_int(s_win[buf][jw][4]) : 0;
+    J.sqy = kGrad ? __float_as_int(s_win[buf][jw][5]) : 0;
+    J.j = j;
     key = kFar;
     ul = 0;
 #pragma unroll
     for (int u = 0; u < NL; ++u) {
-      const float d = manhattan(x[u], y[u], xj, yj);  // NaN for tree and padding pins
-      const bool up = d < dist[u];
-      dist[u] = up ? d : dist[u];
-      pnode[u] = up ? 2 * t : pnode[u];
-      const bool b = dist[u] < key;
-      key = b ? dist[u] : key;
-      ul = b ? u : ul;
+      if (tid == (j & 1023) && u == ju) {  // the joining pin records its step and leaves the candidates
+        s_q[t] = make_float2(nr[u].qx, nr[u].qy);
+        s_rec[t] = nr[u].seg | (j << 16);
+        if constexpr (kGrad) A.step_src[s0 + t - 1] = (uint32_t)nr[u].sqx | ((uint32_t)nr[u].sqy << 16);
+        x[u] = kNaN;
+        nr[u].d = kFar;
+      } else {
+        sph_relax(x[u], y[u], tid + u * 1024, nr[u], J, t);
+      }
+      const bool bt = nr[u].d < key;
+      key = bt ? nr[u].d : key;
+      ul = bt ? u : ul;
     }
   }
-  __syncthreads();  // s_join complete
+  __syncthreads();  // every step recorded (and its sources written)
+  auto pos_of = [&](int l, float &px, float &py) {
+    const int p = l == 0 ? drv : A.sink_pin[s0 + l - 1];
+    px = A.x[p];
+    py = A.y[p];
+  };
+  // ---- pass 1: each step's key (distance order on its segment) and the
+  // segment's start and direction
+  float kq[NL], dirr[NL], c0r[NL], cr[NL];
 #pragma unroll
   for (int u = 0; u < NL; ++u) {
-    const int l = tid + u * 1024;
-    if (l >= 1 && l <= k) {
-      const int pin = A.sink_pin[s0 + l - 1];
-      const int lp = pnode[u] == 0 ? 0 : (int)s_join[pnode[u] / 2];
-      const int ppin = lp == 0 ? A.driver[n] : A.sink_pin[s0 + lp - 1];
-      emit_pin(A, base, tj[u], A.x[pin], A.y[pin], A.x[ppin], A.y[ppin], pnode[u]);
-      A.sink_node[s0 + l - 1] = 2 * tj[u];
+    const int t = tid + 1 + u * 1024;
+    kq[u] = c0r[u] = cr[u] = 0.0f;
+    dirr[u] = 1.0f;
+    if (t <= k) {
+      // every step wrote its record; the clamps only keep each index in range
+      const int sg = min(s_rec[t] & 0xffff, 2 * (t - 1)), sc = (sg + 1) >> 1;
+      const bool axy = sg != 0 && (sg & 1) == 0;
+      float c0 = x0, cend = x0;
+      if (sg != 0) {
+        float pxs, pys;
+        pos_of(min(max(s_rec[sc] >> 16, 1), k), pxs, pys);
+        c0 = axy ? s_q[sc].y : s_q[sc].x;
+        cend = axy ? pys : pxs;
+      }
+      dirr[u] = cend < c0 ? -1.0f : 1.0f;
+      cr[u] = axy ? s_q[t].y : s_q[t].x;
+      kq[u] = dirr[u] * cr[u];
+      c0r[u] = c0;
     }
   }
-  if (tid == 0) emit_root(A, n, base);
+  __syncthreads();
+  // the key replaces the attach point's x; the own point's coordinates are
+  // kept for the corner and pin pieces
+  float qxr[NL], qyr[NL];
+#pragma unroll
+  for (int u = 0; u < NL; ++u) {
+    const int t = tid + 1 + u * 1024;
+    qxr[u] = qyr[u] = 0.0f;
+    if (t <= k) {
+      qxr[u] = s_q[t].x;
+      qyr[u] = s_q[t].y;
+      s_q[t].x = kq[u];
+    }
+  }
+  __syncthreads();
+  // ---- pass 2: rank on the own segment (and the predecessor), the splits
+  // on segments 0, 2t-1 and 2t (and the last of each), then the coordinates
+  // of the three parents
+  int rank[NL], mA[NL], mB[NL], predt[NL], bestAt[NL], bestBt[NL];
+  float cpS[NL], cpK[NL], cpJ[NL];
+  int m0 = 0;
+#pragma unroll
+  for (int u = 0; u < NL; ++u) {
+    const int t = tid + 1 + u * 1024;
+    const int sg = t <= k ? min(s_rec[t] & 0xffff, 2 * (t - 1)) : -1;
+    const float kt = kq[u];
+    int rk = 0, ma = 0, mb = 0, pt = 0, at = 0, bt = 0, z = 0;
+    float pk = 0.0f, ak = 0.0f, bk = 0.0f;
+    for (int v = 1; v <= k; ++v) {  // ascending steps: ties in key go to the later step
+      const int sv = s_rec[v] & 0xffff;
+      const float kv = s_q[v].x;
+      z += sv == 0 ? 1 : 0;
+      if (sv == sg && (kv < kt || (kv == kt && v < t))) {
+        if (rk == 0 || kv >= pk) {
+          pk = kv;
+          pt = v;
+        }
+        ++rk;
+      }
+      if (sv == 2 * t - 1) {
+        if (ma == 0 || kv >= ak) {
+          ak = kv;
+          at = v;
+        }
+        ++ma;
+      }
+      if (sv == 2 * t) {
+        if (mb == 0 || kv >= bk) {
+          bk = kv;
+          bt = v;
+        }
+        ++mb;
+      }
+    }
+    m0 = z;
+    rank[u] = rk;
+    mA[u] = ma;
+    mB[u] = mb;
+    predt[u] = pt;
+    bestAt[u] = at;
+    bestBt[u] = bt;
+    float xj = 0.0f, yj = 0.0f;
+    if (t <= k) pos_of(min(max(s_rec[t] >> 16, 1), k), xj, yj);
+    const float dirA = xj < qxr[u] ? -1.0f : 1.0f, dirB = yj < qyr[u] ? -1.0f : 1.0f;
+    cpS[u] = rk > 0 ? dirr[u] * pk : c0r[u];
+    cpK[u] = ma > 0 ? dirA * ak : qxr[u];
+    cpJ[u] = mb > 0 ? dirB * bk : qyr[u];
+  }
+  __syncthreads();
+  // ---- offsets: an exclusive prefix over steps of (splits on 2t-1 and 2t) + 2
+  int offA[NL];
+  uint32_t carry = (uint32_t)m0 + 1u;
+#pragma unroll
+  for (int u = 0; u < NL; ++u) {
+    const int t = tid + 1 + u * 1024;
+    const uint32_t wv = t <= k ? (uint32_t)(mA[u] + mB[u] + 2) : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan1024(wv, s_w, &tot);
+    offA[u] = (int)(carry + ex);
+    carry += tot;
+  }
+  // publish (offset of segment 2t-1, index of K_t) per step in place of the key
+#pragma unroll
+  for (int u = 0; u < NL; ++u) {
+    const int t = tid + 1 + u * 1024;
+    if (t <= k) s_q[t] = make_float2(__int_as_float(offA[u]), __int_as_float(offA[u] + mA[u]));
+  }
+  __syncthreads();
+  int idxS[NL], jtr[NL], sgr[NL];
+#pragma unroll
+  for (int u = 0; u < NL; ++u) {
+    const int t = tid + 1 + u * 1024;
+    idxS[u] = jtr[u] = sgr[u] = 0;
+    if (t <= k) {
+      const int rec = s_rec[t], sg = min(rec & 0xffff, 2 * (t - 1)), sc = (sg + 1) >> 1;
+      jtr[u] = min(max(rec >> 16, 1), k);
+      sgr[u] = sg;
+      const int offsg = sg == 0 ? 0 : ((sg & 1) ? __float_as_int(s_q[sc].x) : __float_as_int(s_q[sc].y) + 1);
+      idxS[u] = offsg + (sg == 0 ? 1 : 0) + rank[u];
+    }
+  }
+  __syncthreads();  // every step has read the records it needs
+#pragma unroll
+  for (int u = 0; u < NL; ++u) {
+    const int t = tid + 1 + u * 1024;
+    if (t <= k) s_rec[t] = idxS[u];  // the index of S_t replaces the record
+  }
+  __syncthreads();
+  // ---- the nodes
+  double mxd = 0.0, myd = 0.0;
+  double vS[kGrad ? NL : 1], vK[kGrad ? NL : 1], vJ[kGrad ? NL : 1];
+  int uS[kGrad ? NL : 1], wS[kGrad ? NL : 1], wK[kGrad ? NL : 1], wJ[kGrad ? NL : 1];
+#pragma unroll
+  for (int u = 0; u < NL; ++u) {
+    const int t = tid + 1 + u * 1024;
+    if constexpr (kGrad) {
+      vS[u] = vK[u] = vJ[u] = 0.0;
+      uS[u] = wS[u] = wK[u] = wJ[u] = 0;
+    }
+    if (t > k) continue;
+    const int sg = sgr[u], sc = (sg + 1) >> 1;
+    const bool axy = sg != 0 && (sg & 1) == 0;
+    const int idxK = offA[u] + mA[u], idxJ = idxK + 1 + mB[u];
+    const int idxS_s = sg == 0 ? 0 : s_rec[sc];
+    const int idxK_s = sg == 0 ? 0 : __float_as_int(s_q[sc].y);
+    const int pS = rank[u] > 0 ? idxS[u] - 1 : (sg == 0 ? 0 : ((sg & 1) ? idxS_s : idxK_s));
+    const int pK = mA[u] > 0 ? idxK - 1 : idxS[u];
+    const int pJ = mB[u] > 0 ? idxJ - 1 : idxK;
+    float xj, yj;
+    pos_of(jtr[u], xj, yj);
+    const float LS = fabsf(cr[u] - cpS[u]), LK = fabsf(xj - cpK[u]), LJ = fabsf(yj - cpJ[u]);
+    const float ra = axy ? A.ry : A.rx, ca = axy ? A.cy : A.cx;
+    const bool inr = idxS[u] >= 1 && idxS[u] <= 3 * k && idxK >= 1 && idxK <= 3 * k && idxJ <= 3 * k;
+    if (!inr) {
+      if constexpr (kGrad) atomicMin(A.err, (uint32_t)n);
+      continue;
+    }
+    if constexpr (!kGrad) {
+      A.parent[base + idxS[u]] = pS;
+      A.res[base + idxS[u]] = ra * LS;
+      A.cap[base + idxS[u]] = ca * LS;
+      A.parent[base + idxK] = pK;
+      A.res[base + idxK] = A.rx * LK;
+      A.cap[base + idxK] = A.cx * LK;
+      A.parent[base + idxJ] = pJ;
+      A.res[base + idxJ] = A.ry * LJ;
+      A.cap[base + idxJ] = A.cy * LJ;
+      A.sink_node[s0 + jtr[u] - 1] = idxJ;
+    } else {
+      const bool bad = A.g_parent[base + idxS[u]] != pS || A.g_parent[base + idxK] != pK ||
+                       A.g_parent[base + idxJ] != pJ || A.g_sink_node[s0 + jtr[u] - 1] != idxJ;
+      if (bad) atomicMin(A.err, (uint32_t)n);
+      const uint32_t my = A.step_src[s0 + t - 1];
+      const int mx_ = (int)(my & 0xffff), my_ = (int)(my >> 16);
+      const uint32_t pr = rank[u] > 0 ? A.step_src[s0 + predt[u] - 1] : (sg == 0 ? 0u : A.step_src[s0 + sc - 1]);
+      uS[u] = (axy ? my_ : mx_) | (axy ? 1 << 30 : 0);  // bit 30: the S term goes to y
+      wS[u] = sg == 0 ? 0 : (axy ? (int)(pr >> 16) : (int)(pr & 0xffff));
+      wK[u] = mA[u] > 0 ? (int)(A.step_src[s0 + bestAt[u] - 1] & 0xffff) : mx_;
+      wJ[u] = mB[u] > 0 ? (int)(A.step_src[s0 + bestBt[u] - 1] >> 16) : my_;
+      vS[u] = sgn_d(cr[u] - cpS[u]) * ((double)ra * A.g_res[base + idxS[u]] + (double)ca * A.g_cap[base + idxS[u]]);
+      vK[u] = sgn_d(xj - cpK[u]) * ((double)A.rx * A.g_res[base + idxK] + (double)A.cx * A.g_cap[base + idxK]);
+      vJ[u] = sgn_d(yj - cpJ[u]) * ((double)A.ry * A.g_res[base + idxJ] + (double)A.cy * A.g_cap[base + idxJ]);
+      if (axy)
+        myd = fmax(myd, fabs(vS[u]));
+      else
+        mxd = fmax(mxd, fabs(vS[u]));
+      mxd = fmax(mxd, fabs(vK[u]));
+      myd = fmax(myd, fabs(vJ[u]));
+    }
+  }
+  if constexpr (!kGrad) {
+    if (tid == 0) {
+      A.parent[base] = -1;
+      A.res[base] = 0.0f;
+      A.cap[base] = 0.0f;
+      A.node_ptr[n + 1] = base + 3 * (int64_t)k + 1;
+      if (n == 0) A.node_ptr[0] = 0;
+    }
+  } else {
+    // per-net exponents from the largest term per axis (as the bits of
+    // non-negative floats: rounding up to float raises the exponent by at
+    // most one, still in range)
+    const uint32_t wx = kNone - wave_min(kNone - __float_as_uint((float)mxd));
+    const uint32_t wy = kNone - wave_min(kNone - __float_as_uint((float)myd));
+    if (lane == 0) {
+      s_w[wave] = wx;
+      s_w[16 + wave] = wy;
+    }
+    __syncthreads();
+    uint32_t bx = 0, by = 0;
+#pragma unroll
+    for (int v = 0; v < 1024 / kWave; ++v) {
+      bx = max(bx, s_w[v]);
+      by = max(by, s_w[16 + v]);
+    }
+    const int ex = fix_exp((double)__uint_as_float(bx)), ey = fix_exp((double)__uint_as_float(by));
+    unsigned long long *acc = A.acc + 2 * A.acc_off[b];
+#pragma unroll
+    for (int u = 0; u < NL; ++u) {
+      const int t = tid + 1 + u * 1024;
+      if (t > k) continue;
+      const int oS = (uS[u] >> 30) & 1, us = uS[u] & 0xffff;
+      const long long is = to_fixed(vS[u], oS ? ey : ex), ik = to_fixed(vK[u], ex), ij = to_fixed(vJ[u], ey);
+      const int jt = jtr[u];
+      atomicAdd(acc + 2 * us + oS, (unsigned long long)is);
+      atomicAdd(acc + 2 * wS[u] + oS, (unsigned long long)(-is));
+      atomicAdd(acc + 2 * jt, (unsigned long long)ik);
+      atomicAdd(acc + 2 * wK[u], (unsigned long long)(-ik));
+      atomicAdd(acc + 2 * jt + 1, (unsigned long long)ij);
+      atomicAdd(acc + 2 * wJ[u] + 1, (unsigned long long)(-ij));
+    }
+    __threadfence();
+    __syncthreads();
+    for (int l = tid; l <= k; l += 1024) {
+      const int p = l == 0 ? drv : A.sink_pin[s0 + l - 1];
+      const long long sx = (long long)__hip_atomic_load(acc + 2 * l, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const long long sy = (long long)__hip_atomic_load(acc + 2 * l + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      A.gx[p] = (float)ldexp((double)sx, -ex);
+      A.gy[p] = (float)ldexp((double)sy, -ey);
+    }
+  }
 }
 
-// One block per net of list[0 .. *count), looping over the list with a
-// fixed grid; the net's size picks how many register slots each thread runs.
+// Picks the register-slot count NL of a net of k_est_block (pins 0..k over
+// 1024 threads) among kLo..kHi.
+template <bool kGrad, int NL, int kHi>
+__device__ __forceinline__ void est_block_dispatch(int nl, const EstArgs &A, int n, int s0, int k, int64_t base, int b,
+                                                   uint32_t (*s_key)[1024 / kWave], uint32_t (*s_idx)[1024 / kWave],
+                                                   float (*s_win)[1024 / kWave][6], float2 *s_q, int32_t *s_rec,
+                                                   uint32_t *s_w) {
+  if constexpr (NL <= kHi) {
+    if (nl == NL)
+      est_block_net<NL, kGrad>(A, n, s0, k, base, b, s_key, s_idx, s_win, s_q, s_rec, s_w);
+    else
+      est_block_dispatch<kGrad, NL + 1, kHi>(nl, A, n, s0, k, base, b, s_key, s_idx, s_win, s_q, s_rec, s_w);
+  }
+}
+
+// One block per net of list[0 .. *count) whose slot count lies in kLo..kHi,
+// looping over the list with a fixed grid.  Separate kernels per slot range
+// keep the register allocation of the small nets free of the large ones'.
+template <bool kGrad, int kLo, int kHi>
 __global__ __launch_bounds__(1024) void k_est_block(EstArgs A, const int32_t *list, const uint32_t *count) {
   __shared__ uint32_t s_key[2][1024 / kWave];
   __shared__ uint32_t s_idx[2][1024 / kWave];
-  __shared__ PinLoc s_pos[kEstMaxPins];
-  __shared__ uint16_t s_join[kEstMaxPins];
+  __shared__ float s_win[2][1024 / kWave][6];
+  __shared__ uint32_t s_w[2 * (1024 / kWave)];
+  __shared__ float2 s_q[kEstMaxPins];
+  __shared__ int32_t s_rec[kEstMaxPins];
   const int nb = (int)*count;
-  for (int b = blockIdx.x; b < nb; b += gridDim.x) {
+  for (int b = (int)blockIdx.x; b < nb; b += (int)gridDim.x) {
     const int n = list[b];
     const int s0 = A.sink_ptr[n], k = A.sink_ptr[n + 1] - s0;
-    const int64_t base = (int64_t)n + 2 * (int64_t)s0;
-    switch (k >> 10) {  // live slots - 1: pins 0..k over 1024 threads
-#define STA_EST_NET(c) \
-  case c - 1:          \
-    est_block_net<c>(A, n, s0, k, base, s_key, s_idx, s_pos, s_join); \
-    break;
-      STA_EST_NET(1) STA_EST_NET(2) STA_EST_NET(3) STA_EST_NET(4) STA_EST_NET(5) STA_EST_NET(6)
-      STA_EST_NET(7) STA_EST_NET(8) STA_EST_NET(9) STA_EST_NET(10) STA_EST_NET(11) STA_EST_NET(12)
-#undef STA_EST_NET
-      default:
-        break;  // more than kEstMaxPins pins: refused by the host before launch
-    }
+    const int nl = (k >> 10) + 1;  // more than kEstMaxPins pins: refused by the host before launch
+    if (nl < kLo || nl > kHi) continue;
+    const int64_t base = (int64_t)n + 3 * (int64_t)s0;
+    est_block_dispatch<kGrad, kLo, kHi>(nl, A, n, s0, k, base, b, s_key, s_idx, s_win, s_q, s_rec, s_w);
     __syncthreads();  // the next net reuses the buffers
   }
+}
+
+// The accumulator offsets of the gradient mode's large nets: off[b] = the
+// pins of big[0 .. b), *total their sum (one thread; the list is short).
+__global__ void k_est_acc_offsets(const EstArgs A, const int32_t *big, const uint32_t *count, int64_t *off,
+                                  unsigned long long *total) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  int64_t s = 0;
+  for (int b = 0; b < (int)*count; ++b) {
+    const int n = big[b];
+    off[b] = s;
+    s += (int64_t)(A.sink_ptr[n + 1] - A.sink_ptr[n]) + 1;
+  }
+  *total = (unsigned long long)s;
 }
 
 // Input check and work split in one pass.  st[0] / st[1] count the nets of
@@ -405,255 +869,6 @@ __global__ __launch_bounds__(256) void k_est_check(EstArgs A, int n_pins, int n_
   }
 }
 
-// ------------------------------------------------- gradient to positions
-//
-// With the tree fixed, the edge parent pin p -> pin c puts R = r_x |x_c - x_p|
-// and C = c_x |x_c - x_p| on its corner node a and the y terms on its pin node
-// b, so it adds v_x = sgn(x_c - x_p) (r_x dJ/dR_a + c_x dJ/dC_a) to dJ/dx_c and
-// -v_x to dJ/dx_p, likewise along y (sgn(0) = 0).  A pin's gradient is its own
-// edge's term plus the negated terms of its child edges.  The lane and wave
-// kernels add them in FP32 in sink order; the block kernel adds them as
-// integers (each term rounded to 2^-48 of the net's largest term), exact in
-// any order, so every tier is reproducible bit for bit.
-
-__device__ __forceinline__ float sgnf(float v) { return v > 0.0f ? 1.0f : (v < 0.0f ? -1.0f : 0.0f); }
-
-// One lane per net of at most kLanePins pins.
-__global__ __launch_bounds__(256) void k_estg_lane(EstGradArgs G) {
-  const int n = blockIdx.x * 256 + threadIdx.x;
-  if (n >= G.n_nets) return;
-  const int s0 = G.sink_ptr[n], k = G.sink_ptr[n + 1] - s0;
-  if (k + 1 > kLanePins) return;
-  const int64_t base = (int64_t)n + 2 * (int64_t)s0;
-  int pin[kLanePins], node[kLanePins];
-  float x[kLanePins], y[kLanePins], gx[kLanePins], gy[kLanePins];
-  pin[0] = G.driver[n];
-  node[0] = 0;
-#pragma unroll
-  for (int u = 1; u < kLanePins; ++u) {
-    pin[u] = u <= k ? G.sink_pin[s0 + u - 1] : pin[0];
-    node[u] = u <= k ? G.sink_node[s0 + u - 1] : -1;
-  }
-#pragma unroll
-  for (int u = 0; u < kLanePins; ++u) {
-    x[u] = G.x[pin[u]];
-    y[u] = G.y[pin[u]];
-    gx[u] = gy[u] = 0.0f;
-  }
-#pragma unroll
-  for (int u = 1; u < kLanePins; ++u) {
-    if (u > k) break;
-    const int b = node[u], a = b - 1;
-    const int pn = G.parent[base + a];
-    float px = x[0], py = y[0];
-#pragma unroll
-    for (int v = 1; v < kLanePins; ++v) {
-      px = node[v] == pn ? x[v] : px;
-      py = node[v] == pn ? y[v] : py;
-    }
-    const float vx = sgnf(x[u] - px) * (G.rx * G.g_res[base + a] + G.cx * G.g_cap[base + a]);
-    const float vy = sgnf(y[u] - py) * (G.ry * G.g_res[base + b] + G.cy * G.g_cap[base + b]);
-    gx[u] += vx;
-    gy[u] += vy;
-#pragma unroll
-    for (int v = 0; v < kLanePins; ++v) {
-      gx[v] -= node[v] == pn ? vx : 0.0f;
-      gy[v] -= node[v] == pn ? vy : 0.0f;
-    }
-  }
-#pragma unroll
-  for (int u = 0; u < kLanePins; ++u)
-    if (u <= k) {
-      G.gx[pin[u]] = gx[u];
-      G.gy[pin[u]] = gy[u];
-    }
-}
-
-// One wavefront per net of list[0 .. *count) (9..64 pins), one pin per lane.
-__global__ __launch_bounds__(256) void k_estg_wave(EstGradArgs G, const int32_t *list, const uint32_t *count) {
-  __shared__ int32_t s_inv[256 / kWave][kWave];
-  const int wv = threadIdx.x / kWave;
-  const int w = blockIdx.x * (256 / kWave) + wv;
-  if (w >= (int)*count) return;
-  const int n = list[w];
-  const int lane = threadIdx.x & (kWave - 1);
-  const int s0 = G.sink_ptr[n], k = G.sink_ptr[n + 1] - s0;
-  const int64_t base = (int64_t)n + 2 * (int64_t)s0;
-  const bool valid = lane <= k;
-  const int pin = (lane == 0 || !valid) ? G.driver[n] : G.sink_pin[s0 + lane - 1];
-  const int node = (lane == 0 || !valid) ? 0 : G.sink_node[s0 + lane - 1];
-  const float x = G.x[pin], y = G.y[pin];
-  // lane of the pin at each pin node 2t (t = 1..k); slot 0 the driver
-  s_inv[wv][lane] = 0;
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  if (valid && lane > 0) s_inv[wv][node >> 1] = lane;
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  int q = 0;  // this pin's parent lane
-  float vx = 0.0f, vy = 0.0f;
-  if (valid && lane > 0) {
-    const int b = node, a = b - 1;
-    q = s_inv[wv][G.parent[base + a] >> 1];
-    const float px = G.x[q == 0 ? G.driver[n] : G.sink_pin[s0 + q - 1]];
-    const float py = G.y[q == 0 ? G.driver[n] : G.sink_pin[s0 + q - 1]];
-    vx = sgnf(x - px) * (G.rx * G.g_res[base + a] + G.cx * G.g_cap[base + a]);
-    vy = sgnf(y - py) * (G.ry * G.g_res[base + b] + G.cy * G.g_cap[base + b]);
-  }
-  float gx = vx, gy = vy;
-  for (int l = 1; l <= k; ++l) {  // child terms in sink order
-    const int ql = __builtin_amdgcn_readlane(q, l);
-    const float ax = lane_float(vx, (uint32_t)l), ay = lane_float(vy, (uint32_t)l);
-    gx -= lane == ql ? ax : 0.0f;
-    gy -= lane == ql ? ay : 0.0f;
-  }
-  if (valid) {
-    G.gx[pin] = gx;
-    G.gy[pin] = gy;
-  }
-}
-
-// Fixed-point exponent for terms of magnitude up to m: a slot sums at most
-// kEstMaxPins terms, so 2^e m kEstMaxPins stays below 2^62.
-__device__ __forceinline__ int fix_exp(float m) {
-  return m > 0.0f ? 48 - ilogbf(m) : 0;
-}
-
-// One block per net of list[0 .. *count) (more than 64 pins), accumulating
-// into acc[2 * (off[b] + slot)] (x) and [+1] (y), zeroed by the host.
-__global__ __launch_bounds__(1024) void k_estg_block(EstGradArgs G, const int32_t *list, const uint32_t *count,
-                                                     const int64_t *off, unsigned long long *acc) {
-  __shared__ uint16_t s_inv[kEstMaxPins];  // slot of the pin at node 2t, by t (0: the driver)
-  __shared__ uint32_t s_max[2][1024 / kWave];
-  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-  const int nb = (int)*count;
-  for (int bi = blockIdx.x; bi < nb; bi += gridDim.x) {
-    const int n = list[bi];
-    const int s0 = G.sink_ptr[n], k = G.sink_ptr[n + 1] - s0;
-    const int64_t base = (int64_t)n + 2 * (int64_t)s0;
-    unsigned long long *ax = acc + 2 * off[bi];
-    for (int t = tid; t <= k; t += 1024) s_inv[t] = 0;
-    __syncthreads();
-    for (int l = 1 + tid; l <= k; l += 1024) s_inv[G.sink_node[s0 + l - 1] >> 1] = (uint16_t)l;
-    __syncthreads();
-    // pass 1: every term, and the largest magnitude per axis
-    float mx = 0.0f, my = 0.0f;
-    for (int l = 1 + tid; l <= k; l += 1024) {
-      const int b = G.sink_node[s0 + l - 1], a = b - 1;
-      const int q = s_inv[G.parent[base + a] >> 1];
-      const int pin = G.sink_pin[s0 + l - 1], ppin = q == 0 ? G.driver[n] : G.sink_pin[s0 + q - 1];
-      const float vx = sgnf(G.x[pin] - G.x[ppin]) * (G.rx * G.g_res[base + a] + G.cx * G.g_cap[base + a]);
-      const float vy = sgnf(G.y[pin] - G.y[ppin]) * (G.ry * G.g_res[base + b] + G.cy * G.g_cap[base + b]);
-      mx = fmaxf(mx, fabsf(vx));
-      my = fmaxf(my, fabsf(vy));
-    }
-    const uint32_t wx = kNone - wave_min(kNone - __float_as_uint(mx));  // max of non-negative floats
-    const uint32_t wy = kNone - wave_min(kNone - __float_as_uint(my));
-    if (lane == 0) {
-      s_max[0][wave] = wx;
-      s_max[1][wave] = wy;
-    }
-    __syncthreads();
-    uint32_t bx = 0, by = 0;
-#pragma unroll
-    for (int w = 0; w < 1024 / kWave; ++w) {
-      bx = max(bx, s_max[0][w]);
-      by = max(by, s_max[1][w]);
-    }
-    const int ex = fix_exp(__uint_as_float(bx)), ey = fix_exp(__uint_as_float(by));
-    // pass 2: integer sums (own term, and the negated term on the parent)
-    for (int l = 1 + tid; l <= k; l += 1024) {
-      const int b = G.sink_node[s0 + l - 1], a = b - 1;
-      const int q = s_inv[G.parent[base + a] >> 1];
-      const int pin = G.sink_pin[s0 + l - 1], ppin = q == 0 ? G.driver[n] : G.sink_pin[s0 + q - 1];
-      const float vx = sgnf(G.x[pin] - G.x[ppin]) * (G.rx * G.g_res[base + a] + G.cx * G.g_cap[base + a]);
-      const float vy = sgnf(G.y[pin] - G.y[ppin]) * (G.ry * G.g_res[base + b] + G.cy * G.g_cap[base + b]);
-      const long long ix = __double2ll_rn(ldexp((double)vx, ex)), iy = __double2ll_rn(ldexp((double)vy, ey));
-      atomicAdd(ax + 2 * l, (unsigned long long)ix);
-      atomicAdd(ax + 2 * q, (unsigned long long)(-ix));
-      atomicAdd(ax + 2 * l + 1, (unsigned long long)iy);
-      atomicAdd(ax + 2 * q + 1, (unsigned long long)(-iy));
-    }
-    __threadfence();
-    __syncthreads();
-    for (int l = tid; l <= k; l += 1024) {
-      const int pin = l == 0 ? G.driver[n] : G.sink_pin[s0 + l - 1];
-      const long long sx = (long long)__hip_atomic_load(ax + 2 * l, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      const long long sy = (long long)__hip_atomic_load(ax + 2 * l + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      G.gx[pin] = (float)ldexp((double)sx, -ex);
-      G.gy[pin] = (float)ldexp((double)sy, -ey);
-    }
-    __syncthreads();  // s_inv and s_max are reused by the next net
-  }
-}
-
-// Checks of the tree arrays and the work split for the gradient: st[0] / st[1]
-// count the nets of 9..64 / more than 64 pins (lists mid / big), st[2] is the
-// first sink whose node or corner parent is not a valid estimated-tree entry
-// (kNone when none), off[] gets each big net's accumulator offset and
-// *total their sum.  The net CSR and positions are checked by k_est_check.
-__global__ __launch_bounds__(256) void k_estg_check(EstGradArgs G, int n_sinks, int32_t *mid, int32_t *big,
-                                                    int64_t *off, unsigned long long *total, uint32_t *st) {
-  __shared__ uint32_t s_w[256 / kWave];
-  __shared__ uint32_t s_base;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  const int64_t top = max((int64_t)G.n_nets, (int64_t)n_sinks);
-  uint32_t cnt = 0;  // mid nets of this thread, slots reserved per block as in k_est_check
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < G.n_nets; i += stride) {
-    const int k = G.sink_ptr[i + 1] - G.sink_ptr[i];
-    cnt += k + 1 <= kWave && k + 1 > kLanePins ? 1u : 0u;
-  }
-  uint32_t tot;
-  uint32_t pos = block_excl_scan(cnt, s_w, &tot);
-  if (threadIdx.x == 0) s_base = tot > 0 ? atomicAdd(&st[0], tot) : 0u;
-  __syncthreads();
-  pos += s_base;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < top; i += stride) {
-    if (i < G.n_nets) {
-      const int n = (int)i;
-      const int k = G.sink_ptr[n + 1] - G.sink_ptr[n];
-      if (k + 1 > kWave) {
-        const uint32_t b = atomicAdd(&st[1], 1u);
-        big[b] = n;
-        off[b] = (int64_t)atomicAdd(total, (unsigned long long)(k + 1));
-      } else if (k + 1 > kLanePins) {
-        mid[pos++] = n;
-      }
-    }
-  }
-  // sinks: node 2t with 1 <= t <= k, corner parent an even node below the corner
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < G.n_nets; i += stride) {
-    const int n = (int)i;
-    const int s0 = G.sink_ptr[n], k = G.sink_ptr[n + 1] - s0;
-    if (k + 1 > kWave) continue;  // checked by the block-wide pass below
-    const int64_t base = (int64_t)n + 2 * (int64_t)s0;
-    for (int s = s0; s < s0 + k; ++s) {
-      const int b = G.sink_node[s];
-      const bool ok = b >= 2 && b <= 2 * k && (b & 1) == 0 && G.parent[base + b - 1] >= 0 &&
-                      G.parent[base + b - 1] <= b - 2 && (G.parent[base + b - 1] & 1) == 0;
-      if (!ok) atomicMin(&st[2], (uint32_t)s);
-    }
-  }
-}
-
-// The same sink checks for the nets of more than 64 pins, one block per net.
-__global__ __launch_bounds__(256) void k_estg_check_big(EstGradArgs G, const int32_t *big, const uint32_t *count,
-                                                        uint32_t *st) {
-  for (int bi = blockIdx.x; bi < (int)*count; bi += gridDim.x) {
-    const int n = big[bi];
-    const int s0 = G.sink_ptr[n], k = G.sink_ptr[n + 1] - s0;
-    const int64_t base = (int64_t)n + 2 * (int64_t)s0;
-    for (int s = s0 + threadIdx.x; s < s0 + k; s += blockDim.x) {
-      const int b = G.sink_node[s];
-      const bool ok = b >= 2 && b <= 2 * k && (b & 1) == 0 && G.parent[base + b - 1] >= 0 &&
-                      G.parent[base + b - 1] <= b - 2 && (G.parent[base + b - 1] & 1) == 0;
-      if (!ok) atomicMin(&st[2], (uint32_t)s);
-    }
-  }
-}
-
 inline int blocks_of(int64_t n, int b) { return (int)((n + b - 1) / b); }
 
 }  // namespace
@@ -694,42 +909,38 @@ hipError_t est_noalloc_scratch(int device, unsigned char **ptr) {
   return hipSuccess;
 }
 
+template <bool kGrad>
+static hipError_t launch_tiers(const EstArgs &A, const int32_t *mid, const int32_t *big, const uint32_t *st,
+                               uint32_t n_mid, uint32_t n_big, hipStream_t s) {
+  if (A.n_nets <= 0) return hipSuccess;
+  if (n_big > 0) {  // first: the longest blocks start before the short work fills the chip
+    const dim3 grid(std::min<uint32_t>(n_big, 4096u));
+    hipLaunchKernelGGL((k_est_block<kGrad, 9, kEstPer>), grid, dim3(1024), 0, s, A, big, st + 1);
+    hipLaunchKernelGGL((k_est_block<kGrad, 5, 8>), grid, dim3(1024), 0, s, A, big, st + 1);
+    hipLaunchKernelGGL((k_est_block<kGrad, 1, 4>), grid, dim3(1024), 0, s, A, big, st + 1);
+  }
+  if (n_mid > 0)
+    hipLaunchKernelGGL((k_est_group<kWave, kGrad>), dim3(blocks_of(n_mid, 256 / kWave)), dim3(256), 0, s, A, mid,
+                       st);
+  hipLaunchKernelGGL((k_est_group<kLanePins, kGrad>), dim3(blocks_of(A.n_nets, 256 / kLanePins)), dim3(256), 0, s,
+                     A, nullptr, nullptr);
+  return hipGetLastError();
+}
+
 hipError_t launch_est(const EstArgs &A, const int32_t *mid, const int32_t *big, const uint32_t *st, uint32_t n_mid,
                       uint32_t n_big, hipStream_t s) {
-  if (A.n_nets <= 0) return hipSuccess;
-  if (n_big > 0)  // first: the longest blocks start before the short work fills the chip
-    hipLaunchKernelGGL(k_est_block, dim3(std::min<uint32_t>(n_big, 4096u)), dim3(1024), 0, s, A, big, st + 1);
-  if (n_mid > 0)
-    hipLaunchKernelGGL(k_est_wave, dim3(blocks_of(n_mid, 256 / kWave)), dim3(256), 0, s, A, mid, st);
-  hipLaunchKernelGGL(k_est_lane, dim3(blocks_of(A.n_nets, 256)), dim3(256), 0, s, A);
+  return launch_tiers<false>(A, mid, big, st, n_mid, n_big, s);
+}
+
+hipError_t launch_est_acc_offsets(const EstArgs &A, const int32_t *big, const uint32_t *st, int64_t *off,
+                                  unsigned long long *total, hipStream_t s) {
+  hipLaunchKernelGGL(k_est_acc_offsets, dim3(1), dim3(64), 0, s, A, big, st + 1, off, total);
   return hipGetLastError();
 }
 
-hipError_t launch_estg_check(const EstGradArgs &G, int n_sinks, int32_t *mid, int32_t *big, int64_t *off,
-                             unsigned long long *total, uint32_t *st, hipStream_t s) {
-  const int64_t top = std::max<int64_t>(G.n_nets, n_sinks);
-  if (top <= 0) return hipSuccess;
-  const int grid = (int)std::min<int64_t>((top + 255) / 256, 8192);
-  hipLaunchKernelGGL(k_estg_check, dim3(grid), dim3(256), 0, s, G, n_sinks, mid, big, off, total, st);
-  return hipGetLastError();
-}
-
-hipError_t launch_estg_check_big(const EstGradArgs &G, const int32_t *big, uint32_t *st, hipStream_t s) {
-  if (G.n_nets <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_estg_check_big, dim3(std::min(G.n_nets, 1024)), dim3(256), 0, s, G, big, st + 1, st);
-  return hipGetLastError();
-}
-
-hipError_t launch_estg(const EstGradArgs &G, const int32_t *mid, const int32_t *big, const uint32_t *st,
-                       const int64_t *off, unsigned long long *acc, uint32_t n_mid, uint32_t n_big, hipStream_t s) {
-  if (G.n_nets <= 0) return hipSuccess;
-  if (n_big > 0)
-    hipLaunchKernelGGL(k_estg_block, dim3(std::min<uint32_t>(n_big, 4096u)), dim3(1024), 0, s, G, big, st + 1, off,
-                       acc);
-  if (n_mid > 0)
-    hipLaunchKernelGGL(k_estg_wave, dim3(blocks_of(n_mid, 256 / kWave)), dim3(256), 0, s, G, mid, st);
-  hipLaunchKernelGGL(k_estg_lane, dim3(blocks_of(G.n_nets, 256)), dim3(256), 0, s, G);
-  return hipGetLastError();
+hipError_t launch_est_grad(const EstArgs &A, const int32_t *mid, const int32_t *big, const uint32_t *st,
+                           uint32_t n_mid, uint32_t n_big, hipStream_t s) {
+  return launch_tiers<true>(A, mid, big, st, n_mid, n_big, s);
 }
 
 }  // namespace sta

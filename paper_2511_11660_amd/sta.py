@@ -422,7 +422,7 @@ def estimate_rc(d, pin_x, pin_y, r_x, r_y, c_x, c_y, stream=None) -> dict:
                        a(d.net_driver, np.int32), a(d.net_sink_ptr, np.int32),
                        a(d.net_sink_pin, np.int32), STA_HOST)
     n_sinks = int(np.asarray(d.net_sink_ptr)[-1])
-    n_nodes = d.n_nets + 2 * n_sinks
+    n_nodes = d.n_nets + 3 * n_sinks
     w = sta_wire_params(r_x, r_y, c_x, c_y)
     if hasattr(pin_x, "data_ptr"):
         import torch

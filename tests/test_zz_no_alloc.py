@@ -40,7 +40,7 @@ def _estimate(d, noalloc):
     x, y = t(d.x, np.float32), t(d.y, np.float32)
     g = sta_graph_desc(d.n_pins, 0, d.n_nets, 0, 0, None, None, None, None, None, drv.data_ptr(), ptr.data_ptr(),
                        pins.data_ptr(), STA_DEVICE)
-    n_nodes = d.n_nets + 2 * d.n_sinks
+    n_nodes = d.n_nets + 3 * d.n_sinks
     out = {"net_node_ptr": torch.full((d.n_nets + 1,), -7, dtype=torch.int64, device=dev),
            "parent": torch.full((max(n_nodes, 1),), -7, dtype=torch.int32, device=dev),
            "res_kohm": torch.full((max(n_nodes, 1),), -7.0, dtype=torch.float32, device=dev),
