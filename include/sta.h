@@ -461,11 +461,13 @@ sta_status sta_measure_level_floor(int32_t levels, int32_t items, int64_t record
  * hipMalloc).  Same trees, same outputs, bit for bit, and the same errors;
  * but every array (the net CSR per g->mem, which must be STA_DEVICE,
  * positions and outputs) is in device memory, and the call allocates
- * nothing: its check words and its lists of nets of 9-64 pins and of more
- * than 64 pins live in a fixed scratch array of the library (about 4.2 MiB
- * per device, held until the process ends).  Those lists take at most
- * 1,048,576 and 65,536 nets; a netlist with more gives STA_E_UNSUPPORTED
- * before any tree is built.  Every call on one device shares that device's
+ * nothing: its check words, its lists of nets of 9-64 pins and of more than
+ * 64 pins, and the per-pin working space of the nets of more than 64 pins
+ * live in a fixed scratch array of the library (about 12.8 MiB per device,
+ * held until the process ends).  Those lists take at most 1,048,576 and
+ * 65,536 nets, and the nets of more than 64 pins at most 131,072 pins in
+ * all; a netlist with more gives STA_E_UNSUPPORTED before any tree is
+ * built.  Every call on one device shares that device's
  * scratch, so calls that overlap on one device (other host threads, other
  * streams) race and give undefined results; the call synchronizes `stream`
  * twice (after the check and at the end), so calls from one thread do not

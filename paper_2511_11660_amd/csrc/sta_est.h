@@ -18,14 +18,15 @@ struct EstArgs {
   int32_t *parent;
   float *res, *cap;
   int32_t *sink_node;
+  uint32_t *big_tmp;        // nets above 64 pins: 16 words per pin, at 16 acc_off[b] for big-list entry b
+  const int64_t *acc_off;   // pins of the big-list entries before b
   // gradient mode (the trees rebuilt, checked and differentiated)
   const int32_t *g_parent, *g_sink_node;  // the caller's trees (net n at node n + 3 sink_ptr[n])
   const float *g_res, *g_cap;             // dJ/dR, dJ/dC per node
   float *gx, *gy;                         // [n_pins] outputs (pins on no net untouched)
   uint32_t *step_src;                     // [n_sinks] scratch: source pins of each step's attach point
   uint32_t *err;                          // lowest net whose tree differs from the caller's (~0 when none)
-  unsigned long long *acc;                // integer accumulators of the nets above 64 pins
-  const int64_t *acc_off;                 // their offsets (pins), by position in the big list
+  unsigned long long *acc;                // integer accumulators of the nets above 64 pins (2 per pin)
 };
 // st[6] (caller-initialized to {0, 0, 0, ~0, ~0, ~0}): nets of 9..64 pins,
 // nets above 64 pins, their largest sink count, first bad net, first bad sink
@@ -36,9 +37,12 @@ hipError_t launch_est_check(const EstArgs &A, int n_pins, int n_sinks, int32_t *
                             hipStream_t s, uint32_t mid_cap = UINT32_MAX, uint32_t big_cap = UINT32_MAX);
 
 // Scratch of the allocation-free entry point: 256 bytes of check words, then
-// kEstNoallocMid mid-list entries, then kEstNoallocBig big-list entries.
-constexpr uint32_t kEstNoallocMid = 1u << 20, kEstNoallocBig = 1u << 16;
-constexpr size_t kEstScratchBytes = 256 + 4 * ((size_t)kEstNoallocMid + kEstNoallocBig);
+// kEstNoallocMid mid-list entries, kEstNoallocBig big-list entries, their
+// kEstNoallocBig pin offsets (int64), and the big nets' per-pin scratch for
+// at most kEstNoallocBigPins pins in all.
+constexpr uint32_t kEstNoallocMid = 1u << 20, kEstNoallocBig = 1u << 16, kEstNoallocBigPins = 1u << 17;
+constexpr size_t kEstScratchBytes =
+    256 + 4 * ((size_t)kEstNoallocMid + kEstNoallocBig) + 8 * (size_t)kEstNoallocBig + 64 * (size_t)kEstNoallocBigPins;
 // Device address of that scratch on `device`, which must be the current
 // device; looked up once per device and kept.
 hipError_t est_noalloc_scratch(int device, unsigned char **ptr);
@@ -47,9 +51,9 @@ hipError_t est_noalloc_scratch(int device, unsigned char **ptr);
 hipError_t launch_est(const EstArgs &A, const int32_t *mid, const int32_t *big, const uint32_t *st, uint32_t n_mid,
                       uint32_t n_big, hipStream_t s);
 
-// Gradient mode over the same net lists: off[b] / *total get the big nets'
-// accumulator offsets and their pin total (count read from st[1] on the
-// device); acc needs 2 * total zeroed words before launch_est_grad.
+// off[b] / *total get the big nets' pin offsets and their pin total (count
+// read from st[1] on the device): big_tmp needs 16 * total words, and the
+// gradient mode's acc 2 * total zeroed ones.
 hipError_t launch_est_acc_offsets(const EstArgs &A, const int32_t *big, const uint32_t *st, int64_t *off,
                                   unsigned long long *total, hipStream_t s);
 hipError_t launch_est_grad(const EstArgs &A, const int32_t *mid, const int32_t *big, const uint32_t *st,

@@ -2037,6 +2037,19 @@ extern "C" sta_status sta_estimate_rc(const sta_graph_desc *g, const float *pin_
     const int64_t zero = 0;
     HIP_TRY(hipMemcpyAsync(A.node_ptr, &zero, sizeof zero, hipMemcpyHostToDevice, s));
   }
+  // the large nets' per-pin scratch
+  unsigned long long tot = 0;
+  int64_t *off;
+  unsigned long long *total;
+  STA_TRY(tmp.alloc(&off, (size_t)std::max(NN, 1)));
+  STA_TRY(tmp.alloc(&total, 1));
+  if (h[1] > 0) {
+    HIP_TRY(launch_est_acc_offsets(A, big, st, off, total, s));
+    HIP_TRY(hipMemcpyAsync(&tot, total, sizeof tot, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  STA_TRY(tmp.alloc(&A.big_tmp, (size_t)std::max<unsigned long long>(16 * tot, 1)));
+  A.acc_off = off;
   HIP_TRY(launch_est(A, mid, big, st, h[0], h[1], s));
   if (mem == STA_HOST) {
     HIP_TRY(hipMemcpyAsync(net_node_ptr, A.node_ptr, ((size_t)NN + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -2195,6 +2208,20 @@ extern "C" sta_status sta_estimate_rc_noalloc(const sta_graph_desc *g, const flo
     return fail(STA_E_UNSUPPORTED,
                 "%u nets of 9-64 pins and %u of more than 64 pins exceed the fixed scratch (at most %u and %u)", h[0],
                 h[1], kEstNoallocMid, kEstNoallocBig);
+  int64_t *off = reinterpret_cast<int64_t *>(big + kEstNoallocBig);
+  uint32_t *big_tmp = reinterpret_cast<uint32_t *>(off + kEstNoallocBig);
+  uint64_t tot = 0;
+  if (h[1] > 0) {  // the big nets' pin total, into the check words' spare slots
+    unsigned long long *total = reinterpret_cast<unsigned long long *>(scr + 64);
+    HIP_TRY(launch_est_acc_offsets(A, big, st, off, total, s));
+    HIP_TRY(hipMemcpyAsync(&tot, total, sizeof tot, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  if (tot > kEstNoallocBigPins)
+    return fail(STA_E_UNSUPPORTED, "the nets of more than 64 pins hold %llu pins, beyond the fixed scratch (%u)",
+                (unsigned long long)tot, kEstNoallocBigPins);
+  A.big_tmp = big_tmp;
+  A.acc_off = off;
   if (NN == 0) {
     const int64_t zero = 0;
     HIP_TRY(hipMemcpyAsync(A.node_ptr, &zero, sizeof zero, hipMemcpyHostToDevice, s));
@@ -2319,6 +2346,7 @@ extern "C" sta_status sta_estimate_rc_backward(const sta_graph_desc *g, const fl
     HIP_TRY(hipStreamSynchronize(s));
   }
   STA_TRY(tmp.alloc(&A.acc, (size_t)std::max<unsigned long long>(2 * tot, 1)));
+  STA_TRY(tmp.alloc(&A.big_tmp, (size_t)std::max<unsigned long long>(16 * tot, 1)));
   if (tot > 0) HIP_TRY(hipMemsetAsync(A.acc, 0, 2 * tot * sizeof(unsigned long long), s));
   A.acc_off = off;
   A.err = st + 6;

@@ -144,6 +144,15 @@ __device__ __forceinline__ void sph_relax(float x, float y, int self, Near &n, c
   }
 }
 
+// A block barrier that orders LDS only: the join loop exchanges its winners
+// through LDS, while its global stores (each step's record for the numbering)
+// are read only after a full __syncthreads, so a step need not wait for them.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -392,298 +401,310 @@ __device__ __forceinline__ uint32_t block_excl_scan1024(uint32_t c, uint32_t *s_
 }
 
 // One net of k_est_block with NL live register slots per thread (pin
-// l = tid + 1024 u, u < NL); step t is handled by thread (t - 1) % 1024 in
-// slot (t - 1) / 1024 once the joins are done.  LDS per step: the attach
-// point (later the step's key, then its segment offsets) and the segment |
-// pin record (later the index of its S node).
+// l = tid + 1024 u, u < NL); step t is handled by thread (t - 1) % 1024 once
+// the joins are done.  LDS per step: its record (segment | pin), its key and
+// later its wire offsets; the step's attach point, its counters and the
+// results of the passes go to the net's region of the global scratch tmp (16
+// words per step), so no per-step state stays in registers between phases.
+// The steps of each wire are found through a list ordered by wire (counts by
+// atomics, slots from the node offsets), so the passes cost O(k) plus the
+// squares of the wires' S-point counts.
 template <int NL, bool kGrad>
 __device__ __forceinline__ void est_block_net(const EstArgs &A, int n, int s0, int k, int64_t base, int b,
                                               uint32_t (*s_key)[1024 / kWave], uint32_t (*s_idx)[1024 / kWave],
-                                              float (*s_win)[1024 / kWave][6], float2 *s_q, int32_t *s_rec,
-                                              uint32_t *s_w) {
+                                              float (*s_win)[1024 / kWave][6], int32_t *s_rec, float *s_k,
+                                              uint32_t *s_off, uint32_t *s_w) {
   const int tid = (int)threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   const int drv = A.driver[n];
   const float x0 = A.x[drv], y0 = A.y[drv];
   const float kNaN = __builtin_nanf("");
-  float x[NL], y[NL];
-  Near nr[NL];
-  float key = kFar;
-  int ul = 0;
-#pragma unroll
-  for (int u = 0; u < NL; ++u) {
-    const int l = tid + u * 1024;  // pin index in the net: 0 driver, 1..k sinks
-    const bool live = l >= 1 && l <= k;
-    const int pin = A.sink_pin[s0 + (live ? l - 1 : 0)];
-    x[u] = live ? A.x[pin] : kNaN;  // NaN: never nearer than anything
-    y[u] = live ? A.y[pin] : kNaN;
-    nr[u] = Near{live ? manhattan(x[u], y[u], x0, y0) : kFar, x0, y0, 0, 0, 0};
-    const bool bt = nr[u].d < key;  // ascending l: the first minimum wins ties
-    key = bt ? nr[u].d : key;
-    ul = bt ? u : ul;
-  }
-  for (int t = 1; t <= k; ++t) {
-    const uint32_t wk = wave_min(key_of(key));
-    const uint32_t wi = wave_min(key_of(key) == wk && key < kFar ? (uint32_t)(tid + ul * 1024) : kNone);
-    const int buf = t & 1;
-    // the wave's winner publishes its attach point and position
-    if (wi != kNone && (int)(wi & 1023) == tid) {
-      float wqx = 0.0f, wqy = 0.0f, wx = 0.0f, wy = 0.0f;
-      int wsx = 0, wsy = 0;
-#pragma unroll
-      for (int u = 0; u < NL; ++u)
-        if (u == ul) {
-          wqx = nr[u].qx;
-          wqy = nr[u].qy;
-          wsx = nr[u].sqx;
-          wsy = nr[u].sqy;
-          wx = x[u];
-          wy = y[u];
-        }
-      s_win[buf][wave][0] = wqx;
-      s_win[buf][wave][1] = wqy;
-      s_win[buf][wave][2] = wx;
-      s_win[buf][wave][3] = wy;
-      if constexpr (kGrad) {
-        s_win[buf][wave][4] = __int_as_float(wsx);
-        s_win[buf][wave][5] = __int_as_float(wsy);
-      }
-    }
-    if (lane == 0) {
-      s_key[buf][wave] = wk;
-      s_idx[buf][wave] = wi;
-    }
-    __syncthreads();
-    const int e = lane & (1024 / kWave - 1);
-    const uint32_t ek = s_key[buf][e], ei = s_idx[buf][e];
-    const uint32_t bk = row_min16(ek);
-    const uint32_t bi = row_min16(ek == bk ? ei : kNone);
-    const int j = (int)__builtin_amdgcn_readfirstlane((int)bi);  // a pin outside the tree is left
-    const int jw = (j & 1023) / kWave, ju = j >> 10;
-    Join J;
-    J.qx = s_win[buf][jw][0];
-    J.qy = s_win[buf][jw][1];
-    J.xj = s_win[buf][jw][2];
-    J.yj = s_win[buf][jw][3];
-    J.sqx = kGrad ? __float_as_int(s_win[buf][jw][4]) : 0;
-    J.sqy = kGrad ? __float_as_int(s_win[buf][jw][5]) : 0;
-    J.j = j;
-    key = kFar;
-    ul = 0;
+  uint32_t *tmp = A.big_tmp + 16 * A.acc_off[b];  // 16 words per step t at 16 t; t = 0: net counters
+  {
+    float x[NL], y[NL];
+    Near nr[NL];
+    float key = kFar;
+    int ul = 0;
 #pragma unroll
     for (int u = 0; u < NL; ++u) {
-      if (tid == (j & 1023) && u == ju) {  // the joining pin records its step and leaves the candidates
-        s_q[t] = make_float2(nr[u].qx, nr[u].qy);
-        s_rec[t] = nr[u].seg | (j << 16);
-        if constexpr (kGrad) A.step_src[s0 + t - 1] = (uint32_t)nr[u].sqx | ((uint32_t)nr[u].sqy << 16);
-        x[u] = kNaN;
-        nr[u].d = kFar;
-      } else {
-        sph_relax(x[u], y[u], tid + u * 1024, nr[u], J, t);
-      }
-      const bool bt = nr[u].d < key;
+      const int l = tid + u * 1024;  // pin index in the net: 0 driver, 1..k sinks
+      const bool live = l >= 1 && l <= k;
+      const int pin = A.sink_pin[s0 + (live ? l - 1 : 0)];
+      x[u] = live ? A.x[pin] : kNaN;  // NaN: never nearer than anything
+      y[u] = live ? A.y[pin] : kNaN;
+      nr[u] = Near{live ? manhattan(x[u], y[u], x0, y0) : kFar, x0, y0, 0, 0, 0};
+      const bool bt = nr[u].d < key;  // ascending l: the first minimum wins ties
       key = bt ? nr[u].d : key;
       ul = bt ? u : ul;
     }
+    for (int t = 1; t <= k; ++t) {
+      const uint32_t wk = wave_min(key_of(key));
+      const uint32_t wi = wave_min(key_of(key) == wk && key < kFar ? (uint32_t)(tid + ul * 1024) : kNone);
+      const int buf = t & 1;
+      // the wave's winner publishes its attach point and position
+      if (wi != kNone && (int)(wi & 1023) == tid) {
+        float wqx = 0.0f, wqy = 0.0f, wx = 0.0f, wy = 0.0f;
+        int wsx = 0, wsy = 0;
+#pragma unroll
+        for (int u = 0; u < NL; ++u)
+          if (u == ul) {
+            wqx = nr[u].qx;
+            wqy = nr[u].qy;
+            wsx = nr[u].sqx;
+            wsy = nr[u].sqy;
+            wx = x[u];
+            wy = y[u];
+          }
+        s_win[buf][wave][0] = wqx;
+        s_win[buf][wave][1] = wqy;
+        s_win[buf][wave][2] = wx;
+        s_win[buf][wave][3] = wy;
+        if constexpr (kGrad) {
+          s_win[buf][wave][4] = __int_as_float(wsx);
+          s_win[buf][wave][5] = __int_as_float(wsy);
+        }
+      }
+      if (lane == 0) {
+        s_key[buf][wave] = wk;
+        s_idx[buf][wave] = wi;
+      }
+      lds_barrier();
+      const int e = lane & (1024 / kWave - 1);
+      const uint32_t ek = s_key[buf][e], ei = s_idx[buf][e];
+      const uint32_t bk = row_min16(ek);
+      const uint32_t bi = row_min16(ek == bk ? ei : kNone);
+      const int j = (int)__builtin_amdgcn_readfirstlane((int)bi);  // a pin outside the tree is left
+      const int jw = (j & 1023) / kWave, ju = j >> 10;
+      Join J;
+      J.qx = s_win[buf][jw][0];
+      J.qy = s_win[buf][jw][1];
+      J.xj = s_win[buf][jw][2];
+      J.yj = s_win[buf][jw][3];
+      J.sqx = kGrad ? __float_as_int(s_win[buf][jw][4]) : 0;
+      J.sqy = kGrad ? __float_as_int(s_win[buf][jw][5]) : 0;
+      J.j = j;
+      key = kFar;
+      ul = 0;
+#pragma unroll
+      for (int u = 0; u < NL; ++u) {
+        if (tid == (j & 1023) && u == ju) {  // the joining pin records its step and leaves the candidates
+          s_rec[t] = nr[u].seg | (j << 16);
+          tmp[16 * t] = __float_as_uint(nr[u].qx);
+          tmp[16 * t + 1] = __float_as_uint(nr[u].qy);
+          if constexpr (kGrad) A.step_src[s0 + t - 1] = (uint32_t)nr[u].sqx | ((uint32_t)nr[u].sqy << 16);
+          x[u] = kNaN;
+          nr[u].d = kFar;
+        } else {
+          sph_relax(x[u], y[u], tid + u * 1024, nr[u], J, t);
+        }
+        const bool bt = nr[u].d < key;
+        key = bt ? nr[u].d : key;
+        ul = bt ? u : ul;
+      }
+    }
   }
-  __syncthreads();  // every step recorded (and its sources written)
+  __syncthreads();  // every step recorded (LDS, and its point in tmp)
   auto pos_of = [&](int l, float &px, float &py) {
     const int p = l == 0 ? drv : A.sink_pin[s0 + l - 1];
     px = A.x[p];
     py = A.y[p];
   };
-  // ---- pass 1: each step's key (distance order on its segment) and the
-  // segment's start and direction
-  float kq[NL], dirr[NL], c0r[NL], cr[NL];
-#pragma unroll
-  for (int u = 0; u < NL; ++u) {
-    const int t = tid + 1 + u * 1024;
-    kq[u] = c0r[u] = cr[u] = 0.0f;
-    dirr[u] = 1.0f;
-    if (t <= k) {
-      // every step wrote its record; the clamps only keep each index in range
-      const int sg = min(s_rec[t] & 0xffff, 2 * (t - 1)), sc = (sg + 1) >> 1;
-      const bool axy = sg != 0 && (sg & 1) == 0;
-      float c0 = x0, cend = x0;
-      if (sg != 0) {
-        float pxs, pys;
-        pos_of(min(max(s_rec[sc] >> 16, 1), k), pxs, pys);
-        c0 = axy ? s_q[sc].y : s_q[sc].x;
-        cend = axy ? pys : pxs;
-      }
-      dirr[u] = cend < c0 ? -1.0f : 1.0f;
-      cr[u] = axy ? s_q[t].y : s_q[t].x;
-      kq[u] = dirr[u] * cr[u];
-      c0r[u] = c0;
+  // the record of step t, its clamps only keeping every index in range
+  auto seg_of = [&](int t) { return min(s_rec[t] & 0xffff, 2 * (t - 1)); };
+  auto pin_of = [&](int t) { return min(max(s_rec[t] >> 16, 1), k); };
+  // ---- pass 1: each step's key (distance order on its wire: dir * coordinate),
+  // and the step's counters cleared
+  if (tid == 0) {
+    tmp[4] = 0u;  // S points on wire 0
+    tmp[5] = 0u;  // their fill counter
+  }
+  for (int t = tid + 1; t <= k; t += 1024) {
+    const int sg = seg_of(t), sc = (sg + 1) >> 1;
+    const bool axy = sg != 0 && (sg & 1) == 0;
+    float c0 = x0, cend = x0;
+    if (sg != 0) {
+      float pxs, pys;
+      pos_of(pin_of(sc), pxs, pys);
+      c0 = __uint_as_float(tmp[16 * sc + (axy ? 1 : 0)]);
+      cend = axy ? pys : pxs;
     }
+    const float dir = cend < c0 ? -1.0f : 1.0f;
+    s_k[t] = dir * __uint_as_float(tmp[16 * t + (axy ? 1 : 0)]);
+    tmp[16 * t + 2] = __float_as_uint(c0);  // the step's own words: read back only by this step
+    tmp[16 * t + 3] = __float_as_uint(dir);
+#pragma unroll
+    for (int w = 4; w < 10; ++w) tmp[16 * t + w] = 0u;
   }
   __syncthreads();
-  // the key replaces the attach point's x; the own point's coordinates are
-  // kept for the corner and pin pieces
-  float qxr[NL], qyr[NL];
-#pragma unroll
-  for (int u = 0; u < NL; ++u) {
-    const int t = tid + 1 + u * 1024;
-    qxr[u] = qyr[u] = 0.0f;
-    if (t <= k) {
-      qxr[u] = s_q[t].x;
-      qyr[u] = s_q[t].y;
-      s_q[t].x = kq[u];
+  // ---- pass 2: every S point reports to the step whose wire it lies on: a
+  // count per wire and its last point (the largest key, ties to the later
+  // step: an atomic maximum of the orderable key bits and the step)
+  auto owner_word = [&](int sg, int w) -> uint32_t * { return tmp + 16 * ((sg + 1) >> 1) + w; };
+  for (int t = tid + 1; t <= k; t += 1024) {
+    const int sg = seg_of(t);
+    if (sg == 0) {
+      atomicAdd(tmp + 4, 1u);
+      continue;
     }
+    atomicAdd(owner_word(sg, 4), (sg & 1) ? 1u : 0x10000u);
+    const uint32_t bits = __float_as_uint(s_k[t] + 0.0f);  // -0 reads as +0
+    const uint32_t ok = (bits & 0x80000000u) ? ~bits : bits | 0x80000000u;
+    atomicMax(reinterpret_cast<unsigned long long *>(owner_word(sg, (sg & 1) ? 6 : 8)),
+              ((unsigned long long)ok << 32) | (unsigned long long)t);
   }
   __syncthreads();
-  // ---- pass 2: rank on the own segment (and the predecessor), the splits
-  // on segments 0, 2t-1 and 2t (and the last of each), then the coordinates
-  // of the three parents
-  int rank[NL], mA[NL], mB[NL], predt[NL], bestAt[NL], bestBt[NL];
-  float cpS[NL], cpK[NL], cpJ[NL];
-  int m0 = 0;
+  // ---- offsets: an exclusive prefix over steps of (S points on 2t-1 and 2t) + 2
+  uint32_t carry = tmp[4] + 1u;
 #pragma unroll
   for (int u = 0; u < NL; ++u) {
     const int t = tid + 1 + u * 1024;
-    const int sg = t <= k ? min(s_rec[t] & 0xffff, 2 * (t - 1)) : -1;
-    const float kt = kq[u];
-    int rk = 0, ma = 0, mb = 0, pt = 0, at = 0, bt = 0, z = 0;
-    float pk = 0.0f, ak = 0.0f, bk = 0.0f;
-    for (int v = 1; v <= k; ++v) {  // ascending steps: ties in key go to the later step
-      const int sv = s_rec[v] & 0xffff;
-      const float kv = s_q[v].x;
-      z += sv == 0 ? 1 : 0;
-      if (sv == sg && (kv < kt || (kv == kt && v < t))) {
-        if (rk == 0 || kv >= pk) {
+    const uint32_t cnt = t <= k ? tmp[16 * t + 4] : 0u;
+    const uint32_t wv = t <= k ? (cnt & 0xffffu) + (cnt >> 16) + 2u : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan1024(wv, s_w, &tot);
+    if (t <= k) s_off[t] = carry + ex;  // offset of wire 2t-1
+    carry += tot;
+  }
+  __syncthreads();
+  // first node of wire w, its S-point count, and its first slot in the list
+  // of S points ordered by wire (the S points on earlier wires: off(w) - w)
+  auto wire_off = [&](int w) -> int {
+    if (w == 0) return 0;
+    const int sc = (w + 1) >> 1;
+    return (w & 1) ? (int)s_off[sc] : (int)s_off[sc] + (int)(tmp[16 * sc + 4] & 0xffffu) + 1;
+  };
+  auto wire_count = [&](int w) -> int {
+    if (w == 0) return (int)tmp[4];
+    const uint32_t cnt = tmp[16 * ((w + 1) >> 1) + 4];
+    return (int)((w & 1) ? (cnt & 0xffffu) : (cnt >> 16));
+  };
+  // ---- pass 3: the S points into their wires' slots (list at word 10 of slot + 1)
+  for (int t = tid + 1; t <= k; t += 1024) {
+    const int sg = seg_of(t);
+    uint32_t pos;
+    if (sg == 0)
+      pos = atomicAdd(tmp + 5, 1u);
+    else
+      pos = (atomicAdd(owner_word(sg, 5), (sg & 1) ? 1u : 0x10000u) >> ((sg & 1) ? 0 : 16)) & 0xffffu;
+    const int slot = wire_off(sg) - sg + (int)pos;
+    if (slot >= 0 && slot < k) tmp[16 * (slot + 1) + 10] = (uint32_t)t;
+  }
+  __syncthreads();
+  // ---- pass 4: rank on the own wire (and the predecessor) from the wire's
+  // slots; then the signed pieces (child minus parent coordinate) of S_t, K_t
+  // and J_t
+  for (int t = tid + 1; t <= k; t += 1024) {
+    const int sg = seg_of(t), sc = (sg + 1) >> 1;
+    const bool axy = sg != 0 && (sg & 1) == 0;
+    const float kt = s_k[t];
+    const int first = wire_off(sg) - sg, m = wire_count(sg);
+    int rk = 0, pt = 0;
+    float pk = 0.0f;
+    for (int i = 0; i < m; ++i) {
+      const int slot = first + i;
+      const int v = (slot >= 0 && slot < k) ? min(max((int)tmp[16 * (slot + 1) + 10], 1), k) : t;
+      const float kv = s_k[v];
+      if (kv < kt || (kv == kt && v < t)) {
+        if (rk == 0 || kv > pk || (kv == pk && v > pt)) {
           pk = kv;
           pt = v;
         }
         ++rk;
       }
-      if (sv == 2 * t - 1) {
-        if (ma == 0 || kv >= ak) {
-          ak = kv;
-          at = v;
-        }
-        ++ma;
-      }
-      if (sv == 2 * t) {
-        if (mb == 0 || kv >= bk) {
-          bk = kv;
-          bt = v;
-        }
-        ++mb;
-      }
     }
-    m0 = z;
-    rank[u] = rk;
-    mA[u] = ma;
-    mB[u] = mb;
-    predt[u] = pt;
-    bestAt[u] = at;
-    bestBt[u] = bt;
-    float xj = 0.0f, yj = 0.0f;
-    if (t <= k) pos_of(min(max(s_rec[t] >> 16, 1), k), xj, yj);
-    const float dirA = xj < qxr[u] ? -1.0f : 1.0f, dirB = yj < qyr[u] ? -1.0f : 1.0f;
-    cpS[u] = rk > 0 ? dirr[u] * pk : c0r[u];
-    cpK[u] = ma > 0 ? dirA * ak : qxr[u];
-    cpJ[u] = mb > 0 ? dirB * bk : qyr[u];
-  }
-  __syncthreads();
-  // ---- offsets: an exclusive prefix over steps of (splits on 2t-1 and 2t) + 2
-  int offA[NL];
-  uint32_t carry = (uint32_t)m0 + 1u;
-#pragma unroll
-  for (int u = 0; u < NL; ++u) {
-    const int t = tid + 1 + u * 1024;
-    const uint32_t wv = t <= k ? (uint32_t)(mA[u] + mB[u] + 2) : 0u;
-    uint32_t tot;
-    const uint32_t ex = block_excl_scan1024(wv, s_w, &tot);
-    offA[u] = (int)(carry + ex);
-    carry += tot;
-  }
-  // publish (offset of segment 2t-1, index of K_t) per step in place of the key
-#pragma unroll
-  for (int u = 0; u < NL; ++u) {
-    const int t = tid + 1 + u * 1024;
-    if (t <= k) s_q[t] = make_float2(__int_as_float(offA[u]), __int_as_float(offA[u] + mA[u]));
-  }
-  __syncthreads();
-  int idxS[NL], jtr[NL], sgr[NL];
-#pragma unroll
-  for (int u = 0; u < NL; ++u) {
-    const int t = tid + 1 + u * 1024;
-    idxS[u] = jtr[u] = sgr[u] = 0;
-    if (t <= k) {
-      const int rec = s_rec[t], sg = min(rec & 0xffff, 2 * (t - 1)), sc = (sg + 1) >> 1;
-      jtr[u] = min(max(rec >> 16, 1), k);
-      sgr[u] = sg;
-      const int offsg = sg == 0 ? 0 : ((sg & 1) ? __float_as_int(s_q[sc].x) : __float_as_int(s_q[sc].y) + 1);
-      idxS[u] = offsg + (sg == 0 ? 1 : 0) + rank[u];
+    const uint32_t cnt = tmp[16 * t + 4];
+    const int ma = (int)(cnt & 0xffffu), mb = (int)(cnt >> 16);
+    const int at = ma > 0 ? min(max((int)(uint32_t)*reinterpret_cast<unsigned long long *>(tmp + 16 * t + 6), 1), k) : 0;
+    const int bt = mb > 0 ? min(max((int)(uint32_t)*reinterpret_cast<unsigned long long *>(tmp + 16 * t + 8), 1), k) : 0;
+    const float qx = __uint_as_float(tmp[16 * t]), qy = __uint_as_float(tmp[16 * t + 1]);
+    const float c0 = __uint_as_float(tmp[16 * t + 2]), dir = __uint_as_float(tmp[16 * t + 3]);
+    const float c = axy ? qy : qx;
+    float xj, yj;
+    pos_of(pin_of(t), xj, yj);
+    const float dirA = xj < qx ? -1.0f : 1.0f, dirB = yj < qy ? -1.0f : 1.0f;
+    const float cpS = rk > 0 ? dir * pk : c0;
+    const float cpK = ma > 0 ? dirA * s_k[at] : qx;
+    const float cpJ = mb > 0 ? dirB * s_k[bt] : qy;
+    if constexpr (kGrad) {  // the pins bounding the pieces along their axes
+      const uint32_t my = A.step_src[s0 + t - 1];
+      const int mx_ = (int)(my & 0xffff), my_ = (int)(my >> 16);
+      const uint32_t pr = rk > 0 ? A.step_src[s0 + pt - 1] : (sg == 0 ? 0u : A.step_src[s0 + sc - 1]);
+      const int uS = axy ? my_ : mx_;
+      const int wS = sg == 0 ? 0 : (axy ? (int)(pr >> 16) : (int)(pr & 0xffff));
+      const int wK = ma > 0 ? (int)(A.step_src[s0 + at - 1] & 0xffff) : mx_;
+      const int wJ = mb > 0 ? (int)(A.step_src[s0 + bt - 1] >> 16) : my_;
+      tmp[16 * t + 11] = (uint32_t)uS | (axy ? 0x8000u : 0u) | ((uint32_t)wS << 16);  // bit 15: S term to y
+      tmp[16 * t + 12] = (uint32_t)wK | ((uint32_t)wJ << 16);
     }
-  }
-  __syncthreads();  // every step has read the records it needs
-#pragma unroll
-  for (int u = 0; u < NL; ++u) {
-    const int t = tid + 1 + u * 1024;
-    if (t <= k) s_rec[t] = idxS[u];  // the index of S_t replaces the record
+    // the step's own words 0-3, read above; others read word 3 only after the next barrier
+    tmp[16 * t] = __float_as_uint(c - cpS);
+    tmp[16 * t + 1] = __float_as_uint(xj - cpK);
+    tmp[16 * t + 2] = __float_as_uint(yj - cpJ);
+    tmp[16 * t + 3] = (uint32_t)rk;
   }
   __syncthreads();
   // ---- the nodes
-  double mxd = 0.0, myd = 0.0;
-  double vS[kGrad ? NL : 1], vK[kGrad ? NL : 1], vJ[kGrad ? NL : 1];
-  int uS[kGrad ? NL : 1], wS[kGrad ? NL : 1], wK[kGrad ? NL : 1], wJ[kGrad ? NL : 1];
-#pragma unroll
-  for (int u = 0; u < NL; ++u) {
-    const int t = tid + 1 + u * 1024;
-    if constexpr (kGrad) {
-      vS[u] = vK[u] = vJ[u] = 0.0;
-      uS[u] = wS[u] = wK[u] = wJ[u] = 0;
-    }
-    if (t > k) continue;
-    const int sg = sgr[u], sc = (sg + 1) >> 1;
+  auto idx_s = [&](int t) {  // node of S_t
+    const int sg = seg_of(t);
+    return wire_off(sg) + (sg == 0 ? 1 : 0) + (int)tmp[16 * t + 3];
+  };
+  // node indices, parents and pieces of step t (S_t, K_t, J_t)
+  auto nodes_of = [&](int t, int &iS, int &iK, int &iJ, int &pS, int &pK, int &pJ) {
+    const int sg = seg_of(t), sc = (sg + 1) >> 1;
+    const uint32_t cnt = tmp[16 * t + 4];
+    const int rk = (int)tmp[16 * t + 3], ma = (int)(cnt & 0xffffu), mb = (int)(cnt >> 16);
+    iS = idx_s(t);
+    iK = (int)s_off[t] + ma;
+    iJ = iK + 1 + mb;
+    pS = rk > 0 ? iS - 1 : (sg == 0 ? 0 : ((sg & 1) ? idx_s(sc) : (int)s_off[sc] + (int)(tmp[16 * sc + 4] & 0xffffu)));
+    pK = ma > 0 ? iK - 1 : iS;
+    pJ = mb > 0 ? iJ - 1 : iK;
+    return iS >= 1 && iS <= 3 * k && iK >= 1 && iK <= 3 * k && iJ <= 3 * k;
+  };
+  // the three terms of step t in the gradient mode
+  auto terms_of = [&](int t, int iS, int iK, int iJ, double &vS, double &vK, double &vJ) {
+    const int sg = seg_of(t);
     const bool axy = sg != 0 && (sg & 1) == 0;
-    const int idxK = offA[u] + mA[u], idxJ = idxK + 1 + mB[u];
-    const int idxS_s = sg == 0 ? 0 : s_rec[sc];
-    const int idxK_s = sg == 0 ? 0 : __float_as_int(s_q[sc].y);
-    const int pS = rank[u] > 0 ? idxS[u] - 1 : (sg == 0 ? 0 : ((sg & 1) ? idxS_s : idxK_s));
-    const int pK = mA[u] > 0 ? idxK - 1 : idxS[u];
-    const int pJ = mB[u] > 0 ? idxJ - 1 : idxK;
-    float xj, yj;
-    pos_of(jtr[u], xj, yj);
-    const float LS = fabsf(cr[u] - cpS[u]), LK = fabsf(xj - cpK[u]), LJ = fabsf(yj - cpJ[u]);
     const float ra = axy ? A.ry : A.rx, ca = axy ? A.cy : A.cx;
-    const bool inr = idxS[u] >= 1 && idxS[u] <= 3 * k && idxK >= 1 && idxK <= 3 * k && idxJ <= 3 * k;
-    if (!inr) {
+    vS = sgn_d(__uint_as_float(tmp[16 * t])) * ((double)ra * A.g_res[base + iS] + (double)ca * A.g_cap[base + iS]);
+    vK = sgn_d(__uint_as_float(tmp[16 * t + 1])) * ((double)A.rx * A.g_res[base + iK] + (double)A.cx * A.g_cap[base + iK]);
+    vJ = sgn_d(__uint_as_float(tmp[16 * t + 2])) * ((double)A.ry * A.g_res[base + iJ] + (double)A.cy * A.g_cap[base + iJ]);
+    return axy;
+  };
+  double mxd = 0.0, myd = 0.0;
+  for (int t = tid + 1; t <= k; t += 1024) {
+    int iS, iK, iJ, pS, pK, pJ;
+    if (!nodes_of(t, iS, iK, iJ, pS, pK, pJ)) {
       if constexpr (kGrad) atomicMin(A.err, (uint32_t)n);
       continue;
     }
+    const int jt = pin_of(t);
     if constexpr (!kGrad) {
-      A.parent[base + idxS[u]] = pS;
-      A.res[base + idxS[u]] = ra * LS;
-      A.cap[base + idxS[u]] = ca * LS;
-      A.parent[base + idxK] = pK;
-      A.res[base + idxK] = A.rx * LK;
-      A.cap[base + idxK] = A.cx * LK;
-      A.parent[base + idxJ] = pJ;
-      A.res[base + idxJ] = A.ry * LJ;
-      A.cap[base + idxJ] = A.cy * LJ;
-      A.sink_node[s0 + jtr[u] - 1] = idxJ;
+      const int sg = seg_of(t);
+      const bool axy = sg != 0 && (sg & 1) == 0;
+      const float ra = axy ? A.ry : A.rx, ca = axy ? A.cy : A.cx;
+      const float LS = fabsf(__uint_as_float(tmp[16 * t])), LK = fabsf(__uint_as_float(tmp[16 * t + 1])),
+                  LJ = fabsf(__uint_as_float(tmp[16 * t + 2]));
+      A.parent[base + iS] = pS;
+      A.res[base + iS] = ra * LS;
+      A.cap[base + iS] = ca * LS;
+      A.parent[base + iK] = pK;
+      A.res[base + iK] = A.rx * LK;
+      A.cap[base + iK] = A.cx * LK;
+      A.parent[base + iJ] = pJ;
+      A.res[base + iJ] = A.ry * LJ;
+      A.cap[base + iJ] = A.cy * LJ;
+      A.sink_node[s0 + jt - 1] = iJ;
     } else {
-      const bool bad = A.g_parent[base + idxS[u]] != pS || A.g_parent[base + idxK] != pK ||
-                       A.g_parent[base + idxJ] != pJ || A.g_sink_node[s0 + jtr[u] - 1] != idxJ;
+      const bool bad = A.g_parent[base + iS] != pS || A.g_parent[base + iK] != pK || A.g_parent[base + iJ] != pJ ||
+                       A.g_sink_node[s0 + jt - 1] != iJ;
       if (bad) atomicMin(A.err, (uint32_t)n);
-      const uint32_t my = A.step_src[s0 + t - 1];
-      const int mx_ = (int)(my & 0xffff), my_ = (int)(my >> 16);
-      const uint32_t pr = rank[u] > 0 ? A.step_src[s0 + predt[u] - 1] : (sg == 0 ? 0u : A.step_src[s0 + sc - 1]);
-      uS[u] = (axy ? my_ : mx_) | (axy ? 1 << 30 : 0);  // bit 30: the S term goes to y
-      wS[u] = sg == 0 ? 0 : (axy ? (int)(pr >> 16) : (int)(pr & 0xffff));
-      wK[u] = mA[u] > 0 ? (int)(A.step_src[s0 + bestAt[u] - 1] & 0xffff) : mx_;
-      wJ[u] = mB[u] > 0 ? (int)(A.step_src[s0 + bestBt[u] - 1] >> 16) : my_;
-      vS[u] = sgn_d(cr[u] - cpS[u]) * ((double)ra * A.g_res[base + idxS[u]] + (double)ca * A.g_cap[base + idxS[u]]);
-      vK[u] = sgn_d(xj - cpK[u]) * ((double)A.rx * A.g_res[base + idxK] + (double)A.cx * A.g_cap[base + idxK]);
-      vJ[u] = sgn_d(yj - cpJ[u]) * ((double)A.ry * A.g_res[base + idxJ] + (double)A.cy * A.g_cap[base + idxJ]);
-      if (axy)
-        myd = fmax(myd, fabs(vS[u]));
+      double vS, vK, vJ;
+      if (terms_of(t, iS, iK, iJ, vS, vK, vJ))
+        myd = fmax(myd, fabs(vS));
       else
-        mxd = fmax(mxd, fabs(vS[u]));
-      mxd = fmax(mxd, fabs(vK[u]));
-      myd = fmax(myd, fabs(vJ[u]));
+        mxd = fmax(mxd, fabs(vS));
+      mxd = fmax(mxd, fabs(vK));
+      myd = fmax(myd, fabs(vJ));
     }
   }
   if constexpr (!kGrad) {
@@ -700,6 +721,7 @@ __device__ __forceinline__ void est_block_net(const EstArgs &A, int n, int s0, i
     // most one, still in range)
     const uint32_t wx = kNone - wave_min(kNone - __float_as_uint((float)mxd));
     const uint32_t wy = kNone - wave_min(kNone - __float_as_uint((float)myd));
+    __syncthreads();  // s_w free (the offsets scan is done)
     if (lane == 0) {
       s_w[wave] = wx;
       s_w[16 + wave] = wy;
@@ -713,19 +735,22 @@ __device__ __forceinline__ void est_block_net(const EstArgs &A, int n, int s0, i
     }
     const int ex = fix_exp((double)__uint_as_float(bx)), ey = fix_exp((double)__uint_as_float(by));
     unsigned long long *acc = A.acc + 2 * A.acc_off[b];
-#pragma unroll
-    for (int u = 0; u < NL; ++u) {
-      const int t = tid + 1 + u * 1024;
-      if (t > k) continue;
-      const int oS = (uS[u] >> 30) & 1, us = uS[u] & 0xffff;
-      const long long is = to_fixed(vS[u], oS ? ey : ex), ik = to_fixed(vK[u], ex), ij = to_fixed(vJ[u], ey);
-      const int jt = jtr[u];
+    for (int t = tid + 1; t <= k; t += 1024) {
+      int iS, iK, iJ, pS, pK, pJ;
+      if (!nodes_of(t, iS, iK, iJ, pS, pK, pJ)) continue;
+      double vS, vK, vJ;
+      terms_of(t, iS, iK, iJ, vS, vK, vJ);
+      const uint32_t w0 = tmp[16 * t + 11], w1 = tmp[16 * t + 12];
+      const int oS = (w0 >> 15) & 1, us = (int)(w0 & 0x7fff), ws = (int)(w0 >> 16);
+      const int wk = (int)(w1 & 0xffff), wj = (int)(w1 >> 16);
+      const long long is = to_fixed(vS, oS ? ey : ex), ik = to_fixed(vK, ex), ij = to_fixed(vJ, ey);
+      const int jt = pin_of(t);
       atomicAdd(acc + 2 * us + oS, (unsigned long long)is);
-      atomicAdd(acc + 2 * wS[u] + oS, (unsigned long long)(-is));
+      atomicAdd(acc + 2 * ws + oS, (unsigned long long)(-is));
       atomicAdd(acc + 2 * jt, (unsigned long long)ik);
-      atomicAdd(acc + 2 * wK[u], (unsigned long long)(-ik));
+      atomicAdd(acc + 2 * wk, (unsigned long long)(-ik));
       atomicAdd(acc + 2 * jt + 1, (unsigned long long)ij);
-      atomicAdd(acc + 2 * wJ[u] + 1, (unsigned long long)(-ij));
+      atomicAdd(acc + 2 * wj + 1, (unsigned long long)(-ij));
     }
     __threadfence();
     __syncthreads();
@@ -744,13 +769,14 @@ __device__ __forceinline__ void est_block_net(const EstArgs &A, int n, int s0, i
 template <bool kGrad, int NL, int kHi>
 __device__ __forceinline__ void est_block_dispatch(int nl, const EstArgs &A, int n, int s0, int k, int64_t base, int b,
                                                    uint32_t (*s_key)[1024 / kWave], uint32_t (*s_idx)[1024 / kWave],
-                                                   float (*s_win)[1024 / kWave][6], float2 *s_q, int32_t *s_rec,
-                                                   uint32_t *s_w) {
+                                                   float (*s_win)[1024 / kWave][6], int32_t *s_rec, float *s_k,
+                                                   uint32_t *s_off, uint32_t *s_w) {
   if constexpr (NL <= kHi) {
     if (nl == NL)
-      est_block_net<NL, kGrad>(A, n, s0, k, base, b, s_key, s_idx, s_win, s_q, s_rec, s_w);
+      est_block_net<NL, kGrad>(A, n, s0, k, base, b, s_key, s_idx, s_win, s_rec, s_k, s_off, s_w);
     else
-      est_block_dispatch<kGrad, NL + 1, kHi>(nl, A, n, s0, k, base, b, s_key, s_idx, s_win, s_q, s_rec, s_w);
+      est_block_dispatch<kGrad, NL + 1, kHi>(nl, A, n, s0, k, base, b, s_key, s_idx, s_win, s_rec, s_k, s_off,
+                                             s_w);
   }
 }
 
@@ -763,8 +789,9 @@ __global__ __launch_bounds__(1024) void k_est_block(EstArgs A, const int32_t *li
   __shared__ uint32_t s_idx[2][1024 / kWave];
   __shared__ float s_win[2][1024 / kWave][6];
   __shared__ uint32_t s_w[2 * (1024 / kWave)];
-  __shared__ float2 s_q[kEstMaxPins];
   __shared__ int32_t s_rec[kEstMaxPins];
+  __shared__ float s_k[kEstMaxPins];
+  __shared__ uint32_t s_off[kEstMaxPins];
   const int nb = (int)*count;
   for (int b = (int)blockIdx.x; b < nb; b += (int)gridDim.x) {
     const int n = list[b];
@@ -772,7 +799,7 @@ __global__ __launch_bounds__(1024) void k_est_block(EstArgs A, const int32_t *li
     const int nl = (k >> 10) + 1;  // more than kEstMaxPins pins: refused by the host before launch
     if (nl < kLo || nl > kHi) continue;
     const int64_t base = (int64_t)n + 3 * (int64_t)s0;
-    est_block_dispatch<kGrad, kLo, kHi>(nl, A, n, s0, k, base, b, s_key, s_idx, s_win, s_q, s_rec, s_w);
+    est_block_dispatch<kGrad, kLo, kHi>(nl, A, n, s0, k, base, b, s_key, s_idx, s_win, s_rec, s_k, s_off, s_w);
     __syncthreads();  // the next net reuses the buffers
   }
 }
@@ -915,9 +942,7 @@ static hipError_t launch_tiers(const EstArgs &A, const int32_t *mid, const int32
   if (A.n_nets <= 0) return hipSuccess;
   if (n_big > 0) {  // first: the longest blocks start before the short work fills the chip
     const dim3 grid(std::min<uint32_t>(n_big, 4096u));
-    hipLaunchKernelGGL((k_est_block<kGrad, 9, kEstPer>), grid, dim3(1024), 0, s, A, big, st + 1);
-    hipLaunchKernelGGL((k_est_block<kGrad, 5, 8>), grid, dim3(1024), 0, s, A, big, st + 1);
-    hipLaunchKernelGGL((k_est_block<kGrad, 1, 4>), grid, dim3(1024), 0, s, A, big, st + 1);
+    hipLaunchKernelGGL((k_est_block<kGrad, 1, kEstPer>), grid, dim3(1024), 0, s, A, big, st + 1);
   }
   if (n_mid > 0)
     hipLaunchKernelGGL((k_est_group<kWave, kGrad>), dim3(blocks_of(n_mid, 256 / kWave)), dim3(256), 0, s, A, mid,
