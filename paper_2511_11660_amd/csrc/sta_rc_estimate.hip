@@ -118,29 +118,43 @@ __device__ __forceinline__ void clamp_src(float v, int sv, float a, int sa, floa
 }
 
 // Offer pin (x, y) = net-local `self` the two segments of step t; a pin in the
-// tree (or padding) carries x = NaN and never takes one.
+// tree (or padding) carries x = NaN and never takes one.  Branch-free: the
+// updates are selects.  Without kSrc (the estimation) the clamps are a max
+// and a min: the same value as the compare form up to the sign of a zero,
+// which no output depends on (pieces are absolute differences, keys compare
+// -0 equal to +0); with kSrc (the gradient) the compare form also gives the
+// pin each clamped coordinate is copied from.
+template <bool kSrc>
 __device__ __forceinline__ void sph_relax(float x, float y, int self, Near &n, const Join &J, int t) {
   float c;
-  int sc;
-  clamp_src(x, self, J.qx, J.sqx, J.xj, J.j, c, sc);  // segment 2t-1: y = qy, x from qx to x_j
-  float d = fabsf(x - c) + fabsf(y - J.qy);
-  if (d < n.d) {
-    n.d = d;
-    n.seg = 2 * t - 1;
-    n.qx = c;
-    n.qy = J.qy;
-    n.sqx = sc;
-    n.sqy = J.sqy;
+  int sc = 0;
+  if constexpr (kSrc) {
+    clamp_src(x, self, J.qx, J.sqx, J.xj, J.j, c, sc);  // segment 2t-1: y = qy, x from qx to x_j
+  } else {
+    c = fminf(fmaxf(x, fminf(J.qx, J.xj)), fmaxf(J.qx, J.xj));
   }
-  clamp_src(y, self, J.qy, J.sqy, J.yj, J.j, c, sc);  // segment 2t: x = x_j, y from qy to y_j
-  d = fabsf(x - J.xj) + fabsf(y - c);
-  if (d < n.d) {
-    n.d = d;
-    n.seg = 2 * t;
-    n.qx = J.xj;
-    n.qy = c;
-    n.sqx = J.j;
-    n.sqy = sc;
+  const float d1 = fabsf(x - c) + fabsf(y - J.qy);
+  const bool b1 = d1 < n.d;
+  n.d = b1 ? d1 : n.d;
+  n.seg = b1 ? 2 * t - 1 : n.seg;
+  n.qx = b1 ? c : n.qx;
+  n.qy = b1 ? J.qy : n.qy;
+  if constexpr (kSrc) {
+    n.sqx = b1 ? sc : n.sqx;
+    n.sqy = b1 ? J.sqy : n.sqy;
+    clamp_src(y, self, J.qy, J.sqy, J.yj, J.j, c, sc);  // segment 2t: x = x_j, y from qy to y_j
+  } else {
+    c = fminf(fmaxf(y, fminf(J.qy, J.yj)), fmaxf(J.qy, J.yj));
+  }
+  const float d2 = fabsf(x - J.xj) + fabsf(y - c);
+  const bool b2 = d2 < n.d;
+  n.d = b2 ? d2 : n.d;
+  n.seg = b2 ? 2 * t : n.seg;
+  n.qx = b2 ? J.xj : n.qx;
+  n.qy = b2 ? c : n.qy;
+  if constexpr (kSrc) {
+    n.sqx = b2 ? J.j : n.sqx;
+    n.sqy = b2 ? sc : n.sqy;
   }
 }
 
@@ -240,7 +254,7 @@ __global__ __launch_bounds__(256) void k_est_group(EstArgs A, const int32_t *lis
       x = kNaN;
       nr.d = kFar;
     } else {
-      sph_relax(x, y, lane, nr, J, t);
+      sph_relax<kGrad>(x, y, lane, nr, J, t);
     }
   }
   wave_sync();
@@ -412,7 +426,7 @@ __device__ __forceinline__ uint32_t block_excl_scan1024(uint32_t c, uint32_t *s_
 template <int NL, bool kGrad>
 __device__ __forceinline__ void est_block_net(const EstArgs &A, int n, int s0, int k, int64_t base, int b,
                                               uint32_t (*s_key)[1024 / kWave], uint32_t (*s_idx)[1024 / kWave],
-                                              float (*s_win)[1024 / kWave][6], int32_t *s_rec, float *s_k,
+                                              float (*s_win)[1024 / kWave][8], int32_t *s_rec, float *s_k,
                                               uint32_t *s_off, uint32_t *s_w) {
   const int tid = (int)threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   const int drv = A.driver[n];
@@ -420,8 +434,16 @@ __device__ __forceinline__ void est_block_net(const EstArgs &A, int n, int s0, i
   const float kNaN = __builtin_nanf("");
   uint32_t *tmp = A.big_tmp + 16 * A.acc_off[b];  // 16 words per step t at 16 t; t = 0: net counters
   {
+    // The candidates: position p = tid + 1024 u holds a pin outside the tree
+    // (its index in s_off[p], ascending with p, so the lowest position among
+    // equal distances is the lowest index), the first nl slots of each thread
+    // in use; whenever the pins left fit one slot fewer they are packed again
+    // in position order (through words 6-14 of the scratch), so the work per
+    // step follows the pins left rather than the net.
     float x[NL], y[NL];
     Near nr[NL];
+    int li[kGrad ? NL : 1];  // the gradient mode's clamps name the pins
+    int nl = NL;
     float key = kFar;
     int ul = 0;
 #pragma unroll
@@ -429,13 +451,16 @@ __device__ __forceinline__ void est_block_net(const EstArgs &A, int n, int s0, i
       const int l = tid + u * 1024;  // pin index in the net: 0 driver, 1..k sinks
       const bool live = l >= 1 && l <= k;
       const int pin = A.sink_pin[s0 + (live ? l - 1 : 0)];
+      if constexpr (kGrad) li[u] = l;
+      s_off[l] = (uint32_t)l;
       x[u] = live ? A.x[pin] : kNaN;  // NaN: never nearer than anything
       y[u] = live ? A.y[pin] : kNaN;
       nr[u] = Near{live ? manhattan(x[u], y[u], x0, y0) : kFar, x0, y0, 0, 0, 0};
-      const bool bt = nr[u].d < key;  // ascending l: the first minimum wins ties
+      const bool bt = nr[u].d < key;  // ascending position: the first minimum wins ties
       key = bt ? nr[u].d : key;
       ul = bt ? u : ul;
     }
+    __syncthreads();
     for (int t = 1; t <= k; ++t) {
       const uint32_t wk = wave_min(key_of(key));
       const uint32_t wi = wave_min(key_of(key) == wk && key < kFar ? (uint32_t)(tid + ul * 1024) : kNone);
@@ -443,21 +468,25 @@ __device__ __forceinline__ void est_block_net(const EstArgs &A, int n, int s0, i
       // the wave's winner publishes its attach point and position
       if (wi != kNone && (int)(wi & 1023) == tid) {
         float wqx = 0.0f, wqy = 0.0f, wx = 0.0f, wy = 0.0f;
-        int wsx = 0, wsy = 0;
+        int wsx = 0, wsy = 0, wsg = 0;
 #pragma unroll
-        for (int u = 0; u < NL; ++u)
-          if (u == ul) {
-            wqx = nr[u].qx;
-            wqy = nr[u].qy;
-            wsx = nr[u].sqx;
-            wsy = nr[u].sqy;
-            wx = x[u];
-            wy = y[u];
+        for (int u = 0; u < NL; ++u) {
+          const bool me = u == ul;
+          wqx = me ? nr[u].qx : wqx;
+          wqy = me ? nr[u].qy : wqy;
+          if constexpr (kGrad) {
+            wsx = me ? nr[u].sqx : wsx;
+            wsy = me ? nr[u].sqy : wsy;
           }
+          wsg = me ? nr[u].seg : wsg;
+          wx = me ? x[u] : wx;
+          wy = me ? y[u] : wy;
+        }
         s_win[buf][wave][0] = wqx;
         s_win[buf][wave][1] = wqy;
         s_win[buf][wave][2] = wx;
         s_win[buf][wave][3] = wy;
+        s_win[buf][wave][6] = __int_as_float(wsg);
         if constexpr (kGrad) {
           s_win[buf][wave][4] = __int_as_float(wsx);
           s_win[buf][wave][5] = __int_as_float(wsy);
@@ -472,8 +501,9 @@ __device__ __forceinline__ void est_block_net(const EstArgs &A, int n, int s0, i
       const uint32_t ek = s_key[buf][e], ei = s_idx[buf][e];
       const uint32_t bk = row_min16(ek);
       const uint32_t bi = row_min16(ek == bk ? ei : kNone);
-      const int j = (int)__builtin_amdgcn_readfirstlane((int)bi);  // a pin outside the tree is left
-      const int jw = (j & 1023) / kWave, ju = j >> 10;
+      const int jp = min(max((int)__builtin_amdgcn_readfirstlane((int)bi), 0), NL * 1024 - 1);  // a pin is left
+      const int jw = (jp & 1023) / kWave, ju = jp >> 10;
+      const int j = (int)s_off[jp];  // its index in the net
       Join J;
       J.qx = s_win[buf][jw][0];
       J.qy = s_win[buf][jw][1];
@@ -482,23 +512,79 @@ __device__ __forceinline__ void est_block_net(const EstArgs &A, int n, int s0, i
       J.sqx = kGrad ? __float_as_int(s_win[buf][jw][4]) : 0;
       J.sqy = kGrad ? __float_as_int(s_win[buf][jw][5]) : 0;
       J.j = j;
+      if (tid == 0) {  // the step's record, from the winner's published state
+        s_rec[t] = __float_as_int(s_win[buf][jw][6]) | (j << 16);
+        tmp[16 * t] = __float_as_uint(J.qx);
+        tmp[16 * t + 1] = __float_as_uint(J.qy);
+        if constexpr (kGrad) A.step_src[s0 + t - 1] = (uint32_t)J.sqx | ((uint32_t)J.sqy << 16);
+      }
       key = kFar;
       ul = 0;
+      const bool mine = tid == (jp & 1023);
 #pragma unroll
       for (int u = 0; u < NL; ++u) {
-        if (tid == (j & 1023) && u == ju) {  // the joining pin records its step and leaves the candidates
-          s_rec[t] = nr[u].seg | (j << 16);
-          tmp[16 * t] = __float_as_uint(nr[u].qx);
-          tmp[16 * t + 1] = __float_as_uint(nr[u].qy);
-          if constexpr (kGrad) A.step_src[s0 + t - 1] = (uint32_t)nr[u].sqx | ((uint32_t)nr[u].sqy << 16);
-          x[u] = kNaN;
-          nr[u].d = kFar;
-        } else {
-          sph_relax(x[u], y[u], tid + u * 1024, nr[u], J, t);
+        if (u < nl) {  // uniform: the slots in use
+          const bool out = mine && u == ju;  // the joining pin leaves the candidates
+          x[u] = out ? kNaN : x[u];
+          nr[u].d = out ? kFar : nr[u].d;
+          sph_relax<kGrad>(x[u], y[u], kGrad ? li[kGrad ? u : 0] : 0, nr[u], J, t);
+          const bool bt = nr[u].d < key;
+          key = bt ? nr[u].d : key;
+          ul = bt ? u : ul;
         }
-        const bool bt = nr[u].d < key;
-        key = bt ? nr[u].d : key;
-        ul = bt ? u : ul;
+      }
+      if (nl > 1 && k - t <= (nl - 1) * 1024) {  // uniform: pack the pins left into nl - 1 slots
+        __syncthreads();  // the step's reads of s_off and s_win are done
+        uint32_t carry = 0;
+#pragma unroll
+        for (int u = 0; u < NL; ++u) {
+          if (u < nl) {
+            const bool live = x[u] == x[u];  // not NaN
+            uint32_t tot;
+            const uint32_t pos = carry + block_excl_scan1024(live ? 1u : 0u, s_w, &tot);
+            carry += tot;
+            if (live) {
+              uint32_t *o = tmp + 16 * (pos + 1) + 6;
+              o[0] = __float_as_uint(x[u]);
+              o[1] = __float_as_uint(y[u]);
+              o[2] = __float_as_uint(nr[u].d);
+              o[3] = __float_as_uint(nr[u].qx);
+              o[4] = __float_as_uint(nr[u].qy);
+              o[5] = (uint32_t)nr[u].seg;
+              o[6] = s_off[tid + u * 1024];
+              if constexpr (kGrad) {
+                o[7] = (uint32_t)nr[u].sqx;
+                o[8] = (uint32_t)nr[u].sqy;
+              }
+            }
+          }
+        }
+        __syncthreads();  // every pin written (and every old index read)
+        --nl;
+        key = kFar;
+        ul = 0;
+#pragma unroll
+        for (int u = 0; u < NL; ++u) {
+          const int pos = tid + u * 1024;
+          const bool live = u < nl && pos < k - t;
+          const uint32_t *o = tmp + 16 * (min(pos, max(k - t - 1, 0)) + 1) + 6;  // in the net's region
+          x[u] = live ? __uint_as_float(o[0]) : kNaN;
+          y[u] = live ? __uint_as_float(o[1]) : kNaN;
+          nr[u].d = live ? __uint_as_float(o[2]) : kFar;
+          nr[u].qx = live ? __uint_as_float(o[3]) : 0.0f;
+          nr[u].qy = live ? __uint_as_float(o[4]) : 0.0f;
+          nr[u].seg = live ? (int)o[5] : 0;
+          if (u < nl) s_off[pos] = live ? o[6] : 0u;
+          if constexpr (kGrad) {
+            li[u] = live ? (int)o[6] : 0;
+            nr[u].sqx = live ? (int)o[7] : 0;
+            nr[u].sqy = live ? (int)o[8] : 0;
+          }
+          const bool bt = nr[u].d < key;
+          key = bt ? nr[u].d : key;
+          ul = bt ? u : ul;
+        }
+        __syncthreads();  // the new indices in place
       }
     }
   }
@@ -769,7 +855,7 @@ __device__ __forceinline__ void est_block_net(const EstArgs &A, int n, int s0, i
 template <bool kGrad, int NL, int kHi>
 __device__ __forceinline__ void est_block_dispatch(int nl, const EstArgs &A, int n, int s0, int k, int64_t base, int b,
                                                    uint32_t (*s_key)[1024 / kWave], uint32_t (*s_idx)[1024 / kWave],
-                                                   float (*s_win)[1024 / kWave][6], int32_t *s_rec, float *s_k,
+                                                   float (*s_win)[1024 / kWave][8], int32_t *s_rec, float *s_k,
                                                    uint32_t *s_off, uint32_t *s_w) {
   if constexpr (NL <= kHi) {
     if (nl == NL)
@@ -787,7 +873,7 @@ template <bool kGrad, int kLo, int kHi>
 __global__ __launch_bounds__(1024) void k_est_block(EstArgs A, const int32_t *list, const uint32_t *count) {
   __shared__ uint32_t s_key[2][1024 / kWave];
   __shared__ uint32_t s_idx[2][1024 / kWave];
-  __shared__ float s_win[2][1024 / kWave][6];
+  __shared__ float s_win[2][1024 / kWave][8];
   __shared__ uint32_t s_w[2 * (1024 / kWave)];
   __shared__ int32_t s_rec[kEstMaxPins];
   __shared__ float s_k[kEstMaxPins];
