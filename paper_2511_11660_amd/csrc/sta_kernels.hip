@@ -1829,9 +1829,9 @@ __device__ __forceinline__ void wait_done(uint32_t *ctr, uint32_t target) {
     if (__builtin_amdgcn_readfirstlane(v) >= target) break;
     __builtin_amdgcn_s_sleep(1);
   }
-  // the loop exit waits on the counter load; keep the compiler from hoisting
-  // the coherent data loads that follow above it
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  // acquire at agent scope: the producers' stores (released with their count)
+  // are visible to every load after this point, coherent or not
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
 
 __device__ __forceinline__ int take_ticket(uint32_t *ctr) {
@@ -1839,9 +1839,17 @@ __device__ __forceinline__ int take_ticket(uint32_t *ctr) {
   return (int)__builtin_amdgcn_readfirstlane(old);
 }
 
-// Every coherent store of this wave has completed (vmcnt 0) before the counter
-// moves, so a consumer that sees the count reads the new values.
+// A release at agent scope: every store of this wave before it is visible to
+// a consumer that acquires the count (wait_done) after seeing it.
 __device__ __forceinline__ void signal_add(uint32_t *ctr, uint32_t n) {
+  __hip_atomic_fetch_add(ctr, lane_id() == 0 ? n : 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The wide-net barrier's arrival: its data moves only through agent-scope
+// atomic loads and stores, which are coherent across the device by
+// themselves, so the count needs only those stores completed (vmcnt 0)
+// before it moves, not the cache write-back of a release.
+__device__ __forceinline__ void arrive_add(uint32_t *ctr, uint32_t n) {
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
   __builtin_amdgcn_s_waitcnt(0);
   __hip_atomic_fetch_add(ctr, lane_id() == 0 ? n : 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -2391,7 +2399,7 @@ __device__ void wide_sync(WideCtx &c) {
   __syncthreads();
   ++c.passed;
   if (c.nblk > 1 && threadIdx.x < kWave) {
-    signal_add(c.arrive, 1u);
+    arrive_add(c.arrive, 1u);
     const uint32_t target = c.passed * (uint32_t)c.nblk;
     for (;;) {
       const uint32_t v = __hip_atomic_load(c.arrive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
