@@ -2,14 +2,15 @@
 scratch) against the allocating one (sta_estimate_rc, per-call scratch) on the
 same device inputs, through the C ABI: every output bit for bit, on two calls
 in a row (the second smaller, so stale list entries or check words of the
-first call would show), with nets in all three tiers (lane, wave, block)."""
+first call would show), with nets in all three tiers (8-lane group, wave,
+block), and the error beyond the fixed scratch."""
 from types import SimpleNamespace
 
 import numpy as np
 import pytest
 
-from paper_2511_11660_amd.sta import (STA_DEVICE, sta_estimate_rc, sta_estimate_rc_noalloc, sta_graph_desc,
-                                      sta_wire_params)
+from paper_2511_11660_amd.sta import (STA_DEVICE, STA_E_UNSUPPORTED, StaError, sta_estimate_rc,
+                                      sta_estimate_rc_noalloc, sta_graph_desc, sta_wire_params)
 
 pytestmark = pytest.mark.gpu
 
@@ -76,3 +77,15 @@ def test_noalloc_matches_allocating_estimator_twice():
     second = _design([80] + mid[:40] + small[:3000], seed=2)
     print(f"[noalloc] second call: {second.n_nets} nets, {second.n_pins} pins", flush=True)
     _same(_estimate(second, True), _estimate(second, False))
+
+
+def test_noalloc_rejects_big_nets_beyond_its_scratch():
+    """Nets of more than 64 pins holding more pins in all than the fixed
+    scratch takes give STA_E_UNSUPPORTED before any tree is built; the entry
+    point stays usable."""
+    over = _design([12000] * 11, seed=4)  # 132,011 pins in nets above 64 pins
+    with pytest.raises(StaError) as e:
+        _estimate(over, True)
+    assert e.value.status == STA_E_UNSUPPORTED
+    ok = _design([3000, 70, 9, 3], seed=5)
+    _same(_estimate(ok, True), _estimate(ok, False))
