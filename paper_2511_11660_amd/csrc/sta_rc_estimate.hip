@@ -26,11 +26,12 @@
 //   k_est_block      one 1024-thread block per larger net (up to kEstMaxPins
 //                    pins, up to kEstPer per thread in registers)
 // Each runs the join loop (a group minimum of the distance bits, then of the
-// pin indices holding it; the winner's attach point and position broadcast),
-// records every step (attach point, segment, pin) in LDS, and then numbers
-// and writes the nodes with one thread per step: a pass over the net's steps
-// gives each step its rank and chain neighbours, a prefix sum over steps the
-// segment offsets.
+// lowest pin holding it; the winner's attach point and position broadcast),
+// records every step (attach point, segment, pin), and then numbers and
+// writes the nodes with one thread per step: a pass over the net's steps (in
+// the block kernel, over the steps on the same wire, found through a list
+// ordered by wire) gives each step its rank and chain neighbours, a prefix sum
+// over steps the segment offsets.
 //
 // The gradient mode (sta_estimate_rc_backward) rebuilds the trees the same
 // way, checks them against the caller's, and sends each node's dJ/dR and
@@ -89,9 +90,6 @@ __device__ __forceinline__ uint32_t row_min16(uint32_t v) {
 // Non-negative floats order like their bit patterns.
 __device__ __forceinline__ uint32_t key_of(float d) { return __float_as_uint(d); }
 
-__device__ __forceinline__ float lane_float(float v, uint32_t lane) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), (int)lane));
-}
 
 // A pin's nearest point of the tree so far: distance, segment, the point and
 // the net-local pins its two coordinates are copied from.
