@@ -157,7 +157,8 @@ typedef struct {
   int32_t device;
 } sta_info;
 
-/* Fills *opt with the defaults (hard mode, persistent schedule, sorting on). */
+/* Fills *opt with the defaults: hard mode (gamma 5 ps for smooth mode), per-level schedule with
+   side-stream overlap, Elmore net delays, endpoint sorting on, current device. */
 void sta_options_default(sta_options *opt);
 
 /* Validates the inputs on the host, levelizes the timing graph on the device

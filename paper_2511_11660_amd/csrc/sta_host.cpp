@@ -105,6 +105,8 @@ struct sta_ctx {
   std::vector<std::unique_ptr<DevMem>> mem;
   DevDesign D{};
   float *rc_cap = nullptr;
+  const float *rc_pc = nullptr;        // the small nets' lumped pin caps (added in set_wire_caps)
+  int64_t n_small_nodes = 0;           // RC nodes of the small nets (the first in RC order)
   int32_t *pin_loc = nullptr, *net_slot = nullptr, *sink_slot = nullptr, *node_src = nullptr;
   int32_t *ep_pin = nullptr, *pin_level = nullptr, *level_order = nullptr;
   int32_t *slot_drv_pin = nullptr, *slot_sink_pin = nullptr;  // slot -> caller pin (path reports)
@@ -1016,9 +1018,14 @@ static sta_status build_layout(sta_ctx *C, const Inputs &I, const std::vector<in
     for (size_t j = 0; j < rc_order.size(); ++j)
       rc_sinks[j] = make_int2(sink_ptr[rc_order[j]], sink_ptr[rc_order[j] + 1]);
     std::vector<float> pcf(pcd.begin(), pcd.end());
+    // the small nets' C^ = wire cap + pin caps, the float sum the RC pass reads
+    // (wide nets keep the wire cap; their kernels add the pin caps in FP64)
+    C->n_small_nodes = rc_start.back();
+    for (int64_t k = 0; k < C->n_small_nodes; ++k) rc_cap[k] = rc_cap[k] + pcf[k];
     uint8_t *p8;
     STA_TRY(C->upload(&p8, par8)); D.rc_par8 = p8;
     STA_TRY(C->upload(&pf, pcf)); D.rc_pc = pf;
+    C->rc_pc = pf;
     int2 *p2;
     STA_TRY(C->upload(&p2, rc_sinks)); D.rc_sinks = p2;
   }
@@ -1592,10 +1599,10 @@ extern "C" sta_status sta_set_wire_caps(sta_ctx *C, const float *cap_ff, sta_mem
     sta_ctx scratch;
     STA_TRY(scratch.alloc(&tmp, C->n_nodes));
     HIP_TRY(hipMemcpyAsync(tmp, cap_ff, C->n_nodes * sizeof(float), hipMemcpyHostToDevice, s));
-    HIP_TRY(launch_permute_caps(tmp, C->node_src, C->rc_cap, C->n_nodes, s));
+    HIP_TRY(launch_permute_caps(tmp, C->node_src, C->rc_cap, C->n_nodes, C->rc_pc, C->n_small_nodes, s));
     HIP_TRY(hipStreamSynchronize(s));
   } else if (mem == STA_DEVICE) {
-    HIP_TRY(launch_permute_caps(cap_ff, C->node_src, C->rc_cap, C->n_nodes, s));
+    HIP_TRY(launch_permute_caps(cap_ff, C->node_src, C->rc_cap, C->n_nodes, C->rc_pc, C->n_small_nodes, s));
   } else {
     return fail(STA_E_ARG, "bad mem");
   }

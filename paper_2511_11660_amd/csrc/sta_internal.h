@@ -86,10 +86,11 @@ struct DevDesign {
 
   // RC nodes
   const uint8_t *rc_par8;     // net-local parent of a small-net node (root: 0, unused); 0 on wide nets
-  const float *rc_pc;         // receiving pin caps lumped at each node (fixed), summed in sink order
+  const float *rc_pc;         // receiving pin caps lumped at each small-net node (fixed), summed in sink
+                              // order; added into rc_cap whenever the wire caps are set
   const int2 *rc_sinks;       // [small nets] sink-slot range at each RC position
   const float *rc_res;
-  const float *rc_cap;
+  const float *rc_cap;        // small nets: wire cap + rc_pc (one float sum); wide nets: the wire cap
 
   // endpoints
   const float4 *ep_rat;       // [n_ep]
@@ -317,6 +318,6 @@ hipError_t launch_report_rc(const DevDesign &D, const int32_t *net_slot, int n_n
                             const int32_t *sink_slot, int n_sinks, float *net_load,
                             float *sink_delay, float *sink_spread, hipStream_t s);
 hipError_t launch_permute_caps(const float *src, const int32_t *node_src, float *dst, int64_t n,
-                               hipStream_t s);
+                               const float *pc, int64_t n_small, hipStream_t s);
 
 }  // namespace sta

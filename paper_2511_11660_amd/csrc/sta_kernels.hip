@@ -2330,12 +2330,6 @@ __global__ void k_inc_seed(DevDesign D, IncArgs I, const int32_t *nets, int n) {
 
 // ------------------------------------------------------------------ RC
 
-// Elmore recursions on one tree held in LDS (nodes b..b+m-1, parent < child):
-//   load = subtree sum of C^ (bottom-up), d = d(parent) + R load (top-down),
-//   ld = subtree sum of C^ d (bottom-up), m2 = m2(parent) + R ld (top-down).
-// On return A holds m2 and B holds d; the result is the root load.
-// On entry A holds C^ (staged); four passes, the C^ d products formed in the
-// d pass (a node's load is not read again once its d is known).
 __device__ __forceinline__ float rc_tree_lds(const uint8_t *par, const float *R, const float *C,
                                              float *A, float *B, int b, int m) {
   for (int k = m - 1; k >= 1; --k) A[b + par[b + k]] += A[b + k];
@@ -2343,9 +2337,10 @@ __device__ __forceinline__ float rc_tree_lds(const uint8_t *par, const float *R,
   B[b] = 0.0f;
   A[b] = 0.0f;
   for (int k = 1; k < m; ++k) {
+    const float c = C[b + k];  // read before B[b + k] is written: B may be C
     const float d = B[b + par[b + k]] + R[b + k] * A[b + k];
     B[b + k] = d;
-    A[b + k] = C[b + k] * d;
+    A[b + k] = c * d;
   }
   for (int k = m - 1; k >= 1; --k) A[b + par[b + k]] += A[b + k];
   A[b] = 0.0f;
@@ -2761,14 +2756,13 @@ __device__ __forceinline__ void stage_rc_nodes(const DevDesign &D, int k0, int n
   const int tid = threadIdx.x;
   const int last = k0 + max(nk - 1, 0);
   uint8_t p[kPer];
-  float r[kPer], c[kPer], pc[kPer];
+  float r[kPer], c[kPer];
 #pragma unroll
   for (int u = 0; u < kPer; ++u) {
     const int i = min(k0 + u * kRcBlock + tid, last);
     p[u] = D.rc_par8[i];
     r[u] = D.rc_res[i];
-    c[u] = D.rc_cap[i];
-    pc[u] = D.rc_pc[i];
+    c[u] = D.rc_cap[i];  // wire + pin caps (C^)
   }
 #pragma unroll
   for (int u = 0; u < kPer; ++u) {
@@ -2776,8 +2770,8 @@ __device__ __forceinline__ void stage_rc_nodes(const DevDesign &D, int k0, int n
     if (i < nk) {
       par[i] = p[u];
       R[i] = r[u];
-      C[i] = c[u] + pc[u];
-      A[i] = C[i];
+      C[i] = c[u];
+      A[i] = c[u];
     }
   }
 }
@@ -2867,13 +2861,14 @@ __device__ __forceinline__ void rc_reduced_sinks(const DevDesign &D, bool live, 
 // per thread, each thread writing its net's load and sink moments (kRed: the
 // sink delays of the reduced-order model instead of Elmore's).  Block 0 also
 // clears the sweep counters for the launches that follow.
+// The Elmore form keeps its LDS at 27,136 bytes, six blocks per CU (the
+// register limit; 35,844 bytes held it to four, 12% slower): the delays
+// overwrite C^ in place and the nets' node offsets are 16-bit, the last net
+// ending at the chunk's end.
 // only: optional per-chunk flags (incremental update: unflagged chunks return).
 template <bool kRed>
 __global__ __launch_bounds__(kRcBlock) void k_rc(DevDesign D, const int2 *chunks, int n_chunks,
                                                  uint32_t *counters, int n_counters, const uint32_t *only) {
-  __shared__ uint8_t s_par[kRcChunkNodes];
-  __shared__ float s_R[kRcChunkNodes], s_C[kRcChunkNodes], s_A[kRcChunkNodes], s_B[kRcChunkNodes];
-  __shared__ int s_base[kRcBlock + 1];
   const int tid = threadIdx.x;
   if (blockIdx.x == 0)
     for (int i = tid; i < n_counters; i += kRcBlock) counters[i] = 0u;
@@ -2886,49 +2881,59 @@ __global__ __launch_bounds__(kRcBlock) void k_rc(DevDesign D, const int2 *chunks
   const int jc = j < j1 ? j : j0;
   const int x = D.rc_order[jc];
   const int2 sr = D.rc_sinks[jc];
-  stage_rc_nodes(D, k0, nk, s_par, s_R, s_C, s_A);
-  for (int i = tid; i <= j1 - j0; i += kRcBlock) s_base[i] = D.rc_start[j0 + i] - k0;
-  // the first sinks' node ids, in flight across the tree passes
-  constexpr int kPre = 4;
-  int sn[kPre];
-#pragma unroll
-  for (int u = 0; u < kPre; ++u) sn[u] = D.sink_node[min(sr.x + u, max(sr.y - 1, 0))];
-  lds_barrier();
   if constexpr (kRed) {  // reduced-order delays replace the Elmore ones
+    __shared__ uint8_t s_par[kRcChunkNodes];
+    __shared__ float s_R[kRcChunkNodes], s_C[kRcChunkNodes], s_A[kRcChunkNodes], s_B[kRcChunkNodes];
+    __shared__ int s_base[kRcBlock + 1];
+    stage_rc_nodes(D, k0, nk, s_par, s_R, s_C, s_A);
+    for (int i = tid; i <= j1 - j0; i += kRcBlock) s_base[i] = D.rc_start[j0 + i] - k0;
+    lds_barrier();
     if (j < j1) {
       const float L = rc_tree_lds(s_par, s_R, s_C, s_A, s_B, s_base[tid], s_base[tid + 1] - s_base[tid]);
       D.L_net[x] = L;
       if (D.rc_cons_l) D.cons_rec[x].L = L;
     }
     rc_reduced_sinks(D, j < j1, j < j1 ? sr : make_int2(0, 0), s_C, s_A, s_B, s_base);
-    return;
-  }
-  if (j < j1) {
-    const int b = s_base[tid], m = s_base[tid + 1] - b;
-    const int s0 = sr.x, s1 = sr.y;
-    const float L = rc_tree_lds(s_par, s_R, s_C, s_A, s_B, b, m);
-    D.L_net[x] = L;
-    if (D.rc_cons_l) D.cons_rec[x].L = L;
+  } else {
+    __shared__ uint8_t s_par[kRcChunkNodes];
+    __shared__ float s_R[kRcChunkNodes], s_C[kRcChunkNodes], s_A[kRcChunkNodes];
+    __shared__ uint16_t s_base[kRcBlock];
+    static_assert(kRcChunkNodes <= 65536, "16-bit node offsets");
+    stage_rc_nodes(D, k0, nk, s_par, s_R, s_C, s_A);
+    for (int i = tid; i < j1 - j0; i += kRcBlock) s_base[i] = (uint16_t)(D.rc_start[j0 + i] - k0);
+    // the first sinks' node ids, in flight across the tree passes
+    constexpr int kPre = 4;
+    int sn[kPre];
 #pragma unroll
-    for (int u = 0; u < kPre; ++u) {
-      if (s0 + u < s1) {
-        const int k = b + sn[u];
-        const float d = s_B[k];
-        D.dq[s0 + u] = make_float2(d, fmaxf(0.0f, 2.0f * s_A[k] - d * d));
+    for (int u = 0; u < kPre; ++u) sn[u] = D.sink_node[min(sr.x + u, max(sr.y - 1, 0))];
+    lds_barrier();
+    if (j < j1) {
+      const int b = s_base[tid], m = (j + 1 < j1 ? (int)s_base[tid + 1] : nk) - b;
+      const int s0 = sr.x, s1 = sr.y;
+      const float L = rc_tree_lds(s_par, s_R, s_C, s_A, s_C, b, m);  // d in s_C, m2 in s_A
+      D.L_net[x] = L;
+      if (D.rc_cons_l) D.cons_rec[x].L = L;
+#pragma unroll
+      for (int u = 0; u < kPre; ++u) {
+        if (s0 + u < s1) {
+          const int k = b + sn[u];
+          const float d = s_C[k];
+          D.dq[s0 + u] = make_float2(d, fmaxf(0.0f, 2.0f * s_A[k] - d * d));
+        }
       }
-    }
-    // the rest in rounds of kSinkRound: every node id of a round requested
-    // before any is used (clamped, unpredicated loads and stores: a lane past
-    // the net's last sink repeats that sink's write), one round trip a round
-    for (int s = s0 + kPre; s < s1; s += kSinkRound) {
-      int kk[kSinkRound];
+      // the rest in rounds of kSinkRound: every node id of a round requested
+      // before any is used (clamped, unpredicated loads and stores: a lane past
+      // the net's last sink repeats that sink's write), one round trip a round
+      for (int s = s0 + kPre; s < s1; s += kSinkRound) {
+        int kk[kSinkRound];
 #pragma unroll
-      for (int u = 0; u < kSinkRound; ++u) kk[u] = D.sink_node[min(s + u, s1 - 1)];
+        for (int u = 0; u < kSinkRound; ++u) kk[u] = D.sink_node[min(s + u, s1 - 1)];
 #pragma unroll
-      for (int u = 0; u < kSinkRound; ++u) {
-        const int k = b + kk[u];
-        const float d = s_B[k];
-        D.dq[min(s + u, s1 - 1)] = make_float2(d, fmaxf(0.0f, 2.0f * s_A[k] - d * d));
+        for (int u = 0; u < kSinkRound; ++u) {
+          const int k = b + kk[u];
+          const float d = s_C[k];
+          D.dq[min(s + u, s1 - 1)] = make_float2(d, fmaxf(0.0f, 2.0f * s_A[k] - d * d));
+        }
       }
     }
   }
@@ -3639,9 +3644,15 @@ __global__ void k_report_rc(DevDesign D, const int32_t *net_slot, int n_nets, co
   }
 }
 
-__global__ void k_permute_caps(const float *src, const int32_t *node_src, float *dst, int64_t n) {
+// Wire caps into the layout; the small nets' nodes (the first n_small) also
+// take their lumped receiving pin caps, the sum the RC pass reads.
+__global__ void k_permute_caps(const float *src, const int32_t *node_src, float *dst, int64_t n, const float *pc,
+                               int64_t n_small) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < n) dst[k] = src[node_src[k]];
+  if (k < n) {
+    const float c = src[node_src[k]];
+    dst[k] = k < n_small ? c + pc[k] : c;
+  }
 }
 
 inline int blocks_for(int64_t n, int b) { return (int)((n + b - 1) / b); }
@@ -4261,9 +4272,10 @@ hipError_t launch_report_rc(const DevDesign &D, const int32_t *net_slot, int n_n
 }
 
 hipError_t launch_permute_caps(const float *src, const int32_t *node_src, float *dst, int64_t n,
-                               hipStream_t s) {
+                               const float *pc, int64_t n_small, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_permute_caps, dim3(blocks_for(n, 256)), dim3(256), 0, s, src, node_src, dst, n);
+  hipLaunchKernelGGL(k_permute_caps, dim3(blocks_for(n, 256)), dim3(256), 0, s, src, node_src, dst, n, pc,
+                     n_small);
   return hipGetLastError();
 }
 
