@@ -174,6 +174,8 @@ struct sta_ctx {
   int32_t *inc_host = nullptr;         // pinned staging of the list
   int inc_cap = 0;                     // capacity of both (ids)
   hipEvent_t inc_ev = nullptr;         // staging reusable once this has passed
+  std::unique_ptr<DevMem> path_ws;     // path report workspace (grows, kept between reports)
+  size_t path_ws_bytes = 0;
 
   template <class T>
   sta_status alloc(T **out_p, size_t n) {
@@ -2655,6 +2657,34 @@ extern "C" sta_status sta_autotune(sta_ctx *C, int32_t reps, sta_tune_result *be
   return STA_OK;
 }
 
+// Pieces of one device buffer, each 256-byte aligned: a first pass with no
+// base only adds up the size.
+struct Carve {
+  unsigned char *base = nullptr;
+  size_t off = 0;
+  template <class T>
+  T *take(size_t n) {
+    off = (off + 255) & ~(size_t)255;
+    T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+    off += std::max<size_t>(n, 1) * sizeof(T);
+    return p;
+  }
+};
+
+// The path workspace holds at least `bytes` (its old contents are dropped;
+// every report ends synchronized, so nothing still uses them).
+static sta_status path_ws_reserve(sta_ctx *C, size_t bytes) {
+  if (C->path_ws && C->path_ws_bytes >= bytes) return STA_OK;
+  C->path_ws.reset();
+  C->path_ws_bytes = 0;
+  auto m = std::make_unique<DevMem>();
+  const hipError_t e = hipMalloc(&m->p, bytes);
+  if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+  C->path_ws = std::move(m);
+  C->path_ws_bytes = bytes;
+  return STA_OK;
+}
+
 extern "C" sta_status sta_report_paths(sta_ctx *C, const sta_path_query *q, int32_t *n_paths, int32_t *path_ptr,
                                        int32_t *path_pin, int8_t *path_rf, float *path_slack, int32_t *path_endpoint,
                                        sta_mem dst, void *stream) {
@@ -2675,18 +2705,13 @@ extern "C" sta_status sta_report_paths(sta_ctx *C, const sta_path_query *q, int3
   // slack (each holds a path of its own slack), and only those below the
   // threshold (no path of an endpoint is better than its slack)
   const int cand = std::min(q->k, ne);
-  std::vector<int32_t> ord(cand);
-  std::vector<float2> eps(ne);
-  if (cand > 0) {
-    HIP_TRY(hipMemcpyAsync(ord.data(), C->order + (size_t)el * ne, cand * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(eps.data(), C->D.ep_slack, ne * sizeof(float2), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-  }
   int n_sel = 0;
-  while (n_sel < cand) {
-    const float sl = el ? eps[ord[n_sel]].y : eps[ord[n_sel]].x;
-    if (!(sl < q->slack_below)) break;
-    ++n_sel;
+  if (cand > 0) {  // counted on the device: the leading endpoints below the threshold
+    STA_TRY(path_ws_reserve(C, 256));
+    int32_t *cnt = static_cast<int32_t *>(C->path_ws->p);
+    HIP_TRY(launch_paths_count(C->D, C->order + (size_t)el * ne, cand, el, q->slack_below, cnt, s));
+    HIP_TRY(hipMemcpyAsync(&n_sel, cnt, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
   }
   if (n_sel == 0) {
     const int32_t zero = 0;
@@ -2698,67 +2723,70 @@ extern "C" sta_status sta_report_paths(sta_ctx *C, const sta_path_query *q, int3
     return STA_OK;
   }
   const int lmax = C->n_levels;
-  // heap bound: every pop pushes at most 2 max_in - 1 items per cell output on
-  // its path, and a path has at most lmax / 2 + 1 cell outputs
-  const int cap = m * ((lmax / 2 + 1) * (2 * C->max_in - 1) + 2);
-  const double bytes = (double)n_sel * ((double)cap * 16 + (double)m * lmax * 4 + m * 8.0);
-  if (bytes > 16e9) return fail(STA_E_UNSUPPORTED, "path search needs %.1f GB of scratch", bytes / 1e9);
-  sta_ctx tmp;
+  // each endpoint keeps at most m pending items (in LDS when they fit beside
+  // the library), its m paths of at most lmax nodes, their lengths and slacks;
+  // then the global selection and the output, all in the kept workspace
+  // (STA_PATH_QUEUES_GLOBAL set in the environment forces the global-memory
+  // queues, so that both forms can be compared)
+  const bool q_lds = paths_queue_lds_bytes(C->D, m) <= 160 * 1024 && !std::getenv("STA_PATH_QUEUES_GLOBAL");
+  const int nc = n_sel * m, top = std::min(q->k, nc);
+  const size_t sb = sort_temp_bytes(nc);
+  size_t xb = 0;
+  HIP_TRY(exclusive_sum(nullptr, xb, nullptr, nullptr, top + 1, s));
   PathArgs A{};
+  uint32_t *keys, *keys_out;
+  int32_t *vals, *vals_out, *len, *ptr, *pin, *pe;
+  unsigned char *stemp, *xtemp;
+  int8_t *prf;
+  float *psl;
+  for (int pass = 0; pass < 2; ++pass) {
+    Carve cv;
+    if (pass == 1) cv.base = static_cast<unsigned char *>(C->path_ws->p);
+    A.items = q_lds ? nullptr : cv.take<int4>((size_t)n_sel * m);
+    A.nodes = cv.take<int32_t>((size_t)n_sel * m * lmax);
+    A.plen = cv.take<int32_t>((size_t)nc);
+    A.pkey = cv.take<float>((size_t)nc);
+    keys = cv.take<uint32_t>(nc);
+    keys_out = cv.take<uint32_t>(nc);
+    vals = cv.take<int32_t>(nc);
+    vals_out = cv.take<int32_t>(nc);
+    stemp = cv.take<unsigned char>(sb);
+    len = cv.take<int32_t>((size_t)top + 1);
+    ptr = cv.take<int32_t>((size_t)top + 1);
+    xtemp = cv.take<unsigned char>(xb);
+    pin = cv.take<int32_t>((size_t)top * lmax);
+    prf = cv.take<int8_t>((size_t)top * lmax);
+    psl = cv.take<float>((size_t)top);
+    pe = cv.take<int32_t>((size_t)top);
+    if (pass == 0) {
+      if ((double)cv.off > 16e9) return fail(STA_E_UNSUPPORTED, "path search needs %.1f GB of scratch", cv.off / 1e9);
+      STA_TRY(path_ws_reserve(C, cv.off));
+    }
+  }
   A.eps = C->order + (size_t)el * ne;
   A.n_eps = n_sel;
   A.el = el;
   A.m = m;
   A.lmax = lmax;
-  A.cap = cap;
   A.thr = q->slack_below;
   A.drv_pin = C->slot_drv_pin;
   A.sink_pin = C->slot_sink_pin;
-  STA_TRY(tmp.alloc(&A.items, (size_t)n_sel * cap));
-  STA_TRY(tmp.alloc(&A.nodes, (size_t)n_sel * m * lmax));
-  STA_TRY(tmp.alloc(&A.plen, (size_t)n_sel * m));
-  STA_TRY(tmp.alloc(&A.pkey, (size_t)n_sel * m));
   HIP_TRY(launch_paths_enum(C->D, A, s));
   // global selection: ascending slack over every found path (ties in
   // endpoint order, then path order)
-  const int nc = n_sel * m;
-  uint32_t *keys, *keys_out;
-  int32_t *vals, *vals_out;
-  STA_TRY(tmp.alloc(&keys, nc));
-  STA_TRY(tmp.alloc(&keys_out, nc));
-  STA_TRY(tmp.alloc(&vals, nc));
-  STA_TRY(tmp.alloc(&vals_out, nc));
   HIP_TRY(launch_paths_keys(A, keys, vals, s));
-  size_t sb = sort_temp_bytes(nc);
-  unsigned char *stemp;
-  STA_TRY(tmp.alloc(&stemp, sb));
   HIP_TRY(sort_endpoints(stemp, sb, keys, keys_out, vals, vals_out, nc, s));
-  const int top = std::min(q->k, nc);
   std::vector<uint32_t> hk(top);
   HIP_TRY(hipMemcpyAsync(hk.data(), keys_out, top * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   int n_out = 0;
   while (n_out < top && hk[n_out] != 0xffffffffu) ++n_out;
-  int32_t *len, *ptr;
-  STA_TRY(tmp.alloc(&len, n_out + 1));
-  STA_TRY(tmp.alloc(&ptr, n_out + 1));
   HIP_TRY(hipMemsetAsync(len, 0, (n_out + 1) * sizeof(int32_t), s));
   HIP_TRY(launch_paths_lengths(A, vals_out, n_out, len, s));
-  size_t xb = 0;
-  HIP_TRY(exclusive_sum(nullptr, xb, len, ptr, n_out + 1, s));
-  unsigned char *xtemp;
-  STA_TRY(tmp.alloc(&xtemp, xb));
-  HIP_TRY(exclusive_sum(xtemp, xb, len, ptr, n_out + 1, s));
+  HIP_TRY(exclusive_sum(xtemp, xb, len, ptr, n_out + 1, s));  // (scratch sized for top + 1 items)
   int32_t total = 0;
   HIP_TRY(hipMemcpyAsync(&total, ptr + n_out, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  int32_t *pin = nullptr, *pe = nullptr;
-  int8_t *prf = nullptr;
-  float *psl = nullptr;
-  STA_TRY(tmp.alloc(&pin, std::max(total, 1)));
-  STA_TRY(tmp.alloc(&prf, std::max(total, 1)));
-  STA_TRY(tmp.alloc(&psl, std::max(n_out, 1)));
-  STA_TRY(tmp.alloc(&pe, std::max(n_out, 1)));
   HIP_TRY(launch_paths_emit(C->D, A, vals_out, n_out, ptr, pin, prf, psl, pe, s));
   STA_TRY(deliver(path_ptr, ptr, (size_t)(n_out + 1) * 4, dst, s));
   STA_TRY(deliver(path_pin, pin, (size_t)total * 4, dst, s));

@@ -294,14 +294,18 @@ hipError_t launch_iota(int32_t *a, int n, hipStream_t s);
 // deviations from the critical fanins (one thread per endpoint)
 struct PathArgs {
   const int32_t *eps;   // [n_eps] endpoint indices, ascending endpoint slack
-  int n_eps, el, m, lmax, cap;
+  int n_eps, el, m, lmax;
   float thr;
-  int4 *items;          // [n_eps * cap] heap items (key bits, sequence, parent << 24 | position, node)
+  int4 *items;          // [m][n_eps] queue items (key bits, sequence, parent << 24 | position, node), or
+                        // null: the queues are in LDS
   int32_t *nodes;       // [n_eps * m * lmax] path nodes, endpoint first
   int32_t *plen;        // [n_eps * m] path lengths (0: none)
   float *pkey;          // [n_eps * m] path slacks
   const int32_t *drv_pin, *sink_pin;  // slot -> caller pin
 };
+size_t paths_queue_lds_bytes(const DevDesign &D, int m);  // library + LDS queues of one block
+hipError_t launch_paths_count(const DevDesign &D, const int32_t *ord, int cand, int el, float thr, int32_t *out,
+                              hipStream_t s);
 hipError_t launch_paths_enum(const DevDesign &D, const PathArgs &A, hipStream_t s);
 hipError_t launch_paths_keys(const PathArgs &A, uint32_t *keys, int32_t *vals, hipStream_t s);
 hipError_t launch_paths_emit(const DevDesign &D, const PathArgs &A, const int32_t *sel, int n_sel,

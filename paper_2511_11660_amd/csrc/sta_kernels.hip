@@ -3679,32 +3679,38 @@ __device__ __forceinline__ bool item_less(int4 a, int4 b) {
   return ka < kb || (ka == kb && a.y < b.y);
 }
 
-__device__ void heap_push(int4 *h, int &n, int4 it) {
-  int i = n++;
-  while (i > 0) {
-    const int p = (i - 1) >> 1;
-    if (!item_less(it, h[p])) break;
-    h[i] = h[p];
-    i = p;
+// An endpoint's pending items, ascending in (key, sequence), in column i * stride
+// of q (LDS or global memory).  Only the best lim of them are kept, lim the pops
+// still to come: an item pushed later carries at least the key just popped, so
+// an item that ranks beyond the remaining pops can never be popped.  Items live
+// in positions [h, h + n) with h + lim = m throughout.
+struct PathQueue {
+  int4 *q;
+  int stride, h, n, lim;
+  __device__ __forceinline__ int4 at(int i) const { return q[(size_t)i * stride]; }
+  __device__ __forceinline__ void set(int i, int4 v) { q[(size_t)i * stride] = v; }
+  __device__ void push(int4 it) {
+    if (n == lim) {
+      if (n == 0 || !item_less(it, at(h + n - 1))) return;
+      --n;  // the last falls out
+    }
+    int p = h + n;
+    while (p > h && item_less(it, at(p - 1))) {
+      set(p, at(p - 1));
+      --p;
+    }
+    set(p, it);
+    ++n;
   }
-  h[i] = it;
-}
-
-__device__ int4 heap_pop(int4 *h, int &n) {
-  const int4 top = h[0];
-  const int4 last = h[--n];
-  int i = 0;
-  for (;;) {
-    int c = 2 * i + 1;
-    if (c >= n) break;
-    if (c + 1 < n && item_less(h[c + 1], h[c])) ++c;
-    if (!item_less(h[c], last)) break;
-    h[i] = h[c];
-    i = c;
+  __device__ int4 pop() {  // n > 0
+    const int4 top = at(h);
+    ++h;
+    --n;
+    --lim;
+    n = min(n, lim);
+    return top;
   }
-  if (n > 0) h[i] = last;
-  return top;
-}
+};
 
 __device__ __forceinline__ float node_at(const DevDesign &D, int code, int el) {
   const int slot = code >> 1, v = el * 2 + (code & 1);
@@ -3718,14 +3724,27 @@ __device__ __forceinline__ float node_slew(const DevDesign &D, int code, int el)
   return v == 0 ? a.x : v == 1 ? a.y : v == 2 ? a.z : a.w;
 }
 
-__global__ __launch_bounds__(256) void k_paths_enum(DevDesign D, PathArgs A) {
+// One thread per endpoint (blocks of one wavefront, so the endpoints spread
+// over the compute units); its queue in LDS after the library when both fit,
+// else in A.items.
+__global__ __launch_bounds__(kWave) void k_paths_enum(DevDesign D, PathArgs A) {
   extern __shared__ __align__(32) unsigned char smem[];
   const LdsLib lib = load_lib(D, smem);
   __syncthreads();
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= A.n_eps) return;
   const int el = A.el, m = A.m, lmax = A.lmax;
-  int4 *h = A.items + (size_t)t * A.cap;
+  PathQueue Q;
+  if (A.items) {
+    Q.q = A.items + t;
+    Q.stride = A.n_eps;
+  } else {
+    Q.q = reinterpret_cast<int4 *>(smem + lib_lds_bytes(D.n_types, D.tstride)) + threadIdx.x;
+    Q.stride = kWave;
+  }
+  Q.h = 0;
+  Q.n = 0;
+  Q.lim = m;
   int32_t *nodes = A.nodes + (size_t)t * m * lmax;
   int32_t *plen = A.plen + (size_t)t * m;
   float *pkey = A.pkey + (size_t)t * m;
@@ -3734,7 +3753,7 @@ __global__ __launch_bounds__(256) void k_paths_enum(DevDesign D, PathArgs A) {
   const int loc = D.ep_loc[e];
   const int slot = loc >= 0 ? loc : D.n_drv + (-1 - loc);
   const float4 R = D.ep_rat[e];
-  int n = 0, seq = 0;
+  int seq = 0;
   for (int rf = 0; rf < 2; ++rf) {
     const int v = el * 2 + rf;
     const float rat = v == 0 ? R.x : v == 1 ? R.y : v == 2 ? R.z : R.w;
@@ -3742,11 +3761,11 @@ __global__ __launch_bounds__(256) void k_paths_enum(DevDesign D, PathArgs A) {
     const int code = slot * 2 + rf;
     const float a = node_at(D, code, el);
     const float key = el ? rat - a : a - rat;
-    heap_push(h, n, make_int4(__float_as_int(key), seq++, -1, code));
+    Q.push(make_int4(__float_as_int(key), seq++, -1, code));
   }
   const TabLayout lay{D.nx, D.ny};
-  for (int j = 0; j < m && n > 0; ++j) {
-    const int4 it = heap_pop(h, n);
+  for (int j = 0; j < m && Q.n > 0; ++j) {
+    const int4 it = Q.pop();
     const float key = __int_as_float(it.x);
     if (!(key < A.thr)) break;
     int32_t *path = nodes + (size_t)j * lmax;
@@ -3766,6 +3785,55 @@ __global__ __launch_bounds__(256) void k_paths_enum(DevDesign D, PathArgs A) {
       }
       if (sl < D.n_pi) break;  // startpoint
       const int v = el * 2 + rf;
+      if (D.fanin4) {
+        // the cell's loads in one round trip (fanin ids inline), then the
+        // critical input's driver and every input state in the next; the
+        // sidetracks are pushed in the same (input, transition) order
+        const uint32_t cw = D.drv_crit[sl];
+        const float at_out = node_at(D, code, el);
+        const int ty = D.cell_type[sl];
+        const float Lc = D.L_net[sl];
+        const int4 f4 = D.fanin4[sl];
+        const int fin[4] = {f4.x, f4.y, f4.z, f4.w};
+        const int crit = (int)((cw >> (8 * v)) & 0xffu);
+        const int cs = fin[min(crit >> 1, 3)];
+        const int nd = D.sink_drv[max(cs, 0)];  // (unused when the cell has no critical input)
+        float4 iat[4], isl[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const PinState &ps = D.sink_state[max(fin[k], 0)];
+          iat[k] = ps.at;
+          isl[k] = ps.slew;
+        }
+        const CellCtx cc = cell_ctx(D, lib, ty, Lc);
+        bool has_crit = false;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          if (fin[k] < 0) continue;
+#pragma unroll
+          for (int ri = 0; ri < 2; ++ri) {
+            if (!arc_maps(cc.sense, ri, rf)) continue;
+            if (k * 2 + ri == crit) {
+              has_crit = true;
+              continue;
+            }
+            const int w = el * 2 + ri;
+            const float x = w == 0 ? isl[k].x : w == 1 ? isl[k].y : w == 2 ? isl[k].z : isl[k].w;
+            const float ain = w == 0 ? iat[k].x : w == 1 ? iat[k].y : w == 2 ? iat[k].z : iat[k].w;
+            const AxisPos px = axis_find(cc.tb + lay.xa(), cc.tb + lay.rdx(), D.nx, x);
+            const float dl = bilerp(cc.tb + lay.tab(rf), D.ny, px, cc.py);
+            const float cand = ain + dl;
+            const float dev = fmaxf(el ? at_out - cand : cand - at_out, 0.0f);
+            const float k2 = key + dev;
+            if (k2 < A.thr)
+              Q.push(make_int4(__float_as_int(k2), seq++, (j << 24) | len, (D.n_drv + fin[k]) * 2 + ri));
+          }
+        }
+        if (!has_crit) break;  // (every cell output has a critical candidate)
+        path[len++] = (D.n_drv + cs) * 2 + (crit & 1);  // the critical input sink, then its driver
+        code = nd * 2 + (crit & 1);
+        continue;
+      }
       const int crit = (int)((D.drv_crit[sl] >> (8 * v)) & 0xffu);
       const float at_out = node_at(D, code, el);
       const CellCtx cc = cell_ctx(D, lib, D.cell_type[sl], D.L_net[sl]);
@@ -3786,7 +3854,7 @@ __global__ __launch_bounds__(256) void k_paths_enum(DevDesign D, PathArgs A) {
           const float cand = node_at(D, in_code, el) + dl;
           const float dev = fmaxf(el ? at_out - cand : cand - at_out, 0.0f);
           const float k2 = key + dev;
-          if (k2 < A.thr && n < A.cap) heap_push(h, n, make_int4(__float_as_int(k2), seq++, (j << 24) | len, in_code));
+          if (k2 < A.thr) Q.push(make_int4(__float_as_int(k2), seq++, (j << 24) | len, in_code));
         }
       }
       if (next < 0) break;  // (every cell output has a critical candidate)
@@ -4280,10 +4348,34 @@ hipError_t launch_permute_caps(const float *src, const int32_t *node_src, float 
 }
 
 
+__global__ void k_set_i32(int32_t *p, int32_t v) { *p = v; }
+
+// The leading endpoints in slack order whose slack is below thr: the first
+// failing position (cand when none fails).
+__global__ void k_paths_count(const float2 *ep_slack, const int32_t *ord, int cand, int el, float thr, int32_t *out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= cand) return;
+  const float2 e = ep_slack[ord[i]];
+  if (!((el ? e.y : e.x) < thr)) atomicMin(out, i);
+}
+
+hipError_t launch_paths_count(const DevDesign &D, const int32_t *ord, int cand, int el, float thr, int32_t *out,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(1), 0, s, out, (int32_t)cand);
+  if (cand > 0)
+    hipLaunchKernelGGL(k_paths_count, dim3(blocks_for(cand, 256)), dim3(256), 0, s, D.ep_slack, ord, cand, el, thr,
+                       out);
+  return hipGetLastError();
+}
+
+size_t paths_queue_lds_bytes(const DevDesign &D, int m) {
+  return lib_lds_bytes(D.n_types, D.tstride) + sizeof(int4) * (size_t)kWave * m;
+}
+
 hipError_t launch_paths_enum(const DevDesign &D, const PathArgs &A, hipStream_t s) {
   if (A.n_eps <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_paths_enum, dim3(blocks_for(A.n_eps, 256)), dim3(256), lib_lds_bytes(D.n_types, D.tstride),
-                     s, D, A);
+  const size_t lds = A.items ? lib_lds_bytes(D.n_types, D.tstride) : paths_queue_lds_bytes(D, A.m);
+  hipLaunchKernelGGL(k_paths_enum, dim3(blocks_for(A.n_eps, kWave)), dim3(kWave), lds, s, D, A);
   return hipGetLastError();
 }
 

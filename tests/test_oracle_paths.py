@@ -10,10 +10,10 @@ from designs import CIN, COUT, PI, PO, make_design, planar_table, single_segment
 from oracle import paths as P
 
 
-def small_dag(seed, n_pi=5, levels=3, per_level=4):
-    """A small random timing DAG (every cell of 1-3 inputs drawn from earlier
-    levels, multi-sink star nets, mixed unateness) whose paths can all be
-    enumerated."""
+def small_dag(seed, n_pi=5, levels=3, per_level=4, n_inputs=(1, 2, 3, 2)):
+    """A small random timing DAG (every cell of 1-3 inputs, or of the four
+    types' n_inputs, drawn from earlier levels, multi-sink star nets, mixed
+    unateness) whose paths can all be enumerated."""
     rng = np.random.default_rng(seed)
     kinds, cells, sinks_of = [], [], {}
 
@@ -25,7 +25,7 @@ def small_dag(seed, n_pi=5, levels=3, per_level=4):
     for p in pis:
         sinks_of[p] = []
     avail, prev = list(pis), list(pis)
-    n_inputs = [1, 2, 3, 2]
+    n_inputs = list(n_inputs)
     for _ in range(levels):
         outs = []
         for _ in range(per_level):

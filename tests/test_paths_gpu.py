@@ -75,6 +75,41 @@ def test_paths_small_dags(seed, sched):
     s.close()
 
 
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_paths_five_input_cells(seed):
+    """A library type of five inputs: the walk reads each cell's fanins from
+    the CSR lists instead of the inline four."""
+    d = small_dag(seed, n_inputs=(1, 2, 5, 2))
+    assert max(d.n_inputs) == 5
+    r = oracle.sta(d)
+    s = STA(d)
+    s.update()
+    for el in (0, 1):
+        for k, m, thr in [(25, 3, np.inf), (500, 64, np.inf), (40, 5, 5.0)]:
+            got = s.paths(k, m, thr, el)
+            ref = P.top_paths(d, k, m, thr, el, r)
+            _compare(d, got, ref, r, el, thr, k, m)
+    s.close()
+
+
+def test_paths_queues_in_global_memory(monkeypatch):
+    """The endpoint queues in global memory (taken when they and the library
+    do not fit in LDS) give the same report as the LDS queues."""
+    d = synth.generate(synth.mid_config(seed=19, n_cells=30_000, n_levels=25))
+    s = STA(d)
+    s.update()
+    cases = [(300, 8, np.inf, 1), (200, 64, np.inf, 0), (100, 3, 0.0, 1)]
+    lds = [s.paths(*c) for c in cases]
+    monkeypatch.setenv("STA_PATH_QUEUES_GLOBAL", "1")
+    glob = [s.paths(*c) for c in cases]
+    s.close()
+    for a, b in zip(lds, glob):
+        assert len(a) == len(b) and len(a) > 0
+        for p, q in zip(a, b):
+            assert p["endpoint"] == q["endpoint"] and p["slack"] == q["slack"]
+            assert list(p["pins"]) == list(q["pins"]) and list(p["rf"]) == list(q["rf"])
+
+
 def test_paths_tiny_design():
     d = synth.generate(synth.tiny_config(seed=5, dangling_policy=1))
     r = oracle.sta(d)
