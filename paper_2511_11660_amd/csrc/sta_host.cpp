@@ -2386,8 +2386,10 @@ extern "C" sta_status sta_backward(sta_ctx *C, float g_tns, float g_wns, float *
   const bool prof = C->opt.profile != 0;
   const DevDesign &D = C->D;
   if (prof) HIP_TRY(hipEventRecord(C->ev[7], s));
-  // the reverse sweep runs one launch per level in every schedule
-  for (const int4 &ph : C->ph_adj) HIP_TRY(launch_adjoint_phase(D, g_tns, g_wns, ph, s));
+  // the reverse sweep runs one launch per level in every schedule, then the
+  // RC adjoint (run beside the sweep in level groups, it slowed both: 0.90 ->
+  // 1.01 ms on the 1M-pin design)
+  for (const int4 &ph : C->ph_adj) HIP_TRY(launch_adjoint_phase(D, g_tns, g_wns, ph, C->lvl_reg[ph.w].z, s));
   if (prof) HIP_TRY(hipEventRecord(C->ev[8], s));
   STA_TRY(enqueue_rc(C, s, true, grad_wire_res != nullptr));
   if (prof) HIP_TRY(hipEventRecord(C->ev[9], s));

@@ -249,7 +249,7 @@ hipError_t launch_level_floor(const int32_t *idx, const void *src, void *dst, in
 // early/late above the slack bits, and their endpoint indices in vals
 hipError_t launch_reduce_smooth(const DevDesign &D, double *partials, double *out, uint64_t *keys,
                                 int32_t *vals, hipStream_t s);
-hipError_t launch_adjoint_phase(const DevDesign &D, float g_tns, float g_wns, int4 phase, hipStream_t s);
+hipError_t launch_adjoint_phase(const DevDesign &D, float g_tns, float g_wns, int4 phase, int lib_f4, hipStream_t s);
 // res: also dJ/dR (D.g_res) for the small nets; the wide nets always write it
 hipError_t launch_rc_adjoint(const DevDesign &D, const int2 *chunks, int n_chunks, bool res, hipStream_t s);
 hipError_t launch_scatter_grads(const DevDesign &D, const int32_t *node_src, int64_t n_nodes, float *grad_cap,

@@ -3212,11 +3212,13 @@ __device__ __forceinline__ float2 endpoint_seed(const DevDesign &D, float g_tns,
 // log-sum-exp arrival merge, the slew merge's subgradient to its winner, and
 // the NLDM partials.  Every input sink has this cell as its only consumer, so
 // its gradient is written here, once; nothing is accumulated atomically.
-__device__ void cell_adjoint(const DevDesign &D, const LdsLib &lib, int x, const PinState &me, float gA0,
-                             float gA1, float gS0, float gS1) {
-  const int t = D.cell_type[x];
+// kSlots > 0: the inputs are the cell's inline fanin ids fs and their states
+// in (loaded by the caller ahead of time), slot k being arc f0 + k; kSlots = 0
+// reads them from the fanin lists.  Both visit the arcs in the same order.
+template <int kSlots>
+__device__ void cell_adjoint(const DevDesign &D, const LdsLib &lib, int x, int t, float L, int f0, const int *fs,
+                             const PinState *in, const PinState &me, float gA0, float gA1, float gS0, float gS1) {
   const int sense = lib.sense[t];
-  const float L = D.L_net[x];
   const TabLayout lay{D.nx, D.ny};
   const float *tb = lib_type(lib, D, t);
   const AxisPos py = axis_find(tb + lay.ya(), tb + lay.rdy(), D.ny, L);
@@ -3224,13 +3226,27 @@ __device__ void cell_adjoint(const DevDesign &D, const LdsLib &lib, int x, const
   const float g = D.gamma;
   const float ato[2] = {me.at.z, me.at.w};
   const float gA[2] = {gA0, gA1}, gS[2] = {gS0, gS1};
-  const int f0 = D.fanin_ptr[x], f1 = D.fanin_ptr[x + 1];
+  const int f1 = kSlots > 0 ? f0 + kSlots : D.fanin_ptr[x + 1];
+  auto input = [&](int f, int &sidx, PinState &st) {  // false past the cell's inputs
+    if constexpr (kSlots > 0) {
+      sidx = fs[f - f0];
+      st = in[f - f0];
+      return sidx >= 0;
+    } else {
+      sidx = D.fanin_sink[f];
+      st = D.sink_state[sidx];
+      return true;
+    }
+  };
   // slew winners (same scan order and tie rule as the forward merge)
   float best[2] = {-kInf, -kInf};
   int win[2] = {-1, -1};
+#pragma unroll
   for (int f = f0; f < f1; ++f) {
-    const PinState in = D.sink_state[D.fanin_sink[f]];
-    const float is[2] = {in.slew.z, in.slew.w};
+    int sidx;
+    PinState st;
+    if (!input(f, sidx, st)) continue;
+    const float is[2] = {st.slew.z, st.slew.w};
 #pragma unroll
     for (int ri = 0; ri < 2; ++ri) {
       const AxisPos px = axis_find(tb + lay.xa(), tb + lay.rdx(), D.nx, is[ri]);
@@ -3246,11 +3262,13 @@ __device__ void cell_adjoint(const DevDesign &D, const LdsLib &lib, int x, const
     }
   }
   float gL = 0.0f;
+#pragma unroll
   for (int f = f0; f < f1; ++f) {
-    const int sidx = D.fanin_sink[f];
-    const PinState in = D.sink_state[sidx];
-    const float ia[2] = {in.at.z, in.at.w};
-    const float is[2] = {in.slew.z, in.slew.w};
+    int sidx;
+    PinState st;
+    if (!input(f, sidx, st)) continue;
+    const float ia[2] = {st.at.z, st.at.w};
+    const float is[2] = {st.slew.z, st.slew.w};
     float giA[2] = {0.0f, 0.0f}, giS[2] = {0.0f, 0.0f}, ga[2] = {0.0f, 0.0f};
 #pragma unroll
     for (int ri = 0; ri < 2; ++ri) {
@@ -3287,28 +3305,46 @@ __device__ void cell_adjoint(const DevDesign &D, const LdsLib &lib, int x, const
 // thread forms its sink's contribution to its driver's gradient and writes
 // dJ/dd, dJ/dq; then the thread of each driver adds its sinks' contributions
 // in sink order after its own endpoint seed (a fixed order, so the gradients
-// are reproducible) and pushes through its cell.
-__global__ __launch_bounds__(kSweepBlock) void k_adjoint(DevDesign D, float g_tns, float g_wns, int c0, int c1) {
+// are reproducible) and pushes through its cell.  As in the forward level
+// kernel, only the chunk's span of cell types is staged (lib_f4 granules
+// reserved), and with kSlots > 0 a driver's fanin ids and input states are
+// requested at entry, so their latency hides behind the sink rounds.
+template <int kSlots>
+__global__ __launch_bounds__(kSweepBlock) void k_adjoint(DevDesign D, float g_tns, float g_wns, int c0, int c1,
+                                                         int lib_f4) {
   extern __shared__ __align__(32) unsigned char smem[];
   const int c = c0 + blockIdx.x;
   const int tid = threadIdx.x;
   const int4 cr = D.chunk_rec[c];
   const int x0 = __builtin_amdgcn_readfirstlane(cr.x), x1 = __builtin_amdgcn_readfirstlane(cr.y);
+  const int x = x0 + tid;
+  const bool drv = tid < kChunk && x < x1;
+  const int xc = drv ? x : x0;
+  // the cell's own loads first (they head the longest chain), every load
+  // unconditional
+  const int4 f4 = kSlots > 0 ? D.fanin4[xc] : make_int4(-1, -1, -1, -1);
+  const int t = max(D.cell_type[xc], 0);
+  const float L = D.L_net[xc];
+  const int f0 = D.fanin_ptr[xc];
+  const int2 tr = D.chunk_trange[c];
+  const LibSpan span = lib_span(D, tr.x, tr.y);
+  const float4 lib_r = lib_issue_span(D, span);
+  const int fs[4] = {f4.x, f4.y, f4.z, f4.w};
+  PinState in[4];
+#pragma unroll
+  for (int k = 0; k < kSlots; ++k) in[k] = D.sink_state[max(fs[k], 0)];
   const int sb = __builtin_amdgcn_readfirstlane(cr.z);
   const int se = __builtin_amdgcn_readfirstlane(D.sink_ptr[x1]);
   const int sAc = min(sb + tid, max(se - 1, 0));
   const PinState ssA = D.sink_state[sAc];
   const int consA = D.sink_cons[sAc], drvA = D.sink_drv[sAc];
   const float4 gA4 = D.g_sink[sAc];
-  const int x = x0 + tid;
-  const bool drv = tid < kChunk && x < x1;
-  const int xc = drv ? x : x0;
   const PinState me = D.drv_state[xc];
   const int e = D.drv_ep[xc];
   const int sp0 = D.sink_ptr[xc], sp1 = D.sink_ptr[xc + 1];
-  const LdsLib lib = load_lib(D, smem);
-  float2 *dsl = reinterpret_cast<float2 *>(smem + lib_lds_bytes(D.n_types, D.tstride));  // [kChunk]
-  float4 *cb = reinterpret_cast<float4 *>(dsl + kChunk);                                  // [kSweepBlock]
+  const LdsLib lib = lib_store_span(D, smem, span, lib_r, lib_f4);
+  float2 *dsl = reinterpret_cast<float2 *>(smem + span_lds_bytes(lib_f4, D.n_types));  // [kChunk]
+  float4 *cb = reinterpret_cast<float4 *>(dsl + kChunk);                                // [kSweepBlock]
   if (tid < kChunk) dsl[tid] = make_float2(me.slew.z, me.slew.w);
   lds_barrier();
   float gA0 = 0.0f, gA1 = 0.0f, gS0 = 0.0f, gS1 = 0.0f;
@@ -3350,7 +3386,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_adjoint(DevDesign D, float g_tn
   }
   if (drv) {
     if (x >= D.n_pi)
-      cell_adjoint(D, lib, x, me, gA0, gA1, gS0, gS1);
+      cell_adjoint<kSlots>(D, lib, x, t, L, f0, fs, in, me, gA0, gA1, gS0, gS1);
     else
       D.g_load[x] = 0.0f;
   }
@@ -3725,8 +3761,10 @@ __device__ __forceinline__ float node_slew(const DevDesign &D, int code, int el)
 }
 
 // One thread per endpoint (blocks of one wavefront, so the endpoints spread
-// over the compute units); its queue in LDS after the library when both fit,
-// else in A.items.
+// over the compute units); its queue in LDS after the library when both fit
+// (kLds, so that queue accesses are LDS instructions and never wait for the
+// walk's global loads), else in A.items.
+template <bool kLds>
 __global__ __launch_bounds__(kWave) void k_paths_enum(DevDesign D, PathArgs A) {
   extern __shared__ __align__(32) unsigned char smem[];
   const LdsLib lib = load_lib(D, smem);
@@ -3735,12 +3773,12 @@ __global__ __launch_bounds__(kWave) void k_paths_enum(DevDesign D, PathArgs A) {
   if (t >= A.n_eps) return;
   const int el = A.el, m = A.m, lmax = A.lmax;
   PathQueue Q;
-  if (A.items) {
-    Q.q = A.items + t;
-    Q.stride = A.n_eps;
-  } else {
+  if constexpr (kLds) {
     Q.q = reinterpret_cast<int4 *>(smem + lib_lds_bytes(D.n_types, D.tstride)) + threadIdx.x;
     Q.stride = kWave;
+  } else {
+    Q.q = A.items + t;
+    Q.stride = A.n_eps;
   }
   Q.h = 0;
   Q.n = 0;
@@ -3878,19 +3916,23 @@ __global__ void k_paths_lengths(PathArgs A, const int32_t *sel, int n_sel, int32
   if (i < n_sel) len[i] = A.plen[sel[i]];
 }
 
-// One thread per reported path: pins from startpoint to endpoint.
-__global__ void k_paths_emit(DevDesign D, PathArgs A, const int32_t *sel, int n_sel, const int32_t *ptr,
-                             int32_t *pin, int8_t *rf, float *slack, int32_t *ep) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// One wavefront per reported path, a lane per pin: pins from startpoint to
+// endpoint.
+__global__ __launch_bounds__(256) void k_paths_emit(DevDesign D, PathArgs A, const int32_t *sel, int n_sel,
+                                                    const int32_t *ptr, int32_t *pin, int8_t *rf, float *slack,
+                                                    int32_t *ep) {
+  const int i = blockIdx.x * (256 / kWave) + (int)threadIdx.x / kWave, lane = (int)threadIdx.x % kWave;
   if (i >= n_sel) return;
   const int c = sel[i];
   const int t = c / A.m;
   const int len = A.plen[c];
   const int32_t *path = A.nodes + (size_t)c * A.lmax;
-  if (slack) slack[i] = A.pkey[c];
-  if (ep) ep[i] = A.eps[t];
+  if (lane == 0) {
+    if (slack) slack[i] = A.pkey[c];
+    if (ep) ep[i] = A.eps[t];
+  }
   const int o = ptr[i];
-  for (int q = 0; q < len; ++q) {
+  for (int q = lane; q < len; q += kWave) {
     const int code = path[len - 1 - q];
     const int sl = code >> 1;
     if (pin) pin[o + q] = sl < D.n_drv ? A.drv_pin[sl] : A.sink_pin[sl - D.n_drv];
@@ -4141,10 +4183,25 @@ hipError_t launch_reduce_smooth(const DevDesign &D, double *partials, double *ou
 }
 
 
-hipError_t launch_adjoint_phase(const DevDesign &D, float g_tns, float g_wns, int4 ph, hipStream_t s) {
+template <int kSlots>
+static void launch_adjoint_k(const DevDesign &D, float g_tns, float g_wns, int4 ph, int lib_f4, hipStream_t s) {
+  const size_t lds = span_lds_bytes(lib_f4, D.n_types) + sizeof(float2) * kChunk + sizeof(float4) * kSweepBlock;
+  hipLaunchKernelGGL(k_adjoint<kSlots>, dim3(ph.z), dim3(kSweepBlock), lds, s, D, g_tns, g_wns, ph.y, ph.y + ph.z,
+                     lib_f4);
+}
+
+hipError_t launch_adjoint_phase(const DevDesign &D, float g_tns, float g_wns, int4 ph, int lib_f4, hipStream_t s) {
   if (ph.z <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_adjoint, dim3(ph.z), dim3(kSweepBlock), sweep_lds_bytes(D), s, D, g_tns, g_wns, ph.y,
-                     ph.y + ph.z);
+  if (!D.fanin4)
+    launch_adjoint_k<0>(D, g_tns, g_wns, ph, lib_f4, s);
+  else if (D.max_in <= 1)
+    launch_adjoint_k<1>(D, g_tns, g_wns, ph, lib_f4, s);
+  else if (D.max_in == 2)
+    launch_adjoint_k<2>(D, g_tns, g_wns, ph, lib_f4, s);
+  else if (D.max_in == 3)
+    launch_adjoint_k<3>(D, g_tns, g_wns, ph, lib_f4, s);
+  else
+    launch_adjoint_k<4>(D, g_tns, g_wns, ph, lib_f4, s);
   return hipGetLastError();
 }
 
@@ -4374,8 +4431,12 @@ size_t paths_queue_lds_bytes(const DevDesign &D, int m) {
 
 hipError_t launch_paths_enum(const DevDesign &D, const PathArgs &A, hipStream_t s) {
   if (A.n_eps <= 0) return hipSuccess;
-  const size_t lds = A.items ? lib_lds_bytes(D.n_types, D.tstride) : paths_queue_lds_bytes(D, A.m);
-  hipLaunchKernelGGL(k_paths_enum, dim3(blocks_for(A.n_eps, kWave)), dim3(kWave), lds, s, D, A);
+  if (A.items)
+    hipLaunchKernelGGL(k_paths_enum<false>, dim3(blocks_for(A.n_eps, kWave)), dim3(kWave),
+                       lib_lds_bytes(D.n_types, D.tstride), s, D, A);
+  else
+    hipLaunchKernelGGL(k_paths_enum<true>, dim3(blocks_for(A.n_eps, kWave)), dim3(kWave),
+                       paths_queue_lds_bytes(D, A.m), s, D, A);
   return hipGetLastError();
 }
 
@@ -4396,8 +4457,8 @@ hipError_t launch_paths_emit(const DevDesign &D, const PathArgs &A, const int32_
                              const int32_t *ptr, int32_t *pin, int8_t *rf, float *slack, int32_t *ep,
                              hipStream_t s) {
   if (n_sel <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_paths_emit, dim3(blocks_for(n_sel, 256)), dim3(256), 0, s, D, A, sel, n_sel, ptr, pin, rf,
-                     slack, ep);
+  hipLaunchKernelGGL(k_paths_emit, dim3(blocks_for(n_sel, 256 / kWave)), dim3(256), 0, s, D, A, sel, n_sel, ptr,
+                     pin, rf, slack, ep);
   return hipGetLastError();
 }
 
