@@ -3212,12 +3212,9 @@ __device__ __forceinline__ float2 endpoint_seed(const DevDesign &D, float g_tns,
 // log-sum-exp arrival merge, the slew merge's subgradient to its winner, and
 // the NLDM partials.  Every input sink has this cell as its only consumer, so
 // its gradient is written here, once; nothing is accumulated atomically.
-// kSlots > 0: the inputs are the cell's inline fanin ids fs and their states
-// in (loaded by the caller ahead of time), slot k being arc f0 + k; kSlots = 0
-// reads them from the fanin lists.  Both visit the arcs in the same order.
-template <int kSlots>
-__device__ void cell_adjoint(const DevDesign &D, const LdsLib &lib, int x, int t, float L, int f0, const int *fs,
-                             const PinState *in, const PinState &me, float gA0, float gA1, float gS0, float gS1) {
+// (Libraries of more than four inputs: the inputs from the fanin lists.)
+__device__ void cell_adjoint(const DevDesign &D, const LdsLib &lib, int x, int t, float L, int f0,
+                             const PinState &me, float gA0, float gA1, float gS0, float gS1) {
   const int sense = lib.sense[t];
   const TabLayout lay{D.nx, D.ny};
   const float *tb = lib_type(lib, D, t);
@@ -3226,26 +3223,12 @@ __device__ void cell_adjoint(const DevDesign &D, const LdsLib &lib, int x, int t
   const float g = D.gamma;
   const float ato[2] = {me.at.z, me.at.w};
   const float gA[2] = {gA0, gA1}, gS[2] = {gS0, gS1};
-  const int f1 = kSlots > 0 ? f0 + kSlots : D.fanin_ptr[x + 1];
-  auto input = [&](int f, int &sidx, PinState &st) {  // false past the cell's inputs
-    if constexpr (kSlots > 0) {
-      sidx = fs[f - f0];
-      st = in[f - f0];
-      return sidx >= 0;
-    } else {
-      sidx = D.fanin_sink[f];
-      st = D.sink_state[sidx];
-      return true;
-    }
-  };
+  const int f1 = D.fanin_ptr[x + 1];
   // slew winners (same scan order and tie rule as the forward merge)
   float best[2] = {-kInf, -kInf};
   int win[2] = {-1, -1};
-#pragma unroll
   for (int f = f0; f < f1; ++f) {
-    int sidx;
-    PinState st;
-    if (!input(f, sidx, st)) continue;
+    const PinState st = D.sink_state[D.fanin_sink[f]];
     const float is[2] = {st.slew.z, st.slew.w};
 #pragma unroll
     for (int ri = 0; ri < 2; ++ri) {
@@ -3262,11 +3245,9 @@ __device__ void cell_adjoint(const DevDesign &D, const LdsLib &lib, int x, int t
     }
   }
   float gL = 0.0f;
-#pragma unroll
   for (int f = f0; f < f1; ++f) {
-    int sidx;
-    PinState st;
-    if (!input(f, sidx, st)) continue;
+    const int sidx = D.fanin_sink[f];
+    const PinState st = D.sink_state[sidx];
     const float ia[2] = {st.at.z, st.at.w};
     const float is[2] = {st.slew.z, st.slew.w};
     float giA[2] = {0.0f, 0.0f}, giS[2] = {0.0f, 0.0f}, ga[2] = {0.0f, 0.0f};
@@ -3299,6 +3280,86 @@ __device__ void cell_adjoint(const DevDesign &D, const LdsLib &lib, int x, int t
   D.g_load[x] = gL;
 }
 
+// The same step with four lanes per cell output, lane k holding input slot k
+// (inline fanin ids): the slew winner is the first maximum over the slots in
+// (slot, transition) order, found by a reduction over the four lanes; each
+// lane writes its input's sink and arc gradients, and lane 0 the load
+// gradient, the lanes' sums added in slot order.  The four lanes of a cell are
+// active together.
+__device__ void cell_adjoint_lane(const DevDesign &D, const LdsLib &lib, int x, int t, float L, int f0, int k,
+                                  int fk, const PinState &in, float2 ato2, float4 gg) {
+  const int sense = lib.sense[t];
+  const TabLayout lay{D.nx, D.ny};
+  const float *tb = lib_type(lib, D, t);
+  const AxisPos py = axis_find(tb + lay.ya(), tb + lay.rdy(), D.ny, L);
+  const float rdy = tb[lay.rdy() + py.i];
+  const float g = D.gamma;
+  const float ato[2] = {ato2.x, ato2.y};
+  const float gA[2] = {gg.x, gg.y}, gS[2] = {gg.z, gg.w};
+  const bool has = fk >= 0;
+  const float ia[2] = {in.at.z, in.at.w};
+  const float is[2] = {in.slew.z, in.slew.w};
+  AxisPos px[2];
+#pragma unroll
+  for (int ri = 0; ri < 2; ++ri) px[ri] = axis_find(tb + lay.xa(), tb + lay.rdx(), D.nx, is[ri]);
+  // slew winners: this slot's first maximum, then the lanes' in slot order
+  float best[2] = {-kInf, -kInf};
+  int win[2] = {-1, -1};
+#pragma unroll
+  for (int ri = 0; ri < 2; ++ri) {
+#pragma unroll
+    for (int ro = 0; ro < 2; ++ro) {
+      if (!has || !arc_maps(sense, ri, ro)) continue;
+      const float cs = bilerp(tb + lay.tab(2 + ro), D.ny, px[ri], py);
+      if (cs > best[ro]) {
+        best[ro] = cs;
+        win[ro] = k * 2 + ri;
+      }
+    }
+  }
+#pragma unroll
+  for (int ro = 0; ro < 2; ++ro) {
+#pragma unroll
+    for (int o = 1; o < 4; o <<= 1) {
+      const float ob = __shfl_xor(best[ro], o, 4);
+      const int ow = __shfl_xor(win[ro], o, 4);
+      const bool take = ob > best[ro] || (ob == best[ro] && ow >= 0 && (win[ro] < 0 || ow < win[ro]));
+      best[ro] = take ? ob : best[ro];
+      win[ro] = take ? ow : win[ro];
+    }
+  }
+  float gL = 0.0f;
+  if (has) {
+    float giA[2] = {0.0f, 0.0f}, giS[2] = {0.0f, 0.0f}, ga[2] = {0.0f, 0.0f};
+#pragma unroll
+    for (int ri = 0; ri < 2; ++ri) {
+      const float rdx = tb[lay.rdx() + px[ri].i];
+#pragma unroll
+      for (int ro = 0; ro < 2; ++ro) {
+        if (!arc_maps(sense, ri, ro)) continue;
+        float dX, dY;
+        const float dl = bilerp_d(tb + lay.tab(ro), D.ny, px[ri], py, rdx, rdy, dX, dY);
+        const float w = expf((ia[ri] + dl - ato[ro]) / g);
+        const float wa = w * gA[ro];
+        giA[ri] += wa;
+        giS[ri] += wa * dX;
+        gL += wa * dY;
+        ga[ro] += wa;
+        if (win[ro] == k * 2 + ri) {
+          float sX, sY;
+          (void)bilerp_d(tb + lay.tab(2 + ro), D.ny, px[ri], py, rdx, rdy, sX, sY);
+          giS[ri] += gS[ro] * sX;
+          gL += gS[ro] * sY;
+        }
+      }
+    }
+    D.g_sink[fk] = make_float4(giA[0], giA[1], giS[0], giS[1]);
+    D.g_arc[f0 + k] = make_float2(ga[0], ga[1]);
+  }
+  const float l1 = __shfl(gL, 1, 4), l2 = __shfl(gL, 2, 4), l3 = __shfl(gL, 3, 4);
+  if (k == 0) D.g_load[x] = ((gL + l1) + l2) + l3;
+}
+
 // Per-level reverse sweep: one block per chunk.  The chunk's sinks (all of
 // them, also those a high-fanout driver leaves to pieces in the forward
 // sweep) are taken 256 at a time, one per thread, with coalesced loads: each
@@ -3307,8 +3368,11 @@ __device__ void cell_adjoint(const DevDesign &D, const LdsLib &lib, int x, int t
 // in sink order after its own endpoint seed (a fixed order, so the gradients
 // are reproducible) and pushes through its cell.  As in the forward level
 // kernel, only the chunk's span of cell types is staged (lib_f4 granules
-// reserved), and with kSlots > 0 a driver's fanin ids and input states are
-// requested at entry, so their latency hides behind the sink rounds.
+// reserved).  With kSlots > 0 (inline fanin ids) the cell step runs on four
+// lanes per driver, thread 4 d + k holding input slot k of driver d, whose id,
+// input state and driver values it requests at entry, so their latency hides
+// behind the sink rounds; the drivers' summed gradients reach the four lanes
+// through LDS.
 template <int kSlots>
 __global__ __launch_bounds__(kSweepBlock) void k_adjoint(DevDesign D, float g_tns, float g_wns, int c0, int c1,
                                                          int lib_f4) {
@@ -3320,19 +3384,21 @@ __global__ __launch_bounds__(kSweepBlock) void k_adjoint(DevDesign D, float g_tn
   const int x = x0 + tid;
   const bool drv = tid < kChunk && x < x1;
   const int xc = drv ? x : x0;
-  // the cell's own loads first (they head the longest chain), every load
-  // unconditional
-  const int4 f4 = kSlots > 0 ? D.fanin4[xc] : make_int4(-1, -1, -1, -1);
-  const int t = max(D.cell_type[xc], 0);
-  const float L = D.L_net[xc];
-  const int f0 = D.fanin_ptr[xc];
+  // the cell step's loads first (they head the longest chain), every load
+  // unconditional: with kSlots > 0 those of driver tid / 4's slot tid % 4
+  const int d4 = tid >> 2, k4 = tid & 3;
+  const bool live4 = x0 + d4 < x1;
+  const int xs = kSlots > 0 ? (live4 ? x0 + d4 : x0) : xc;
+  const int4 f4 = kSlots > 0 ? D.fanin4[xs] : make_int4(-1, -1, -1, -1);
+  const int t = max(D.cell_type[xs], 0);
+  const float L = D.L_net[xs];
+  const int f0 = D.fanin_ptr[xs];
   const int2 tr = D.chunk_trange[c];
   const LibSpan span = lib_span(D, tr.x, tr.y);
   const float4 lib_r = lib_issue_span(D, span);
-  const int fs[4] = {f4.x, f4.y, f4.z, f4.w};
-  PinState in[4];
-#pragma unroll
-  for (int k = 0; k < kSlots; ++k) in[k] = D.sink_state[max(fs[k], 0)];
+  const int fk = k4 == 0 ? f4.x : k4 == 1 ? f4.y : k4 == 2 ? f4.z : f4.w;
+  const PinState ink = D.sink_state[max(fk, 0)];
+  const float2 ato4 = kSlots > 0 ? reinterpret_cast<const float2 *>(&D.drv_state[xs].at)[1] : make_float2(0.f, 0.f);
   const int sb = __builtin_amdgcn_readfirstlane(cr.z);
   const int se = __builtin_amdgcn_readfirstlane(D.sink_ptr[x1]);
   const int sAc = min(sb + tid, max(se - 1, 0));
@@ -3384,11 +3450,23 @@ __global__ __launch_bounds__(kSweepBlock) void k_adjoint(DevDesign D, float g_tn
     }
     lds_barrier();
   }
-  if (drv) {
-    if (x >= D.n_pi)
-      cell_adjoint<kSlots>(D, lib, x, t, L, f0, fs, in, me, gA0, gA1, gS0, gS1);
-    else
-      D.g_load[x] = 0.0f;
+  if constexpr (kSlots > 0) {
+    if (drv) cb[tid] = make_float4(gA0, gA1, gS0, gS1);  // (cb is free after the last round's barrier)
+    lds_barrier();
+    if (live4) {  // (uniform over a driver's four lanes)
+      const int xd = x0 + d4;
+      if (xd >= D.n_pi)
+        cell_adjoint_lane(D, lib, xd, t, L, f0, k4, fk, ink, ato4, cb[d4]);
+      else if (k4 == 0)
+        D.g_load[xd] = 0.0f;
+    }
+  } else {
+    if (drv) {
+      if (x >= D.n_pi)
+        cell_adjoint(D, lib, x, t, L, f0, me, gA0, gA1, gS0, gS1);
+      else
+        D.g_load[x] = 0.0f;
+    }
   }
 }
 

@@ -65,6 +65,18 @@ def test_smooth_forward_and_adjoint(cfg, sched):
     _check_smooth(d, sched, big_net_nodes=40 if cfg == "tiny" else 0)
 
 
+@pytest.mark.parametrize("seed", [1, 2])
+def test_smooth_adjoint_five_input_cells(seed):
+    """A library type of five inputs: the reverse cell step reads the fanin
+    lists (one lane per cell) instead of the inline four (four lanes)."""
+    import sys, os
+    sys.path.insert(0, os.path.dirname(__file__))
+    from test_oracle_paths import small_dag
+    d = small_dag(seed, levels=5, per_level=6, n_inputs=(1, 2, 5, 2))
+    assert max(d.n_inputs) == 5
+    _check_smooth(d, STA_SCHED_PER_LEVEL)
+
+
 def test_adjoint_is_deterministic():
     d = synth.generate(synth.mid_config(n_cells=20_000, n_levels=25, seed=15))
     s = STA(d, mode=1, gamma_ps=GAMMA)
