@@ -379,9 +379,12 @@ sta_status sta_autotune(sta_ctx *ctx, int32_t reps, sta_tune_result *best, void 
  *                       each pin's transition (0 rise, 1 fall); a path has
  *                       at most n_levels (sta_info) pins
  *   path_slack [k]      slack of each path; path_endpoint [k] its endpoint index
- * Any array may be NULL; arrays go to `dst` memory.  Allocates device scratch
- * for the search (bounded by k, per_endpoint and the level count);
- * synchronizes `stream`. */
+ * Any array may be NULL; arrays go to `dst` memory.  The search's device
+ * scratch (bounded by k, per_endpoint, the level count and the driver count)
+ * is a workspace the context keeps and grows across reports, freed with the
+ * context; each endpoint's pending paths sit in LDS when they fit beside the
+ * library (the environment variable STA_PATH_QUEUES_GLOBAL, when set, keeps
+ * them in global memory instead, for testing).  Synchronizes `stream`. */
 typedef struct {
   int32_t k;                   /* most paths reported (>= 1) */
   int32_t per_endpoint;        /* most paths per endpoint, 1..64 */
