@@ -380,7 +380,7 @@ sta_status sta_autotune(sta_ctx *ctx, int32_t reps, sta_tune_result *best, void 
  *                       at most n_levels (sta_info) pins
  *   path_slack [k]      slack of each path; path_endpoint [k] its endpoint index
  * Any array may be NULL; arrays go to `dst` memory.  The search's device
- * scratch (bounded by k, per_endpoint, the level count and the driver count)
+ * scratch (bounded by k, per_endpoint and the level count)
  * is a workspace the context keeps and grows across reports, freed with the
  * context; each endpoint's pending paths sit in LDS when they fit beside the
  * library (the environment variable STA_PATH_QUEUES_GLOBAL, when set, keeps
