@@ -112,15 +112,19 @@ def _time_updates(ctxs, stream, steps):
     return ev0.elapsed_time(ev1) / steps
 
 
-def adjoint_ratio(steps: int) -> dict:
+def adjoint_ratio(steps: int, sched: str = "auto") -> dict:
     """Smooth-mode update (LSE arrival merges, smooth TNS/WNS) and its reverse
-    pass (sta_backward into device gradient buffers) on the 1M-pin design."""
+    pass (sta_backward into device gradient buffers) on the 1M-pin design; the
+    forward's schedule autotuned, or the one given."""
     import torch
     from paper_2511_11660_amd import synth
     from paper_2511_11660_amd.sta import STA
     d = synth.generate(synth.mid_config())
-    s = STA(d, mode=1, gamma_ps=5.0, sort_endpoints=0, device=0)
-    r = s.autotune(reps=3)
+    s = STA(d, mode=1, gamma_ps=5.0, sort_endpoints=0, device=0, sched=0 if sched == "auto" else int(sched))
+    if sched == "auto":
+        chosen = s.autotune(reps=3).sched
+    else:
+        chosen = int(sched)
     stream = torch.cuda.current_stream()
     gc = torch.empty(int(d.n_nodes), dtype=torch.float32, device="cuda")
     gr = torch.empty(int(d.n_nodes), dtype=torch.float32, device="cuda")
@@ -142,7 +146,7 @@ def adjoint_ratio(steps: int) -> dict:
     t_bwd = ev0.elapsed_time(ev1) / steps
     s.close()
     return {"workload": "1M-pin synthetic design, smooth mode gamma 5 ps", "pins": d.n_pins,
-            "schedule": _SCHED_NAMES[r.sched], "forward_ms": t_fwd, "backward_ms": t_bwd,
+            "schedule": _SCHED_NAMES[chosen], "forward_ms": t_fwd, "backward_ms": t_bwd,
             "ratio": t_bwd / t_fwd}
 
 
@@ -520,7 +524,7 @@ def main() -> int:
         out["reduced_order"] = reduced_order_side(design, sched, s_blocks, args.steps, ms)
     if "adjoint" in side:
         print("[bench] adjoint ratio (1M-pin smooth)", file=sys.stderr, flush=True)
-        out["adjoint"] = adjoint_ratio(args.steps)
+        out["adjoint"] = adjoint_ratio(args.steps, args.sched)
     if "paths" in side:
         print("[bench] top-k path report", file=sys.stderr, flush=True)
         out["paths"] = paths_side(design, sched, s_blocks)
