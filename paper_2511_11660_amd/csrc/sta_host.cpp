@@ -97,7 +97,7 @@ struct sta_ctx {
   int device = 0;
   sta_options opt{};
   int n_pins = 0, n_cells = 0, n_nets = 0, n_pi = 0, n_po = 0, n_sinks = 0, n_drv = 0, n_ep = 0;
-  int n_cell_levels = 0, n_levels = 0, n_chunks = 0, n_big = 0, n_rc_chunks = 0;
+  int n_cell_levels = 0, n_levels = 0, n_chunks = 0, n_big = 0, n_rc_chunks = 0, n_rc_adj_chunks = 0;
   int64_t n_nodes = 0;
   int n_cu = 0, sweep_grid = 1;
   bool coop = false;                   // persistent sweeps use the cooperative level-major kernels
@@ -112,6 +112,7 @@ struct sta_ctx {
   int32_t *slot_drv_pin = nullptr, *slot_sink_pin = nullptr;  // slot -> caller pin (path reports)
   int max_in = 1;                      // most inputs of any library type
   int2 *rc_chunks = nullptr;
+  int2 *rc_adj_chunks = nullptr;       // the RC adjoint's smaller chunks over the same net order
   BigNet *big = nullptr;
   int32_t *big_end = nullptr, *big_nsp = nullptr, *big_nsl = nullptr, *big_egp = nullptr, *big_egl = nullptr;
   WideNets wide{};
@@ -667,7 +668,7 @@ static sta_status build_layout(sta_ctx *C, const Inputs &I, const std::vector<in
     rc_m[x] = (int32_t)m;
   }
   std::vector<int32_t> rc_order, rc_start, rc_chunk_slot0;
-  std::vector<int2> rc_chunks;
+  std::vector<int2> rc_chunks, rc_adj_chunks;
   {
     std::vector<int32_t> small, wide;
     for (int x = 0; x < ND; ++x) (rc_m[x] > big_thr ? wide : small).push_back(x);
@@ -693,6 +694,14 @@ static sta_status build_layout(sta_ctx *C, const Inputs &I, const std::vector<in
       rc_chunk_slot0.push_back(mn);
       rc_chunks.push_back(make_int2((int)j0, (int)j1));
       j0 = j1;
+    }
+    for (size_t a = 0; a < small.size();) {  // the adjoint's chunks: same order, smaller cuts
+      size_t b = a;
+      int64_t nodes = 0;
+      while (b < small.size() && (int)(b - a) < kRcAdjBlock && nodes + rc_m[small[b]] <= kRcAdjChunkNodes)
+        nodes += rc_m[small[b++]];
+      rc_adj_chunks.push_back(make_int2((int)a, (int)b));
+      a = b;
     }
     int32_t pos = 0;
     rc_start.reserve(small.size() + 1);
@@ -1085,6 +1094,8 @@ static sta_status build_layout(sta_ctx *C, const Inputs &I, const std::vector<in
   STA_TRY(C->upload(&C->slot_drv_pin, drv_pin));
   STA_TRY(C->upload(&C->slot_sink_pin, sink_pin_of_slot));
   STA_TRY(C->upload(&C->rc_chunks, rc_chunks));
+  STA_TRY(C->upload(&C->rc_adj_chunks, rc_adj_chunks));
+  C->n_rc_adj_chunks = (int)rc_adj_chunks.size();
   STA_TRY(C->upload(&C->big, big));
   {
     // incremental update: chunk and phases of every driver / chunk, and the
@@ -1621,7 +1632,7 @@ static sta_status enqueue_rc(sta_ctx *C, hipStream_t s, bool adjoint, bool res =
     HIP_TRY(adjoint ? launch_rc_adjoint_wide(D, C->wide, C->side) : launch_rc_wide(D, C->wide, C->side));
     HIP_TRY(hipEventRecord(C->ev_join, C->side));
   }
-  HIP_TRY(adjoint ? launch_rc_adjoint(D, C->rc_chunks, C->n_rc_chunks, res, s)
+  HIP_TRY(adjoint ? launch_rc_adjoint(D, C->rc_adj_chunks, C->n_rc_adj_chunks, res, s)
                   : launch_rc(D, C->rc_chunks, C->n_rc_chunks, s));
   if (C->n_big > 0) HIP_TRY(hipStreamWaitEvent(s, C->ev_join, 0));
   return STA_OK;

@@ -27,6 +27,8 @@ constexpr int kSweepBlock = 256;            // 4 waves, each wave owns one chunk
 constexpr int kChunk = kWave;               // driver slots per sweep chunk
 constexpr int kRcBlock = 256;               // one small net per thread
 constexpr int kRcChunkNodes = 2048;         // RC nodes staged in LDS per block
+constexpr int kRcAdjBlock = 128;            // the RC adjoint's blocks: nets and
+constexpr int kRcAdjChunkNodes = 1024;      // nodes (its LDS holds eight arrays)
 constexpr int kRcSortWindow = 4096;         // slots within which small nets are ordered by size
 constexpr int kSmallNetMaxNodes = 255;      // parents fit in a byte
 constexpr int kReduceBlocks = 128;

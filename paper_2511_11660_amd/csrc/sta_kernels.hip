@@ -2750,23 +2750,24 @@ __device__ double red2_half_time(const Red2 &r, double d, double m2) {
 // Stages nodes [k0, k0 + nk) of one RC chunk into LDS: parent, R and
 // C^ = C + lumped pin caps.  Each thread requests all of its (clamped,
 // unpredicated) loads before its first LDS store.
+template <int kNodes = kRcChunkNodes, int kThreads = kRcBlock>
 __device__ __forceinline__ void stage_rc_nodes(const DevDesign &D, int k0, int nk, uint8_t *par, float *R,
                                                float *C, float *A) {
-  constexpr int kPer = kRcChunkNodes / kRcBlock;
+  constexpr int kPer = kNodes / kThreads;
   const int tid = threadIdx.x;
   const int last = k0 + max(nk - 1, 0);
   uint8_t p[kPer];
   float r[kPer], c[kPer];
 #pragma unroll
   for (int u = 0; u < kPer; ++u) {
-    const int i = min(k0 + u * kRcBlock + tid, last);
+    const int i = min(k0 + u * kThreads + tid, last);
     p[u] = D.rc_par8[i];
     r[u] = D.rc_res[i];
     c[u] = D.rc_cap[i];  // wire + pin caps (C^)
   }
 #pragma unroll
   for (int u = 0; u < kPer; ++u) {
-    const int i = u * kRcBlock + tid;
+    const int i = u * kThreads + tid;
     if (i < nk) {
       par[i] = p[u];
       R[i] = r[u];
@@ -3564,12 +3565,15 @@ __global__ __launch_bounds__(kWideBlock) void k_rc_adjoint_wide(DevDesign D, Wid
 }
 
 // kRes: also dJ/dR per segment (one more LDS array; only when it is asked for).
+// Its own chunks, of at most kRcAdjBlock nets and kRcAdjChunkNodes nodes (the
+// same net order as the forward's): eight arrays at 2048 nodes held it to two
+// blocks per compute unit.
 template <bool kRes>
-__global__ __launch_bounds__(kRcBlock) void k_rc_adjoint(DevDesign D, const int2 *chunks, int n_chunks) {
-  __shared__ uint8_t s_par[kRcChunkNodes];
-  __shared__ float s_R[kRcChunkNodes], s_C[kRcChunkNodes], s_A[kRcChunkNodes], s_B[kRcChunkNodes];
-  __shared__ float s_E[kRcChunkNodes], s_F[kRcChunkNodes], s_G[kRes ? kRcChunkNodes : 1];
-  __shared__ int s_base[kRcBlock + 1];
+__global__ __launch_bounds__(kRcAdjBlock) void k_rc_adjoint(DevDesign D, const int2 *chunks, int n_chunks) {
+  __shared__ uint8_t s_par[kRcAdjChunkNodes];
+  __shared__ float s_R[kRcAdjChunkNodes], s_C[kRcAdjChunkNodes], s_A[kRcAdjChunkNodes], s_B[kRcAdjChunkNodes];
+  __shared__ float s_E[kRcAdjChunkNodes], s_F[kRcAdjChunkNodes], s_G[kRes ? kRcAdjChunkNodes : 1];
+  __shared__ int s_base[kRcAdjBlock + 1];
   const int tid = threadIdx.x;
   const int ci = xcd_major(n_chunks);
   if (ci >= n_chunks) return;
@@ -3580,8 +3584,8 @@ __global__ __launch_bounds__(kRcBlock) void k_rc_adjoint(DevDesign D, const int2
   const int jc = j < j1 ? j : j0;
   const int x = D.rc_order[jc];
   const int2 sr = D.rc_sinks[jc];
-  stage_rc_nodes(D, k0, nk, s_par, s_R, s_C, s_A);
-  for (int i = tid; i <= j1 - j0; i += kRcBlock) s_base[i] = D.rc_start[j0 + i] - k0;
+  stage_rc_nodes<kRcAdjChunkNodes, kRcAdjBlock>(D, k0, nk, s_par, s_R, s_C, s_A);
+  for (int i = tid; i <= j1 - j0; i += kRcAdjBlock) s_base[i] = D.rc_start[j0 + i] - k0;
   __syncthreads();
   if (j < j1) {
     const int b = s_base[tid], m = s_base[tid + 1] - b;
@@ -3633,7 +3637,7 @@ __global__ __launch_bounds__(kRcBlock) void k_rc_adjoint(DevDesign D, const int2
     for (int k = 0; k < m; ++k) C[b + k] = gL + F[b + k] + B[b + k] * A[b + k];
   }
   __syncthreads();
-  for (int i = tid; i < nk; i += kRcBlock) {
+  for (int i = tid; i < nk; i += kRcAdjBlock) {
     D.g_cap[k0 + i] = s_C[i];
     if constexpr (kRes) D.g_res[k0 + i] = s_G[i];
   }
@@ -4286,9 +4290,9 @@ hipError_t launch_adjoint_phase(const DevDesign &D, float g_tns, float g_wns, in
 hipError_t launch_rc_adjoint(const DevDesign &D, const int2 *chunks, int n_chunks, bool res, hipStream_t s) {
   if (n_chunks <= 0) return hipSuccess;
   if (res)
-    hipLaunchKernelGGL(k_rc_adjoint<true>, dim3(xcd_grid(n_chunks)), dim3(kRcBlock), 0, s, D, chunks, n_chunks);
+    hipLaunchKernelGGL(k_rc_adjoint<true>, dim3(xcd_grid(n_chunks)), dim3(kRcAdjBlock), 0, s, D, chunks, n_chunks);
   else
-    hipLaunchKernelGGL(k_rc_adjoint<false>, dim3(xcd_grid(n_chunks)), dim3(kRcBlock), 0, s, D, chunks, n_chunks);
+    hipLaunchKernelGGL(k_rc_adjoint<false>, dim3(xcd_grid(n_chunks)), dim3(kRcAdjBlock), 0, s, D, chunks, n_chunks);
   return hipGetLastError();
 }
 
