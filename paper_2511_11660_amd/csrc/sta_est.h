@@ -47,9 +47,11 @@ constexpr size_t kEstScratchBytes =
 // device; looked up once per device and kept.
 hipError_t est_noalloc_scratch(int device, unsigned char **ptr);
 // n_mid = st[0], n_big = st[1] as read back by the host; the kernels read
-// the counts from st as well
+// the counts from st as well.  The block kernel of the nets above 64 pins
+// runs on s; the two smaller tiers on `side` when given (the caller orders
+// side after s's earlier work and s after side's), else on s after it.
 hipError_t launch_est(const EstArgs &A, const int32_t *mid, const int32_t *big, const uint32_t *st, uint32_t n_mid,
-                      uint32_t n_big, hipStream_t s);
+                      uint32_t n_big, hipStream_t s, hipStream_t side = nullptr);
 
 // off[b] / *total get the big nets' pin offsets and their pin total (count
 // read from st[1] on the device): big_tmp needs 16 * total words, and the
@@ -57,6 +59,6 @@ hipError_t launch_est(const EstArgs &A, const int32_t *mid, const int32_t *big, 
 hipError_t launch_est_acc_offsets(const EstArgs &A, const int32_t *big, const uint32_t *st, int64_t *off,
                                   unsigned long long *total, hipStream_t s);
 hipError_t launch_est_grad(const EstArgs &A, const int32_t *mid, const int32_t *big, const uint32_t *st,
-                           uint32_t n_mid, uint32_t n_big, hipStream_t s);
+                           uint32_t n_mid, uint32_t n_big, hipStream_t s, hipStream_t side = nullptr);
 
 }  // namespace sta

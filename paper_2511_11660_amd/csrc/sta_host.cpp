@@ -219,6 +219,39 @@ struct sta_ctx {
 // their speed; sharing the first pair keeps every context on those.  Contexts
 // used at once from several caller streams stay correct (every use is ordered
 // by the context's own events) but share the pair's hardware queues.
+// Two events released with their owner (an event may be destroyed while waits
+// on it are still queued).
+struct EventPair {
+  hipEvent_t a = nullptr, b = nullptr;
+  ~EventPair() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+};
+
+static hipError_t device_side_streams(int device, hipStream_t *a, hipStream_t *b);
+
+// The estimator's tiers with the small nets beside the large nets' block
+// kernel: on the current device's first side stream, forked from s and joined
+// back into it (the block kernel's longest net holds a few compute units for
+// most of the pass while the rest of the chip would idle).
+template <class Launch>
+static sta_status est_forked(hipStream_t s, Launch &&launch) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  hipStream_t side = nullptr, side2 = nullptr;
+  HIP_TRY(device_side_streams(dev, &side, &side2));
+  EventPair ev;
+  HIP_TRY(hipEventCreateWithFlags(&ev.a, hipEventDisableTiming));
+  HIP_TRY(hipEventCreateWithFlags(&ev.b, hipEventDisableTiming));
+  HIP_TRY(hipEventRecord(ev.a, s));
+  HIP_TRY(hipStreamWaitEvent(side, ev.a, 0));
+  HIP_TRY(launch(side));
+  HIP_TRY(hipEventRecord(ev.b, side));
+  HIP_TRY(hipStreamWaitEvent(s, ev.b, 0));
+  return STA_OK;
+}
+
 static hipError_t device_side_streams(int device, hipStream_t *a, hipStream_t *b) {
   static std::mutex mu;
   static std::vector<std::pair<hipStream_t, hipStream_t>> pool;
@@ -2070,7 +2103,7 @@ extern "C" sta_status sta_estimate_rc(const sta_graph_desc *g, const float *pin_
   }
   STA_TRY(tmp.alloc(&A.big_tmp, (size_t)std::max<unsigned long long>(16 * tot, 1)));
   A.acc_off = off;
-  HIP_TRY(launch_est(A, mid, big, st, h[0], h[1], s));
+  STA_TRY(est_forked(s, [&](hipStream_t side) { return launch_est(A, mid, big, st, h[0], h[1], s, side); }));
   if (mem == STA_HOST) {
     HIP_TRY(hipMemcpyAsync(net_node_ptr, A.node_ptr, ((size_t)NN + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
     if (n_nodes > 0) {
@@ -2371,7 +2404,7 @@ extern "C" sta_status sta_estimate_rc_backward(const sta_graph_desc *g, const fl
   A.acc_off = off;
   A.err = st + 6;
   // the trees rebuilt from the positions, checked against the caller's, and differentiated
-  HIP_TRY(launch_est_grad(A, mid, big, st, h[0], h[1], s));
+  STA_TRY(est_forked(s, [&](hipStream_t side) { return launch_est_grad(A, mid, big, st, h[0], h[1], s, side); }));
   HIP_TRY(hipMemcpyAsync(h + 6, st + 6, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   if (h[6] != ~0u)

@@ -1022,23 +1022,24 @@ hipError_t est_noalloc_scratch(int device, unsigned char **ptr) {
 
 template <bool kGrad>
 static hipError_t launch_tiers(const EstArgs &A, const int32_t *mid, const int32_t *big, const uint32_t *st,
-                               uint32_t n_mid, uint32_t n_big, hipStream_t s) {
+                               uint32_t n_mid, uint32_t n_big, hipStream_t s, hipStream_t side) {
   if (A.n_nets <= 0) return hipSuccess;
   if (n_big > 0) {  // first: the longest blocks start before the short work fills the chip
     const dim3 grid(std::min<uint32_t>(n_big, 4096u));
     hipLaunchKernelGGL((k_est_block<kGrad, 1, kEstPer>), grid, dim3(1024), 0, s, A, big, st + 1);
   }
+  hipStream_t t = side ? side : s;  // the tiers write other nets than the block kernel
   if (n_mid > 0)
-    hipLaunchKernelGGL((k_est_group<kWave, kGrad>), dim3(blocks_of(n_mid, 256 / kWave)), dim3(256), 0, s, A, mid,
+    hipLaunchKernelGGL((k_est_group<kWave, kGrad>), dim3(blocks_of(n_mid, 256 / kWave)), dim3(256), 0, t, A, mid,
                        st);
-  hipLaunchKernelGGL((k_est_group<kLanePins, kGrad>), dim3(blocks_of(A.n_nets, 256 / kLanePins)), dim3(256), 0, s,
+  hipLaunchKernelGGL((k_est_group<kLanePins, kGrad>), dim3(blocks_of(A.n_nets, 256 / kLanePins)), dim3(256), 0, t,
                      A, nullptr, nullptr);
   return hipGetLastError();
 }
 
 hipError_t launch_est(const EstArgs &A, const int32_t *mid, const int32_t *big, const uint32_t *st, uint32_t n_mid,
-                      uint32_t n_big, hipStream_t s) {
-  return launch_tiers<false>(A, mid, big, st, n_mid, n_big, s);
+                      uint32_t n_big, hipStream_t s, hipStream_t side) {
+  return launch_tiers<false>(A, mid, big, st, n_mid, n_big, s, side);
 }
 
 hipError_t launch_est_acc_offsets(const EstArgs &A, const int32_t *big, const uint32_t *st, int64_t *off,
@@ -1048,8 +1049,8 @@ hipError_t launch_est_acc_offsets(const EstArgs &A, const int32_t *big, const ui
 }
 
 hipError_t launch_est_grad(const EstArgs &A, const int32_t *mid, const int32_t *big, const uint32_t *st,
-                           uint32_t n_mid, uint32_t n_big, hipStream_t s) {
-  return launch_tiers<true>(A, mid, big, st, n_mid, n_big, s);
+                           uint32_t n_mid, uint32_t n_big, hipStream_t s, hipStream_t side) {
+  return launch_tiers<true>(A, mid, big, st, n_mid, n_big, s, side);
 }
 
 }  // namespace sta
