@@ -3893,6 +3893,16 @@ __global__ __launch_bounds__(kWave) void k_paths_enum(DevDesign D, PathArgs A) {
     if (it.z >= 0) {  // prefix of the parent path up to the sidetrack
       const int parent = it.z >> 24, pos = it.z & 0xffffff;
       const int32_t *pp = nodes + (size_t)parent * lmax;
+      // sixteen loads in flight before their stores (the two paths never
+      // overlap, which the compiler cannot see), then the tail
+      constexpr int kCopy = 16;
+      for (; len + kCopy <= pos; len += kCopy) {
+        int32_t v[kCopy];
+#pragma unroll
+        for (int u = 0; u < kCopy; ++u) v[u] = pp[len + u];
+#pragma unroll
+        for (int u = 0; u < kCopy; ++u) path[len + u] = v[u];
+      }
       for (; len < pos; ++len) path[len] = pp[len];
     }
     int code = it.w;
