@@ -9,6 +9,7 @@ import oracle
 from oracle import paths as P
 from paper_2511_11660_amd import synth
 from paper_2511_11660_amd.sta import STA, STA_SCHED_PER_LEVEL, STA_SCHED_PERSISTENT
+from designs import PI
 from test_oracle_paths import _connected, small_dag
 
 pytestmark = pytest.mark.gpu
@@ -141,3 +142,32 @@ def test_paths_empty_and_threshold_edges():
     one = s.paths(1, 1, np.inf, 1)
     assert len(one) == 1
     s.close()
+
+
+def test_paths_10m_worst_late():
+    """The benchmark's 10M-pin design: the 200 worst late paths (at most 2 per
+    endpoint) against the oracle's, rank by rank in slack, and every reported
+    path a timing path whose FP64 slack, summed with the oracle's arc delays,
+    matches."""
+    d = synth.generate(synth.large_config())
+    print(f"[paths] 10M design: {d.n_pins} pins", flush=True)
+    s = STA(d)
+    s.update()
+    got = s.paths(200, 2, np.inf, 1)
+    s.close()
+    print("[paths] GPU report done", flush=True)
+    r = oracle.sta(d)
+    print("[paths] oracle timing done", flush=True)
+    ref = P.top_paths(d, 200, 2, np.inf, 1, r)
+    print("[paths] oracle paths done", flush=True)
+    tol = max(1e-3, 1e-5 * _scale(r))
+    gs = np.array([p["slack"] for p in got])
+    rs = np.array([p["slack"] for p in ref])
+    assert len(gs) == len(rs) == 200
+    assert np.all(np.abs(gs - rs) <= tol), np.abs(gs - rs).max()
+    g = P._Graph(d, r)
+    print("[paths] oracle graph done", flush=True)
+    kind = np.asarray(d.pin_kind)
+    for p in got:  # (_fp64_slack asserts that every step is an arc of the graph)
+        assert kind[p["pins"][0]] == PI  # a path starts at a primary input
+        assert abs(_fp64_slack(g, r, p, 1) - p["slack"]) <= tol
