@@ -58,9 +58,13 @@ def test_single_segment_nets_are_rc_ln2():
     compare_full(d, oracle.sta(d, sink_delay=AR.sink_delays(d)), got)
 
 
-def test_mid_design_sampled_delays():
-    """1.2M pins: 2000 sampled nets' sink delays against the oracle's model."""
-    d = synth.generate(synth.mid_config())
+@pytest.mark.parametrize("cfg", ["mid", "large"])
+def test_sampled_delays(cfg):
+    """1.2M and 12M pins (the benchmark's design): 2000 sampled nets' sink
+    delays against the oracle's model, and on the large design also two nets
+    above 255 nodes, which the wide-net kernels handle."""
+    d = synth.generate(synth.mid_config() if cfg == "mid" else synth.large_config())
+    print(f"[arnoldi] {cfg}: {d.n_pins} pins", flush=True)
     s = STA(d, delay_model=1, sched=STA_SCHED_PER_LEVEL)
     s.update()
     _, dr, _ = s.rc()
@@ -72,6 +76,11 @@ def test_mid_design_sampled_delays():
     cell_of[np.asarray(d.cell_in_pin)] = np.repeat(np.arange(d.n_cells), np.diff(d.cell_in_ptr))
     rng = np.random.default_rng(2)
     nets = rng.choice(np.flatnonzero(np.diff(nsp) > 0), 2000, replace=False)
+    if cfg == "large":  # and the two smallest wide nets (5k nodes: the dense oracle takes seconds each)
+        m = np.diff(ptr)
+        wide = np.flatnonzero((m > 255) & (np.diff(nsp) > 0))
+        assert wide.size >= 2
+        nets = np.concatenate([nets, wide[np.argsort(m[wide], kind="stable")[:2]]])
     got, ref = [], []
     for n in nets:
         a, b = ptr[n], ptr[n + 1]
