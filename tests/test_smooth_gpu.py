@@ -77,6 +77,15 @@ def test_smooth_adjoint_five_input_cells(seed):
     _check_smooth(d, STA_SCHED_PER_LEVEL)
 
 
+def test_smooth_benchmark_design():
+    """The adjoint measurement's own workload (the 1.2M-pin design, gamma 5 ps,
+    per-level schedule): smooth arrivals and all four gradients against the
+    oracle's."""
+    d = synth.generate(synth.mid_config())
+    print(f"[smooth] benchmark design pins={d.n_pins}", flush=True)
+    _check_smooth(d, STA_SCHED_PER_LEVEL)
+
+
 def test_adjoint_is_deterministic():
     d = synth.generate(synth.mid_config(n_cells=20_000, n_levels=25, seed=15))
     s = STA(d, mode=1, gamma_ps=GAMMA)
