@@ -100,6 +100,15 @@ def test_incremental_mid_design(blocks):
     _chain(d, [1, 10, 100, 3000], seed=3, sweep_blocks=blocks)
 
 
+def test_incremental_benchmark_design():
+    """The incremental measurement's own workload: the 10M-pin design after 1,
+    100 and 10,000 nets are re-capped, each bitwise a full update with the same
+    caps (10,000 nets goes past the full-update threshold), the last also
+    against the oracle."""
+    d = synth.generate(synth.large_config())
+    _chain(d, [1, 100, 10_000], seed=4)
+
+
 @pytest.mark.parametrize("blocks", [0, 1])
 def test_incremental_split_high_fanout_drivers(blocks):
     cfg = synth.mid_config(seed=34, n_cells=8_000, n_levels=12, n_hf=3, hf_min=1500, hf_max=3000)
