@@ -32,7 +32,7 @@ constexpr int kRcAdjChunkNodes = 1024;      // nodes (its LDS holds eight arrays
 constexpr int kRcSortWindow = 4096;         // slots within which small nets are ordered by size
 constexpr int kSmallNetMaxNodes = 255;      // parents fit in a byte
 constexpr int kReduceBlocks = 128;
-constexpr int kLevelCpb = 2;                // chunks per block of the full-update level kernels
+constexpr int kLevelCpb = 1;                // chunks per block of the full-update level kernels
 
 struct alignas(32) PinState {
   float4 at;

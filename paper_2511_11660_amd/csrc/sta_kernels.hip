@@ -656,8 +656,8 @@ __device__ __forceinline__ void merge_slots(const DevDesign &D, const CellCtx &c
 // kSlots: inline fanin slots to merge (the library's most inputs, <= 4), so
 // the slot loop is straight-line code whose table loads can all be issued
 // together; a cell with fewer inputs masks its empty slots.
-// kCpb: chunks per block (256 threads each).  Two chunks share one staging of
-// the library, which halves the LDS fill traffic of a level; a block's second
+// kCpb: chunks per block (256 threads each; the full update uses kLevelCpb).
+// Chunks of one block share one staging of their types' tables; a block's
 // chunk past the phase's n chunks only reaches the barriers (reads clamped to
 // the last chunk, nothing written).  The incremental kernels keep one.
 template <bool kInc, int kSlots, int kCpb>
